@@ -1,0 +1,200 @@
+"""Seeded synthetic PDE matrices and right-hand sides.
+
+This module only assembles test problems (sparse s.p.d. matrices in CSR form,
+exact solutions and right-hand sides).  It contains none of the AMG method's
+arithmetic, so both the HIP solve path and the CPU oracle may take their inputs
+from it.  Every random draw comes from ``numpy.random.default_rng(seed)``
+(PCG64), in the order documented in each function.
+
+Problem families (stand-ins for the paper's test matrices, Section 5):
+
+* ``aniso9``   -- rotated anisotropic diffusion -div(K grad u) on the unit
+  square with the coefficient matrix K of Section 5.1 (a = eps + cos^2 theta,
+  b = eps + sin^2 theta, c = cos theta sin theta), 9-point finite differences.
+* ``jump7``    -- 3-D diffusion with piecewise-constant jumping coefficient,
+  7-point finite differences, harmonic-mean face coefficients.
+* ``elast_q1`` -- 3-D linear elasticity (Lame equations of Section 5.2) with
+  trilinear hexahedral elements and node-based ordering of the three
+  displacement components per node.
+* ``grf_fv5``  -- cell-centred 5-point finite volumes with conductivity exp(g),
+  g a Gaussian random field.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+
+@dataclass
+class Problem:
+    """A sparse s.p.d. system A x = b in CSR form (int32 indices, float64 values)."""
+
+    name: str
+    rowptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+    b: np.ndarray
+    x_star: np.ndarray | None = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.rowptr.shape[0] - 1)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    def scipy(self) -> sp.csr_matrix:
+        return sp.csr_matrix((self.val, self.col, self.rowptr), shape=(self.n, self.n))
+
+
+def _to_csr(rows, cols, vals, n) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    A = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    A.eliminate_zeros()
+    return (A.indptr.astype(np.int32), A.indices.astype(np.int32),
+            A.data.astype(np.float64))
+
+
+def _symmetrize_exact(rowptr, col, val):
+    """Make the stored values bitwise symmetric: v_ij = v_ji = (v_ij + v_ji)/2."""
+    n = rowptr.shape[0] - 1
+    A = sp.csr_matrix((val, col, rowptr), shape=(n, n))
+    S = ((A + A.T) * 0.5).tocsr()
+    S.sort_indices()
+    return S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.astype(np.float64)
+
+
+def aniso9_matrix(m: int, eps: float, theta: float):
+    """9-point FD matrix (times h^2) of -div(K grad u) on an m x m interior grid.
+
+    K = [[a, c], [c, b]] with a = eps + cos^2(theta), b = eps + sin^2(theta),
+    c = cos(theta) sin(theta) (Section 5.1).  The mixed derivative uses the
+    central cross difference, so the stencil is
+        centre 2(a+b); east/west -a; north/south -b; NE/SW -c/2; NW/SE +c/2.
+    It is s.p.d. for every eps > 0 since ab - c^2 = eps(1 + eps) > 0.
+    Nodes are numbered x-fastest: k = iy*m + ix.  Homogeneous Dirichlet.
+    """
+    a = eps + math.cos(theta) ** 2
+    b = eps + math.sin(theta) ** 2
+    c = math.cos(theta) * math.sin(theta)
+    iy, ix = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+    ix = ix.ravel()
+    iy = iy.ravel()
+    k = iy * m + ix
+    stencil = [(0, 0, 2.0 * (a + b)), (1, 0, -a), (-1, 0, -a), (0, 1, -b), (0, -1, -b),
+               (1, 1, -0.5 * c), (-1, -1, -0.5 * c), (-1, 1, 0.5 * c), (1, -1, 0.5 * c)]
+    R, C, V = [], [], []
+    for dx, dy, w in stencil:
+        if w == 0.0:
+            continue
+        jx = ix + dx
+        jy = iy + dy
+        ok = (jx >= 0) & (jx < m) & (jy >= 0) & (jy < m)
+        R.append(k[ok])
+        C.append((jy * m + jx)[ok])
+        V.append(np.full(int(ok.sum()), w))
+    return _to_csr(np.concatenate(R), np.concatenate(C), np.concatenate(V), m * m)
+
+
+def aniso9(m: int = 64, eps: float = 1e-2, theta: float = math.pi / 4, seed: int = 0) -> Problem:
+    """Rotated anisotropic diffusion; b = A x*, x* ~ U[-1, 1] (one draw of n uniforms)."""
+    rp, ci, v = aniso9_matrix(m, eps, theta)
+    n = m * m
+    rng = np.random.default_rng(seed)
+    xs = rng.uniform(-1.0, 1.0, n)
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    return Problem(f"aniso9_m{m}", rp, ci, v, A @ xs, xs,
+                   dict(m=m, eps=eps, theta=theta, seed=seed))
+
+
+def jump7_coefficient(m: int, cube: int, p: float, rng) -> np.ndarray:
+    """Nodal coefficient kappa on an m^3 grid (x fastest).
+
+    The grid is cut into (m/cube)^3 cubes.  Each cube is selected with
+    probability p (first draw: one uniform per cube); a selected cube gets
+    1e3 or 1e-3 with equal probability (second draw: one uniform per cube);
+    all other cubes get 1.
+    """
+    nc = m // cube
+    sel = rng.uniform(size=(nc, nc, nc)) < p
+    hi = rng.uniform(size=(nc, nc, nc)) < 0.5
+    kc = np.where(sel, np.where(hi, 1e3, 1e-3), 1.0)
+    kc = np.repeat(np.repeat(np.repeat(kc, cube, 0), cube, 1), cube, 2)
+    return kc  # indexed [z, y, x]
+
+
+def jump7_matrix(kappa: np.ndarray):
+    """7-point FD diffusion matrix from nodal kappa[z, y, x] (x fastest numbering).
+
+    Face coefficient = harmonic mean of the two nodes' kappa; a Dirichlet
+    boundary face takes the node's own kappa; diagonal = sum of the six face
+    coefficients.
+    """
+    mz, my, mx = kappa.shape
+    n = mx * my * mz
+    idx = np.arange(n).reshape(mz, my, mx)
+    diag = np.zeros((mz, my, mx))
+    R, C, V = [], [], []
+    for axis in range(3):
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[axis] = slice(0, -1)
+        hi[axis] = slice(1, None)
+        k1 = kappa[tuple(lo)]
+        k2 = kappa[tuple(hi)]
+        f = 2.0 * k1 * k2 / (k1 + k2)
+        i1 = idx[tuple(lo)].ravel()
+        i2 = idx[tuple(hi)].ravel()
+        R += [i1, i2]
+        C += [i2, i1]
+        V += [-f.ravel(), -f.ravel()]
+        diag[tuple(lo)] += f
+        diag[tuple(hi)] += f
+        # boundary faces (Dirichlet ghost) on both ends of this axis
+        first = [slice(None)] * 3
+        last = [slice(None)] * 3
+        first[axis] = slice(0, 1)
+        last[axis] = slice(-1, None)
+        diag[tuple(first)] += kappa[tuple(first)]
+        diag[tuple(last)] += kappa[tuple(last)]
+    R.append(idx.ravel())
+    C.append(idx.ravel())
+    V.append(diag.ravel())
+    return _to_csr(np.concatenate(R), np.concatenate(C), np.concatenate(V), n)
+
+
+def jump7(m: int = 128, cube: int = 8, p: float = 0.5, seed: int = 0) -> Problem:
+    """3-D jump-coefficient diffusion.  Draw order: cube selection, cube
+    high/low, then x* ~ U[-1, 1]; b = A x*."""
+    rng = np.random.default_rng(seed)
+    kap = jump7_coefficient(m, cube, p, rng)
+    rp, ci, v = jump7_matrix(kap)
+    n = m ** 3
+    xs = rng.uniform(-1.0, 1.0, n)
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    return Problem(f"jump7_m{m}", rp, ci, v, A @ xs, xs, dict(m=m, cube=cube, p=p, seed=seed))
+
+
+def laplace7(m: int) -> Problem:
+    """Constant-coefficient 7-point Laplacian on m^3 (b = A 1)."""
+    rp, ci, v = jump7_matrix(np.ones((m, m, m)))
+    n = m ** 3
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    xs = np.ones(n)
+    return Problem(f"laplace7_m{m}", rp, ci, v, A @ xs, xs, dict(m=m))
+
+
+def random_vectors(n: int, k: int, seed: int) -> np.ndarray:
+    """k independent U[-1, 1] vectors of length n, column-major (k, n) array.
+
+    These are the random initial iterates of the bootstrap's testing phase
+    (Algorithm 1); they are drawn here so that every consumer sees the same
+    numbers."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1.0, 1.0, size=(k, n))

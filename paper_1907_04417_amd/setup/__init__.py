@@ -1,0 +1,152 @@
+"""Host setup (input generator) of the multiple-vector aggregation AMG.
+
+Thin ctypes binding to ``libmvsetup.so`` (built from ``mvsetup.cpp`` by
+``paper_1907_04417_amd.build``).  ``build_hierarchy`` runs the bootstrap of
+Algorithm 1, composes the aggregates and writes the hierarchy file that the
+GPU library (``mvamg_hier_read``) and the CPU oracle read.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmvsetup.so")
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("nvec_max", ctypes.c_int), ("nu", ctypes.c_int), ("rho_des", ctypes.c_double),
+                ("maxstage", ctypes.c_int), ("tol_svd", ctypes.c_double),
+                ("compose", ctypes.c_int), ("coarse_cap", ctypes.c_int),
+                ("boot_coarse_min", ctypes.c_int), ("hier_stage", ctypes.c_int),
+                ("store_w", ctypes.c_int), ("max_levels", ctypes.c_int),
+                ("nthreads", ctypes.c_int)]
+
+
+@dataclass
+class SetupParams:
+    """Parameters of the setup; defaults follow Section 5 of the paper
+    (nu = 15 testing steps, rho_des = 0.8, at most 15 stages, TOL = 0.1,
+    three bootstrap levels composed into aggregates of at most 64 nodes)."""
+
+    nvec_max: int = 4
+    nu: int = 15
+    rho_des: float = 0.8
+    maxstage: int = 15
+    tol_svd: float = 0.1
+    compose: int = 3
+    coarse_cap: int = 2048
+    boot_coarse_min: int = 64
+    hier_stage: int = -1
+    store_w: int = 1
+    max_levels: int = 40
+    nthreads: int = 0
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"setup library not built: {LIB_PATH} (run __graft_entry__.build())")
+        lib = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        lib.mvsetup_build.argtypes = [ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_double),
+                                      P(ctypes.c_double), P(_Params), ctypes.c_char_p, P(ctypes.c_double)]
+        lib.mvsetup_build.restype = ctypes.c_int
+        lib.mvsetup_last_error.restype = ctypes.c_char_p
+        lib.mvsetup_pairwise.argtypes = [ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_double),
+                                         P(ctypes.c_double), P(ctypes.c_int), P(ctypes.c_double)]
+        lib.mvsetup_pairwise.restype = ctypes.c_int
+        lib.mvsetup_edge_weights.argtypes = [ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int),
+                                             P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double)]
+        lib.mvsetup_edge_weights.restype = ctypes.c_int
+        lib.mvsetup_aggregate_basis.argtypes = [P(ctypes.c_double), ctypes.c_int, ctypes.c_int,
+                                                ctypes.c_double, P(ctypes.c_double), P(ctypes.c_double)]
+        lib.mvsetup_aggregate_basis.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _csr(rowptr, col, val):
+    return (np.ascontiguousarray(rowptr, dtype=np.int32), np.ascontiguousarray(col, dtype=np.int32),
+            np.ascontiguousarray(val, dtype=np.float64))
+
+
+def build_hierarchy(rowptr, col, val, path: str, x0: np.ndarray, params: SetupParams | None = None) -> dict:
+    """Run the setup on A (CSR) and write the hierarchy to ``path``.
+
+    ``x0`` is a (nvec_max - 1, n) array of random initial iterates for the
+    bootstrap testing phase.  Returns the setup statistics."""
+    lib = _load()
+    p = params or SetupParams()
+    rp, ci, v = _csr(rowptr, col, val)
+    n = rp.shape[0] - 1
+    k = max(p.nvec_max - 1, 1)
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    if x0.size < k * n:
+        raise ValueError(f"x0 must hold {k} vectors of length {n}")
+    cp = _Params(p.nvec_max, p.nu, p.rho_des, p.maxstage, p.tol_svd, p.compose, p.coarse_cap,
+                 p.boot_coarse_min, p.hier_stage, p.store_w, p.max_levels, p.nthreads)
+    stats = np.zeros(64)
+    rc = lib.mvsetup_build(n, _ptr(rp, ctypes.c_int), _ptr(ci, ctypes.c_int), _ptr(v, ctypes.c_double),
+                           _ptr(x0, ctypes.c_double), ctypes.byref(cp), path.encode(),
+                           _ptr(stats, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError("setup failed: " + lib.mvsetup_last_error().decode())
+    nl = int(stats[0])
+    ns = int(stats[4])
+    return dict(nlevels=nl, nvec=int(stats[1]), opc=float(stats[2]), cr=float(stats[3]),
+                rho=[float(r) for r in stats[5:5 + ns]],
+                n=[int(x) for x in stats[24:24 + nl]], nnz=[int(x) for x in stats[44:44 + nl]])
+
+
+def pairwise(rowptr, col, val, w):
+    """One pairwise aggregation step: returns (nc, agg, p)."""
+    lib = _load()
+    rp, ci, v = _csr(rowptr, col, val)
+    n = rp.shape[0] - 1
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    agg = np.zeros(n, dtype=np.int32)
+    p = np.zeros(n)
+    nc = lib.mvsetup_pairwise(n, _ptr(rp, ctypes.c_int), _ptr(ci, ctypes.c_int), _ptr(v, ctypes.c_double),
+                              _ptr(w, ctypes.c_double), _ptr(agg, ctypes.c_int), _ptr(p, ctypes.c_double))
+    if nc < 0:
+        raise RuntimeError(lib.mvsetup_last_error().decode())
+    return nc, agg, p
+
+
+def edge_weights(rowptr, col, val, w):
+    lib = _load()
+    rp, ci, v = _csr(rowptr, col, val)
+    n = rp.shape[0] - 1
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    c = np.zeros(ci.shape[0])
+    rc = lib.mvsetup_edge_weights(n, _ptr(rp, ctypes.c_int), _ptr(ci, ctypes.c_int), _ptr(v, ctypes.c_double),
+                                  _ptr(w, ctypes.c_double), _ptr(c, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError(lib.mvsetup_last_error().decode())
+    return c
+
+
+def aggregate_basis(Pa: np.ndarray, tol_a: float):
+    """Truncated orthonormal basis of the columns of Pa: returns (U, drop2)."""
+    lib = _load()
+    Pa = np.ascontiguousarray(Pa, dtype=np.float64)
+    na, m = Pa.shape
+    U = np.zeros(na * m)
+    d2 = ctypes.c_double(0.0)
+    k = lib.mvsetup_aggregate_basis(_ptr(Pa, ctypes.c_double), na, m, tol_a, _ptr(U, ctypes.c_double),
+                                    ctypes.byref(d2))
+    if k < 0:
+        raise RuntimeError(lib.mvsetup_last_error().decode())
+    return U[:na * k].reshape(na, k), d2.value

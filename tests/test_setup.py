@@ -1,0 +1,157 @@
+"""Pins of the host setup generator (input of the solve phase), no GPU.
+
+Section 3: matching validity, D-orthogonality of P_c and P_f, the edge weight
+as the diagonal of A_f.  Section 4: orthonormal aggregate bases, smooth vectors
+in Range(P) up to the dropped singular values, Galerkin coarse matrices.
+Colourings are valid and aggregates partition every level.
+"""
+import numpy as np
+import pytest
+
+from oracle.hierfile import read_hierarchy
+from paper_1907_04417_amd import problems
+from paper_1907_04417_amd import setup as mvs
+from tests import dense_ref as dr
+
+
+def _edges(P):
+    rows = np.repeat(np.arange(P.n), np.diff(P.rowptr))
+    return rows, P.col
+
+
+def test_edge_weight_golden(setup_lib):
+    """2x2 example worked by hand: A = [[2,-1],[-1,2]], w = (1,1) gives
+    w_e^perp = (-1/2, 1/2)/1 and (w_e^perp)^T A w_e^perp = 3/2."""
+    rp = np.array([0, 2, 4])
+    ci = np.array([0, 1, 0, 1])
+    v = np.array([2.0, -1.0, -1.0, 2.0])
+    c = mvs.edge_weights(rp, ci, v, np.array([1.0, 1.0]))
+    assert c[1] == pytest.approx(1.5, rel=1e-15) and c[2] == pytest.approx(1.5, rel=1e-15)
+
+
+def test_edge_weight_is_diag_of_Af(setup_lib):
+    """c_ij equals (w_e^perp)^T A_ee w_e^perp with w_e^perp from eq. (3.1)."""
+    P = problems.aniso9(9, eps=1e-2, theta=0.3)
+    w = np.random.default_rng(0).uniform(0.2, 1.0, P.n) * np.sign(np.random.default_rng(1).standard_normal(P.n))
+    c = mvs.edge_weights(P.rowptr, P.col, P.val, w)
+    A = dr.dense(P.rowptr, P.col, P.val)
+    rows, cols = _edges(P)
+    for k in range(P.nnz):
+        i, j = rows[k], cols[k]
+        if i == j:
+            continue
+        we = np.array([-w[j] / A[i, i], w[i] / A[j, j]])
+        we /= np.sqrt(w[j] ** 2 / A[i, i] + w[i] ** 2 / A[j, j])
+        Aee = A[np.ix_([i, j], [i, j])]
+        assert c[k] == pytest.approx(we @ Aee @ we, rel=1e-12, abs=1e-14)
+
+
+def test_pairwise_matching_and_D_orthogonality(setup_lib):
+    """Pairs are edges of A, no vertex is shared, the matching is maximal, P_c
+    has orthonormal columns containing w, and P_c^T D P_f = 0 (Section 3)."""
+    P = problems.aniso9(10, eps=1e-2, theta=0.7)
+    w = np.random.default_rng(2).uniform(0.1, 1.0, P.n)
+    nc, agg, p = mvs.pairwise(P.rowptr, P.col, P.val, w)
+    A = dr.dense(P.rowptr, P.col, P.val)
+    sizes = np.bincount(agg, minlength=nc)
+    assert sizes.min() >= 1 and sizes.max() <= 2
+    Pc = np.zeros((P.n, nc))
+    Pc[np.arange(P.n), agg] = p
+    np.testing.assert_allclose(Pc.T @ Pc, np.eye(nc), atol=1e-14)
+    np.testing.assert_allclose(Pc @ (Pc.T @ w), w, rtol=1e-13)
+    pairs = [np.nonzero(agg == a)[0] for a in range(nc) if sizes[a] == 2]
+    Pf = np.zeros((P.n, len(pairs)))
+    matched = np.zeros(P.n, bool)
+    for e, (i, j) in enumerate(pairs):
+        assert A[i, j] != 0.0
+        matched[[i, j]] = True
+        Pf[i, e] = -w[j] / A[i, i]
+        Pf[j, e] = w[i] / A[j, j]
+    D = np.diag(np.diag(A))
+    np.testing.assert_allclose(Pc.T @ D @ Pf, 0.0, atol=1e-13)
+    # maximal: no edge joins two unmatched vertices (all weights are positive here)
+    un = np.nonzero(~matched)[0]
+    assert not np.any(A[np.ix_(un, un)] - np.diag(np.diag(A[np.ix_(un, un)])))
+
+
+def test_aggregate_basis_svd_identity(setup_lib):
+    """U^T U = I, and ||(I - U U^T) Pa||_F^2 equals the sum of the dropped
+    squared singular values (exact SVD identity, eq. 4.3)."""
+    rng = np.random.default_rng(5)
+    for na, m, tol in [(40, 4, 0.0), (7, 5, 0.0), (30, 6, 0.5), (3, 6, 0.0), (1, 3, 0.0)]:
+        Pa = rng.standard_normal((na, m))
+        Pa[:, -1] = Pa[:, 0] * 2.0 + 1e-3 * rng.standard_normal(na)  # near-dependent column
+        U, d2 = mvs.aggregate_basis(Pa, tol)
+        k = U.shape[1]
+        np.testing.assert_allclose(U.T @ U, np.eye(k), atol=1e-13)
+        s = np.linalg.svd(Pa, compute_uv=False)
+        assert k == max(1, min(na, int(np.sum(s > tol))))
+        resid = Pa - U @ (U.T @ Pa)
+        assert np.sum(resid ** 2) == pytest.approx(np.sum(s[k:] ** 2), rel=1e-8, abs=1e-20)
+        assert d2 == pytest.approx(np.sum(s[k:] ** 2), rel=1e-8, abs=1e-20)
+        # sign convention: largest-magnitude entry of each column is positive
+        assert np.all(U[np.abs(U).argmax(axis=0), np.arange(k)] > 0)
+
+
+@pytest.mark.parametrize("fx", ["tiny_hier", "small3d_hier"])
+def test_hierarchy_invariants(fx, request):
+    P, path, st = request.getfixturevalue(fx)
+    H = read_hierarchy(path)
+    assert H.nlevels == st["nlevels"] and H.nlevels >= 3
+    np.testing.assert_array_equal(H.levels[0].val, P.val)
+    for l in range(H.nlevels - 1):
+        L, T, C = H.levels[l], H.transfers[l], H.levels[l + 1]
+        A = dr.dense(L.rowptr, L.col, L.val)
+        # aggregates partition the level
+        assert np.array_equal(np.sort(T.arows), np.arange(L.n))
+        # colouring valid: every row once, no two coupled rows share a colour
+        assert np.array_equal(np.sort(L.crows), np.arange(L.n))
+        colour = np.empty(L.n, int)
+        for c in range(len(L.cptr) - 1):
+            colour[L.crows[L.cptr[c]:L.cptr[c + 1]]] = c
+        i, j = np.nonzero(A)
+        off = i != j
+        assert not np.any(colour[i[off]] == colour[j[off]])
+        # per-aggregate orthonormality => P^T P = I
+        Pm = dr.prolongator(T, L.n, C.n)
+        np.testing.assert_allclose(Pm.T @ Pm, np.eye(C.n), atol=1e-13)
+        # Galerkin coarse matrix, exactly symmetric
+        Ac = dr.dense(C.rowptr, C.col, C.val)
+        np.testing.assert_allclose(Ac, Pm.T @ A @ Pm, atol=1e-12 * np.abs(Ac).max())
+        assert np.array_equal(Ac, Ac.T)
+        np.linalg.cholesky(Ac)
+        # projected smooth vectors: W^{l+1} = P^T W^l, and P W^{l+1} reproduces
+        # W^l up to the dropped singular values of every aggregate
+        np.testing.assert_allclose(C.W, Pm.T @ L.W, atol=1e-12 * np.abs(L.W).max())
+        miss = np.sum((L.W - Pm @ C.W) ** 2)
+        assert miss == pytest.approx(T.drop2.sum(), rel=1e-6, abs=1e-20 + 1e-14 * np.sum(L.W ** 2))
+
+
+def test_w0_is_constant_and_bootstrap_vectors_A_normalised(tiny_hier):
+    """w_0 = 1 (Section 5) and w_r = x^nu / ||x^nu||_A (Algorithm 1)."""
+    P, path, _ = tiny_hier
+    H = read_hierarchy(path)
+    W = H.levels[0].W
+    A = dr.dense(P.rowptr, P.col, P.val)
+    np.testing.assert_array_equal(W[:, 0], 1.0)
+    for r in range(1, W.shape[1]):
+        assert W[:, r] @ A @ W[:, r] == pytest.approx(1.0, rel=1e-12)
+
+
+def test_setup_is_deterministic_across_thread_counts(setup_lib, tmp_path):
+    P = problems.jump7(8, cube=2, seed=9)
+    x0 = problems.random_vectors(P.n, 2, 1)
+    outs = []
+    for nt in (1, 3):
+        path = str(tmp_path / f"h{nt}.bin")
+        mvs.build_hierarchy(P.rowptr, P.col, P.val, path, x0,
+                            mvs.SetupParams(nvec_max=3, boot_coarse_min=8, coarse_cap=40, nthreads=nt))
+        outs.append(open(path, "rb").read())
+    assert outs[0] == outs[1]
+
+
+def test_setup_rejects_bad_input(setup_lib, tmp_path):
+    rp = np.array([0, 1, 2])
+    ci = np.array([0, 1])
+    with pytest.raises(RuntimeError):
+        mvs.build_hierarchy(rp, ci, np.array([1.0, -1.0]), str(tmp_path / "x.bin"), np.zeros((3, 2)))
