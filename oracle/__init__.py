@@ -36,7 +36,7 @@ _F = ctypes.POINTER(ctypes.c_float)
 
 class _Level(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("rowptr", _I), ("col", _I), ("val", _D),
-                ("ncol", ctypes.c_int), ("cptr", _I), ("crows", _I),
+                ("order", _I),
                 ("nagg", ctypes.c_int), ("aptr", _I), ("arows", _I), ("coff", _I),
                 ("uoff", _I), ("U", _D)]
 
@@ -105,12 +105,13 @@ class Oracle:
             lv[l].n = L.n
             lv[l].rowptr, lv[l].col, lv[l].val = _p(rp, _I), _p(ci, _I), _p(v, _D)
             if l + 1 < hier.nlevels:
-                cp, cr = _i32(L.cptr), _i32(L.crows)
+                od = _i32(L.order)
+                if od.shape[0] != L.n or not np.array_equal(np.sort(od), np.arange(L.n)):
+                    raise ValueError("smoother order is not a permutation of the rows")
                 T = hier.transfers[l]
                 arrs = [_i32(T.aptr), _i32(T.arows), _i32(T.coff), _i32(T.uoff), _f64(T.U)]
-                self._keep += [cp, cr, *arrs]
-                lv[l].ncol = cp.shape[0] - 1
-                lv[l].cptr, lv[l].crows = _p(cp, _I), _p(cr, _I)
+                self._keep += [od, *arrs]
+                lv[l].order = _p(od, _I)
                 lv[l].nagg = T.nagg
                 lv[l].aptr, lv[l].arows, lv[l].coff, lv[l].uoff = (_p(a, _I) for a in arrs[:4])
                 lv[l].U = _p(arrs[4], _D)

@@ -7,8 +7,10 @@ parser.  The file is a sequence of named little-endian arrays:
 
 Chunks: meta (int64: version, nlevels, nvec, n, nnz, nstages, stage used),
 params, stats, rho; per level l: A{l}.rowptr/.col/.val (CSR of A^l),
-A{l}.cptr/.crows (colouring of a non-coarsest level), W{l} (projected smooth
-vectors, row-major n_l x nvec); per transfer l -> l+1: P{l}.aptr/.arows
+W{l} (projected smooth vectors, row-major n_l x nvec); on a non-coarsest
+level the Gauss-Seidel order: A{l}.order (the rows in relaxation order),
+A{l}.gptr (groups: runs of `order`), A{l}.sptr (stages: runs of groups whose
+rows are mutually uncoupled); per transfer l -> l+1: P{l}.aptr/.arows
 (aggregate members), P{l}.coff (coarse offsets, k_a = coff[a+1] - coff[a]),
 P{l}.uoff (offset of U_a), P{l}.U (U_a row-major n_a x k_a), P{l}.drop2
 (sum of the squared dropped singular values).
@@ -54,8 +56,9 @@ class Level:
     rowptr: np.ndarray
     col: np.ndarray
     val: np.ndarray
-    cptr: np.ndarray | None = None
-    crows: np.ndarray | None = None
+    order: np.ndarray | None = None
+    gptr: np.ndarray | None = None
+    sptr: np.ndarray | None = None
     W: np.ndarray | None = None
 
 
@@ -98,8 +101,9 @@ def read_hierarchy(path: str) -> Hierarchy:
         if f"W{l}" in c:
             lev.W = c[f"W{l}"].reshape(lev.n, nvec)
         if l + 1 < nl:
-            lev.cptr = c[f"A{l}.cptr"]
-            lev.crows = c[f"A{l}.crows"]
+            lev.order = c[f"A{l}.order"]
+            lev.gptr = c[f"A{l}.gptr"]
+            lev.sptr = c[f"A{l}.sptr"]
             transfers.append(Transfer(c[f"P{l}.aptr"], c[f"P{l}.arows"], c[f"P{l}.coff"],
                                       c[f"P{l}.uoff"], c[f"P{l}.U"], c[f"P{l}.drop2"]))
         levels.append(lev)

@@ -30,10 +30,8 @@ typedef struct {
   const int* rowptr;
   const int* col;
   const double* val;
-  /* colouring of a non-coarsest level: rows crows[cptr[c]..cptr[c+1]) have colour c */
-  int ncol;
-  const int* cptr;
-  const int* crows;
+  /* Gauss-Seidel order of a non-coarsest level: the n rows in relaxation order */
+  const int* order;
   /* block-diagonal prolongator to the next level (Section 4):
      aggregate a has members arows[aptr[a]..aptr[a+1]), coarse dofs
      coff[a]..coff[a+1]-1, and U_a (n_a x k_a, row-major) at U + uoff[a]. */
@@ -123,8 +121,8 @@ static void gs_row(const orc_level* L, const double* val, const double* r, doubl
   x[i] = s / d;
 }
 
-/* One Gauss-Seidel sweep in the order O: colour order (colours 0..C-1, rows
-   of a colour as listed) or lexicographic; backward = exact reverse of O. */
+/* One Gauss-Seidel sweep in the order O: the level's stored order (rows grouped
+   colour by colour) or lexicographic; backward = exact reverse of O. */
 static void gs_sweep(const orc_hier* H, int l, const double* val, const double* r, double* x,
                      int forward) {
   const orc_level* L = &H->lv[l];
@@ -135,11 +133,11 @@ static void gs_sweep(const orc_hier* H, int l, const double* val, const double* 
       for (int i = L->n - 1; i >= 0; --i) gs_row(L, val, r, x, i);
     return;
   }
-  const int n = L->cptr[L->ncol];
+  const int n = L->n;
   if (forward)
-    for (int q = 0; q < n; ++q) gs_row(L, val, r, x, L->crows[q]);
+    for (int q = 0; q < n; ++q) gs_row(L, val, r, x, L->order[q]);
   else
-    for (int q = n - 1; q >= 0; --q) gs_row(L, val, r, x, L->crows[q]);
+    for (int q = n - 1; q >= 0; --q) gs_row(L, val, r, x, L->order[q]);
 }
 
 /* l1-Jacobi (Baker, Falgout, Kolev, Yang 2011): x <- x + D_l1^{-1} (r - A x),
@@ -246,11 +244,11 @@ static void gs_sweep32(const orc_hier* H, int l, const float* val, const float* 
       for (int i = L->n - 1; i >= 0; --i) gs_row32(L, val, r, x, i);
     return;
   }
-  const int n = L->cptr[L->ncol];
+  const int n = L->n;
   if (forward)
-    for (int q = 0; q < n; ++q) gs_row32(L, val, r, x, L->crows[q]);
+    for (int q = 0; q < n; ++q) gs_row32(L, val, r, x, L->order[q]);
   else
-    for (int q = n - 1; q >= 0; --q) gs_row32(L, val, r, x, L->crows[q]);
+    for (int q = n - 1; q >= 0; --q) gs_row32(L, val, r, x, L->order[q]);
 }
 
 static void l1_jacobi32(const orc_level* L, const float* val, const float* r, float* x) {
@@ -457,7 +455,8 @@ done:
  * Mixed precision: the V-cycle in binary32 (casts at its entry and exit),
  * everything else binary64.  Because the binary32 cycle is not an exactly
  * symmetric operator, CG uses the flexible beta that keeps p_{k+1} locally
- * A-orthogonal to p_k (Notay 2000): beta = z_{k+1}.(r_{k+1} - r_k) / (r_k . z_k).
+ * A-orthogonal to p_k (Notay 2000): beta = z_{k+1}.(r_{k+1} - r_k) / (r_k . z_k),
+ * evaluated with r_{k+1} - r_k = -alpha_k A p_k as beta = -alpha_k z_{k+1}.q_k / rho_k.
  * When the recursive residual
  * meets tol, the true residual b - A x is recomputed in binary64; if it does
  * not meet tol the iteration restarts from x (at most max_restarts times).
@@ -469,7 +468,6 @@ int orc_pcg_mixed(const orc_hier* H, int n, const int* rp, const int* ci, const 
                   int* nit, double* true_rel) {
   double* r = (double*)malloc(sizeof(double) * (size_t)n);
   double* z = (double*)malloc(sizeof(double) * (size_t)n);
-  double* rold = (double*)malloc(sizeof(double) * (size_t)n);
   double* p = (double*)malloc(sizeof(double) * (size_t)n);
   double* q = (double*)malloc(sizeof(double) * (size_t)n);
   float* r32 = (float*)malloc(sizeof(float) * (size_t)n);
@@ -505,7 +503,6 @@ int orc_pcg_mixed(const orc_hier* H, int n, const int* rp, const int* ci, const 
         goto done;
       }
       const double alpha = rho / pq;
-      memcpy(rold, r, sizeof(double) * (size_t)n);
       for (int i = 0; i < n; ++i) x[i] += alpha * p[i];
       for (int i = 0; i < n; ++i) r[i] -= alpha * q[i];
       ++it;
@@ -518,9 +515,7 @@ int orc_pcg_mixed(const orc_hier* H, int n, const int* rp, const int* ci, const 
       for (int i = 0; i < n; ++i) r32[i] = (float)r[i];
       vcycle32(H, 0, v32, r32, z32);
       for (int i = 0; i < n; ++i) z[i] = (double)z32[i];
-      double num = 0.0;
-      for (int i = 0; i < n; ++i) num += z[i] * (r[i] - rold[i]);
-      const double beta = num / rho;
+      const double beta = -alpha * dotp(z, q, n) / rho;
       rho = dotp(r, z, n);
       for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
     }
@@ -537,7 +532,6 @@ done:
   *nit = it;
   free(r);
   free(z);
-  free(rold);
   free(p);
   free(q);
   free(r32);

@@ -23,7 +23,7 @@ class _Params(ctypes.Structure):
                 ("compose", ctypes.c_int), ("coarse_cap", ctypes.c_int),
                 ("boot_coarse_min", ctypes.c_int), ("hier_stage", ctypes.c_int),
                 ("store_w", ctypes.c_int), ("max_levels", ctypes.c_int),
-                ("nthreads", ctypes.c_int)]
+                ("nthreads", ctypes.c_int), ("fine_group", ctypes.c_int)]
 
 
 @dataclass
@@ -44,6 +44,7 @@ class SetupParams:
     store_w: int = 1
     max_levels: int = 40
     nthreads: int = 0
+    fine_group: int = 1
 
 
 _lib = None
@@ -96,7 +97,7 @@ def build_hierarchy(rowptr, col, val, path: str, x0: np.ndarray, params: SetupPa
     if x0.size < k * n:
         raise ValueError(f"x0 must hold {k} vectors of length {n}")
     cp = _Params(p.nvec_max, p.nu, p.rho_des, p.maxstage, p.tol_svd, p.compose, p.coarse_cap,
-                 p.boot_coarse_min, p.hier_stage, p.store_w, p.max_levels, p.nthreads)
+                 p.boot_coarse_min, p.hier_stage, p.store_w, p.max_levels, p.nthreads, p.fine_group)
     stats = np.zeros(64)
     rc = lib.mvsetup_build(n, _ptr(rp, ctypes.c_int), _ptr(ci, ctypes.c_int), _ptr(v, ctypes.c_double),
                            _ptr(x0, ctypes.c_double), ctypes.byref(cp), path.encode(),

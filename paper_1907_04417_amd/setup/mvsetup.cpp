@@ -21,8 +21,10 @@
 //     restricted smooth vectors (eq. 4.3) truncated at
 //     TOL * size(a)/size(A) (Section 5), block-diagonal orthonormal P and
 //     Galerkin coarse matrices, smooth vectors projected level by level;
-//   * a greedy first-fit colouring of every non-coarsest level, which fixes
-//     the order of the multicolour Gauss-Seidel smoother.
+//   * the Gauss-Seidel order of every non-coarsest level: a greedy first-fit
+//     colouring of groups of rows (single rows on the finest level, the k_a
+//     coarse dofs of one aggregate on coarser levels), groups listed colour by
+//     colour.
 //
 // All parallel loops are written so that results do not depend on the number
 // of threads (fixed-size chunks for reductions, per-row independent work).
@@ -152,6 +154,51 @@ void gs_sweep(const Csr& A, const std::vector<double>& d, const Colouring& C,
       x[i] = s / d[i];
     }
   }
+}
+
+// Smoother ordering of a multi-vector level.  Rows are split into groups of
+// consecutive indices (gstart); groups are coloured greedily (first fit, in
+// natural group order) on the graph in which two groups are adjacent when A
+// couples any of their rows.  The Gauss-Seidel order O lists the groups colour
+// by colour ("stages"), the rows of a group in increasing index.  Groups of one
+// stage are not coupled, so they can be relaxed simultaneously; the rows of a
+// group are relaxed one after the other.
+struct GsOrder {
+  std::vector<int> order, gptr, sptr;
+};
+
+GsOrder group_order(const Csr& A, const std::vector<int>& gstart) {
+  const int G = (int)gstart.size() - 1;
+  std::vector<int> grp(A.n);
+  for (int g = 0; g < G; ++g)
+    for (int i = gstart[g]; i < gstart[g + 1]; ++i) grp[i] = g;
+  std::vector<int> gcol(G, -1), forbid;
+  for (int g = 0; g < G; ++g) {
+    for (int i = gstart[g]; i < gstart[g + 1]; ++i)
+      for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        const int h = grp[A.ci[k]];
+        if (h != g && gcol[h] >= 0) forbid[gcol[h]] = g;
+      }
+    int c = 0;
+    while (c < (int)forbid.size() && forbid[c] == g) ++c;
+    if (c == (int)forbid.size()) forbid.push_back(-1);
+    gcol[g] = c;
+  }
+  const int ncol = (int)forbid.size();
+  GsOrder O;
+  O.sptr.assign(ncol + 1, 0);
+  for (int g = 0; g < G; ++g) O.sptr[gcol[g] + 1]++;
+  for (int c = 0; c < ncol; ++c) O.sptr[c + 1] += O.sptr[c];
+  std::vector<int> gs(G), pos(O.sptr.begin(), O.sptr.end() - 1);
+  for (int g = 0; g < G; ++g) gs[pos[gcol[g]]++] = g;
+  O.gptr.assign(G + 1, 0);
+  O.order.reserve(A.n);
+  for (int t = 0; t < G; ++t) {
+    const int g = gs[t];
+    for (int i = gstart[g]; i < gstart[g + 1]; ++i) O.order.push_back(i);
+    O.gptr[t + 1] = (int)O.order.size();
+  }
+  return O;
 }
 
 // Make stored values bitwise symmetric: v_ij = v_ji = (v_ij + v_ji)/2.
@@ -437,6 +484,7 @@ struct Params {
   int hier_stage;       // bootstrap hierarchy to compose: -1 last, else index (0 = first)
   int store_w;          // store projected smooth vectors in the file
   int max_levels;       // cap on bootstrap hierarchy depth
+  int fine_group;       // rows per smoother group on the finest level (1: point)
 };
 
 // Builds B_r's hierarchy from the fine matrix and smooth vector w
@@ -521,7 +569,7 @@ void bh_vcycle(BHier& H, int l, const double* r, double* x) {
 
 struct MvLevel {
   Csr A;
-  Colouring C;
+  GsOrder O;
   // transfer to the next level
   int nagg = 0;
   std::vector<int> aptr, arows, coff, uoff;
@@ -723,6 +771,7 @@ struct mvsetup_params {
   int maxstage;
   double tol_svd;
   int compose, coarse_cap, boot_coarse_min, hier_stage, store_w, max_levels, nthreads;
+  int fine_group;
 };
 
 const char* mvsetup_last_error(void) { return g_err.c_str(); }
@@ -740,8 +789,9 @@ int mvsetup_build(int n, const int* rowptr, const int* col, const double* val,
     Params prm{prm_in->nvec_max, prm_in->nu,         prm_in->rho_des,
                prm_in->maxstage, prm_in->tol_svd,    prm_in->compose,
                prm_in->coarse_cap, prm_in->boot_coarse_min, prm_in->hier_stage,
-               prm_in->store_w,  prm_in->max_levels};
-    if (prm.nvec_max < 1 || prm.nu < 1 || prm.compose < 1 || prm.max_levels < 2)
+               prm_in->store_w,  prm_in->max_levels, prm_in->fine_group};
+    if (prm.nvec_max < 1 || prm.nu < 1 || prm.compose < 1 || prm.max_levels < 2 ||
+        prm.fine_group < 1 || n % prm.fine_group != 0)
       fail("invalid setup parameters");
     if (prm_in->nthreads > 0) omp_set_num_threads(prm_in->nthreads);
     Csr A;
@@ -884,7 +934,15 @@ int mvsetup_build(int n, const int* rowptr, const int* col, const double* val,
           }
         }
       }
-      M.C = greedy_colour(M.A);
+      {
+        std::vector<int> gstart;
+        if (l == 0) {
+          for (int i = 0; i <= nl; i += prm.fine_group) gstart.push_back(i);
+        } else {
+          gstart = mv[l - 1].coff;
+        }
+        M.O = group_order(M.A, gstart);
+      }
       std::vector<int> nbnode(nc);
       for (int a = 0; a < M.nagg; ++a)
         for (int ll = M.coff[a]; ll < M.coff[a + 1]; ++ll) nbnode[ll] = a;
@@ -938,8 +996,9 @@ int mvsetup_build(int n, const int* rowptr, const int* col, const double* val,
       ch.push_back({nm("A%d.val", l), 2, M.A.v.data(), M.A.v.size()});
       if (prm.store_w) ch.push_back({nm("W%d", l), 2, M.W.data(), M.W.size()});
       if (l == L) break;
-      ch.push_back({nm("A%d.cptr", l), 1, M.C.cptr.data(), M.C.cptr.size()});
-      ch.push_back({nm("A%d.crows", l), 1, M.C.crows.data(), M.C.crows.size()});
+      ch.push_back({nm("A%d.order", l), 1, M.O.order.data(), M.O.order.size()});
+      ch.push_back({nm("A%d.gptr", l), 1, M.O.gptr.data(), M.O.gptr.size()});
+      ch.push_back({nm("A%d.sptr", l), 1, M.O.sptr.data(), M.O.sptr.size()});
       ch.push_back({nm("P%d.aptr", l), 1, M.aptr.data(), M.aptr.size()});
       ch.push_back({nm("P%d.arows", l), 1, M.arows.data(), M.arows.size()});
       ch.push_back({nm("P%d.coff", l), 1, M.coff.data(), M.coff.size()});

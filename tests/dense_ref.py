@@ -46,7 +46,7 @@ def vcycle_matrix(H):
     for l in range(L - 1, -1, -1):
         A = As[l]
         n = A.shape[0]
-        M = gs_splitting(A, H.levels[l].crows)
+        M = gs_splitting(A, H.levels[l].order)
         P = prolongator(H.transfers[l], n, As[l + 1].shape[0])
         I = np.eye(n)
         E = (I - np.linalg.solve(M.T, A)) @ (I - P @ B @ P.T @ A) @ (I - np.linalg.solve(M, A))

@@ -28,7 +28,7 @@ def test_gs_sweep_closed_form(fx, request):
     for l in range(H.nlevels - 1):
         L = H.levels[l]
         A = dr.dense(L.rowptr, L.col, L.val)
-        M = dr.gs_splitting(A, L.crows)
+        M = dr.gs_splitting(A, L.order)
         rng = np.random.default_rng(l)
         r, x = rng.standard_normal(L.n), rng.standard_normal(L.n)
         xf = O.smooth(l, r, x, forward=True)
@@ -101,7 +101,7 @@ def test_nearby_matrix_keeps_spd(tiny_hier):
 
 def _singleton_hierarchy(P):
     n = P.n
-    lv0 = Level(n, P.rowptr, P.col, P.val, cptr=None, crows=None)
+    lv0 = Level(n, P.rowptr, P.col, P.val)
     # greedy colouring by brute force for the fine level
     A = dr.dense(P.rowptr, P.col, P.val)
     colour = -np.ones(n, dtype=int)
@@ -112,8 +112,9 @@ def _singleton_hierarchy(P):
             c += 1
         colour[i] = c
     order = np.argsort(colour, kind="stable").astype(np.int32)
-    lv0.cptr = np.concatenate([[0], np.cumsum(np.bincount(colour))]).astype(np.int32)
-    lv0.crows = order
+    lv0.sptr = np.concatenate([[0], np.cumsum(np.bincount(colour))]).astype(np.int32)
+    lv0.gptr = np.arange(n + 1, dtype=np.int32)
+    lv0.order = order
     lv1 = Level(n, P.rowptr, P.col, P.val)
     ar = np.arange(n + 1, dtype=np.int32)
     T = Transfer(ar, np.arange(n, dtype=np.int32), ar, ar, np.ones(n), np.zeros(n))

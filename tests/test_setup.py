@@ -104,14 +104,26 @@ def test_hierarchy_invariants(fx, request):
         A = dr.dense(L.rowptr, L.col, L.val)
         # aggregates partition the level
         assert np.array_equal(np.sort(T.arows), np.arange(L.n))
-        # colouring valid: every row once, no two coupled rows share a colour
-        assert np.array_equal(np.sort(L.crows), np.arange(L.n))
-        colour = np.empty(L.n, int)
-        for c in range(len(L.cptr) - 1):
-            colour[L.crows[L.cptr[c]:L.cptr[c + 1]]] = c
+        # smoother order: every row once; groups are runs of consecutive rows
+        # (single rows on the finest level, one aggregate's coarse dofs
+        # below); two coupled rows of different groups never share a stage
+        assert np.array_equal(np.sort(L.order), np.arange(L.n))
+        stage = np.empty(L.n, int)
+        group = np.empty(L.n, int)
+        for g in range(len(L.gptr) - 1):
+            rows = L.order[L.gptr[g]:L.gptr[g + 1]]
+            assert np.array_equal(rows, np.arange(rows[0], rows[0] + len(rows)))
+            group[rows] = g
+        for c in range(len(L.sptr) - 1):
+            stage[L.order[L.gptr[L.sptr[c]]:L.gptr[L.sptr[c + 1]]]] = c
+        if l == 0:
+            assert len(L.gptr) - 1 == L.n
+        else:
+            Tp = H.transfers[l - 1]
+            assert len(L.gptr) - 1 == Tp.nagg
         i, j = np.nonzero(A)
-        off = i != j
-        assert not np.any(colour[i[off]] == colour[j[off]])
+        off = group[i] != group[j]
+        assert not np.any(stage[i[off]] == stage[j[off]])
         # per-aggregate orthonormality => P^T P = I
         Pm = dr.prolongator(T, L.n, C.n)
         np.testing.assert_allclose(Pm.T @ Pm, np.eye(C.n), atol=1e-13)
