@@ -1,0 +1,150 @@
+/*
+ * mvamg.h -- C ABI of the MI355X (gfx950) solve phase of the single-hierarchy
+ * multiple-vector aggregation-based AMG (D'Ambra & Vassilevski, "Improving
+ * Solve Time of Aggregation-based Adaptive AMG").
+ *
+ * The library solves A x = b, A sparse symmetric positive definite (Section 1),
+ * by conjugate gradients preconditioned with one V-cycle of a hierarchy whose
+ * prolongators P^k = blockdiag(U_a) are block diagonal over composite
+ * aggregates, each block an orthonormal basis of the smooth vectors restricted
+ * to the aggregate, with Galerkin coarse matrices A^k = (P^k)^T A^{k-1} P^k
+ * (Section 4).  The cycle uses forward Gauss-Seidel pre-smoothing, backward
+ * Gauss-Seidel post-smoothing and an exact coarsest solve (Section 5).
+ *
+ * Conventions shared by every entry point:
+ *   - Device pointers are HIP device memory owned by the caller (for example
+ *     torch tensors); the library never frees them.  Host pointers are plain
+ *     host memory.  Vectors are float64 of length n (the order of the rows of
+ *     the hierarchy file's level 0) unless stated otherwise.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *     device work of a call is enqueued on it; calls that return results to
+ *     the host synchronise it.
+ *   - Every call returns an mvamg_status.  On failure mvamg_last_error()
+ *     returns a message (thread-local, valid until the next call on that
+ *     thread).  No C++ exception crosses the ABI.  Arguments are validated on
+ *     the host before any kernel is launched.
+ *   - A handle is bound to the device that was current at mvamg_upload;
+ *     calls on it must run with that device current.  Calls on one handle must
+ *     not overlap (the handle owns its work vectors).
+ */
+#ifndef MVAMG_H
+#define MVAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MVAMG_OK = 0,
+  MVAMG_NOT_CONVERGED = 1,  /* maxit reached; x holds the last iterate, info is filled */
+  MVAMG_ERR_ARG = -1,       /* invalid argument (null pointer, size, unsupported option) */
+  MVAMG_ERR_FILE = -2,      /* hierarchy file missing, truncated or inconsistent */
+  MVAMG_ERR_NOT_SPD = -3,   /* coarsest Cholesky pivot <= 0, or a non-positive diagonal */
+  MVAMG_ERR_NONFINITE = -4, /* NaN or Inf in the right-hand side or initial guess */
+  MVAMG_ERR_BREAKDOWN = -5, /* p^T A p <= 0 in CG (matrix not s.p.d.) */
+  MVAMG_ERR_HIP = -6        /* a HIP runtime call failed */
+} mvamg_status;
+
+/* Parsed hierarchy file in host memory, owned by the library. */
+typedef struct mvamg_hier_host mvamg_hier_host;
+/* Hierarchy resident on one GPU, owned by the library (device memory
+   allocated at upload, released by mvamg_free). */
+typedef struct mvamg_hier mvamg_hier;
+
+enum { MVAMG_SMOOTH_GS = 0, MVAMG_SMOOTH_L1JACOBI = 1 };
+
+typedef struct {
+  int precision;     /* 64: whole cycle in binary64; 32: cycle (smoother, level
+                        residuals, transfers) in binary32, coarsest solve, CG
+                        recurrences and inner products in binary64, flexible CG */
+  int smoother;      /* MVAMG_SMOOTH_GS (multicolour Gauss-Seidel, Section 5) or
+                        MVAMG_SMOOTH_L1JACOBI (one l1-Jacobi sweep pre and post) */
+  double rtol;       /* stop when ||r_k||_2 <= rtol * ||b - A x_0||_2 (Section 5) */
+  int maxit;         /* iteration cap (the paper uses 1000) */
+  int max_restarts;  /* precision 32: restarts from x when the recomputed true
+                        residual misses rtol (iterative refinement); ignored for 64 */
+  double* history;   /* host, optional (NULL): receives ||r_k|| / ||r_0|| for
+                        k = 0..iterations; capacity maxit + 1 */
+} mvamg_solve_params;
+
+typedef struct {
+  int iterations;      /* CG iterations (A p products) performed */
+  int converged;       /* 1 if rtol was met */
+  int restarts;        /* true-residual restarts taken (precision 32) */
+  double rel_res;      /* last recursive ||r_k|| / ||r_0|| */
+  double rel_res_true; /* ||b - A x|| / ||r_0|| recomputed in binary64 at exit */
+} mvamg_info;
+
+/* ---------------------------------------------------------------- setup */
+
+/* Reads a hierarchy file written by the host setup (levels A^k in CSR, the
+   smoother order of every non-coarsest level, the blocks U_a of every P^k).
+   *out must be released with mvamg_hier_host_free.  Errors: MVAMG_ERR_FILE. */
+mvamg_status mvamg_hier_read(const char* path, mvamg_hier_host** out);
+void mvamg_hier_host_free(mvamg_hier_host* h);
+
+/* Level count, fine size n and fine nonzeros of a parsed file. */
+mvamg_status mvamg_hier_host_info(const mvamg_hier_host* h, int* nlevels, int* n, int64_t* nnz);
+
+/* Copies the hierarchy to the current device in the library's layout
+   (rows permuted into smoother order, off-group entries in sliced-ELL or
+   grouped CSR, per-aggregate U blocks), keeps binary32 copies for the mixed
+   cycle, and factors the coarsest matrix with a dense Cholesky on the device
+   (Section 5 uses a direct coarsest solve).  The host object may be freed
+   afterwards.  Errors: MVAMG_ERR_ARG, MVAMG_ERR_NOT_SPD, MVAMG_ERR_HIP. */
+mvamg_status mvamg_upload(const mvamg_hier_host* h, void* stream, mvamg_hier** out);
+void mvamg_free(mvamg_hier* h);
+
+/* Level count and sizes of an uploaded hierarchy: n[l], nnz[l] for
+   l < nlevels (arrays of capacity 32, may be NULL), stages[l] = number of
+   smoother stages (0 on the coarsest). */
+mvamg_status mvamg_levels(const mvamg_hier* h, int* nlevels, int* n, int64_t* nnz, int* stages);
+
+/* Replaces the values of the finest matrix by val_dev (device, float64,
+   nnz entries in the CSR order of the file's level 0): a near-by matrix with
+   the same pattern (Section 1).  The fine-level products and smoothing use
+   the new values, coarser levels keep the stored Galerkin matrices. */
+mvamg_status mvamg_set_fine_values(mvamg_hier* h, const double* val_dev, void* stream);
+
+/* ---------------------------------------------------------------- solve */
+
+/* y = A x with the current finest matrix (device vectors, file order). */
+mvamg_status mvamg_spmv(mvamg_hier* h, const double* x_dev, double* y_dev, void* stream);
+
+/* z = B r: one V-cycle from a zero initial guess (Section 5).
+   precision 64 or 32 (binary32 inside the cycle), smoother as in
+   mvamg_solve_params.  r_dev and z_dev must not alias. */
+mvamg_status mvamg_cycle_apply(mvamg_hier* h, const double* r_dev, double* z_dev, int precision,
+                               int smoother, void* stream);
+
+/* Preconditioned CG (Section 5) on A x = b with B = one V-cycle.  x_dev holds
+   x_0 on entry (zero for the paper's setting) and the solution on exit.
+   Returns MVAMG_OK, MVAMG_NOT_CONVERGED, or an error.  One 8-byte
+   device-to-host copy per iteration carries ||r_k|| for the stopping test. */
+mvamg_status mvamg_pcg_solve(mvamg_hier* h, const double* b_dev, double* x_dev,
+                             const mvamg_solve_params* prm, mvamg_info* info, void* stream);
+
+/* Adjoint solve for a loss L(x): A^T lambda = dL/dx.  A is symmetric, so
+   this is the same preconditioned CG with right-hand side dLdx_dev (the
+   hierarchy is reused as is).  lambda_dev receives the solution (initial
+   guess zero). */
+mvamg_status mvamg_adjoint_solve(mvamg_hier* h, const double* dLdx_dev, double* lambda_dev,
+                                 const mvamg_solve_params* prm, mvamg_info* info, void* stream);
+
+/* Gradient of L with respect to the stored finest-matrix values:
+   dval[k] = -lambda_i x_j for the k-th stored entry (i, j) of the file's
+   level-0 CSR pattern.  (dL/db = lambda.) */
+mvamg_status mvamg_grad_coeffs(mvamg_hier* h, const double* lambda_dev, const double* x_dev,
+                               double* dval_dev, void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* mvamg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MVAMG_H */

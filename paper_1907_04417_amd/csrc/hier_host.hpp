@@ -1,0 +1,350 @@
+// Host side of the library: hierarchy-file parser and the construction of the
+// device layout (row permutation into smoother order, sliced-ELL or grouped
+// CSR storage, per-group diagonal blocks, transfer descriptors).  Plain C++,
+// no device code.  This parser is independent of the CPU oracle's reader.
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace mvamg {
+
+struct Error : std::runtime_error {
+  int status;
+  Error(int s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+// ------------------------------------------------------------ file parsing
+
+struct HostLevel {
+  int n = 0;
+  std::vector<int> rp, ci;
+  std::vector<double> v;
+  std::vector<int> order, gptr, sptr;  // smoother order (non-coarsest levels)
+  std::vector<int> aptr, arows, coff, uoff;  // transfer to the next level
+  std::vector<double> U;
+};
+
+struct HostHier {
+  int nl = 0, nvec = 0;
+  std::vector<HostLevel> lv;
+};
+
+inline HostHier read_hierarchy_file(const char* path) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) throw Error(-2, std::string("cannot open hierarchy file ") + path);
+  std::vector<char> buf;
+  {
+    std::fseek(f, 0, SEEK_END);
+    long sz = std::ftell(f);
+    std::fseek(f, 0, SEEK_SET);
+    if (sz < 16) {
+      std::fclose(f);
+      throw Error(-2, "hierarchy file too short");
+    }
+    buf.resize((size_t)sz);
+    size_t got = std::fread(buf.data(), 1, buf.size(), f);
+    std::fclose(f);
+    if (got != buf.size()) throw Error(-2, "read error on hierarchy file");
+  }
+  if (std::memcmp(buf.data(), "MVAMGH01", 8) != 0) throw Error(-2, "bad magic in hierarchy file");
+  uint32_t ver, nch;
+  std::memcpy(&ver, buf.data() + 8, 4);
+  std::memcpy(&nch, buf.data() + 12, 4);
+  if (ver != 1) throw Error(-2, "unsupported hierarchy file version");
+  struct Ch {
+    uint32_t dtype;
+    uint64_t count;
+    size_t off;
+  };
+  std::map<std::string, Ch> ch;
+  size_t off = 16;
+  for (uint32_t c = 0; c < nch; ++c) {
+    if (off + 64 > buf.size()) throw Error(-2, "truncated hierarchy file");
+    char name[49] = {0};
+    std::memcpy(name, buf.data() + off, 48);
+    Ch e;
+    std::memcpy(&e.dtype, buf.data() + off + 48, 4);
+    std::memcpy(&e.count, buf.data() + off + 56, 8);
+    off += 64;
+    const size_t es = (e.dtype == 1) ? 4 : (e.dtype == 2 || e.dtype == 3) ? 8 : 0;
+    if (!es) throw Error(-2, "unknown chunk type in hierarchy file");
+    if (e.count > (buf.size() - off) / es) throw Error(-2, "truncated hierarchy file");
+    e.off = off;
+    off += es * e.count;
+    off += (8 - (es * e.count) % 8) % 8;
+    ch[name] = e;
+  }
+  auto get_i32 = [&](const std::string& nm, std::vector<int>& out) {
+    auto it = ch.find(nm);
+    if (it == ch.end() || it->second.dtype != 1) throw Error(-2, "missing chunk " + nm);
+    out.resize(it->second.count);
+    std::memcpy(out.data(), buf.data() + it->second.off, 4 * it->second.count);
+  };
+  auto get_f64 = [&](const std::string& nm, std::vector<double>& out) {
+    auto it = ch.find(nm);
+    if (it == ch.end() || it->second.dtype != 2) throw Error(-2, "missing chunk " + nm);
+    out.resize(it->second.count);
+    std::memcpy(out.data(), buf.data() + it->second.off, 8 * it->second.count);
+  };
+  auto it = ch.find("meta");
+  if (it == ch.end() || it->second.dtype != 3 || it->second.count < 3) throw Error(-2, "missing meta chunk");
+  int64_t meta[3];
+  std::memcpy(meta, buf.data() + it->second.off, 24);
+  HostHier H;
+  H.nl = (int)meta[1];
+  H.nvec = (int)meta[2];
+  if (H.nl < 1 || H.nl > 32) throw Error(-2, "bad level count in hierarchy file");
+  H.lv.resize(H.nl);
+  for (int l = 0; l < H.nl; ++l) {
+    HostLevel& L = H.lv[l];
+    const std::string s = std::to_string(l);
+    get_i32("A" + s + ".rowptr", L.rp);
+    get_i32("A" + s + ".col", L.ci);
+    get_f64("A" + s + ".val", L.v);
+    L.n = (int)L.rp.size() - 1;
+    if (L.n < 1 || L.rp[0] != 0 || (size_t)L.rp[L.n] != L.ci.size() || L.ci.size() != L.v.size())
+      throw Error(-2, "inconsistent CSR arrays at level " + s);
+    for (int i = 0; i < L.n; ++i) {
+      if (L.rp[i + 1] < L.rp[i]) throw Error(-2, "rowptr not monotone at level " + s);
+      for (int k = L.rp[i]; k < L.rp[i + 1]; ++k)
+        if (L.ci[k] < 0 || L.ci[k] >= L.n) throw Error(-2, "column index out of range at level " + s);
+    }
+    if (l + 1 < H.nl) {
+      get_i32("A" + s + ".order", L.order);
+      get_i32("A" + s + ".gptr", L.gptr);
+      get_i32("A" + s + ".sptr", L.sptr);
+      get_i32("P" + s + ".aptr", L.aptr);
+      get_i32("P" + s + ".arows", L.arows);
+      get_i32("P" + s + ".coff", L.coff);
+      get_i32("P" + s + ".uoff", L.uoff);
+      get_f64("P" + s + ".U", L.U);
+    }
+  }
+  // transfer consistency
+  for (int l = 0; l + 1 < H.nl; ++l) {
+    const HostLevel& L = H.lv[l];
+    const int na = (int)L.aptr.size() - 1;
+    const std::string s = std::to_string(l);
+    if (na < 1 || (int)L.coff.size() != na + 1 || (int)L.uoff.size() != na + 1 || L.aptr[0] != 0 ||
+        L.aptr[na] != L.n || (int)L.arows.size() != L.n || L.coff[0] != 0 ||
+        L.coff[na] != H.lv[l + 1].n || L.uoff[0] != 0 || (size_t)L.uoff[na] != L.U.size())
+      throw Error(-2, "inconsistent transfer arrays at level " + s);
+    std::vector<char> seen(L.n, 0);
+    for (int a = 0; a < na; ++a) {
+      const int m = L.aptr[a + 1] - L.aptr[a], k = L.coff[a + 1] - L.coff[a];
+      if (m < 1 || k < 1 || L.uoff[a + 1] - L.uoff[a] != m * k)
+        throw Error(-2, "inconsistent aggregate at level " + s);
+    }
+    for (int q = 0; q < L.n; ++q) {
+      const int i = L.arows[q];
+      if (i < 0 || i >= L.n || seen[i]) throw Error(-2, "aggregates do not partition level " + s);
+      seen[i] = 1;
+    }
+  }
+  return H;
+}
+
+// ----------------------------------------------------------- device layout
+
+constexpr int kKmax = 8;  // largest group / aggregate block handled by the kernels
+
+struct Slab {
+  int row0, nrows, width, off;  // sliced ELL: 64 rows, column-major entries
+};
+
+struct LevelLayout {
+  int n = 0;
+  bool sell = false;  // point groups stored as sliced ELL (64-row slabs)
+  int G = 64;         // lanes per group for grouped CSR
+  int kmax = 1;
+  std::vector<int> perm, iperm;  // new -> old, old -> new
+  std::vector<int> gstart;       // ngroups + 1, rows in new numbering
+  std::vector<int> sgrp;         // nstages + 1, group ranges of the stages
+  // sliced ELL (sell) or grouped CSR (else) of the entries outside the diagonal blocks
+  std::vector<Slab> slabs;
+  std::vector<int> sslab;  // nstages + 1 slab ranges of the stages
+  std::vector<int> rowptr;
+  std::vector<int> col;
+  std::vector<double> val;
+  std::vector<int> src;  // index of each entry in the file's CSR value array (-1: padding)
+  // dense k x k diagonal blocks of the groups (row-major)
+  std::vector<int> dboff;
+  std::vector<double> dblk;
+  std::vector<int> dsrc;
+};
+
+struct TransferLayout {
+  int nagg = 0, max_na = 0;
+  std::vector<int> aptr, arows, uoff;
+  std::vector<int> cst, kk;  // first coarse row (new numbering of the next level), block width
+  std::vector<double> U;
+};
+
+inline void build_level_layout(const HostLevel& L, LevelLayout& Y) {
+  const int n = L.n;
+  Y.n = n;
+  Y.perm = L.order;
+  if ((int)Y.perm.size() != n) throw Error(-2, "smoother order has wrong length");
+  Y.iperm.assign(n, -1);
+  for (int p = 0; p < n; ++p) {
+    const int i = Y.perm[p];
+    if (i < 0 || i >= n || Y.iperm[i] >= 0) throw Error(-2, "smoother order is not a permutation");
+    Y.iperm[i] = p;
+  }
+  const int ng = (int)L.gptr.size() - 1;
+  const int ns = (int)L.sptr.size() - 1;
+  if (ng < 1 || L.gptr[0] != 0 || L.gptr[ng] != n || ns < 1 || L.sptr[0] != 0 || L.sptr[ns] != ng)
+    throw Error(-2, "inconsistent smoother groups");
+  Y.gstart = L.gptr;
+  Y.sgrp = L.sptr;
+  std::vector<int> grp(n);
+  Y.kmax = 1;
+  bool point = true;
+  for (int g = 0; g < ng; ++g) {
+    const int k = L.gptr[g + 1] - L.gptr[g];
+    if (k < 1) throw Error(-2, "empty smoother group");
+    if (k > kKmax) throw Error(-1, "smoother group larger than 8 rows is not supported");
+    Y.kmax = std::max(Y.kmax, k);
+    if (k > 1) point = false;
+    for (int p = L.gptr[g]; p < L.gptr[g + 1]; ++p) grp[p] = g;
+    // rows of a group are consecutive in the file numbering as well
+    for (int p = L.gptr[g] + 1; p < L.gptr[g + 1]; ++p)
+      if (Y.perm[p] != Y.perm[p - 1] + 1) throw Error(-2, "smoother group rows not consecutive");
+  }
+  // stage independence: coupled rows of different groups lie in different stages
+  std::vector<int> stage(ng);
+  for (int c = 0; c < ns; ++c)
+    for (int g = L.sptr[c]; g < L.sptr[c + 1]; ++g) stage[g] = c;
+  Y.dboff.assign(ng + 1, 0);
+  for (int g = 0; g < ng; ++g) {
+    const int k = L.gptr[g + 1] - L.gptr[g];
+    Y.dboff[g + 1] = Y.dboff[g] + k * k;
+  }
+  Y.dblk.assign(Y.dboff[ng], 0.0);
+  Y.dsrc.assign(Y.dboff[ng], -1);
+  int maxlen = 0;
+  int64_t offcount = 0;
+  for (int p = 0; p < n; ++p) {
+    const int i = Y.perm[p], g = grp[p], g0 = Y.gstart[g], k = Y.gstart[g + 1] - g0;
+    int len = 0;
+    bool hasdiag = false;
+    for (int e = L.rp[i]; e < L.rp[i + 1]; ++e) {
+      const int q = Y.iperm[L.ci[e]];
+      if (q >= g0 && q < g0 + k) {
+        const int idx = Y.dboff[g] + (p - g0) * k + (q - g0);
+        Y.dblk[idx] += L.v[e];
+        Y.dsrc[idx] = e;
+        if (q == p) hasdiag = true;
+      } else {
+        if (stage[grp[q]] == stage[g]) throw Error(-2, "smoother stage couples two of its groups");
+        ++len;
+      }
+    }
+    if (!hasdiag) throw Error(-3, "missing diagonal entry");
+    const double d = Y.dblk[Y.dboff[g] + (p - g0) * k + (p - g0)];
+    if (!(d > 0.0)) throw Error(-3, "non-positive diagonal entry");
+    maxlen = std::max(maxlen, len);
+    offcount += len;
+  }
+  if (offcount > (int64_t)1 << 30) throw Error(-1, "level too large for 32-bit entry offsets");
+  Y.sell = point && maxlen <= 64;
+  if (Y.sell) {
+    Y.sslab.assign(ns + 1, 0);
+    for (int c = 0; c < ns; ++c) {
+      const int r0 = Y.gstart[L.sptr[c]], r1 = Y.gstart[L.sptr[c + 1]];
+      for (int b = r0; b < r1; b += 64) {
+        Slab s;
+        s.row0 = b;
+        s.nrows = std::min(64, r1 - b);
+        s.width = 0;
+        for (int p = b; p < b + s.nrows; ++p) {
+          const int i = Y.perm[p];
+          s.width = std::max(s.width, L.rp[i + 1] - L.rp[i] - 1);
+        }
+        s.off = 0;
+        Y.slabs.push_back(s);
+      }
+      Y.sslab[c + 1] = (int)Y.slabs.size();
+    }
+    int64_t tot = 0;
+    for (Slab& s : Y.slabs) {
+      s.off = (int)tot;
+      tot += (int64_t)s.width * 64;
+      if (tot > ((int64_t)1 << 31) - 1) throw Error(-1, "level too large for 32-bit slab offsets");
+    }
+    Y.col.assign(tot, 0);
+    Y.val.assign(tot, 0.0);
+    Y.src.assign(tot, -1);
+    for (const Slab& s : Y.slabs)
+      for (int lane = 0; lane < s.nrows; ++lane) {
+        const int p = s.row0 + lane, i = Y.perm[p];
+        int j = 0;
+        for (int e = L.rp[i]; e < L.rp[i + 1]; ++e) {
+          const int q = Y.iperm[L.ci[e]];
+          if (q == p) continue;
+          const int64_t at = (int64_t)s.off + (int64_t)j * 64 + lane;
+          Y.col[at] = q;
+          Y.val[at] = L.v[e];
+          Y.src[at] = e;
+          ++j;
+        }
+        for (; j < s.width; ++j) Y.col[(int64_t)s.off + (int64_t)j * 64 + lane] = p;  // zero padding
+      }
+  } else {
+    Y.rowptr.assign(n + 1, 0);
+    Y.col.reserve(offcount);
+    Y.val.reserve(offcount);
+    Y.src.reserve(offcount);
+    for (int p = 0; p < n; ++p) {
+      const int i = Y.perm[p], g = grp[p], g0 = Y.gstart[g], k = Y.gstart[g + 1] - g0;
+      for (int e = L.rp[i]; e < L.rp[i + 1]; ++e) {
+        const int q = Y.iperm[L.ci[e]];
+        if (q >= g0 && q < g0 + k) continue;
+        Y.col.push_back(q);
+        Y.val.push_back(L.v[e]);
+        Y.src.push_back(e);
+      }
+      Y.rowptr[p + 1] = (int)Y.col.size();
+    }
+    // lanes per group: about one pass over the group's entries
+    const double avg = (double)offcount / (double)ng;
+    Y.G = avg > 48 ? 64 : avg > 24 ? 32 : avg > 12 ? 16 : 8;
+  }
+}
+
+inline void build_transfer_layout(const HostLevel& L, const LevelLayout& Yf, const LevelLayout* Yc,
+                                  TransferLayout& T) {
+  const int na = (int)L.aptr.size() - 1;
+  T.nagg = na;
+  T.aptr = L.aptr;
+  T.uoff = L.uoff;
+  T.U = L.U;
+  T.arows.resize(L.arows.size());
+  for (size_t q = 0; q < L.arows.size(); ++q) T.arows[q] = Yf.iperm[L.arows[q]];
+  T.cst.resize(na);
+  T.kk.resize(na);
+  T.max_na = 0;
+  for (int a = 0; a < na; ++a) {
+    const int k = L.coff[a + 1] - L.coff[a];
+    if (k > kKmax) throw Error(-1, "aggregate basis wider than 8 columns is not supported");
+    T.kk[a] = k;
+    T.max_na = std::max(T.max_na, L.aptr[a + 1] - L.aptr[a]);
+    if (Yc) {
+      T.cst[a] = Yc->iperm[L.coff[a]];
+      for (int l = 1; l < k; ++l)
+        if (Yc->iperm[L.coff[a] + l] != T.cst[a] + l)
+          throw Error(-2, "coarse dofs of an aggregate are not a smoother group");
+    } else {
+      T.cst[a] = L.coff[a];
+    }
+  }
+}
+
+}  // namespace mvamg

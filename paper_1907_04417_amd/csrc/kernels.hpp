@@ -1,0 +1,614 @@
+// Device kernels of the solve phase (gfx950, 64-lane wavefronts).
+//
+// Storage of a level (rows renumbered into smoother order, so that every
+// smoother stage is a contiguous row range and every group a contiguous run):
+//   * point levels with short rows: sliced ELL, 64-row slabs, entries of a
+//     slab column-major (lane i reads row i's j-th entry at off + 64 j + i,
+//     one coalesced 512-byte load per wave for binary64 values);
+//   * other levels: CSR of the entries outside the diagonal blocks, G lanes
+//     per group striding over the group's contiguous entry range;
+//   * the k x k diagonal block of every group, dense row-major.
+// All kernels are HBM-bandwidth bound (about 2 flops per 12 bytes), so they
+// use plain vector FMA, not matrix cores.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hier_host.hpp"
+
+namespace mvamg {
+
+constexpr int kBlock = 256;
+
+// ----------------------------------------------------------- reductions
+
+enum Scalar {
+  S_RHO = 0,   // r.z of the current iterate
+  S_PQ = 1,    // p.A p
+  S_ALPHA = 2, // rho / pq
+  S_RR = 3,    // r.r
+  S_BETA = 4,  // CG beta
+  S_FLAG = 5,  // breakdown flag (p.Ap <= 0)
+  S_R0 = 6,    // ||r_0||^2
+  S_ZQ = 7,    // z.q (flexible beta)
+  S_NSCAL = 16
+};
+
+enum RedMode { M_STORE_RR = 0, M_PQ = 1, M_RHO0 = 2, M_RZ = 3, M_RZ_FLEX = 4, M_STORE_R0 = 5, M_NONE = 6 };
+
+struct Red {
+  double* part;       // one slot per block and value (2 * grid)
+  unsigned* counter;  // zero between launches
+  double* scal;
+  int mode;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int G>
+__device__ __forceinline__ double seg_sum(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+
+template <int G>
+__device__ __forceinline__ float seg_sum(float v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+
+// Sum over a 256-thread block in a fixed order; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) t = ((lds[0] + lds[1]) + lds[2]) + lds[3];
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ void epilogue(int mode, double v0, double v1, double* scal) {
+  switch (mode) {
+    case M_STORE_RR: scal[S_RR] = v0; break;
+    case M_STORE_R0: scal[S_R0] = v0; break;
+    case M_PQ:
+      scal[S_PQ] = v0;
+      if (!(v0 > 0.0)) scal[S_FLAG] = 1.0;
+      scal[S_ALPHA] = scal[S_RHO] / v0;
+      break;
+    case M_RHO0: scal[S_RHO] = v0; break;
+    case M_RZ:
+      scal[S_BETA] = v0 / scal[S_RHO];
+      scal[S_RHO] = v0;
+      break;
+    case M_RZ_FLEX:
+      scal[S_ZQ] = v1;
+      scal[S_BETA] = -scal[S_ALPHA] * v1 / scal[S_RHO];
+      scal[S_RHO] = v0;
+      break;
+  }
+}
+
+// Grid-wide deterministic reduction of up to two values: every block writes
+// its partial sums, the last block to finish adds the partials in block order
+// and applies the epilogue.  Partials and the counter are published with
+// device-scope fences (the L2 caches of the XCDs are not coherent otherwise).
+template <int NV>
+__device__ void grid_reduce(double a0, double a1, Red red) {
+  __shared__ double lds[4];
+  __shared__ int last;
+  const double b0 = block_sum(a0, lds);
+  double b1 = 0.0;
+  if (NV > 1) b1 = block_sum(a1, lds);
+  if (threadIdx.x == 0) {
+    red.part[blockIdx.x] = b0;
+    if (NV > 1) red.part[gridDim.x + blockIdx.x] = b1;
+    __threadfence();
+    const unsigned t = __hip_atomic_fetch_add(red.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const volatile double* part = red.part;
+  double s0 = 0.0, s1 = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += kBlock) {
+    s0 += part[i];
+    if (NV > 1) s1 += part[gridDim.x + i];
+  }
+  s0 = block_sum(s0, lds);
+  if (NV > 1) s1 = block_sum(s1, lds);
+  if (threadIdx.x == 0) {
+    epilogue(red.mode, s0, s1, red.scal);
+    *red.counter = 0u;
+    __threadfence();
+  }
+}
+
+// ------------------------------------------------------- vector kernels
+
+__global__ __launch_bounds__(kBlock) void k_gather(int n, const int* __restrict__ perm,
+                                                   const double* __restrict__ in, double* __restrict__ out) {
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) out[p] = in[perm[p]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(int n, const int* __restrict__ perm,
+                                                    const double* __restrict__ in, double* __restrict__ out) {
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) out[perm[p]] = in[p];
+}
+
+template <typename Ti, typename To>
+__global__ __launch_bounds__(kBlock) void k_cast(int n, const Ti* __restrict__ in, To* __restrict__ out) {
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) out[p] = (To)in[p];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy(int n, const T* __restrict__ in, T* __restrict__ out) {
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) out[p] = in[p];
+}
+
+// sum of a.b (and c.d) with an epilogue
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_dot(int n, const double* __restrict__ a, const double* __restrict__ b,
+                                                const double* __restrict__ c, const double* __restrict__ d, Red red) {
+  double s0 = 0.0, s1 = 0.0;
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) {
+    s0 += a[p] * b[p];
+    if (NV > 1) s1 += c[p] * d[p];
+  }
+  grid_reduce<NV>(s0, s1, red);
+}
+
+// x += alpha p; r -= alpha q; sum r.r
+__global__ __launch_bounds__(kBlock) void k_axpy2_dot(int n, const double* __restrict__ scal,
+                                                      const double* __restrict__ p, const double* __restrict__ q,
+                                                      double* __restrict__ x, double* __restrict__ r, Red red) {
+  const double alpha = scal[S_ALPHA];
+  double s = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  grid_reduce<1>(s, 0.0, red);
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(kBlock) void k_xpay(int n, const double* __restrict__ scal, const double* __restrict__ z,
+                                                 double* __restrict__ p) {
+  const double beta = scal[S_BETA];
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = z[i] + beta * p[i];
+}
+
+// ------------------------------------------------- sliced-ELL (point) levels
+
+// One Gauss-Seidel stage: x_p <- (r_p - sum_{j != p} a_pj x_j) / a_pp for the
+// rows of the slabs [s0, s1) (rows of one stage are not coupled).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ slabs, int s0, int s1,
+                                                    const int* __restrict__ col, const T* __restrict__ val,
+                                                    const T* __restrict__ diag, const T* __restrict__ r, T* x) {
+  const int s = s0 + blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (s >= s1) return;
+  const int lane = threadIdx.x & 63;
+  const Slab sl = slabs[s];
+  if (lane >= sl.nrows) return;
+  const int p = sl.row0 + lane;
+  const int* c = col + sl.off + lane;
+  const T* v = val + sl.off + lane;
+  T acc = r[p];
+  for (int j = 0; j < sl.width; ++j) acc -= v[64 * j] * x[c[64 * j]];
+  x[p] = acc / diag[p];
+}
+
+// Forward sweep from x = 0: stage 0 rows get r_p / a_pp (their neighbours are
+// still zero), every other row is zeroed.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_zero_stage0_point(int n, int rows0, const T* __restrict__ diag,
+                                                              const T* __restrict__ r, T* __restrict__ x) {
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock)
+    x[p] = (p < rows0) ? r[p] / diag[p] : T(0);
+}
+
+// s = r - A x (MODE 0), or y = A x with sum x.y (MODE 1, binary64 only)
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ slabs, int nslabs,
+                                                       const int* __restrict__ col, const T* __restrict__ val,
+                                                       const T* __restrict__ diag, const T* __restrict__ r,
+                                                       const T* __restrict__ x, T* __restrict__ s, Red red) {
+  const int sidx = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  double dsum = 0.0;
+  if (sidx < nslabs) {
+    const Slab sl = slabs[sidx];
+    if (lane < sl.nrows) {
+      const int p = sl.row0 + lane;
+      const int* c = col + sl.off + lane;
+      const T* v = val + sl.off + lane;
+      const T xp = x[p];
+      T acc = diag[p] * xp;
+      for (int j = 0; j < sl.width; ++j) acc += v[64 * j] * x[c[64 * j]];
+      if (MODE == 0) {
+        s[p] = r[p] - acc;
+      } else {
+        s[p] = acc;
+        dsum = (double)xp * (double)acc;
+      }
+    }
+  }
+  if (MODE == 1) grid_reduce<1>(dsum, 0.0, red);
+}
+
+// ------------------------------------------------------ grouped levels
+
+// Sum of the off-group entries of the group's rows, acc[l] for row l < k.
+template <typename T, int G>
+__device__ __forceinline__ void group_offsum(int p0, int k, const int* __restrict__ rowptr,
+                                             const int* __restrict__ col, const T* __restrict__ val, const T* x,
+                                             int lane, T (&acc)[kKmax]) {
+  // row boundaries; entries past row k-1 repeat rowptr[p0 + k] (every load in bounds)
+  int rb[kKmax + 1];
+#pragma unroll
+  for (int q = 0; q <= kKmax; ++q) rb[q] = rowptr[p0 + min(q, k)];
+#pragma unroll
+  for (int q = 0; q < kKmax; ++q) acc[q] = T(0);
+  const int e1 = rb[k];
+  for (int e = rb[0] + lane; e < e1; e += G) {
+    const T t = val[e] * x[col[e]];
+#pragma unroll
+    for (int q = 0; q < kKmax; ++q)
+      if (e >= rb[q] && e < rb[q + 1]) acc[q] += t;
+  }
+#pragma unroll
+  for (int q = 0; q < kKmax; ++q)
+    if (q < k) acc[q] = seg_sum<G>(acc[q]);
+}
+
+// One Gauss-Seidel stage on the groups [g0, g1): every group relaxes its rows
+// one after the other (forward: l = 0..k-1, backward: l = k-1..0) using the
+// latest values of the other rows.
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_gs_grp(int g0, int g1, const int* __restrict__ gstart,
+                                                   const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                   const T* __restrict__ val, const int* __restrict__ dboff,
+                                                   const T* __restrict__ dblk, const T* __restrict__ r, T* x,
+                                                   int backward) {
+  const int g = g0 + blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  if (g >= g1) return;
+  const int lane = threadIdx.x % G;
+  const int p0 = gstart[g], k = gstart[g + 1] - p0;
+  T acc[kKmax];
+  group_offsum<T, G>(p0, k, rowptr, col, val, x, lane, acc);
+  T xv[kKmax], rv[kKmax];
+#pragma unroll
+  for (int q = 0; q < kKmax; ++q) {
+    const int qq = min(q, k - 1);
+    const T xq = x[p0 + qq], rq = r[p0 + qq];
+    xv[q] = (q < k) ? xq : T(0);
+    rv[q] = (q < k) ? rq : T(0);
+  }
+  const T* B = dblk + dboff[g];
+  if (!backward) {
+#pragma unroll
+    for (int l = 0; l < kKmax; ++l) {
+      if (l < k) {
+        T s = rv[l] - acc[l];
+#pragma unroll
+        for (int q = 0; q < kKmax; ++q)
+          if (q < k && q != l) s -= B[l * k + q] * xv[q];
+        xv[l] = s / B[l * k + l];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int l = kKmax - 1; l >= 0; --l) {
+      if (l < k) {
+        T s = rv[l] - acc[l];
+#pragma unroll
+        for (int q = 0; q < kKmax; ++q)
+          if (q < k && q != l) s -= B[l * k + q] * xv[q];
+        xv[l] = s / B[l * k + l];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kKmax; ++q)
+    if (q < k && lane == q % G) x[p0 + q] = xv[q];
+}
+
+// Forward sweep from x = 0 on a grouped level: the groups of stage 0 solve
+// their lower-triangular block (the rest of the row multiplies zeros); all
+// other rows are zeroed.  One thread per group.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_zero_stage0_grp(int ng, int ng0, const int* __restrict__ gstart,
+                                                            const int* __restrict__ dboff, const T* __restrict__ dblk,
+                                                            const T* __restrict__ r, T* __restrict__ x) {
+  for (int g = blockIdx.x * kBlock + threadIdx.x; g < ng; g += gridDim.x * kBlock) {
+    const int p0 = gstart[g], k = gstart[g + 1] - p0;
+    if (g >= ng0) {
+      for (int q = 0; q < k; ++q) x[p0 + q] = T(0);
+      continue;
+    }
+    const T* B = dblk + dboff[g];
+    T xv[kKmax];
+#pragma unroll
+    for (int l = 0; l < kKmax; ++l) {
+      xv[l] = T(0);
+      if (l < k) {
+        T s = r[p0 + l];
+#pragma unroll
+        for (int q = 0; q < kKmax; ++q)
+          if (q < l) s -= B[l * k + q] * xv[q];
+        xv[l] = s / B[l * k + l];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kKmax; ++q)
+      if (q < k) x[p0 + q] = xv[q];
+  }
+}
+
+// s = r - A x (MODE 0) or y = A x with sum x.y (MODE 1, binary64) on all groups.
+template <typename T, int G, int MODE>
+__global__ __launch_bounds__(kBlock) void k_resid_grp(int ng, const int* __restrict__ gstart,
+                                                      const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                      const T* __restrict__ val, const int* __restrict__ dboff,
+                                                      const T* __restrict__ dblk, const T* __restrict__ r,
+                                                      const T* __restrict__ x, T* __restrict__ s, Red red) {
+  const int g = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  double dsum = 0.0;
+  if (g < ng) {
+    const int p0 = gstart[g], k = gstart[g + 1] - p0;
+    T acc[kKmax];
+    group_offsum<T, G>(p0, k, rowptr, col, val, x, lane, acc);
+    T xv[kKmax];
+#pragma unroll
+    for (int q = 0; q < kKmax; ++q) {
+      const T xq = x[p0 + min(q, k - 1)];
+      xv[q] = (q < k) ? xq : T(0);
+    }
+    const T* B = dblk + dboff[g];
+#pragma unroll
+    for (int l = 0; l < kKmax; ++l) {
+      if (l < k && lane == l % G) {
+        T t = acc[l];
+#pragma unroll
+        for (int q = 0; q < kKmax; ++q)
+          if (q < k) t += B[l * k + q] * xv[q];
+        if (MODE == 0) {
+          s[p0 + l] = r[p0 + l] - t;
+        } else {
+          s[p0 + l] = t;
+          dsum += (double)xv[l] * (double)t;
+        }
+      }
+    }
+  }
+  if (MODE == 1) grid_reduce<1>(dsum, 0.0, red);
+}
+
+// ------------------------------------------------------------ l1-Jacobi
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_l1_init(int n, const T* __restrict__ dl1, const T* __restrict__ r,
+                                                    T* __restrict__ x) {
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) x[p] = r[p] / dl1[p];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_l1_update(int n, const T* __restrict__ dl1, const T* __restrict__ s,
+                                                      T* __restrict__ x) {
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) x[p] += s[p] / dl1[p];
+}
+
+// l1 row norms d_p = sum_j |a_pj| (entries outside and inside the diagonal block)
+__global__ __launch_bounds__(kBlock) void k_l1norm_sell(const Slab* __restrict__ slabs, int nslabs,
+                                                        const double* __restrict__ val, const double* __restrict__ diag,
+                                                        double* __restrict__ dl1) {
+  const int sidx = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (sidx >= nslabs) return;
+  const Slab sl = slabs[sidx];
+  if (lane >= sl.nrows) return;
+  double a = fabs(diag[sl.row0 + lane]);
+  for (int j = 0; j < sl.width; ++j) a += fabs(val[sl.off + 64 * j + lane]);
+  dl1[sl.row0 + lane] = a;
+}
+
+__global__ __launch_bounds__(kBlock) void k_l1norm_grp(int ng, const int* __restrict__ gstart,
+                                                       const int* __restrict__ rowptr, const double* __restrict__ val,
+                                                       const int* __restrict__ dboff, const double* __restrict__ dblk,
+                                                       double* __restrict__ dl1) {
+  for (int g = blockIdx.x * kBlock + threadIdx.x; g < ng; g += gridDim.x * kBlock) {
+    const int p0 = gstart[g], k = gstart[g + 1] - p0;
+    for (int l = 0; l < k; ++l) {
+      double a = 0.0;
+      for (int e = rowptr[p0 + l]; e < rowptr[p0 + l + 1]; ++e) a += fabs(val[e]);
+      for (int q = 0; q < k; ++q) a += fabs(dblk[dboff[g] + l * k + q]);
+      dl1[p0 + l] = a;
+    }
+  }
+}
+
+// ------------------------------------------------------------- transfers
+
+// r_c = P^T s with P = blockdiag(U_a): one wave per aggregate, lane li takes
+// member li; r_c[cst_a + l] = sum_li U_a[li, l] s[member li].
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict(int nagg, const int* __restrict__ aptr,
+                                                     const int* __restrict__ arows, const int* __restrict__ uoff,
+                                                     const int* __restrict__ cst, const int* __restrict__ kk,
+                                                     const T* __restrict__ U, const T* __restrict__ s,
+                                                     T* __restrict__ rc) {
+  const int a = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (a >= nagg) return;
+  const int lane = threadIdx.x & 63;
+  const int m0 = aptr[a], na = aptr[a + 1] - m0, k = kk[a];
+  const T* Ua = U + uoff[a];
+  T acc[kKmax];
+#pragma unroll
+  for (int q = 0; q < kKmax; ++q) acc[q] = T(0);
+  for (int li = lane; li < na; li += 64) {
+    const T sv = s[arows[m0 + li]];
+#pragma unroll
+    for (int q = 0; q < kKmax; ++q)
+      if (q < k) acc[q] += Ua[li * k + q] * sv;
+  }
+  const int c0 = cst[a];
+#pragma unroll
+  for (int q = 0; q < kKmax; ++q) {
+    if (q < k) {
+      const T t = seg_sum<64>(acc[q]);
+      if (lane == q) rc[c0 + q] = t;
+    }
+  }
+}
+
+// x += P x_c: lane li of the aggregate's wave updates member li.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(int nagg, const int* __restrict__ aptr,
+                                                    const int* __restrict__ arows, const int* __restrict__ uoff,
+                                                    const int* __restrict__ cst, const int* __restrict__ kk,
+                                                    const T* __restrict__ U, const T* __restrict__ xc,
+                                                    T* __restrict__ x) {
+  const int a = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (a >= nagg) return;
+  const int lane = threadIdx.x & 63;
+  const int m0 = aptr[a], na = aptr[a + 1] - m0, k = kk[a], c0 = cst[a];
+  const T* Ua = U + uoff[a];
+  T xv[kKmax];
+#pragma unroll
+  for (int q = 0; q < kKmax; ++q) {
+    const T xq = xc[c0 + min(q, k - 1)];
+    xv[q] = (q < k) ? xq : T(0);
+  }
+  for (int li = lane; li < na; li += 64) {
+    T t = T(0);
+#pragma unroll
+    for (int q = 0; q < kKmax; ++q)
+      if (q < k) t += Ua[li * k + q] * xv[q];
+    x[arows[m0 + li]] += t;
+  }
+}
+
+// ------------------------------------------------------------- coarsest
+
+// y = A x (add = 0) or y += A x (add = 1), A dense row-major n x n, one wave per row.
+__global__ __launch_bounds__(kBlock) void k_gemv(int n, const double* __restrict__ A, const double* __restrict__ x,
+                                                 double* __restrict__ y, int add) {
+  const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const int lane = threadIdx.x & 63;
+  const double* Ai = A + (size_t)i * n;
+  double acc = 0.0;
+  for (int j = lane; j < n; j += 64) acc += Ai[j] * x[j];
+  acc = wave_sum(acc);
+  if (lane == 0) y[i] = add ? y[i] + acc : acc;
+}
+
+// t = r - A z with A in CSR (coarsest level), one wave per row.
+__global__ __launch_bounds__(kBlock) void k_csr_resid_wave(int n, const int* __restrict__ rp,
+                                                           const int* __restrict__ ci, const double* __restrict__ v,
+                                                           const double* __restrict__ r, const double* __restrict__ z,
+                                                           double* __restrict__ t) {
+  const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const int lane = threadIdx.x & 63;
+  double acc = 0.0;
+  for (int e = rp[i] + lane; e < rp[i + 1]; e += 64) acc += v[e] * z[ci[e]];
+  acc = wave_sum(acc);
+  if (lane == 0) t[i] = r[i] - acc;
+}
+
+// Dense Cholesky A = L L^T (lower triangle overwrites A), one block of 1024
+// threads, left-looking by columns.  flag is set if a pivot is not positive.
+__global__ __launch_bounds__(1024) void k_cholesky(int n, double* M, int* flag) {
+  __shared__ double red[16];
+  for (int j = 0; j < n; ++j) {
+    double part = 0.0;
+    for (int k = threadIdx.x; k < j; k += 1024) part += M[(size_t)j * n + k] * M[(size_t)j * n + k];
+    part = wave_sum(part);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int w = 0; w < 16; ++w) s += red[w];
+      const double d = M[(size_t)j * n + j] - s;
+      if (!(d > 0.0)) *flag = 1;
+      M[(size_t)j * n + j] = sqrt(d);
+    }
+    __syncthreads();
+    const double ljj = M[(size_t)j * n + j];
+    for (int i = j + 1 + threadIdx.x; i < n; i += 1024) {
+      double t = M[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) t -= M[(size_t)i * n + k] * M[(size_t)j * n + k];
+      M[(size_t)i * n + j] = t / ljj;
+    }
+    __syncthreads();
+  }
+}
+
+// X = A^{-1} = L^{-T} L^{-1}: thread j solves L y = e_j then L^T x = y for
+// column j of X (row-major; neighbouring threads touch neighbouring columns).
+__global__ __launch_bounds__(kBlock) void k_chol_inverse(int n, const double* __restrict__ L, double* __restrict__ X) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  for (int i = 0; i < n; ++i) {
+    double s = (i == j) ? 1.0 : 0.0;
+    if (i >= j) {
+      for (int k = j; k < i; ++k) s -= L[(size_t)i * n + k] * X[(size_t)k * n + j];
+      s /= L[(size_t)i * n + i];
+    }
+    X[(size_t)i * n + j] = s;
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = X[(size_t)i * n + j];
+    for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * X[(size_t)k * n + j];
+    X[(size_t)i * n + j] = s / L[(size_t)i * n + i];
+  }
+}
+
+// Dense copy of a CSR matrix (coarsest level) into M (zeroed beforehand).
+__global__ __launch_bounds__(kBlock) void k_csr_to_dense(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                         const double* __restrict__ v, double* __restrict__ M) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    for (int e = rp[i]; e < rp[i + 1]; ++e) M[(size_t)i * n + ci[e]] += v[e];
+}
+
+// ------------------------------------------------- values, casts, gradient
+
+// dst[e] = src_idx[e] >= 0 ? val[src_idx[e]] : 0 (layout fill from file-order values)
+__global__ __launch_bounds__(kBlock) void k_fill_values(int64_t m, const int* __restrict__ src,
+                                                        const double* __restrict__ val, double* __restrict__ dst) {
+  for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < m; e += (int64_t)gridDim.x * kBlock) {
+    const int s = src[e];
+    dst[e] = (s >= 0) ? val[s] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_f32(int64_t m, const double* __restrict__ in, float* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < m; e += (int64_t)gridDim.x * kBlock)
+    out[e] = (float)in[e];
+}
+
+// dval[e] = -lambda_i x_j for the stored entries (i, j) of a CSR pattern
+__global__ __launch_bounds__(kBlock) void k_grad_coeffs(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                        const double* __restrict__ lam, const double* __restrict__ x,
+                                                        double* __restrict__ dval) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const double li = lam[i];
+    for (int e = rp[i]; e < rp[i + 1]; ++e) dval[e] = -li * x[ci[e]];
+  }
+}
+
+}  // namespace mvamg

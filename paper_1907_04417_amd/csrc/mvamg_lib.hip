@@ -1,0 +1,767 @@
+// C ABI of the MI355X solve phase (declared in include/mvamg.h): hierarchy
+// upload, V-cycle (Section 5: forward/backward Gauss-Seidel, block-diagonal
+// multiple-vector transfers of Section 4, exact coarsest solve) and
+// preconditioned CG with the paper's stopping rule (Section 5).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "hier_host.hpp"
+#include "kernels.hpp"
+#include "mvamg.h"
+
+using namespace mvamg;
+
+struct mvamg_hier_host {
+  HostHier h;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+void hipcheck(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error(MVAMG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHECK(x) hipcheck((x), #x)
+#define LAUNCHCHECK(name) hipcheck(hipGetLastError(), name)
+
+int grid_for(int64_t n) {
+  int64_t b = (n + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > 2048) b = 2048;
+  return (int)b;
+}
+
+struct DevLevel {
+  int n = 0;
+  bool sell = false;
+  int G = 64;
+  int ng = 0, ns = 0, nslabs = 0;
+  int rows0 = 0;  // rows of stage 0 (point levels)
+  std::vector<int> h_sgrp, h_sslab;
+  int64_t nent = 0;    // stored off-group entries (with padding)
+  int64_t ndblk = 0;
+  // device arrays
+  Slab* slabs = nullptr;
+  int* rowptr = nullptr;
+  int* col = nullptr;
+  double* val = nullptr;
+  float* val32 = nullptr;
+  int* src = nullptr;
+  int* gstart = nullptr;
+  int* dboff = nullptr;
+  double* dblk = nullptr;
+  float* dblk32 = nullptr;
+  int* dsrc = nullptr;
+  double* diag = nullptr;  // point levels: the diagonal (alias of dblk)
+  float* diag32 = nullptr;
+  double* dl1 = nullptr;
+  float* dl1_32 = nullptr;
+  // work vectors
+  double *r = nullptr, *x = nullptr, *s = nullptr;
+  float *r32 = nullptr, *x32 = nullptr, *s32 = nullptr;
+};
+
+struct DevTransfer {
+  int nagg = 0;
+  int *aptr = nullptr, *arows = nullptr, *uoff = nullptr, *cst = nullptr, *kk = nullptr;
+  double* U = nullptr;
+  float* U32 = nullptr;
+};
+
+struct DevCoarse {
+  int n = 0;
+  double* Ainv = nullptr;
+  int *rp = nullptr, *ci = nullptr;
+  double* v = nullptr;
+  double *r = nullptr, *z = nullptr, *t = nullptr;
+};
+
+}  // namespace
+
+struct mvamg_hier {
+  int device = 0;
+  int nl = 0, n = 0;
+  int64_t nnz = 0;
+  std::vector<int> lev_n;
+  std::vector<int64_t> lev_nnz;
+  std::vector<DevLevel> lv;  // nl entries; the last holds only work vectors
+  std::vector<DevTransfer> tr;
+  DevCoarse co;
+  int* perm0 = nullptr;  // level-0 new -> file index
+  int* frp = nullptr;    // file CSR pattern of level 0
+  int* fci = nullptr;
+  // CG vectors (binary64, level-0 smoother order)
+  double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double* scal = nullptr;
+  double* part = nullptr;
+  unsigned* counter = nullptr;
+  double* pinned = nullptr;
+  std::vector<void*> allocs;
+
+  template <typename T>
+  T* dalloc(size_t count) {
+    void* ptr = nullptr;
+    if (count == 0) count = 1;
+    HIPCHECK(hipMalloc(&ptr, count * sizeof(T)));
+    allocs.push_back(ptr);
+    return (T*)ptr;
+  }
+  template <typename T>
+  T* upload_vec(const std::vector<T>& v, hipStream_t st) {
+    T* d = dalloc<T>(v.size());
+    if (!v.empty()) HIPCHECK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return d;
+  }
+  ~mvamg_hier() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (pinned) (void)hipHostFree(pinned);
+  }
+};
+
+namespace {
+
+Red mkred(mvamg_hier* h, int mode) { return Red{h->part, h->counter, h->scal, mode}; }
+
+// --------------------------------------------------------- level operators
+
+template <typename T>
+const T* lval(const DevLevel& L);
+template <>
+const double* lval<double>(const DevLevel& L) {
+  return L.val;
+}
+template <>
+const float* lval<float>(const DevLevel& L) {
+  return L.val32;
+}
+template <typename T>
+const T* ldblk(const DevLevel& L);
+template <>
+const double* ldblk<double>(const DevLevel& L) {
+  return L.dblk;
+}
+template <>
+const float* ldblk<float>(const DevLevel& L) {
+  return L.dblk32;
+}
+template <typename T>
+const T* ldl1(const DevLevel& L);
+template <>
+const double* ldl1<double>(const DevLevel& L) {
+  return L.dl1;
+}
+template <>
+const float* ldl1<float>(const DevLevel& L) {
+  return L.dl1_32;
+}
+template <typename T>
+const T* tU(const DevTransfer& P);
+template <>
+const double* tU<double>(const DevTransfer& P) {
+  return P.U;
+}
+template <>
+const float* tU<float>(const DevTransfer& P) {
+  return P.U32;
+}
+template <typename T>
+T* lr(DevLevel& L);
+template <>
+double* lr<double>(DevLevel& L) {
+  return L.r;
+}
+template <>
+float* lr<float>(DevLevel& L) {
+  return L.r32;
+}
+template <typename T>
+T* lx(DevLevel& L);
+template <>
+double* lx<double>(DevLevel& L) {
+  return L.x;
+}
+template <>
+float* lx<float>(DevLevel& L) {
+  return L.x32;
+}
+template <typename T>
+T* ls(DevLevel& L);
+template <>
+double* ls<double>(DevLevel& L) {
+  return L.s;
+}
+template <>
+float* ls<float>(DevLevel& L) {
+  return L.s32;
+}
+
+template <typename T>
+void gs_stage(const DevLevel& L, int c, const T* r, T* x, int backward, hipStream_t st) {
+  if (L.sell) {
+    const int s0 = L.h_sslab[c], s1 = L.h_sslab[c + 1];
+    if (s1 <= s0) return;
+    const int grid = (s1 - s0 + 3) / 4;
+    k_gs_sell<T><<<grid, kBlock, 0, st>>>(L.slabs, s0, s1, L.col, lval<T>(L), ldblk<T>(L), r, x);
+  } else {
+    const int g0 = L.h_sgrp[c], g1 = L.h_sgrp[c + 1];
+    if (g1 <= g0) return;
+    const int gpb = kBlock / L.G;
+    const int grid = (g1 - g0 + gpb - 1) / gpb;
+    switch (L.G) {
+      case 8: k_gs_grp<T, 8><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.rowptr, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      case 16: k_gs_grp<T, 16><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.rowptr, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      case 32: k_gs_grp<T, 32><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.rowptr, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      default: k_gs_grp<T, 64><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.rowptr, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+    }
+  }
+  LAUNCHCHECK("gs_stage");
+}
+
+template <typename T>
+void zero_stage0(const DevLevel& L, const T* r, T* x, hipStream_t st) {
+  if (L.sell) {
+    k_zero_stage0_point<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.rows0, ldblk<T>(L), r, x);
+  } else {
+    k_zero_stage0_grp<T><<<grid_for(L.ng), kBlock, 0, st>>>(L.ng, L.h_sgrp[1], L.gstart, L.dboff, ldblk<T>(L), r, x);
+  }
+  LAUNCHCHECK("zero_stage0");
+}
+
+// MODE 0: s = r - A x;  MODE 1: s = A x and x.s reduced with `red`
+template <typename T, int MODE>
+void resid(const DevLevel& L, const T* r, const T* x, T* s, Red red, hipStream_t st) {
+  if (L.sell) {
+    const int grid = (L.nslabs + 3) / 4;
+    k_resid_sell<T, MODE><<<grid, kBlock, 0, st>>>(L.slabs, L.nslabs, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red);
+  } else {
+    const int gpb = kBlock / L.G;
+    const int grid = (L.ng + gpb - 1) / gpb;
+    switch (L.G) {
+      case 8: k_resid_grp<T, 8, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.rowptr, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+      case 16: k_resid_grp<T, 16, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.rowptr, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+      case 32: k_resid_grp<T, 32, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.rowptr, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+      default: k_resid_grp<T, 64, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.rowptr, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+    }
+  }
+  LAUNCHCHECK("resid");
+}
+
+int resid_grid(const DevLevel& L) {
+  if (L.sell) return (L.nslabs + 3) / 4;
+  const int gpb = kBlock / L.G;
+  return (L.ng + gpb - 1) / gpb;
+}
+
+template <typename T>
+void coarse_solve(mvamg_hier* h, const T* r, T* z, hipStream_t st);
+
+template <>
+void coarse_solve<double>(mvamg_hier* h, const double* r, double* z, hipStream_t st) {
+  DevCoarse& C = h->co;
+  const int grid = (C.n + 3) / 4;
+  // z = A^{-1} r, one step of refinement: z += A^{-1} (r - A z)
+  k_gemv<<<grid, kBlock, 0, st>>>(C.n, C.Ainv, r, z, 0);
+  k_csr_resid_wave<<<grid, kBlock, 0, st>>>(C.n, C.rp, C.ci, C.v, r, z, C.t);
+  k_gemv<<<grid, kBlock, 0, st>>>(C.n, C.Ainv, C.t, z, 1);
+  LAUNCHCHECK("coarse_solve");
+}
+
+template <>
+void coarse_solve<float>(mvamg_hier* h, const float* r, float* z, hipStream_t st) {
+  DevCoarse& C = h->co;
+  k_cast<float, double><<<grid_for(C.n), kBlock, 0, st>>>(C.n, r, C.r);
+  coarse_solve<double>(h, C.r, C.z, st);
+  k_cast<double, float><<<grid_for(C.n), kBlock, 0, st>>>(C.n, C.z, z);
+  LAUNCHCHECK("coarse_solve32");
+}
+
+// x = B_l r (one V-cycle from a zero guess)
+template <typename T>
+void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st) {
+  if (l == h->nl - 1) {
+    coarse_solve<T>(h, r, x, st);
+    return;
+  }
+  DevLevel& L = h->lv[l];
+  DevLevel& C = h->lv[l + 1];
+  const DevTransfer& P = h->tr[l];
+  T* s = ls<T>(L);
+  T* rc = lr<T>(C);
+  T* xc = lx<T>(C);
+  const Red none = mkred(h, 0);
+  // pre-smoothing: one forward sweep from x = 0
+  if (smoother == MVAMG_SMOOTH_GS) {
+    zero_stage0<T>(L, r, x, st);
+    for (int c = 1; c < L.ns; ++c) gs_stage<T>(L, c, r, x, 0, st);
+  } else {
+    k_l1_init<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, ldl1<T>(L), r, x);
+  }
+  // residual, restriction
+  resid<T, 0>(L, r, x, s, none, st);
+  const int tg = (P.nagg + 3) / 4;
+  k_restrict<T><<<tg, kBlock, 0, st>>>(P.nagg, P.aptr, P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc);
+  LAUNCHCHECK("restrict");
+  vcycle<T>(h, l + 1, rc, xc, smoother, st);
+  k_prolong<T><<<tg, kBlock, 0, st>>>(P.nagg, P.aptr, P.arows, P.uoff, P.cst, P.kk, tU<T>(P), xc, x);
+  LAUNCHCHECK("prolong");
+  // post-smoothing: one backward sweep
+  if (smoother == MVAMG_SMOOTH_GS) {
+    for (int c = L.ns - 1; c >= 0; --c) gs_stage<T>(L, c, r, x, 1, st);
+  } else {
+    resid<T, 0>(L, r, x, s, none, st);
+    k_l1_update<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, ldl1<T>(L), s, x);
+  }
+  LAUNCHCHECK("vcycle");
+}
+
+// z = B r for level-0 binary64 vectors in smoother order
+void apply_B(mvamg_hier* h, const double* r, double* z, int precision, int smoother, hipStream_t st) {
+  if (precision == 64) {
+    vcycle<double>(h, 0, r, z, smoother, st);
+  } else {
+    DevLevel& L = h->lv[0];
+    k_cast<double, float><<<grid_for(L.n), kBlock, 0, st>>>(L.n, r, L.r32);
+    vcycle<float>(h, 0, L.r32, L.x32, smoother, st);
+    k_cast<float, double><<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.x32, z);
+    LAUNCHCHECK("apply_B32");
+  }
+}
+
+// q = A p (level 0, smoother order) with p.q into S_PQ / alpha
+void spmv0_dot(mvamg_hier* h, const double* p, double* q, int mode, hipStream_t st) {
+  resid<double, 1>(h->lv[0], nullptr, p, q, mkred(h, mode), st);
+}
+
+void dot(mvamg_hier* h, const double* a, const double* b, int mode, hipStream_t st) {
+  const int n = h->n;
+  k_dot<1><<<grid_for(n), kBlock, 0, st>>>(n, a, b, nullptr, nullptr, mkred(h, mode));
+  LAUNCHCHECK("dot");
+}
+
+void read_scalars(mvamg_hier* h, hipStream_t st) {
+  HIPCHECK(hipMemcpyAsync(h->pinned, h->scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+}
+
+void fill_level_values(mvamg_hier* h, int l, const double* val_file, hipStream_t st) {
+  DevLevel& L = h->lv[l];
+  k_fill_values<<<grid_for(L.nent), kBlock, 0, st>>>(L.nent, L.src, val_file, L.val);
+  k_fill_values<<<grid_for(L.ndblk), kBlock, 0, st>>>(L.ndblk, L.dsrc, val_file, L.dblk);
+  LAUNCHCHECK("fill_values");
+}
+
+void derive_level(mvamg_hier* h, int l, hipStream_t st) {
+  DevLevel& L = h->lv[l];
+  k_to_f32<<<grid_for(L.nent), kBlock, 0, st>>>(L.nent, L.val, L.val32);
+  k_to_f32<<<grid_for(L.ndblk), kBlock, 0, st>>>(L.ndblk, L.dblk, L.dblk32);
+  if (L.sell) {
+    k_l1norm_sell<<<(L.nslabs + 3) / 4, kBlock, 0, st>>>(L.slabs, L.nslabs, L.val, L.dblk, L.dl1);
+  } else {
+    k_l1norm_grp<<<grid_for(L.ng), kBlock, 0, st>>>(L.ng, L.gstart, L.rowptr, L.val, L.dboff, L.dblk, L.dl1);
+  }
+  k_to_f32<<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.dl1, L.dl1_32);
+  LAUNCHCHECK("derive_level");
+}
+
+mvamg_status fail_status(const Error& e) {
+  g_err = e.what();
+  return (mvamg_status)e.status;
+}
+
+void check_device(const mvamg_hier* h) {
+  int dev = -1;
+  HIPCHECK(hipGetDevice(&dev));
+  if (dev != h->device) throw Error(MVAMG_ERR_ARG, "handle used with a different current device");
+}
+
+// Core CG loop shared by solve and adjoint solve.
+mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvamg_solve_params* prm,
+                 mvamg_info* info, hipStream_t st) {
+  if (!prm || !b_file || !x_file) throw Error(MVAMG_ERR_ARG, "null argument");
+  if (prm->precision != 64 && prm->precision != 32) throw Error(MVAMG_ERR_ARG, "precision must be 64 or 32");
+  if (prm->smoother != MVAMG_SMOOTH_GS && prm->smoother != MVAMG_SMOOTH_L1JACOBI)
+    throw Error(MVAMG_ERR_ARG, "unknown smoother");
+  if (prm->maxit < 0 || !(prm->rtol >= 0.0)) throw Error(MVAMG_ERR_ARG, "invalid maxit or rtol");
+  check_device(h);
+  const int n = h->n;
+  const int eg = grid_for(n);
+  DevLevel& L0 = h->lv[0];
+  mvamg_info inf{};
+  const bool flex = (prm->precision == 32);
+  // into smoother order
+  k_gather<<<eg, kBlock, 0, st>>>(n, h->perm0, b_file, h->b);
+  k_gather<<<eg, kBlock, 0, st>>>(n, h->perm0, x_file, h->x);
+  LAUNCHCHECK("gather");
+  HIPCHECK(hipMemsetAsync(h->scal, 0, S_NSCAL * sizeof(double), st));
+  resid<double, 0>(L0, h->b, h->x, h->r, mkred(h, 0), st);
+  dot(h, h->r, h->r, M_STORE_R0, st);
+  read_scalars(h, st);
+  const double r0 = std::sqrt(h->pinned[S_R0]);
+  if (!std::isfinite(r0)) throw Error(MVAMG_ERR_NONFINITE, "non-finite initial residual (check b and x0)");
+  if (prm->history) prm->history[0] = 1.0;
+  mvamg_status status = MVAMG_NOT_CONVERGED;
+  double h_last = 1.0;
+  if (r0 == 0.0) {
+    status = MVAMG_OK;
+    inf.converged = 1;
+    h_last = 0.0;
+  } else {
+    int it = 0;
+    const int max_restarts = flex ? std::max(0, prm->max_restarts) : 0;
+    for (int restart = 0; restart <= max_restarts && it < prm->maxit; ++restart) {
+      if (restart > 0) {
+        resid<double, 0>(L0, h->b, h->x, h->r, mkred(h, 0), st);
+        inf.restarts = restart;
+      }
+      apply_B(h, h->r, h->z, prm->precision, prm->smoother, st);
+      dot(h, h->r, h->z, M_RHO0, st);
+      k_copy<double><<<eg, kBlock, 0, st>>>(n, h->z, h->p);
+      bool met = false;
+      while (it < prm->maxit) {
+        spmv0_dot(h, h->p, h->q, M_PQ, st);
+        k_axpy2_dot<<<eg, kBlock, 0, st>>>(n, h->scal, h->p, h->q, h->x, h->r, mkred(h, M_STORE_RR));
+        LAUNCHCHECK("axpy2");
+        read_scalars(h, st);
+        ++it;
+        if (h->pinned[S_FLAG] != 0.0) {
+          inf.iterations = it;
+          throw Error(MVAMG_ERR_BREAKDOWN, "CG breakdown: p^T A p <= 0 (matrix not s.p.d.)");
+        }
+        h_last = std::sqrt(h->pinned[S_RR]) / r0;
+        if (prm->history) prm->history[it] = h_last;
+        if (!std::isfinite(h_last)) throw Error(MVAMG_ERR_NONFINITE, "non-finite residual during CG");
+        if (h_last <= prm->rtol) {
+          met = true;
+          break;
+        }
+        apply_B(h, h->r, h->z, prm->precision, prm->smoother, st);
+        if (flex) {
+          k_dot<2><<<eg, kBlock, 0, st>>>(n, h->z, h->r, h->z, h->q, mkred(h, M_RZ_FLEX));
+        } else {
+          k_dot<1><<<eg, kBlock, 0, st>>>(n, h->z, h->r, nullptr, nullptr, mkred(h, M_RZ));
+        }
+        k_xpay<<<eg, kBlock, 0, st>>>(n, h->scal, h->z, h->p);
+        LAUNCHCHECK("pcg update");
+      }
+      if (!flex) {
+        if (met) status = MVAMG_OK;
+        break;
+      }
+      // binary32 cycle: confirm with the true residual in binary64
+      resid<double, 0>(L0, h->b, h->x, h->q, mkred(h, 0), st);
+      dot(h, h->q, h->q, M_STORE_RR, st);
+      read_scalars(h, st);
+      const double tr = std::sqrt(h->pinned[S_RR]) / r0;
+      if (met && tr <= prm->rtol) {
+        status = MVAMG_OK;
+        break;
+      }
+    }
+    inf.iterations = it;
+    inf.converged = (status == MVAMG_OK);
+  }
+  inf.rel_res = h_last;
+  // true residual in binary64 and back to file order
+  resid<double, 0>(L0, h->b, h->x, h->q, mkred(h, 0), st);
+  dot(h, h->q, h->q, M_STORE_RR, st);
+  k_scatter<<<eg, kBlock, 0, st>>>(n, h->perm0, h->x, x_file);
+  LAUNCHCHECK("scatter");
+  read_scalars(h, st);
+  inf.rel_res_true = (r0 > 0.0) ? std::sqrt(h->pinned[S_RR]) / r0 : 0.0;
+  if (info) *info = inf;
+  return status;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+const char* mvamg_last_error(void) { return g_err.c_str(); }
+
+mvamg_status mvamg_hier_read(const char* path, mvamg_hier_host** out) {
+  try {
+    if (!path || !out) throw Error(MVAMG_ERR_ARG, "null argument");
+    *out = nullptr;
+    std::unique_ptr<mvamg_hier_host> h(new mvamg_hier_host);
+    h->h = read_hierarchy_file(path);
+    *out = h.release();
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return MVAMG_ERR_FILE;
+  }
+}
+
+void mvamg_hier_host_free(mvamg_hier_host* h) { delete h; }
+
+mvamg_status mvamg_hier_host_info(const mvamg_hier_host* h, int* nlevels, int* n, int64_t* nnz) {
+  if (!h) {
+    g_err = "null handle";
+    return MVAMG_ERR_ARG;
+  }
+  if (nlevels) *nlevels = h->h.nl;
+  if (n) *n = h->h.lv[0].n;
+  if (nnz) *nnz = (int64_t)h->h.lv[0].ci.size();
+  return MVAMG_OK;
+}
+
+mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** out) {
+  hipStream_t st = (hipStream_t)stream;
+  std::unique_ptr<mvamg_hier> h;
+  try {
+    if (!hh || !out) throw Error(MVAMG_ERR_ARG, "null argument");
+    *out = nullptr;
+    const HostHier& H = hh->h;
+    if (H.nl < 2) throw Error(MVAMG_ERR_ARG, "hierarchy needs at least two levels");
+    h.reset(new mvamg_hier);
+    HIPCHECK(hipGetDevice(&h->device));
+    h->nl = H.nl;
+    h->n = H.lv[0].n;
+    h->nnz = (int64_t)H.lv[0].ci.size();
+    for (int l = 0; l < H.nl; ++l) {
+      h->lev_n.push_back(H.lv[l].n);
+      h->lev_nnz.push_back((int64_t)H.lv[l].ci.size());
+    }
+    // ---- layouts
+    std::vector<LevelLayout> Y(H.nl - 1);
+    for (int l = 0; l + 1 < H.nl; ++l) build_level_layout(H.lv[l], Y[l]);
+    h->lv.resize(H.nl);
+    h->tr.resize(H.nl - 1);
+    int maxgrid = 2048;
+    for (int l = 0; l + 1 < H.nl; ++l) {
+      const LevelLayout& y = Y[l];
+      DevLevel& L = h->lv[l];
+      L.n = y.n;
+      L.sell = y.sell;
+      L.G = y.G;
+      L.ng = (int)y.gstart.size() - 1;
+      L.ns = (int)y.sgrp.size() - 1;
+      L.h_sgrp = y.sgrp;
+      L.h_sslab = y.sslab;
+      L.nslabs = (int)y.slabs.size();
+      L.rows0 = y.gstart[y.sgrp[1]];
+      L.nent = (int64_t)y.val.size();
+      L.ndblk = (int64_t)y.dblk.size();
+      if (y.sell) L.slabs = h->upload_vec(y.slabs, st);
+      if (!y.sell) L.rowptr = h->upload_vec(y.rowptr, st);
+      L.col = h->upload_vec(y.col, st);
+      L.val = h->upload_vec(y.val, st);
+      L.val32 = h->dalloc<float>(y.val.size());
+      L.gstart = h->upload_vec(y.gstart, st);
+      L.dboff = h->upload_vec(y.dboff, st);
+      L.dblk = h->upload_vec(y.dblk, st);
+      L.dblk32 = h->dalloc<float>(y.dblk.size());
+      if (l == 0) {
+        L.src = h->upload_vec(y.src, st);
+        L.dsrc = h->upload_vec(y.dsrc, st);
+      }
+      L.dl1 = h->dalloc<double>(y.n);
+      L.dl1_32 = h->dalloc<float>(y.n);
+      L.s = h->dalloc<double>(y.n);
+      L.s32 = h->dalloc<float>(y.n);
+      L.r32 = h->dalloc<float>(y.n);
+      L.x32 = h->dalloc<float>(y.n);
+      if (l > 0) {
+        L.r = h->dalloc<double>(y.n);
+        L.x = h->dalloc<double>(y.n);
+      }
+      maxgrid = std::max(maxgrid, resid_grid(L));
+    }
+    for (int l = 0; l + 1 < H.nl; ++l) {
+      TransferLayout T;
+      build_transfer_layout(H.lv[l], Y[l], (l + 2 < H.nl) ? &Y[l + 1] : nullptr, T);
+      DevTransfer& P = h->tr[l];
+      P.nagg = T.nagg;
+      P.aptr = h->upload_vec(T.aptr, st);
+      P.arows = h->upload_vec(T.arows, st);
+      P.uoff = h->upload_vec(T.uoff, st);
+      P.cst = h->upload_vec(T.cst, st);
+      P.kk = h->upload_vec(T.kk, st);
+      P.U = h->upload_vec(T.U, st);
+      P.U32 = h->dalloc<float>(T.U.size());
+      k_to_f32<<<grid_for((int64_t)T.U.size()), kBlock, 0, st>>>((int64_t)T.U.size(), P.U, P.U32);
+      LAUNCHCHECK("U32");
+    }
+    // ---- coarsest level: dense Cholesky and inverse on the device
+    {
+      const HostLevel& C = H.lv[H.nl - 1];
+      DevLevel& LC = h->lv[H.nl - 1];
+      LC.n = C.n;
+      LC.r = h->dalloc<double>(C.n);
+      LC.x = h->dalloc<double>(C.n);
+      LC.r32 = h->dalloc<float>(C.n);
+      LC.x32 = h->dalloc<float>(C.n);
+      DevCoarse& D = h->co;
+      D.n = C.n;
+      if ((int64_t)C.n * C.n > ((int64_t)1 << 28)) throw Error(MVAMG_ERR_ARG, "coarsest level too large for a dense solve");
+      D.rp = h->upload_vec(C.rp, st);
+      D.ci = h->upload_vec(C.ci, st);
+      D.v = h->upload_vec(C.v, st);
+      D.r = h->dalloc<double>(C.n);
+      D.z = h->dalloc<double>(C.n);
+      D.t = h->dalloc<double>(C.n);
+      double* M = h->dalloc<double>((size_t)C.n * C.n);
+      D.Ainv = h->dalloc<double>((size_t)C.n * C.n);
+      int* flag = h->dalloc<int>(1);
+      HIPCHECK(hipMemsetAsync(M, 0, sizeof(double) * (size_t)C.n * C.n, st));
+      HIPCHECK(hipMemsetAsync(flag, 0, sizeof(int), st));
+      k_csr_to_dense<<<grid_for(C.n), kBlock, 0, st>>>(C.n, D.rp, D.ci, D.v, M);
+      k_cholesky<<<1, 1024, 0, st>>>(C.n, M, flag);
+      k_chol_inverse<<<(C.n + kBlock - 1) / kBlock, kBlock, 0, st>>>(C.n, M, D.Ainv);
+      LAUNCHCHECK("coarsest factorisation");
+      int hflag = 0;
+      HIPCHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipStreamSynchronize(st));
+      if (hflag) throw Error(MVAMG_ERR_NOT_SPD, "coarsest matrix is not positive definite (Cholesky pivot <= 0)");
+    }
+    // ---- level-0 extras and CG state
+    {
+      const int n = h->n;
+      h->perm0 = h->upload_vec(Y[0].perm, st);
+      h->frp = h->upload_vec(H.lv[0].rp, st);
+      h->fci = h->upload_vec(H.lv[0].ci, st);
+      h->b = h->dalloc<double>(n);
+      h->x = h->dalloc<double>(n);
+      h->r = h->dalloc<double>(n);
+      h->z = h->dalloc<double>(n);
+      h->p = h->dalloc<double>(n);
+      h->q = h->dalloc<double>(n);
+      h->lv[0].r = h->r;
+      h->lv[0].x = h->z;
+      h->scal = h->dalloc<double>(S_NSCAL);
+      h->part = h->dalloc<double>(2 * (size_t)maxgrid);
+      h->counter = h->dalloc<unsigned>(1);
+      HIPCHECK(hipMemsetAsync(h->counter, 0, sizeof(unsigned), st));
+      HIPCHECK(hipMemsetAsync(h->scal, 0, S_NSCAL * sizeof(double), st));
+      HIPCHECK(hipHostMalloc((void**)&h->pinned, S_NSCAL * sizeof(double), hipHostMallocDefault));
+    }
+    for (int l = 0; l + 1 < H.nl; ++l) derive_level(h.get(), l, st);
+    HIPCHECK(hipStreamSynchronize(st));
+    *out = h.release();
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    if (st) (void)hipStreamSynchronize(st);
+    return fail_status(e);
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return MVAMG_ERR_HIP;
+  }
+}
+
+void mvamg_free(mvamg_hier* h) {
+  if (!h) return;
+  (void)hipDeviceSynchronize();
+  delete h;
+}
+
+mvamg_status mvamg_levels(const mvamg_hier* h, int* nlevels, int* n, int64_t* nnz, int* stages) {
+  if (!h) {
+    g_err = "null handle";
+    return MVAMG_ERR_ARG;
+  }
+  if (nlevels) *nlevels = h->nl;
+  for (int l = 0; l < h->nl && l < 32; ++l) {
+    if (n) n[l] = h->lev_n[l];
+    if (nnz) nnz[l] = h->lev_nnz[l];
+    if (stages) stages[l] = (l + 1 < h->nl) ? h->lv[l].ns : 0;
+  }
+  return MVAMG_OK;
+}
+
+mvamg_status mvamg_set_fine_values(mvamg_hier* h, const double* val, void* stream) {
+  try {
+    if (!h || !val) throw Error(MVAMG_ERR_ARG, "null argument");
+    check_device(h);
+    hipStream_t st = (hipStream_t)stream;
+    fill_level_values(h, 0, val, st);
+    derive_level(h, 0, st);
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_spmv(mvamg_hier* h, const double* x, double* y, void* stream) {
+  try {
+    if (!h || !x || !y) throw Error(MVAMG_ERR_ARG, "null argument");
+    check_device(h);
+    hipStream_t st = (hipStream_t)stream;
+    const int eg = grid_for(h->n);
+    k_gather<<<eg, kBlock, 0, st>>>(h->n, h->perm0, x, h->p);
+    resid<double, 1>(h->lv[0], nullptr, h->p, h->q, mkred(h, M_NONE), st);
+    k_scatter<<<eg, kBlock, 0, st>>>(h->n, h->perm0, h->q, y);
+    LAUNCHCHECK("spmv");
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_cycle_apply(mvamg_hier* h, const double* r, double* z, int precision, int smoother,
+                               void* stream) {
+  try {
+    if (!h || !r || !z) throw Error(MVAMG_ERR_ARG, "null argument");
+    if (r == z) throw Error(MVAMG_ERR_ARG, "r and z must not alias");
+    if (precision != 64 && precision != 32) throw Error(MVAMG_ERR_ARG, "precision must be 64 or 32");
+    if (smoother != MVAMG_SMOOTH_GS && smoother != MVAMG_SMOOTH_L1JACOBI) throw Error(MVAMG_ERR_ARG, "unknown smoother");
+    check_device(h);
+    hipStream_t st = (hipStream_t)stream;
+    const int eg = grid_for(h->n);
+    k_gather<<<eg, kBlock, 0, st>>>(h->n, h->perm0, r, h->r);
+    apply_B(h, h->r, h->z, precision, smoother, st);
+    k_scatter<<<eg, kBlock, 0, st>>>(h->n, h->perm0, h->z, z);
+    LAUNCHCHECK("cycle_apply");
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_pcg_solve(mvamg_hier* h, const double* b, double* x, const mvamg_solve_params* prm,
+                             mvamg_info* info, void* stream) {
+  try {
+    if (!h) throw Error(MVAMG_ERR_ARG, "null handle");
+    return pcg(h, b, x, prm, info, (hipStream_t)stream);
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_adjoint_solve(mvamg_hier* h, const double* dLdx, double* lambda, const mvamg_solve_params* prm,
+                                 mvamg_info* info, void* stream) {
+  try {
+    if (!h || !lambda) throw Error(MVAMG_ERR_ARG, "null argument");
+    check_device(h);
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHECK(hipMemsetAsync(lambda, 0, sizeof(double) * (size_t)h->n, st));
+    return pcg(h, dLdx, lambda, prm, info, st);
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_grad_coeffs(mvamg_hier* h, const double* lambda, const double* x, double* dval, void* stream) {
+  try {
+    if (!h || !lambda || !x || !dval) throw Error(MVAMG_ERR_ARG, "null argument");
+    check_device(h);
+    hipStream_t st = (hipStream_t)stream;
+    k_grad_coeffs<<<grid_for(h->n), kBlock, 0, st>>>(h->n, h->frp, h->fci, lambda, x, dval);
+    LAUNCHCHECK("grad_coeffs");
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,241 @@
+"""Python binding of the C ABI in include/mvamg.h (ctypes, argument marshalling
+only).  Every step of the solve runs in the HIP library ``libmvamg.so``; there
+is no CPU fallback: if the library is missing or no GPU is present, the calls
+raise.
+
+Function names mirror the C entry points (``mvamg_`` prefix dropped).  Device
+vectors are passed as torch CUDA tensors (float64, contiguous) or raw device
+addresses; streams default to torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmvamg.so")
+
+OK, NOT_CONVERGED = 0, 1
+ERR_ARG, ERR_FILE, ERR_NOT_SPD, ERR_NONFINITE, ERR_BREAKDOWN, ERR_HIP = -1, -2, -3, -4, -5, -6
+SMOOTH_GS, SMOOTH_L1JACOBI = 0, 1
+
+EXPORTED = ["mvamg_hier_read", "mvamg_hier_host_free", "mvamg_hier_host_info", "mvamg_upload", "mvamg_free",
+            "mvamg_levels", "mvamg_set_fine_values", "mvamg_spmv", "mvamg_cycle_apply", "mvamg_pcg_solve",
+            "mvamg_adjoint_solve", "mvamg_grad_coeffs", "mvamg_last_error"]
+
+
+class MvamgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"mvamg status {status}: {msg}")
+        self.status = status
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("smoother", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("maxit", ctypes.c_int), ("max_restarts", ctypes.c_int),
+                ("history", ctypes.POINTER(ctypes.c_double))]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("rel_res", ctypes.c_double), ("rel_res_true", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmvamg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
+        L = ctypes.CDLL(path)
+        vp, P = ctypes.c_void_p, ctypes.POINTER
+        L.mvamg_hier_read.argtypes = [ctypes.c_char_p, P(vp)]
+        L.mvamg_hier_host_free.argtypes = [vp]
+        L.mvamg_hier_host_free.restype = None
+        L.mvamg_hier_host_info.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int64)]
+        L.mvamg_upload.argtypes = [vp, vp, P(vp)]
+        L.mvamg_free.argtypes = [vp]
+        L.mvamg_free.restype = None
+        L.mvamg_levels.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int64), P(ctypes.c_int)]
+        L.mvamg_set_fine_values.argtypes = [vp, vp, vp]
+        L.mvamg_spmv.argtypes = [vp, vp, vp, vp]
+        L.mvamg_cycle_apply.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+        L.mvamg_pcg_solve.argtypes = [vp, vp, vp, P(SolveParams), P(Info), vp]
+        L.mvamg_adjoint_solve.argtypes = [vp, vp, vp, P(SolveParams), P(Info), vp]
+        L.mvamg_grad_coeffs.argtypes = [vp, vp, vp, vp, vp]
+        L.mvamg_last_error.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name not in ("mvamg_hier_host_free", "mvamg_free", "mvamg_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return load().mvamg_last_error().decode()
+
+
+def _check(st, allow=(OK,)):
+    if st not in allow:
+        raise MvamgError(st, last_error())
+    return st
+
+
+def _dev(t) -> int:
+    """Device address of a torch CUDA tensor (float64/int, contiguous) or an int."""
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+# ------------------------------------------------------------- raw entry points
+
+def hier_read(path: str) -> int:
+    h = ctypes.c_void_p()
+    _check(load().mvamg_hier_read(path.encode(), ctypes.byref(h)))
+    return h.value
+
+
+def hier_host_free(hh: int) -> None:
+    load().mvamg_hier_host_free(hh)
+
+
+def hier_host_info(hh: int):
+    nl, n, nnz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+    _check(load().mvamg_hier_host_info(hh, ctypes.byref(nl), ctypes.byref(n), ctypes.byref(nnz)))
+    return nl.value, n.value, nnz.value
+
+
+def upload(hh: int, stream=None) -> int:
+    h = ctypes.c_void_p()
+    _check(load().mvamg_upload(hh, _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def free(h: int) -> None:
+    load().mvamg_free(h)
+
+
+def levels(h: int):
+    nl = ctypes.c_int()
+    n = (ctypes.c_int * 32)()
+    nnz = (ctypes.c_int64 * 32)()
+    stg = (ctypes.c_int * 32)()
+    _check(load().mvamg_levels(h, ctypes.byref(nl), n, nnz, stg))
+    k = nl.value
+    return dict(nlevels=k, n=list(n[:k]), nnz=list(nnz[:k]), stages=list(stg[:k]))
+
+
+def set_fine_values(h: int, val, stream=None) -> None:
+    _check(load().mvamg_set_fine_values(h, _dev(val), _stream(stream)))
+
+
+def spmv(h: int, x, y, stream=None) -> None:
+    _check(load().mvamg_spmv(h, _dev(x), _dev(y), _stream(stream)))
+
+
+def cycle_apply(h: int, r, z, precision: int = 64, smoother: int = SMOOTH_GS, stream=None) -> None:
+    _check(load().mvamg_cycle_apply(h, _dev(r), _dev(z), precision, smoother, _stream(stream)))
+
+
+def _params(rtol, maxit, precision, smoother, max_restarts, history):
+    hp = history.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if history is not None else None
+    return SolveParams(precision, smoother, rtol, maxit, max_restarts, hp)
+
+
+def pcg_solve(h: int, b, x, rtol=1e-8, maxit=1000, precision=64, smoother=SMOOTH_GS, max_restarts=3,
+              history: np.ndarray | None = None, stream=None) -> Info:
+    info = Info()
+    prm = _params(rtol, maxit, precision, smoother, max_restarts, history)
+    _check(load().mvamg_pcg_solve(h, _dev(b), _dev(x), ctypes.byref(prm), ctypes.byref(info), _stream(stream)),
+           allow=(OK, NOT_CONVERGED))
+    return info
+
+
+def adjoint_solve(h: int, dLdx, lam, rtol=1e-8, maxit=1000, precision=64, smoother=SMOOTH_GS, max_restarts=3,
+                  history: np.ndarray | None = None, stream=None) -> Info:
+    info = Info()
+    prm = _params(rtol, maxit, precision, smoother, max_restarts, history)
+    _check(load().mvamg_adjoint_solve(h, _dev(dLdx), _dev(lam), ctypes.byref(prm), ctypes.byref(info),
+                                      _stream(stream)), allow=(OK, NOT_CONVERGED))
+    return info
+
+
+def grad_coeffs(h: int, lam, x, dval, stream=None) -> None:
+    _check(load().mvamg_grad_coeffs(h, _dev(lam), _dev(x), _dev(dval), _stream(stream)))
+
+
+# ------------------------------------------------------------ convenience class
+
+@dataclass
+class SolveResult:
+    iterations: int
+    converged: bool
+    rel_res: float
+    rel_res_true: float
+    restarts: int
+    history: np.ndarray
+
+
+class Solver:
+    """A hierarchy file uploaded to the current GPU."""
+
+    def __init__(self, path: str, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("mvamg needs a GPU (HIP device)")
+        hh = hier_read(path)
+        try:
+            self.nlevels, self.n, self.nnz = hier_host_info(hh)
+            self.h = upload(hh, stream)
+        finally:
+            hier_host_free(hh)
+        self.info = levels(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, b, x=None, rtol=1e-8, maxit=1000, precision=64, smoother=SMOOTH_GS, max_restarts=3,
+              stream=None):
+        import torch
+        if x is None:
+            x = torch.zeros_like(b)
+        hist = np.zeros(maxit + 1)
+        inf = pcg_solve(self.h, b, x, rtol, maxit, precision, smoother, max_restarts, hist, stream)
+        return x, SolveResult(inf.iterations, bool(inf.converged), inf.rel_res, inf.rel_res_true, inf.restarts,
+                              hist[:inf.iterations + 1].copy())
+
+    def cycle(self, r, precision=64, smoother=SMOOTH_GS, stream=None):
+        import torch
+        z = torch.empty_like(r)
+        cycle_apply(self.h, r, z, precision, smoother, stream)
+        return z
+
+    def spmv(self, x, stream=None):
+        import torch
+        y = torch.empty_like(x)
+        spmv(self.h, x, y, stream)
+        return y

@@ -1,0 +1,57 @@
+"""Named synthetic workloads: problem generator + setup parameters, with the
+hierarchy file cached on disk (setup is the untimed input generator).
+
+    aniso64   2-D rotated anisotropic diffusion, 9-point, 64 x 64 interior grid
+              (eps = 1e-2, theta = pi/4), at most 3 smooth vectors
+    jump128   3-D jump-coefficient diffusion, 7-point, 128^3 (coefficient 1e3
+              or 1e-3 on 8^3 cubes selected with p = 0.5, else 1), at most 4
+              smooth vectors
+    jump32    the same family on 32^3 (test size)
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import math
+import os
+
+from . import problems
+from .setup import SetupParams, build_hierarchy
+
+CONFIGS = {
+    "aniso64": dict(gen=lambda: problems.aniso9(64, 1e-2, math.pi / 4, seed=0), nvec=3, setup={}),
+    "aniso128": dict(gen=lambda: problems.aniso9(128, 1e-2, math.pi / 4, seed=0), nvec=3, setup={}),
+    "jump128": dict(gen=lambda: problems.jump7(128, 8, 0.5, seed=0), nvec=4, setup={}),
+    "jump32": dict(gen=lambda: problems.jump7(32, 4, 0.5, seed=1), nvec=4, setup={}),
+    "jump16": dict(gen=lambda: problems.jump7(16, 2, 0.5, seed=2), nvec=4,
+                   setup=dict(boot_coarse_min=8, coarse_cap=64, compose=2)),
+}
+
+BOOTSTRAP_SEED = 1000
+
+
+def cache_dir() -> str:
+    d = os.environ.get("MVAMG_CACHE", "/tmp/mvamg_cache")
+    os.makedirs(d, exist_ok=True)
+    return d
+
+
+def load(name: str, **setup_overrides):
+    """Returns (problem, hierarchy_path, setup_stats)."""
+    cfg = CONFIGS[name]
+    P = cfg["gen"]()
+    sp = dict(cfg["setup"])
+    sp.update(setup_overrides)
+    params = SetupParams(nvec_max=cfg["nvec"], **sp)
+    key = hashlib.sha1(json.dumps([name, sorted(params.__dict__.items())], default=str).encode()).hexdigest()[:12]
+    path = os.path.join(cache_dir(), f"{name}_{key}.bin")
+    meta = path + ".json"
+    if os.path.exists(path) and os.path.exists(meta):
+        with open(meta) as f:
+            return P, path, json.load(f)
+    x0 = problems.random_vectors(P.n, max(cfg["nvec"] - 1, 1), BOOTSTRAP_SEED)
+    st = build_hierarchy(P.rowptr, P.col, P.val, path + ".tmp", x0, params)
+    os.replace(path + ".tmp", path)
+    with open(meta, "w") as f:
+        json.dump(st, f)
+    return P, path, st

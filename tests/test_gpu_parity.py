@@ -1,0 +1,200 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same hierarchy file and the same seeded inputs.
+
+Tolerances: binary64 cycle and CG history 1e-10 relative, solution 1e-9
+relative (rounding-order differences only: parallel reductions, FMA
+contraction); binary32 cycle 1e-4 relative to the oracle's binary32 cycle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1907_04417_amd import mvamg, workloads
+
+pytestmark = pytest.mark.gpu
+
+WORKLOADS = ["aniso64", "jump16", "jump32"]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="session")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="session")
+def cases(torch_gpu):
+    out = {}
+    for name in WORKLOADS:
+        P, path, st = workloads.load(name)
+        _say(f"[case] {name}: n={P.n} nnz={P.nnz} levels={st['n']}")
+        out[name] = (P, path, st, mvamg.Solver(path), oracle.Oracle(path))
+    return out
+
+
+def _t(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _relinf(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_spmv_parity(name, cases, torch_gpu):
+    P, path, st, S, O = cases[name]
+    _say(f"[spmv] {name}")
+    x = np.random.default_rng(1).standard_normal(P.n)
+    y = S.spmv(_t(torch_gpu, x)).cpu().numpy()
+    assert _relinf(y, oracle.spmv(P.rowptr, P.col, P.val, x)) <= 1e-13
+
+
+@pytest.mark.parametrize("smoother", [mvamg.SMOOTH_GS, mvamg.SMOOTH_L1JACOBI])
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_cycle_parity(name, smoother, cases, torch_gpu):
+    P, path, st, S, O = cases[name]
+    _say(f"[cycle] {name} smoother={smoother}")
+    Oc = O if smoother == mvamg.SMOOTH_GS else oracle.Oracle(path, smoother=oracle.L1_JACOBI)
+    r = np.random.default_rng(2).standard_normal(P.n)
+    z = S.cycle(_t(torch_gpu, r), smoother=smoother).cpu().numpy()
+    assert _relinf(z, Oc.vcycle(r)) <= 1e-11
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_cycle_fp32_parity(name, cases, torch_gpu):
+    P, path, st, S, O = cases[name]
+    _say(f"[cycle32] {name}")
+    r = np.random.default_rng(3).standard_normal(P.n)
+    z = S.cycle(_t(torch_gpu, r), precision=32).cpu().numpy()
+    z32 = O.vcycle32(r.astype(np.float32)).astype(np.float64)
+    z64 = O.vcycle(r)
+    assert np.linalg.norm(z - z32) <= 1e-4 * np.linalg.norm(z32)
+    assert np.linalg.norm(z - z64) <= 1e-4 * np.linalg.norm(z64)
+
+
+def _hist_parity(hg, ho, tol):
+    """Same iteration count (one more or less only when the last residual is
+    within 1e-8 relative of the tolerance) and histories equal to 1e-10."""
+    m = min(len(hg), len(ho))
+    if len(hg) != len(ho):
+        assert abs(len(hg) - len(ho)) == 1 and abs(ho[m - 1] / tol - 1) < 1e-8
+    rel = np.abs(hg[:m] - ho[:m]) / ho[:m]
+    assert rel.max() <= 1e-10, rel.max()
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_pcg_parity_fp64(name, cases, torch_gpu):
+    P, path, st, S, O = cases[name]
+    _say(f"[pcg64] {name}")
+    x, res = S.solve(_t(torch_gpu, P.b), rtol=1e-8)
+    xo, ho, nito, sto = O.pcg(P.b, tol=1e-8)
+    assert res.converged and sto == 0
+    _hist_parity(res.history, ho, 1e-8)
+    assert _relinf(x.cpu().numpy(), xo) <= 1e-9
+    assert res.rel_res_true <= 1.01e-8
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_pcg_mixed_precision(name, cases, torch_gpu):
+    """Binary32 cycle, binary64 flexible CG: meets the tolerance on the true
+    residual; iteration count close to the oracle's mixed run; error against
+    the binary64 oracle solution reported."""
+    P, path, st, S, O = cases[name]
+    _say(f"[pcg32] {name}")
+    x, res = S.solve(_t(torch_gpu, P.b), rtol=1e-8, precision=32)
+    xo, ho, nito, sto, tro = O.pcg_mixed(P.b, tol=1e-8)
+    x64, _, nit64, _ = O.pcg(P.b, tol=1e-8)
+    assert res.converged and res.rel_res_true <= 1e-8
+    assert abs(res.iterations - nito) <= max(3, nito // 10)
+    err = _relinf(x.cpu().numpy(), x64)
+    _say(f"  mixed: it={res.iterations} (oracle mixed {nito}, fp64 {nit64}) err_vs_fp64={err:.2e}")
+    assert err <= 1e-5
+
+
+def test_nearby_matrix_values(cases, torch_gpu):
+    P, path, st, S0, O = cases["jump16"]
+    _say("[nearby] jump16")
+    S = mvamg.Solver(path)
+    rng = np.random.default_rng(5)
+    # a near-by s.p.d. matrix with the same pattern: D A D, D = exp(0.05 N(0, 1))
+    d = np.exp(0.05 * rng.standard_normal(P.n))
+    rows = np.repeat(np.arange(P.n), np.diff(P.rowptr))
+    v2 = P.val * d[rows] * d[P.col]
+    mvamg.set_fine_values(S.h, _t(torch_gpu, v2))
+    b = rng.standard_normal(P.n)
+    x, res = S.solve(_t(torch_gpu, b), rtol=1e-9)
+    xo, ho, nito, sto = O.pcg(b, tol=1e-9, val=v2)
+    _hist_parity(res.history, ho, 1e-9)
+    assert _relinf(x.cpu().numpy(), xo) <= 1e-9
+    y = S.spmv(_t(torch_gpu, b)).cpu().numpy()
+    assert _relinf(y, oracle.spmv(P.rowptr, P.col, v2, b)) <= 1e-13
+    S.close()
+
+
+def test_adjoint_and_coefficient_gradient(cases, torch_gpu):
+    torch = torch_gpu
+    P, path, st, S, O = cases["jump32"]
+    _say("[adjoint] jump32")
+    rng = np.random.default_rng(6)
+    g = rng.standard_normal(P.n)
+    lam = torch.zeros(P.n, dtype=torch.float64, device="cuda")
+    inf = mvamg.adjoint_solve(S.h, _t(torch, g), lam, rtol=1e-10)
+    lo, ho, nito, sto = O.pcg(g, tol=1e-10)
+    assert inf.converged and abs(inf.iterations - nito) <= 1
+    assert _relinf(lam.cpu().numpy(), lo) <= 1e-9
+    x, _ = S.solve(_t(torch, P.b), rtol=1e-10)
+    dval = torch.zeros(P.nnz, dtype=torch.float64, device="cuda")
+    mvamg.grad_coeffs(S.h, lam, x, dval)
+    ref = oracle.grad_coeffs(P.rowptr, P.col, lam.cpu().numpy(), x.cpu().numpy())
+    assert np.array_equal(dval.cpu().numpy(), ref)
+
+
+def test_zero_rhs_and_errors(cases, torch_gpu):
+    torch = torch_gpu
+    P, path, st, S, O = cases["aniso64"]
+    _say("[edge] zero rhs, nonfinite rhs, maxit")
+    x, res = S.solve(torch.zeros(P.n, dtype=torch.float64, device="cuda"))
+    assert res.iterations == 0 and res.converged and not x.any()
+    b = _t(torch, P.b)
+    b[17] = float("nan")
+    with pytest.raises(mvamg.MvamgError) as e:
+        S.solve(b)
+    assert e.value.status == mvamg.ERR_NONFINITE
+    x, res = S.solve(_t(torch, P.b), maxit=3)
+    assert not res.converged and res.iterations == 3
+    xo, ho, nito, sto = O.pcg(P.b, tol=1e-8, maxit=3)
+    assert sto == 1
+    assert _relinf(x.cpu().numpy(), xo) <= 1e-10
+    with pytest.raises(mvamg.MvamgError) as e:
+        mvamg.pcg_solve(S.h, b, b, precision=16)
+    assert e.value.status == mvamg.ERR_ARG
+
+
+def test_warm_start(cases, torch_gpu):
+    torch = torch_gpu
+    P, path, st, S, O = cases["jump16"]
+    _say("[warm start] jump16")
+    x0 = np.random.default_rng(8).standard_normal(P.n)
+    x, res = S.solve(_t(torch, P.b), x=_t(torch, x0), rtol=1e-8)
+    xo, ho, nito, sto = O.pcg(P.b, x0=x0, tol=1e-8)
+    _hist_parity(res.history, ho, 1e-8)
+    assert _relinf(x.cpu().numpy(), xo) <= 1e-9
+
+
+def test_solves_are_bitwise_repeatable(cases, torch_gpu):
+    P, path, st, S, O = cases["jump32"]
+    _say("[repeat] jump32")
+    b = _t(torch_gpu, P.b)
+    x1, r1 = S.solve(b)
+    x2, r2 = S.solve(b)
+    assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+    assert np.array_equal(r1.history, r2.history)
