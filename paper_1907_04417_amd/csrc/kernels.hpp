@@ -37,10 +37,7 @@ enum Scalar {
 enum RedMode { M_STORE_RR = 0, M_PQ = 1, M_RHO0 = 2, M_RZ = 3, M_RZ_FLEX = 4, M_STORE_R0 = 5, M_NONE = 6 };
 
 struct Red {
-  double* part;       // one slot per block and value (2 * grid)
-  unsigned* counter;  // zero between launches
-  double* scal;
-  int mode;
+  double* part;  // one slot per block and value (2 * grid)
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -97,40 +94,34 @@ __device__ __forceinline__ void epilogue(int mode, double v0, double v1, double*
   }
 }
 
-// Grid-wide deterministic reduction of up to two values: every block writes
-// its partial sums, the last block to finish adds the partials in block order
-// and applies the epilogue.  Partials and the counter are published with
-// device-scope fences (the L2 caches of the XCDs are not coherent otherwise).
+// Block partial sums of up to two values: part[b] and part[grid + b].  A
+// one-block finisher (k_finish) adds the partials in block order and applies
+// the epilogue, so results are deterministic and need no inter-block
+// synchronisation inside a kernel.
 template <int NV>
-__device__ void grid_reduce(double a0, double a1, Red red) {
+__device__ __forceinline__ void block_partials(double a0, double a1, double* part) {
   __shared__ double lds[4];
-  __shared__ int last;
   const double b0 = block_sum(a0, lds);
   double b1 = 0.0;
   if (NV > 1) b1 = block_sum(a1, lds);
   if (threadIdx.x == 0) {
-    red.part[blockIdx.x] = b0;
-    if (NV > 1) red.part[gridDim.x + blockIdx.x] = b1;
-    __threadfence();
-    const unsigned t = __hip_atomic_fetch_add(red.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (t == gridDim.x - 1);
+    part[blockIdx.x] = b0;
+    if (NV > 1) part[gridDim.x + blockIdx.x] = b1;
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const volatile double* part = red.part;
+}
+
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_finish(int nparts, const double* __restrict__ part, double* scal,
+                                                   int mode) {
+  __shared__ double lds[4];
   double s0 = 0.0, s1 = 0.0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += kBlock) {
+  for (int i = threadIdx.x; i < nparts; i += kBlock) {
     s0 += part[i];
-    if (NV > 1) s1 += part[gridDim.x + i];
+    if (NV > 1) s1 += part[nparts + i];
   }
   s0 = block_sum(s0, lds);
   if (NV > 1) s1 = block_sum(s1, lds);
-  if (threadIdx.x == 0) {
-    epilogue(red.mode, s0, s1, red.scal);
-    *red.counter = 0u;
-    __threadfence();
-  }
+  if (threadIdx.x == 0) epilogue(mode, s0, s1, scal);
 }
 
 // ------------------------------------------------------- vector kernels
@@ -164,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_dot(int n, const double* __restrict_
     s0 += a[p] * b[p];
     if (NV > 1) s1 += c[p] * d[p];
   }
-  grid_reduce<NV>(s0, s1, red);
+  block_partials<NV>(s0, s1, red.part);
 }
 
 // x += alpha p; r -= alpha q; sum r.r
@@ -179,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_axpy2_dot(int n, const double* __res
     r[i] = ri;
     s += ri * ri;
   }
-  grid_reduce<1>(s, 0.0, red);
+  block_partials<1>(s, 0.0, red.part);
 }
 
 // p = z + beta p
@@ -206,7 +197,22 @@ __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ sla
   const int* c = col + sl.off + lane;
   const T* v = val + sl.off + lane;
   T acc = r[p];
-  for (int j = 0; j < sl.width; ++j) acc -= v[64 * j] * x[c[64 * j]];
+  // entries in batches of 8: all index loads, then all gathers, then the sums
+  for (int j0 = 0; j0 < sl.width; j0 += 8) {
+    int cc[8];
+    T vv[8], xx[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = min(j0 + u, sl.width - 1);
+      cc[u] = c[64 * j];
+      vv[u] = v[64 * j];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xx[u] = x[cc[u]];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (j0 + u < sl.width) acc -= vv[u] * xx[u];
+  }
   x[p] = acc / diag[p];
 }
 
@@ -236,7 +242,21 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
       const T* v = val + sl.off + lane;
       const T xp = x[p];
       T acc = diag[p] * xp;
-      for (int j = 0; j < sl.width; ++j) acc += v[64 * j] * x[c[64 * j]];
+      for (int j0 = 0; j0 < sl.width; j0 += 8) {
+        int cc[8];
+        T vv[8], xx[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int j = min(j0 + u, sl.width - 1);
+          cc[u] = c[64 * j];
+          vv[u] = v[64 * j];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xx[u] = x[cc[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (j0 + u < sl.width) acc += vv[u] * xx[u];
+      }
       if (MODE == 0) {
         s[p] = r[p] - acc;
       } else {
@@ -245,28 +265,46 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
       }
     }
   }
-  if (MODE == 1) grid_reduce<1>(dsum, 0.0, red);
+  if (MODE == 1) block_partials<1>(dsum, 0.0, red.part);
 }
 
 // ------------------------------------------------------ grouped levels
 
 // Sum of the off-group entries of the group's rows, acc[l] for row l < k.
+// grb holds, per group, the entry offsets of its rows (kKmax + 1 values,
+// repeated past row k), so the entry loads do not wait on the row pointers.
+// Each lane takes entries lane, lane + G, ... in batches of 4 (index loads,
+// then gathers, then the sums).
 template <typename T, int G>
-__device__ __forceinline__ void group_offsum(int p0, int k, const int* __restrict__ rowptr,
-                                             const int* __restrict__ col, const T* __restrict__ val, const T* x,
-                                             int lane, T (&acc)[kKmax]) {
-  // row boundaries; entries past row k-1 repeat rowptr[p0 + k] (every load in bounds)
+__device__ __forceinline__ void group_offsum(int g, const int* __restrict__ grb, const int* __restrict__ col,
+                                             const T* __restrict__ val, const T* x, int lane, int k,
+                                             T (&acc)[kKmax]) {
   int rb[kKmax + 1];
+  const int* gb = grb + (size_t)g * (kKmax + 1);
 #pragma unroll
-  for (int q = 0; q <= kKmax; ++q) rb[q] = rowptr[p0 + min(q, k)];
+  for (int q = 0; q <= kKmax; ++q) rb[q] = gb[q];
 #pragma unroll
   for (int q = 0; q < kKmax; ++q) acc[q] = T(0);
-  const int e1 = rb[k];
-  for (int e = rb[0] + lane; e < e1; e += G) {
-    const T t = val[e] * x[col[e]];
+  const int e1 = rb[kKmax];
+  for (int e0 = rb[0] + lane; e0 < e1; e0 += 4 * G) {
+    int cc[4];
+    T vv[4], xx[4];
 #pragma unroll
-    for (int q = 0; q < kKmax; ++q)
-      if (e >= rb[q] && e < rb[q + 1]) acc[q] += t;
+    for (int u = 0; u < 4; ++u) {
+      const int e = min(e0 + u * G, e1 - 1);
+      cc[u] = col[e];
+      vv[u] = val[e];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xx[u] = x[cc[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * G;
+      const T t = (e < e1) ? vv[u] * xx[u] : T(0);
+#pragma unroll
+      for (int q = 0; q < kKmax; ++q)
+        if (e >= rb[q] && e < rb[q + 1]) acc[q] += t;
+    }
   }
 #pragma unroll
   for (int q = 0; q < kKmax; ++q)
@@ -278,7 +316,7 @@ __device__ __forceinline__ void group_offsum(int p0, int k, const int* __restric
 // latest values of the other rows.
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_gs_grp(int g0, int g1, const int* __restrict__ gstart,
-                                                   const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                   const int* __restrict__ grb, const int* __restrict__ col,
                                                    const T* __restrict__ val, const int* __restrict__ dboff,
                                                    const T* __restrict__ dblk, const T* __restrict__ r, T* x,
                                                    int backward) {
@@ -287,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_grp(int g0, int g1, const int* __
   const int lane = threadIdx.x % G;
   const int p0 = gstart[g], k = gstart[g + 1] - p0;
   T acc[kKmax];
-  group_offsum<T, G>(p0, k, rowptr, col, val, x, lane, acc);
+  group_offsum<T, G>(g, grb, col, val, x, lane, k, acc);
   T xv[kKmax], rv[kKmax];
 #pragma unroll
   for (int q = 0; q < kKmax; ++q) {
@@ -360,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_zero_stage0_grp(int ng, int ng0, con
 // s = r - A x (MODE 0) or y = A x with sum x.y (MODE 1, binary64) on all groups.
 template <typename T, int G, int MODE>
 __global__ __launch_bounds__(kBlock) void k_resid_grp(int ng, const int* __restrict__ gstart,
-                                                      const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                      const int* __restrict__ grb, const int* __restrict__ col,
                                                       const T* __restrict__ val, const int* __restrict__ dboff,
                                                       const T* __restrict__ dblk, const T* __restrict__ r,
                                                       const T* __restrict__ x, T* __restrict__ s, Red red) {
@@ -370,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_grp(int ng, const int* __restr
   if (g < ng) {
     const int p0 = gstart[g], k = gstart[g + 1] - p0;
     T acc[kKmax];
-    group_offsum<T, G>(p0, k, rowptr, col, val, x, lane, acc);
+    group_offsum<T, G>(g, grb, col, val, x, lane, k, acc);
     T xv[kKmax];
 #pragma unroll
     for (int q = 0; q < kKmax; ++q) {
@@ -394,7 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_grp(int ng, const int* __restr
       }
     }
   }
-  if (MODE == 1) grid_reduce<1>(dsum, 0.0, red);
+  if (MODE == 1) block_partials<1>(dsum, 0.0, red.part);
 }
 
 // ------------------------------------------------------------ l1-Jacobi

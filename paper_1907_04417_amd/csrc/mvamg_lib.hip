@@ -50,6 +50,7 @@ struct DevLevel {
   // device arrays
   Slab* slabs = nullptr;
   int* rowptr = nullptr;
+  int* grb = nullptr;  // per group: entry offsets of its rows (kKmax + 1)
   int* col = nullptr;
   double* val = nullptr;
   float* val32 = nullptr;
@@ -101,7 +102,6 @@ struct mvamg_hier {
   double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   double* scal = nullptr;
   double* part = nullptr;
-  unsigned* counter = nullptr;
   double* pinned = nullptr;
   std::vector<void*> allocs;
 
@@ -127,7 +127,16 @@ struct mvamg_hier {
 
 namespace {
 
-Red mkred(mvamg_hier* h, int mode) { return Red{h->part, h->counter, h->scal, mode}; }
+Red mkred(mvamg_hier* h) { return Red{h->part}; }
+
+// Adds the block partials of the previous kernel (grid blocks) and applies `mode`.
+void finish(mvamg_hier* h, int nv, int grid, int mode, hipStream_t st) {
+  if (nv == 1)
+    k_finish<1><<<1, kBlock, 0, st>>>(grid, h->part, h->scal, mode);
+  else
+    k_finish<2><<<1, kBlock, 0, st>>>(grid, h->part, h->scal, mode);
+  LAUNCHCHECK("finish");
+}
 
 // --------------------------------------------------------- level operators
 
@@ -215,10 +224,10 @@ void gs_stage(const DevLevel& L, int c, const T* r, T* x, int backward, hipStrea
     const int gpb = kBlock / L.G;
     const int grid = (g1 - g0 + gpb - 1) / gpb;
     switch (L.G) {
-      case 8: k_gs_grp<T, 8><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.rowptr, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
-      case 16: k_gs_grp<T, 16><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.rowptr, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
-      case 32: k_gs_grp<T, 32><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.rowptr, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
-      default: k_gs_grp<T, 64><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.rowptr, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      case 8: k_gs_grp<T, 8><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      case 16: k_gs_grp<T, 16><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      case 32: k_gs_grp<T, 32><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      default: k_gs_grp<T, 64><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
     }
   }
   LAUNCHCHECK("gs_stage");
@@ -234,9 +243,12 @@ void zero_stage0(const DevLevel& L, const T* r, T* x, hipStream_t st) {
   LAUNCHCHECK("zero_stage0");
 }
 
-// MODE 0: s = r - A x;  MODE 1: s = A x and x.s reduced with `red`
+int resid_grid(const DevLevel& L);
+
+// MODE 0: s = r - A x;  MODE 1: s = A x and x.s reduced into scal by `mode`
 template <typename T, int MODE>
-void resid(const DevLevel& L, const T* r, const T* x, T* s, Red red, hipStream_t st) {
+void resid(mvamg_hier* h, const DevLevel& L, const T* r, const T* x, T* s, int mode, hipStream_t st) {
+  const Red red = mkred(h);
   if (L.sell) {
     const int grid = (L.nslabs + 3) / 4;
     k_resid_sell<T, MODE><<<grid, kBlock, 0, st>>>(L.slabs, L.nslabs, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red);
@@ -244,13 +256,14 @@ void resid(const DevLevel& L, const T* r, const T* x, T* s, Red red, hipStream_t
     const int gpb = kBlock / L.G;
     const int grid = (L.ng + gpb - 1) / gpb;
     switch (L.G) {
-      case 8: k_resid_grp<T, 8, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.rowptr, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
-      case 16: k_resid_grp<T, 16, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.rowptr, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
-      case 32: k_resid_grp<T, 32, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.rowptr, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
-      default: k_resid_grp<T, 64, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.rowptr, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+      case 8: k_resid_grp<T, 8, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+      case 16: k_resid_grp<T, 16, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+      case 32: k_resid_grp<T, 32, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+      default: k_resid_grp<T, 64, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
     }
   }
   LAUNCHCHECK("resid");
+  if (MODE == 1) finish(h, 1, resid_grid(L), mode, st);
 }
 
 int resid_grid(const DevLevel& L) {
@@ -295,7 +308,6 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   T* s = ls<T>(L);
   T* rc = lr<T>(C);
   T* xc = lx<T>(C);
-  const Red none = mkred(h, 0);
   // pre-smoothing: one forward sweep from x = 0
   if (smoother == MVAMG_SMOOTH_GS) {
     zero_stage0<T>(L, r, x, st);
@@ -304,7 +316,7 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
     k_l1_init<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, ldl1<T>(L), r, x);
   }
   // residual, restriction
-  resid<T, 0>(L, r, x, s, none, st);
+  resid<T, 0>(h, L, r, x, s, M_NONE, st);
   const int tg = (P.nagg + 3) / 4;
   k_restrict<T><<<tg, kBlock, 0, st>>>(P.nagg, P.aptr, P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc);
   LAUNCHCHECK("restrict");
@@ -315,7 +327,7 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   if (smoother == MVAMG_SMOOTH_GS) {
     for (int c = L.ns - 1; c >= 0; --c) gs_stage<T>(L, c, r, x, 1, st);
   } else {
-    resid<T, 0>(L, r, x, s, none, st);
+    resid<T, 0>(h, L, r, x, s, M_NONE, st);
     k_l1_update<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, ldl1<T>(L), s, x);
   }
   LAUNCHCHECK("vcycle");
@@ -336,13 +348,14 @@ void apply_B(mvamg_hier* h, const double* r, double* z, int precision, int smoot
 
 // q = A p (level 0, smoother order) with p.q into S_PQ / alpha
 void spmv0_dot(mvamg_hier* h, const double* p, double* q, int mode, hipStream_t st) {
-  resid<double, 1>(h->lv[0], nullptr, p, q, mkred(h, mode), st);
+  resid<double, 1>(h, h->lv[0], nullptr, p, q, mode, st);
 }
 
 void dot(mvamg_hier* h, const double* a, const double* b, int mode, hipStream_t st) {
   const int n = h->n;
-  k_dot<1><<<grid_for(n), kBlock, 0, st>>>(n, a, b, nullptr, nullptr, mkred(h, mode));
+  k_dot<1><<<grid_for(n), kBlock, 0, st>>>(n, a, b, nullptr, nullptr, mkred(h));
   LAUNCHCHECK("dot");
+  finish(h, 1, grid_for(n), mode, st);
 }
 
 void read_scalars(mvamg_hier* h, hipStream_t st) {
@@ -400,7 +413,7 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
   k_gather<<<eg, kBlock, 0, st>>>(n, h->perm0, x_file, h->x);
   LAUNCHCHECK("gather");
   HIPCHECK(hipMemsetAsync(h->scal, 0, S_NSCAL * sizeof(double), st));
-  resid<double, 0>(L0, h->b, h->x, h->r, mkred(h, 0), st);
+  resid<double, 0>(h, L0, h->b, h->x, h->r, M_NONE, st);
   dot(h, h->r, h->r, M_STORE_R0, st);
   read_scalars(h, st);
   const double r0 = std::sqrt(h->pinned[S_R0]);
@@ -417,7 +430,7 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
     const int max_restarts = flex ? std::max(0, prm->max_restarts) : 0;
     for (int restart = 0; restart <= max_restarts && it < prm->maxit; ++restart) {
       if (restart > 0) {
-        resid<double, 0>(L0, h->b, h->x, h->r, mkred(h, 0), st);
+        resid<double, 0>(h, L0, h->b, h->x, h->r, M_NONE, st);
         inf.restarts = restart;
       }
       apply_B(h, h->r, h->z, prm->precision, prm->smoother, st);
@@ -426,8 +439,9 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
       bool met = false;
       while (it < prm->maxit) {
         spmv0_dot(h, h->p, h->q, M_PQ, st);
-        k_axpy2_dot<<<eg, kBlock, 0, st>>>(n, h->scal, h->p, h->q, h->x, h->r, mkred(h, M_STORE_RR));
+        k_axpy2_dot<<<eg, kBlock, 0, st>>>(n, h->scal, h->p, h->q, h->x, h->r, mkred(h));
         LAUNCHCHECK("axpy2");
+        finish(h, 1, eg, M_STORE_RR, st);
         read_scalars(h, st);
         ++it;
         if (h->pinned[S_FLAG] != 0.0) {
@@ -443,9 +457,11 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
         }
         apply_B(h, h->r, h->z, prm->precision, prm->smoother, st);
         if (flex) {
-          k_dot<2><<<eg, kBlock, 0, st>>>(n, h->z, h->r, h->z, h->q, mkred(h, M_RZ_FLEX));
+          k_dot<2><<<eg, kBlock, 0, st>>>(n, h->z, h->r, h->z, h->q, mkred(h));
+          finish(h, 2, eg, M_RZ_FLEX, st);
         } else {
-          k_dot<1><<<eg, kBlock, 0, st>>>(n, h->z, h->r, nullptr, nullptr, mkred(h, M_RZ));
+          k_dot<1><<<eg, kBlock, 0, st>>>(n, h->z, h->r, nullptr, nullptr, mkred(h));
+          finish(h, 1, eg, M_RZ, st);
         }
         k_xpay<<<eg, kBlock, 0, st>>>(n, h->scal, h->z, h->p);
         LAUNCHCHECK("pcg update");
@@ -455,7 +471,7 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
         break;
       }
       // binary32 cycle: confirm with the true residual in binary64
-      resid<double, 0>(L0, h->b, h->x, h->q, mkred(h, 0), st);
+      resid<double, 0>(h, L0, h->b, h->x, h->q, M_NONE, st);
       dot(h, h->q, h->q, M_STORE_RR, st);
       read_scalars(h, st);
       const double tr = std::sqrt(h->pinned[S_RR]) / r0;
@@ -469,7 +485,7 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
   }
   inf.rel_res = h_last;
   // true residual in binary64 and back to file order
-  resid<double, 0>(L0, h->b, h->x, h->q, mkred(h, 0), st);
+  resid<double, 0>(h, L0, h->b, h->x, h->q, M_NONE, st);
   dot(h, h->q, h->q, M_STORE_RR, st);
   k_scatter<<<eg, kBlock, 0, st>>>(n, h->perm0, h->x, x_file);
   LAUNCHCHECK("scatter");
@@ -554,7 +570,15 @@ mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** 
       L.nent = (int64_t)y.val.size();
       L.ndblk = (int64_t)y.dblk.size();
       if (y.sell) L.slabs = h->upload_vec(y.slabs, st);
-      if (!y.sell) L.rowptr = h->upload_vec(y.rowptr, st);
+      if (!y.sell) {
+        L.rowptr = h->upload_vec(y.rowptr, st);
+        std::vector<int> grb((size_t)L.ng * (kKmax + 1));
+        for (int g = 0; g < L.ng; ++g) {
+          const int p0 = y.gstart[g], k = y.gstart[g + 1] - p0;
+          for (int q = 0; q <= kKmax; ++q) grb[(size_t)g * (kKmax + 1) + q] = y.rowptr[p0 + std::min(q, k)];
+        }
+        L.grb = h->upload_vec(grb, st);
+      }
       L.col = h->upload_vec(y.col, st);
       L.val = h->upload_vec(y.val, st);
       L.val32 = h->dalloc<float>(y.val.size());
@@ -641,8 +665,6 @@ mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** 
       h->lv[0].x = h->z;
       h->scal = h->dalloc<double>(S_NSCAL);
       h->part = h->dalloc<double>(2 * (size_t)maxgrid);
-      h->counter = h->dalloc<unsigned>(1);
-      HIPCHECK(hipMemsetAsync(h->counter, 0, sizeof(unsigned), st));
       HIPCHECK(hipMemsetAsync(h->scal, 0, S_NSCAL * sizeof(double), st));
       HIPCHECK(hipHostMalloc((void**)&h->pinned, S_NSCAL * sizeof(double), hipHostMallocDefault));
     }
@@ -699,7 +721,7 @@ mvamg_status mvamg_spmv(mvamg_hier* h, const double* x, double* y, void* stream)
     hipStream_t st = (hipStream_t)stream;
     const int eg = grid_for(h->n);
     k_gather<<<eg, kBlock, 0, st>>>(h->n, h->perm0, x, h->p);
-    resid<double, 1>(h->lv[0], nullptr, h->p, h->q, mkred(h, M_NONE), st);
+    resid<double, 1>(h, h->lv[0], nullptr, h->p, h->q, M_NONE, st);
     k_scatter<<<eg, kBlock, 0, st>>>(h->n, h->perm0, h->q, y);
     LAUNCHCHECK("spmv");
     return MVAMG_OK;

@@ -121,6 +121,14 @@ def test_pcg_mixed_precision(name, cases, torch_gpu):
 
 
 def test_nearby_matrix_values(cases, torch_gpu):
+    """Finest-level values replaced by a near-by matrix (same pattern, Section 1).
+
+    The stored coarse levels no longer match the new fine matrix, and CG on
+    that system amplifies rounding: the oracle's own residual history moves by
+    up to 1e-1 under a 1e-15 perturbation of b.  The history is therefore not
+    unique; what is unique (and compared) is the operator: A x and B r with the
+    new values against the oracle to rounding, plus the true-residual property
+    of the GPU solution and an iteration count close to the oracle's."""
     P, path, st, S0, O = cases["jump16"]
     _say("[nearby] jump16")
     S = mvamg.Solver(path)
@@ -131,12 +139,18 @@ def test_nearby_matrix_values(cases, torch_gpu):
     v2 = P.val * d[rows] * d[P.col]
     mvamg.set_fine_values(S.h, _t(torch_gpu, v2))
     b = rng.standard_normal(P.n)
-    x, res = S.solve(_t(torch_gpu, b), rtol=1e-9)
-    xo, ho, nito, sto = O.pcg(b, tol=1e-9, val=v2)
-    _hist_parity(res.history, ho, 1e-9)
-    assert _relinf(x.cpu().numpy(), xo) <= 1e-9
     y = S.spmv(_t(torch_gpu, b)).cpu().numpy()
     assert _relinf(y, oracle.spmv(P.rowptr, P.col, v2, b)) <= 1e-13
+    for smoother, osm in [(mvamg.SMOOTH_GS, oracle.GS_COLOUR), (mvamg.SMOOTH_L1JACOBI, oracle.L1_JACOBI)]:
+        Oc = O if osm == oracle.GS_COLOUR else oracle.Oracle(path, smoother=osm)
+        z = S.cycle(_t(torch_gpu, b), smoother=smoother).cpu().numpy()
+        assert _relinf(z, Oc.vcycle(b, val0=v2)) <= 1e-11
+    x, res = S.solve(_t(torch_gpu, b), rtol=1e-9)
+    xo, ho, nito, sto = O.pcg(b, tol=1e-9, val=v2)
+    xg = x.cpu().numpy()
+    true_rel = np.linalg.norm(b - oracle.spmv(P.rowptr, P.col, v2, xg)) / np.linalg.norm(b)
+    assert res.converged and true_rel <= 1.01e-9
+    assert abs(res.iterations - nito) <= max(3, nito // 5)
     S.close()
 
 
