@@ -162,7 +162,7 @@ struct Slab {
 struct LevelLayout {
   int n = 0;
   bool sell = false;  // point groups stored as sliced ELL (64-row slabs)
-  int G = 64;         // lanes per group for grouped CSR
+  int G = 8;          // grouped CSR: kernel instantiation for groups of <= G rows
   int kmax = 1;
   std::vector<int> perm, iperm;  // new -> old, old -> new
   std::vector<int> gstart;       // ngroups + 1, rows in new numbering
@@ -313,9 +313,8 @@ inline void build_level_layout(const HostLevel& L, LevelLayout& Y) {
       }
       Y.rowptr[p + 1] = (int)Y.col.size();
     }
-    // lanes per group: about one pass over the group's entries
-    const double avg = (double)offcount / (double)ng;
-    Y.G = avg > 48 ? 64 : avg > 24 ? 32 : avg > 12 ? 16 : 8;
+    // kernels are instantiated for groups of up to 1, 2, 4 or 8 rows
+    Y.G = Y.kmax <= 1 ? 1 : Y.kmax <= 2 ? 2 : Y.kmax <= 4 ? 4 : 8;
   }
 }
 

@@ -270,97 +270,86 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
 
 // ------------------------------------------------------ grouped levels
 
-// Sum of the off-group entries of the group's rows, acc[l] for row l < k.
-// grb holds, per group, the entry offsets of its rows (kKmax + 1 values,
-// repeated past row k), so the entry loads do not wait on the row pointers.
-// Each lane takes entries lane, lane + G, ... in batches of 4 (index loads,
-// then gathers, then the sums).
-template <typename T, int G>
-__device__ __forceinline__ void group_offsum(int g, const int* __restrict__ grb, const int* __restrict__ col,
-                                             const T* __restrict__ val, const T* x, int lane, int k,
-                                             T (&acc)[kKmax]) {
-  int rb[kKmax + 1];
-  const int* gb = grb + (size_t)g * (kKmax + 1);
+// Grouped levels: one wavefront per group, 64 / KMAX lanes per row (KMAX =
+// the level's largest group, a power of two <= 8).  Lane sub of row l strides
+// over row l's off-group entries (batches of 4: index loads, gathers, sums),
+// a segmented shuffle adds the row, and the k row sums are broadcast to the
+// wave.  The group index is made wave-uniform so its descriptors and the k x k
+// diagonal block are read with scalar loads.  grb holds, per group, the entry
+// offsets of its rows (kKmax + 1 values, repeated past row k).
+template <typename T, int KMAX>
+__device__ __forceinline__ void group_rowsums(int g, int l, int sub, int k, const int* __restrict__ grb,
+                                              const int* __restrict__ col, const T* __restrict__ val, const T* x,
+                                              T (&a)[KMAX]) {
+  constexpr int LPR = 64 / KMAX;
+  T acc = T(0);
+  if (l < k) {
+    const int* gb = grb + (size_t)g * (kKmax + 1);
+    const int e1 = gb[l + 1];
+    for (int e0 = gb[l] + sub; e0 < e1; e0 += 4 * LPR) {
+      int cc[4];
+      T vv[4], xx[4];
 #pragma unroll
-  for (int q = 0; q <= kKmax; ++q) rb[q] = gb[q];
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(e0 + u * LPR, e1 - 1);
+        cc[u] = col[e];
+        vv[u] = val[e];
+      }
 #pragma unroll
-  for (int q = 0; q < kKmax; ++q) acc[q] = T(0);
-  const int e1 = rb[kKmax];
-  for (int e0 = rb[0] + lane; e0 < e1; e0 += 4 * G) {
-    int cc[4];
-    T vv[4], xx[4];
+      for (int u = 0; u < 4; ++u) xx[u] = x[cc[u]];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = min(e0 + u * G, e1 - 1);
-      cc[u] = col[e];
-      vv[u] = val[e];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) xx[u] = x[cc[u]];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = e0 + u * G;
-      const T t = (e < e1) ? vv[u] * xx[u] : T(0);
-#pragma unroll
-      for (int q = 0; q < kKmax; ++q)
-        if (e >= rb[q] && e < rb[q + 1]) acc[q] += t;
+      for (int u = 0; u < 4; ++u)
+        if (e0 + u * LPR < e1) acc += vv[u] * xx[u];
     }
   }
+  acc = seg_sum<LPR>(acc);
 #pragma unroll
-  for (int q = 0; q < kKmax; ++q)
-    if (q < k) acc[q] = seg_sum<G>(acc[q]);
+  for (int q = 0; q < KMAX; ++q) a[q] = __shfl(acc, q * LPR, 64);
 }
 
 // One Gauss-Seidel stage on the groups [g0, g1): every group relaxes its rows
-// one after the other (forward: l = 0..k-1, backward: l = k-1..0) using the
+// one after the other (forward: l = 0..k-1, backward: l = k-1..0) with the
 // latest values of the other rows.
-template <typename T, int G>
+template <typename T, int KMAX>
 __global__ __launch_bounds__(kBlock) void k_gs_grp(int g0, int g1, const int* __restrict__ gstart,
                                                    const int* __restrict__ grb, const int* __restrict__ col,
                                                    const T* __restrict__ val, const int* __restrict__ dboff,
                                                    const T* __restrict__ dblk, const T* __restrict__ r, T* x,
                                                    int backward) {
-  const int g = g0 + blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  const int g = __builtin_amdgcn_readfirstlane(g0 + (int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6));
   if (g >= g1) return;
-  const int lane = threadIdx.x % G;
+  const int lane = threadIdx.x & 63;
+  const int l = lane / (64 / KMAX), sub = lane % (64 / KMAX);
   const int p0 = gstart[g], k = gstart[g + 1] - p0;
-  T acc[kKmax];
-  group_offsum<T, G>(g, grb, col, val, x, lane, k, acc);
-  T xv[kKmax], rv[kKmax];
+  const T* B = dblk + dboff[g];
+  T xv[KMAX], rv[KMAX];
 #pragma unroll
-  for (int q = 0; q < kKmax; ++q) {
+  for (int q = 0; q < KMAX; ++q) {
     const int qq = min(q, k - 1);
     const T xq = x[p0 + qq], rq = r[p0 + qq];
     xv[q] = (q < k) ? xq : T(0);
     rv[q] = (q < k) ? rq : T(0);
   }
-  const T* B = dblk + dboff[g];
-  if (!backward) {
+  T a[KMAX];
+  group_rowsums<T, KMAX>(g, l, sub, k, grb, col, val, x, a);
 #pragma unroll
-    for (int l = 0; l < kKmax; ++l) {
-      if (l < k) {
-        T s = rv[l] - acc[l];
+  for (int t = 0; t < KMAX; ++t) {
+    const int ll = backward ? KMAX - 1 - t : t;
+    if (ll < k) {
+      T s = rv[ll] - a[ll];
 #pragma unroll
-        for (int q = 0; q < kKmax; ++q)
-          if (q < k && q != l) s -= B[l * k + q] * xv[q];
-        xv[l] = s / B[l * k + l];
-      }
-    }
-  } else {
-#pragma unroll
-    for (int l = kKmax - 1; l >= 0; --l) {
-      if (l < k) {
-        T s = rv[l] - acc[l];
-#pragma unroll
-        for (int q = 0; q < kKmax; ++q)
-          if (q < k && q != l) s -= B[l * k + q] * xv[q];
-        xv[l] = s / B[l * k + l];
-      }
+      for (int q = 0; q < KMAX; ++q)
+        if (q < k && q != ll) s -= B[ll * k + q] * xv[q];
+      xv[ll] = s / B[ll * k + ll];
     }
   }
+  if (sub == 0 && l < k) {
+    T v = xv[0];
 #pragma unroll
-  for (int q = 0; q < kKmax; ++q)
-    if (q < k && lane == q % G) x[p0 + q] = xv[q];
+    for (int q = 1; q < KMAX; ++q)
+      if (l == q) v = xv[q];
+    x[p0 + l] = v;
+  }
 }
 
 // Forward sweep from x = 0 on a grouped level: the groups of stage 0 solve
@@ -396,39 +385,43 @@ __global__ __launch_bounds__(kBlock) void k_zero_stage0_grp(int ng, int ng0, con
 }
 
 // s = r - A x (MODE 0) or y = A x with sum x.y (MODE 1, binary64) on all groups.
-template <typename T, int G, int MODE>
+template <typename T, int KMAX, int MODE>
 __global__ __launch_bounds__(kBlock) void k_resid_grp(int ng, const int* __restrict__ gstart,
                                                       const int* __restrict__ grb, const int* __restrict__ col,
                                                       const T* __restrict__ val, const int* __restrict__ dboff,
                                                       const T* __restrict__ dblk, const T* __restrict__ r,
                                                       const T* __restrict__ x, T* __restrict__ s, Red red) {
-  const int g = blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  const int lane = threadIdx.x % G;
+  const int g = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int l = lane / (64 / KMAX), sub = lane % (64 / KMAX);
   double dsum = 0.0;
   if (g < ng) {
     const int p0 = gstart[g], k = gstart[g + 1] - p0;
-    T acc[kKmax];
-    group_offsum<T, G>(g, grb, col, val, x, lane, k, acc);
-    T xv[kKmax];
+    const T* B = dblk + dboff[g];
+    T xv[KMAX];
 #pragma unroll
-    for (int q = 0; q < kKmax; ++q) {
+    for (int q = 0; q < KMAX; ++q) {
       const T xq = x[p0 + min(q, k - 1)];
       xv[q] = (q < k) ? xq : T(0);
     }
-    const T* B = dblk + dboff[g];
+    T a[KMAX];
+    group_rowsums<T, KMAX>(g, l, sub, k, grb, col, val, x, a);
+    if (sub == 0 && l < k) {
+      T t = T(0), xl = T(0);
 #pragma unroll
-    for (int l = 0; l < kKmax; ++l) {
-      if (l < k && lane == l % G) {
-        T t = acc[l];
-#pragma unroll
-        for (int q = 0; q < kKmax; ++q)
-          if (q < k) t += B[l * k + q] * xv[q];
-        if (MODE == 0) {
-          s[p0 + l] = r[p0 + l] - t;
-        } else {
-          s[p0 + l] = t;
-          dsum += (double)xv[l] * (double)t;
+      for (int q = 0; q < KMAX; ++q)
+        if (q == l) {
+          t = a[q];
+          xl = xv[q];
         }
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q)
+        if (q < k) t += B[l * k + q] * xv[q];
+      if (MODE == 0) {
+        s[p0 + l] = r[p0 + l] - t;
+      } else {
+        s[p0 + l] = t;
+        dsum = (double)xl * (double)t;
       }
     }
   }

@@ -6,6 +6,8 @@
 
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -41,7 +43,7 @@ int grid_for(int64_t n) {
 struct DevLevel {
   int n = 0;
   bool sell = false;
-  int G = 64;
+  int G = 8;  // KMAX of a grouped level (largest group, power of two)
   int ng = 0, ns = 0, nslabs = 0;
   int rows0 = 0;  // rows of stage 0 (point levels)
   std::vector<int> h_sgrp, h_sslab;
@@ -103,6 +105,9 @@ struct mvamg_hier {
   double* scal = nullptr;
   double* part = nullptr;
   double* pinned = nullptr;
+  hipStream_t cap = nullptr;              // stream used only to capture graphs
+  std::map<int, hipGraphExec_t> graphs;   // one CG iteration per (precision, smoother)
+  bool use_graphs = true;
   std::vector<void*> allocs;
 
   template <typename T>
@@ -120,6 +125,8 @@ struct mvamg_hier {
     return d;
   }
   ~mvamg_hier() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    if (cap) (void)hipStreamDestroy(cap);
     for (void* p : allocs) (void)hipFree(p);
     if (pinned) (void)hipHostFree(pinned);
   }
@@ -221,13 +228,12 @@ void gs_stage(const DevLevel& L, int c, const T* r, T* x, int backward, hipStrea
   } else {
     const int g0 = L.h_sgrp[c], g1 = L.h_sgrp[c + 1];
     if (g1 <= g0) return;
-    const int gpb = kBlock / L.G;
-    const int grid = (g1 - g0 + gpb - 1) / gpb;
+    const int grid = (g1 - g0 + 3) / 4;
     switch (L.G) {
-      case 8: k_gs_grp<T, 8><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
-      case 16: k_gs_grp<T, 16><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
-      case 32: k_gs_grp<T, 32><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
-      default: k_gs_grp<T, 64><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      case 1: k_gs_grp<T, 1><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      case 2: k_gs_grp<T, 2><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      case 4: k_gs_grp<T, 4><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      default: k_gs_grp<T, 8><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
     }
   }
   LAUNCHCHECK("gs_stage");
@@ -253,13 +259,12 @@ void resid(mvamg_hier* h, const DevLevel& L, const T* r, const T* x, T* s, int m
     const int grid = (L.nslabs + 3) / 4;
     k_resid_sell<T, MODE><<<grid, kBlock, 0, st>>>(L.slabs, L.nslabs, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red);
   } else {
-    const int gpb = kBlock / L.G;
-    const int grid = (L.ng + gpb - 1) / gpb;
+    const int grid = (L.ng + 3) / 4;
     switch (L.G) {
-      case 8: k_resid_grp<T, 8, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
-      case 16: k_resid_grp<T, 16, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
-      case 32: k_resid_grp<T, 32, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
-      default: k_resid_grp<T, 64, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+      case 1: k_resid_grp<T, 1, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+      case 2: k_resid_grp<T, 2, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+      case 4: k_resid_grp<T, 4, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+      default: k_resid_grp<T, 8, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
     }
   }
   LAUNCHCHECK("resid");
@@ -268,8 +273,7 @@ void resid(mvamg_hier* h, const DevLevel& L, const T* r, const T* x, T* s, int m
 
 int resid_grid(const DevLevel& L) {
   if (L.sell) return (L.nslabs + 3) / 4;
-  const int gpb = kBlock / L.G;
-  return (L.ng + gpb - 1) / gpb;
+  return (L.ng + 3) / 4;
 }
 
 template <typename T>
@@ -394,6 +398,58 @@ void check_device(const mvamg_hier* h) {
   if (dev != h->device) throw Error(MVAMG_ERR_ARG, "handle used with a different current device");
 }
 
+// One CG half-step A: q = A p, alpha = rho / p.q, x += alpha p, r -= alpha q,
+// r.r -- then the scalars are copied to pinned host memory.
+void cg_step_a(mvamg_hier* h, hipStream_t st) {
+  const int n = h->n, eg = grid_for(n);
+  spmv0_dot(h, h->p, h->q, M_PQ, st);
+  k_axpy2_dot<<<eg, kBlock, 0, st>>>(n, h->scal, h->p, h->q, h->x, h->r, mkred(h));
+  LAUNCHCHECK("axpy2");
+  finish(h, 1, eg, M_STORE_RR, st);
+  HIPCHECK(hipMemcpyAsync(h->pinned, h->scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, st));
+}
+
+// Half-step B: z = B r, beta (standard or flexible), p = z + beta p.
+void cg_step_b(mvamg_hier* h, int precision, int smoother, hipStream_t st) {
+  const int n = h->n, eg = grid_for(n);
+  apply_B(h, h->r, h->z, precision, smoother, st);
+  if (precision == 32) {
+    k_dot<2><<<eg, kBlock, 0, st>>>(n, h->z, h->r, h->z, h->q, mkred(h));
+    finish(h, 2, eg, M_RZ_FLEX, st);
+  } else {
+    k_dot<1><<<eg, kBlock, 0, st>>>(n, h->z, h->r, nullptr, nullptr, mkred(h));
+    finish(h, 1, eg, M_RZ, st);
+  }
+  k_xpay<<<eg, kBlock, 0, st>>>(n, h->scal, h->z, h->p);
+  LAUNCHCHECK("xpay");
+}
+
+// One full iteration (B then A) captured once as a HIP graph and replayed:
+// about 60 kernels and one copy per launch instead of as many host launches.
+hipGraphExec_t iteration_graph(mvamg_hier* h, int precision, int smoother) {
+  const int key = precision * 4 + smoother;
+  auto it = h->graphs.find(key);
+  if (it != h->graphs.end()) return it->second;
+  if (!h->cap) HIPCHECK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  HIPCHECK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+  try {
+    cg_step_b(h, precision, smoother, h->cap);
+    cg_step_a(h, h->cap);
+  } catch (...) {
+    (void)hipStreamEndCapture(h->cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  HIPCHECK(hipStreamEndCapture(h->cap, &g));
+  hipGraphExec_t ge = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  hipcheck(e, "hipGraphInstantiate");
+  h->graphs[key] = ge;
+  return ge;
+}
+
 // Core CG loop shared by solve and adjoint solve.
 mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvamg_solve_params* prm,
                  mvamg_info* info, hipStream_t st) {
@@ -437,12 +493,19 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
       dot(h, h->r, h->z, M_RHO0, st);
       k_copy<double><<<eg, kBlock, 0, st>>>(n, h->z, h->p);
       bool met = false;
+      hipGraphExec_t ge = h->use_graphs ? iteration_graph(h, prm->precision, prm->smoother) : nullptr;
+      bool first = true;
       while (it < prm->maxit) {
-        spmv0_dot(h, h->p, h->q, M_PQ, st);
-        k_axpy2_dot<<<eg, kBlock, 0, st>>>(n, h->scal, h->p, h->q, h->x, h->r, mkred(h));
-        LAUNCHCHECK("axpy2");
-        finish(h, 1, eg, M_STORE_RR, st);
-        read_scalars(h, st);
+        if (first) {
+          cg_step_a(h, st);
+          first = false;
+        } else if (ge) {
+          HIPCHECK(hipGraphLaunch(ge, st));
+        } else {
+          cg_step_b(h, prm->precision, prm->smoother, st);
+          cg_step_a(h, st);
+        }
+        HIPCHECK(hipStreamSynchronize(st));
         ++it;
         if (h->pinned[S_FLAG] != 0.0) {
           inf.iterations = it;
@@ -455,16 +518,6 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
           met = true;
           break;
         }
-        apply_B(h, h->r, h->z, prm->precision, prm->smoother, st);
-        if (flex) {
-          k_dot<2><<<eg, kBlock, 0, st>>>(n, h->z, h->r, h->z, h->q, mkred(h));
-          finish(h, 2, eg, M_RZ_FLEX, st);
-        } else {
-          k_dot<1><<<eg, kBlock, 0, st>>>(n, h->z, h->r, nullptr, nullptr, mkred(h));
-          finish(h, 1, eg, M_RZ, st);
-        }
-        k_xpay<<<eg, kBlock, 0, st>>>(n, h->scal, h->z, h->p);
-        LAUNCHCHECK("pcg update");
       }
       if (!flex) {
         if (met) status = MVAMG_OK;
@@ -542,6 +595,10 @@ mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** 
     if (H.nl < 2) throw Error(MVAMG_ERR_ARG, "hierarchy needs at least two levels");
     h.reset(new mvamg_hier);
     HIPCHECK(hipGetDevice(&h->device));
+    {
+      const char* ev = std::getenv("MVAMG_NO_GRAPH");
+      h->use_graphs = !(ev && ev[0] && ev[0] != '0');
+    }
     h->nl = H.nl;
     h->n = H.lv[0].n;
     h->nnz = (int64_t)H.lv[0].ci.size();
