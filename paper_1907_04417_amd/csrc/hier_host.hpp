@@ -190,41 +190,67 @@ struct TransferLayout {
 inline void build_level_layout(const HostLevel& L, LevelLayout& Y) {
   const int n = L.n;
   Y.n = n;
-  Y.perm = L.order;
-  if ((int)Y.perm.size() != n) throw Error(-2, "smoother order has wrong length");
+  if ((int)L.order.size() != n) throw Error(-2, "smoother order has wrong length");
+  const int ng = (int)L.gptr.size() - 1;
+  const int ns = (int)L.sptr.size() - 1;
+  if (ng < 1 || L.gptr[0] != 0 || L.gptr[ng] != n || ns < 1 || L.sptr[0] != 0 || L.sptr[ns] != ng)
+    throw Error(-2, "inconsistent smoother groups");
+  for (int g = 0; g < ng; ++g)
+    if (L.gptr[g + 1] <= L.gptr[g]) throw Error(-2, "empty smoother group");
+  // Groups of one stage are mutually independent, so their order inside the
+  // stage does not change the sweep.  On levels with multi-row groups they are
+  // sorted by the aggregate (of the transfer to the next level) that holds
+  // their first row, so the transfers read and write contiguous runs; on
+  // point levels the file order is kept, which keeps the neighbour gathers of
+  // the sliced-ELL products local (for a grid numbering).
+  bool multi = false;
+  for (int g = 0; g < ng; ++g) multi = multi || (L.gptr[g + 1] - L.gptr[g] > 1);
+  std::vector<int> aggof(n, 0);
+  for (int a = 0; a + 1 < (int)L.aptr.size(); ++a)
+    for (int m = L.aptr[a]; m < L.aptr[a + 1]; ++m)
+      if (L.arows[m] >= 0 && L.arows[m] < n) aggof[L.arows[m]] = a;
+  std::vector<int> gorder(ng);
+  for (int g = 0; g < ng; ++g) gorder[g] = g;
+  for (int c = 0; c < ns && multi; ++c)
+    std::stable_sort(gorder.begin() + L.sptr[c], gorder.begin() + L.sptr[c + 1], [&](int a, int b) {
+      return aggof[L.order[L.gptr[a]]] < aggof[L.order[L.gptr[b]]];
+    });
+  Y.perm.clear();
+  Y.perm.reserve(n);
+  Y.gstart.assign(ng + 1, 0);
+  for (int t = 0; t < ng; ++t) {
+    const int g = gorder[t];
+    for (int q = L.gptr[g]; q < L.gptr[g + 1]; ++q) Y.perm.push_back(L.order[q]);
+    Y.gstart[t + 1] = (int)Y.perm.size();
+  }
+  Y.sgrp = L.sptr;
   Y.iperm.assign(n, -1);
   for (int p = 0; p < n; ++p) {
     const int i = Y.perm[p];
     if (i < 0 || i >= n || Y.iperm[i] >= 0) throw Error(-2, "smoother order is not a permutation");
     Y.iperm[i] = p;
   }
-  const int ng = (int)L.gptr.size() - 1;
-  const int ns = (int)L.sptr.size() - 1;
-  if (ng < 1 || L.gptr[0] != 0 || L.gptr[ng] != n || ns < 1 || L.sptr[0] != 0 || L.sptr[ns] != ng)
-    throw Error(-2, "inconsistent smoother groups");
-  Y.gstart = L.gptr;
-  Y.sgrp = L.sptr;
   std::vector<int> grp(n);
   Y.kmax = 1;
   bool point = true;
   for (int g = 0; g < ng; ++g) {
-    const int k = L.gptr[g + 1] - L.gptr[g];
+    const int k = Y.gstart[g + 1] - Y.gstart[g];
     if (k < 1) throw Error(-2, "empty smoother group");
     if (k > kKmax) throw Error(-1, "smoother group larger than 8 rows is not supported");
     Y.kmax = std::max(Y.kmax, k);
     if (k > 1) point = false;
-    for (int p = L.gptr[g]; p < L.gptr[g + 1]; ++p) grp[p] = g;
+    for (int p = Y.gstart[g]; p < Y.gstart[g + 1]; ++p) grp[p] = g;
     // rows of a group are consecutive in the file numbering as well
-    for (int p = L.gptr[g] + 1; p < L.gptr[g + 1]; ++p)
+    for (int p = Y.gstart[g] + 1; p < Y.gstart[g + 1]; ++p)
       if (Y.perm[p] != Y.perm[p - 1] + 1) throw Error(-2, "smoother group rows not consecutive");
   }
   // stage independence: coupled rows of different groups lie in different stages
   std::vector<int> stage(ng);
   for (int c = 0; c < ns; ++c)
-    for (int g = L.sptr[c]; g < L.sptr[c + 1]; ++g) stage[g] = c;
+    for (int g = Y.sgrp[c]; g < Y.sgrp[c + 1]; ++g) stage[g] = c;
   Y.dboff.assign(ng + 1, 0);
   for (int g = 0; g < ng; ++g) {
-    const int k = L.gptr[g + 1] - L.gptr[g];
+    const int k = Y.gstart[g + 1] - Y.gstart[g];
     Y.dboff[g + 1] = Y.dboff[g] + k * k;
   }
   Y.dblk.assign(Y.dboff[ng], 0.0);
@@ -258,7 +284,7 @@ inline void build_level_layout(const HostLevel& L, LevelLayout& Y) {
   if (Y.sell) {
     Y.sslab.assign(ns + 1, 0);
     for (int c = 0; c < ns; ++c) {
-      const int r0 = Y.gstart[L.sptr[c]], r1 = Y.gstart[L.sptr[c + 1]];
+      const int r0 = Y.gstart[Y.sgrp[c]], r1 = Y.gstart[Y.sgrp[c + 1]];
       for (int b = r0; b < r1; b += 64) {
         Slab s;
         s.row0 = b;
@@ -324,7 +350,14 @@ inline void build_transfer_layout(const HostLevel& L, const LevelLayout& Yf, con
   T.nagg = na;
   T.aptr = L.aptr;
   T.uoff = L.uoff;
-  T.U = L.U;
+  // U_a stored column-major (k_a x n_a): column l of a block is one
+  // contiguous, coalesced run for the wave that handles the aggregate.
+  T.U.resize(L.U.size());
+  for (int a = 0; a < na; ++a) {
+    const int m = L.aptr[a + 1] - L.aptr[a], k = L.coff[a + 1] - L.coff[a];
+    for (int li = 0; li < m; ++li)
+      for (int l = 0; l < k; ++l) T.U[(size_t)L.uoff[a] + (size_t)l * m + li] = L.U[(size_t)L.uoff[a] + (size_t)li * k + l];
+  }
   T.arows.resize(L.arows.size());
   for (size_t q = 0; q < L.arows.size(); ++q) T.arows[q] = Yf.iperm[L.arows[q]];
   T.cst.resize(na);

@@ -474,13 +474,23 @@ __global__ __launch_bounds__(kBlock) void k_l1norm_grp(int ng, const int* __rest
 // ------------------------------------------------------------- transfers
 
 // r_c = P^T s with P = blockdiag(U_a): one wave per aggregate, lane li takes
-// member li; r_c[cst_a + l] = sum_li U_a[li, l] s[member li].
-template <typename T>
+// member li; r_c[cst_a + l] = sum_li U_a[li, l] s[member li].  U_a is stored
+// column-major (U[l * n_a + li]).
+//
+// The k coarse rows of an aggregate are one smoother group of the next level,
+// so the kernel can also start that level's pre-smoothing from x_c = 0
+// (INIT = 1: the groups of stage 0 solve their lower-triangular diagonal block,
+// the others are zero -- the first Gauss-Seidel stage; INIT = 2: x_c = r_c / d_l1,
+// the first l1-Jacobi sweep).  cgrp[a] is the group of aggregate a on the next
+// level, ng0 the number of groups in its stage 0.
+template <typename T, int INIT>
 __global__ __launch_bounds__(kBlock) void k_restrict(int nagg, const int* __restrict__ aptr,
                                                      const int* __restrict__ arows, const int* __restrict__ uoff,
                                                      const int* __restrict__ cst, const int* __restrict__ kk,
                                                      const T* __restrict__ U, const T* __restrict__ s,
-                                                     T* __restrict__ rc) {
+                                                     T* __restrict__ rc, const int* __restrict__ cgrp, int ng0,
+                                                     const int* __restrict__ cdboff, const T* __restrict__ cdblk,
+                                                     const T* __restrict__ cdl1, T* __restrict__ xc) {
   const int a = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   if (a >= nagg) return;
   const int lane = threadIdx.x & 63;
@@ -493,15 +503,43 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nagg, const int* __rest
     const T sv = s[arows[m0 + li]];
 #pragma unroll
     for (int q = 0; q < kKmax; ++q)
-      if (q < k) acc[q] += Ua[li * k + q] * sv;
+      if (q < k) acc[q] += Ua[q * na + li] * sv;
   }
   const int c0 = cst[a];
 #pragma unroll
   for (int q = 0; q < kKmax; ++q) {
     if (q < k) {
-      const T t = seg_sum<64>(acc[q]);
-      if (lane == q) rc[c0 + q] = t;
+      acc[q] = seg_sum<64>(acc[q]);
+      if (lane == q) rc[c0 + q] = acc[q];
     }
+  }
+  if (INIT == 1) {
+    const int g = cgrp[a];
+    T xv[kKmax];
+    if (g < ng0) {
+      const T* B = cdblk + cdboff[g];
+#pragma unroll
+      for (int l = 0; l < kKmax; ++l) {
+        xv[l] = T(0);
+        if (l < k) {
+          T t = acc[l];
+#pragma unroll
+          for (int q = 0; q < kKmax; ++q)
+            if (q < l) t -= B[l * k + q] * xv[q];
+          xv[l] = t / B[l * k + l];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int l = 0; l < kKmax; ++l) xv[l] = T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < kKmax; ++q)
+      if (q < k && lane == q) xc[c0 + q] = xv[q];
+  } else if (INIT == 2) {
+#pragma unroll
+    for (int q = 0; q < kKmax; ++q)
+      if (q < k && lane == q) xc[c0 + q] = acc[q] / cdl1[c0 + q];
   }
 }
 
@@ -527,93 +565,43 @@ __global__ __launch_bounds__(kBlock) void k_prolong(int nagg, const int* __restr
     T t = T(0);
 #pragma unroll
     for (int q = 0; q < kKmax; ++q)
-      if (q < k) t += Ua[li * k + q] * xv[q];
+      if (q < k) t += Ua[q * na + li] * xv[q];
     x[arows[m0 + li]] += t;
+  }
+}
+
+// x += P x_c in fine-row order (coalesced): thread per fine row i with
+// cinfo[i] = 8 * (first coarse row of its aggregate) + (k - 1) and the row's
+// k entries of U at Urow[q * n + i] (zero past k).
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kBlock) void k_prolong_rows(int n, const int* __restrict__ cinfo,
+                                                         const T* __restrict__ Urow, const T* __restrict__ xc,
+                                                         T* __restrict__ x) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const int ci = cinfo[i];
+    const int c0 = ci >> 3, k = (ci & 7) + 1;
+    T t = T(0);
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q)
+      if (q < k) t += Urow[(size_t)q * n + i] * xc[c0 + q];
+    x[i] += t;
   }
 }
 
 // ------------------------------------------------------------- coarsest
 
-// y = A x (add = 0) or y += A x (add = 1), A dense row-major n x n, one wave per row.
-__global__ __launch_bounds__(kBlock) void k_gemv(int n, const double* __restrict__ A, const double* __restrict__ x,
-                                                 double* __restrict__ y, int add) {
+// y = A x (add = 0) or y += A x (add = 1), A dense row-major n x n with
+// leading dimension ld, one wave per row.
+__global__ __launch_bounds__(kBlock) void k_gemv(int n, int ld, const double* __restrict__ A,
+                                                 const double* __restrict__ x, double* __restrict__ y, int add) {
   const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   if (i >= n) return;
   const int lane = threadIdx.x & 63;
-  const double* Ai = A + (size_t)i * n;
+  const double* Ai = A + (size_t)i * ld;
   double acc = 0.0;
   for (int j = lane; j < n; j += 64) acc += Ai[j] * x[j];
   acc = wave_sum(acc);
   if (lane == 0) y[i] = add ? y[i] + acc : acc;
-}
-
-// t = r - A z with A in CSR (coarsest level), one wave per row.
-__global__ __launch_bounds__(kBlock) void k_csr_resid_wave(int n, const int* __restrict__ rp,
-                                                           const int* __restrict__ ci, const double* __restrict__ v,
-                                                           const double* __restrict__ r, const double* __restrict__ z,
-                                                           double* __restrict__ t) {
-  const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  if (i >= n) return;
-  const int lane = threadIdx.x & 63;
-  double acc = 0.0;
-  for (int e = rp[i] + lane; e < rp[i + 1]; e += 64) acc += v[e] * z[ci[e]];
-  acc = wave_sum(acc);
-  if (lane == 0) t[i] = r[i] - acc;
-}
-
-// Dense Cholesky A = L L^T (lower triangle overwrites A), one block of 1024
-// threads, left-looking by columns.  flag is set if a pivot is not positive.
-__global__ __launch_bounds__(1024) void k_cholesky(int n, double* M, int* flag) {
-  __shared__ double red[16];
-  for (int j = 0; j < n; ++j) {
-    double part = 0.0;
-    for (int k = threadIdx.x; k < j; k += 1024) part += M[(size_t)j * n + k] * M[(size_t)j * n + k];
-    part = wave_sum(part);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int w = 0; w < 16; ++w) s += red[w];
-      const double d = M[(size_t)j * n + j] - s;
-      if (!(d > 0.0)) *flag = 1;
-      M[(size_t)j * n + j] = sqrt(d);
-    }
-    __syncthreads();
-    const double ljj = M[(size_t)j * n + j];
-    for (int i = j + 1 + threadIdx.x; i < n; i += 1024) {
-      double t = M[(size_t)i * n + j];
-      for (int k = 0; k < j; ++k) t -= M[(size_t)i * n + k] * M[(size_t)j * n + k];
-      M[(size_t)i * n + j] = t / ljj;
-    }
-    __syncthreads();
-  }
-}
-
-// X = A^{-1} = L^{-T} L^{-1}: thread j solves L y = e_j then L^T x = y for
-// column j of X (row-major; neighbouring threads touch neighbouring columns).
-__global__ __launch_bounds__(kBlock) void k_chol_inverse(int n, const double* __restrict__ L, double* __restrict__ X) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= n) return;
-  for (int i = 0; i < n; ++i) {
-    double s = (i == j) ? 1.0 : 0.0;
-    if (i >= j) {
-      for (int k = j; k < i; ++k) s -= L[(size_t)i * n + k] * X[(size_t)k * n + j];
-      s /= L[(size_t)i * n + i];
-    }
-    X[(size_t)i * n + j] = s;
-  }
-  for (int i = n - 1; i >= 0; --i) {
-    double s = X[(size_t)i * n + j];
-    for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * X[(size_t)k * n + j];
-    X[(size_t)i * n + j] = s / L[(size_t)i * n + i];
-  }
-}
-
-// Dense copy of a CSR matrix (coarsest level) into M (zeroed beforehand).
-__global__ __launch_bounds__(kBlock) void k_csr_to_dense(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                         const double* __restrict__ v, double* __restrict__ M) {
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
-    for (int e = rp[i]; e < rp[i + 1]; ++e) M[(size_t)i * n + ci[e]] += v[e];
 }
 
 // ------------------------------------------------- values, casts, gradient

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "hier_host.hpp"
+#include "dense.hpp"
 #include "kernels.hpp"
 #include "mvamg.h"
 
@@ -74,16 +75,19 @@ struct DevLevel {
 struct DevTransfer {
   int nagg = 0;
   int *aptr = nullptr, *arows = nullptr, *uoff = nullptr, *cst = nullptr, *kk = nullptr;
+  int* cgrp = nullptr;  // group of each aggregate on the next level (if that level is smoothed)
+  int nf = 0, kmax = 1;  // fine rows, widest block
+  int* cinfo = nullptr;  // per fine row: 8 * first coarse row + (k - 1)
+  double* Urow = nullptr;  // per fine row, column-major [q * nf + row]
+  float* Urow32 = nullptr;
   double* U = nullptr;
   float* U32 = nullptr;
 };
 
 struct DevCoarse {
-  int n = 0;
-  double* Ainv = nullptr;
-  int *rp = nullptr, *ci = nullptr;
-  double* v = nullptr;
-  double *r = nullptr, *z = nullptr, *t = nullptr;
+  int n = 0, np = 0;         // size, padded size (multiple of 64)
+  double* Ainv = nullptr;    // np x np row-major, inverse of the coarsest matrix
+  double *r = nullptr, *z = nullptr;
 };
 
 }  // namespace
@@ -117,6 +121,14 @@ struct mvamg_hier {
     HIPCHECK(hipMalloc(&ptr, count * sizeof(T)));
     allocs.push_back(ptr);
     return (T*)ptr;
+  }
+  void dfree(void* ptr) {
+    for (auto it = allocs.begin(); it != allocs.end(); ++it)
+      if (*it == ptr) {
+        (void)hipFree(ptr);
+        allocs.erase(it);
+        return;
+      }
   }
   template <typename T>
   T* upload_vec(const std::vector<T>& v, hipStream_t st) {
@@ -176,6 +188,16 @@ const double* ldl1<double>(const DevLevel& L) {
 template <>
 const float* ldl1<float>(const DevLevel& L) {
   return L.dl1_32;
+}
+template <typename T>
+const T* tUrow(const DevTransfer& P);
+template <>
+const double* tUrow<double>(const DevTransfer& P) {
+  return P.Urow;
+}
+template <>
+const float* tUrow<float>(const DevTransfer& P) {
+  return P.Urow32;
 }
 template <typename T>
 const T* tU(const DevTransfer& P);
@@ -281,12 +303,9 @@ void coarse_solve(mvamg_hier* h, const T* r, T* z, hipStream_t st);
 
 template <>
 void coarse_solve<double>(mvamg_hier* h, const double* r, double* z, hipStream_t st) {
+  // z = A_L^{-1} r with the inverse formed at upload from the Cholesky factor
   DevCoarse& C = h->co;
-  const int grid = (C.n + 3) / 4;
-  // z = A^{-1} r, one step of refinement: z += A^{-1} (r - A z)
-  k_gemv<<<grid, kBlock, 0, st>>>(C.n, C.Ainv, r, z, 0);
-  k_csr_resid_wave<<<grid, kBlock, 0, st>>>(C.n, C.rp, C.ci, C.v, r, z, C.t);
-  k_gemv<<<grid, kBlock, 0, st>>>(C.n, C.Ainv, C.t, z, 1);
+  k_gemv<<<(C.n + 3) / 4, kBlock, 0, st>>>(C.n, C.np, C.Ainv, r, z, 0);
   LAUNCHCHECK("coarse_solve");
 }
 
@@ -299,9 +318,10 @@ void coarse_solve<float>(mvamg_hier* h, const float* r, float* z, hipStream_t st
   LAUNCHCHECK("coarse_solve32");
 }
 
-// x = B_l r (one V-cycle from a zero guess)
+// x = B_l r (one V-cycle from a zero guess).  x_started: the restriction of
+// the finer level has already performed the first pre-smoothing step on x.
 template <typename T>
-void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st) {
+void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st, bool x_started = false) {
   if (l == h->nl - 1) {
     coarse_solve<T>(h, r, x, st);
     return;
@@ -314,18 +334,37 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   T* xc = lx<T>(C);
   // pre-smoothing: one forward sweep from x = 0
   if (smoother == MVAMG_SMOOTH_GS) {
-    zero_stage0<T>(L, r, x, st);
+    if (!x_started) zero_stage0<T>(L, r, x, st);
     for (int c = 1; c < L.ns; ++c) gs_stage<T>(L, c, r, x, 0, st);
-  } else {
+  } else if (!x_started) {
     k_l1_init<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, ldl1<T>(L), r, x);
   }
-  // residual, restriction
+  // residual, restriction (fused with the first smoothing step of the next level)
   resid<T, 0>(h, L, r, x, s, M_NONE, st);
   const int tg = (P.nagg + 3) / 4;
-  k_restrict<T><<<tg, kBlock, 0, st>>>(P.nagg, P.aptr, P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc);
+  const bool next_smoothed = (l + 2 < h->nl);
+  if (!next_smoothed) {
+    k_restrict<T, 0><<<tg, kBlock, 0, st>>>(P.nagg, P.aptr, P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc,
+                                            nullptr, 0, nullptr, nullptr, nullptr, nullptr);
+  } else if (smoother == MVAMG_SMOOTH_GS) {
+    k_restrict<T, 1><<<tg, kBlock, 0, st>>>(P.nagg, P.aptr, P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc,
+                                            P.cgrp, C.h_sgrp[1], C.dboff, ldblk<T>(C), nullptr, xc);
+  } else {
+    k_restrict<T, 2><<<tg, kBlock, 0, st>>>(P.nagg, P.aptr, P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc,
+                                            nullptr, 0, nullptr, nullptr, ldl1<T>(C), xc);
+  }
   LAUNCHCHECK("restrict");
-  vcycle<T>(h, l + 1, rc, xc, smoother, st);
-  k_prolong<T><<<tg, kBlock, 0, st>>>(P.nagg, P.aptr, P.arows, P.uoff, P.cst, P.kk, tU<T>(P), xc, x);
+  vcycle<T>(h, l + 1, rc, xc, smoother, st, next_smoothed);
+  {
+    const int pg = grid_for(P.nf);
+    switch (P.kmax) {
+      case 1: k_prolong_rows<T, 1><<<pg, kBlock, 0, st>>>(P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
+      case 2: k_prolong_rows<T, 2><<<pg, kBlock, 0, st>>>(P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
+      case 3:
+      case 4: k_prolong_rows<T, 4><<<pg, kBlock, 0, st>>>(P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
+      default: k_prolong_rows<T, 8><<<pg, kBlock, 0, st>>>(P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
+    }
+  }
   LAUNCHCHECK("prolong");
   // post-smoothing: one backward sweep
   if (smoother == MVAMG_SMOOTH_GS) {
@@ -669,12 +708,50 @@ mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** 
       P.uoff = h->upload_vec(T.uoff, st);
       P.cst = h->upload_vec(T.cst, st);
       P.kk = h->upload_vec(T.kk, st);
+      if (l + 2 < H.nl) {
+        // group index, on level l+1, of the rows cst[a] .. cst[a] + k - 1
+        const LevelLayout& yc = Y[l + 1];
+        std::vector<int> rowgrp(yc.n), cg(T.nagg);
+        for (int g = 0; g + 1 < (int)yc.gstart.size(); ++g)
+          for (int p = yc.gstart[g]; p < yc.gstart[g + 1]; ++p) rowgrp[p] = g;
+        for (int a = 0; a < T.nagg; ++a) {
+          const int g = rowgrp[T.cst[a]];
+          if (yc.gstart[g] != T.cst[a] || yc.gstart[g + 1] - yc.gstart[g] != T.kk[a])
+            throw Error(MVAMG_ERR_FILE, "coarse dofs of an aggregate are not one smoother group");
+          cg[a] = g;
+        }
+        P.cgrp = h->upload_vec(cg, st);
+      }
       P.U = h->upload_vec(T.U, st);
       P.U32 = h->dalloc<float>(T.U.size());
       k_to_f32<<<grid_for((int64_t)T.U.size()), kBlock, 0, st>>>((int64_t)T.U.size(), P.U, P.U32);
       LAUNCHCHECK("U32");
+      {
+        // row-order copy of P for the prolongation
+        const int nf = H.lv[l].n;
+        int kmax = 1;
+        for (int a = 0; a < T.nagg; ++a) kmax = std::max(kmax, T.kk[a]);
+        std::vector<int> cinfo(nf);
+        std::vector<double> urow((size_t)kmax * nf, 0.0);
+        for (int a = 0; a < T.nagg; ++a) {
+          const int m = T.aptr[a + 1] - T.aptr[a], k = T.kk[a];
+          if ((int64_t)T.cst[a] * 8 >= ((int64_t)1 << 31)) throw Error(MVAMG_ERR_ARG, "coarse level too large");
+          for (int li = 0; li < m; ++li) {
+            const int p = T.arows[T.aptr[a] + li];
+            cinfo[p] = T.cst[a] * 8 + (k - 1);
+            for (int q = 0; q < k; ++q) urow[(size_t)q * nf + p] = T.U[(size_t)T.uoff[a] + (size_t)q * m + li];
+          }
+        }
+        P.nf = nf;
+        P.kmax = kmax;
+        P.cinfo = h->upload_vec(cinfo, st);
+        P.Urow = h->upload_vec(urow, st);
+        P.Urow32 = h->dalloc<float>(urow.size());
+        k_to_f32<<<grid_for((int64_t)urow.size()), kBlock, 0, st>>>((int64_t)urow.size(), P.Urow, P.Urow32);
+        LAUNCHCHECK("Urow32");
+      }
     }
-    // ---- coarsest level: dense Cholesky and inverse on the device
+    // ---- coarsest level: blocked dense Cholesky and inverse on the device
     {
       const HostLevel& C = H.lv[H.nl - 1];
       DevLevel& LC = h->lv[H.nl - 1];
@@ -685,26 +762,42 @@ mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** 
       LC.x32 = h->dalloc<float>(C.n);
       DevCoarse& D = h->co;
       D.n = C.n;
-      if ((int64_t)C.n * C.n > ((int64_t)1 << 28)) throw Error(MVAMG_ERR_ARG, "coarsest level too large for a dense solve");
-      D.rp = h->upload_vec(C.rp, st);
-      D.ci = h->upload_vec(C.ci, st);
-      D.v = h->upload_vec(C.v, st);
+      D.np = ((C.n + TD - 1) / TD) * TD;
+      const int np = D.np, nb = np / TD;
+      if ((int64_t)np * np > ((int64_t)1 << 29)) throw Error(MVAMG_ERR_ARG, "coarsest level too large for a dense solve");
       D.r = h->dalloc<double>(C.n);
       D.z = h->dalloc<double>(C.n);
-      D.t = h->dalloc<double>(C.n);
-      double* M = h->dalloc<double>((size_t)C.n * C.n);
-      D.Ainv = h->dalloc<double>((size_t)C.n * C.n);
+      int* rp = h->upload_vec(C.rp, st);
+      int* ci = h->upload_vec(C.ci, st);
+      double* v = h->upload_vec(C.v, st);
+      double* M = h->dalloc<double>((size_t)np * np);
+      double* Li = h->dalloc<double>((size_t)np * np);
+      D.Ainv = h->dalloc<double>((size_t)np * np);
       int* flag = h->dalloc<int>(1);
-      HIPCHECK(hipMemsetAsync(M, 0, sizeof(double) * (size_t)C.n * C.n, st));
+      HIPCHECK(hipMemsetAsync(M, 0, sizeof(double) * (size_t)np * np, st));
       HIPCHECK(hipMemsetAsync(flag, 0, sizeof(int), st));
-      k_csr_to_dense<<<grid_for(C.n), kBlock, 0, st>>>(C.n, D.rp, D.ci, D.v, M);
-      k_cholesky<<<1, 1024, 0, st>>>(C.n, M, flag);
-      k_chol_inverse<<<(C.n + kBlock - 1) / kBlock, kBlock, 0, st>>>(C.n, M, D.Ainv);
+      k_csr_to_padded<<<grid_for(np), kBlock, 0, st>>>(C.n, np, rp, ci, v, M);
+      for (int kb = 0; kb < nb; ++kb) {
+        k_potrf_tile<<<1, 256, 0, st>>>(M, np, kb, flag);
+        const int m = nb - kb - 1;
+        if (m > 0) {
+          k_trsm_tile<<<m, 256, 0, st>>>(M, np, kb);
+          k_update_tiles<<<dim3(m, m), 256, 0, st>>>(M, np, kb);
+        }
+      }
+      k_trtri_diag<<<nb, 256, 0, st>>>(M, Li, np);
+      for (int i = 1; i < nb; ++i) k_trtri_row<<<i, 256, 0, st>>>(M, Li, np, i);
+      k_lauum<<<dim3(nb, nb), 256, 0, st>>>(Li, D.Ainv, np);
       LAUNCHCHECK("coarsest factorisation");
       int hflag = 0;
       HIPCHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
       HIPCHECK(hipStreamSynchronize(st));
       if (hflag) throw Error(MVAMG_ERR_NOT_SPD, "coarsest matrix is not positive definite (Cholesky pivot <= 0)");
+      h->dfree(M);
+      h->dfree(Li);
+      h->dfree(rp);
+      h->dfree(ci);
+      h->dfree(v);
     }
     // ---- level-0 extras and CG state
     {

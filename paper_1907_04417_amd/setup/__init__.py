@@ -30,7 +30,10 @@ class _Params(ctypes.Structure):
 class SetupParams:
     """Parameters of the setup; defaults follow Section 5 of the paper
     (nu = 15 testing steps, rho_des = 0.8, at most 15 stages, TOL = 0.1,
-    three bootstrap levels composed into aggregates of at most 64 nodes)."""
+    three bootstrap levels composed into aggregates of at most 64 nodes).
+    A level of at most coarse_cap rows is the coarsest one and is solved
+    directly; 5000 gives the three-level hierarchies of the paper's tables on
+    problems of a few million unknowns."""
 
     nvec_max: int = 4
     nu: int = 15
@@ -38,7 +41,7 @@ class SetupParams:
     maxstage: int = 15
     tol_svd: float = 0.1
     compose: int = 3
-    coarse_cap: int = 2048
+    coarse_cap: int = 5000
     boot_coarse_min: int = 64
     hier_stage: int = -1
     store_w: int = 1

@@ -863,7 +863,7 @@ int mvsetup_build(int n, const int* rowptr, const int* col, const double* val,
     for (int l = 0;; ++l) {
       MvLevel& M = mv[l];
       const int nl = M.A.n;
-      if (nl <= prm.coarse_cap || t >= D) break;
+      if ((l > 0 && nl <= prm.coarse_cap) || t >= D) break;
       const int tn = std::min(t + prm.compose, D);
       // composite aggregate map of bootstrap nodes at level t -> level tn
       const int nb_t = H.lv[t].A.n;

@@ -235,3 +235,39 @@ def test_graph_replay_matches_eager(cases, torch_gpu):
         assert np.array_equal(xg.cpu().numpy(), xe.cpu().numpy())
         assert np.array_equal(rg.history, re_.history)
     Se.close()
+
+
+def test_full_size_jump128(torch_gpu):
+    """Full benchmark size (128^3, n = 2,097,152; hierarchy as bench.py uses
+    it): one V-cycle against the oracle's, then the whole CG history and the
+    solution.  The coarsest level (4648 rows, condition number about 8e6) is
+    solved with its inverse, whose rounding differs from the oracle's
+    triangular solves by about 1e-11 relative, so the cycle is compared to
+    1e-10 here."""
+    import time
+    torch = torch_gpu
+    t = time.time()
+    P, path, st = workloads.load("jump128")
+    _say(f"[full] jump128 levels={st['n']} setup {time.time() - t:.1f}s")
+    S = mvamg.Solver(path)
+    t = time.time()
+    O = oracle.Oracle(path)
+    _say(f"  oracle factorisation {time.time() - t:.1f}s")
+    r = np.random.default_rng(9).standard_normal(P.n)
+    z = S.cycle(_t(torch, r)).cpu().numpy()
+    zo = O.vcycle(r)
+    err = _relinf(z, zo)
+    _say(f"  cycle rel err {err:.2e}")
+    assert err <= 1e-10
+    x, res = S.solve(_t(torch, P.b), rtol=1e-8)
+    t = time.time()
+    xo, ho, nito, sto = O.pcg(P.b, tol=1e-8)
+    _say(f"  gpu it={res.iterations} oracle it={nito} ({time.time() - t:.1f}s)")
+    m = min(len(res.history), len(ho))
+    herr = float(np.max(np.abs(res.history[:m] - ho[:m]) / ho[:m]))
+    xerr = _relinf(x.cpu().numpy(), xo)
+    _say(f"  history rel err {herr:.2e} solution rel err {xerr:.2e} true res {res.rel_res_true:.2e}")
+    _hist_parity(res.history, ho, 1e-8)
+    assert xerr <= 1e-9
+    assert res.converged and res.rel_res_true <= 1.01e-8
+    S.close()
