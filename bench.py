@@ -3,18 +3,27 @@
 Workload (N = 1): 3-D jump-coefficient diffusion, 7-point finite differences
 on 128^3 nodes (n = 2,097,152), coefficient 1e3 or 1e-3 on 8^3-node cubes
 selected with p = 0.5, else 1; b = A x*, x* ~ U[-1, 1]; hierarchy with at most
-4 smooth vectors (setup on the host, untimed).  One step = one preconditioned
-CG solve from x_0 = 0 to ||r|| <= 1e-8 ||r_0|| with the binary64 cycle, all
-inputs resident in HBM.  The binary32-cycle variant is timed in the same run
-and reported beside it.
+4 smooth vectors (host setup, untimed).  One step = one preconditioned CG
+solve from x_0 = 0 to ||r|| <= 1e-8 ||r_0|| with the binary64 cycle, inputs
+resident in HBM.  The binary32-cycle variant (binary64 CG outside) is timed in
+the same run and reported beside it.
 
-Prints one JSON line (see the keys below).
+Timing: `value` comes from K uninstrumented steps.  A second pass of the same
+K steps carries start/stop HIP events on every cycle kernel (the library's
+measurement switch) and yields the per-kernel-class time and algorithmic
+bytes; the dominant class gives the `roofline` object.  Measured HBM traffic
+(rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated with a plain copy) is taken
+from profiles/traffic.md when it was recorded for the current kernel source.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -24,25 +33,54 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+WORKLOAD_DESC = {
+    "jump128": "jump128: 3-D jump-coefficient diffusion, 7-point FD, 128^3 nodes, coefficient 1e3/1e-3 on 8^3 "
+               "cubes (p=0.5), <=4 smooth vectors, rtol 1e-8",
+    "aniso64": "aniso64: 2-D rotated anisotropic diffusion, 9-point FD, 64^2 interior nodes, eps=1e-2, "
+               "theta=pi/4, <=3 smooth vectors, rtol 1e-8",
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def counted_bytes_per_iteration(lv, tr_U, nvec_k):
-    """Algorithmic HBM bytes of one binary64 CG iteration (values 8 B, indices 4 B):
-    S_l = 12 nnz_l + 4 (n_l + 1) per pass over A_l, T_l = 8 sum(n_a k_a) + 4 n_l + 8 n_agg
-    per pass over P_l, V_l = 8 n_l per vector pass."""
+def kernel_source_hash() -> str:
+    h = hashlib.sha1()
+    d = os.path.join(ROOT, "paper_1907_04417_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hpp", ".hip")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:12]
+
+
+def recorded_traffic(kclass_name: str, workload: str):
+    """Per-launch HBM bytes of a kernel class from profiles/traffic.md, or None
+    when none was recorded for the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.md")
+    if not os.path.exists(path):
+        return None
+    src = kernel_source_hash()
+    for line in open(path):
+        m = re.match(r"\s*traffic:\s+(\S+)\s+(\S+)\s+bytes_per_launch=([0-9.eE+]+)\s+source=(\S+)", line)
+        if m and m.group(1) == kclass_name and m.group(2) == workload and m.group(4) == src:
+            return float(m.group(3))
+    return None
+
+
+def counted_bytes_per_iteration(lv, nu):
+    """Algorithmic HBM bytes of one binary64 CG iteration: a pass over A_l is
+    12 nnz_l + 4 (n_l + 1) bytes, a pass over P_l is 8 sum(n_a k_a) + 4 n_l + 8 n_{l+1},
+    a vector pass 8 n_l; the coarsest solve reads its n_L^2 inverse once."""
     n, nnz = lv["n"], lv["nnz"]
     L = len(n) - 1
     S = [12 * nnz[l] + 4 * (n[l] + 1) for l in range(L + 1)]
     V = [8 * n[l] for l in range(L + 1)]
-    b = S[0] + 15 * V[0]  # CG: A p, dot products, vector updates
+    b = S[0] + 15 * V[0]
     for l in range(L):
-        T = 8 * tr_U[l] + 4 * n[l] + 8 * n[l + 1]
+        T = 8 * nu[l] + 4 * n[l] + 8 * n[l + 1]
         b += 3 * S[l] + 2 * T + 13 * V[l]
-    b += 3 * 8 * n[L] * n[L]  # coarsest: two dense products with A_L^{-1} and one residual
+    b += 8 * n[L] * n[L]
     return b
 
 
@@ -53,11 +91,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="jump128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--no-profile-pass", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path; "
+              f"run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -80,48 +118,72 @@ def main():
         return mvamg.pcg_solve(S.h, b, x, rtol=1e-8, maxit=1000, precision=precision, history=hist,
                                stream=stream)
 
-    results = {}
-    for prec in (64, 32):
+    def timed(precision):
         for _ in range(args.warmup):
-            solve(prec)
+            solve(precision)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t_wall = time.perf_counter()
         e0.record(stream)
-        its = []
         for _ in range(args.steps):
-            inf = solve(prec)
-            its.append(inf.iterations)
+            inf = solve(precision)
         e1.record(stream)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t_wall
-        ms = e0.elapsed_time(e1) / args.steps
+        return e0.elapsed_time(e1) / args.steps, inf
+
+    results = {}
+    for prec in (64, 32):
+        ms, inf = timed(prec)
         xs = x.cpu().numpy()
-        err = float(np.abs(xs - P.x_star).max() / np.abs(P.x_star).max())
-        results[prec] = dict(ms=ms, wall_ms=1e3 * wall / args.steps, nit=its[-1], converged=bool(inf.converged),
-                             rel_res_true=inf.rel_res_true, err_vs_xstar=err, x=xs)
-        log(f"[bench] precision {prec}: {ms:.3f} ms/solve, nit={its[-1]}, true_res={inf.rel_res_true:.2e}")
+        results[prec] = dict(ms=ms, nit=inf.iterations, converged=bool(inf.converged),
+                             rel_res_true=inf.rel_res_true, x=xs)
+        log(f"[bench] precision {prec}: {ms:.3f} ms/solve, nit={inf.iterations}, true_res={inf.rel_res_true:.2e}")
 
     H = read_hierarchy(path)
     lv = mvamg.levels(S.h)
-    tr_U = [int(T.U.shape[0]) for T in H.transfers]
-    bpi = counted_bytes_per_iteration(lv, tr_U, H.nvec)
+    nu = [int(T.U.shape[0]) for T in H.transfers]
+    bpi = counted_bytes_per_iteration(lv, nu)
     r64 = results[64]
-    gbs = bpi * r64["nit"] / (r64["ms"] * 1e-3) / 1e9
+
+    roofline = None
+    kernels = {}
+    if not args.no_profile_pass:
+        mvamg.profile(S.h, True)
+        t_prof = time.perf_counter()
+        for _ in range(args.steps):
+            solve(64)
+        torch.cuda.synchronize()
+        t_prof = (time.perf_counter() - t_prof) * 1e3 / args.steps
+        for kc, name in enumerate(mvamg.KC_NAMES):
+            nl, ms, by = mvamg.kernel_stats(S.h, kc)
+            if nl:
+                kernels[name] = dict(launches=nl // args.steps, ms_per_step=ms / args.steps,
+                                     us_per_launch=1e3 * ms / nl, gbs=by / (ms * 1e-3) / 1e9 if ms > 0 else None)
+        mvamg.profile(S.h, False)
+        dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+        kc = mvamg.KC_NAMES.index(dom)
+        dl = kernels[dom]
+        achieved = dl["gbs"]
+        traffic = recorded_traffic(dom, args.workload)
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
+                    "launches_per_step": dl["launches"], "us_per_launch": dl["us_per_launch"],
+                    "profiled_ms_per_step": t_prof}
+        log(f"[bench] dominant kernel class {dom}: {dl['ms_per_step']:.2f} ms/step over {dl['launches']} launches, "
+            f"{achieved:.0f} GB/s")
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        O = oracle.Oracle(H)
         tc = time.perf_counter()
-        _, ho, nit_c, _ = O.pcg(P.b, tol=1e-8, maxit=args.cpu_iters)
+        O = oracle.Oracle(H)
+        tf = time.perf_counter() - tc
+        tc = time.perf_counter()
+        _, ho, nit_c, _ = O.pcg(P.b, tol=1e-8)
         tcpu = time.perf_counter() - tc
-        per_it = tcpu / max(nit_c, 1)
-        est = per_it * r64["nit"]
-        cpu = dict(value=1.0 / est, unit="solves/s", cores=1, kind="oracle",
-                   sample=f"{nit_c} of the {r64['nit']} CG iterations of one solve of the same system "
-                          f"({tcpu:.1f} s), scaled to the full iteration count")
-        log(f"[bench] oracle: {per_it * 1e3:.1f} ms/iteration -> {est:.1f} s/solve")
+        cpu = dict(value=1.0 / tcpu, unit="solves/s", cores=1, kind="oracle",
+                   sample=f"one complete solve of the same system ({nit_c} CG iterations, {tcpu:.1f} s on one host "
+                          f"core; the oracle's own coarsest factorisation, {tf:.1f} s, is setup and not counted)")
+        log(f"[bench] oracle: {tcpu:.1f} s/solve ({nit_c} iterations)")
 
     r32 = results[32]
     out = {
@@ -137,16 +199,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "jump128: 3-D jump-coefficient diffusion, 7-point FD, 128^3 nodes, "
-                               "coefficient 1e3/1e-3 on 8^3 cubes (p=0.5), <=4 smooth vectors, rtol 1e-8",
-                   "n": P.n, "nnz": P.nnz, "levels": lv["n"], "level_nnz": lv["nnz"], "stages": lv["stages"],
-                   "opc": st["opc"], "nit": r64["nit"]},
-        "hbm_gbs_counted": gbs,
-        "bytes_per_iteration": bpi,
-        "mixed": {"value": 1e3 / r32["ms"], "unit": "solves/s", "ms_per_step": r32["ms"], "nit": r32["nit"],
-                  "speedup_vs_fp64": r64["ms"] / r32["ms"], "rel_res_true": r32["rel_res_true"],
-                  "err_vs_fp64_solution": float(np.abs(r32["x"] - r64["x"]).max() / np.abs(r64["x"]).max())},
+        "config": {"workload": WORKLOAD_DESC.get(args.workload, args.workload), "n": P.n, "nnz": P.nnz,
+                   "levels": lv["n"], "level_nnz": lv["nnz"], "stages": lv["stages"], "opc": st["opc"],
+                   "nit": r64["nit"]},
+        "roofline": roofline,
         "cpu_baseline": cpu,
+        "hbm_gbs_counted_whole_solve": bpi * r64["nit"] / (r64["ms"] * 1e-3) / 1e9,
+        "bytes_per_iteration": bpi,
+        "kernels": kernels,
+        "mixed": {"value": 1e3 / r32["ms"], "unit": "solves/s", "dtype": "f32 cycle, f64 CG",
+                  "ms_per_step": r32["ms"], "nit": r32["nit"], "speedup_vs_fp64": r64["ms"] / r32["ms"],
+                  "rel_res_true": r32["rel_res_true"],
+                  "err_vs_fp64_solution": float(np.abs(r32["x"] - r64["x"]).max() / np.abs(r64["x"]).max())},
     }
     print(json.dumps(out), flush=True)
 

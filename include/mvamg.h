@@ -140,6 +140,31 @@ mvamg_status mvamg_adjoint_solve(mvamg_hier* h, const double* dLdx_dev, double* 
 mvamg_status mvamg_grad_coeffs(mvamg_hier* h, const double* lambda_dev, const double* x_dev,
                                double* dval_dev, void* stream);
 
+/* ---------------------------------------------------------- measurement */
+
+/* Kernel classes for mvamg_kernel_stats. */
+enum {
+  MVAMG_KC_SMOOTH_FINE = 0,   /* smoother stages of the finest level */
+  MVAMG_KC_SMOOTH_COARSE = 1, /* smoother stages of coarser levels */
+  MVAMG_KC_SPMV = 2,          /* q = A p of CG (finest level) */
+  MVAMG_KC_RESIDUAL = 3,      /* s = r - A x inside the cycle (all smoothed levels) */
+  MVAMG_KC_RESTRICT = 4,      /* r_c = P^T s */
+  MVAMG_KC_PROLONG = 5,       /* x += P x_c */
+  MVAMG_KC_COARSE = 6,        /* coarsest solve (dense product with A_L^{-1}) */
+  MVAMG_KC_COUNT = 7
+};
+
+/* Measurement switch (not needed for solving).  enable != 0: every later
+   launch of the classes above carries start/stop HIP events on its stream
+   (graph replay is off meanwhile) and its algorithmic HBM bytes (each stored
+   matrix entry = value + 4-byte index, each vector element touched once) are
+   booked to its class.  Calling it resets the totals. */
+mvamg_status mvamg_profile(mvamg_hier* h, int enable);
+
+/* Launch count, summed kernel time (ms) and summed algorithmic bytes of one
+   kernel class since the last mvamg_profile call. */
+mvamg_status mvamg_kernel_stats(mvamg_hier* h, int kclass, int64_t* launches, double* ms, double* bytes);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* mvamg_last_error(void);
 

@@ -2,6 +2,7 @@
 // upload, V-cycle (Section 5: forward/backward Gauss-Seidel, block-diagonal
 // multiple-vector transfers of Section 4, exact coarsest solve) and
 // preconditioned CG with the paper's stopping rule (Section 5).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -34,10 +35,19 @@ void hipcheck(hipError_t e, const char* what) {
 #define HIPCHECK(x) hipcheck((x), #x)
 #define LAUNCHCHECK(name) hipcheck(hipGetLastError(), name)
 
+// grid of a grid-stride kernel whose block partials are reduced afterwards
 int grid_for(int64_t n) {
   int64_t b = (n + kBlock - 1) / kBlock;
   if (b < 1) b = 1;
   if (b > 2048) b = 2048;
+  return (int)b;
+}
+
+// grid of a pure elementwise kernel: one element per thread
+int grid_elem(int64_t n) {
+  int64_t b = (n + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > 65535) b = 65535;
   return (int)b;
 }
 
@@ -49,6 +59,8 @@ struct DevLevel {
   int rows0 = 0;  // rows of stage 0 (point levels)
   std::vector<int> h_sgrp, h_sslab;
   int64_t nent = 0;    // stored off-group entries (with padding)
+  int64_t nnz = 0;     // stored entries of A_l (file), for byte counts
+  std::vector<int64_t> stage_rows, stage_nnz;
   int64_t ndblk = 0;
   // device arrays
   Slab* slabs = nullptr;
@@ -77,6 +89,7 @@ struct DevTransfer {
   int *aptr = nullptr, *arows = nullptr, *uoff = nullptr, *cst = nullptr, *kk = nullptr;
   int* cgrp = nullptr;  // group of each aggregate on the next level (if that level is smoothed)
   int nf = 0, kmax = 1;  // fine rows, widest block
+  int64_t nu = 0;        // entries of the U blocks
   int* cinfo = nullptr;  // per fine row: 8 * first coarse row + (k - 1)
   double* Urow = nullptr;  // per fine row, column-major [q * nf + row]
   float* Urow32 = nullptr;
@@ -112,6 +125,17 @@ struct mvamg_hier {
   hipStream_t cap = nullptr;              // stream used only to capture graphs
   std::map<int, hipGraphExec_t> graphs;   // one CG iteration per (precision, smoother)
   bool use_graphs = true;
+  // measurement: per-launch HIP events for every instrumented kernel
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Pending {
+    int kc;
+    hipEvent_t e0, e1;
+    double bytes;
+  };
+  std::vector<Pending> pending;
+  int64_t kc_launches[MVAMG_KC_COUNT] = {};
+  double kc_ms[MVAMG_KC_COUNT] = {}, kc_bytes[MVAMG_KC_COUNT] = {};
   std::vector<void*> allocs;
 
   template <typename T>
@@ -137,6 +161,11 @@ struct mvamg_hier {
     return d;
   }
   ~mvamg_hier() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    for (auto& pd : pending) {
+      (void)hipEventDestroy(pd.e0);
+      (void)hipEventDestroy(pd.e1);
+    }
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
     if (cap) (void)hipStreamDestroy(cap);
     for (void* p : allocs) (void)hipFree(p);
@@ -147,6 +176,47 @@ struct mvamg_hier {
 namespace {
 
 Red mkred(mvamg_hier* h) { return Red{h->part}; }
+
+hipEvent_t take_event(mvamg_hier* h) {
+  if (!h->ev_pool.empty()) {
+    hipEvent_t e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHECK(hipEventCreate(&e));
+  return e;
+}
+
+// Launches kern; while measurement is on, the launch carries start/stop
+// events (AMD's extended launch) and its algorithmic bytes are booked to
+// kernel class kc.
+template <typename... KArgs, typename... Args>
+void klaunch(mvamg_hier* h, int kc, double bytes, void (*kern)(KArgs...), dim3 grid, dim3 block, hipStream_t st,
+             Args... args) {
+  static_assert(sizeof...(KArgs) == sizeof...(Args), "argument count");
+  if (h->prof) {
+    hipEvent_t e0 = take_event(h), e1 = take_event(h);
+    hipExtLaunchKernelGGL(kern, grid, block, 0, st, e0, e1, 0, static_cast<KArgs>(args)...);
+    h->pending.push_back({kc, e0, e1, bytes});
+  } else {
+    hipLaunchKernelGGL(kern, grid, block, 0, st, static_cast<KArgs>(args)...);
+  }
+}
+
+// Books the finished measured launches (the stream has been synchronised).
+void harvest(mvamg_hier* h) {
+  for (auto& pd : h->pending) {
+    float ms = 0.0f;
+    HIPCHECK(hipEventElapsedTime(&ms, pd.e0, pd.e1));
+    h->kc_launches[pd.kc] += 1;
+    h->kc_ms[pd.kc] += ms;
+    h->kc_bytes[pd.kc] += pd.bytes;
+    h->ev_pool.push_back(pd.e0);
+    h->ev_pool.push_back(pd.e1);
+  }
+  h->pending.clear();
+}
 
 // Adds the block partials of the previous kernel (grid blocks) and applies `mode`.
 void finish(mvamg_hier* h, int nv, int grid, int mode, hipStream_t st) {
@@ -240,33 +310,44 @@ float* ls<float>(DevLevel& L) {
   return L.s32;
 }
 
+// algorithmic bytes of one smoother stage: every stored entry of its rows
+// (value + 4-byte index), and per row an index, r, x written and x read
 template <typename T>
-void gs_stage(const DevLevel& L, int c, const T* r, T* x, int backward, hipStream_t st) {
+double stage_bytes(const DevLevel& L, int c) {
+  return (double)L.stage_nnz[c] * (sizeof(T) + 4) + (double)L.stage_rows[c] * (4 + 3 * sizeof(T));
+}
+
+template <typename T>
+void gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, int backward, hipStream_t st) {
+  const int kc = (l == 0) ? MVAMG_KC_SMOOTH_FINE : MVAMG_KC_SMOOTH_COARSE;
+  const double by = stage_bytes<T>(L, c);
   if (L.sell) {
     const int s0 = L.h_sslab[c], s1 = L.h_sslab[c + 1];
     if (s1 <= s0) return;
     const int grid = (s1 - s0 + 3) / 4;
-    k_gs_sell<T><<<grid, kBlock, 0, st>>>(L.slabs, s0, s1, L.col, lval<T>(L), ldblk<T>(L), r, x);
+    klaunch(h, kc, by, k_gs_sell<T>, grid, kBlock, st, L.slabs, s0, s1, L.col, lval<T>(L), ldblk<T>(L), r, x);
   } else {
     const int g0 = L.h_sgrp[c], g1 = L.h_sgrp[c + 1];
     if (g1 <= g0) return;
     const int grid = (g1 - g0 + 3) / 4;
     switch (L.G) {
-      case 1: k_gs_grp<T, 1><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
-      case 2: k_gs_grp<T, 2><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
-      case 4: k_gs_grp<T, 4><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
-      default: k_gs_grp<T, 8><<<grid, kBlock, 0, st>>>(g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      case 1: klaunch(h, kc, by, k_gs_grp<T, 1>, grid, kBlock, st, g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      case 2: klaunch(h, kc, by, k_gs_grp<T, 2>, grid, kBlock, st, g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      case 4: klaunch(h, kc, by, k_gs_grp<T, 4>, grid, kBlock, st, g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      default: klaunch(h, kc, by, k_gs_grp<T, 8>, grid, kBlock, st, g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
     }
   }
   LAUNCHCHECK("gs_stage");
 }
 
 template <typename T>
-void zero_stage0(const DevLevel& L, const T* r, T* x, hipStream_t st) {
+void zero_stage0(mvamg_hier* h, int l, const DevLevel& L, const T* r, T* x, hipStream_t st) {
+  const int kc = (l == 0) ? MVAMG_KC_SMOOTH_FINE : MVAMG_KC_SMOOTH_COARSE;
+  const double by = (double)L.n * sizeof(T) + (double)L.stage_rows[0] * (2 * sizeof(T));
   if (L.sell) {
-    k_zero_stage0_point<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.rows0, ldblk<T>(L), r, x);
+    klaunch(h, kc, by, k_zero_stage0_point<T>, grid_elem(L.n), kBlock, st, L.n, L.rows0, ldblk<T>(L), r, x);
   } else {
-    k_zero_stage0_grp<T><<<grid_for(L.ng), kBlock, 0, st>>>(L.ng, L.h_sgrp[1], L.gstart, L.dboff, ldblk<T>(L), r, x);
+    klaunch(h, kc, by, k_zero_stage0_grp<T>, grid_for(L.ng), kBlock, st, L.ng, L.h_sgrp[1], L.gstart, L.dboff, ldblk<T>(L), r, x);
   }
   LAUNCHCHECK("zero_stage0");
 }
@@ -275,18 +356,21 @@ int resid_grid(const DevLevel& L);
 
 // MODE 0: s = r - A x;  MODE 1: s = A x and x.s reduced into scal by `mode`
 template <typename T, int MODE>
-void resid(mvamg_hier* h, const DevLevel& L, const T* r, const T* x, T* s, int mode, hipStream_t st) {
+void resid(mvamg_hier* h, int l, const DevLevel& L, const T* r, const T* x, T* s, int mode, hipStream_t st) {
   const Red red = mkred(h);
+  const int kc = MODE == 1 ? MVAMG_KC_SPMV : MVAMG_KC_RESIDUAL;
+  const double by = (double)L.nnz * (sizeof(T) + 4) + 4.0 * (L.n + 1) + (double)L.n * sizeof(T) * (MODE == 1 ? 2 : 3);
+  (void)l;
   if (L.sell) {
     const int grid = (L.nslabs + 3) / 4;
-    k_resid_sell<T, MODE><<<grid, kBlock, 0, st>>>(L.slabs, L.nslabs, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red);
+    klaunch(h, kc, by, k_resid_sell<T, MODE>, grid, kBlock, st, L.slabs, L.nslabs, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red);
   } else {
     const int grid = (L.ng + 3) / 4;
     switch (L.G) {
-      case 1: k_resid_grp<T, 1, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
-      case 2: k_resid_grp<T, 2, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
-      case 4: k_resid_grp<T, 4, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
-      default: k_resid_grp<T, 8, MODE><<<grid, kBlock, 0, st>>>(L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+      case 1: klaunch(h, kc, by, k_resid_grp<T, 1, MODE>, grid, kBlock, st, L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+      case 2: klaunch(h, kc, by, k_resid_grp<T, 2, MODE>, grid, kBlock, st, L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+      case 4: klaunch(h, kc, by, k_resid_grp<T, 4, MODE>, grid, kBlock, st, L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+      default: klaunch(h, kc, by, k_resid_grp<T, 8, MODE>, grid, kBlock, st, L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
     }
   }
   LAUNCHCHECK("resid");
@@ -305,7 +389,8 @@ template <>
 void coarse_solve<double>(mvamg_hier* h, const double* r, double* z, hipStream_t st) {
   // z = A_L^{-1} r with the inverse formed at upload from the Cholesky factor
   DevCoarse& C = h->co;
-  k_gemv<<<(C.n + 3) / 4, kBlock, 0, st>>>(C.n, C.np, C.Ainv, r, z, 0);
+  klaunch(h, MVAMG_KC_COARSE, 8.0 * C.n * C.n + 16.0 * C.n, k_gemv, (C.n + 3) / 4, kBlock, st, C.n, C.np,
+          C.Ainv, r, z, 0);
   LAUNCHCHECK("coarse_solve");
 }
 
@@ -334,43 +419,48 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   T* xc = lx<T>(C);
   // pre-smoothing: one forward sweep from x = 0
   if (smoother == MVAMG_SMOOTH_GS) {
-    if (!x_started) zero_stage0<T>(L, r, x, st);
-    for (int c = 1; c < L.ns; ++c) gs_stage<T>(L, c, r, x, 0, st);
+    if (!x_started) zero_stage0<T>(h, l, L, r, x, st);
+    for (int c = 1; c < L.ns; ++c) gs_stage<T>(h, l, L, c, r, x, 0, st);
   } else if (!x_started) {
     k_l1_init<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, ldl1<T>(L), r, x);
   }
   // residual, restriction (fused with the first smoothing step of the next level)
-  resid<T, 0>(h, L, r, x, s, M_NONE, st);
+  resid<T, 0>(h, l, L, r, x, s, M_NONE, st);
   const int tg = (P.nagg + 3) / 4;
+  const double tby = (double)P.nu * sizeof(T) + (double)L.n * (4 + sizeof(T)) + (double)C.n * sizeof(T);
   const bool next_smoothed = (l + 2 < h->nl);
   if (!next_smoothed) {
-    k_restrict<T, 0><<<tg, kBlock, 0, st>>>(P.nagg, P.aptr, P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc,
-                                            nullptr, 0, nullptr, nullptr, nullptr, nullptr);
+    klaunch(h, MVAMG_KC_RESTRICT, tby, k_restrict<T, 0>, tg, kBlock, st, P.nagg, P.aptr, P.arows, P.uoff, P.cst,
+            P.kk, tU<T>(P), s, rc, (const int*)nullptr, 0, (const int*)nullptr, (const T*)nullptr,
+            (const T*)nullptr, (T*)nullptr);
   } else if (smoother == MVAMG_SMOOTH_GS) {
-    k_restrict<T, 1><<<tg, kBlock, 0, st>>>(P.nagg, P.aptr, P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc,
-                                            P.cgrp, C.h_sgrp[1], C.dboff, ldblk<T>(C), nullptr, xc);
+    klaunch(h, MVAMG_KC_RESTRICT, tby + (double)C.n * sizeof(T), k_restrict<T, 1>, tg, kBlock, st, P.nagg, P.aptr,
+            P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc, P.cgrp, C.h_sgrp[1], C.dboff, ldblk<T>(C),
+            (const T*)nullptr, xc);
   } else {
-    k_restrict<T, 2><<<tg, kBlock, 0, st>>>(P.nagg, P.aptr, P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc,
-                                            nullptr, 0, nullptr, nullptr, ldl1<T>(C), xc);
+    klaunch(h, MVAMG_KC_RESTRICT, tby + (double)C.n * sizeof(T), k_restrict<T, 2>, tg, kBlock, st, P.nagg, P.aptr,
+            P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc, (const int*)nullptr, 0, (const int*)nullptr,
+            (const T*)nullptr, ldl1<T>(C), xc);
   }
   LAUNCHCHECK("restrict");
   vcycle<T>(h, l + 1, rc, xc, smoother, st, next_smoothed);
   {
-    const int pg = grid_for(P.nf);
+    const int pg = grid_elem(P.nf);
+    const double pby = (double)P.nu * sizeof(T) + (double)L.n * (4 + 2 * sizeof(T)) + (double)C.n * sizeof(T);
     switch (P.kmax) {
-      case 1: k_prolong_rows<T, 1><<<pg, kBlock, 0, st>>>(P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
-      case 2: k_prolong_rows<T, 2><<<pg, kBlock, 0, st>>>(P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
+      case 1: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 1>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
+      case 2: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 2>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
       case 3:
-      case 4: k_prolong_rows<T, 4><<<pg, kBlock, 0, st>>>(P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
-      default: k_prolong_rows<T, 8><<<pg, kBlock, 0, st>>>(P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
+      case 4: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 4>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
+      default: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 8>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
     }
   }
   LAUNCHCHECK("prolong");
   // post-smoothing: one backward sweep
   if (smoother == MVAMG_SMOOTH_GS) {
-    for (int c = L.ns - 1; c >= 0; --c) gs_stage<T>(L, c, r, x, 1, st);
+    for (int c = L.ns - 1; c >= 0; --c) gs_stage<T>(h, l, L, c, r, x, 1, st);
   } else {
-    resid<T, 0>(h, L, r, x, s, M_NONE, st);
+    resid<T, 0>(h, l, L, r, x, s, M_NONE, st);
     k_l1_update<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, ldl1<T>(L), s, x);
   }
   LAUNCHCHECK("vcycle");
@@ -391,7 +481,7 @@ void apply_B(mvamg_hier* h, const double* r, double* z, int precision, int smoot
 
 // q = A p (level 0, smoother order) with p.q into S_PQ / alpha
 void spmv0_dot(mvamg_hier* h, const double* p, double* q, int mode, hipStream_t st) {
-  resid<double, 1>(h, h->lv[0], nullptr, p, q, mode, st);
+  resid<double, 1>(h, 0, h->lv[0], nullptr, p, q, mode, st);
 }
 
 void dot(mvamg_hier* h, const double* a, const double* b, int mode, hipStream_t st) {
@@ -459,7 +549,7 @@ void cg_step_b(mvamg_hier* h, int precision, int smoother, hipStream_t st) {
     k_dot<1><<<eg, kBlock, 0, st>>>(n, h->z, h->r, nullptr, nullptr, mkred(h));
     finish(h, 1, eg, M_RZ, st);
   }
-  k_xpay<<<eg, kBlock, 0, st>>>(n, h->scal, h->z, h->p);
+  k_xpay<<<grid_elem(n), kBlock, 0, st>>>(n, h->scal, h->z, h->p);
   LAUNCHCHECK("xpay");
 }
 
@@ -508,7 +598,7 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
   k_gather<<<eg, kBlock, 0, st>>>(n, h->perm0, x_file, h->x);
   LAUNCHCHECK("gather");
   HIPCHECK(hipMemsetAsync(h->scal, 0, S_NSCAL * sizeof(double), st));
-  resid<double, 0>(h, L0, h->b, h->x, h->r, M_NONE, st);
+  resid<double, 0>(h, 0, L0, h->b, h->x, h->r, M_NONE, st);
   dot(h, h->r, h->r, M_STORE_R0, st);
   read_scalars(h, st);
   const double r0 = std::sqrt(h->pinned[S_R0]);
@@ -525,14 +615,14 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
     const int max_restarts = flex ? std::max(0, prm->max_restarts) : 0;
     for (int restart = 0; restart <= max_restarts && it < prm->maxit; ++restart) {
       if (restart > 0) {
-        resid<double, 0>(h, L0, h->b, h->x, h->r, M_NONE, st);
+        resid<double, 0>(h, 0, L0, h->b, h->x, h->r, M_NONE, st);
         inf.restarts = restart;
       }
       apply_B(h, h->r, h->z, prm->precision, prm->smoother, st);
       dot(h, h->r, h->z, M_RHO0, st);
       k_copy<double><<<eg, kBlock, 0, st>>>(n, h->z, h->p);
       bool met = false;
-      hipGraphExec_t ge = h->use_graphs ? iteration_graph(h, prm->precision, prm->smoother) : nullptr;
+      hipGraphExec_t ge = (h->use_graphs && !h->prof) ? iteration_graph(h, prm->precision, prm->smoother) : nullptr;
       bool first = true;
       while (it < prm->maxit) {
         if (first) {
@@ -563,7 +653,7 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
         break;
       }
       // binary32 cycle: confirm with the true residual in binary64
-      resid<double, 0>(h, L0, h->b, h->x, h->q, M_NONE, st);
+      resid<double, 0>(h, 0, L0, h->b, h->x, h->q, M_NONE, st);
       dot(h, h->q, h->q, M_STORE_RR, st);
       read_scalars(h, st);
       const double tr = std::sqrt(h->pinned[S_RR]) / r0;
@@ -577,12 +667,13 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
   }
   inf.rel_res = h_last;
   // true residual in binary64 and back to file order
-  resid<double, 0>(h, L0, h->b, h->x, h->q, M_NONE, st);
+  resid<double, 0>(h, 0, L0, h->b, h->x, h->q, M_NONE, st);
   dot(h, h->q, h->q, M_STORE_RR, st);
   k_scatter<<<eg, kBlock, 0, st>>>(n, h->perm0, h->x, x_file);
   LAUNCHCHECK("scatter");
   read_scalars(h, st);
   inf.rel_res_true = (r0 > 0.0) ? std::sqrt(h->pinned[S_RR]) / r0 : 0.0;
+  if (h->prof) harvest(h);
   if (info) *info = inf;
   return status;
 }
@@ -594,6 +685,37 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
 extern "C" {
 
 const char* mvamg_last_error(void) { return g_err.c_str(); }
+
+mvamg_status mvamg_profile(mvamg_hier* h, int enable) {
+  try {
+    if (!h) throw Error(MVAMG_ERR_ARG, "null handle");
+    HIPCHECK(hipDeviceSynchronize());
+    harvest(h);
+    h->prof = enable != 0;
+    for (int k = 0; k < MVAMG_KC_COUNT; ++k) {
+      h->kc_launches[k] = 0;
+      h->kc_ms[k] = 0.0;
+      h->kc_bytes[k] = 0.0;
+    }
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_kernel_stats(mvamg_hier* h, int kclass, int64_t* launches, double* ms, double* bytes) {
+  try {
+    if (!h || kclass < 0 || kclass >= MVAMG_KC_COUNT) throw Error(MVAMG_ERR_ARG, "bad handle or kernel class");
+    HIPCHECK(hipDeviceSynchronize());
+    harvest(h);
+    if (launches) *launches = h->kc_launches[kclass];
+    if (ms) *ms = h->kc_ms[kclass];
+    if (bytes) *bytes = h->kc_bytes[kclass];
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
 
 mvamg_status mvamg_hier_read(const char* path, mvamg_hier_host** out) {
   try {
@@ -664,6 +786,15 @@ mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** 
       L.nslabs = (int)y.slabs.size();
       L.rows0 = y.gstart[y.sgrp[1]];
       L.nent = (int64_t)y.val.size();
+      L.nnz = (int64_t)H.lv[l].ci.size();
+      L.stage_rows.assign(L.ns, 0);
+      L.stage_nnz.assign(L.ns, 0);
+      for (int c = 0; c < L.ns; ++c)
+        for (int p = y.gstart[y.sgrp[c]]; p < y.gstart[y.sgrp[c + 1]]; ++p) {
+          const int i = y.perm[p];
+          L.stage_rows[c] += 1;
+          L.stage_nnz[c] += H.lv[l].rp[i + 1] - H.lv[l].rp[i];
+        }
       L.ndblk = (int64_t)y.dblk.size();
       if (y.sell) L.slabs = h->upload_vec(y.slabs, st);
       if (!y.sell) {
@@ -703,6 +834,7 @@ mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** 
       build_transfer_layout(H.lv[l], Y[l], (l + 2 < H.nl) ? &Y[l + 1] : nullptr, T);
       DevTransfer& P = h->tr[l];
       P.nagg = T.nagg;
+      P.nu = (int64_t)T.U.size();
       P.aptr = h->upload_vec(T.aptr, st);
       P.arows = h->upload_vec(T.arows, st);
       P.uoff = h->upload_vec(T.uoff, st);
@@ -871,7 +1003,7 @@ mvamg_status mvamg_spmv(mvamg_hier* h, const double* x, double* y, void* stream)
     hipStream_t st = (hipStream_t)stream;
     const int eg = grid_for(h->n);
     k_gather<<<eg, kBlock, 0, st>>>(h->n, h->perm0, x, h->p);
-    resid<double, 1>(h, h->lv[0], nullptr, h->p, h->q, M_NONE, st);
+    resid<double, 1>(h, 0, h->lv[0], nullptr, h->p, h->q, M_NONE, st);
     k_scatter<<<eg, kBlock, 0, st>>>(h->n, h->perm0, h->q, y);
     LAUNCHCHECK("spmv");
     return MVAMG_OK;

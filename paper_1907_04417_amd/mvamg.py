@@ -24,7 +24,12 @@ SMOOTH_GS, SMOOTH_L1JACOBI = 0, 1
 
 EXPORTED = ["mvamg_hier_read", "mvamg_hier_host_free", "mvamg_hier_host_info", "mvamg_upload", "mvamg_free",
             "mvamg_levels", "mvamg_set_fine_values", "mvamg_spmv", "mvamg_cycle_apply", "mvamg_pcg_solve",
-            "mvamg_adjoint_solve", "mvamg_grad_coeffs", "mvamg_last_error"]
+            "mvamg_adjoint_solve", "mvamg_grad_coeffs", "mvamg_profile", "mvamg_kernel_stats",
+            "mvamg_last_error"]
+
+# kernel classes of mvamg_kernel_stats
+KC_SMOOTH_FINE, KC_SMOOTH_COARSE, KC_SPMV, KC_RESIDUAL, KC_RESTRICT, KC_PROLONG, KC_COARSE = range(7)
+KC_NAMES = ["smooth_fine", "smooth_coarse", "spmv", "residual", "restrict", "prolong", "coarse_solve"]
 
 
 class MvamgError(RuntimeError):
@@ -69,6 +74,9 @@ def load(path: str = LIB_PATH):
         L.mvamg_pcg_solve.argtypes = [vp, vp, vp, P(SolveParams), P(Info), vp]
         L.mvamg_adjoint_solve.argtypes = [vp, vp, vp, P(SolveParams), P(Info), vp]
         L.mvamg_grad_coeffs.argtypes = [vp, vp, vp, vp, vp]
+        L.mvamg_profile.argtypes = [vp, ctypes.c_int]
+        L.mvamg_kernel_stats.argtypes = [vp, ctypes.c_int, P(ctypes.c_int64), P(ctypes.c_double),
+                                         P(ctypes.c_double)]
         L.mvamg_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name not in ("mvamg_hier_host_free", "mvamg_free", "mvamg_last_error"):
@@ -178,6 +186,18 @@ def adjoint_solve(h: int, dLdx, lam, rtol=1e-8, maxit=1000, precision=64, smooth
 
 def grad_coeffs(h: int, lam, x, dval, stream=None) -> None:
     _check(load().mvamg_grad_coeffs(h, _dev(lam), _dev(x), _dev(dval), _stream(stream)))
+
+
+def profile(h: int, enable: bool) -> None:
+    """Turn per-launch kernel timing on or off (resets the totals)."""
+    _check(load().mvamg_profile(h, 1 if enable else 0))
+
+
+def kernel_stats(h: int, kclass: int):
+    """(launches, milliseconds, algorithmic bytes) of one kernel class."""
+    n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    _check(load().mvamg_kernel_stats(h, kclass, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+    return n.value, ms.value, by.value
 
 
 # ------------------------------------------------------------ convenience class
