@@ -198,3 +198,100 @@ def random_vectors(n: int, k: int, seed: int) -> np.ndarray:
     numbers."""
     rng = np.random.default_rng(seed)
     return rng.uniform(-1.0, 1.0, size=(k, n))
+
+
+# ----------------------------------------------------------------------------
+# Cell-centred finite volumes with conductivity exp(g), g a Gaussian random field
+
+def grf(m: int, length: float = 0.05, sigma: float = 1.0, seed: int = 0) -> np.ndarray:
+    """Gaussian random field on an m x m cell grid of the unit square with
+    squared-exponential covariance sigma^2 exp(-r^2 / (2 length^2)).
+
+    Sampled by spectral filtering of white noise (one standard-normal draw per
+    node of a 2m x 2m periodic grid, row-major) with the square root of the
+    covariance's spectral density exp(-2 pi^2 length^2 |k|^2), cropped to
+    m x m and rescaled to zero mean and unit pointwise variance times sigma."""
+    rng = np.random.default_rng(seed)
+    M = 2 * m
+    h = 1.0 / m
+    noise = rng.standard_normal((M, M))
+    k = np.fft.fftfreq(M, d=h)
+    k2 = k[:, None] ** 2 + k[None, :] ** 2
+    filt = np.exp(-np.pi ** 2 * length ** 2 * k2)  # sqrt of exp(-2 pi^2 l^2 |k|^2)
+    f = np.real(np.fft.ifft2(np.fft.fft2(noise) * filt))[:m, :m]
+    f = (f - f.mean()) / f.std()
+    return sigma * f
+
+
+class FV5:
+    """Pattern of the 5-point cell-centred finite-volume matrix on m x m cells
+    (x fastest) and the map from conductivities to its CSR values.
+
+    Face transmissibility between cells a and b: 2 k_a k_b / (k_a + k_b);
+    Dirichlet boundary face of cell c: 2 k_c; A_cc = sum of the cell's face
+    transmissibilities, A_ab = -T_ab.  Right-hand side h^2 * 1."""
+
+    def __init__(self, m: int):
+        self.m = m
+        n = m * m
+        self.n = n
+        idx = np.arange(n).reshape(m, m)
+        fa = np.concatenate([idx[:, :-1].ravel(), idx[:-1, :].ravel()])
+        fb = np.concatenate([idx[:, 1:].ravel(), idx[1:, :].ravel()])
+        self.fa, self.fb = fa, fb
+        # boundary faces: one per cell side on the domain boundary
+        bc = np.concatenate([idx[:, 0], idx[:, -1], idx[0, :], idx[-1, :]])
+        self.bc = bc
+        rows = np.concatenate([np.arange(n), fa, fb])
+        cols = np.concatenate([np.arange(n), fb, fa])
+        A = sp.coo_matrix((np.arange(rows.shape[0], dtype=np.float64) + 1, (rows, cols)), shape=(n, n)).tocsr()
+        A.sort_indices()
+        self.rowptr = A.indptr.astype(np.int32)
+        self.col = A.indices.astype(np.int32)
+        order = (A.data - 1).astype(np.int64)  # position k of the CSR array came from triple order[k]
+        inv = np.empty_like(order)
+        inv[order] = np.arange(order.shape[0])
+        self.pos_diag = inv[:n]
+        nf = fa.shape[0]
+        self.pos_ab = inv[n:n + nf]
+        self.pos_ba = inv[n + nf:]
+        self.b = np.full(n, 1.0 / (m * m))
+
+    def values(self, kappa: np.ndarray) -> np.ndarray:
+        k = kappa.ravel()
+        T = 2.0 * k[self.fa] * k[self.fb] / (k[self.fa] + k[self.fb])
+        v = np.zeros(self.col.shape[0])
+        d = np.zeros(self.n)
+        np.add.at(d, self.fa, T)
+        np.add.at(d, self.fb, T)
+        np.add.at(d, self.bc, 2.0 * k[self.bc])
+        v[self.pos_diag] = d
+        v[self.pos_ab] = -T
+        v[self.pos_ba] = -T
+        return v
+
+    def values_torch(self, g):
+        """CSR values as a differentiable function of g (torch), kappa = exp(g)."""
+        import torch
+        k = torch.exp(g.reshape(-1))
+        dev = k.device
+        fa = torch.as_tensor(self.fa, device=dev)
+        fb = torch.as_tensor(self.fb, device=dev)
+        bc = torch.as_tensor(self.bc, device=dev)
+        T = 2.0 * k[fa] * k[fb] / (k[fa] + k[fb])
+        d = torch.zeros(self.n, dtype=k.dtype, device=dev)
+        d = d.index_add(0, fa, T).index_add(0, fb, T).index_add(0, bc, 2.0 * k[bc])
+        v = torch.zeros(self.col.shape[0], dtype=k.dtype, device=dev)
+        v = v.index_copy(0, torch.as_tensor(self.pos_diag, device=dev), d)
+        v = v.index_copy(0, torch.as_tensor(self.pos_ab, device=dev), -T)
+        v = v.index_copy(0, torch.as_tensor(self.pos_ba, device=dev), -T)
+        return v
+
+
+def grf_fv5(m: int = 1024, seed: int = 0) -> Problem:
+    """The differentiable-solve workload: kappa = exp(g), g a GRF (seed), the
+    5-point FV matrix and b = h^2 * 1."""
+    g = grf(m, seed=seed)
+    fv = FV5(m)
+    v = fv.values(np.exp(g))
+    return Problem(f"grf_fv5_m{m}", fv.rowptr, fv.col, v, fv.b.copy(), None, dict(m=m, seed=seed, g=g, fv=fv))

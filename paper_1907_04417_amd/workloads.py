@@ -7,6 +7,8 @@ hierarchy file cached on disk (setup is the untimed input generator).
               or 1e-3 on 8^3 cubes selected with p = 0.5, else 1), at most 4
               smooth vectors
     jump32    the same family on 32^3 (test size)
+    grf1024   cell-centred 5-point finite volumes on 1024^2 cells, conductivity
+              exp(g), g a Gaussian random field (length 0.05, sigma 1), b = h^2 * 1
 """
 from __future__ import annotations
 
@@ -25,6 +27,8 @@ CONFIGS = {
     "jump32": dict(gen=lambda: problems.jump7(32, 4, 0.5, seed=1), nvec=4, setup={}),
     "jump16": dict(gen=lambda: problems.jump7(16, 2, 0.5, seed=2), nvec=4,
                    setup=dict(boot_coarse_min=8, coarse_cap=64, compose=2)),
+    "grf1024": dict(gen=lambda: problems.grf_fv5(1024, seed=0), nvec=3, setup={}),
+    "grf32": dict(gen=lambda: problems.grf_fv5(32, seed=3), nvec=3, setup=dict(boot_coarse_min=8, coarse_cap=64)),
 }
 
 BOOTSTRAP_SEED = 1000
