@@ -140,6 +140,61 @@ mvamg_status mvamg_adjoint_solve(mvamg_hier* h, const double* dLdx_dev, double* 
 mvamg_status mvamg_grad_coeffs(mvamg_hier* h, const double* lambda_dev, const double* x_dev,
                                double* dval_dev, void* stream);
 
+/* ------------------------------------------- several right-hand sides */
+
+/* Up to MVAMG_BLOCK_MAX right-hand sides through one hierarchy (the same
+   method applied to each column; the paper motivates amortising one
+   hierarchy over many solves, Sections 1 and 6).  Blocks are device arrays
+   of n x m binary64 values, row-major (row i holds the m values of row i of
+   every column, file order of the rows).  The library stages them in n x 32
+   blocks so that one load of a matrix entry serves every column; columns
+   m..31 are carried as zero.  The first block call on a handle allocates
+   about (7 x 8 + 3 x 4) x 32 bytes per fine row of work space, kept until
+   mvamg_free.  Not available on batch handles. */
+#define MVAMG_BLOCK_MAX 32
+
+/* Y = A X for m columns (1 <= m <= 32). */
+mvamg_status mvamg_spmv_block(mvamg_hier* h, const double* X_dev, double* Y_dev, int m, void* stream);
+
+/* Z = B R: one V-cycle per column (as mvamg_cycle_apply). */
+mvamg_status mvamg_cycle_apply_block(mvamg_hier* h, const double* R_dev, double* Z_dev, int m, int precision,
+                                     int smoother, void* stream);
+
+/* Preconditioned CG on the m systems A X[:, c] = B[:, c] at once.  Every
+   column has its own alpha, beta, stopping test, iteration count and (binary32
+   cycle) restarts; a column that met rtol keeps its iterate while the others
+   go on.  info: m entries (may be NULL).  prm->history, if not NULL, holds
+   m x (maxit + 1) values, column c's history at c * (maxit + 1).  Returns
+   MVAMG_OK if every column converged, MVAMG_NOT_CONVERGED otherwise; a
+   breakdown or non-finite value in any column is an error for the call. */
+mvamg_status mvamg_pcg_solve_block(mvamg_hier* h, const double* B_dev, double* X_dev, int m,
+                                   const mvamg_solve_params* prm, mvamg_info* info, void* stream);
+
+/* ------------------------------------------------ batch of problems */
+
+/* Uploads nprob independent hierarchies (each parsed by mvamg_hier_read, all
+   with the same number of levels) as one block-diagonal hierarchy: level l
+   holds level l of every problem, smoother stage c holds stage c of every
+   problem, and every problem keeps its own coarsest inverse.  Each launch of
+   a level kernel then covers the same step of all problems.  Vectors of a
+   batch are the problems' vectors one after another (problem p at rows
+   offsets[p] .. offsets[p+1]-1 of mvamg_batch_problems).  The handle is
+   released with mvamg_free; mvamg_spmv, mvamg_cycle_apply (block diagonal)
+   and mvamg_set_fine_values accept it, mvamg_pcg_solve does not.
+   Errors: MVAMG_ERR_ARG (level counts differ, too large), as mvamg_upload. */
+mvamg_status mvamg_batch_upload(const mvamg_hier_host* const* hs, int nprob, void* stream, mvamg_hier** out);
+
+/* Problem count (0 for a single-problem handle) and row offsets
+   (nprob + 1 entries, may be NULL). */
+mvamg_status mvamg_batch_problems(const mvamg_hier* h, int* nprob, int* offsets);
+
+/* Preconditioned CG on every problem of a batch, each with its own
+   recurrence, stopping test and restarts (as mvamg_pcg_solve_block with
+   problems in place of columns; info and history have nprob entries /
+   rows). */
+mvamg_status mvamg_batch_pcg_solve(mvamg_hier* h, const double* b_dev, double* x_dev,
+                                   const mvamg_solve_params* prm, mvamg_info* info, void* stream);
+
 /* ---------------------------------------------------------- measurement */
 
 /* Kernel classes for mvamg_kernel_stats. */

@@ -151,6 +151,83 @@ inline HostHier read_hierarchy_file(const char* path) {
   return H;
 }
 
+// Block-diagonal union of independent hierarchies with the same number of
+// levels: level l of the union holds level l of every problem (rows of
+// problem p after those of problems 0..p-1), stage c of its smoother order is
+// stage c of every problem (groups and their order kept), and its aggregates
+// are those of every problem.  A V-cycle of the union is the V-cycle of each
+// problem, side by side.  The coarsest level's diagonal blocks are the
+// problems' coarsest matrices.
+inline HostHier union_hierarchy(const std::vector<const HostHier*>& Hs) {
+  const int np = (int)Hs.size();
+  if (np < 1) throw Error(-1, "empty batch");
+  const int nl = Hs[0]->nl;
+  for (const HostHier* H : Hs)
+    if (H->nl != nl) throw Error(-1, "the problems of a batch must have the same number of levels");
+  HostHier U;
+  U.nl = nl;
+  for (const HostHier* H : Hs) U.nvec = std::max(U.nvec, H->nvec);
+  U.lv.resize(nl);
+  std::vector<std::vector<int64_t>> off(nl, std::vector<int64_t>(np + 1, 0));
+  for (int l = 0; l < nl; ++l)
+    for (int p = 0; p < np; ++p) off[l][p + 1] = off[l][p] + Hs[p]->lv[l].n;
+  for (int l = 0; l < nl; ++l) {
+    if (off[l][np] >= ((int64_t)1 << 31)) throw Error(-1, "batch too large for 32-bit row indices");
+    HostLevel& L = U.lv[l];
+    L.n = (int)off[l][np];
+    L.rp.assign(1, 0);
+    for (int p = 0; p < np; ++p) {
+      const HostLevel& S = Hs[p]->lv[l];
+      const int o = (int)off[l][p];
+      if ((int64_t)L.ci.size() + (int64_t)S.ci.size() >= ((int64_t)1 << 31))
+        throw Error(-1, "batch too large for 32-bit entry offsets");
+      for (int i = 0; i < S.n; ++i) {
+        for (int e = S.rp[i]; e < S.rp[i + 1]; ++e) {
+          L.ci.push_back(S.ci[e] + o);
+          L.v.push_back(S.v[e]);
+        }
+        L.rp.push_back((int)L.ci.size());
+      }
+    }
+    if (l + 1 == nl) break;
+    int ns = 0;
+    for (int p = 0; p < np; ++p) ns = std::max(ns, (int)Hs[p]->lv[l].sptr.size() - 1);
+    L.gptr.assign(1, 0);
+    L.sptr.assign(1, 0);
+    for (int c = 0; c < ns; ++c) {
+      for (int p = 0; p < np; ++p) {
+        const HostLevel& S = Hs[p]->lv[l];
+        if (c + 1 >= (int)S.sptr.size()) continue;
+        const int o = (int)off[l][p];
+        for (int g = S.sptr[c]; g < S.sptr[c + 1]; ++g) {
+          for (int q = S.gptr[g]; q < S.gptr[g + 1]; ++q) L.order.push_back(S.order[q] + o);
+          L.gptr.push_back((int)L.order.size());
+        }
+      }
+      L.sptr.push_back((int)L.gptr.size() - 1);
+    }
+    L.aptr.assign(1, 0);
+    L.coff.assign(1, 0);
+    L.uoff.assign(1, 0);
+    int64_t ubase = 0;
+    for (int p = 0; p < np; ++p) {
+      const HostLevel& S = Hs[p]->lv[l];
+      const int o = (int)off[l][p], oc = (int)off[l + 1][p];
+      const int na = (int)S.aptr.size() - 1;
+      for (int a = 0; a < na; ++a) {
+        for (int m = S.aptr[a]; m < S.aptr[a + 1]; ++m) L.arows.push_back(S.arows[m] + o);
+        L.aptr.push_back((int)L.arows.size());
+        L.coff.push_back(oc + S.coff[a + 1]);
+        if (ubase + S.uoff[a + 1] >= ((int64_t)1 << 31)) throw Error(-1, "batch too large for 32-bit block offsets");
+        L.uoff.push_back((int)(ubase + S.uoff[a + 1]));
+      }
+      L.U.insert(L.U.end(), S.U.begin(), S.U.end());
+      ubase += (int64_t)S.U.size();
+    }
+  }
+  return U;
+}
+
 // ----------------------------------------------------------- device layout
 
 constexpr int kKmax = 8;  // largest group / aggregate block handled by the kernels

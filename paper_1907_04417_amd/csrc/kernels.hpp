@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void k_zero_stage0_point(int n, int rows0, 
     x[p] = (p < rows0) ? r[p] / diag[p] : T(0);
 }
 
-// s = r - A x (MODE 0), or y = A x with sum x.y (MODE 1, binary64 only)
+// s = r - A x (MODE 0), y = A x with sum x.y (MODE 1, binary64 only), or y = A x (MODE 2)
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ slabs, int nslabs,
                                                        const int* __restrict__ col, const T* __restrict__ val,
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
         s[p] = r[p] - acc;
       } else {
         s[p] = acc;
-        dsum = (double)xp * (double)acc;
+        if (MODE == 1) dsum = (double)xp * (double)acc;
       }
     }
   }
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_zero_stage0_grp(int ng, int ng0, con
   }
 }
 
-// s = r - A x (MODE 0) or y = A x with sum x.y (MODE 1, binary64) on all groups.
+// s = r - A x (MODE 0), y = A x with sum x.y (MODE 1, binary64) or y = A x (MODE 2) on all groups.
 template <typename T, int KMAX, int MODE>
 __global__ __launch_bounds__(kBlock) void k_resid_grp(int ng, const int* __restrict__ gstart,
                                                       const int* __restrict__ grb, const int* __restrict__ col,
@@ -421,7 +421,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_grp(int ng, const int* __restr
         s[p0 + l] = r[p0 + l] - t;
       } else {
         s[p0 + l] = t;
-        dsum = (double)xl * (double)t;
+        if (MODE == 1) dsum = (double)xl * (double)t;
       }
     }
   }

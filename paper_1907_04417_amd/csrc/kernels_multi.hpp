@@ -1,0 +1,671 @@
+// Device kernels for many systems at once: several right-hand sides through
+// one hierarchy, and several independent problems solved together.
+//
+// Block vectors (several right-hand sides): n x 32 row-major, row i holding
+// the 32 values x[i * 32 + c], so one matrix entry, loaded once, multiplies a
+// contiguous 256-byte row (binary64) of the block.  A half wavefront (32
+// lanes) owns one matrix row, lane c its column c.
+//
+// Every system s (a column, or a problem) runs its own conjugate-gradient
+// recurrence: its scalars sit at scal[s * S_NSCAL + k] and a per-system flag
+// S_ACT stops its updates once its residual met the tolerance.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace mvamg {
+
+constexpr int kNB = 32;  // columns of a block vector
+
+// per-system scalars beyond those of a single system
+enum MScalar { S_ACT = 8, S_RTOL = 9, S_R0N = 10, S_TRR = 11 };
+
+enum MMode {
+  MM_STORE_R0 = 0,  // ||r_0||^2 and its root
+  MM_STORE_RR = 1,  // r.r after an update; clears S_ACT once ||r|| / ||r_0|| <= rtol
+  MM_STORE_TRR = 2, // ||b - A x||^2 recomputed
+  MM_PQ = 3,        // p.A p and alpha (zero for stopped systems)
+  MM_RHO0 = 4,      // r.z at a (re)start
+  MM_RZ = 5,        // r.z and beta (zero for stopped systems)
+  MM_RZ_FLEX = 6    // r.z, z.q and the flexible beta
+};
+
+__device__ __forceinline__ void mepilogue(int mode, double v0, double v1, double* sc) {
+  const bool act = sc[S_ACT] != 0.0;
+  switch (mode) {
+    case MM_STORE_R0:
+      sc[S_R0] = v0;
+      sc[S_R0N] = sqrt(v0);
+      break;
+    case MM_STORE_RR:
+      sc[S_RR] = v0;
+      if (act && sqrt(v0) / sc[S_R0N] <= sc[S_RTOL]) sc[S_ACT] = 0.0;
+      break;
+    case MM_STORE_TRR: sc[S_TRR] = v0; break;
+    case MM_PQ:
+      if (act) {
+        sc[S_PQ] = v0;
+        if (!(v0 > 0.0)) sc[S_FLAG] = 1.0;
+        sc[S_ALPHA] = sc[S_RHO] / v0;
+      } else {
+        sc[S_ALPHA] = 0.0;
+      }
+      break;
+    case MM_RHO0: sc[S_RHO] = v0; break;
+    case MM_RZ:
+      sc[S_BETA] = act ? v0 / sc[S_RHO] : 0.0;
+      sc[S_RHO] = v0;
+      break;
+    case MM_RZ_FLEX:
+      if (act) {
+        sc[S_ZQ] = v1;
+        sc[S_BETA] = -sc[S_ALPHA] * v1 / sc[S_RHO];
+      } else {
+        sc[S_BETA] = 0.0;
+      }
+      sc[S_RHO] = v0;
+      break;
+  }
+}
+
+// all scalars zero, S_RTOL = rtol
+__global__ __launch_bounds__(kBlock) void k_minit(int nsys, double* scal, double rtol) {
+  for (int i = threadIdx.x; i < nsys * S_NSCAL; i += kBlock) scal[i] = ((i % S_NSCAL) == S_RTOL) ? rtol : 0.0;
+}
+
+// S_ACT of every system from act[s] (0 or 1); S_FLAG cleared
+__global__ __launch_bounds__(kBlock) void k_mset_active(int nsys, const double* __restrict__ act, double* scal) {
+  for (int s = threadIdx.x; s < nsys; s += kBlock) {
+    scal[s * S_NSCAL + S_ACT] = act[s];
+    scal[s * S_NSCAL + S_FLAG] = 0.0;
+  }
+}
+
+// Block s adds the partials part[(v * nsys + s) * nparts + b] in order b =
+// 0, 1, ... and applies the epilogue of system s.
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_mfinish(int nsys, int nparts, const double* __restrict__ part,
+                                                    double* scal, int mode) {
+  __shared__ double lds[4];
+  const int s = blockIdx.x;
+  const double* p0 = part + (size_t)s * nparts;
+  const double* p1 = part + (size_t)(nsys + s) * nparts;
+  double s0 = 0.0, s1 = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) {
+    s0 += p0[i];
+    if (NV > 1) s1 += p1[i];
+  }
+  s0 = block_sum(s0, lds);
+  if (NV > 1) s1 = block_sum(s1, lds);
+  if (threadIdx.x == 0) mepilogue(mode, s0, s1, scal + (size_t)s * S_NSCAL);
+}
+
+// ------------------------------------------------- block-vector kernels
+
+// Per-column sums over a 256-thread block whose lane c (threadIdx & 31) holds
+// column c: part[(v * 32 + c) * gridDim.x + blockIdx.x].  Every thread of the
+// block must call it.
+__device__ __forceinline__ void bcol_partials(double a, int v, double* part) {
+  __shared__ double lds[4][kNB];
+  a += __shfl_xor(a, 32, 64);
+  const int w = threadIdx.x >> 6, c = threadIdx.x & 31;
+  if ((threadIdx.x & 63) < 32) lds[w][c] = a;
+  __syncthreads();
+  if (threadIdx.x < 32)
+    part[(size_t)(v * kNB + c) * gridDim.x + blockIdx.x] = ((lds[0][c] + lds[1][c]) + lds[2][c]) + lds[3][c];
+  __syncthreads();
+}
+
+// rows handled per 256-thread block and step of a row-per-half-wave loop
+constexpr int kRowsPerBlock = kBlock / kNB;
+
+// out[p][c] = in[perm[p]][c] for c < m (in: n x m row-major), 0 for c >= m
+__global__ __launch_bounds__(kBlock) void k_bgather(int n, const int* __restrict__ perm, int m,
+                                                    const double* __restrict__ in, double* __restrict__ out) {
+  const int c = threadIdx.x & 31;
+  for (int p = (blockIdx.x * kBlock + threadIdx.x) >> 5; p < n; p += gridDim.x * kRowsPerBlock)
+    out[(size_t)p * kNB + c] = (c < m) ? in[(size_t)perm[p] * m + c] : 0.0;
+}
+
+// out[perm[p]][c] = in[p][c] for c < m
+__global__ __launch_bounds__(kBlock) void k_bscatter(int n, const int* __restrict__ perm, int m,
+                                                     const double* __restrict__ in, double* __restrict__ out) {
+  const int c = threadIdx.x & 31;
+  for (int p = (blockIdx.x * kBlock + threadIdx.x) >> 5; p < n; p += gridDim.x * kRowsPerBlock)
+    if (c < m) out[(size_t)perm[p] * m + c] = in[(size_t)p * kNB + c];
+}
+
+// per-column a.b (and c.d)
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_bdot(int n, const double* __restrict__ a, const double* __restrict__ b,
+                                                 const double* __restrict__ c2, const double* __restrict__ d,
+                                                 double* __restrict__ part) {
+  const int c = threadIdx.x & 31;
+  double s0 = 0.0, s1 = 0.0;
+  for (int p = (blockIdx.x * kBlock + threadIdx.x) >> 5; p < n; p += gridDim.x * kRowsPerBlock) {
+    const size_t i = (size_t)p * kNB + c;
+    s0 += a[i] * b[i];
+    if (NV > 1) s1 += c2[i] * d[i];
+  }
+  bcol_partials(s0, 0, part);
+  if (NV > 1) bcol_partials(s1, 1, part);
+}
+
+// columns still running: x += alpha_c p, r -= alpha_c q; per-column r.r
+__global__ __launch_bounds__(kBlock) void k_baxpy2_dot(int n, const double* __restrict__ scal,
+                                                       const double* __restrict__ p, const double* __restrict__ q,
+                                                       double* __restrict__ x, double* __restrict__ r,
+                                                       double* __restrict__ part) {
+  const int c = threadIdx.x & 31;
+  const double alpha = scal[c * S_NSCAL + S_ALPHA];
+  const bool act = scal[c * S_NSCAL + S_ACT] != 0.0;
+  double s = 0.0;
+  for (int row = (blockIdx.x * kBlock + threadIdx.x) >> 5; row < n; row += gridDim.x * kRowsPerBlock) {
+    const size_t i = (size_t)row * kNB + c;
+    double ri = r[i];
+    if (act) {
+      x[i] += alpha * p[i];
+      ri -= alpha * q[i];
+      r[i] = ri;
+    }
+    s += ri * ri;
+  }
+  bcol_partials(s, 0, part);
+}
+
+// p = z + beta_c p
+__global__ __launch_bounds__(kBlock) void k_bxpay(int n, const double* __restrict__ scal,
+                                                  const double* __restrict__ z, double* __restrict__ p) {
+  const int c = threadIdx.x & 31;
+  const double beta = scal[c * S_NSCAL + S_BETA];
+  for (int row = (blockIdx.x * kBlock + threadIdx.x) >> 5; row < n; row += gridDim.x * kRowsPerBlock) {
+    const size_t i = (size_t)row * kNB + c;
+    p[i] = z[i] + beta * p[i];
+  }
+}
+
+// Gauss-Seidel stage on the slabs [s0, s1) of a sliced-ELL level: half wave
+// per row, (blockIdx, threadIdx) -> row (s0 + hw / 64, hw % 64).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bgs_sell(const Slab* __restrict__ slabs, int s0, int s1,
+                                                     const int* __restrict__ col, const T* __restrict__ val,
+                                                     const T* __restrict__ diag, const T* __restrict__ r, T* x) {
+  const int hw = (blockIdx.x * kBlock + threadIdx.x) >> 5;
+  const int s = s0 + (hw >> 6), i = hw & 63;
+  if (s >= s1) return;
+  const Slab sl = slabs[s];
+  if (i >= sl.nrows) return;
+  const int c = threadIdx.x & 31;
+  const int p = sl.row0 + i;
+  const int* cp = col + sl.off + i;
+  const T* vp = val + sl.off + i;
+  T acc = r[(size_t)p * kNB + c];
+  for (int j0 = 0; j0 < sl.width; j0 += 8) {
+    int cc[8];
+    T vv[8], xx[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = min(j0 + u, sl.width - 1);
+      cc[u] = cp[64 * j];
+      vv[u] = vp[64 * j];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xx[u] = x[(size_t)cc[u] * kNB + c];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (j0 + u < sl.width) acc -= vv[u] * xx[u];
+  }
+  x[(size_t)p * kNB + c] = acc / diag[p];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bzero_stage0_point(int n, int rows0, const T* __restrict__ diag,
+                                                               const T* __restrict__ r, T* __restrict__ x) {
+  const int c = threadIdx.x & 31;
+  for (int p = (blockIdx.x * kBlock + threadIdx.x) >> 5; p < n; p += gridDim.x * kRowsPerBlock) {
+    const size_t i = (size_t)p * kNB + c;
+    x[i] = (p < rows0) ? r[i] / diag[p] : T(0);
+  }
+}
+
+// MODE 0: s = r - A x;  MODE 1: s = A x with per-column x.s partials;
+// MODE 2: s = A x.  Grid-stride over the rows of all slabs.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_bresid_sell(const Slab* __restrict__ slabs, int nslabs,
+                                                        const int* __restrict__ col, const T* __restrict__ val,
+                                                        const T* __restrict__ diag, const T* __restrict__ r,
+                                                        const T* __restrict__ x, T* __restrict__ s,
+                                                        double* __restrict__ part) {
+  const int c = threadIdx.x & 31;
+  double dsum = 0.0;
+  const int nhw = nslabs * 64;
+  for (int hw = (blockIdx.x * kBlock + threadIdx.x) >> 5; hw < nhw; hw += gridDim.x * kRowsPerBlock) {
+    const Slab sl = slabs[hw >> 6];
+    const int i = hw & 63;
+    if (i >= sl.nrows) continue;
+    const int p = sl.row0 + i;
+    const int* cp = col + sl.off + i;
+    const T* vp = val + sl.off + i;
+    const T xp = x[(size_t)p * kNB + c];
+    T acc = diag[p] * xp;
+    for (int j0 = 0; j0 < sl.width; j0 += 8) {
+      int cc[8];
+      T vv[8], xx[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = min(j0 + u, sl.width - 1);
+        cc[u] = cp[64 * j];
+        vv[u] = vp[64 * j];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xx[u] = x[(size_t)cc[u] * kNB + c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (j0 + u < sl.width) acc += vv[u] * xx[u];
+    }
+    if (MODE == 0) {
+      s[(size_t)p * kNB + c] = r[(size_t)p * kNB + c] - acc;
+    } else {
+      s[(size_t)p * kNB + c] = acc;
+      if (MODE == 1) dsum += (double)xp * (double)acc;
+    }
+  }
+  if (MODE == 1) bcol_partials(dsum, 0, part);
+}
+
+// Off-group row sums of group g for column c: half wave h adds rows
+// h, h + 2, ...; afterwards every lane holds a[q] for all rows q < k.
+template <typename T, int KMAX>
+__device__ __forceinline__ void bgroup_rowsums(int g, int h, int c, int k, const int* __restrict__ grb,
+                                               const int* __restrict__ col, const T* __restrict__ val, const T* x,
+                                               T (&a)[KMAX]) {
+  constexpr int NT = (KMAX + 1) / 2;
+  const int* gb = grb + (size_t)g * (kKmax + 1);
+  T mine[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int l = 2 * t + h;
+    T acc = T(0);
+    if (l < k) {
+      const int e1 = gb[l + 1];
+      for (int e0 = gb[l]; e0 < e1; e0 += 4) {
+        int cc[4];
+        T vv[4], xx[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = min(e0 + u, e1 - 1);
+          cc[u] = col[e];
+          vv[u] = val[e];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xx[u] = x[(size_t)cc[u] * kNB + c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (e0 + u < e1) acc += vv[u] * xx[u];
+      }
+    }
+    mine[t] = acc;
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const T other = __shfl_xor(mine[t], 32, 64);
+    a[2 * t] = h == 0 ? mine[t] : other;
+    if (2 * t + 1 < KMAX) a[2 * t + 1] = h == 0 ? other : mine[t];
+  }
+}
+
+// Gauss-Seidel stage on the groups [g0, g1): wave per group, every column
+// relaxes the group's rows one after the other (forward or backward).
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kBlock) void k_bgs_grp(int g0, int g1, const int* __restrict__ gstart,
+                                                    const int* __restrict__ grb, const int* __restrict__ col,
+                                                    const T* __restrict__ val, const int* __restrict__ dboff,
+                                                    const T* __restrict__ dblk, const T* __restrict__ r, T* x,
+                                                    int backward) {
+  const int g = __builtin_amdgcn_readfirstlane(g0 + (int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6));
+  if (g >= g1) return;
+  const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
+  const int p0 = gstart[g], k = gstart[g + 1] - p0;
+  const T* B = dblk + dboff[g];
+  T xv[KMAX], rv[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    const size_t i = (size_t)(p0 + min(q, k - 1)) * kNB + c;
+    const T xq = x[i], rq = r[i];
+    xv[q] = (q < k) ? xq : T(0);
+    rv[q] = (q < k) ? rq : T(0);
+  }
+  T a[KMAX];
+  bgroup_rowsums<T, KMAX>(g, h, c, k, grb, col, val, x, a);
+#pragma unroll
+  for (int t = 0; t < KMAX; ++t) {
+    const int ll = backward ? KMAX - 1 - t : t;
+    if (ll < k) {
+      T s = rv[ll] - a[ll];
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q)
+        if (q < k && q != ll) s -= B[ll * k + q] * xv[q];
+      xv[ll] = s / B[ll * k + ll];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q)
+    if (q < k && (q & 1) == h) x[(size_t)(p0 + q) * kNB + c] = xv[q];
+}
+
+// forward sweep from x = 0 on a grouped level (thread per group and column)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bzero_stage0_grp(int ng, int ng0, const int* __restrict__ gstart,
+                                                             const int* __restrict__ dboff,
+                                                             const T* __restrict__ dblk, const T* __restrict__ r,
+                                                             T* __restrict__ x) {
+  const int c = threadIdx.x & 31;
+  for (int g = (blockIdx.x * kBlock + threadIdx.x) >> 5; g < ng; g += gridDim.x * kRowsPerBlock) {
+    const int p0 = gstart[g], k = gstart[g + 1] - p0;
+    if (g >= ng0) {
+      for (int q = 0; q < k; ++q) x[(size_t)(p0 + q) * kNB + c] = T(0);
+      continue;
+    }
+    const T* B = dblk + dboff[g];
+    T xv[kKmax];
+#pragma unroll
+    for (int l = 0; l < kKmax; ++l) {
+      xv[l] = T(0);
+      if (l < k) {
+        T s = r[(size_t)(p0 + l) * kNB + c];
+#pragma unroll
+        for (int q = 0; q < kKmax; ++q)
+          if (q < l) s -= B[l * k + q] * xv[q];
+        xv[l] = s / B[l * k + l];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kKmax; ++q)
+      if (q < k) x[(size_t)(p0 + q) * kNB + c] = xv[q];
+  }
+}
+
+// s = r - A x (MODE 0), s = A x with per-column x.s partials (MODE 1) or
+// s = A x (MODE 2) on all groups; grid-stride, wave per group.
+template <typename T, int KMAX, int MODE>
+__global__ __launch_bounds__(kBlock) void k_bresid_grp(int ng, const int* __restrict__ gstart,
+                                                       const int* __restrict__ grb, const int* __restrict__ col,
+                                                       const T* __restrict__ val, const int* __restrict__ dboff,
+                                                       const T* __restrict__ dblk, const T* __restrict__ r,
+                                                       const T* __restrict__ x, T* __restrict__ s,
+                                                       double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
+  double dsum = 0.0;
+  const int gfirst = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6));
+  for (int g = gfirst; g < ng; g += gridDim.x * (kBlock / 64)) {
+    const int p0 = gstart[g], k = gstart[g + 1] - p0;
+    const T* B = dblk + dboff[g];
+    T xv[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+      const T xq = x[(size_t)(p0 + min(q, k - 1)) * kNB + c];
+      xv[q] = (q < k) ? xq : T(0);
+    }
+    T a[KMAX];
+    bgroup_rowsums<T, KMAX>(g, h, c, k, grb, col, val, x, a);
+#pragma unroll
+    for (int l = 0; l < KMAX; ++l) {
+      if (l < k && (l & 1) == h) {
+        T t = a[l];
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q)
+          if (q < k) t += B[l * k + q] * xv[q];
+        const size_t i = (size_t)(p0 + l) * kNB + c;
+        if (MODE == 0) {
+          s[i] = r[i] - t;
+        } else {
+          s[i] = t;
+          if (MODE == 1) dsum += (double)xv[l] * (double)t;
+        }
+      }
+    }
+  }
+  if (MODE == 1) bcol_partials(dsum, 0, part);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bl1_init(int n, const T* __restrict__ dl1, const T* __restrict__ r,
+                                                     T* __restrict__ x) {
+  const int c = threadIdx.x & 31;
+  for (int p = (blockIdx.x * kBlock + threadIdx.x) >> 5; p < n; p += gridDim.x * kRowsPerBlock)
+    x[(size_t)p * kNB + c] = r[(size_t)p * kNB + c] / dl1[p];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bl1_update(int n, const T* __restrict__ dl1, const T* __restrict__ s,
+                                                       T* __restrict__ x) {
+  const int c = threadIdx.x & 31;
+  for (int p = (blockIdx.x * kBlock + threadIdx.x) >> 5; p < n; p += gridDim.x * kRowsPerBlock)
+    x[(size_t)p * kNB + c] += s[(size_t)p * kNB + c] / dl1[p];
+}
+
+// r_c = P^T s for block vectors: wave per aggregate, half wave h takes members
+// h, h + 2, ... (four in flight), the halves are added with one exchange.
+// INIT as in k_restrict (1: first Gauss-Seidel stage of the next level from
+// x_c = 0, 2: first l1-Jacobi step).
+template <typename T, int INIT>
+__global__ __launch_bounds__(kBlock) void k_brestrict(int nagg, const int* __restrict__ aptr,
+                                                      const int* __restrict__ arows, const int* __restrict__ uoff,
+                                                      const int* __restrict__ cst, const int* __restrict__ kk,
+                                                      const T* __restrict__ U, const T* __restrict__ s,
+                                                      T* __restrict__ rc, const int* __restrict__ cgrp, int ng0,
+                                                      const int* __restrict__ cdboff, const T* __restrict__ cdblk,
+                                                      const T* __restrict__ cdl1, T* __restrict__ xc) {
+  const int a = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (a >= nagg) return;
+  const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
+  const int m0 = aptr[a], na = aptr[a + 1] - m0, k = kk[a];
+  const T* Ua = U + uoff[a];
+  T acc[kKmax];
+#pragma unroll
+  for (int q = 0; q < kKmax; ++q) acc[q] = T(0);
+  for (int l0 = h; l0 < na; l0 += 8) {
+    T sv[4];
+    int li[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) li[u] = min(l0 + 2 * u, na - 1);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sv[u] = s[(size_t)arows[m0 + li[u]] * kNB + c];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (l0 + 2 * u < na) {
+#pragma unroll
+        for (int q = 0; q < kKmax; ++q)
+          if (q < k) acc[q] += Ua[q * na + li[u]] * sv[u];
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < kKmax; ++q) acc[q] += __shfl_xor(acc[q], 32, 64);
+  const int c0 = cst[a];
+#pragma unroll
+  for (int q = 0; q < kKmax; ++q)
+    if (q < k && (q & 1) == h) rc[(size_t)(c0 + q) * kNB + c] = acc[q];
+  if (INIT == 1) {
+    const int g = cgrp[a];
+    T xv[kKmax];
+    if (g < ng0) {
+      const T* B = cdblk + cdboff[g];
+#pragma unroll
+      for (int l = 0; l < kKmax; ++l) {
+        xv[l] = T(0);
+        if (l < k) {
+          T t = acc[l];
+#pragma unroll
+          for (int q = 0; q < kKmax; ++q)
+            if (q < l) t -= B[l * k + q] * xv[q];
+          xv[l] = t / B[l * k + l];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int l = 0; l < kKmax; ++l) xv[l] = T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < kKmax; ++q)
+      if (q < k && (q & 1) == h) xc[(size_t)(c0 + q) * kNB + c] = xv[q];
+  } else if (INIT == 2) {
+#pragma unroll
+    for (int q = 0; q < kKmax; ++q)
+      if (q < k && (q & 1) == h) xc[(size_t)(c0 + q) * kNB + c] = acc[q] / cdl1[c0 + q];
+  }
+}
+
+// x += P x_c for block vectors, in fine-row order (half wave per row)
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kBlock) void k_bprolong_rows(int n, const int* __restrict__ cinfo,
+                                                          const T* __restrict__ Urow, const T* __restrict__ xc,
+                                                          T* __restrict__ x) {
+  const int c = threadIdx.x & 31;
+  for (int i = (blockIdx.x * kBlock + threadIdx.x) >> 5; i < n; i += gridDim.x * kRowsPerBlock) {
+    const int ci = cinfo[i];
+    const int c0 = ci >> 3, k = (ci & 7) + 1;
+    T t = T(0);
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q)
+      if (q < k) t += Urow[(size_t)q * n + i] * xc[(size_t)(c0 + q) * kNB + c];
+    x[(size_t)i * kNB + c] += t;
+  }
+}
+
+// Z = A R for the coarsest level: A dense row-major with leading dimension ld
+// (a multiple of 64, entries past n zero, rows up to ld readable), R and Z
+// n x 32.  A block computes 8 * RPH rows: half wave hw holds rows
+// blk * 8 * RPH + hw + 8 t (t < RPH) for column c; R is staged through LDS in
+// chunks of 64 rows and every A entry is read once per block.
+template <int RPH>
+__global__ __launch_bounds__(kBlock) void k_bgemm(int n, int ld, const double* __restrict__ A,
+                                                  const double* __restrict__ R, double* __restrict__ Z) {
+  __shared__ double Rs[64][kNB];
+  const int c = threadIdx.x & 31, hw = threadIdx.x >> 5;
+  const int row0 = blockIdx.x * 8 * RPH + hw;
+  double acc[RPH];
+  const double* Ar[RPH];
+#pragma unroll
+  for (int t = 0; t < RPH; ++t) {
+    acc[t] = 0.0;
+    Ar[t] = A + (size_t)min(row0 + 8 * t, ld - 1) * ld;
+  }
+  for (int k0 = 0; k0 < ld; k0 += 64) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + kBlock * u;
+      const int kr = e >> 5, cc = e & 31;
+      Rs[kr][cc] = (k0 + kr < n) ? R[(size_t)(k0 + kr) * kNB + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 64; kk += 4) {
+      const double r0 = Rs[kk][c], r1 = Rs[kk + 1][c], r2 = Rs[kk + 2][c], r3 = Rs[kk + 3][c];
+#pragma unroll
+      for (int t = 0; t < RPH; ++t) {
+        const double2 a01 = *reinterpret_cast<const double2*>(Ar[t] + k0 + kk);
+        const double2 a23 = *reinterpret_cast<const double2*>(Ar[t] + k0 + kk + 2);
+        acc[t] += a01.x * r0 + a01.y * r1 + a23.x * r2 + a23.y * r3;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < RPH; ++t) {
+    const int i = row0 + 8 * t;
+    if (i < n) Z[(size_t)i * kNB + c] = acc[t];
+  }
+}
+
+// -------------------------------------------- independent problems (batch)
+
+// y = blockdiag(A_p) x on the coarsest level of a batch: wave per row; the
+// rows [coff[p], coff[p+1]) belong to problem p, whose inverse is dense
+// row-major with leading dimension cnp[p] (even) at A + aoff[p].
+__global__ __launch_bounds__(kBlock) void k_gemv_batch(int n, const int* __restrict__ cprob,
+                                                       const int* __restrict__ coff, const int* __restrict__ cnp,
+                                                       const int64_t* __restrict__ aoff,
+                                                       const double* __restrict__ A, const double* __restrict__ x,
+                                                       double* __restrict__ y) {
+  const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const int lane = threadIdx.x & 63;
+  const int p = cprob[i], c0 = coff[p], m = coff[p + 1] - c0, ld = cnp[p];
+  const double2* Ai = reinterpret_cast<const double2*>(A + aoff[p] + (size_t)(i - c0) * ld);
+  const double* xp = x + c0;
+  double a0 = 0.0, a1 = 0.0;
+  const int m2 = m / 2;
+  int j = lane;
+  for (; j + 64 < m2; j += 128) {
+    const double2 v0 = Ai[j], v1 = Ai[j + 64];
+    a0 += v0.x * xp[2 * j] + v0.y * xp[2 * j + 1];
+    a1 += v1.x * xp[2 * j + 128] + v1.y * xp[2 * j + 129];
+  }
+  for (; j < m2; j += 64) {
+    const double2 v = Ai[j];
+    a0 += v.x * xp[2 * j] + v.y * xp[2 * j + 1];
+  }
+  if ((m & 1) && lane == 0) a1 += A[aoff[p] + (size_t)(i - c0) * ld + m - 1] * xp[m - 1];
+  const double acc = wave_sum(a0 + a1);
+  if (lane == 0) y[i] = acc;
+}
+
+// Problem p owns the entries idx[j], j in [poff[p], poff[p+1]), of the level-0
+// vectors.  Grid (chunks, problems); partials at part[(v * nprob + p) *
+// gridDim.x + chunk].
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_pdot(const int* __restrict__ poff, const int* __restrict__ idx,
+                                                 const double* __restrict__ a, const double* __restrict__ b,
+                                                 const double* __restrict__ c, const double* __restrict__ d,
+                                                 double* __restrict__ part) {
+  __shared__ double lds[4];
+  const int p = blockIdx.y, j1 = poff[p + 1];
+  double s0 = 0.0, s1 = 0.0;
+  for (int j = poff[p] + blockIdx.x * kBlock + threadIdx.x; j < j1; j += gridDim.x * kBlock) {
+    const int i = idx[j];
+    s0 += a[i] * b[i];
+    if (NV > 1) s1 += c[i] * d[i];
+  }
+  s0 = block_sum(s0, lds);
+  if (NV > 1) s1 = block_sum(s1, lds);
+  if (threadIdx.x == 0) {
+    part[(size_t)p * gridDim.x + blockIdx.x] = s0;
+    if (NV > 1) part[(size_t)(gridDim.y + p) * gridDim.x + blockIdx.x] = s1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_paxpy2_dot(const int* __restrict__ poff, const int* __restrict__ idx,
+                                                       const double* __restrict__ scal, const double* __restrict__ pv,
+                                                       const double* __restrict__ q, double* __restrict__ x,
+                                                       double* __restrict__ r, double* __restrict__ part) {
+  __shared__ double lds[4];
+  const int p = blockIdx.y, j1 = poff[p + 1];
+  const double alpha = scal[p * S_NSCAL + S_ALPHA];
+  const bool act = scal[p * S_NSCAL + S_ACT] != 0.0;
+  double s = 0.0;
+  for (int j = poff[p] + blockIdx.x * kBlock + threadIdx.x; j < j1; j += gridDim.x * kBlock) {
+    const int i = idx[j];
+    double ri = r[i];
+    if (act) {
+      x[i] += alpha * pv[i];
+      ri -= alpha * q[i];
+      r[i] = ri;
+    }
+    s += ri * ri;
+  }
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) part[(size_t)p * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pxpay(const int* __restrict__ poff, const int* __restrict__ idx,
+                                                  const double* __restrict__ scal, const double* __restrict__ z,
+                                                  double* __restrict__ pv) {
+  const int p = blockIdx.y, j1 = poff[p + 1];
+  const double beta = scal[p * S_NSCAL + S_BETA];
+  for (int j = poff[p] + blockIdx.x * kBlock + threadIdx.x; j < j1; j += gridDim.x * kBlock) {
+    const int i = idx[j];
+    pv[i] = z[i] + beta * pv[i];
+  }
+}
+
+}  // namespace mvamg

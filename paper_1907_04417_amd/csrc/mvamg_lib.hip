@@ -11,11 +11,13 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "hier_host.hpp"
 #include "dense.hpp"
 #include "kernels.hpp"
+#include "kernels_multi.hpp"
 #include "mvamg.h"
 
 using namespace mvamg;
@@ -82,6 +84,9 @@ struct DevLevel {
   // work vectors
   double *r = nullptr, *x = nullptr, *s = nullptr;
   float *r32 = nullptr, *x32 = nullptr, *s32 = nullptr;
+  // block work vectors (n x 32, allocated on the first block call)
+  double *br = nullptr, *bx = nullptr, *bs = nullptr;
+  float *br32 = nullptr, *bx32 = nullptr, *bs32 = nullptr;
 };
 
 struct DevTransfer {
@@ -98,9 +103,24 @@ struct DevTransfer {
 };
 
 struct DevCoarse {
-  int n = 0, np = 0;         // size, padded size (multiple of 64)
-  double* Ainv = nullptr;    // np x np row-major, inverse of the coarsest matrix
+  int n = 0, np = 0;         // size, padded size (multiple of 64) of a single block
+  int nb = 1;                // diagonal blocks (one per problem of a batch)
+  double* Ainv = nullptr;    // np x np row-major inverse; a batch: the blocks' inverses one after another
+  int *cprob = nullptr, *coff = nullptr, *cnp = nullptr;  // batch: row -> block, block rows, padded sizes
+  int64_t* aoff = nullptr;   // batch: offset of each block's inverse
+  double ainv_entries = 0.0; // sum of the blocks' n_b^2 (algorithmic bytes / 8)
   double *r = nullptr, *z = nullptr;
+  double *br = nullptr, *bz = nullptr;  // block vectors for the binary32 block cycle
+};
+
+// per-system scalars and partials of the multi-system solves
+struct MultiBufs {
+  int nsys = 0, nparts = 0;
+  double* scal = nullptr;    // nsys * S_NSCAL
+  double* part = nullptr;    // 2 * nsys * nparts
+  double* act = nullptr;     // nsys flags staged for k_mset_active
+  double* pinned = nullptr;  // host copy of scal
+  double* pact = nullptr;    // host staging of act
 };
 
 }  // namespace
@@ -122,6 +142,17 @@ struct mvamg_hier {
   double* scal = nullptr;
   double* part = nullptr;
   double* pinned = nullptr;
+  // batch of independent problems (nprob > 0): level-0 rows of problem p are
+  // the file rows [poff[p], poff[p+1]); iperm0 maps a file row to smoother order
+  int nprob = 0;
+  int pchunks = 1;
+  std::vector<int> h_poff;
+  int* poff = nullptr;
+  int* iperm0 = nullptr;
+  // several systems at once
+  MultiBufs mb;
+  bool blk_ready = false;
+  double *bb = nullptr, *bxv = nullptr, *bp = nullptr, *bq = nullptr;  // level-0 block CG vectors
   hipStream_t cap = nullptr;              // stream used only to capture graphs
   std::map<int, hipGraphExec_t> graphs;   // one CG iteration per (precision, smoother)
   bool use_graphs = true;
@@ -170,6 +201,8 @@ struct mvamg_hier {
     if (cap) (void)hipStreamDestroy(cap);
     for (void* p : allocs) (void)hipFree(p);
     if (pinned) (void)hipHostFree(pinned);
+    if (mb.pinned) (void)hipHostFree(mb.pinned);
+    if (mb.pact) (void)hipHostFree(mb.pact);
   }
 };
 
@@ -354,12 +387,12 @@ void zero_stage0(mvamg_hier* h, int l, const DevLevel& L, const T* r, T* x, hipS
 
 int resid_grid(const DevLevel& L);
 
-// MODE 0: s = r - A x;  MODE 1: s = A x and x.s reduced into scal by `mode`
+// MODE 0: s = r - A x;  MODE 1: s = A x and x.s reduced into scal by `mode`;  MODE 2: s = A x
 template <typename T, int MODE>
 void resid(mvamg_hier* h, int l, const DevLevel& L, const T* r, const T* x, T* s, int mode, hipStream_t st) {
   const Red red = mkred(h);
-  const int kc = MODE == 1 ? MVAMG_KC_SPMV : MVAMG_KC_RESIDUAL;
-  const double by = (double)L.nnz * (sizeof(T) + 4) + 4.0 * (L.n + 1) + (double)L.n * sizeof(T) * (MODE == 1 ? 2 : 3);
+  const int kc = MODE != 0 ? MVAMG_KC_SPMV : MVAMG_KC_RESIDUAL;
+  const double by = (double)L.nnz * (sizeof(T) + 4) + 4.0 * (L.n + 1) + (double)L.n * sizeof(T) * (MODE != 0 ? 2 : 3);
   (void)l;
   if (L.sell) {
     const int grid = (L.nslabs + 3) / 4;
@@ -389,8 +422,12 @@ template <>
 void coarse_solve<double>(mvamg_hier* h, const double* r, double* z, hipStream_t st) {
   // z = A_L^{-1} r with the inverse formed at upload from the Cholesky factor
   DevCoarse& C = h->co;
-  klaunch(h, MVAMG_KC_COARSE, 8.0 * C.n * C.n + 16.0 * C.n, k_gemv, (C.n + 3) / 4, kBlock, st, C.n, C.np,
-          C.Ainv, r, z, 0);
+  if (C.nb == 1)
+    klaunch(h, MVAMG_KC_COARSE, 8.0 * C.n * C.n + 16.0 * C.n, k_gemv, (C.n + 3) / 4, kBlock, st, C.n, C.np,
+            C.Ainv, r, z, 0);
+  else
+    klaunch(h, MVAMG_KC_COARSE, 8.0 * C.ainv_entries + 16.0 * C.n, k_gemv_batch, (C.n + 3) / 4, kBlock, st, C.n,
+            C.cprob, C.coff, C.cnp, C.aoff, C.Ainv, r, z);
   LAUNCHCHECK("coarse_solve");
 }
 
@@ -587,6 +624,7 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
   if (prm->smoother != MVAMG_SMOOTH_GS && prm->smoother != MVAMG_SMOOTH_L1JACOBI)
     throw Error(MVAMG_ERR_ARG, "unknown smoother");
   if (prm->maxit < 0 || !(prm->rtol >= 0.0)) throw Error(MVAMG_ERR_ARG, "invalid maxit or rtol");
+  if (h->nprob > 0) throw Error(MVAMG_ERR_ARG, "a batch handle is solved with mvamg_batch_pcg_solve");
   check_device(h);
   const int n = h->n;
   const int eg = grid_for(n);
@@ -678,81 +716,39 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
   return status;
 }
 
-}  // namespace
-
-// ====================================================================== ABI
-
-extern "C" {
-
-const char* mvamg_last_error(void) { return g_err.c_str(); }
-
-mvamg_status mvamg_profile(mvamg_hier* h, int enable) {
-  try {
-    if (!h) throw Error(MVAMG_ERR_ARG, "null handle");
-    HIPCHECK(hipDeviceSynchronize());
-    harvest(h);
-    h->prof = enable != 0;
-    for (int k = 0; k < MVAMG_KC_COUNT; ++k) {
-      h->kc_launches[k] = 0;
-      h->kc_ms[k] = 0.0;
-      h->kc_bytes[k] = 0.0;
+// Dense Cholesky of one coarsest block (CSR C padded with the identity to np
+// rows) and its inverse L^{-T} L^{-1} written to out (np x np).  M and Li are
+// scratch of at least np x np; the block's CSR arrays are added to temps.
+void factor_block(mvamg_hier* h, const HostLevel& C, int np, double* M, double* Li, double* out, int* flag,
+                  std::vector<void*>& temps, hipStream_t st) {
+  const int nb = np / TD;
+  int* rp = h->upload_vec(C.rp, st);
+  int* ci = h->upload_vec(C.ci, st);
+  double* v = h->upload_vec(C.v, st);
+  temps.push_back(rp);
+  temps.push_back(ci);
+  temps.push_back(v);
+  HIPCHECK(hipMemsetAsync(M, 0, sizeof(double) * (size_t)np * np, st));
+  k_csr_to_padded<<<grid_for(np), kBlock, 0, st>>>(C.n, np, rp, ci, v, M);
+  for (int kb = 0; kb < nb; ++kb) {
+    k_potrf_tile<<<1, 256, 0, st>>>(M, np, kb, flag);
+    const int m = nb - kb - 1;
+    if (m > 0) {
+      k_trsm_tile<<<m, 256, 0, st>>>(M, np, kb);
+      k_update_tiles<<<dim3(m, m), 256, 0, st>>>(M, np, kb);
     }
-    return MVAMG_OK;
-  } catch (const Error& e) {
-    return fail_status(e);
   }
+  k_trtri_diag<<<nb, 256, 0, st>>>(M, Li, np);
+  for (int i = 1; i < nb; ++i) k_trtri_row<<<i, 256, 0, st>>>(M, Li, np, i);
+  k_lauum<<<dim3(nb, nb), 256, 0, st>>>(Li, out, np);
+  LAUNCHCHECK("factor_block");
 }
 
-mvamg_status mvamg_kernel_stats(mvamg_hier* h, int kclass, int64_t* launches, double* ms, double* bytes) {
-  try {
-    if (!h || kclass < 0 || kclass >= MVAMG_KC_COUNT) throw Error(MVAMG_ERR_ARG, "bad handle or kernel class");
-    HIPCHECK(hipDeviceSynchronize());
-    harvest(h);
-    if (launches) *launches = h->kc_launches[kclass];
-    if (ms) *ms = h->kc_ms[kclass];
-    if (bytes) *bytes = h->kc_bytes[kclass];
-    return MVAMG_OK;
-  } catch (const Error& e) {
-    return fail_status(e);
-  }
-}
-
-mvamg_status mvamg_hier_read(const char* path, mvamg_hier_host** out) {
-  try {
-    if (!path || !out) throw Error(MVAMG_ERR_ARG, "null argument");
-    *out = nullptr;
-    std::unique_ptr<mvamg_hier_host> h(new mvamg_hier_host);
-    h->h = read_hierarchy_file(path);
-    *out = h.release();
-    return MVAMG_OK;
-  } catch (const Error& e) {
-    return fail_status(e);
-  } catch (const std::exception& e) {
-    g_err = e.what();
-    return MVAMG_ERR_FILE;
-  }
-}
-
-void mvamg_hier_host_free(mvamg_hier_host* h) { delete h; }
-
-mvamg_status mvamg_hier_host_info(const mvamg_hier_host* h, int* nlevels, int* n, int64_t* nnz) {
-  if (!h) {
-    g_err = "null handle";
-    return MVAMG_ERR_ARG;
-  }
-  if (nlevels) *nlevels = h->h.nl;
-  if (n) *n = h->h.lv[0].n;
-  if (nnz) *nnz = (int64_t)h->h.lv[0].ci.size();
-  return MVAMG_OK;
-}
-
-mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** out) {
-  hipStream_t st = (hipStream_t)stream;
+// Device copy of a hierarchy; cblk lists the diagonal blocks of its
+// coarsest level (one for a single problem, one per problem of a batch).
+std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<const HostLevel*>& cblk, hipStream_t st) {
   std::unique_ptr<mvamg_hier> h;
   try {
-    if (!hh || !out) throw Error(MVAMG_ERR_ARG, "null argument");
-    *out = nullptr;
-    const HostHier& H = hh->h;
     if (H.nl < 2) throw Error(MVAMG_ERR_ARG, "hierarchy needs at least two levels");
     h.reset(new mvamg_hier);
     HIPCHECK(hipGetDevice(&h->device));
@@ -883,7 +879,7 @@ mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** 
         LAUNCHCHECK("Urow32");
       }
     }
-    // ---- coarsest level: blocked dense Cholesky and inverse on the device
+    // ---- coarsest level: blocked dense Cholesky and inverse of every diagonal block
     {
       const HostLevel& C = H.lv[H.nl - 1];
       DevLevel& LC = h->lv[H.nl - 1];
@@ -894,32 +890,31 @@ mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** 
       LC.x32 = h->dalloc<float>(C.n);
       DevCoarse& D = h->co;
       D.n = C.n;
-      D.np = ((C.n + TD - 1) / TD) * TD;
-      const int np = D.np, nb = np / TD;
-      if ((int64_t)np * np > ((int64_t)1 << 29)) throw Error(MVAMG_ERR_ARG, "coarsest level too large for a dense solve");
+      D.nb = (int)cblk.size();
+      std::vector<int> coff(D.nb + 1, 0), cnp(D.nb);
+      std::vector<int64_t> aoff(D.nb + 1, 0);
+      int npmax = 0;
+      for (int bk = 0; bk < D.nb; ++bk) {
+        const int nbk = cblk[bk]->n;
+        cnp[bk] = ((nbk + TD - 1) / TD) * TD;
+        if ((int64_t)cnp[bk] * cnp[bk] > ((int64_t)1 << 29))
+          throw Error(MVAMG_ERR_ARG, "coarsest level too large for a dense solve");
+        coff[bk + 1] = coff[bk] + nbk;
+        aoff[bk + 1] = aoff[bk] + (int64_t)cnp[bk] * cnp[bk];
+        npmax = std::max(npmax, cnp[bk]);
+        D.ainv_entries += (double)nbk * nbk;
+      }
+      if (coff[D.nb] != C.n) throw Error(MVAMG_ERR_ARG, "coarsest blocks do not cover the coarsest level");
+      D.np = cnp[0];
       D.r = h->dalloc<double>(C.n);
       D.z = h->dalloc<double>(C.n);
-      int* rp = h->upload_vec(C.rp, st);
-      int* ci = h->upload_vec(C.ci, st);
-      double* v = h->upload_vec(C.v, st);
-      double* M = h->dalloc<double>((size_t)np * np);
-      double* Li = h->dalloc<double>((size_t)np * np);
-      D.Ainv = h->dalloc<double>((size_t)np * np);
+      D.Ainv = h->dalloc<double>((size_t)aoff[D.nb]);
+      double* M = h->dalloc<double>((size_t)npmax * npmax);
+      double* Li = h->dalloc<double>((size_t)npmax * npmax);
       int* flag = h->dalloc<int>(1);
-      HIPCHECK(hipMemsetAsync(M, 0, sizeof(double) * (size_t)np * np, st));
       HIPCHECK(hipMemsetAsync(flag, 0, sizeof(int), st));
-      k_csr_to_padded<<<grid_for(np), kBlock, 0, st>>>(C.n, np, rp, ci, v, M);
-      for (int kb = 0; kb < nb; ++kb) {
-        k_potrf_tile<<<1, 256, 0, st>>>(M, np, kb, flag);
-        const int m = nb - kb - 1;
-        if (m > 0) {
-          k_trsm_tile<<<m, 256, 0, st>>>(M, np, kb);
-          k_update_tiles<<<dim3(m, m), 256, 0, st>>>(M, np, kb);
-        }
-      }
-      k_trtri_diag<<<nb, 256, 0, st>>>(M, Li, np);
-      for (int i = 1; i < nb; ++i) k_trtri_row<<<i, 256, 0, st>>>(M, Li, np, i);
-      k_lauum<<<dim3(nb, nb), 256, 0, st>>>(Li, D.Ainv, np);
+      std::vector<void*> temps;
+      for (int bk = 0; bk < D.nb; ++bk) factor_block(h.get(), *cblk[bk], cnp[bk], M, Li, D.Ainv + aoff[bk], flag, temps, st);
       LAUNCHCHECK("coarsest factorisation");
       int hflag = 0;
       HIPCHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -927,14 +922,22 @@ mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** 
       if (hflag) throw Error(MVAMG_ERR_NOT_SPD, "coarsest matrix is not positive definite (Cholesky pivot <= 0)");
       h->dfree(M);
       h->dfree(Li);
-      h->dfree(rp);
-      h->dfree(ci);
-      h->dfree(v);
+      for (void* t : temps) h->dfree(t);
+      if (D.nb > 1) {
+        std::vector<int> cprob(C.n);
+        for (int bk = 0; bk < D.nb; ++bk)
+          for (int i = coff[bk]; i < coff[bk + 1]; ++i) cprob[i] = bk;
+        D.cprob = h->upload_vec(cprob, st);
+        D.coff = h->upload_vec(coff, st);
+        D.cnp = h->upload_vec(cnp, st);
+        D.aoff = h->upload_vec(aoff, st);
+      }
     }
     // ---- level-0 extras and CG state
     {
       const int n = h->n;
       h->perm0 = h->upload_vec(Y[0].perm, st);
+      h->iperm0 = h->upload_vec(Y[0].iperm, st);
       h->frp = h->upload_vec(H.lv[0].rp, st);
       h->fci = h->upload_vec(H.lv[0].ci, st);
       h->b = h->dalloc<double>(n);
@@ -952,6 +955,128 @@ mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** 
     }
     for (int l = 0; l + 1 < H.nl; ++l) derive_level(h.get(), l, st);
     HIPCHECK(hipStreamSynchronize(st));
+  } catch (...) {
+    (void)hipStreamSynchronize(st);  // queued work may still use h's memory
+    throw;
+  }
+  return h;
+}
+
+
+#include "multi_host.hpp"
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+const char* mvamg_last_error(void) { return g_err.c_str(); }
+
+mvamg_status mvamg_profile(mvamg_hier* h, int enable) {
+  try {
+    if (!h) throw Error(MVAMG_ERR_ARG, "null handle");
+    HIPCHECK(hipDeviceSynchronize());
+    harvest(h);
+    h->prof = enable != 0;
+    for (int k = 0; k < MVAMG_KC_COUNT; ++k) {
+      h->kc_launches[k] = 0;
+      h->kc_ms[k] = 0.0;
+      h->kc_bytes[k] = 0.0;
+    }
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_kernel_stats(mvamg_hier* h, int kclass, int64_t* launches, double* ms, double* bytes) {
+  try {
+    if (!h || kclass < 0 || kclass >= MVAMG_KC_COUNT) throw Error(MVAMG_ERR_ARG, "bad handle or kernel class");
+    HIPCHECK(hipDeviceSynchronize());
+    harvest(h);
+    if (launches) *launches = h->kc_launches[kclass];
+    if (ms) *ms = h->kc_ms[kclass];
+    if (bytes) *bytes = h->kc_bytes[kclass];
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_hier_read(const char* path, mvamg_hier_host** out) {
+  try {
+    if (!path || !out) throw Error(MVAMG_ERR_ARG, "null argument");
+    *out = nullptr;
+    std::unique_ptr<mvamg_hier_host> h(new mvamg_hier_host);
+    h->h = read_hierarchy_file(path);
+    *out = h.release();
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return MVAMG_ERR_FILE;
+  }
+}
+
+void mvamg_hier_host_free(mvamg_hier_host* h) { delete h; }
+
+mvamg_status mvamg_hier_host_info(const mvamg_hier_host* h, int* nlevels, int* n, int64_t* nnz) {
+  if (!h) {
+    g_err = "null handle";
+    return MVAMG_ERR_ARG;
+  }
+  if (nlevels) *nlevels = h->h.nl;
+  if (n) *n = h->h.lv[0].n;
+  if (nnz) *nnz = (int64_t)h->h.lv[0].ci.size();
+  return MVAMG_OK;
+}
+
+mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** out) {
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    if (!hh || !out) throw Error(MVAMG_ERR_ARG, "null argument");
+    *out = nullptr;
+    const HostHier& H = hh->h;
+    if (H.nl < 2) throw Error(MVAMG_ERR_ARG, "hierarchy needs at least two levels");
+    const std::vector<const HostLevel*> cb{&H.lv[H.nl - 1]};
+    *out = upload_hier(H, cb, st).release();
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return MVAMG_ERR_HIP;
+  }
+}
+
+mvamg_status mvamg_batch_upload(const mvamg_hier_host* const* hs, int nprob, void* stream, mvamg_hier** out) {
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    if (!hs || !out || nprob < 1) throw Error(MVAMG_ERR_ARG, "null argument or empty batch");
+    *out = nullptr;
+    std::vector<const HostHier*> Hs;
+    for (int p = 0; p < nprob; ++p) {
+      if (!hs[p]) throw Error(MVAMG_ERR_ARG, "null hierarchy in batch");
+      Hs.push_back(&hs[p]->h);
+    }
+    const HostHier U = union_hierarchy(Hs);
+    if (U.nl < 2) throw Error(MVAMG_ERR_ARG, "hierarchy needs at least two levels");
+    std::vector<const HostLevel*> cb;
+    for (const HostHier* H : Hs) cb.push_back(&H->lv[H->nl - 1]);
+    std::unique_ptr<mvamg_hier> h = upload_hier(U, cb, st);
+    h->nprob = nprob;
+    h->h_poff.assign(nprob + 1, 0);
+    int maxn = 1;
+    for (int p = 0; p < nprob; ++p) {
+      h->h_poff[p + 1] = h->h_poff[p] + Hs[p]->lv[0].n;
+      maxn = std::max(maxn, Hs[p]->lv[0].n);
+    }
+    h->poff = h->upload_vec(h->h_poff, st);
+    h->pchunks = std::min(64, std::max(1, (maxn + 2047) / 2048));
+    ensure_multi(h.get(), nprob, h->pchunks);
+    HIPCHECK(hipStreamSynchronize(st));
     *out = h.release();
     return MVAMG_OK;
   } catch (const Error& e) {
@@ -961,6 +1086,17 @@ mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** 
     g_err = e.what();
     return MVAMG_ERR_HIP;
   }
+}
+
+mvamg_status mvamg_batch_problems(const mvamg_hier* h, int* nprob, int* offsets) {
+  if (!h) {
+    g_err = "null handle";
+    return MVAMG_ERR_ARG;
+  }
+  if (nprob) *nprob = h->nprob;
+  if (offsets)
+    for (int p = 0; p <= h->nprob && h->nprob > 0; ++p) offsets[p] = h->h_poff[p];
+  return MVAMG_OK;
 }
 
 void mvamg_free(mvamg_hier* h) {
@@ -1063,6 +1199,72 @@ mvamg_status mvamg_grad_coeffs(mvamg_hier* h, const double* lambda, const double
     k_grad_coeffs<<<grid_for(h->n), kBlock, 0, st>>>(h->n, h->frp, h->fci, lambda, x, dval);
     LAUNCHCHECK("grad_coeffs");
     return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_spmv_block(mvamg_hier* h, const double* X, double* Y, int m, void* stream) {
+  try {
+    if (!h || !X || !Y) throw Error(MVAMG_ERR_ARG, "null argument");
+    if (m < 1 || m > MVAMG_BLOCK_MAX) throw Error(MVAMG_ERR_ARG, "block width must be 1..32");
+    check_device(h);
+    hipStream_t st = (hipStream_t)stream;
+    ensure_block(h);
+    k_bgather<<<bgrid_elem(h->n), kBlock, 0, st>>>(h->n, h->perm0, m, X, h->bp);
+    bresid<double, 2>(h, h->lv[0], nullptr, h->bp, h->bq, MM_STORE_R0, st);
+    k_bscatter<<<bgrid_elem(h->n), kBlock, 0, st>>>(h->n, h->perm0, m, h->bq, Y);
+    LAUNCHCHECK("spmv_block");
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_cycle_apply_block(mvamg_hier* h, const double* R, double* Z, int m, int precision, int smoother,
+                                     void* stream) {
+  try {
+    if (!h || !R || !Z) throw Error(MVAMG_ERR_ARG, "null argument");
+    if (R == Z) throw Error(MVAMG_ERR_ARG, "R and Z must not alias");
+    if (m < 1 || m > MVAMG_BLOCK_MAX) throw Error(MVAMG_ERR_ARG, "block width must be 1..32");
+    if (precision != 64 && precision != 32) throw Error(MVAMG_ERR_ARG, "precision must be 64 or 32");
+    if (smoother != MVAMG_SMOOTH_GS && smoother != MVAMG_SMOOTH_L1JACOBI) throw Error(MVAMG_ERR_ARG, "unknown smoother");
+    check_device(h);
+    hipStream_t st = (hipStream_t)stream;
+    ensure_block(h);
+    DevLevel& L0 = h->lv[0];
+    k_bgather<<<bgrid_elem(h->n), kBlock, 0, st>>>(h->n, h->perm0, m, R, L0.br);
+    bapply_B(h, L0.br, L0.bx, precision, smoother, st);
+    k_bscatter<<<bgrid_elem(h->n), kBlock, 0, st>>>(h->n, h->perm0, m, L0.bx, Z);
+    LAUNCHCHECK("cycle_apply_block");
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_pcg_solve_block(mvamg_hier* h, const double* B, double* X, int m, const mvamg_solve_params* prm,
+                                   mvamg_info* info, void* stream) {
+  try {
+    if (!h) throw Error(MVAMG_ERR_ARG, "null handle");
+    if (m < 1 || m > MVAMG_BLOCK_MAX) throw Error(MVAMG_ERR_ARG, "block width must be 1..32");
+    check_device(h);
+    ensure_block(h);
+    BlockOps O(h, m);
+    return multi_pcg(O, B, X, prm, info, (hipStream_t)stream);
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_batch_pcg_solve(mvamg_hier* h, const double* b, double* x, const mvamg_solve_params* prm,
+                                   mvamg_info* info, void* stream) {
+  try {
+    if (!h) throw Error(MVAMG_ERR_ARG, "null handle");
+    if (h->nprob < 1) throw Error(MVAMG_ERR_ARG, "not a batch handle (use mvamg_pcg_solve)");
+    check_device(h);
+    BatchOps O(h);
+    return multi_pcg(O, b, x, prm, info, (hipStream_t)stream);
   } catch (const Error& e) {
     return fail_status(e);
   }

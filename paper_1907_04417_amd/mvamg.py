@@ -25,7 +25,9 @@ SMOOTH_GS, SMOOTH_L1JACOBI = 0, 1
 EXPORTED = ["mvamg_hier_read", "mvamg_hier_host_free", "mvamg_hier_host_info", "mvamg_upload", "mvamg_free",
             "mvamg_levels", "mvamg_set_fine_values", "mvamg_spmv", "mvamg_cycle_apply", "mvamg_pcg_solve",
             "mvamg_adjoint_solve", "mvamg_grad_coeffs", "mvamg_profile", "mvamg_kernel_stats",
-            "mvamg_last_error"]
+            "mvamg_last_error", "mvamg_spmv_block", "mvamg_cycle_apply_block", "mvamg_pcg_solve_block",
+            "mvamg_batch_upload", "mvamg_batch_problems", "mvamg_batch_pcg_solve"]
+BLOCK_MAX = 32
 
 # kernel classes of mvamg_kernel_stats
 KC_SMOOTH_FINE, KC_SMOOTH_COARSE, KC_SPMV, KC_RESIDUAL, KC_RESTRICT, KC_PROLONG, KC_COARSE = range(7)
@@ -78,6 +80,12 @@ def load(path: str = LIB_PATH):
         L.mvamg_kernel_stats.argtypes = [vp, ctypes.c_int, P(ctypes.c_int64), P(ctypes.c_double),
                                          P(ctypes.c_double)]
         L.mvamg_last_error.restype = ctypes.c_char_p
+        L.mvamg_spmv_block.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+        L.mvamg_cycle_apply_block.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+        L.mvamg_pcg_solve_block.argtypes = [vp, vp, vp, ctypes.c_int, P(SolveParams), P(Info), vp]
+        L.mvamg_batch_upload.argtypes = [P(vp), ctypes.c_int, vp, P(vp)]
+        L.mvamg_batch_problems.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int)]
+        L.mvamg_batch_pcg_solve.argtypes = [vp, vp, vp, P(SolveParams), P(Info), vp]
         for name in EXPORTED:
             if name not in ("mvamg_hier_host_free", "mvamg_free", "mvamg_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -188,6 +196,64 @@ def grad_coeffs(h: int, lam, x, dval, stream=None) -> None:
     _check(load().mvamg_grad_coeffs(h, _dev(lam), _dev(x), _dev(dval), _stream(stream)))
 
 
+def _block_width(X) -> int:
+    m = 1 if X.dim() == 1 else X.shape[1]
+    if not 1 <= m <= BLOCK_MAX:
+        raise ValueError(f"block width must be 1..{BLOCK_MAX}")
+    return m
+
+
+def spmv_block(h: int, X, Y, stream=None) -> None:
+    """Y = A X for an n x m row-major block (m <= 32)."""
+    _check(load().mvamg_spmv_block(h, _dev(X), _dev(Y), _block_width(X), _stream(stream)))
+
+
+def cycle_apply_block(h: int, R, Z, precision: int = 64, smoother: int = SMOOTH_GS, stream=None) -> None:
+    _check(load().mvamg_cycle_apply_block(h, _dev(R), _dev(Z), _block_width(R), precision, smoother,
+                                          _stream(stream)))
+
+
+def pcg_solve_block(h: int, B, X, rtol=1e-8, maxit=1000, precision=64, smoother=SMOOTH_GS, max_restarts=3,
+                    history: np.ndarray | None = None, stream=None) -> list:
+    """CG on every column of the n x m block B (X: initial guesses, overwritten).
+    history: m x (maxit + 1) array or None.  Returns one Info per column."""
+    m = _block_width(B)
+    infos = (Info * m)()
+    prm = _params(rtol, maxit, precision, smoother, max_restarts, history)
+    _check(load().mvamg_pcg_solve_block(h, _dev(B), _dev(X), m, ctypes.byref(prm), infos, _stream(stream)),
+           allow=(OK, NOT_CONVERGED))
+    return list(infos)
+
+
+def batch_upload(hhs, stream=None) -> int:
+    """Upload parsed hierarchies (mvamg_hier_read handles) as one batch."""
+    arr = (ctypes.c_void_p * len(hhs))(*hhs)
+    h = ctypes.c_void_p()
+    _check(load().mvamg_batch_upload(arr, len(hhs), _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def batch_problems(h: int):
+    """(problem count, row offsets) of a batch handle."""
+    k = ctypes.c_int()
+    _check(load().mvamg_batch_problems(h, ctypes.byref(k), None))
+    off = (ctypes.c_int * (k.value + 1))()
+    _check(load().mvamg_batch_problems(h, ctypes.byref(k), off))
+    return k.value, list(off)
+
+
+def batch_pcg_solve(h: int, b, x, rtol=1e-8, maxit=1000, precision=64, smoother=SMOOTH_GS, max_restarts=3,
+                    history: np.ndarray | None = None, stream=None) -> list:
+    """CG on every problem of a batch (b, x: the problems' vectors one after
+    another).  history: nprob x (maxit + 1) array or None.  One Info per problem."""
+    k, _ = batch_problems(h)
+    infos = (Info * k)()
+    prm = _params(rtol, maxit, precision, smoother, max_restarts, history)
+    _check(load().mvamg_batch_pcg_solve(h, _dev(b), _dev(x), ctypes.byref(prm), infos, _stream(stream)),
+           allow=(OK, NOT_CONVERGED))
+    return list(infos)
+
+
 def profile(h: int, enable: bool) -> None:
     """Turn per-launch kernel timing on or off (resets the totals)."""
     _check(load().mvamg_profile(h, 1 if enable else 0))
@@ -259,3 +325,33 @@ class Solver:
         y = torch.empty_like(x)
         spmv(self.h, x, y, stream)
         return y
+
+
+class BatchSolver:
+    """Several hierarchy files (same number of levels) uploaded as one batch."""
+
+    def __init__(self, paths, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("mvamg needs a GPU (HIP device)")
+        hhs = []
+        try:
+            for p in paths:
+                hhs.append(hier_read(p))
+            self.h = batch_upload(hhs, stream)
+        finally:
+            for hh in hhs:
+                hier_host_free(hh)
+        self.nprob, self.offsets = batch_problems(self.h)
+        self.info = levels(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

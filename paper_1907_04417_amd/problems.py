@@ -18,6 +18,9 @@ Problem families (stand-ins for the paper's test matrices, Section 5):
   displacement components per node.
 * ``grf_fv5``  -- cell-centred 5-point finite volumes with conductivity exp(g),
   g a Gaussian random field.
+* ``block_rhs``   -- many right-hand sides B = A X* for one matrix.
+* ``aniso_batch`` -- many independent ``aniso9`` problems of uneven size,
+  anisotropy and angle.
 """
 from __future__ import annotations
 
@@ -111,6 +114,31 @@ def aniso9(m: int = 64, eps: float = 1e-2, theta: float = math.pi / 4, seed: int
     A = sp.csr_matrix((v, ci, rp), shape=(n, n))
     return Problem(f"aniso9_m{m}", rp, ci, v, A @ xs, xs,
                    dict(m=m, eps=eps, theta=theta, seed=seed))
+
+
+def block_rhs(P: Problem, k: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """k right-hand sides B = A X* for one matrix, X* ~ U[-1, 1] drawn as one
+    (n, k) array (row-major: row i holds the k values of unknown i).
+    Returns (B, X*), both n x k C-contiguous."""
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1.0, 1.0, size=(P.n, k))
+    B = np.ascontiguousarray(P.scipy() @ X)
+    return B, X
+
+
+def aniso_batch(nprob: int = 64, smin: int = 32, smax: int = 512, seed: int = 0) -> list[Problem]:
+    """Independent rotated anisotropic problems of uneven size.
+
+    Draws from default_rng(seed), in this order: nprob grid sides uniform on
+    the integers smin..smax, nprob values log10(eps) uniform on [-4, 0], nprob
+    angles theta uniform on [0, pi).  Problem p is then aniso9(side_p, eps_p,
+    theta_p, seed = 1000 * seed + 1 + p) (its own x*)."""
+    rng = np.random.default_rng(seed)
+    sides = rng.integers(smin, smax + 1, size=nprob)
+    leps = rng.uniform(-4.0, 0.0, size=nprob)
+    theta = rng.uniform(0.0, math.pi, size=nprob)
+    return [aniso9(int(sides[p]), float(10.0 ** leps[p]), float(theta[p]), seed=1000 * seed + 1 + p)
+            for p in range(nprob)]
 
 
 def jump7_coefficient(m: int, cube: int, p: float, rng) -> np.ndarray:

@@ -9,6 +9,14 @@ hierarchy file cached on disk (setup is the untimed input generator).
     jump32    the same family on 32^3 (test size)
     grf1024   cell-centred 5-point finite volumes on 1024^2 cells, conductivity
               exp(g), g a Gaussian random field (length 0.05, sigma 1), b = h^2 * 1
+    aniso1024 the aniso64 operator on a 1024 x 1024 grid (32 right-hand sides
+              B = A X* from block_rhs(seed 5) in the multi-RHS runs)
+
+Batches (load_batch): independent problems, each with its own hierarchy, all
+set up with three levels (bootstrap depth at most 6, three bootstrap levels
+composed per level, no size cap on the coarse levels):
+    batch64   64 aniso9 problems, sides 32..512, eps 1e-4..1, theta 0..pi
+    batch6    6 problems, sides 32..64 (test size)
 """
 from __future__ import annotations
 
@@ -29,6 +37,15 @@ CONFIGS = {
                    setup=dict(boot_coarse_min=8, coarse_cap=64, compose=2)),
     "grf1024": dict(gen=lambda: problems.grf_fv5(1024, seed=0), nvec=3, setup={}),
     "grf32": dict(gen=lambda: problems.grf_fv5(32, seed=3), nvec=3, setup=dict(boot_coarse_min=8, coarse_cap=64)),
+    "aniso1024": dict(gen=lambda: problems.aniso9(1024, 1e-2, math.pi / 4, seed=0), nvec=3, setup={}),
+}
+
+BLOCK_RHS_SEED = 5
+
+BATCH_SETUP = dict(boot_coarse_min=8, coarse_cap=0, max_levels=7, compose=3)
+BATCHES = {
+    "batch64": dict(gen=lambda: problems.aniso_batch(64, 32, 512, seed=0), nvec=3, setup=BATCH_SETUP),
+    "batch6": dict(gen=lambda: problems.aniso_batch(6, 32, 64, seed=1), nvec=3, setup=BATCH_SETUP),
 }
 
 BOOTSTRAP_SEED = 1000
@@ -59,3 +76,32 @@ def load(name: str, **setup_overrides):
     with open(meta, "w") as f:
         json.dump(st, f)
     return P, path, st
+
+
+def _hierarchy(tag: str, P, nvec: int, setup: dict):
+    params = SetupParams(nvec_max=nvec, **setup)
+    key = hashlib.sha1(json.dumps([tag, P.n, P.nnz, sorted(params.__dict__.items())],
+                                  default=str).encode()).hexdigest()[:12]
+    path = os.path.join(cache_dir(), f"{tag}_{key}.bin")
+    meta = path + ".json"
+    if os.path.exists(path) and os.path.exists(meta):
+        with open(meta) as f:
+            return path, json.load(f)
+    x0 = problems.random_vectors(P.n, max(nvec - 1, 1), BOOTSTRAP_SEED)
+    st = build_hierarchy(P.rowptr, P.col, P.val, path + ".tmp", x0, params)
+    os.replace(path + ".tmp", path)
+    with open(meta, "w") as f:
+        json.dump(st, f)
+    return path, st
+
+
+def load_batch(name: str):
+    """Returns (problems, hierarchy_paths, setup_stats) of a batch."""
+    cfg = BATCHES[name]
+    Ps = cfg["gen"]()
+    paths, stats = [], []
+    for p, P in enumerate(Ps):
+        path, st = _hierarchy(f"{name}_p{p}", P, cfg["nvec"], cfg["setup"])
+        paths.append(path)
+        stats.append(st)
+    return Ps, paths, stats

@@ -62,3 +62,29 @@ def test_null_handle_is_an_argument_error(lib):
     rc = lib.mvamg_levels(None, None, None, None, None)
     assert rc == mvamg.ERR_ARG
     assert "null" in mvamg.last_error()
+
+
+def test_batch_upload_validates_on_the_host(lib, tiny_hier, tmp_path):
+    """A batch needs at least one problem, no null entries and the same number
+    of levels in every hierarchy; these are rejected before any device work."""
+    from paper_1907_04417_amd import problems
+    from paper_1907_04417_amd.setup import SetupParams, build_hierarchy
+    _, path3, st3 = tiny_hier
+    P = problems.aniso9(10, seed=4)
+    path2 = str(tmp_path / "two_levels.bin")
+    st2 = build_hierarchy(P.rowptr, P.col, P.val, path2, problems.random_vectors(P.n, 1, 7),
+                          SetupParams(nvec_max=2, boot_coarse_min=4, coarse_cap=40, compose=1))
+    assert st2["nlevels"] != st3["nlevels"]
+    hs = [mvamg.hier_read(path3), mvamg.hier_read(path2)]
+    try:
+        out = ctypes.c_void_p()
+        arr = (ctypes.c_void_p * 2)(*hs)
+        assert lib.mvamg_batch_upload(arr, 2, None, ctypes.byref(out)) == mvamg.ERR_ARG
+        assert "same number of levels" in mvamg.last_error()
+        assert lib.mvamg_batch_upload(arr, 0, None, ctypes.byref(out)) == mvamg.ERR_ARG
+        nul = (ctypes.c_void_p * 2)(hs[0], None)
+        assert lib.mvamg_batch_upload(nul, 2, None, ctypes.byref(out)) == mvamg.ERR_ARG
+        assert out.value is None
+    finally:
+        for hh in hs:
+            mvamg.hier_host_free(hh)
