@@ -218,6 +218,94 @@ def laplace7(m: int) -> Problem:
     return Problem(f"laplace7_m{m}", rp, ci, v, A @ xs, xs, dict(m=m))
 
 
+def q1_hex_stiffness(E: float, nu: float, h: float) -> np.ndarray:
+    """24 x 24 stiffness matrix of a trilinear hexahedron (cube of side h) for
+    isotropic linear elasticity (Lame equations, Section 5.2) with Young's
+    modulus E and Poisson ratio nu: K = sum over the 2 x 2 x 2 Gauss points of
+    B^T D B |J| w.  Local nodes in the order (x, y, z) in {0,1}^3, x fastest;
+    dofs node-major (3 per node)."""
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    mu = E / (2.0 * (1.0 + nu))
+    D = np.zeros((6, 6))
+    D[:3, :3] = lam
+    D[np.arange(3), np.arange(3)] += 2.0 * mu
+    D[3:, 3:] = np.eye(3) * mu
+    corners = np.array([[(a >> 0) & 1, (a >> 1) & 1, (a >> 2) & 1] for a in range(8)], dtype=float)
+    g = 0.5 / math.sqrt(3.0)
+    K = np.zeros((24, 24))
+    for gp in np.array(np.meshgrid([0.5 - g, 0.5 + g], [0.5 - g, 0.5 + g], [0.5 - g, 0.5 + g], indexing="ij")).reshape(3, -1).T:
+        # derivatives of the shape functions prod_d (c_d xi_d + (1 - c_d)(1 - xi_d)) on the unit cube
+        dN = np.zeros((8, 3))
+        for a, c in enumerate(corners):
+            f = [c[d] * gp[d] + (1 - c[d]) * (1 - gp[d]) for d in range(3)]
+            df = [2 * c[d] - 1 for d in range(3)]
+            dN[a] = [df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]]
+        dN /= h
+        B = np.zeros((6, 24))
+        for a in range(8):
+            bx, by, bz = dN[a]
+            B[0, 3 * a], B[1, 3 * a + 1], B[2, 3 * a + 2] = bx, by, bz
+            B[3, 3 * a], B[3, 3 * a + 1] = by, bx
+            B[4, 3 * a + 1], B[4, 3 * a + 2] = bz, by
+            B[5, 3 * a], B[5, 3 * a + 2] = bz, bx
+        K += B.T @ D @ B * (h ** 3) / 8.0
+    return K
+
+
+def elast_q1(m: int = 48, radius: float = 3.0, frac: float = 0.1, seed: int = 0) -> Problem:
+    """3-D linear elasticity (Section 5.2), trilinear hexahedra, node-based
+    ordering (the three displacement components of a node are consecutive).
+
+    Grid: m x m x m free nodes (x fastest) plus one clamped node layer at
+    x = 0, i.e. m elements along x and m - 1 along y and z, spacing h = 1/m.
+    Material: E = 1, nu = 0.3, with spherical inclusions of nu = 0.49 (radius
+    `radius` cells): sphere centres are drawn uniformly in the box (three
+    uniforms each, x then y then z) until the elements whose centre lies in a
+    sphere make up at least `frac` of all elements.  Load: the face x = 1 is
+    pushed downward (a force -h^2 in z on each of its nodes).  n = 3 m^3."""
+    h = 1.0 / m
+    nex, ney, nez = m, m - 1, m - 1
+    rng = np.random.default_rng(seed)
+    ex, ey, ez = np.meshgrid(np.arange(nex), np.arange(ney), np.arange(nez), indexing="ij")
+    ex, ey, ez = ex.ravel(), ey.ravel(), ez.ravel()
+    cx, cy, cz = (ex + 0.5) * h, (ey + 0.5) * h, (ez + 0.5) * h
+    incl = np.zeros(ex.shape[0], dtype=bool)
+    r2 = (radius * h) ** 2
+    while incl.mean() < frac:
+        c = rng.uniform(0.0, 1.0, size=3) * np.array([1.0, (m - 1) * h, (m - 1) * h])
+        incl |= (cx - c[0]) ** 2 + (cy - c[1]) ** 2 + (cz - c[2]) ** 2 <= r2
+    Ks = [q1_hex_stiffness(1.0, 0.3, h), q1_hex_stiffness(1.0, 0.49, h)]
+    # global node of local corner (a, b, c) of element (ex, ey, ez): layer ex + a in x (0 = clamped)
+    rows, cols, vals = [], [], []
+    for mat in (0, 1):
+        sel = incl if mat == 1 else ~incl
+        exs, eys, ezs = ex[sel], ey[sel], ez[sel]
+        dofs = np.empty((exs.shape[0], 24), dtype=np.int64)
+        free = np.empty((exs.shape[0], 24), dtype=bool)
+        for a in range(8):
+            ix, iy, iz = exs + (a & 1), eys + ((a >> 1) & 1), ezs + ((a >> 2) & 1)
+            node = (iz * m + iy) * m + (ix - 1)
+            for d in range(3):
+                dofs[:, 3 * a + d] = 3 * node + d
+                free[:, 3 * a + d] = ix >= 1
+        K = Ks[mat]
+        ok = free[:, :, None] & free[:, None, :]
+        R = np.broadcast_to(dofs[:, :, None], ok.shape)[ok]
+        C = np.broadcast_to(dofs[:, None, :], ok.shape)[ok]
+        V = np.broadcast_to(K[None, :, :], ok.shape)[ok]
+        rows.append(R)
+        cols.append(C)
+        vals.append(V)
+    n = 3 * m ** 3
+    rp, ci, v = _to_csr(np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), n)
+    rp, ci, v = _symmetrize_exact(rp, ci, v)
+    b = np.zeros(n)
+    face = np.arange(m * m) * m + (m - 1)  # nodes with ix = m (x = 1): last free layer
+    b[3 * face + 2] = -h * h
+    return Problem(f"elast_q1_m{m}", rp, ci, v, b, None,
+                   dict(m=m, radius=radius, frac=float(incl.mean()), seed=seed))
+
+
 def random_vectors(n: int, k: int, seed: int) -> np.ndarray:
     """k independent U[-1, 1] vectors of length n, column-major (k, n) array.
 

@@ -20,7 +20,7 @@ from paper_1907_04417_amd import mvamg, problems, workloads
 
 pytestmark = pytest.mark.gpu
 
-BLOCK_CASES = ["aniso64", "jump16"]
+BLOCK_CASES = ["aniso64", "jump16", "elast12"]
 
 
 def _say(*a):

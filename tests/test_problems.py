@@ -58,3 +58,59 @@ def test_grf_moments_and_correlation_length():
     c1 = np.corrcoef(g[:, :-1].ravel(), g[:, 1:].ravel())[0, 1]
     c40 = np.corrcoef(g[:, :-40].ravel(), g[:, 40:].ravel())[0, 1]
     assert c1 > 0.9 and abs(c40) < 0.2
+
+
+def test_q1_stiffness_kernel_is_the_rigid_body_modes():
+    """The trilinear element matrix is symmetric positive semidefinite and its
+    null space is exactly the 6 rigid-body modes (3 translations, 3 rotations)."""
+    from paper_1907_04417_amd import problems
+    h = 0.25
+    K = problems.q1_hex_stiffness(1.0, 0.3, h)
+    assert np.abs(K - K.T).max() <= 1e-14 * np.abs(K).max()
+    ev = np.linalg.eigvalsh(K)
+    assert np.sum(np.abs(ev) <= 1e-12 * ev.max()) == 6 and ev.min() > -1e-12 * ev.max()
+    corners = np.array([[(a >> 0) & 1, (a >> 1) & 1, (a >> 2) & 1] for a in range(8)], dtype=float) * h
+    modes = []
+    for d in range(3):
+        t = np.zeros((8, 3))
+        t[:, d] = 1.0
+        modes.append(t.ravel())
+    for (i, j) in ((0, 1), (1, 2), (0, 2)):
+        r = np.zeros((8, 3))
+        r[:, i], r[:, j] = -corners[:, j], corners[:, i]
+        modes.append(r.ravel())
+    for v in modes:
+        assert np.abs(K @ v).max() <= 1e-12 * np.abs(K).max() * np.abs(v).max()
+
+
+def test_elast_q1_assembly():
+    """Clamped assembly is symmetric positive definite with node-based
+    ordering; away from the clamp a translation is in the kernel of the rows
+    whose element patch is complete (interior nodes)."""
+    from paper_1907_04417_amd import problems
+    P = problems.elast_q1(5, seed=1)
+    A = P.scipy().toarray()
+    assert P.n == 3 * 5 ** 3 and np.array_equal(A, A.T)
+    assert np.linalg.eigvalsh(A).min() > 0.0
+    # rows of an interior node (ix = 2, iy = 2, iz = 2 of the free grid) annihilate translations
+    node = (2 * 5 + 2) * 5 + 2
+    for d in range(3):
+        t = np.zeros(P.n)
+        t[d::3] = 1.0
+        assert np.abs((A @ t)[3 * node:3 * node + 3]).max() <= 1e-12 * np.abs(A).max()
+    # load on the face x = 1 only, downward
+    assert np.all(P.b[0::3] == 0.0) and np.all(P.b[1::3] == 0.0) and P.b.sum() < 0.0
+    assert 0.1 <= P.meta["frac"]
+
+
+def test_block_rhs_and_batch_draws():
+    from paper_1907_04417_amd import problems
+    P = problems.aniso9(8, seed=0)
+    B, X = problems.block_rhs(P, 3, seed=2)
+    assert B.shape == (P.n, 3) and B.flags.c_contiguous
+    assert np.allclose(B, P.scipy() @ X, rtol=0, atol=1e-14)
+    Ps = problems.aniso_batch(5, 10, 20, seed=3)
+    sides = [p.meta["m"] for p in Ps]
+    assert all(10 <= s <= 20 for s in sides)
+    assert all(1e-4 <= p.meta["eps"] <= 1.0 and 0.0 <= p.meta["theta"] < np.pi for p in Ps)
+    assert [p.meta["seed"] for p in Ps] == [3001 + p for p in range(5)]
