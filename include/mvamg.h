@@ -195,6 +195,37 @@ mvamg_status mvamg_batch_problems(const mvamg_hier* h, int* nprob, int* offsets)
 mvamg_status mvamg_batch_pcg_solve(mvamg_hier* h, const double* b_dev, double* x_dev,
                                    const mvamg_solve_params* prm, mvamg_info* info, void* stream);
 
+/* --------------------------------------------------------- autotuning */
+
+enum {
+  MVAMG_TUNE_GROUP_LANES = 1,   /* grouped levels: 64 / G lanes per row, G from the
+                                   largest group (power of two) up to 8 */
+  MVAMG_TUNE_BLOCK_COARSE = 2,  /* block path: coarsest product on vector FMA or on
+                                   MFMA (wave count, inner-dimension split); allocates
+                                   the block work space */
+  MVAMG_TUNE_BATCH_CHUNKS = 4,  /* batch: chunks per problem of its reductions */
+  MVAMG_TUNE_ALL = 7
+};
+
+/* Times the kernel variants selected by `what` on this hierarchy's own data
+   (a few launches each on `stream`, which is synchronised) and keeps the
+   fastest for later calls on the handle.  report (may be NULL) receives the
+   measured times and the choice, truncated to cap bytes.  A different choice
+   changes rounding only; results with a fixed choice repeat bitwise. */
+mvamg_status mvamg_autotune(mvamg_hier* h, int what, char* report, size_t cap, void* stream);
+
+/* The handle's current choices as text ("G1=8;gemm=4;..."), NUL-terminated;
+   MVAMG_ERR_ARG if cap is too small. */
+mvamg_status mvamg_tune_get(const mvamg_hier* h, char* buf, size_t cap);
+
+/* Restores choices written by mvamg_tune_get (every value is checked before
+   any is applied).  Waits for the device to be idle. */
+mvamg_status mvamg_tune_set(mvamg_hier* h, const char* text);
+
+/* Device and hierarchy signature (GPU architecture and CU count, problem
+   count, level sizes and nonzeros) for keying a cache of tuning choices. */
+mvamg_status mvamg_signature(const mvamg_hier* h, char* buf, size_t cap);
+
 /* ---------------------------------------------------------- measurement */
 
 /* Kernel classes for mvamg_kernel_stats. */

@@ -142,6 +142,11 @@ __global__ __launch_bounds__(kBlock) void k_cast(int n, const Ti* __restrict__ i
 }
 
 template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(int64_t n, T v, T* __restrict__ out) {
+  for (int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x; p < n; p += (int64_t)gridDim.x * kBlock) out[p] = v;
+}
+
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_copy(int n, const T* __restrict__ in, T* __restrict__ out) {
   for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) out[p] = in[p];
 }

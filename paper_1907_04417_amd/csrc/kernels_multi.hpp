@@ -577,6 +577,78 @@ __global__ __launch_bounds__(kBlock) void k_bgemm(int n, int ld, const double* _
   }
 }
 
+typedef double dbl4_t __attribute__((ext_vector_type(4)));
+
+// Z = A R for the coarsest level on matrix cores (binary64 16x16x4 MFMA).
+// Block (row tile t, split ks) owns rows 16 t .. 16 t + 15 and all 32
+// columns for the KS-th share ks of the inner dimension; its W waves split
+// that share again in contiguous ranges and add their 16 x 32 partial tiles
+// in LDS in wave order.  With KS = 1 the tile goes to Z, else to
+// P + ks * n * 32 and k_bsum_splits adds the splits in order (deterministic).
+// Per 16-wide inner step lane l holds A[16 t + l % 16][k + 4 (l / 16) .. + 3]
+// (one 32-byte load); MFMA j of the step multiplies the entries j of those
+// quads with the matching rows of R, so the inner index is permuted the same
+// way on both operands.  Accumulator entry i of lane l is D[4 i + l / 16][l % 16].
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_bgemm_mfma(int n, int ld, const double* __restrict__ A,
+                                                       const double* __restrict__ R, double* __restrict__ Z) {
+  __shared__ double part[W][16][kNB];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int r0 = blockIdx.x * 16, ks = blockIdx.y, KS = gridDim.y;
+  const int nk = ld / 16;
+  const int s0 = ((ks * W + w) * nk) / (KS * W), s1 = ((ks * W + w + 1) * nk) / (KS * W);
+  const double* Arow = A + (size_t)(r0 + li) * ld + 4 * lq;
+  dbl4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+  for (int s = s0; s < s1; ++s) {
+    const int kq = 16 * s + 4 * lq;
+    const double2 a01 = *reinterpret_cast<const double2*>(Arow + 16 * s);
+    const double2 a23 = *reinterpret_cast<const double2*>(Arow + 16 * s + 2);
+    double b0[4], b1[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int kr = kq + j;
+      const bool in = kr < n;
+      const size_t o = (size_t)(in ? kr : 0) * kNB + li;
+      b0[j] = in ? R[o] : 0.0;
+      b1[j] = in ? R[o + 16] : 0.0;
+    }
+    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.x, b0[0], acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.x, b1[0], acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.y, b0[1], acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.y, b1[1], acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.x, b0[2], acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.x, b1[2], acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.y, b0[3], acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.y, b1[3], acc1, 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    part[w][4 * i + lq][li] = acc0[i];
+    part[w][4 * i + lq][16 + li] = acc1[i];
+  }
+  __syncthreads();
+  double* out = Z + (size_t)ks * n * kNB;
+  for (int e = threadIdx.x; e < 16 * kNB; e += 64 * W) {
+    const int row = e / kNB, c = e % kNB;
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) sum += part[q][row][c];
+    if (r0 + row < n) out[(size_t)(r0 + row) * kNB + c] = sum;
+  }
+}
+
+// Z[e] = sum over ks = 0 .. KS-1 of P[ks * m + e], in that order
+__global__ __launch_bounds__(kBlock) void k_bsum_splits(int m, int KS, const double* __restrict__ P,
+                                                        double* __restrict__ Z) {
+  for (int e = blockIdx.x * kBlock + threadIdx.x; e < m; e += gridDim.x * kBlock) {
+    double s = P[e];
+    for (int ks = 1; ks < KS; ++ks) s += P[(size_t)ks * m + e];
+    Z[e] = s;
+  }
+}
+
 // -------------------------------------------- independent problems (batch)
 
 // y = blockdiag(A_p) x on the coarsest level of a batch: wave per row; the

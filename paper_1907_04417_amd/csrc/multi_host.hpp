@@ -16,6 +16,17 @@ T* pick(double* d, float* f) {
     return f;
 }
 
+// Variants of the coarsest block product Z = A_L^{-1} R (chosen by the
+// autotuner): vector FMA with one row per half wave, or MFMA with W waves per
+// 16-row tile and the inner dimension split KS ways.
+struct GemmVariant {
+  int mfma, W, KS;
+};
+constexpr GemmVariant kGemmVariants[] = {{0, 0, 1}, {1, 16, 1}, {1, 4, 2}, {1, 4, 4}, {1, 4, 8}, {1, 2, 8}};
+constexpr int kGemmVariantCount = sizeof(kGemmVariants) / sizeof(kGemmVariants[0]);
+constexpr int kGemmDefault = 4;
+constexpr int kGemmMaxSplit = 8;
+
 // ----------------------------------------------------- work arrays
 
 void ensure_multi(mvamg_hier* h, int nsys, int nparts) {
@@ -85,6 +96,7 @@ void ensure_block(mvamg_hier* h) {
   h->bq = h->dalloc<double>(m0);
   h->co.br = h->dalloc<double>((size_t)h->co.n * kNB);
   h->co.bz = h->dalloc<double>((size_t)h->co.n * kNB);
+  h->co.bsplit = h->dalloc<double>((size_t)kGemmMaxSplit * h->co.n * kNB);
   int nparts = 2048;
   for (int l = 0; l + 1 < h->nl; ++l) nparts = std::max(nparts, bresid_grid(h->lv[l]));
   ensure_multi(h, kNB, nparts);
@@ -158,26 +170,40 @@ void bresid(mvamg_hier* h, const DevLevel& L, const T* r, const T* x, T* s, int 
   }
 }
 
-// rows of the coarsest block product per 256-thread block
-constexpr int kGemmRph = 2;
+void launch_bgemm(mvamg_hier* h, int variant, const double* R, double* Z, hipStream_t st) {
+  DevCoarse& C = h->co;
+  const double by = 8.0 * C.n * (double)C.n + 2.0 * C.n * kNB * 8.0;
+  const GemmVariant v = kGemmVariants[variant < 0 ? kGemmDefault : variant];
+  const int nt = (C.n + 15) / 16;
+  double* out = (v.KS == 1) ? Z : C.bsplit;
+  if (!v.mfma) {
+    klaunch(h, MVAMG_KC_COARSE, by, k_bgemm<1>, C.np / 8, kBlock, st, C.n, C.np, C.Ainv, R, Z);
+  } else {
+    const dim3 grid(nt, v.KS);
+    switch (v.W) {
+      case 16: klaunch(h, MVAMG_KC_COARSE, by, k_bgemm_mfma<16>, grid, dim3(1024), st, C.n, C.np, C.Ainv, R, out); break;
+      case 8: klaunch(h, MVAMG_KC_COARSE, by, k_bgemm_mfma<8>, grid, dim3(512), st, C.n, C.np, C.Ainv, R, out); break;
+      case 4: klaunch(h, MVAMG_KC_COARSE, by, k_bgemm_mfma<4>, grid, dim3(256), st, C.n, C.np, C.Ainv, R, out); break;
+      default: klaunch(h, MVAMG_KC_COARSE, by, k_bgemm_mfma<2>, grid, dim3(128), st, C.n, C.np, C.Ainv, R, out); break;
+    }
+    if (v.KS > 1) {
+      const int m = C.n * kNB;
+      k_bsum_splits<<<grid_elem(m), kBlock, 0, st>>>(m, v.KS, C.bsplit, Z);
+    }
+  }
+  LAUNCHCHECK("bgemm");
+}
 
 template <typename T>
 void bcoarse_solve(mvamg_hier* h, const T* r, T* z, hipStream_t st) {
   DevCoarse& C = h->co;
-  const double by = 8.0 * C.n * (double)C.n + 2.0 * C.n * kNB * 8.0;
-  const double* rd;
-  double* zd;
   if constexpr (std::is_same<T, double>::value) {
-    rd = r;
-    zd = z;
+    launch_bgemm(h, h->gemm_variant, r, z, st);
   } else {
     k_cast<float, double><<<grid_elem((int64_t)C.n * kNB), kBlock, 0, st>>>(C.n * kNB, r, C.br);
-    rd = C.br;
-    zd = C.bz;
-  }
-  klaunch(h, MVAMG_KC_COARSE, by, k_bgemm<kGemmRph>, C.np / (8 * kGemmRph), kBlock, st, C.n, C.np, C.Ainv, rd, zd);
-  if constexpr (!std::is_same<T, double>::value)
+    launch_bgemm(h, h->gemm_variant, C.br, C.bz, st);
     k_cast<double, float><<<grid_elem((int64_t)C.n * kNB), kBlock, 0, st>>>(C.n * kNB, C.bz, z);
+  }
   LAUNCHCHECK("bcoarse_solve");
 }
 

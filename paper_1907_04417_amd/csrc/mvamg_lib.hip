@@ -56,7 +56,8 @@ int grid_elem(int64_t n) {
 struct DevLevel {
   int n = 0;
   bool sell = false;
-  int G = 8;  // KMAX of a grouped level (largest group, power of two)
+  int G = 8;   // kernel instantiation of a grouped level: 64 / G lanes per row (autotuned, >= G0)
+  int G0 = 8;  // smallest admissible G: the level's largest group rounded up to a power of two
   int ng = 0, ns = 0, nslabs = 0;
   int rows0 = 0;  // rows of stage 0 (point levels)
   std::vector<int> h_sgrp, h_sslab;
@@ -111,6 +112,7 @@ struct DevCoarse {
   double ainv_entries = 0.0; // sum of the blocks' n_b^2 (algorithmic bytes / 8)
   double *r = nullptr, *z = nullptr;
   double *br = nullptr, *bz = nullptr;  // block vectors for the binary32 block cycle
+  double* bsplit = nullptr;             // partial products of a split block product
 };
 
 // per-system scalars and partials of the multi-system solves
@@ -152,6 +154,7 @@ struct mvamg_hier {
   // several systems at once
   MultiBufs mb;
   bool blk_ready = false;
+  int gemm_variant = -1;  // coarsest block product variant (-1: default; autotuned)
   double *bb = nullptr, *bxv = nullptr, *bp = nullptr, *bq = nullptr;  // level-0 block CG vectors
   hipStream_t cap = nullptr;              // stream used only to capture graphs
   std::map<int, hipGraphExec_t> graphs;   // one CG iteration per (precision, smoother)
@@ -775,6 +778,7 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
       L.n = y.n;
       L.sell = y.sell;
       L.G = y.G;
+      L.G0 = y.G;
       L.ng = (int)y.gstart.size() - 1;
       L.ns = (int)y.sgrp.size() - 1;
       L.h_sgrp = y.sgrp;
@@ -964,6 +968,7 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
 
 
 #include "multi_host.hpp"
+#include "tune_host.hpp"
 
 }  // namespace
 
@@ -1265,6 +1270,70 @@ mvamg_status mvamg_batch_pcg_solve(mvamg_hier* h, const double* b, double* x, co
     check_device(h);
     BatchOps O(h);
     return multi_pcg(O, b, x, prm, info, (hipStream_t)stream);
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_autotune(mvamg_hier* h, int what, char* report, size_t cap, void* stream) {
+  try {
+    if (!h) throw Error(MVAMG_ERR_ARG, "null handle");
+    if (what & ~MVAMG_TUNE_ALL) throw Error(MVAMG_ERR_ARG, "unknown tuning bits");
+    check_device(h);
+    hipStream_t st = (hipStream_t)stream;
+    const bool prof = h->prof;
+    h->prof = false;
+    std::string rep;
+    try {
+      if (what & MVAMG_TUNE_GROUP_LANES) tune_group_lanes(h, st, rep);
+      if ((what & MVAMG_TUNE_BLOCK_COARSE) && h->nprob == 0) tune_block_coarse(h, st, rep);
+      if (what & MVAMG_TUNE_BATCH_CHUNKS) tune_batch_chunks(h, st, rep);
+    } catch (...) {
+      h->prof = prof;
+      throw;
+    }
+    h->prof = prof;
+    HIPCHECK(hipStreamSynchronize(st));
+    drop_graphs(h);
+    rep += "chosen: " + tune_text(h);
+    if (report && cap > 0) {
+      const size_t k = std::min(cap - 1, rep.size());
+      std::memcpy(report, rep.data(), k);
+      report[k] = 0;
+    }
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_tune_get(const mvamg_hier* h, char* buf, size_t cap) {
+  try {
+    if (!h) throw Error(MVAMG_ERR_ARG, "null handle");
+    copy_text(tune_text(h), buf, cap);
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_tune_set(mvamg_hier* h, const char* text) {
+  try {
+    if (!h || !text) throw Error(MVAMG_ERR_ARG, "null argument");
+    check_device(h);
+    HIPCHECK(hipDeviceSynchronize());
+    apply_tune_text(h, text);
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_signature(const mvamg_hier* h, char* buf, size_t cap) {
+  try {
+    if (!h) throw Error(MVAMG_ERR_ARG, "null handle");
+    copy_text(signature_text(h), buf, cap);
+    return MVAMG_OK;
   } catch (const Error& e) {
     return fail_status(e);
   }

@@ -26,8 +26,10 @@ EXPORTED = ["mvamg_hier_read", "mvamg_hier_host_free", "mvamg_hier_host_info", "
             "mvamg_levels", "mvamg_set_fine_values", "mvamg_spmv", "mvamg_cycle_apply", "mvamg_pcg_solve",
             "mvamg_adjoint_solve", "mvamg_grad_coeffs", "mvamg_profile", "mvamg_kernel_stats",
             "mvamg_last_error", "mvamg_spmv_block", "mvamg_cycle_apply_block", "mvamg_pcg_solve_block",
-            "mvamg_batch_upload", "mvamg_batch_problems", "mvamg_batch_pcg_solve"]
+            "mvamg_batch_upload", "mvamg_batch_problems", "mvamg_batch_pcg_solve", "mvamg_autotune",
+            "mvamg_tune_get", "mvamg_tune_set", "mvamg_signature"]
 BLOCK_MAX = 32
+TUNE_GROUP_LANES, TUNE_BLOCK_COARSE, TUNE_BATCH_CHUNKS, TUNE_ALL = 1, 2, 4, 7
 
 # kernel classes of mvamg_kernel_stats
 KC_SMOOTH_FINE, KC_SMOOTH_COARSE, KC_SPMV, KC_RESIDUAL, KC_RESTRICT, KC_PROLONG, KC_COARSE = range(7)
@@ -86,6 +88,10 @@ def load(path: str = LIB_PATH):
         L.mvamg_batch_upload.argtypes = [P(vp), ctypes.c_int, vp, P(vp)]
         L.mvamg_batch_problems.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int)]
         L.mvamg_batch_pcg_solve.argtypes = [vp, vp, vp, P(SolveParams), P(Info), vp]
+        L.mvamg_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t, vp]
+        L.mvamg_tune_get.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+        L.mvamg_tune_set.argtypes = [vp, ctypes.c_char_p]
+        L.mvamg_signature.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
         for name in EXPORTED:
             if name not in ("mvamg_hier_host_free", "mvamg_free", "mvamg_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -252,6 +258,55 @@ def batch_pcg_solve(h: int, b, x, rtol=1e-8, maxit=1000, precision=64, smoother=
     _check(load().mvamg_batch_pcg_solve(h, _dev(b), _dev(x), ctypes.byref(prm), infos, _stream(stream)),
            allow=(OK, NOT_CONVERGED))
     return list(infos)
+
+
+def autotune(h: int, what: int = TUNE_ALL, stream=None) -> str:
+    """Time the kernel variants on this hierarchy and keep the fastest; returns the report."""
+    buf = ctypes.create_string_buffer(8192)
+    _check(load().mvamg_autotune(h, what, buf, len(buf), _stream(stream)))
+    return buf.value.decode()
+
+
+def tune_get(h: int) -> str:
+    buf = ctypes.create_string_buffer(1024)
+    _check(load().mvamg_tune_get(h, buf, len(buf)))
+    return buf.value.decode()
+
+
+def tune_set(h: int, text: str) -> None:
+    _check(load().mvamg_tune_set(h, text.encode()))
+
+
+def signature(h: int) -> str:
+    buf = ctypes.create_string_buffer(4096)
+    _check(load().mvamg_signature(h, buf, len(buf)))
+    return buf.value.decode()
+
+
+def tuned(h: int, cache_path: str | None = None, what: int = TUNE_ALL, stream=None) -> str:
+    """Apply cached tuning choices for this device and hierarchy signature, or
+    autotune and add them to the cache (a JSON file, default
+    $MVAMG_TUNE_CACHE or ~/.cache/mvamg_tune.json).  Returns the choices."""
+    import json
+    path = cache_path or os.environ.get("MVAMG_TUNE_CACHE",
+                                        os.path.join(os.path.expanduser("~"), ".cache", "mvamg_tune.json"))
+    key = f"{signature(h)}|what={what}"
+    cache = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            cache = json.load(f)
+    if key in cache:
+        tune_set(h, cache[key])
+        return cache[key]
+    autotune(h, what, stream)
+    text = tune_get(h)
+    cache[key] = text
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + f".{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1)
+    os.replace(tmp, path)
+    return text
 
 
 def profile(h: int, enable: bool) -> None:
