@@ -15,6 +15,15 @@ bytes; the dominant class gives the `roofline` object.  Measured HBM traffic
 (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated with a plain copy) is taken
 from profiles/traffic.md when it was recorded for the current kernel source.
 
+Also measured in the same run (unless --no-multi), at equal 1e-8 relative
+residual per system:
+  * multi_rhs: 32 right-hand sides B = A X* on the 1024^2 rotated anisotropic
+    problem, one block solve against 32 single-system binary64 solves;
+  * batch: 64 independent anisotropic problems (sides 32..512) in one batch
+    against 64 separate binary64 solves.
+Both with the binary64 and the binary32 cycle; kernel choices from the
+project's autotuner.
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -84,6 +93,139 @@ def counted_bytes_per_iteration(lv, nu):
     return b
 
 
+def _timed_ms(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) * 1e3 / steps, out
+
+
+def _kernel_table(mvamg, h, nsolves):
+    kernels = {}
+    for kc, name in enumerate(mvamg.KC_NAMES):
+        nl, ms, by = mvamg.kernel_stats(h, kc)
+        if nl:
+            kernels[name] = dict(launches=nl // nsolves, ms_per_solve=ms / nsolves, us_per_launch=1e3 * ms / nl,
+                                 gbs=by / (ms * 1e-3) / 1e9 if ms > 0 else None)
+    return kernels
+
+
+def bench_multi_rhs(args, torch, mvamg, workloads, tune_cache):
+    """32 right-hand sides through one hierarchy (block solve) against 32
+    single-system solves of the same columns."""
+    from paper_1907_04417_amd import problems
+    t0 = time.time()
+    P, path, st = workloads.load("aniso1024")
+    S = mvamg.Solver(path)
+    tune = mvamg.tuned(S.h, tune_cache)
+    log(f"[bench] multi-rhs aniso1024: levels={st['n']} setup+upload {time.time() - t0:.1f}s tuning {tune}")
+    B, _ = problems.block_rhs(P, 32, seed=workloads.BLOCK_RHS_SEED)
+    Bd = torch.from_numpy(B).cuda()
+    X = torch.zeros_like(Bd)
+    steps = max(1, min(args.steps, 3))
+    res = {}
+    for prec in (64, 32):
+        def blk():
+            X.zero_()
+            return mvamg.pcg_solve_block(S.h, Bd, X, rtol=1e-8, precision=prec)
+        ms, infos = _timed_ms(torch, blk, steps, 1)
+        its = [i.iterations for i in infos]
+        ok = all(i.converged and i.rel_res_true <= 1.01e-8 for i in infos)
+        cols = [Bd[:, c].contiguous() for c in range(32)]
+        xs = torch.zeros(P.n, dtype=torch.float64, device="cuda")
+
+        def singles():
+            for c in range(32):
+                xs.zero_()
+                mvamg.pcg_solve(S.h, cols[c], xs, rtol=1e-8, precision=prec)
+        ms1, _ = _timed_ms(torch, singles, 1, 0)
+        res[prec] = dict(ms=ms, ms_single_total=ms1, its=(min(its), max(its)), ok=ok)
+        log(f"[bench] multi-rhs precision {prec}: {ms:.1f} ms per 32-column solve, 32 single solves {ms1:.1f} ms")
+    mvamg.profile(S.h, True)
+    X.zero_()
+    mvamg.pcg_solve_block(S.h, Bd, X, rtol=1e-8)
+    torch.cuda.synchronize()
+    kernels = _kernel_table(mvamg, S.h, 1)
+    mvamg.profile(S.h, False)
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_solve"])
+    S.close()
+    r64, r32 = res[64], res[32]
+    return {
+        "workload": "aniso1024 x 32: 2-D rotated anisotropic diffusion, 9-point FD, 1024^2 (n = 1,048,576), "
+                    "eps=1e-2, theta=pi/4, <=3 smooth vectors; 32 right-hand sides B = A X*, X* ~ U[-1,1]; rtol 1e-8 "
+                    "per column",
+        "value": 32e3 / r64["ms"], "unit": "solves/s", "ms_per_block_solve": r64["ms"], "nit": r64["its"],
+        "all_converged": r64["ok"] and r32["ok"],
+        "single_fp64_ms_for_32": res[64]["ms_single_total"], "speedup_vs_single_fp64": res[64]["ms_single_total"] / r64["ms"],
+        "fp32_cycle": {"value": 32e3 / r32["ms"], "ms_per_block_solve": r32["ms"], "nit": r32["its"],
+                       "speedup_vs_single_fp64": res[64]["ms_single_total"] / r32["ms"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": kernels[dom]["gbs"] / HBM_PEAK_GBS, "traffic": None},
+        "kernels": kernels,
+    }
+
+
+def bench_batch(args, torch, mvamg, workloads, tune_cache):
+    """64 independent problems in one batch against 64 separate solves."""
+    t0 = time.time()
+    Ps, paths, stats = workloads.load_batch("batch64")
+    BS = mvamg.BatchSolver(paths)
+    tune = mvamg.tuned(BS.h, tune_cache)
+    log(f"[bench] batch64: rows={sum(P.n for P in Ps)} setup+upload {time.time() - t0:.1f}s tuning {tune}")
+    b = torch.from_numpy(np.concatenate([P.b for P in Ps])).cuda()
+    x = torch.zeros_like(b)
+    steps = max(1, min(args.steps, 3))
+    Ss = [mvamg.Solver(p) for p in paths]
+    for S1 in Ss:
+        mvamg.tuned(S1.h, tune_cache)
+    bs = [torch.from_numpy(P.b).cuda() for P in Ps]
+    xs = [torch.zeros_like(v) for v in bs]
+    res = {}
+    for prec in (64, 32):
+        def bat():
+            x.zero_()
+            return mvamg.batch_pcg_solve(BS.h, b, x, rtol=1e-8, precision=prec)
+        ms, infos = _timed_ms(torch, bat, steps, 1)
+        its = [i.iterations for i in infos]
+        ok = all(i.converged and i.rel_res_true <= 1.01e-8 for i in infos)
+
+        def seq():
+            for S1, bb, xx in zip(Ss, bs, xs):
+                xx.zero_()
+                mvamg.pcg_solve(S1.h, bb, xx, rtol=1e-8, precision=prec)
+        ms1, _ = _timed_ms(torch, seq, 1, 1)
+        res[prec] = dict(ms=ms, ms_seq=ms1, its=(min(its), max(its)), ok=ok)
+        log(f"[bench] batch precision {prec}: {ms:.1f} ms per batch, 64 separate solves {ms1:.1f} ms")
+    mvamg.profile(BS.h, True)
+    x.zero_()
+    mvamg.batch_pcg_solve(BS.h, b, x, rtol=1e-8)
+    torch.cuda.synchronize()
+    kernels = _kernel_table(mvamg, BS.h, 1)
+    mvamg.profile(BS.h, False)
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_solve"])
+    for S1 in Ss:
+        S1.close()
+    BS.close()
+    r64, r32 = res[64], res[32]
+    return {
+        "workload": "batch64: 64 independent 2-D rotated anisotropic 9-point problems, sides U{32..512}, eps "
+                    "log-uniform [1e-4, 1], theta U[0, pi), own 3-level hierarchies (<=3 smooth vectors); rtol 1e-8 "
+                    "per problem",
+        "value": 64e3 / r64["ms"], "unit": "problems/s", "ms_per_batch": r64["ms"], "nit": r64["its"],
+        "rows": int(sum(P.n for P in Ps)), "all_converged": r64["ok"] and r32["ok"],
+        "separate_fp64_ms_for_64": r64["ms_seq"], "speedup_vs_separate_fp64": r64["ms_seq"] / r64["ms"],
+        "fp32_cycle": {"value": 64e3 / r32["ms"], "ms_per_batch": r32["ms"], "nit": r32["its"],
+                       "speedup_vs_separate_fp64": r64["ms_seq"] / r32["ms"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": kernels[dom]["gbs"] / HBM_PEAK_GBS, "traffic": None},
+        "kernels": kernels,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +234,7 @@ def main():
     ap.add_argument("--workload", default="jump128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile-pass", action="store_true")
+    ap.add_argument("--no-multi", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path; "
@@ -108,6 +251,8 @@ def main():
     log(f"[bench] setup {args.workload}: n={P.n} nnz={P.nnz} levels={st['n']} opc={st['opc']:.3f} "
         f"({time.time() - t0:.1f}s)")
     S = mvamg.Solver(path)
+    tune_cache = os.path.join(ROOT, "gpurun_out", "tune_cache.json")
+    log(f"[bench] tuning: {mvamg.tuned(S.h, tune_cache)}")
     stream = torch.cuda.current_stream()
     b = torch.from_numpy(P.b).cuda()
     x = torch.zeros_like(b)
@@ -185,6 +330,11 @@ def main():
                           f"core; the oracle's own coarsest factorisation, {tf:.1f} s, is setup and not counted)")
         log(f"[bench] oracle: {tcpu:.1f} s/solve ({nit_c} iterations)")
 
+    multi = batch = None
+    if not args.no_multi:
+        multi = bench_multi_rhs(args, torch, mvamg, workloads, tune_cache)
+        batch = bench_batch(args, torch, mvamg, workloads, tune_cache)
+
     r32 = results[32]
     out = {
         "metric": "AMG-PCG solves/s to 1e-8 rel. residual (FP64 cycle)",
@@ -211,6 +361,8 @@ def main():
                   "ms_per_step": r32["ms"], "nit": r32["nit"], "speedup_vs_fp64": r64["ms"] / r32["ms"],
                   "rel_res_true": r32["rel_res_true"],
                   "err_vs_fp64_solution": float(np.abs(r32["x"] - r64["x"]).max() / np.abs(r64["x"]).max())},
+        "multi_rhs": multi,
+        "batch": batch,
     }
     print(json.dumps(out), flush=True)
 

@@ -264,7 +264,9 @@ struct TransferLayout {
   std::vector<double> U;
 };
 
-inline void build_level_layout(const HostLevel& L, LevelLayout& Y) {
+// rowprob (optional, file-row order): the problem of every row when the
+// level belongs to a batch; sliced-ELL slabs are then cut where it changes.
+inline void build_level_layout(const HostLevel& L, LevelLayout& Y, const std::vector<int>* rowprob = nullptr) {
   const int n = L.n;
   Y.n = n;
   if ((int)L.order.size() != n) throw Error(-2, "smoother order has wrong length");
@@ -362,10 +364,16 @@ inline void build_level_layout(const HostLevel& L, LevelLayout& Y) {
     Y.sslab.assign(ns + 1, 0);
     for (int c = 0; c < ns; ++c) {
       const int r0 = Y.gstart[Y.sgrp[c]], r1 = Y.gstart[Y.sgrp[c + 1]];
-      for (int b = r0; b < r1; b += 64) {
+      for (int b = r0; b < r1;) {
         Slab s;
         s.row0 = b;
         s.nrows = std::min(64, r1 - b);
+        if (rowprob)
+          for (int q = 1; q < s.nrows; ++q)
+            if ((*rowprob)[Y.perm[b + q]] != (*rowprob)[Y.perm[b]]) {
+              s.nrows = q;
+              break;
+            }
         s.width = 0;
         for (int p = b; p < b + s.nrows; ++p) {
           const int i = Y.perm[p];
@@ -373,6 +381,7 @@ inline void build_level_layout(const HostLevel& L, LevelLayout& Y) {
         }
         s.off = 0;
         Y.slabs.push_back(s);
+        b += s.nrows;
       }
       Y.sslab[c + 1] = (int)Y.slabs.size();
     }

@@ -36,6 +36,18 @@ enum Scalar {
 
 enum RedMode { M_STORE_RR = 0, M_PQ = 1, M_RHO0 = 2, M_RZ = 3, M_RZ_FLEX = 4, M_STORE_R0 = 5, M_NONE = 6 };
 
+// Batches of independent problems: a work unit (slab, row, aggregate) of
+// problem q is skipped when act is given and act[q * S_NSCAL] == 0 (the
+// problem has stopped; act points at its per-problem S_ACT flag).
+struct Skip {
+  const int* uprob;   // problem of each work unit
+  const double* act;  // nullptr: nothing is skipped
+};
+
+__device__ __forceinline__ bool skipped(const Skip& k, int unit) {
+  return k.act != nullptr && k.act[(size_t)k.uprob[unit] * S_NSCAL] == 0.0;
+}
+
 struct Red {
   double* part;  // one slot per block and value (2 * grid)
 };
@@ -192,9 +204,10 @@ __global__ __launch_bounds__(kBlock) void k_xpay(int n, const double* __restrict
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ slabs, int s0, int s1,
                                                     const int* __restrict__ col, const T* __restrict__ val,
-                                                    const T* __restrict__ diag, const T* __restrict__ r, T* x) {
+                                                    const T* __restrict__ diag, const T* __restrict__ r, T* x,
+                                                    Skip sk) {
   const int s = s0 + blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  if (s >= s1) return;
+  if (s >= s1 || skipped(sk, s)) return;
   const int lane = threadIdx.x & 63;
   const Slab sl = slabs[s];
   if (lane >= sl.nrows) return;
@@ -225,9 +238,9 @@ __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ sla
 // still zero), every other row is zeroed.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_zero_stage0_point(int n, int rows0, const T* __restrict__ diag,
-                                                              const T* __restrict__ r, T* __restrict__ x) {
+                                                              const T* __restrict__ r, T* __restrict__ x, Skip sk) {
   for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock)
-    x[p] = (p < rows0) ? r[p] / diag[p] : T(0);
+    if (!skipped(sk, p)) x[p] = (p < rows0) ? r[p] / diag[p] : T(0);
 }
 
 // s = r - A x (MODE 0), y = A x with sum x.y (MODE 1, binary64 only), or y = A x (MODE 2)
@@ -235,11 +248,11 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ slabs, int nslabs,
                                                        const int* __restrict__ col, const T* __restrict__ val,
                                                        const T* __restrict__ diag, const T* __restrict__ r,
-                                                       const T* __restrict__ x, T* __restrict__ s, Red red) {
+                                                       const T* __restrict__ x, T* __restrict__ s, Red red, Skip sk) {
   const int sidx = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   double dsum = 0.0;
-  if (sidx < nslabs) {
+  if (sidx < nslabs && !skipped(sk, sidx)) {
     const Slab sl = slabs[sidx];
     if (lane < sl.nrows) {
       const int p = sl.row0 + lane;
@@ -495,9 +508,9 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nagg, const int* __rest
                                                      const T* __restrict__ U, const T* __restrict__ s,
                                                      T* __restrict__ rc, const int* __restrict__ cgrp, int ng0,
                                                      const int* __restrict__ cdboff, const T* __restrict__ cdblk,
-                                                     const T* __restrict__ cdl1, T* __restrict__ xc) {
+                                                     const T* __restrict__ cdl1, T* __restrict__ xc, Skip sk) {
   const int a = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  if (a >= nagg) return;
+  if (a >= nagg || skipped(sk, a)) return;
   const int lane = threadIdx.x & 63;
   const int m0 = aptr[a], na = aptr[a + 1] - m0, k = kk[a];
   const T* Ua = U + uoff[a];
@@ -581,8 +594,9 @@ __global__ __launch_bounds__(kBlock) void k_prolong(int nagg, const int* __restr
 template <typename T, int KMAX>
 __global__ __launch_bounds__(kBlock) void k_prolong_rows(int n, const int* __restrict__ cinfo,
                                                          const T* __restrict__ Urow, const T* __restrict__ xc,
-                                                         T* __restrict__ x) {
+                                                         T* __restrict__ x, Skip sk) {
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    if (skipped(sk, i)) continue;
     const int ci = cinfo[i];
     const int c0 = ci >> 3, k = (ci & 7) + 1;
     T t = T(0);

@@ -684,14 +684,26 @@ __global__ __launch_bounds__(kBlock) void k_gemv_batch(int n, const int* __restr
 
 // Problem p owns the entries idx[j], j in [poff[p], poff[p+1]), of the level-0
 // vectors.  Grid (chunks, problems); partials at part[(v * nprob + p) *
-// gridDim.x + chunk].
+// gridDim.x + chunk].  With act given, the blocks of a stopped problem
+// (act[p * S_NSCAL] == 0) write zero partials and touch nothing else.
+__device__ __forceinline__ bool pstopped(const double* act, int p) {
+  return act != nullptr && act[(size_t)p * S_NSCAL] == 0.0;
+}
+
 template <int NV>
 __global__ __launch_bounds__(kBlock) void k_pdot(const int* __restrict__ poff, const int* __restrict__ idx,
                                                  const double* __restrict__ a, const double* __restrict__ b,
                                                  const double* __restrict__ c, const double* __restrict__ d,
-                                                 double* __restrict__ part) {
+                                                 double* __restrict__ part, const double* __restrict__ act) {
   __shared__ double lds[4];
   const int p = blockIdx.y, j1 = poff[p + 1];
+  if (pstopped(act, p)) {
+    if (threadIdx.x == 0) {
+      part[(size_t)p * gridDim.x + blockIdx.x] = 0.0;
+      if (NV > 1) part[(size_t)(gridDim.y + p) * gridDim.x + blockIdx.x] = 0.0;
+    }
+    return;
+  }
   double s0 = 0.0, s1 = 0.0;
   for (int j = poff[p] + blockIdx.x * kBlock + threadIdx.x; j < j1; j += gridDim.x * kBlock) {
     const int i = idx[j];
@@ -709,11 +721,15 @@ __global__ __launch_bounds__(kBlock) void k_pdot(const int* __restrict__ poff, c
 __global__ __launch_bounds__(kBlock) void k_paxpy2_dot(const int* __restrict__ poff, const int* __restrict__ idx,
                                                        const double* __restrict__ scal, const double* __restrict__ pv,
                                                        const double* __restrict__ q, double* __restrict__ x,
-                                                       double* __restrict__ r, double* __restrict__ part) {
+                                                       double* __restrict__ r, double* __restrict__ part, int skip) {
   __shared__ double lds[4];
   const int p = blockIdx.y, j1 = poff[p + 1];
   const double alpha = scal[p * S_NSCAL + S_ALPHA];
   const bool act = scal[p * S_NSCAL + S_ACT] != 0.0;
+  if (skip && !act) {
+    if (threadIdx.x == 0) part[(size_t)p * gridDim.x + blockIdx.x] = 0.0;
+    return;
+  }
   double s = 0.0;
   for (int j = poff[p] + blockIdx.x * kBlock + threadIdx.x; j < j1; j += gridDim.x * kBlock) {
     const int i = idx[j];
@@ -731,8 +747,9 @@ __global__ __launch_bounds__(kBlock) void k_paxpy2_dot(const int* __restrict__ p
 
 __global__ __launch_bounds__(kBlock) void k_pxpay(const int* __restrict__ poff, const int* __restrict__ idx,
                                                   const double* __restrict__ scal, const double* __restrict__ z,
-                                                  double* __restrict__ pv) {
+                                                  double* __restrict__ pv, int skip) {
   const int p = blockIdx.y, j1 = poff[p + 1];
+  if (skip && scal[p * S_NSCAL + S_ACT] == 0.0) return;
   const double beta = scal[p * S_NSCAL + S_BETA];
   for (int j = poff[p] + blockIdx.x * kBlock + threadIdx.x; j < j1; j += gridDim.x * kBlock) {
     const int i = idx[j];

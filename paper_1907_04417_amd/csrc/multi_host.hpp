@@ -295,6 +295,11 @@ struct MultiOps {
   virtual void true_resid(hipStream_t st) = 0;  // q = b - A x, per-system q.q (MM_STORE_TRR)
   virtual void dot(const double* a, const double* b, const double* c, const double* d, int nv, int mode,
                    hipStream_t st) = 0;
+  // the dot products inside an iteration (stopped systems may be skipped)
+  virtual void dot_iter(const double* a, const double* b, const double* c, const double* d, int nv, int mode,
+                        hipStream_t st) {
+    dot(a, b, c, d, nv, mode, st);
+  }
   virtual void cycle(int precision, int smoother, hipStream_t st) = 0;  // z = B r
   virtual void copy_zp(hipStream_t st) = 0;
   virtual void spmv_pq(hipStream_t st) = 0;    // q = A p, per-system p.q (MM_PQ)
@@ -313,9 +318,9 @@ void multi_step_a(MultiOps& O, hipStream_t st) {
 void multi_step_b(MultiOps& O, int precision, int smoother, hipStream_t st) {
   O.cycle(precision, smoother, st);
   if (precision == 32)
-    O.dot(O.z, O.r, O.z, O.q, 2, MM_RZ_FLEX, st);
+    O.dot_iter(O.z, O.r, O.z, O.q, 2, MM_RZ_FLEX, st);
   else
-    O.dot(O.z, O.r, nullptr, nullptr, 1, MM_RZ, st);
+    O.dot_iter(O.z, O.r, nullptr, nullptr, 1, MM_RZ, st);
   O.xpay(st);
 }
 
@@ -556,6 +561,9 @@ struct BlockOps : MultiOps {
 
 // ------------------------------------------------- batch of problems
 
+// Inside the CG iterations the work of problems that have stopped is skipped
+// (level-0 kernels and the per-problem vector kernels); their iterates and
+// residuals stay as they were, exactly as for a problem solved on its own.
 struct BatchOps : MultiOps {
   explicit BatchOps(mvamg_hier* hh) {
     h = hh;
@@ -567,6 +575,12 @@ struct BatchOps : MultiOps {
     p = h->p;
     q = h->q;
   }
+  struct SkipScope {  // level-0 kernels skip stopped problems while alive
+    mvamg_hier* h;
+    explicit SkipScope(mvamg_hier* hh) : h(hh) { h->skip_act = h->mb.scal + S_ACT; }
+    ~SkipScope() { h->skip_act = nullptr; }
+  };
+  const double* act() const { return h->mb.scal + S_ACT; }
   dim3 pgrid() const { return dim3(h->pchunks, h->nprob); }
   void load(const double* b, const double* x, hipStream_t st) override {
     k_gather<<<grid_for(h->n), kBlock, 0, st>>>(h->n, h->perm0, b, h->b);
@@ -582,33 +596,47 @@ struct BatchOps : MultiOps {
     ::resid<double, 0>(h, 0, h->lv[0], h->b, h->x, q, M_NONE, st);
     dot(q, q, nullptr, nullptr, 1, MM_STORE_TRR, st);
   }
-  void dot(const double* a, const double* b, const double* c, const double* d, int nv, int mode,
-           hipStream_t st) override {
+  void pdot(const double* a, const double* b, const double* c, const double* d, int nv, int mode,
+            const double* skip, hipStream_t st) {
     if (nv == 1) {
-      k_pdot<1><<<pgrid(), kBlock, 0, st>>>(h->poff, h->iperm0, a, b, nullptr, nullptr, h->mb.part);
+      k_pdot<1><<<pgrid(), kBlock, 0, st>>>(h->poff, h->iperm0, a, b, nullptr, nullptr, h->mb.part, skip);
       k_mfinish<1><<<h->nprob, kBlock, 0, st>>>(h->nprob, h->pchunks, h->mb.part, h->mb.scal, mode);
     } else {
-      k_pdot<2><<<pgrid(), kBlock, 0, st>>>(h->poff, h->iperm0, a, b, c, d, h->mb.part);
+      k_pdot<2><<<pgrid(), kBlock, 0, st>>>(h->poff, h->iperm0, a, b, c, d, h->mb.part, skip);
       k_mfinish<2><<<h->nprob, kBlock, 0, st>>>(h->nprob, h->pchunks, h->mb.part, h->mb.scal, mode);
     }
     LAUNCHCHECK("pdot");
   }
-  void cycle(int precision, int smoother, hipStream_t st) override { apply_B(h, r, z, precision, smoother, st); }
+  void dot(const double* a, const double* b, const double* c, const double* d, int nv, int mode,
+           hipStream_t st) override {
+    pdot(a, b, c, d, nv, mode, nullptr, st);
+  }
+  void dot_iter(const double* a, const double* b, const double* c, const double* d, int nv, int mode,
+                hipStream_t st) override {
+    pdot(a, b, c, d, nv, mode, act(), st);
+  }
+  void cycle(int precision, int smoother, hipStream_t st) override {
+    SkipScope sk(h);
+    apply_B(h, r, z, precision, smoother, st);
+  }
   void copy_zp(hipStream_t st) override {
     k_copy<double><<<grid_elem(h->n), kBlock, 0, st>>>(h->n, z, p);
     LAUNCHCHECK("copy");
   }
   void spmv_pq(hipStream_t st) override {
-    ::resid<double, 2>(h, 0, h->lv[0], nullptr, p, q, M_NONE, st);
-    dot(p, q, nullptr, nullptr, 1, MM_PQ, st);
+    {
+      SkipScope sk(h);
+      ::resid<double, 2>(h, 0, h->lv[0], nullptr, p, q, M_NONE, st);
+    }
+    dot_iter(p, q, nullptr, nullptr, 1, MM_PQ, st);
   }
   void axpy2(hipStream_t st) override {
-    k_paxpy2_dot<<<pgrid(), kBlock, 0, st>>>(h->poff, h->iperm0, h->mb.scal, p, q, h->x, r, h->mb.part);
+    k_paxpy2_dot<<<pgrid(), kBlock, 0, st>>>(h->poff, h->iperm0, h->mb.scal, p, q, h->x, r, h->mb.part, 1);
     k_mfinish<1><<<h->nprob, kBlock, 0, st>>>(h->nprob, h->pchunks, h->mb.part, h->mb.scal, MM_STORE_RR);
     LAUNCHCHECK("paxpy2");
   }
   void xpay(hipStream_t st) override {
-    k_pxpay<<<pgrid(), kBlock, 0, st>>>(h->poff, h->iperm0, h->mb.scal, z, p);
+    k_pxpay<<<pgrid(), kBlock, 0, st>>>(h->poff, h->iperm0, h->mb.scal, z, p, 1);
     LAUNCHCHECK("pxpay");
   }
 };

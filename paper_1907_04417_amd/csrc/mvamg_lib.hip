@@ -85,6 +85,9 @@ struct DevLevel {
   // work vectors
   double *r = nullptr, *x = nullptr, *s = nullptr;
   float *r32 = nullptr, *x32 = nullptr, *s32 = nullptr;
+  // batch, level 0: problem of every slab and of every row (smoother order)
+  int* slabprob = nullptr;
+  int* rowprob = nullptr;
   // block work vectors (n x 32, allocated on the first block call)
   double *br = nullptr, *bx = nullptr, *bs = nullptr;
   float *br32 = nullptr, *bx32 = nullptr, *bs32 = nullptr;
@@ -94,6 +97,7 @@ struct DevTransfer {
   int nagg = 0;
   int *aptr = nullptr, *arows = nullptr, *uoff = nullptr, *cst = nullptr, *kk = nullptr;
   int* cgrp = nullptr;  // group of each aggregate on the next level (if that level is smoothed)
+  int* aprob = nullptr; // batch, level 0: problem of every aggregate
   int nf = 0, kmax = 1;  // fine rows, widest block
   int64_t nu = 0;        // entries of the U blocks
   int* cinfo = nullptr;  // per fine row: 8 * first coarse row + (k - 1)
@@ -151,6 +155,9 @@ struct mvamg_hier {
   std::vector<int> h_poff;
   int* poff = nullptr;
   int* iperm0 = nullptr;
+  // while set (batch CG iterations), level-0 kernels skip the work units of
+  // problems whose S_ACT flag (at skip_act + S_NSCAL * problem) is zero
+  const double* skip_act = nullptr;
   // several systems at once
   MultiBufs mb;
   bool blk_ready = false;
@@ -212,6 +219,15 @@ struct mvamg_hier {
 namespace {
 
 Red mkred(mvamg_hier* h) { return Red{h->part}; }
+
+enum SkipUnit { SKIP_SLAB, SKIP_ROW, SKIP_AGG };
+
+Skip lskip(const mvamg_hier* h, int l, SkipUnit u) {
+  if (l != 0 || !h->skip_act) return Skip{nullptr, nullptr};
+  const int* up = (u == SKIP_SLAB) ? h->lv[0].slabprob : (u == SKIP_ROW) ? h->lv[0].rowprob : h->tr[0].aprob;
+  if (!up) return Skip{nullptr, nullptr};
+  return Skip{up, h->skip_act};
+}
 
 hipEvent_t take_event(mvamg_hier* h) {
   if (!h->ev_pool.empty()) {
@@ -361,7 +377,8 @@ void gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, 
     const int s0 = L.h_sslab[c], s1 = L.h_sslab[c + 1];
     if (s1 <= s0) return;
     const int grid = (s1 - s0 + 3) / 4;
-    klaunch(h, kc, by, k_gs_sell<T>, grid, kBlock, st, L.slabs, s0, s1, L.col, lval<T>(L), ldblk<T>(L), r, x);
+    klaunch(h, kc, by, k_gs_sell<T>, grid, kBlock, st, L.slabs, s0, s1, L.col, lval<T>(L), ldblk<T>(L), r, x,
+            lskip(h, l, SKIP_SLAB));
   } else {
     const int g0 = L.h_sgrp[c], g1 = L.h_sgrp[c + 1];
     if (g1 <= g0) return;
@@ -381,7 +398,8 @@ void zero_stage0(mvamg_hier* h, int l, const DevLevel& L, const T* r, T* x, hipS
   const int kc = (l == 0) ? MVAMG_KC_SMOOTH_FINE : MVAMG_KC_SMOOTH_COARSE;
   const double by = (double)L.n * sizeof(T) + (double)L.stage_rows[0] * (2 * sizeof(T));
   if (L.sell) {
-    klaunch(h, kc, by, k_zero_stage0_point<T>, grid_elem(L.n), kBlock, st, L.n, L.rows0, ldblk<T>(L), r, x);
+    klaunch(h, kc, by, k_zero_stage0_point<T>, grid_elem(L.n), kBlock, st, L.n, L.rows0, ldblk<T>(L), r, x,
+            lskip(h, l, SKIP_ROW));
   } else {
     klaunch(h, kc, by, k_zero_stage0_grp<T>, grid_for(L.ng), kBlock, st, L.ng, L.h_sgrp[1], L.gstart, L.dboff, ldblk<T>(L), r, x);
   }
@@ -396,10 +414,10 @@ void resid(mvamg_hier* h, int l, const DevLevel& L, const T* r, const T* x, T* s
   const Red red = mkred(h);
   const int kc = MODE != 0 ? MVAMG_KC_SPMV : MVAMG_KC_RESIDUAL;
   const double by = (double)L.nnz * (sizeof(T) + 4) + 4.0 * (L.n + 1) + (double)L.n * sizeof(T) * (MODE != 0 ? 2 : 3);
-  (void)l;
   if (L.sell) {
     const int grid = (L.nslabs + 3) / 4;
-    klaunch(h, kc, by, k_resid_sell<T, MODE>, grid, kBlock, st, L.slabs, L.nslabs, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red);
+    klaunch(h, kc, by, k_resid_sell<T, MODE>, grid, kBlock, st, L.slabs, L.nslabs, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red,
+            lskip(h, l, SKIP_SLAB));
   } else {
     const int grid = (L.ng + 3) / 4;
     switch (L.G) {
@@ -472,27 +490,28 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   if (!next_smoothed) {
     klaunch(h, MVAMG_KC_RESTRICT, tby, k_restrict<T, 0>, tg, kBlock, st, P.nagg, P.aptr, P.arows, P.uoff, P.cst,
             P.kk, tU<T>(P), s, rc, (const int*)nullptr, 0, (const int*)nullptr, (const T*)nullptr,
-            (const T*)nullptr, (T*)nullptr);
+            (const T*)nullptr, (T*)nullptr, lskip(h, l, SKIP_AGG));
   } else if (smoother == MVAMG_SMOOTH_GS) {
     klaunch(h, MVAMG_KC_RESTRICT, tby + (double)C.n * sizeof(T), k_restrict<T, 1>, tg, kBlock, st, P.nagg, P.aptr,
             P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc, P.cgrp, C.h_sgrp[1], C.dboff, ldblk<T>(C),
-            (const T*)nullptr, xc);
+            (const T*)nullptr, xc, lskip(h, l, SKIP_AGG));
   } else {
     klaunch(h, MVAMG_KC_RESTRICT, tby + (double)C.n * sizeof(T), k_restrict<T, 2>, tg, kBlock, st, P.nagg, P.aptr,
             P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc, (const int*)nullptr, 0, (const int*)nullptr,
-            (const T*)nullptr, ldl1<T>(C), xc);
+            (const T*)nullptr, ldl1<T>(C), xc, lskip(h, l, SKIP_AGG));
   }
   LAUNCHCHECK("restrict");
   vcycle<T>(h, l + 1, rc, xc, smoother, st, next_smoothed);
   {
     const int pg = grid_elem(P.nf);
     const double pby = (double)P.nu * sizeof(T) + (double)L.n * (4 + 2 * sizeof(T)) + (double)C.n * sizeof(T);
+    const Skip sk = lskip(h, l, SKIP_ROW);
     switch (P.kmax) {
-      case 1: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 1>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
-      case 2: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 2>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
+      case 1: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 1>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x, sk); break;
+      case 2: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 2>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x, sk); break;
       case 3:
-      case 4: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 4>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
-      default: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 8>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
+      case 4: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 4>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x, sk); break;
+      default: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 8>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x, sk); break;
     }
   }
   LAUNCHCHECK("prolong");
@@ -749,7 +768,8 @@ void factor_block(mvamg_hier* h, const HostLevel& C, int np, double* M, double* 
 
 // Device copy of a hierarchy; cblk lists the diagonal blocks of its
 // coarsest level (one for a single problem, one per problem of a batch).
-std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<const HostLevel*>& cblk, hipStream_t st) {
+std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<const HostLevel*>& cblk, hipStream_t st,
+                                        const std::vector<int>* rowprob0 = nullptr) {
   std::unique_ptr<mvamg_hier> h;
   try {
     if (H.nl < 2) throw Error(MVAMG_ERR_ARG, "hierarchy needs at least two levels");
@@ -768,7 +788,7 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
     }
     // ---- layouts
     std::vector<LevelLayout> Y(H.nl - 1);
-    for (int l = 0; l + 1 < H.nl; ++l) build_level_layout(H.lv[l], Y[l]);
+    for (int l = 0; l + 1 < H.nl; ++l) build_level_layout(H.lv[l], Y[l], l == 0 ? rowprob0 : nullptr);
     h->lv.resize(H.nl);
     h->tr.resize(H.nl - 1);
     int maxgrid = 2048;
@@ -937,6 +957,23 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
         D.aoff = h->upload_vec(aoff, st);
       }
     }
+    // ---- batch: problem of every level-0 slab, row and aggregate
+    if (rowprob0) {
+      const LevelLayout& y = Y[0];
+      DevLevel& L0 = h->lv[0];
+      std::vector<int> rp(y.n);
+      for (int p = 0; p < y.n; ++p) rp[p] = (*rowprob0)[y.perm[p]];
+      L0.rowprob = h->upload_vec(rp, st);
+      if (y.sell) {
+        std::vector<int> sp(y.slabs.size());
+        for (size_t q = 0; q < y.slabs.size(); ++q) sp[q] = rp[y.slabs[q].row0];
+        L0.slabprob = h->upload_vec(sp, st);
+      }
+      const HostLevel& F = H.lv[0];
+      std::vector<int> ap(F.aptr.size() - 1);
+      for (size_t a = 0; a + 1 < F.aptr.size(); ++a) ap[a] = (*rowprob0)[F.arows[F.aptr[a]]];
+      h->tr[0].aprob = h->upload_vec(ap, st);
+    }
     // ---- level-0 extras and CG state
     {
       const int n = h->n;
@@ -1070,7 +1107,9 @@ mvamg_status mvamg_batch_upload(const mvamg_hier_host* const* hs, int nprob, voi
     if (U.nl < 2) throw Error(MVAMG_ERR_ARG, "hierarchy needs at least two levels");
     std::vector<const HostLevel*> cb;
     for (const HostHier* H : Hs) cb.push_back(&H->lv[H->nl - 1]);
-    std::unique_ptr<mvamg_hier> h = upload_hier(U, cb, st);
+    std::vector<int> rowprob0;
+    for (int p = 0; p < nprob; ++p) rowprob0.insert(rowprob0.end(), Hs[p]->lv[0].n, p);
+    std::unique_ptr<mvamg_hier> h = upload_hier(U, cb, st, &rowprob0);
     h->nprob = nprob;
     h->h_poff.assign(nprob + 1, 0);
     int maxn = 1;

@@ -97,7 +97,8 @@ void tune_batch_chunks(mvamg_hier* h, hipStream_t st, std::string& rep) {
   double tbest = 1e30;
   for (int c : kChunkCandidates) {
     const double t = time_ms(st, 10, [&]() {
-      k_pdot<1><<<dim3(c, h->nprob), kBlock, 0, st>>>(h->poff, h->iperm0, h->r, h->r, nullptr, nullptr, h->mb.part);
+      k_pdot<1><<<dim3(c, h->nprob), kBlock, 0, st>>>(h->poff, h->iperm0, h->r, h->r, nullptr, nullptr, h->mb.part,
+                                                      nullptr);
       k_mfinish<1><<<h->nprob, kBlock, 0, st>>>(h->nprob, c, h->mb.part, h->mb.scal, MM_STORE_TRR);
     });
     rep += "chunks " + std::to_string(c) + ": " + fmt_us(t) + " us; ";

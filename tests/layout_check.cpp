@@ -1,0 +1,147 @@
+// Host-only check of the library's device-layout construction (no GPU): reads
+// hierarchy files with the library's own parser, builds the layouts the
+// upload would build (optionally for the block-diagonal union of several
+// files, as a batch upload does) and checks their invariants.  Built by the
+// CPU test suite with AddressSanitizer.
+//
+// usage: layout_check [--batch] file...   prints "ok <summary>" or fails
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hier_host.hpp"
+
+using namespace mvamg;
+
+static int fails = 0;
+#define CHECK(c, msg)                                                 \
+  do {                                                                \
+    if (!(c)) {                                                       \
+      std::fprintf(stderr, "check failed: %s (%s)\n", msg, #c);       \
+      if (++fails > 20) return 1;                                     \
+    }                                                                 \
+  } while (0)
+
+static int check_level(const HostLevel& L, const LevelLayout& Y, const std::vector<int>* rowprob) {
+  const int n = L.n;
+  CHECK((int)Y.perm.size() == n && (int)Y.iperm.size() == n, "permutation size");
+  for (int p = 0; p < n; ++p) CHECK(Y.iperm[Y.perm[p]] == p, "perm/iperm inverse");
+  const int ng = (int)Y.gstart.size() - 1, ns = (int)Y.sgrp.size() - 1;
+  CHECK(Y.gstart[0] == 0 && Y.gstart[ng] == n, "groups cover the rows");
+  CHECK(Y.sgrp[0] == 0 && Y.sgrp[ns] == ng, "stages cover the groups");
+  // every row's stored entries (off-group + diagonal block) reproduce its CSR row sum and |.| sum
+  std::vector<int> grp(n);
+  for (int g = 0; g < ng; ++g)
+    for (int p = Y.gstart[g]; p < Y.gstart[g + 1]; ++p) grp[p] = g;
+  std::vector<double> s1(n, 0.0), s2(n, 0.0);
+  for (int g = 0; g < ng; ++g) {
+    const int k = Y.gstart[g + 1] - Y.gstart[g];
+    for (int a = 0; a < k; ++a)
+      for (int b = 0; b < k; ++b) {
+        const double v = Y.dblk[Y.dboff[g] + a * k + b];
+        s1[Y.gstart[g] + a] += v;
+        s2[Y.gstart[g] + a] += std::fabs(v);
+      }
+  }
+  if (Y.sell) {
+    CHECK((int)Y.sslab.size() == ns + 1, "stage slab ranges");
+    for (int c = 0; c < ns; ++c) {
+      int next = Y.gstart[Y.sgrp[c]];
+      for (int q = Y.sslab[c]; q < Y.sslab[c + 1]; ++q) {
+        const Slab& sl = Y.slabs[q];
+        CHECK(sl.row0 == next && sl.nrows >= 1 && sl.nrows <= 64, "slabs tile the stage in order");
+        next += sl.nrows;
+        if (rowprob)
+          for (int i = 1; i < sl.nrows; ++i)
+            CHECK((*rowprob)[Y.perm[sl.row0 + i]] == (*rowprob)[Y.perm[sl.row0]], "slab inside one problem");
+        for (int i = 0; i < sl.nrows; ++i) {
+          const int p = sl.row0 + i, r = Y.perm[p];
+          CHECK(sl.width >= L.rp[r + 1] - L.rp[r] - 1, "slab width covers the row");
+          for (int j = 0; j < sl.width; ++j) {
+            const int64_t at = (int64_t)sl.off + (int64_t)j * 64 + i;
+            CHECK(at >= 0 && at < (int64_t)Y.col.size(), "slab entry in range");
+            CHECK(Y.col[at] >= 0 && Y.col[at] < n, "slab column in range");
+            s1[p] += Y.val[at];
+            s2[p] += std::fabs(Y.val[at]);
+          }
+        }
+      }
+      CHECK(next == Y.gstart[Y.sgrp[c + 1]], "slabs end with the stage");
+    }
+  } else {
+    CHECK((int)Y.rowptr.size() == n + 1 && Y.rowptr[n] == (int)Y.col.size(), "grouped CSR");
+    for (int p = 0; p < n; ++p)
+      for (int e = Y.rowptr[p]; e < Y.rowptr[p + 1]; ++e) {
+        const int q = Y.col[e];
+        CHECK(q >= 0 && q < n && grp[q] != grp[p], "off-group entry");
+        s1[p] += Y.val[e];
+        s2[p] += std::fabs(Y.val[e]);
+      }
+  }
+  for (int p = 0; p < n; ++p) {
+    const int r = Y.perm[p];
+    double t1 = 0.0, t2 = 0.0;
+    for (int e = L.rp[r]; e < L.rp[r + 1]; ++e) {
+      t1 += L.v[e];
+      t2 += std::fabs(L.v[e]);
+    }
+    CHECK(std::fabs(s1[p] - t1) <= 1e-12 * (t2 + 1e-300) + 1e-300 && std::fabs(s2[p] - t2) <= 1e-12 * t2,
+          "stored entries reproduce the row");
+  }
+  return 0;
+}
+
+int main(int argc, char** argv) {
+  bool batch = false;
+  std::vector<std::string> files;
+  for (int i = 1; i < argc; ++i) {
+    if (std::strcmp(argv[i], "--batch") == 0)
+      batch = true;
+    else
+      files.push_back(argv[i]);
+  }
+  if (files.empty()) return 2;
+  try {
+    std::vector<HostHier> Hs;
+    for (const std::string& f : files) Hs.push_back(read_hierarchy_file(f.c_str()));
+    std::vector<HostHier> todo;
+    std::vector<std::vector<int>> rowprob(1);
+    if (batch) {
+      std::vector<const HostHier*> ptr;
+      for (const HostHier& H : Hs) ptr.push_back(&H);
+      todo.push_back(union_hierarchy(ptr));
+      for (size_t p = 0; p < Hs.size(); ++p) rowprob[0].insert(rowprob[0].end(), Hs[p].lv[0].n, (int)p);
+      // the union is block diagonal: rows of problem p only couple rows of problem p
+      const HostLevel& U0 = todo[0].lv[0];
+      for (int i = 0; i < U0.n; ++i)
+        for (int e = U0.rp[i]; e < U0.rp[i + 1]; ++e) CHECK(rowprob[0][U0.ci[e]] == rowprob[0][i], "union is block diagonal");
+    } else {
+      todo = Hs;
+    }
+    for (const HostHier& H : todo) {
+      std::vector<LevelLayout> Y(H.nl - 1);
+      for (int l = 0; l + 1 < H.nl; ++l) {
+        build_level_layout(H.lv[l], Y[l], (batch && l == 0) ? &rowprob[0] : nullptr);
+        if (check_level(H.lv[l], Y[l], (batch && l == 0) ? &rowprob[0] : nullptr)) return 1;
+      }
+      for (int l = 0; l + 1 < H.nl; ++l) {
+        TransferLayout T;
+        build_transfer_layout(H.lv[l], Y[l], (l + 2 < H.nl) ? &Y[l + 1] : nullptr, T);
+        int64_t cover = 0;
+        for (int a = 0; a < T.nagg; ++a) {
+          CHECK(T.kk[a] >= 1 && T.kk[a] <= kKmax, "block width");
+          CHECK(T.cst[a] >= 0 && T.cst[a] + T.kk[a] <= H.lv[l + 1].n, "coarse rows in range");
+          cover += T.kk[a];
+        }
+        CHECK(cover == H.lv[l + 1].n, "aggregates cover the coarse level");
+      }
+      std::printf("ok levels=%d n0=%d sell0=%d\n", H.nl, H.lv[0].n, H.nl > 1 ? (int)Y[0].sell : -1);
+    }
+  } catch (const std::exception& e) {
+    std::fprintf(stderr, "error: %s\n", e.what());
+    return 3;
+  }
+  return fails ? 1 : 0;
+}

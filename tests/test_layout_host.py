@@ -1,0 +1,48 @@
+"""Host logic of the library's device layout (no GPU): the layout builder of
+csrc/hier_host.hpp, compiled with g++ under AddressSanitizer, is run on
+hierarchy files (single problems and the union of a batch) and checks its
+invariants (tests/layout_check.cpp)."""
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def checker(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("lc") / "layout_check")
+    src = os.path.join(ROOT, "tests", "layout_check.cpp")
+    inc = os.path.join(ROOT, "paper_1907_04417_amd", "csrc")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                    "-I", inc, src, "-o", exe], check=True)
+    return exe
+
+
+def _run(exe, *args):
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    r = subprocess.run([exe, *args], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.startswith("ok"), r.stdout
+    return r.stdout
+
+
+def test_layout_of_single_hierarchies(checker, tiny_hier, small3d_hier):
+    for _, path, _ in (tiny_hier, small3d_hier):
+        _run(checker, path)
+
+
+def test_layout_of_workloads(checker):
+    from paper_1907_04417_amd import workloads
+    for name in ("jump16", "elast12"):
+        _, path, _ = workloads.load(name)
+        out = _run(checker, path)
+        if name == "elast12":
+            assert "sell0=0" in out  # node-grouped fine level
+
+
+def test_layout_of_a_batch_union(checker):
+    from paper_1907_04417_amd import workloads
+    Ps, paths, _ = workloads.load_batch("batch6")
+    _run(checker, "--batch", *paths)
