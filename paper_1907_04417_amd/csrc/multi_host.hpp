@@ -287,6 +287,7 @@ struct MultiOps {
   int nsys = 0;   // systems carried on the device
   int nrep = 0;   // systems reported to the caller (the first nrep)
   int key = 0;    // graph cache key base
+  const std::vector<char>* host_act = nullptr;  // host mirror of the systems' S_ACT flags
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   virtual ~MultiOps() {}
   virtual void load(const double* b, const double* x, hipStream_t st) = 0;  // caller layout -> internal
@@ -391,6 +392,7 @@ mvamg_status multi_pcg(MultiOps& O, const double* b, double* x, const mvamg_solv
   std::vector<double> r0(ns), hlast(ns, 1.0);
   std::vector<int> it(ns, 0), restarts(ns, 0);
   std::vector<char> run(ns, 0), met(ns, 0), conv(ns, 0), act(ns, 0);
+  O.host_act = &act;
   for (int s = 0; s < ns; ++s) {
     r0[s] = std::sqrt(pin[s * S_NSCAL + S_R0]);
     if (!std::isfinite(r0[s]))
@@ -577,8 +579,17 @@ struct BatchOps : MultiOps {
   }
   struct SkipScope {  // level-0 kernels skip stopped problems while alive
     mvamg_hier* h;
-    explicit SkipScope(mvamg_hier* hh) : h(hh) { h->skip_act = h->mb.scal + S_ACT; }
-    ~SkipScope() { h->skip_act = nullptr; }
+    SkipScope(mvamg_hier* hh, const std::vector<char>* act) : h(hh) {
+      h->skip_act = h->mb.scal + S_ACT;
+      double rows = 0.0;
+      for (int p = 0; p < h->nprob; ++p)
+        if (!act || (*act)[p]) rows += h->h_poff[p + 1] - h->h_poff[p];
+      h->skip_frac = rows / std::max(1, h->n);
+    }
+    ~SkipScope() {
+      h->skip_act = nullptr;
+      h->skip_frac = 1.0;
+    }
   };
   const double* act() const { return h->mb.scal + S_ACT; }
   dim3 pgrid() const { return dim3(h->pchunks, h->nprob); }
@@ -616,7 +627,7 @@ struct BatchOps : MultiOps {
     pdot(a, b, c, d, nv, mode, act(), st);
   }
   void cycle(int precision, int smoother, hipStream_t st) override {
-    SkipScope sk(h);
+    SkipScope sk(h, host_act);
     apply_B(h, r, z, precision, smoother, st);
   }
   void copy_zp(hipStream_t st) override {
@@ -625,7 +636,7 @@ struct BatchOps : MultiOps {
   }
   void spmv_pq(hipStream_t st) override {
     {
-      SkipScope sk(h);
+      SkipScope sk(h, host_act);
       ::resid<double, 2>(h, 0, h->lv[0], nullptr, p, q, M_NONE, st);
     }
     dot_iter(p, q, nullptr, nullptr, 1, MM_PQ, st);

@@ -158,6 +158,7 @@ struct mvamg_hier {
   // while set (batch CG iterations), level-0 kernels skip the work units of
   // problems whose S_ACT flag (at skip_act + S_NSCAL * problem) is zero
   const double* skip_act = nullptr;
+  double skip_frac = 1.0;  // meanwhile: fraction of level-0 rows still worked on (byte accounting)
   // several systems at once
   MultiBufs mb;
   bool blk_ready = false;
@@ -221,6 +222,9 @@ namespace {
 Red mkred(mvamg_hier* h) { return Red{h->part}; }
 
 enum SkipUnit { SKIP_SLAB, SKIP_ROW, SKIP_AGG };
+
+// algorithmic bytes of a level-l launch that skips stopped problems
+double skip_bytes(const mvamg_hier* h, int l, double bytes) { return (l == 0 && h->skip_act) ? bytes * h->skip_frac : bytes; }
 
 Skip lskip(const mvamg_hier* h, int l, SkipUnit u) {
   if (l != 0 || !h->skip_act) return Skip{nullptr, nullptr};
@@ -372,7 +376,7 @@ double stage_bytes(const DevLevel& L, int c) {
 template <typename T>
 void gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, int backward, hipStream_t st) {
   const int kc = (l == 0) ? MVAMG_KC_SMOOTH_FINE : MVAMG_KC_SMOOTH_COARSE;
-  const double by = stage_bytes<T>(L, c);
+  const double by = skip_bytes(h, l, stage_bytes<T>(L, c));
   if (L.sell) {
     const int s0 = L.h_sslab[c], s1 = L.h_sslab[c + 1];
     if (s1 <= s0) return;
@@ -396,7 +400,7 @@ void gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, 
 template <typename T>
 void zero_stage0(mvamg_hier* h, int l, const DevLevel& L, const T* r, T* x, hipStream_t st) {
   const int kc = (l == 0) ? MVAMG_KC_SMOOTH_FINE : MVAMG_KC_SMOOTH_COARSE;
-  const double by = (double)L.n * sizeof(T) + (double)L.stage_rows[0] * (2 * sizeof(T));
+  const double by = skip_bytes(h, l, (double)L.n * sizeof(T) + (double)L.stage_rows[0] * (2 * sizeof(T)));
   if (L.sell) {
     klaunch(h, kc, by, k_zero_stage0_point<T>, grid_elem(L.n), kBlock, st, L.n, L.rows0, ldblk<T>(L), r, x,
             lskip(h, l, SKIP_ROW));
@@ -413,7 +417,8 @@ template <typename T, int MODE>
 void resid(mvamg_hier* h, int l, const DevLevel& L, const T* r, const T* x, T* s, int mode, hipStream_t st) {
   const Red red = mkred(h);
   const int kc = MODE != 0 ? MVAMG_KC_SPMV : MVAMG_KC_RESIDUAL;
-  const double by = (double)L.nnz * (sizeof(T) + 4) + 4.0 * (L.n + 1) + (double)L.n * sizeof(T) * (MODE != 0 ? 2 : 3);
+  const double by = skip_bytes(h, l, (double)L.nnz * (sizeof(T) + 4) + 4.0 * (L.n + 1) +
+                                         (double)L.n * sizeof(T) * (MODE != 0 ? 2 : 3));
   if (L.sell) {
     const int grid = (L.nslabs + 3) / 4;
     klaunch(h, kc, by, k_resid_sell<T, MODE>, grid, kBlock, st, L.slabs, L.nslabs, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red,
@@ -485,18 +490,18 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   // residual, restriction (fused with the first smoothing step of the next level)
   resid<T, 0>(h, l, L, r, x, s, M_NONE, st);
   const int tg = (P.nagg + 3) / 4;
-  const double tby = (double)P.nu * sizeof(T) + (double)L.n * (4 + sizeof(T)) + (double)C.n * sizeof(T);
+  const double tby = skip_bytes(h, l, (double)P.nu * sizeof(T) + (double)L.n * (4 + sizeof(T)) + (double)C.n * sizeof(T));
   const bool next_smoothed = (l + 2 < h->nl);
   if (!next_smoothed) {
     klaunch(h, MVAMG_KC_RESTRICT, tby, k_restrict<T, 0>, tg, kBlock, st, P.nagg, P.aptr, P.arows, P.uoff, P.cst,
             P.kk, tU<T>(P), s, rc, (const int*)nullptr, 0, (const int*)nullptr, (const T*)nullptr,
             (const T*)nullptr, (T*)nullptr, lskip(h, l, SKIP_AGG));
   } else if (smoother == MVAMG_SMOOTH_GS) {
-    klaunch(h, MVAMG_KC_RESTRICT, tby + (double)C.n * sizeof(T), k_restrict<T, 1>, tg, kBlock, st, P.nagg, P.aptr,
+    klaunch(h, MVAMG_KC_RESTRICT, tby + skip_bytes(h, l, (double)C.n * sizeof(T)), k_restrict<T, 1>, tg, kBlock, st, P.nagg, P.aptr,
             P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc, P.cgrp, C.h_sgrp[1], C.dboff, ldblk<T>(C),
             (const T*)nullptr, xc, lskip(h, l, SKIP_AGG));
   } else {
-    klaunch(h, MVAMG_KC_RESTRICT, tby + (double)C.n * sizeof(T), k_restrict<T, 2>, tg, kBlock, st, P.nagg, P.aptr,
+    klaunch(h, MVAMG_KC_RESTRICT, tby + skip_bytes(h, l, (double)C.n * sizeof(T)), k_restrict<T, 2>, tg, kBlock, st, P.nagg, P.aptr,
             P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc, (const int*)nullptr, 0, (const int*)nullptr,
             (const T*)nullptr, ldl1<T>(C), xc, lskip(h, l, SKIP_AGG));
   }
@@ -504,7 +509,7 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   vcycle<T>(h, l + 1, rc, xc, smoother, st, next_smoothed);
   {
     const int pg = grid_elem(P.nf);
-    const double pby = (double)P.nu * sizeof(T) + (double)L.n * (4 + 2 * sizeof(T)) + (double)C.n * sizeof(T);
+    const double pby = skip_bytes(h, l, (double)P.nu * sizeof(T) + (double)L.n * (4 + 2 * sizeof(T)) + (double)C.n * sizeof(T));
     const Skip sk = lskip(h, l, SKIP_ROW);
     switch (P.kmax) {
       case 1: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 1>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x, sk); break;
