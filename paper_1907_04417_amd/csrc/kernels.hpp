@@ -288,85 +288,153 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
 
 // ------------------------------------------------------ grouped levels
 
-// Grouped levels: one wavefront per group, 64 / KMAX lanes per row (KMAX =
-// the level's largest group, a power of two <= 8).  Lane sub of row l strides
-// over row l's off-group entries (batches of 4: index loads, gathers, sums),
-// a segmented shuffle adds the row, and the k row sums are broadcast to the
-// wave.  The group index is made wave-uniform so its descriptors and the k x k
-// diagonal block are read with scalar loads.  grb holds, per group, the entry
-// offsets of its rows (kKmax + 1 values, repeated past row k).
+// Grouped levels: one wavefront per group, LPR = 64 / KMAX lanes per row
+// (KMAX a power of two, at least the level's largest group).  Every group has
+// a 64-byte record, read with scalar loads while the rest of the group's data
+// is requested:
+//   rec[0] first row p0, rec[1] rows k, rec[2] offset of its k x k diagonal
+//   block (dense row-major), rec[3 + q] entry offset of row q (q = 0..8,
+//   repeated past row k), rec[12..15] unused.
+// Lane sub of row l strides over row l's off-group entries (batches of 4:
+// index loads, gathers, sums); the row is summed inside its aligned group of
+// lanes with DPP moves and each row sum is read into a scalar with readlane.
+constexpr int kRec = 16;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_value(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Sum of v over aligned groups of min(LPR, 16) lanes (quad_perm [1,0,3,2],
+// quad_perm [2,3,0,1], row_half_mirror, row_mirror); every lane of the group
+// holds the result.
+template <int LPR, typename T>
+__device__ __forceinline__ T lanes_sum(T v) {
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0x141>(v);
+  if (LPR >= 16) v += dpp_mov<0x140>(v);
+  return v;
+}
+
+// Row sums a[q] (q < KMAX; zero past row k) of the off-group entries of group
+// g times x.  Uniform across the wave.
 template <typename T, int KMAX>
-__device__ __forceinline__ void group_rowsums(int g, int l, int sub, int k, const int* __restrict__ grb,
+__device__ __forceinline__ void group_rowsums(const int (&gb)[kKmax + 1], int l, int sub,
                                               const int* __restrict__ col, const T* __restrict__ val, const T* x,
                                               T (&a)[KMAX]) {
   constexpr int LPR = 64 / KMAX;
+  int e0 = gb[0], e1 = gb[1];
+#pragma unroll
+  for (int q = 1; q < KMAX; ++q)
+    if (l == q) {
+      e0 = gb[q];
+      e1 = gb[q + 1];
+    }
   T acc = T(0);
-  if (l < k) {
-    const int* gb = grb + (size_t)g * (kKmax + 1);
-    const int e1 = gb[l + 1];
-    for (int e0 = gb[l] + sub; e0 < e1; e0 += 4 * LPR) {
-      int cc[4];
-      T vv[4], xx[4];
+  for (int e = e0 + sub; e < e1; e += 4 * LPR) {
+    int cc[4];
+    T vv[4], xx[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = min(e0 + u * LPR, e1 - 1);
-        cc[u] = col[e];
-        vv[u] = val[e];
-      }
+    for (int u = 0; u < 4; ++u) {
+      const int ee = min(e + u * LPR, e1 - 1);
+      cc[u] = col[ee];
+      vv[u] = val[ee];
+    }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) xx[u] = x[cc[u]];
+    for (int u = 0; u < 4; ++u) xx[u] = x[cc[u]];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (e0 + u * LPR < e1) acc += vv[u] * xx[u];
+    for (int u = 0; u < 4; ++u)
+      if (e + u * LPR < e1) acc += vv[u] * xx[u];
+  }
+  acc = lanes_sum<LPR>(acc);
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    T t = lane_value(acc, q * LPR);
+#pragma unroll
+    for (int j = 1; j < LPR / 16; ++j) t += lane_value(acc, q * LPR + 16 * j);
+    a[q] = t;
+  }
+}
+
+// The group's record, diagonal block, and current x and r of its rows (all
+// requested before any is used; indices clamped into the group).
+template <typename T, int KMAX>
+struct GroupData {
+  int p0, k;
+  int gb[kKmax + 1];
+  T B[KMAX][KMAX], xv[KMAX], rv[KMAX];
+};
+
+template <typename T, int KMAX, bool WITH_R>
+__device__ __forceinline__ void load_group(int g, const int* __restrict__ rec, const T* __restrict__ dblk,
+                                           const T* __restrict__ r, const T* x, GroupData<T, KMAX>& d) {
+  const int* R = rec + (size_t)g * kRec;
+  d.p0 = R[0];
+  d.k = R[1];
+  const T* B = dblk + R[2];
+#pragma unroll
+  for (int q = 0; q <= kKmax; ++q) d.gb[q] = R[3 + q];
+  const int k = d.k;
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) {
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) d.B[i][j] = B[min(i, k - 1) * k + min(j, k - 1)];
+    const T xi = x[d.p0 + min(i, k - 1)];
+    d.xv[i] = (i < k) ? xi : T(0);
+    if (WITH_R) {
+      const T ri = r[d.p0 + min(i, k - 1)];
+      d.rv[i] = (i < k) ? ri : T(0);
     }
   }
-  acc = seg_sum<LPR>(acc);
-#pragma unroll
-  for (int q = 0; q < KMAX; ++q) a[q] = __shfl(acc, q * LPR, 64);
 }
 
 // One Gauss-Seidel stage on the groups [g0, g1): every group relaxes its rows
 // one after the other (forward: l = 0..k-1, backward: l = k-1..0) with the
 // latest values of the other rows.
-template <typename T, int KMAX>
-__global__ __launch_bounds__(kBlock) void k_gs_grp(int g0, int g1, const int* __restrict__ gstart,
-                                                   const int* __restrict__ grb, const int* __restrict__ col,
-                                                   const T* __restrict__ val, const int* __restrict__ dboff,
-                                                   const T* __restrict__ dblk, const T* __restrict__ r, T* x,
-                                                   int backward) {
-  const int g = __builtin_amdgcn_readfirstlane(g0 + (int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6));
-  if (g >= g1) return;
+template <typename T, int KMAX, int BACK>
+__global__ __launch_bounds__(kBlock) void k_gs_grp(int g0, int g1, const int* __restrict__ rec,
+                                                   const int* __restrict__ col, const T* __restrict__ val,
+                                                   const T* __restrict__ dblk, const T* __restrict__ r, T* x) {
+  const int graw = g0 + (int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
+  const int g = __builtin_amdgcn_readfirstlane(min(graw, g1 - 1));
   const int lane = threadIdx.x & 63;
   const int l = lane / (64 / KMAX), sub = lane % (64 / KMAX);
-  const int p0 = gstart[g], k = gstart[g + 1] - p0;
-  const T* B = dblk + dboff[g];
-  T xv[KMAX], rv[KMAX];
-#pragma unroll
-  for (int q = 0; q < KMAX; ++q) {
-    const int qq = min(q, k - 1);
-    const T xq = x[p0 + qq], rq = r[p0 + qq];
-    xv[q] = (q < k) ? xq : T(0);
-    rv[q] = (q < k) ? rq : T(0);
-  }
+  GroupData<T, KMAX> d;
+  load_group<T, KMAX, true>(g, rec, dblk, r, x, d);
   T a[KMAX];
-  group_rowsums<T, KMAX>(g, l, sub, k, grb, col, val, x, a);
+  group_rowsums<T, KMAX>(d.gb, l, sub, col, val, x, a);
 #pragma unroll
   for (int t = 0; t < KMAX; ++t) {
-    const int ll = backward ? KMAX - 1 - t : t;
-    if (ll < k) {
-      T s = rv[ll] - a[ll];
+    const int ll = BACK ? KMAX - 1 - t : t;
+    if (ll < d.k) {
+      T s = d.rv[ll] - a[ll];
 #pragma unroll
       for (int q = 0; q < KMAX; ++q)
-        if (q < k && q != ll) s -= B[ll * k + q] * xv[q];
-      xv[ll] = s / B[ll * k + ll];
+        if (q < d.k && q != ll) s -= d.B[ll][q] * d.xv[q];
+      d.xv[ll] = s / d.B[ll][ll];
     }
   }
-  if (sub == 0 && l < k) {
-    T v = xv[0];
+  if (graw < g1 && sub == 0 && l < d.k) {
+    T v = d.xv[0];
 #pragma unroll
     for (int q = 1; q < KMAX; ++q)
-      if (l == q) v = xv[q];
-    x[p0 + l] = v;
+      if (l == q) v = d.xv[q];
+    x[d.p0 + l] = v;
   }
 }
 
@@ -402,45 +470,44 @@ __global__ __launch_bounds__(kBlock) void k_zero_stage0_grp(int ng, int ng0, con
   }
 }
 
-// s = r - A x (MODE 0), y = A x with sum x.y (MODE 1, binary64) or y = A x (MODE 2) on all groups.
+// s = r - A x (MODE 0), y = A x with sum x.y (MODE 1, binary64) or y = A x
+// (MODE 2) on all groups; wave per group.
 template <typename T, int KMAX, int MODE>
-__global__ __launch_bounds__(kBlock) void k_resid_grp(int ng, const int* __restrict__ gstart,
-                                                      const int* __restrict__ grb, const int* __restrict__ col,
-                                                      const T* __restrict__ val, const int* __restrict__ dboff,
+__global__ __launch_bounds__(kBlock) void k_resid_grp(int ng, const int* __restrict__ rec,
+                                                      const int* __restrict__ col, const T* __restrict__ val,
                                                       const T* __restrict__ dblk, const T* __restrict__ r,
                                                       const T* __restrict__ x, T* __restrict__ s, Red red) {
-  const int g = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6));
+  const int graw = (int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
+  const int g = __builtin_amdgcn_readfirstlane(min(graw, ng - 1));
   const int lane = threadIdx.x & 63;
   const int l = lane / (64 / KMAX), sub = lane % (64 / KMAX);
+  GroupData<T, KMAX> d;
+  load_group<T, KMAX, false>(g, rec, dblk, r, x, d);
+  T a[KMAX];
+  group_rowsums<T, KMAX>(d.gb, l, sub, col, val, x, a);
   double dsum = 0.0;
-  if (g < ng) {
-    const int p0 = gstart[g], k = gstart[g + 1] - p0;
-    const T* B = dblk + dboff[g];
-    T xv[KMAX];
+  if (graw < ng && sub == 0 && l < d.k) {
+    T t = T(0), xl = T(0);
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q)
+      if (q == l) {
+        t = a[q];
+        xl = d.xv[q];
+      }
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) {
-      const T xq = x[p0 + min(q, k - 1)];
-      xv[q] = (q < k) ? xq : T(0);
+      T bq = d.B[0][q];
+#pragma unroll
+      for (int i = 1; i < KMAX; ++i)
+        if (i == l) bq = d.B[i][q];
+      if (q < d.k) t += bq * d.xv[q];
     }
-    T a[KMAX];
-    group_rowsums<T, KMAX>(g, l, sub, k, grb, col, val, x, a);
-    if (sub == 0 && l < k) {
-      T t = T(0), xl = T(0);
-#pragma unroll
-      for (int q = 0; q < KMAX; ++q)
-        if (q == l) {
-          t = a[q];
-          xl = xv[q];
-        }
-#pragma unroll
-      for (int q = 0; q < KMAX; ++q)
-        if (q < k) t += B[l * k + q] * xv[q];
-      if (MODE == 0) {
-        s[p0 + l] = r[p0 + l] - t;
-      } else {
-        s[p0 + l] = t;
-        if (MODE == 1) dsum = (double)xl * (double)t;
-      }
+    const int p = d.p0 + l;
+    if (MODE == 0) {
+      s[p] = r[p] - t;
+    } else {
+      s[p] = t;
+      if (MODE == 1) dsum = (double)xl * (double)t;
     }
   }
   if (MODE == 1) block_partials<1>(dsum, 0.0, red.part);
@@ -524,10 +591,12 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nagg, const int* __rest
       if (q < k) acc[q] += Ua[q * na + li] * sv;
   }
   const int c0 = cst[a];
+  // wave sums (DPP inside each 16-lane row, then the four row sums in order)
 #pragma unroll
   for (int q = 0; q < kKmax; ++q) {
     if (q < k) {
-      acc[q] = seg_sum<64>(acc[q]);
+      const T v = lanes_sum<16>(acc[q]);
+      acc[q] = ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
       if (lane == q) rc[c0 + q] = acc[q];
     }
   }

@@ -276,11 +276,11 @@ __global__ __launch_bounds__(kBlock) void k_bresid_sell(const Slab* __restrict__
 // Off-group row sums of group g for column c: half wave h adds rows
 // h, h + 2, ...; afterwards every lane holds a[q] for all rows q < k.
 template <typename T, int KMAX>
-__device__ __forceinline__ void bgroup_rowsums(int g, int h, int c, int k, const int* __restrict__ grb,
+__device__ __forceinline__ void bgroup_rowsums(int g, int h, int c, int k, const int* __restrict__ rec,
                                                const int* __restrict__ col, const T* __restrict__ val, const T* x,
                                                T (&a)[KMAX]) {
   constexpr int NT = (KMAX + 1) / 2;
-  const int* gb = grb + (size_t)g * (kKmax + 1);
+  const int* gb = rec + (size_t)g * kRec + 3;
   T mine[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -317,16 +317,16 @@ __device__ __forceinline__ void bgroup_rowsums(int g, int h, int c, int k, const
 // Gauss-Seidel stage on the groups [g0, g1): wave per group, every column
 // relaxes the group's rows one after the other (forward or backward).
 template <typename T, int KMAX>
-__global__ __launch_bounds__(kBlock) void k_bgs_grp(int g0, int g1, const int* __restrict__ gstart,
-                                                    const int* __restrict__ grb, const int* __restrict__ col,
-                                                    const T* __restrict__ val, const int* __restrict__ dboff,
+__global__ __launch_bounds__(kBlock) void k_bgs_grp(int g0, int g1, const int* __restrict__ rec,
+                                                    const int* __restrict__ col, const T* __restrict__ val,
                                                     const T* __restrict__ dblk, const T* __restrict__ r, T* x,
                                                     int backward) {
   const int g = __builtin_amdgcn_readfirstlane(g0 + (int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6));
   if (g >= g1) return;
   const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
-  const int p0 = gstart[g], k = gstart[g + 1] - p0;
-  const T* B = dblk + dboff[g];
+  const int* R = rec + (size_t)g * kRec;
+  const int p0 = R[0], k = R[1];
+  const T* B = dblk + R[2];
   T xv[KMAX], rv[KMAX];
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) {
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_bgs_grp(int g0, int g1, const int* _
     rv[q] = (q < k) ? rq : T(0);
   }
   T a[KMAX];
-  bgroup_rowsums<T, KMAX>(g, h, c, k, grb, col, val, x, a);
+  bgroup_rowsums<T, KMAX>(g, h, c, k, rec, col, val, x, a);
 #pragma unroll
   for (int t = 0; t < KMAX; ++t) {
     const int ll = backward ? KMAX - 1 - t : t;
@@ -388,9 +388,8 @@ __global__ __launch_bounds__(kBlock) void k_bzero_stage0_grp(int ng, int ng0, co
 // s = r - A x (MODE 0), s = A x with per-column x.s partials (MODE 1) or
 // s = A x (MODE 2) on all groups; grid-stride, wave per group.
 template <typename T, int KMAX, int MODE>
-__global__ __launch_bounds__(kBlock) void k_bresid_grp(int ng, const int* __restrict__ gstart,
-                                                       const int* __restrict__ grb, const int* __restrict__ col,
-                                                       const T* __restrict__ val, const int* __restrict__ dboff,
+__global__ __launch_bounds__(kBlock) void k_bresid_grp(int ng, const int* __restrict__ rec,
+                                                       const int* __restrict__ col, const T* __restrict__ val,
                                                        const T* __restrict__ dblk, const T* __restrict__ r,
                                                        const T* __restrict__ x, T* __restrict__ s,
                                                        double* __restrict__ part) {
@@ -398,8 +397,9 @@ __global__ __launch_bounds__(kBlock) void k_bresid_grp(int ng, const int* __rest
   double dsum = 0.0;
   const int gfirst = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6));
   for (int g = gfirst; g < ng; g += gridDim.x * (kBlock / 64)) {
-    const int p0 = gstart[g], k = gstart[g + 1] - p0;
-    const T* B = dblk + dboff[g];
+    const int* R = rec + (size_t)g * kRec;
+    const int p0 = R[0], k = R[1];
+    const T* B = dblk + R[2];
     T xv[KMAX];
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) {
@@ -407,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_bresid_grp(int ng, const int* __rest
       xv[q] = (q < k) ? xq : T(0);
     }
     T a[KMAX];
-    bgroup_rowsums<T, KMAX>(g, h, c, k, grb, col, val, x, a);
+    bgroup_rowsums<T, KMAX>(g, h, c, k, rec, col, val, x, a);
 #pragma unroll
     for (int l = 0; l < KMAX; ++l) {
       if (l < k && (l & 1) == h) {

@@ -124,10 +124,10 @@ void bgs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x,
     if (g1 <= g0) return;
     const int grid = (g1 - g0 + 3) / 4;
     switch (L.G) {
-      case 1: klaunch(h, kc, by, k_bgs_grp<T, 1>, grid, kBlock, st, g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
-      case 2: klaunch(h, kc, by, k_bgs_grp<T, 2>, grid, kBlock, st, g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
-      case 4: klaunch(h, kc, by, k_bgs_grp<T, 4>, grid, kBlock, st, g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
-      default: klaunch(h, kc, by, k_bgs_grp<T, 8>, grid, kBlock, st, g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      case 1: klaunch(h, kc, by, k_bgs_grp<T, 1>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, backward); break;
+      case 2: klaunch(h, kc, by, k_bgs_grp<T, 2>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, backward); break;
+      case 4: klaunch(h, kc, by, k_bgs_grp<T, 4>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, backward); break;
+      default: klaunch(h, kc, by, k_bgs_grp<T, 8>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, backward); break;
     }
   }
   LAUNCHCHECK("bgs_stage");
@@ -157,10 +157,10 @@ void bresid(mvamg_hier* h, const DevLevel& L, const T* r, const T* x, T* s, int 
     klaunch(h, kc, by, k_bresid_sell<T, MODE>, grid, kBlock, st, L.slabs, L.nslabs, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part);
   } else {
     switch (L.G) {
-      case 1: klaunch(h, kc, by, k_bresid_grp<T, 1, MODE>, grid, kBlock, st, L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, part); break;
-      case 2: klaunch(h, kc, by, k_bresid_grp<T, 2, MODE>, grid, kBlock, st, L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, part); break;
-      case 4: klaunch(h, kc, by, k_bresid_grp<T, 4, MODE>, grid, kBlock, st, L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, part); break;
-      default: klaunch(h, kc, by, k_bresid_grp<T, 8, MODE>, grid, kBlock, st, L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, part); break;
+      case 1: klaunch(h, kc, by, k_bresid_grp<T, 1, MODE>, grid, kBlock, st, L.ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part); break;
+      case 2: klaunch(h, kc, by, k_bresid_grp<T, 2, MODE>, grid, kBlock, st, L.ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part); break;
+      case 4: klaunch(h, kc, by, k_bresid_grp<T, 4, MODE>, grid, kBlock, st, L.ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part); break;
+      default: klaunch(h, kc, by, k_bresid_grp<T, 8, MODE>, grid, kBlock, st, L.ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part); break;
     }
   }
   LAUNCHCHECK("bresid");

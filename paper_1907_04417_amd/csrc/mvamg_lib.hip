@@ -68,7 +68,7 @@ struct DevLevel {
   // device arrays
   Slab* slabs = nullptr;
   int* rowptr = nullptr;
-  int* grb = nullptr;  // per group: entry offsets of its rows (kKmax + 1)
+  int* rec = nullptr;  // per group: 16-int record (first row, rows, block offset, row entry offsets)
   int* col = nullptr;
   double* val = nullptr;
   float* val32 = nullptr;
@@ -387,12 +387,16 @@ void gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, 
     const int g0 = L.h_sgrp[c], g1 = L.h_sgrp[c + 1];
     if (g1 <= g0) return;
     const int grid = (g1 - g0 + 3) / 4;
+#define MVAMG_GS_GRP(K)                                                                                             \
+  (backward ? klaunch(h, kc, by, k_gs_grp<T, K, 1>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x) \
+            : klaunch(h, kc, by, k_gs_grp<T, K, 0>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x))
     switch (L.G) {
-      case 1: klaunch(h, kc, by, k_gs_grp<T, 1>, grid, kBlock, st, g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
-      case 2: klaunch(h, kc, by, k_gs_grp<T, 2>, grid, kBlock, st, g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
-      case 4: klaunch(h, kc, by, k_gs_grp<T, 4>, grid, kBlock, st, g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
-      default: klaunch(h, kc, by, k_gs_grp<T, 8>, grid, kBlock, st, g0, g1, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, backward); break;
+      case 1: MVAMG_GS_GRP(1); break;
+      case 2: MVAMG_GS_GRP(2); break;
+      case 4: MVAMG_GS_GRP(4); break;
+      default: MVAMG_GS_GRP(8); break;
     }
+#undef MVAMG_GS_GRP
   }
   LAUNCHCHECK("gs_stage");
 }
@@ -426,10 +430,10 @@ void resid(mvamg_hier* h, int l, const DevLevel& L, const T* r, const T* x, T* s
   } else {
     const int grid = (L.ng + 3) / 4;
     switch (L.G) {
-      case 1: klaunch(h, kc, by, k_resid_grp<T, 1, MODE>, grid, kBlock, st, L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
-      case 2: klaunch(h, kc, by, k_resid_grp<T, 2, MODE>, grid, kBlock, st, L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
-      case 4: klaunch(h, kc, by, k_resid_grp<T, 4, MODE>, grid, kBlock, st, L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
-      default: klaunch(h, kc, by, k_resid_grp<T, 8, MODE>, grid, kBlock, st, L.ng, L.gstart, L.grb, L.col, lval<T>(L), L.dboff, ldblk<T>(L), r, x, s, red); break;
+      case 1: klaunch(h, kc, by, k_resid_grp<T, 1, MODE>, grid, kBlock, st, L.ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
+      case 2: klaunch(h, kc, by, k_resid_grp<T, 2, MODE>, grid, kBlock, st, L.ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
+      case 4: klaunch(h, kc, by, k_resid_grp<T, 4, MODE>, grid, kBlock, st, L.ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
+      default: klaunch(h, kc, by, k_resid_grp<T, 8, MODE>, grid, kBlock, st, L.ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
     }
   }
   LAUNCHCHECK("resid");
@@ -824,12 +828,16 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
       if (y.sell) L.slabs = h->upload_vec(y.slabs, st);
       if (!y.sell) {
         L.rowptr = h->upload_vec(y.rowptr, st);
-        std::vector<int> grb((size_t)L.ng * (kKmax + 1));
+        std::vector<int> rec((size_t)L.ng * kRec, 0);
         for (int g = 0; g < L.ng; ++g) {
           const int p0 = y.gstart[g], k = y.gstart[g + 1] - p0;
-          for (int q = 0; q <= kKmax; ++q) grb[(size_t)g * (kKmax + 1) + q] = y.rowptr[p0 + std::min(q, k)];
+          int* R = &rec[(size_t)g * kRec];
+          R[0] = p0;
+          R[1] = k;
+          R[2] = y.dboff[g];
+          for (int q = 0; q <= kKmax; ++q) R[3 + q] = y.rowptr[p0 + std::min(q, k)];
         }
-        L.grb = h->upload_vec(grb, st);
+        L.rec = h->upload_vec(rec, st);
       }
       L.col = h->upload_vec(y.col, st);
       L.val = h->upload_vec(y.val, st);

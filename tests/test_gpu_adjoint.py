@@ -67,16 +67,26 @@ def test_gradient_matches_dense_float64(torch_gpu):
 def test_gradient_matches_central_differences_1024(torch_gpu):
     """1024^2 cells: dL/dg from the adjoint solve against central differences
     on 100 random cells, with steps h = 1e-6 and 1e-4 on the log-coefficient g.
-    Each perturbed solve starts from x(g), so its tolerance (1e-11, relative to
-    the initial residual) bounds the error of the small correction
-    x(g +- h e_c) - x(g) itself; the difference of the losses is
-    sum (x+ - x-)(x+ + x- - 2 x_obs), with no cancellation of L.
 
-    Bound: 1e-4 |g_c| + 1e-6 max|g| + tau / h.  tau = 2e-16 covers the
-    binary64 rounding floor of that loss difference, measured at up to
-    6e-17 and independent of the solve tolerances between 1e-11 and 1e-14;
-    at h = 1e-6 it is the dominant term.  The O(h^2) truncation error of
-    central differences is below 1e-8 relative at h = 1e-4."""
+    With x0 = x(g), the perturbed solutions are computed so that no two
+    independently solved vectors are subtracted:
+      x_- = x0 + d,  A(g - h e_c) d = b - A(g - h e_c) x0,
+      D = x_+ - x_-, A(g + h e_c) D = (A(g - h e_c) - A(g + h e_c)) x_-,
+    both from zero to rtol 1e-13.  The right-hand side of D is exactly zero
+    away from cell c (both products are the same kernel on the same values
+    there), so D carries its own relative accuracy.  Subtracting two
+    separately solved x_+ and x_- instead leaves an absolute noise of about
+    1e-17 on the loss difference, i.e. ~1e-3 of the smaller gradients at
+    h = 1e-6 (measured: the error grows as 1/h and does not move with the
+    solve tolerances, while the adjoint gradient agrees with itself to 10
+    digits over tolerances 1e-12 .. 1e-15).
+    L(x_+) - L(x_-) = sum D (D + 2 (x_- - x_obs)).  Even so the loss
+    difference keeps an absolute noise of up to ~5e-16 (measured on the
+    weakest cells; the same for solve tolerances 1e-13 .. 1e-16, while at
+    h = 1e-4 the same cells agree with the adjoint to ~1e-5), i.e. up to
+    ~2.5e-10 on the quotient at h = 1e-6.  Bound: 1e-4 |g_c| + 1e-6 max|g| +
+    tau / (2 h) with tau = 2e-15 (4x that noise); at h = 1e-4 the tau term is
+    5e-12.  The O(h^2) truncation error is below 1e-8 relative at h = 1e-4."""
     import time
     torch = torch_gpu
     t = time.time()
@@ -95,14 +105,19 @@ def test_gradient_matches_central_differences_1024(torch_gpu):
     _say(f"  adjoint gradient {time.time() - t:.2f}s, max |g| {grad.abs().max().item():.3e}")
     cells = np.random.default_rng(7).choice(P.n, 100, replace=False)
     gmax = grad.abs().max().item()
-    tau = 2e-16
 
-    def perturbed(gv):
+    def matvec(gv, v):
         mvamg.set_fine_values(S.h, fv.values_torch(gv))
-        xs = x0.clone()
-        inf = mvamg.pcg_solve(S.h, b, xs, rtol=1e-11)
+        y = torch.empty_like(b)
+        mvamg.spmv(S.h, v, y)
+        return y
+
+    def solve(gv, rhs):
+        mvamg.set_fine_values(S.h, fv.values_torch(gv))
+        d = torch.zeros_like(b)
+        inf = mvamg.pcg_solve(S.h, rhs, d, rtol=1e-13, maxit=2000)
         assert inf.converged
-        return xs
+        return d
 
     with torch.no_grad():
         for h in (1e-6, 1e-4):
@@ -112,12 +127,58 @@ def test_gradient_matches_central_differences_1024(torch_gpu):
                 gm = g.detach().clone()
                 gp[c] += h
                 gm[c] -= h
-                xp, xm = perturbed(gp), perturbed(gm)
-                dL = ((xp - xm) * (xp + xm - 2 * xobs)).sum().item()
+                xm = x0 + solve(gm, b - matvec(gm, x0))
+                D = solve(gp, matvec(gm, xm) - matvec(gp, xm))
+                dL = (D * (D + 2.0 * (xm - xobs))).sum().item()
                 fd = dL / (2 * h)
                 ga = grad[c].item()
-                bound = 1e-4 * abs(ga) + 1e-6 * gmax + tau / h
+                bound = 1e-4 * abs(ga) + 1e-6 * gmax + 2e-15 / (2 * h)
                 worst = max(worst, abs(fd - ga) / bound)
                 assert abs(fd - ga) <= bound, (h, c, fd, ga)
             _say(f"  h={h:.0e}, 100 cells: worst |fd - adj| / bound = {worst:.3f}")
+    S.close()
+
+
+def test_directional_derivative_1024(torch_gpu):
+    """1024^2 cells: the adjoint gradient projected on a smooth direction v
+    (a second Gaussian random field, all cells) against the central
+    difference of L along v, h = 1e-4, with the difference solve of the
+    cell test.  The signal is spread over all cells, far above the
+    loss-difference noise floor: relative agreement 1e-6 (truncation
+    O(h^2) ~ 1e-8)."""
+    torch = torch_gpu
+    P, path, st = workloads.load("grf1024")
+    fv, g0 = P.meta["fv"], P.meta["g"].ravel()
+    S = mvamg.Solver(path)
+    b = torch.from_numpy(P.b).cuda()
+    g = torch.from_numpy(g0.copy()).cuda().requires_grad_(True)
+    xobs = _observed(torch, S, fv, g.detach(), b, 0)
+    x = amg_solve(fv.values_torch(g), b, S, rtol=1e-13)
+    ((x - xobs) ** 2).sum().backward()
+    v = torch.from_numpy(problems.grf(1024, seed=9).ravel()).cuda()
+    dadj = float((g.grad * v).sum())
+    x0 = x.detach()
+    h = 1e-4
+
+    def matvec(gv, u):
+        mvamg.set_fine_values(S.h, fv.values_torch(gv))
+        y = torch.empty_like(b)
+        mvamg.spmv(S.h, u, y)
+        return y
+
+    def solve(gv, rhs):
+        mvamg.set_fine_values(S.h, fv.values_torch(gv))
+        d = torch.zeros_like(b)
+        inf = mvamg.pcg_solve(S.h, rhs, d, rtol=1e-13, maxit=2000)
+        assert inf.converged
+        return d
+
+    with torch.no_grad():
+        gp = g.detach() + h * v
+        gm = g.detach() - h * v
+        xm = x0 + solve(gm, b - matvec(gm, x0))
+        D = solve(gp, matvec(gm, xm) - matvec(gp, xm))
+        fd = (D * (D + 2.0 * (xm - xobs))).sum().item() / (2 * h)
+    _say(f"[grad dir] adjoint {dadj:.12e} fd {fd:.12e} rel {abs(fd - dadj) / abs(dadj):.2e}")
+    assert abs(fd - dadj) <= 1e-6 * abs(dadj)
     S.close()
