@@ -52,10 +52,42 @@ struct Red {
   double* part;  // one slot per block and value (2 * grid)
 };
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_value(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Sum of v over aligned groups of min(LPR, 16) lanes (quad_perm [1,0,3,2],
+// quad_perm [2,3,0,1], row_half_mirror, row_mirror); every lane of the group
+// holds the result.
+template <int LPR, typename T>
+__device__ __forceinline__ T lanes_sum(T v) {
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0x141>(v);
+  if (LPR >= 16) v += dpp_mov<0x140>(v);
   return v;
+}
+
+// Sum over the 64 lanes (DPP inside each 16-lane row, then the four row sums
+// in order); every lane holds the result.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = lanes_sum<16>(v);
+  return ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
 }
 
 template <int G>
@@ -84,23 +116,25 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
   return t;
 }
 
-__device__ __forceinline__ void epilogue(int mode, double v0, double v1, double* scal) {
+// rho and alpha are read by the caller before the sums (their loads overlap
+// with the partial loads).
+__device__ __forceinline__ void epilogue(int mode, double v0, double v1, double rho, double alpha, double* scal) {
   switch (mode) {
     case M_STORE_RR: scal[S_RR] = v0; break;
     case M_STORE_R0: scal[S_R0] = v0; break;
     case M_PQ:
       scal[S_PQ] = v0;
       if (!(v0 > 0.0)) scal[S_FLAG] = 1.0;
-      scal[S_ALPHA] = scal[S_RHO] / v0;
+      scal[S_ALPHA] = rho / v0;
       break;
     case M_RHO0: scal[S_RHO] = v0; break;
     case M_RZ:
-      scal[S_BETA] = v0 / scal[S_RHO];
+      scal[S_BETA] = v0 / rho;
       scal[S_RHO] = v0;
       break;
     case M_RZ_FLEX:
       scal[S_ZQ] = v1;
-      scal[S_BETA] = -scal[S_ALPHA] * v1 / scal[S_RHO];
+      scal[S_BETA] = -alpha * v1 / rho;
       scal[S_RHO] = v0;
       break;
   }
@@ -126,6 +160,7 @@ template <int NV>
 __global__ __launch_bounds__(kBlock) void k_finish(int nparts, const double* __restrict__ part, double* scal,
                                                    int mode) {
   __shared__ double lds[4];
+  const double rho = scal[S_RHO], alpha = scal[S_ALPHA];
   double s0 = 0.0, s1 = 0.0;
   for (int i = threadIdx.x; i < nparts; i += kBlock) {
     s0 += part[i];
@@ -133,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_finish(int nparts, const double* __r
   }
   s0 = block_sum(s0, lds);
   if (NV > 1) s1 = block_sum(s1, lds);
-  if (threadIdx.x == 0) epilogue(mode, s0, s1, scal);
+  if (threadIdx.x == 0) epilogue(mode, s0, s1, rho, alpha, scal);
 }
 
 // ------------------------------------------------------- vector kernels
@@ -300,37 +335,6 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
 // lanes with DPP moves and each row sum is read into a scalar with readlane.
 constexpr int kRec = 16;
 
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-__device__ __forceinline__ double lane_value(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ float lane_value(float v, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-
-// Sum of v over aligned groups of min(LPR, 16) lanes (quad_perm [1,0,3,2],
-// quad_perm [2,3,0,1], row_half_mirror, row_mirror); every lane of the group
-// holds the result.
-template <int LPR, typename T>
-__device__ __forceinline__ T lanes_sum(T v) {
-  v += dpp_mov<0xB1>(v);
-  v += dpp_mov<0x4E>(v);
-  v += dpp_mov<0x141>(v);
-  if (LPR >= 16) v += dpp_mov<0x140>(v);
-  return v;
-}
-
 // Row sums a[q] (q < KMAX; zero past row k) of the off-group entries of group
 // g times x.  Uniform across the wave.
 template <typename T, int KMAX>
@@ -416,6 +420,10 @@ __global__ __launch_bounds__(kBlock) void k_gs_grp(int g0, int g1, const int* __
   const int l = lane / (64 / KMAX), sub = lane % (64 / KMAX);
   GroupData<T, KMAX> d;
   load_group<T, KMAX, true>(g, rec, dblk, r, x, d);
+  // reciprocals of the diagonal, computed while the entry gathers are in flight
+  T dinv[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) dinv[q] = T(1) / d.B[q][q];
   T a[KMAX];
   group_rowsums<T, KMAX>(d.gb, l, sub, col, val, x, a);
 #pragma unroll
@@ -426,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_grp(int g0, int g1, const int* __
 #pragma unroll
       for (int q = 0; q < KMAX; ++q)
         if (q < d.k && q != ll) s -= d.B[ll][q] * d.xv[q];
-      d.xv[ll] = s / d.B[ll][ll];
+      d.xv[ll] = s * dinv[ll];
     }
   }
   if (graw < g1 && sub == 0 && l < d.k) {
