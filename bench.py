@@ -93,6 +93,25 @@ def counted_bytes_per_iteration(lv, nu):
     return b
 
 
+def measured_copy_gbs(torch, mib=1024, reps=10):
+    """Stream-copy bandwidth of this GPU: bytes read + written per second by a
+    plain device-to-device copy of `mib` MiB."""
+    a = torch.empty(mib << 17, dtype=torch.float64, device="cuda").fill_(1.0)
+    c = torch.empty_like(a)
+    c.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        c.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * a.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, c
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def _timed_ms(torch, fn, steps, warmup):
     for _ in range(warmup):
         fn()
@@ -246,6 +265,8 @@ def main():
     from oracle.hierfile import read_hierarchy
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    copy_gbs = measured_copy_gbs(torch)
+    log(f"[bench] device copy: {copy_gbs:.0f} GB/s (read + write)")
     t0 = time.time()
     P, path, st = workloads.load(args.workload)
     log(f"[bench] setup {args.workload}: n={P.n} nnz={P.nnz} levels={st['n']} opc={st['opc']:.3f} "
@@ -311,6 +332,7 @@ def main():
         traffic = recorded_traffic(dom, args.workload)
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
+                    "measured_copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                     "launches_per_step": dl["launches"], "us_per_launch": dl["us_per_launch"],
                     "profiled_ms_per_step": t_prof}
         log(f"[bench] dominant kernel class {dom}: {dl['ms_per_step']:.2f} ms/step over {dl['launches']} launches, "

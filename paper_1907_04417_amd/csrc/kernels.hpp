@@ -235,12 +235,16 @@ __global__ __launch_bounds__(kBlock) void k_xpay(int n, const double* __restrict
 // ------------------------------------------------- sliced-ELL (point) levels
 
 // One Gauss-Seidel stage: x_p <- (r_p - sum_{j != p} a_pj x_j) / a_pp for the
-// rows of the slabs [s0, s1) (rows of one stage are not coupled).
+// rows of the slabs [s0, s1) (rows of one stage are not coupled).  In the
+// forward sweep from x = 0, lim is the stage's first row: entries of later
+// stages (column >= lim) multiply values that are still zero and are
+// skipped, so those rows need not be cleared beforehand; otherwise lim is
+// past every row.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ slabs, int s0, int s1,
                                                     const int* __restrict__ col, const T* __restrict__ val,
                                                     const T* __restrict__ diag, const T* __restrict__ r, T* x,
-                                                    Skip sk) {
+                                                    Skip sk, int lim) {
   const int s = s0 + blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   if (s >= s1 || skipped(sk, s)) return;
   const int lane = threadIdx.x & 63;
@@ -261,21 +265,21 @@ __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ sla
       vv[u] = v[64 * j];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) xx[u] = x[cc[u]];
+    for (int u = 0; u < 8; ++u) xx[u] = x[min(cc[u], lim - 1)];
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (j0 + u < sl.width) acc -= vv[u] * xx[u];
+      if (j0 + u < sl.width && cc[u] < lim) acc -= vv[u] * xx[u];
   }
   x[p] = acc / diag[p];
 }
 
-// Forward sweep from x = 0: stage 0 rows get r_p / a_pp (their neighbours are
-// still zero), every other row is zeroed.
+// First stage of the forward sweep from x = 0 on a point level: x_p = r_p /
+// a_pp for the rows p < rows0 (the other rows are written by their stages).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_zero_stage0_point(int n, int rows0, const T* __restrict__ diag,
-                                                              const T* __restrict__ r, T* __restrict__ x, Skip sk) {
-  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock)
-    if (!skipped(sk, p)) x[p] = (p < rows0) ? r[p] / diag[p] : T(0);
+__global__ __launch_bounds__(kBlock) void k_stage0_point(int rows0, const T* __restrict__ diag,
+                                                         const T* __restrict__ r, T* __restrict__ x, Skip sk) {
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < rows0; p += gridDim.x * kBlock)
+    if (!skipped(sk, p)) x[p] = r[p] / diag[p];
 }
 
 // s = r - A x (MODE 0), y = A x with sum x.y (MODE 1, binary64 only), or y = A x (MODE 2)

@@ -185,11 +185,13 @@ __global__ __launch_bounds__(kBlock) void k_bxpay(int n, const double* __restric
 }
 
 // Gauss-Seidel stage on the slabs [s0, s1) of a sliced-ELL level: half wave
-// per row, (blockIdx, threadIdx) -> row (s0 + hw / 64, hw % 64).
+// per row, (blockIdx, threadIdx) -> row (s0 + hw / 64, hw % 64).  lim as in
+// k_gs_sell (forward sweep from zero: entries of later stages skipped).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bgs_sell(const Slab* __restrict__ slabs, int s0, int s1,
                                                      const int* __restrict__ col, const T* __restrict__ val,
-                                                     const T* __restrict__ diag, const T* __restrict__ r, T* x) {
+                                                     const T* __restrict__ diag, const T* __restrict__ r, T* x,
+                                                     int lim) {
   const int hw = (blockIdx.x * kBlock + threadIdx.x) >> 5;
   const int s = s0 + (hw >> 6), i = hw & 63;
   if (s >= s1) return;
@@ -210,22 +212,21 @@ __global__ __launch_bounds__(kBlock) void k_bgs_sell(const Slab* __restrict__ sl
       vv[u] = vp[64 * j];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) xx[u] = x[(size_t)cc[u] * kNB + c];
+    for (int u = 0; u < 8; ++u) xx[u] = x[(size_t)min(cc[u], lim - 1) * kNB + c];
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (j0 + u < sl.width) acc -= vv[u] * xx[u];
+      if (j0 + u < sl.width && cc[u] < lim) acc -= vv[u] * xx[u];
   }
   x[(size_t)p * kNB + c] = acc / diag[p];
 }
 
+// x = r / d on the rows p < rows0 (first stage of the forward sweep from zero)
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_bzero_stage0_point(int n, int rows0, const T* __restrict__ diag,
-                                                               const T* __restrict__ r, T* __restrict__ x) {
+__global__ __launch_bounds__(kBlock) void k_bstage0_point(int rows0, const T* __restrict__ diag,
+                                                          const T* __restrict__ r, T* __restrict__ x) {
   const int c = threadIdx.x & 31;
-  for (int p = (blockIdx.x * kBlock + threadIdx.x) >> 5; p < n; p += gridDim.x * kRowsPerBlock) {
-    const size_t i = (size_t)p * kNB + c;
-    x[i] = (p < rows0) ? r[i] / diag[p] : T(0);
-  }
+  for (int p = (blockIdx.x * kBlock + threadIdx.x) >> 5; p < rows0; p += gridDim.x * kRowsPerBlock)
+    x[(size_t)p * kNB + c] = r[(size_t)p * kNB + c] / diag[p];
 }
 
 // MODE 0: s = r - A x;  MODE 1: s = A x with per-column x.s partials;

@@ -111,14 +111,16 @@ double bstage_bytes(const DevLevel& L, int c) {
 }
 
 template <typename T>
-void bgs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, int backward, hipStream_t st) {
+void bgs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, int backward, hipStream_t st,
+               bool first_sweep = false) {
   const int kc = (l == 0) ? MVAMG_KC_SMOOTH_FINE : MVAMG_KC_SMOOTH_COARSE;
   const double by = bstage_bytes<T>(L, c);
   if (L.sell) {
     const int s0 = L.h_sslab[c], s1 = L.h_sslab[c + 1];
     if (s1 <= s0) return;
     const int grid = (s1 - s0) * (64 / kRowsPerBlock);
-    klaunch(h, kc, by, k_bgs_sell<T>, grid, kBlock, st, L.slabs, s0, s1, L.col, lval<T>(L), ldblk<T>(L), r, x);
+    klaunch(h, kc, by, k_bgs_sell<T>, grid, kBlock, st, L.slabs, s0, s1, L.col, lval<T>(L), ldblk<T>(L), r, x,
+            first_sweep ? L.h_srow[c] : INT_MAX);
   } else {
     const int g0 = L.h_sgrp[c], g1 = L.h_sgrp[c + 1];
     if (g1 <= g0) return;
@@ -138,7 +140,8 @@ void bzero_stage0(mvamg_hier* h, int l, const DevLevel& L, const T* r, T* x, hip
   const int kc = (l == 0) ? MVAMG_KC_SMOOTH_FINE : MVAMG_KC_SMOOTH_COARSE;
   const double by = ((double)L.n + 2.0 * L.stage_rows[0]) * kNB * sizeof(T);
   if (L.sell) {
-    klaunch(h, kc, by, k_bzero_stage0_point<T>, bgrid_elem(L.n), kBlock, st, L.n, L.rows0, ldblk<T>(L), r, x);
+    klaunch(h, kc, 3.0 * L.rows0 * kNB * sizeof(T), k_bstage0_point<T>, bgrid_elem(L.rows0), kBlock, st, L.rows0,
+            ldblk<T>(L), r, x);
   } else {
     klaunch(h, kc, by, k_bzero_stage0_grp<T>, bgrid_elem(L.ng), kBlock, st, L.ng, L.h_sgrp[1], L.gstart, L.dboff, ldblk<T>(L), r, x);
   }
@@ -222,7 +225,7 @@ void bvcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t s
   T* xc = pick<T>(C.bx, C.bx32);
   if (smoother == MVAMG_SMOOTH_GS) {
     if (!x_started) bzero_stage0<T>(h, l, L, r, x, st);
-    for (int c = 1; c < L.ns; ++c) bgs_stage<T>(h, l, L, c, r, x, 0, st);
+    for (int c = 1; c < L.ns; ++c) bgs_stage<T>(h, l, L, c, r, x, 0, st, !x_started && L.sell);
   } else if (!x_started) {
     k_bl1_init<T><<<bgrid_elem(L.n), kBlock, 0, st>>>(L.n, ldl1<T>(L), r, x);
   }

@@ -61,6 +61,7 @@ struct DevLevel {
   int ng = 0, ns = 0, nslabs = 0;
   int rows0 = 0;  // rows of stage 0 (point levels)
   std::vector<int> h_sgrp, h_sslab;
+  std::vector<int> h_srow;  // first row of every stage (nstages + 1 entries)
   int64_t nent = 0;    // stored off-group entries (with padding)
   int64_t nnz = 0;     // stored entries of A_l (file), for byte counts
   std::vector<int64_t> stage_rows, stage_nnz;
@@ -373,16 +374,20 @@ double stage_bytes(const DevLevel& L, int c) {
   return (double)L.stage_nnz[c] * (sizeof(T) + 4) + (double)L.stage_rows[c] * (4 + 3 * sizeof(T));
 }
 
+// first_sweep: forward sweep from x = 0 on a point level (entries of later
+// stages skipped; see k_gs_sell)
 template <typename T>
-void gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, int backward, hipStream_t st) {
+void gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, int backward, hipStream_t st,
+              bool first_sweep = false) {
   const int kc = (l == 0) ? MVAMG_KC_SMOOTH_FINE : MVAMG_KC_SMOOTH_COARSE;
   const double by = skip_bytes(h, l, stage_bytes<T>(L, c));
   if (L.sell) {
     const int s0 = L.h_sslab[c], s1 = L.h_sslab[c + 1];
     if (s1 <= s0) return;
     const int grid = (s1 - s0 + 3) / 4;
+    const int lim = first_sweep ? L.h_srow[c] : INT_MAX;
     klaunch(h, kc, by, k_gs_sell<T>, grid, kBlock, st, L.slabs, s0, s1, L.col, lval<T>(L), ldblk<T>(L), r, x,
-            lskip(h, l, SKIP_SLAB));
+            lskip(h, l, SKIP_SLAB), lim);
   } else {
     const int g0 = L.h_sgrp[c], g1 = L.h_sgrp[c + 1];
     if (g1 <= g0) return;
@@ -401,14 +406,18 @@ void gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, 
   LAUNCHCHECK("gs_stage");
 }
 
+// First step of the forward sweep from x = 0.  Point levels: x = r / d on
+// stage 0 only (later stages skip the unset rows); grouped levels: stage-0
+// groups solve their lower-triangular block and every other row is zeroed.
 template <typename T>
 void zero_stage0(mvamg_hier* h, int l, const DevLevel& L, const T* r, T* x, hipStream_t st) {
   const int kc = (l == 0) ? MVAMG_KC_SMOOTH_FINE : MVAMG_KC_SMOOTH_COARSE;
-  const double by = skip_bytes(h, l, (double)L.n * sizeof(T) + (double)L.stage_rows[0] * (2 * sizeof(T)));
   if (L.sell) {
-    klaunch(h, kc, by, k_zero_stage0_point<T>, grid_elem(L.n), kBlock, st, L.n, L.rows0, ldblk<T>(L), r, x,
+    const double by = skip_bytes(h, l, (double)L.rows0 * (3 * sizeof(T)));
+    klaunch(h, kc, by, k_stage0_point<T>, grid_elem(L.rows0), kBlock, st, L.rows0, ldblk<T>(L), r, x,
             lskip(h, l, SKIP_ROW));
   } else {
+    const double by = skip_bytes(h, l, (double)L.n * sizeof(T) + (double)L.stage_rows[0] * (2 * sizeof(T)));
     klaunch(h, kc, by, k_zero_stage0_grp<T>, grid_for(L.ng), kBlock, st, L.ng, L.h_sgrp[1], L.gstart, L.dboff, ldblk<T>(L), r, x);
   }
   LAUNCHCHECK("zero_stage0");
@@ -487,7 +496,7 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   // pre-smoothing: one forward sweep from x = 0
   if (smoother == MVAMG_SMOOTH_GS) {
     if (!x_started) zero_stage0<T>(h, l, L, r, x, st);
-    for (int c = 1; c < L.ns; ++c) gs_stage<T>(h, l, L, c, r, x, 0, st);
+    for (int c = 1; c < L.ns; ++c) gs_stage<T>(h, l, L, c, r, x, 0, st, !x_started && L.sell);
   } else if (!x_started) {
     k_l1_init<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, ldl1<T>(L), r, x);
   }
@@ -812,6 +821,8 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
       L.ns = (int)y.sgrp.size() - 1;
       L.h_sgrp = y.sgrp;
       L.h_sslab = y.sslab;
+      L.h_srow.resize(y.sgrp.size());
+      for (size_t c = 0; c < y.sgrp.size(); ++c) L.h_srow[c] = y.gstart[y.sgrp[c]];
       L.nslabs = (int)y.slabs.size();
       L.rows0 = y.gstart[y.sgrp[1]];
       L.nent = (int64_t)y.val.size();

@@ -4,8 +4,12 @@ hierarchy files (single problems and the union of a batch) and checks its
 invariants (tests/layout_check.cpp)."""
 import os
 import subprocess
+import sys
 
+import numpy as np
 import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -46,3 +50,19 @@ def test_layout_of_a_batch_union(checker):
     from paper_1907_04417_amd import workloads
     Ps, paths, _ = workloads.load_batch("batch6")
     _run(checker, "--batch", *paths)
+
+
+def test_invalid_colouring_is_rejected(checker, tmp_path):
+    """A smoother stage that couples two of its groups (all groups put in
+    stage 0) is rejected by the host layout code before any device work."""
+    import subprocess
+    from hierpatch import patched_copy, read_chunk
+    from paper_1907_04417_amd import workloads
+    _, path, _ = workloads.load("jump16")
+    sptr = read_chunk(path, "A0.sptr")
+    assert len(sptr) > 2
+    bad = str(tmp_path / "bad_stages.bin")
+    patched_copy(path, bad, "A0.sptr", lambda v: np.where(np.arange(len(v)) == 0, 0, v[-1]))
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    r = subprocess.run([checker, bad], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 3 and "couples two of its groups" in r.stderr, r.stderr
