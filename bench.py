@@ -34,6 +34,7 @@ import json
 import os
 import re
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -272,7 +273,7 @@ def main():
     log(f"[bench] setup {args.workload}: n={P.n} nnz={P.nnz} levels={st['n']} opc={st['opc']:.3f} "
         f"({time.time() - t0:.1f}s)")
     S = mvamg.Solver(path)
-    tune_cache = os.path.join(ROOT, "gpurun_out", "tune_cache.json")
+    tune_cache = os.environ.get("MVAMG_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "mvamg_tune.json"))
     log(f"[bench] tuning: {mvamg.tuned(S.h, tune_cache)}")
     stream = torch.cuda.current_stream()
     b = torch.from_numpy(P.b).cuda()
