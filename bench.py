@@ -184,7 +184,7 @@ def bench_multi_rhs(args, torch, mvamg, workloads, tune_cache):
         "fp32_cycle": {"value": 32e3 / r32["ms"], "ms_per_block_solve": r32["ms"], "nit": r32["its"],
                        "speedup_vs_single_fp64": res[64]["ms_single_total"] / r32["ms"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": kernels[dom]["gbs"] / HBM_PEAK_GBS, "traffic": None},
+                     "frac": kernels[dom]["gbs"] / HBM_PEAK_GBS, "traffic": recorded_traffic(dom, "aniso1024x32")},
         "kernels": kernels,
     }
 

@@ -119,6 +119,16 @@ __device__ __forceinline__ void bcol_partials(double a, int v, double* part) {
 // rows handled per 256-thread block and step of a row-per-half-wave loop
 constexpr int kRowsPerBlock = kBlock / kNB;
 
+// Logical block index with consecutive logical blocks on one XCD.  Blocks are
+// handed to the 8 XCDs round robin (block b to XCD b % 8) and each XCD has
+// its own L2; a block of a block-vector kernel covers only 8 rows, so rows
+// that share neighbours are spread over all L2s unless XCD x works on one
+// contiguous run of logical blocks.  A bijection of [0, nb) for any nb.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+  return x * q + min(x, r) + i;
+}
+
 // out[p][c] = in[perm[p]][c] for c < m (in: n x m row-major), 0 for c >= m
 __global__ __launch_bounds__(kBlock) void k_bgather(int n, const int* __restrict__ perm, int m,
                                                     const double* __restrict__ in, double* __restrict__ out) {
@@ -192,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_bgs_sell(const Slab* __restrict__ sl
                                                      const int* __restrict__ col, const T* __restrict__ val,
                                                      const T* __restrict__ diag, const T* __restrict__ r, T* x,
                                                      int lim) {
-  const int hw = (blockIdx.x * kBlock + threadIdx.x) >> 5;
+  const int hw = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) >> 5;
   const int s = s0 + (hw >> 6), i = hw & 63;
   if (s >= s1) return;
   const Slab sl = slabs[s];
@@ -240,7 +250,8 @@ __global__ __launch_bounds__(kBlock) void k_bresid_sell(const Slab* __restrict__
   const int c = threadIdx.x & 31;
   double dsum = 0.0;
   const int nhw = nslabs * 64;
-  for (int hw = (blockIdx.x * kBlock + threadIdx.x) >> 5; hw < nhw; hw += gridDim.x * kRowsPerBlock) {
+  for (int hw = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) >> 5; hw < nhw;
+       hw += gridDim.x * kRowsPerBlock) {
     const Slab sl = slabs[hw >> 6];
     const int i = hw & 63;
     if (i >= sl.nrows) continue;
@@ -322,7 +333,8 @@ __global__ __launch_bounds__(kBlock) void k_bgs_grp(int g0, int g1, const int* _
                                                     const int* __restrict__ col, const T* __restrict__ val,
                                                     const T* __restrict__ dblk, const T* __restrict__ r, T* x,
                                                     int backward) {
-  const int g = __builtin_amdgcn_readfirstlane(g0 + (int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6));
+  const int g = __builtin_amdgcn_readfirstlane(g0 + xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) +
+                                               (int)(threadIdx.x >> 6));
   if (g >= g1) return;
   const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
   const int* R = rec + (size_t)g * kRec;
@@ -396,7 +408,8 @@ __global__ __launch_bounds__(kBlock) void k_bresid_grp(int ng, const int* __rest
                                                        double* __restrict__ part) {
   const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
   double dsum = 0.0;
-  const int gfirst = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6));
+  const int gfirst = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) +
+                                                    (int)(threadIdx.x >> 6));
   for (int g = gfirst; g < ng; g += gridDim.x * (kBlock / 64)) {
     const int* R = rec + (size_t)g * kRec;
     const int p0 = R[0], k = R[1];
@@ -522,7 +535,7 @@ __global__ __launch_bounds__(kBlock) void k_bprolong_rows(int n, const int* __re
                                                           const T* __restrict__ Urow, const T* __restrict__ xc,
                                                           T* __restrict__ x) {
   const int c = threadIdx.x & 31;
-  for (int i = (blockIdx.x * kBlock + threadIdx.x) >> 5; i < n; i += gridDim.x * kRowsPerBlock) {
+  for (int i = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) >> 5; i < n; i += gridDim.x * kRowsPerBlock) {
     const int ci = cinfo[i];
     const int c0 = ci >> 3, k = (ci & 7) + 1;
     T t = T(0);

@@ -66,10 +66,18 @@ int bgrid_elem(int64_t rows) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, 65535));
 }
 
-// grid of the block residual kernels (grid-stride, one partial per block)
-int bresid_grid(const DevLevel& L) {
-  if (L.sell) return bgrid_for((int64_t)L.nslabs * 64);
-  return (int)std::max<int64_t>(1, std::min<int64_t>((L.ng + 3) / 4, 2048));
+// grid of the block residual kernels (grid-stride).  With per-column
+// partial sums (MODE 1) at most one block per slab (or per four groups),
+// capped at kMaxBlockParts partials per column; otherwise one row per half
+// wave (one group per wave).
+constexpr int kMaxBlockParts = 16384;
+int bresid_grid(const DevLevel& L, int mode) {
+  if (L.sell) {
+    const int64_t b = (mode == 1) ? L.nslabs : (int64_t)L.nslabs * (64 / kRowsPerBlock);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, mode == 1 ? kMaxBlockParts : (int64_t)1 << 24));
+  }
+  const int64_t b = (L.ng + 3) / 4;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, mode == 1 ? kMaxBlockParts : (int64_t)1 << 24));
 }
 
 void ensure_block(mvamg_hier* h) {
@@ -98,7 +106,7 @@ void ensure_block(mvamg_hier* h) {
   h->co.bz = h->dalloc<double>((size_t)h->co.n * kNB);
   h->co.bsplit = h->dalloc<double>((size_t)kGemmMaxSplit * h->co.n * kNB);
   int nparts = 2048;
-  for (int l = 0; l + 1 < h->nl; ++l) nparts = std::max(nparts, bresid_grid(h->lv[l]));
+  for (int l = 0; l + 1 < h->nl; ++l) nparts = std::max(nparts, bresid_grid(h->lv[l], 1));
   ensure_multi(h, kNB, nparts);
   h->blk_ready = true;
 }
@@ -154,7 +162,7 @@ void bresid(mvamg_hier* h, const DevLevel& L, const T* r, const T* x, T* s, int 
   const int kc = MODE != 0 ? MVAMG_KC_SPMV : MVAMG_KC_RESIDUAL;
   const double by = (double)L.nnz * (sizeof(T) + 4) + 4.0 * (L.n + 1) +
                     (double)L.n * kNB * sizeof(T) * (MODE != 0 ? 2 : 3);
-  const int grid = bresid_grid(L);
+  const int grid = bresid_grid(L, MODE);
   double* part = h->mb.part;
   if (L.sell) {
     klaunch(h, kc, by, k_bresid_sell<T, MODE>, grid, kBlock, st, L.slabs, L.nslabs, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part);

@@ -2,7 +2,8 @@
 
     python -m paper_1907_04417_amd.measure run [workload] [steps]
         a plain 256 MiB device copy (counter calibration) followed by `steps`
-        binary64 solves; meant to run under rocprofv3.
+        binary64 solves; meant to run under rocprofv3.  Workload
+        aniso1024x32: the 32-column block solve on aniso1024.
     python -m paper_1907_04417_amd.measure traffic <fetch.csv> <write.csv> <workload>
         per-launch HBM traffic of every kernel class from two rocprofv3 --pmc
         runs (FETCH_SIZE, WRITE_SIZE), each scaled by the ratio of the copy's
@@ -24,9 +25,22 @@ COPY_BYTES = 256 << 20
 
 def kernel_class(name: str) -> str | None:
     """Kernel class (as in mvamg_kernel_stats) of a binary64 cycle kernel symbol."""
+    if "k_bgemm" in name or "k_bsum_splits" in name:
+        return "coarse_solve"
     if "double" not in name and "k_gemv" not in name:
         return None
-    if "k_gs_sell" in name or "k_zero_stage0_point" in name:
+    if "k_bgs_sell" in name or "k_bstage0_point" in name:
+        return "smooth_fine"
+    if "k_bgs_grp" in name or "k_bzero_stage0_grp" in name:
+        return "smooth_coarse"
+    m = re.search(r"k_bresid_(sell|grp)<double,(?:\d,)?(\d)>", name.replace(" ", ""))
+    if m:
+        return "spmv" if m.group(2) == "1" else "residual"
+    if "k_brestrict" in name:
+        return "restrict"
+    if "k_bprolong_rows" in name:
+        return "prolong"
+    if "k_gs_sell" in name or "k_stage0_point" in name:
         return "smooth_fine"
     if "k_gs_grp" in name or "k_zero_stage0_grp" in name:
         return "smooth_coarse"
@@ -53,12 +67,22 @@ def run(workload: str = "jump128", steps: int = 3) -> None:
     c.copy_(a)  # the calibration copy: reads and writes COPY_BYTES
     torch.cuda.synchronize()
     del a, c
-    P, path, st = workloads.load(workload)
-    S = mvamg.Solver(path)
-    b = torch.from_numpy(P.b).cuda()
-    for _ in range(steps):
-        x = torch.zeros_like(b)
-        mvamg.pcg_solve(S.h, b, x, rtol=1e-8)
+    if workload == "aniso1024x32":
+        from . import problems
+        P, path, st = workloads.load("aniso1024")
+        S = mvamg.Solver(path)
+        B, _ = problems.block_rhs(P, 32, seed=workloads.BLOCK_RHS_SEED)
+        Bd = torch.from_numpy(B).cuda()
+        for _ in range(steps):
+            X = torch.zeros_like(Bd)
+            mvamg.pcg_solve_block(S.h, Bd, X, rtol=1e-8)
+    else:
+        P, path, st = workloads.load(workload)
+        S = mvamg.Solver(path)
+        b = torch.from_numpy(P.b).cuda()
+        for _ in range(steps):
+            x = torch.zeros_like(b)
+            mvamg.pcg_solve(S.h, b, x, rtol=1e-8)
     torch.cuda.synchronize()
     print(f"measure run done: {workload} x{steps}", flush=True)
 
@@ -80,7 +104,9 @@ def traffic(fetch_csv: str, write_csv: str, workload: str) -> None:
             d = int(r["Dispatch_Id"])
             per[d] += float(r["Counter_Value"])
             names[d] = r["Kernel_Name"]
-        copy = [d for d, n in names.items() if "copy" in n.lower() or "elementwise" in n.lower()]
+        # the calibration copy: the runtime's / torch's copy kernel, not the library's own k_copy
+        copy = [d for d, n in names.items()
+                if ("copy" in n.lower() or "elementwise" in n.lower()) and "mvamg" not in n]
         copy_kib = max((per[d] for d in copy), default=0.0)
         scale = (COPY_BYTES / 1024.0) / copy_kib if copy_kib > 0 else 1.0
         acc = defaultdict(lambda: [0, 0.0])
