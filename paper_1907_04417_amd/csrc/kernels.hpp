@@ -20,6 +20,17 @@ namespace mvamg {
 
 constexpr int kBlock = 256;
 
+// Logical block index with consecutive logical blocks on one XCD.  Blocks are
+// handed to the 8 XCDs round robin (block b to XCD b % 8) and each XCD has
+// its own L2.  Rows that share neighbours (or, in a transfer, the residual
+// lines of neighbouring aggregates) sit in nearby blocks; handed out round
+// robin they are fetched once per XCD, unless XCD x works on one contiguous
+// run of logical blocks.  A bijection of [0, nb) for any nb.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+  return x * q + min(x, r) + i;
+}
+
 // ----------------------------------------------------------- reductions
 
 enum Scalar {
@@ -245,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ sla
                                                     const int* __restrict__ col, const T* __restrict__ val,
                                                     const T* __restrict__ diag, const T* __restrict__ r, T* x,
                                                     Skip sk, int lim) {
-  const int s = s0 + blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
   if (s >= s1 || skipped(sk, s)) return;
   const int lane = threadIdx.x & 63;
   const Slab sl = slabs[s];
@@ -288,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
                                                        const int* __restrict__ col, const T* __restrict__ val,
                                                        const T* __restrict__ diag, const T* __restrict__ r,
                                                        const T* __restrict__ x, T* __restrict__ s, Red red, Skip sk) {
-  const int sidx = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int sidx = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   double dsum = 0.0;
   if (sidx < nslabs && !skipped(sk, sidx)) {
@@ -418,7 +429,7 @@ template <typename T, int KMAX, int BACK>
 __global__ __launch_bounds__(kBlock) void k_gs_grp(int g0, int g1, const int* __restrict__ rec,
                                                    const int* __restrict__ col, const T* __restrict__ val,
                                                    const T* __restrict__ dblk, const T* __restrict__ r, T* x) {
-  const int graw = g0 + (int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
+  const int graw = g0 + xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (int)(threadIdx.x >> 6);
   const int g = __builtin_amdgcn_readfirstlane(min(graw, g1 - 1));
   const int lane = threadIdx.x & 63;
   const int l = lane / (64 / KMAX), sub = lane % (64 / KMAX);
@@ -489,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_grp(int ng, const int* __restr
                                                       const int* __restrict__ col, const T* __restrict__ val,
                                                       const T* __restrict__ dblk, const T* __restrict__ r,
                                                       const T* __restrict__ x, T* __restrict__ s, Red red) {
-  const int graw = (int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
+  const int graw = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (int)(threadIdx.x >> 6);
   const int g = __builtin_amdgcn_readfirstlane(min(graw, ng - 1));
   const int lane = threadIdx.x & 63;
   const int l = lane / (64 / KMAX), sub = lane % (64 / KMAX);
@@ -570,42 +581,68 @@ __global__ __launch_bounds__(kBlock) void k_l1norm_grp(int ng, const int* __rest
 
 // ------------------------------------------------------------- transfers
 
+// Per-aggregate record of a transfer, kARec ints: first entry of the
+// aggregate's members in arows, member count n_a, block width k, offset of
+// U_a, first coarse row, and the offset of the aggregate's k x k diagonal
+// block on the next level when that level is smoothed by Gauss-Seidel and
+// the aggregate's group there belongs to stage 0 (-1 otherwise).  One record
+// replaces the chain aggregate -> group -> block offset -> block.
+constexpr int kARec = 8;
+enum ARecField { AR_M0 = 0, AR_NA = 1, AR_K = 2, AR_UOFF = 3, AR_C0 = 4, AR_DB = 5 };
+
 // r_c = P^T s with P = blockdiag(U_a): one wave per aggregate, lane li takes
-// member li; r_c[cst_a + l] = sum_li U_a[li, l] s[member li].  U_a is stored
-// column-major (U[l * n_a + li]).
+// member li; r_c[c0 + l] = sum_li U_a[li, l] s[member li].  U_a is stored
+// column-major (U[l * n_a + li]); KMAX bounds the block widths k.
 //
 // The k coarse rows of an aggregate are one smoother group of the next level,
 // so the kernel can also start that level's pre-smoothing from x_c = 0
 // (INIT = 1: the groups of stage 0 solve their lower-triangular diagonal block,
 // the others are zero -- the first Gauss-Seidel stage; INIT = 2: x_c = r_c / d_l1,
-// the first l1-Jacobi sweep).  cgrp[a] is the group of aggregate a on the next
-// level, ng0 the number of groups in its stage 0.
-template <typename T, int INIT>
-__global__ __launch_bounds__(kBlock) void k_restrict(int nagg, const int* __restrict__ aptr,
-                                                     const int* __restrict__ arows, const int* __restrict__ uoff,
-                                                     const int* __restrict__ cst, const int* __restrict__ kk,
-                                                     const T* __restrict__ U, const T* __restrict__ s,
-                                                     T* __restrict__ rc, const int* __restrict__ cgrp, int ng0,
-                                                     const int* __restrict__ cdboff, const T* __restrict__ cdblk,
-                                                     const T* __restrict__ cdl1, T* __restrict__ xc, Skip sk) {
-  const int a = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+// the first l1-Jacobi sweep).  The record, then U_a, the member rows and the
+// diagonal block's lower triangle are all requested before the gather of s.
+template <typename T, int KMAX, int INIT>
+__global__ __launch_bounds__(kBlock) void k_restrict(int nagg, const int* __restrict__ arec,
+                                                     const int* __restrict__ arows, const T* __restrict__ U,
+                                                     const T* __restrict__ s, T* __restrict__ rc,
+                                                     const T* __restrict__ cdblk, const T* __restrict__ cdl1,
+                                                     T* __restrict__ xc, Skip sk) {
+  const int a = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) +
+                                               (int)(threadIdx.x >> 6));
   if (a >= nagg || skipped(sk, a)) return;
   const int lane = threadIdx.x & 63;
-  const int m0 = aptr[a], na = aptr[a + 1] - m0, k = kk[a];
-  const T* Ua = U + uoff[a];
-  T acc[kKmax];
+  const int* R = arec + (size_t)a * kARec;
+  const int m0 = R[AR_M0], na = R[AR_NA], k = R[AR_K], c0 = R[AR_C0];
+  const T* Ua = U + R[AR_UOFF];
+  // lower triangle of the diagonal block (indices clamped into the k x k
+  // block; a record without a block reads the level's first block, which is
+  // at least k x k, and discards it)
+  constexpr int NB = (INIT == 1) ? KMAX * (KMAX + 1) / 2 : 1;
+  T bl[NB];
+  int db = -1;
+  if (INIT == 1) {
+    db = R[AR_DB];
+    const T* B = cdblk + max(db, 0);
 #pragma unroll
-  for (int q = 0; q < kKmax; ++q) acc[q] = T(0);
-  for (int li = lane; li < na; li += 64) {
-    const T sv = s[arows[m0 + li]];
+    for (int l = 0; l < KMAX; ++l)
 #pragma unroll
-    for (int q = 0; q < kKmax; ++q)
-      if (q < k) acc[q] += Ua[q * na + li] * sv;
+      for (int q = 0; q <= l; ++q) bl[l * (l + 1) / 2 + q] = B[min(l, k - 1) * k + min(q, k - 1)];
   }
-  const int c0 = cst[a];
+  T acc[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) acc[q] = T(0);
+  for (int li = lane; li < na; li += 64) {
+    const int row = arows[m0 + li];
+    T u[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) u[q] = Ua[min(q, k - 1) * na + li];
+    const T sv = s[row];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q)
+      if (q < k) acc[q] += u[q] * sv;
+  }
   // wave sums (DPP inside each 16-lane row, then the four row sums in order)
 #pragma unroll
-  for (int q = 0; q < kKmax; ++q) {
+  for (int q = 0; q < KMAX; ++q) {
     if (q < k) {
       const T v = lanes_sum<16>(acc[q]);
       acc[q] = ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
@@ -613,59 +650,21 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nagg, const int* __rest
     }
   }
   if (INIT == 1) {
-    const int g = cgrp[a];
-    T xv[kKmax];
-    if (g < ng0) {
-      const T* B = cdblk + cdboff[g];
+    T xv[KMAX];
 #pragma unroll
-      for (int l = 0; l < kKmax; ++l) {
-        xv[l] = T(0);
-        if (l < k) {
-          T t = acc[l];
+    for (int l = 0; l < KMAX; ++l) {
+      T t = acc[l];
 #pragma unroll
-          for (int q = 0; q < kKmax; ++q)
-            if (q < l) t -= B[l * k + q] * xv[q];
-          xv[l] = t / B[l * k + l];
-        }
-      }
-    } else {
-#pragma unroll
-      for (int l = 0; l < kKmax; ++l) xv[l] = T(0);
+      for (int q = 0; q < l; ++q) t -= bl[l * (l + 1) / 2 + q] * xv[q];
+      xv[l] = (db >= 0 && l < k) ? t / bl[l * (l + 1) / 2 + l] : T(0);
     }
 #pragma unroll
-    for (int q = 0; q < kKmax; ++q)
+    for (int q = 0; q < KMAX; ++q)
       if (q < k && lane == q) xc[c0 + q] = xv[q];
   } else if (INIT == 2) {
 #pragma unroll
-    for (int q = 0; q < kKmax; ++q)
+    for (int q = 0; q < KMAX; ++q)
       if (q < k && lane == q) xc[c0 + q] = acc[q] / cdl1[c0 + q];
-  }
-}
-
-// x += P x_c: lane li of the aggregate's wave updates member li.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong(int nagg, const int* __restrict__ aptr,
-                                                    const int* __restrict__ arows, const int* __restrict__ uoff,
-                                                    const int* __restrict__ cst, const int* __restrict__ kk,
-                                                    const T* __restrict__ U, const T* __restrict__ xc,
-                                                    T* __restrict__ x) {
-  const int a = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  if (a >= nagg) return;
-  const int lane = threadIdx.x & 63;
-  const int m0 = aptr[a], na = aptr[a + 1] - m0, k = kk[a], c0 = cst[a];
-  const T* Ua = U + uoff[a];
-  T xv[kKmax];
-#pragma unroll
-  for (int q = 0; q < kKmax; ++q) {
-    const T xq = xc[c0 + min(q, k - 1)];
-    xv[q] = (q < k) ? xq : T(0);
-  }
-  for (int li = lane; li < na; li += 64) {
-    T t = T(0);
-#pragma unroll
-    for (int q = 0; q < kKmax; ++q)
-      if (q < k) t += Ua[q * na + li] * xv[q];
-    x[arows[m0 + li]] += t;
   }
 }
 
@@ -676,7 +675,7 @@ template <typename T, int KMAX>
 __global__ __launch_bounds__(kBlock) void k_prolong_rows(int n, const int* __restrict__ cinfo,
                                                          const T* __restrict__ Urow, const T* __restrict__ xc,
                                                          T* __restrict__ x, Skip sk) {
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+  for (int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     if (skipped(sk, i)) continue;
     const int ci = cinfo[i];
     const int c0 = ci >> 3, k = (ci & 7) + 1;

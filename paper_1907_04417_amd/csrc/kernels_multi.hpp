@@ -119,16 +119,6 @@ __device__ __forceinline__ void bcol_partials(double a, int v, double* part) {
 // rows handled per 256-thread block and step of a row-per-half-wave loop
 constexpr int kRowsPerBlock = kBlock / kNB;
 
-// Logical block index with consecutive logical blocks on one XCD.  Blocks are
-// handed to the 8 XCDs round robin (block b to XCD b % 8) and each XCD has
-// its own L2; a block of a block-vector kernel covers only 8 rows, so rows
-// that share neighbours are spread over all L2s unless XCD x works on one
-// contiguous run of logical blocks.  A bijection of [0, nb) for any nb.
-__device__ __forceinline__ int xcd_block(int b, int nb) {
-  const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
-  return x * q + min(x, r) + i;
-}
-
 // out[p][c] = in[perm[p]][c] for c < m (in: n x m row-major), 0 for c >= m
 __global__ __launch_bounds__(kBlock) void k_bgather(int n, const int* __restrict__ perm, int m,
                                                     const double* __restrict__ in, double* __restrict__ out) {
@@ -460,21 +450,21 @@ __global__ __launch_bounds__(kBlock) void k_bl1_update(int n, const T* __restric
 
 // r_c = P^T s for block vectors: wave per aggregate, half wave h takes members
 // h, h + 2, ... (four in flight), the halves are added with one exchange.
-// INIT as in k_restrict (1: first Gauss-Seidel stage of the next level from
-// x_c = 0, 2: first l1-Jacobi step).
+// Aggregate records and INIT as in k_restrict (1: first Gauss-Seidel stage of
+// the next level from x_c = 0, 2: first l1-Jacobi step).
 template <typename T, int INIT>
-__global__ __launch_bounds__(kBlock) void k_brestrict(int nagg, const int* __restrict__ aptr,
-                                                      const int* __restrict__ arows, const int* __restrict__ uoff,
-                                                      const int* __restrict__ cst, const int* __restrict__ kk,
-                                                      const T* __restrict__ U, const T* __restrict__ s,
-                                                      T* __restrict__ rc, const int* __restrict__ cgrp, int ng0,
-                                                      const int* __restrict__ cdboff, const T* __restrict__ cdblk,
-                                                      const T* __restrict__ cdl1, T* __restrict__ xc) {
-  const int a = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+__global__ __launch_bounds__(kBlock) void k_brestrict(int nagg, const int* __restrict__ arec,
+                                                      const int* __restrict__ arows, const T* __restrict__ U,
+                                                      const T* __restrict__ s, T* __restrict__ rc,
+                                                      const T* __restrict__ cdblk, const T* __restrict__ cdl1,
+                                                      T* __restrict__ xc) {
+  const int a = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) +
+                                               (int)(threadIdx.x >> 6));
   if (a >= nagg) return;
   const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
-  const int m0 = aptr[a], na = aptr[a + 1] - m0, k = kk[a];
-  const T* Ua = U + uoff[a];
+  const int* R = arec + (size_t)a * kARec;
+  const int m0 = R[AR_M0], na = R[AR_NA], k = R[AR_K];
+  const T* Ua = U + R[AR_UOFF];
   T acc[kKmax];
 #pragma unroll
   for (int q = 0; q < kKmax; ++q) acc[q] = T(0);
@@ -495,15 +485,15 @@ __global__ __launch_bounds__(kBlock) void k_brestrict(int nagg, const int* __res
   }
 #pragma unroll
   for (int q = 0; q < kKmax; ++q) acc[q] += __shfl_xor(acc[q], 32, 64);
-  const int c0 = cst[a];
+  const int c0 = R[AR_C0];
 #pragma unroll
   for (int q = 0; q < kKmax; ++q)
     if (q < k && (q & 1) == h) rc[(size_t)(c0 + q) * kNB + c] = acc[q];
   if (INIT == 1) {
-    const int g = cgrp[a];
+    const int db = R[AR_DB];
     T xv[kKmax];
-    if (g < ng0) {
-      const T* B = cdblk + cdboff[g];
+    if (db >= 0) {
+      const T* B = cdblk + db;
 #pragma unroll
       for (int l = 0; l < kKmax; ++l) {
         xv[l] = T(0);

@@ -242,17 +242,14 @@ void bvcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t s
   const double tby = (double)P.nu * sizeof(T) + (double)L.n * (4 + kNB * sizeof(T)) + (double)C.n * kNB * sizeof(T);
   const bool next_smoothed = (l + 2 < h->nl);
   if (!next_smoothed) {
-    klaunch(h, MVAMG_KC_RESTRICT, tby, k_brestrict<T, 0>, tg, kBlock, st, P.nagg, P.aptr, P.arows, P.uoff, P.cst,
-            P.kk, tU<T>(P), s, rc, (const int*)nullptr, 0, (const int*)nullptr, (const T*)nullptr,
-            (const T*)nullptr, (T*)nullptr);
+    klaunch(h, MVAMG_KC_RESTRICT, tby, k_brestrict<T, 0>, tg, kBlock, st, P.nagg, P.arec, P.arows, tU<T>(P), s, rc,
+            (const T*)nullptr, (const T*)nullptr, (T*)nullptr);
   } else if (smoother == MVAMG_SMOOTH_GS) {
     klaunch(h, MVAMG_KC_RESTRICT, tby + (double)C.n * kNB * sizeof(T), k_brestrict<T, 1>, tg, kBlock, st, P.nagg,
-            P.aptr, P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc, P.cgrp, C.h_sgrp[1], C.dboff, ldblk<T>(C),
-            (const T*)nullptr, xc);
+            P.arec, P.arows, tU<T>(P), s, rc, ldblk<T>(C), (const T*)nullptr, xc);
   } else {
     klaunch(h, MVAMG_KC_RESTRICT, tby + (double)C.n * kNB * sizeof(T), k_brestrict<T, 2>, tg, kBlock, st, P.nagg,
-            P.aptr, P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc, (const int*)nullptr, 0, (const int*)nullptr,
-            (const T*)nullptr, ldl1<T>(C), xc);
+            P.arec, P.arows, tU<T>(P), s, rc, (const T*)nullptr, ldl1<T>(C), xc);
   }
   LAUNCHCHECK("brestrict");
   bvcycle<T>(h, l + 1, rc, xc, smoother, st, next_smoothed);

@@ -96,8 +96,8 @@ struct DevLevel {
 
 struct DevTransfer {
   int nagg = 0;
-  int *aptr = nullptr, *arows = nullptr, *uoff = nullptr, *cst = nullptr, *kk = nullptr;
-  int* cgrp = nullptr;  // group of each aggregate on the next level (if that level is smoothed)
+  int* arows = nullptr;  // member rows of every aggregate (level order), runs given by the records
+  int* arec = nullptr;  // per-aggregate records (kARec ints each)
   int* aprob = nullptr; // batch, level 0: problem of every aggregate
   int nf = 0, kmax = 1;  // fine rows, widest block
   int64_t nu = 0;        // entries of the U blocks
@@ -505,19 +505,29 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   const int tg = (P.nagg + 3) / 4;
   const double tby = skip_bytes(h, l, (double)P.nu * sizeof(T) + (double)L.n * (4 + sizeof(T)) + (double)C.n * sizeof(T));
   const bool next_smoothed = (l + 2 < h->nl);
-  if (!next_smoothed) {
-    klaunch(h, MVAMG_KC_RESTRICT, tby, k_restrict<T, 0>, tg, kBlock, st, P.nagg, P.aptr, P.arows, P.uoff, P.cst,
-            P.kk, tU<T>(P), s, rc, (const int*)nullptr, 0, (const int*)nullptr, (const T*)nullptr,
-            (const T*)nullptr, (T*)nullptr, lskip(h, l, SKIP_AGG));
-  } else if (smoother == MVAMG_SMOOTH_GS) {
-    klaunch(h, MVAMG_KC_RESTRICT, tby + skip_bytes(h, l, (double)C.n * sizeof(T)), k_restrict<T, 1>, tg, kBlock, st, P.nagg, P.aptr,
-            P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc, P.cgrp, C.h_sgrp[1], C.dboff, ldblk<T>(C),
-            (const T*)nullptr, xc, lskip(h, l, SKIP_AGG));
-  } else {
-    klaunch(h, MVAMG_KC_RESTRICT, tby + skip_bytes(h, l, (double)C.n * sizeof(T)), k_restrict<T, 2>, tg, kBlock, st, P.nagg, P.aptr,
-            P.arows, P.uoff, P.cst, P.kk, tU<T>(P), s, rc, (const int*)nullptr, 0, (const int*)nullptr,
-            (const T*)nullptr, ldl1<T>(C), xc, lskip(h, l, SKIP_AGG));
+  const int init = !next_smoothed ? 0 : (smoother == MVAMG_SMOOTH_GS ? 1 : 2);
+  const double iby = next_smoothed ? skip_bytes(h, l, (double)C.n * sizeof(T)) : 0.0;
+  const T* cdblk = init == 1 ? ldblk<T>(C) : nullptr;
+  const T* cdl1 = init == 2 ? ldl1<T>(C) : nullptr;
+  T* xcs = init != 0 ? xc : nullptr;
+  const Skip ask = lskip(h, l, SKIP_AGG);
+#define MVAMG_RESTRICT(KM)                                                                                        \
+  switch (init) {                                                                                                 \
+    case 0: klaunch(h, MVAMG_KC_RESTRICT, tby, k_restrict<T, KM, 0>, tg, kBlock, st, P.nagg, P.arec, P.arows,   \
+                    tU<T>(P), s, rc, cdblk, cdl1, xcs, ask); break;                                               \
+    case 1: klaunch(h, MVAMG_KC_RESTRICT, tby + iby, k_restrict<T, KM, 1>, tg, kBlock, st, P.nagg, P.arec,      \
+                    P.arows, tU<T>(P), s, rc, cdblk, cdl1, xcs, ask); break;                                      \
+    default: klaunch(h, MVAMG_KC_RESTRICT, tby + iby, k_restrict<T, KM, 2>, tg, kBlock, st, P.nagg, P.arec,     \
+                     P.arows, tU<T>(P), s, rc, cdblk, cdl1, xcs, ask); break;                                     \
   }
+  switch (P.kmax) {
+    case 1: MVAMG_RESTRICT(1); break;
+    case 2: MVAMG_RESTRICT(2); break;
+    case 3:
+    case 4: MVAMG_RESTRICT(4); break;
+    default: MVAMG_RESTRICT(8); break;
+  }
+#undef MVAMG_RESTRICT
   LAUNCHCHECK("restrict");
   vcycle<T>(h, l + 1, rc, xc, smoother, st, next_smoothed);
   {
@@ -879,24 +889,33 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
       DevTransfer& P = h->tr[l];
       P.nagg = T.nagg;
       P.nu = (int64_t)T.U.size();
-      P.aptr = h->upload_vec(T.aptr, st);
       P.arows = h->upload_vec(T.arows, st);
-      P.uoff = h->upload_vec(T.uoff, st);
-      P.cst = h->upload_vec(T.cst, st);
-      P.kk = h->upload_vec(T.kk, st);
-      if (l + 2 < H.nl) {
-        // group index, on level l+1, of the rows cst[a] .. cst[a] + k - 1
-        const LevelLayout& yc = Y[l + 1];
-        std::vector<int> rowgrp(yc.n), cg(T.nagg);
-        for (int g = 0; g + 1 < (int)yc.gstart.size(); ++g)
-          for (int p = yc.gstart[g]; p < yc.gstart[g + 1]; ++p) rowgrp[p] = g;
+      {
+        // per-aggregate records; when level l+1 is smoothed, the coarse rows
+        // cst[a] .. cst[a] + k - 1 must be one of its smoother groups
+        std::vector<int> rec((size_t)T.nagg * kARec, 0);
         for (int a = 0; a < T.nagg; ++a) {
-          const int g = rowgrp[T.cst[a]];
-          if (yc.gstart[g] != T.cst[a] || yc.gstart[g + 1] - yc.gstart[g] != T.kk[a])
-            throw Error(MVAMG_ERR_FILE, "coarse dofs of an aggregate are not one smoother group");
-          cg[a] = g;
+          int* R = rec.data() + (size_t)a * kARec;
+          R[AR_M0] = T.aptr[a];
+          R[AR_NA] = T.aptr[a + 1] - T.aptr[a];
+          R[AR_K] = T.kk[a];
+          R[AR_UOFF] = T.uoff[a];
+          R[AR_C0] = T.cst[a];
+          R[AR_DB] = -1;
         }
-        P.cgrp = h->upload_vec(cg, st);
+        if (l + 2 < H.nl) {
+          const LevelLayout& yc = Y[l + 1];
+          std::vector<int> rowgrp(yc.n);
+          for (int g = 0; g + 1 < (int)yc.gstart.size(); ++g)
+            for (int p = yc.gstart[g]; p < yc.gstart[g + 1]; ++p) rowgrp[p] = g;
+          for (int a = 0; a < T.nagg; ++a) {
+            const int g = rowgrp[T.cst[a]];
+            if (yc.gstart[g] != T.cst[a] || yc.gstart[g + 1] - yc.gstart[g] != T.kk[a])
+              throw Error(MVAMG_ERR_FILE, "coarse dofs of an aggregate are not one smoother group");
+            if (g < yc.sgrp[1]) rec[(size_t)a * kARec + AR_DB] = yc.dboff[g];
+          }
+        }
+        P.arec = h->upload_vec(rec, st);
       }
       P.U = h->upload_vec(T.U, st);
       P.U32 = h->dalloc<float>(T.U.size());
