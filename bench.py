@@ -56,11 +56,15 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    """Hash of what per-launch traffic depends on: the kernel and layout
+    sources, and the setup source that writes the hierarchies (stage counts,
+    aggregates)."""
     h = hashlib.sha1()
     d = os.path.join(ROOT, "paper_1907_04417_amd", "csrc")
     for f in sorted(os.listdir(d)):
         if f.endswith((".hpp", ".hip")):
             h.update(open(os.path.join(d, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_1907_04417_amd", "setup", "mvsetup.cpp"), "rb").read())
     return h.hexdigest()[:12]
 
 

@@ -30,6 +30,7 @@
 // of threads (fixed-size chunks for reductions, per-row independent work).
 
 #include <algorithm>
+#include <random>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -156,10 +157,107 @@ void gs_sweep(const Csr& A, const std::vector<double>& d, const Colouring& C,
   }
 }
 
+// Lowers the number of colours of a proper colouring of the graph (gp, gi)
+// (CSR, no self loops) by tabu search -- TabuCol (Hertz and de Werra, 1987)
+// with the tabu tenure of Galinier and Hao (1999).  For a target of k colours
+// the vertices coloured k or higher take their least-conflicting colour below
+// k; then, repeatedly, the move of one conflicting vertex to another colour
+// that lowers the number of monochromatic edges most is made (ties broken by a
+// fixed-seed generator, moves back to a recently left colour forbidden for
+// 10 + U{0..9} + 0.6 * conflicts moves unless they reach a new best).  A target
+// reached without conflicts replaces the colouring and the next lower one is
+// tried; the search stops at the first target not reached within `budget`
+// move evaluations.  Deterministic for a given graph and start.
+int reduce_colours(const std::vector<int>& gp, const std::vector<int>& gi, std::vector<int>& col, int ncol,
+                   int64_t budget) {
+  const int n = (int)col.size();
+  std::mt19937 rng(20260101u);
+  for (int k = ncol - 1; k >= 2; --k) {
+    std::vector<int> c2 = col;
+    std::vector<int> cnt(k);
+    for (int g = 0; g < n; ++g)
+      if (c2[g] >= k) c2[g] = -1;
+    for (int g = 0; g < n; ++g)
+      if (c2[g] < 0) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (int e = gp[g]; e < gp[g + 1]; ++e)
+          if (c2[gi[e]] >= 0) cnt[c2[gi[e]]]++;
+        c2[g] = (int)(std::min_element(cnt.begin(), cnt.end()) - cnt.begin());
+      }
+    std::vector<int> gamma((size_t)n * k, 0);  // neighbours of g with colour c
+    for (int g = 0; g < n; ++g)
+      for (int e = gp[g]; e < gp[g + 1]; ++e) gamma[(size_t)g * k + c2[gi[e]]]++;
+    std::vector<int> cv, cpos(n, -1);  // conflicting vertices
+    auto track = [&](int g) {
+      const bool in = gamma[(size_t)g * k + c2[g]] > 0;
+      if (in && cpos[g] < 0) {
+        cpos[g] = (int)cv.size();
+        cv.push_back(g);
+      } else if (!in && cpos[g] >= 0) {
+        const int last = cv.back();
+        cv[cpos[g]] = last;
+        cpos[last] = cpos[g];
+        cv.pop_back();
+        cpos[g] = -1;
+      }
+    };
+    int64_t conf = 0;
+    for (int g = 0; g < n; ++g) {
+      conf += gamma[(size_t)g * k + c2[g]];
+      track(g);
+    }
+    conf /= 2;
+    std::vector<int64_t> tabu((size_t)n * k, 0);
+    int64_t it = 0, evals = 0, best = conf;
+    while (conf > 0 && evals < budget) {
+      ++it;
+      int bg = -1, bc = -1, ties = 0;
+      int64_t bd = INT64_MAX;
+      for (const int g : cv) {
+        const int* gm = gamma.data() + (size_t)g * k;
+        const int cg = c2[g];
+        for (int c = 0; c < k; ++c) {
+          if (c == cg) continue;
+          ++evals;
+          const int64_t d = (int64_t)gm[c] - gm[cg];
+          if (tabu[(size_t)g * k + c] > it && !(conf + d < best)) continue;
+          if (d < bd) {
+            bd = d;
+            bg = g;
+            bc = c;
+            ties = 1;
+          } else if (d == bd && rng() % (uint32_t)(++ties) == 0) {
+            bg = g;
+            bc = c;
+          }
+        }
+      }
+      if (bg < 0) break;
+      const int old = c2[bg];
+      c2[bg] = bc;
+      conf += bd;
+      for (int e = gp[bg]; e < gp[bg + 1]; ++e) {
+        const int h = gi[e];
+        gamma[(size_t)h * k + old]--;
+        gamma[(size_t)h * k + bc]++;
+        track(h);
+      }
+      track(bg);
+      tabu[(size_t)bg * k + old] = it + 10 + (int64_t)(rng() % 10u) + (int64_t)(0.6 * (double)conf);
+      best = std::min(best, conf);
+    }
+    if (conf > 0) break;
+    col.swap(c2);
+    ncol = k;
+  }
+  return ncol;
+}
+
 // Smoother ordering of a multi-vector level.  Rows are split into groups of
 // consecutive indices (gstart); groups are coloured greedily (first fit, in
 // natural group order) on the graph in which two groups are adjacent when A
-// couples any of their rows.  The Gauss-Seidel order O lists the groups colour
+// couples any of their rows, and the colour count is then lowered by
+// reduce_colours (fewer colours: fewer stages, each a kernel launch).  The Gauss-Seidel order O lists the groups colour
 // by colour ("stages"), the rows of a group in increasing index.  Groups of one
 // stage are not coupled, so they can be relaxed simultaneously; the rows of a
 // group are relaxed one after the other.
@@ -184,7 +282,22 @@ GsOrder group_order(const Csr& A, const std::vector<int>& gstart) {
     if (c == (int)forbid.size()) forbid.push_back(-1);
     gcol[g] = c;
   }
-  const int ncol = (int)forbid.size();
+  int ncol = (int)forbid.size();
+  if (ncol > 2) {
+    std::vector<int> gp(G + 1, 0), gi, mark(G, -1);
+    for (int g = 0; g < G; ++g) {
+      for (int i = gstart[g]; i < gstart[g + 1]; ++i)
+        for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+          const int h = grp[A.ci[k]];
+          if (h != g && mark[h] != g) {
+            mark[h] = g;
+            gi.push_back(h);
+          }
+        }
+      gp[g + 1] = (int)gi.size();
+    }
+    ncol = reduce_colours(gp, gi, gcol, ncol, 40 * (int64_t)gi.size() + 10000000);
+  }
   GsOrder O;
   O.sptr.assign(ncol + 1, 0);
   for (int g = 0; g < G; ++g) O.sptr[gcol[g] + 1]++;

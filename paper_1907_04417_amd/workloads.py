@@ -59,6 +59,14 @@ BATCHES = {
 BOOTSTRAP_SEED = 1000
 
 
+def _setup_source_tag() -> str:
+    """Hash of the setup library's source: cached hierarchies are keyed by it,
+    so a change to the setup never reuses files an older setup wrote."""
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "setup", "mvsetup.cpp")
+    with open(src, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
+
+
 def cache_dir() -> str:
     d = os.environ.get("MVAMG_CACHE", "/tmp/mvamg_cache")
     os.makedirs(d, exist_ok=True)
@@ -72,7 +80,8 @@ def load(name: str, **setup_overrides):
     sp = dict(cfg["setup"])
     sp.update(setup_overrides)
     params = SetupParams(nvec_max=cfg["nvec"], **sp)
-    key = hashlib.sha1(json.dumps([name, sorted(params.__dict__.items())], default=str).encode()).hexdigest()[:12]
+    key = hashlib.sha1(json.dumps([name, sorted(params.__dict__.items()), _setup_source_tag()],
+                                  default=str).encode()).hexdigest()[:12]
     path = os.path.join(cache_dir(), f"{name}_{key}.bin")
     meta = path + ".json"
     if os.path.exists(path) and os.path.exists(meta):
@@ -88,7 +97,7 @@ def load(name: str, **setup_overrides):
 
 def _hierarchy(tag: str, P, nvec: int, setup: dict):
     params = SetupParams(nvec_max=nvec, **setup)
-    key = hashlib.sha1(json.dumps([tag, P.n, P.nnz, sorted(params.__dict__.items())],
+    key = hashlib.sha1(json.dumps([tag, P.n, P.nnz, sorted(params.__dict__.items()), _setup_source_tag()],
                                   default=str).encode()).hexdigest()[:12]
     path = os.path.join(cache_dir(), f"{tag}_{key}.bin")
     meta = path + ".json"

@@ -124,6 +124,24 @@ def test_hierarchy_invariants(fx, request):
         i, j = np.nonzero(A)
         off = group[i] != group[j]
         assert not np.any(stage[i[off]] == stage[j[off]])
+        # no empty stage, and never more stages than first-fit greedy colouring
+        # of the group graph in natural group order (the colour search only
+        # lowers the count)
+        assert np.all(np.diff(L.sptr) > 0)
+        first = np.array([L.order[L.gptr[g]] for g in range(len(L.gptr) - 1)])
+        rank = np.empty(len(first), int)
+        rank[np.argsort(first)] = np.arange(len(first))
+        nbrs = [set() for _ in first]
+        for a, b in zip(rank[group[i[off]]], rank[group[j[off]]]):
+            nbrs[a].add(b)
+        gcol = []
+        for g in range(len(first)):
+            used = {gcol[h] for h in nbrs[g] if h < g}
+            c = 0
+            while c in used:
+                c += 1
+            gcol.append(c)
+        assert len(L.sptr) - 1 <= max(gcol) + 1
         # per-aggregate orthonormality => P^T P = I
         Pm = dr.prolongator(T, L.n, C.n)
         np.testing.assert_allclose(Pm.T @ Pm, np.eye(C.n), atol=1e-13)
@@ -167,3 +185,39 @@ def test_setup_rejects_bad_input(setup_lib, tmp_path):
     ci = np.array([0, 1])
     with pytest.raises(RuntimeError):
         mvs.build_hierarchy(rp, ci, np.array([1.0, -1.0]), str(tmp_path / "x.bin"), np.zeros((3, 2)))
+
+
+def _first_fit_colours(L):
+    """First-fit greedy colour count of L's group graph, groups in natural order."""
+    n = L.n
+    group = np.empty(n, int)
+    for g in range(len(L.gptr) - 1):
+        group[L.order[L.gptr[g]:L.gptr[g + 1]]] = g
+    first = np.array([L.order[L.gptr[g]] for g in range(len(L.gptr) - 1)])
+    rank = np.empty(len(first), int)
+    rank[np.argsort(first)] = np.arange(len(first))
+    nbrs = [set() for _ in first]
+    for i in range(n):
+        for j in L.col[L.rowptr[i]:L.rowptr[i + 1]]:
+            a, b = rank[group[i]], rank[group[j]]
+            if a != b:
+                nbrs[a].add(b)
+    col = []
+    for g in range(len(first)):
+        used = {col[h] for h in nbrs[g] if h < g}
+        c = 0
+        while c in used:
+            c += 1
+        col.append(c)
+    return max(col) + 1
+
+
+def test_colour_search_lowers_the_stage_count(setup_lib):
+    # jump16, level 1: first fit needs 8 colours; the tabu search finds 5
+    from paper_1907_04417_amd import workloads
+    P, path, st = workloads.load("jump16")
+    L = read_hierarchy(path).levels[1]
+    greedy = _first_fit_colours(L)
+    stages = len(L.sptr) - 1
+    assert stages < greedy, (stages, greedy)
+    assert stages == 5 and greedy == 8
