@@ -717,6 +717,99 @@ __global__ __launch_bounds__(kBlock) void k_gemv(int n, int ld, const double* __
   if (lane == 0) y[i] = add ? y[i] + acc : acc;
 }
 
+// Symmetric A (n x n) as its lower-triangle 64 x 64 tiles: tile t = (I, J),
+// J <= I, listed in tij, stored row-major at tiles + 4096 t with every entry
+// of a row or column >= n zero; diagonal tiles whole.  Built once from the
+// padded row-major matrix A (leading dimension ld).
+__global__ __launch_bounds__(kBlock) void k_pack_tiles(int n, int ld, const int2* __restrict__ tij,
+                                                       const double* __restrict__ A, double* __restrict__ tiles) {
+  const int t = blockIdx.x;
+  const int2 ij = tij[t];
+  for (int e = threadIdx.x; e < 4096; e += kBlock) {
+    const int r = ij.x * 64 + (e >> 6), c = ij.y * 64 + (e & 63);
+    tiles[(size_t)t * 4096 + e] = (r < n && c < n) ? A[(size_t)r * ld + c] : 0.0;
+  }
+}
+
+// y = A x, first pass: tile t = (I, J) adds A_IJ x_J to row block I and, for
+// J < I, A_IJ^T x_I to row block J, each into its own slot of part (row
+// block R, column block C at part + 64 (R nt + C)); k_symv_sum adds the slots.
+// Every tile is read once -- half the bytes of the full product.  Wave w
+// takes rows 16 w .. 16 w + 15 of the tile, lane l the columns 2 (l % 32),
+// 2 (l % 32) + 1 of rows 16 w + 2 i + l / 32 (i < 8, one 16-byte load each).
+__global__ __launch_bounds__(kBlock) void k_symv_tiles(int n, int nt, const int2* __restrict__ tij,
+                                                       const double* __restrict__ tiles,
+                                                       const double* __restrict__ x, double* __restrict__ part) {
+  __shared__ double colp[kBlock / 64][64];
+  const int t = blockIdx.x;
+  const int2 ij = tij[t];
+  const int I = ij.x, J = ij.y;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, h = lane >> 5, cp = 2 * (lane & 31);
+  const double* Tt = tiles + (size_t)t * 4096;
+  double2 a[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a[i] = *reinterpret_cast<const double2*>(Tt + (16 * w + 2 * i + h) * 64 + cp);
+  const int cj = J * 64 + cp;
+  const double xj0 = (cj < n) ? x[cj] : 0.0, xj1 = (cj + 1 < n) ? x[cj + 1] : 0.0;
+  double xi[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int ri = I * 64 + 16 * w + 2 * i + h;
+    xi[i] = (ri < n) ? x[ri] : 0.0;
+  }
+  // row sums: DPP inside the 16-lane rows, then the two rows of each half wave
+  double out = 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const double v = lanes_sum<16>(a[i].x * xj0 + a[i].y * xj1);
+    const double s0 = lane_value(v, 0) + lane_value(v, 16), s1 = lane_value(v, 32) + lane_value(v, 48);
+    if (lane == 2 * i) out = s0;
+    if (lane == 2 * i + 1) out = s1;
+  }
+  if (lane < 16) part[((size_t)I * nt + J) * 64 + 16 * w + lane] = out;
+  if (J < I) {
+    // column sums over the wave's rows, then over the four waves in order
+    double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      c0 += a[i].x * xi[i];
+      c1 += a[i].y * xi[i];
+    }
+    c0 += __shfl_xor(c0, 32, 64);
+    c1 += __shfl_xor(c1, 32, 64);
+    if (h == 0) {
+      colp[w][cp] = c0;
+      colp[w][cp + 1] = c1;
+    }
+    __syncthreads();
+    if (w == 0) part[((size_t)J * nt + I) * 64 + lane] = ((colp[0][lane] + colp[1][lane]) + colp[2][lane]) + colp[3][lane];
+  }
+}
+
+// y = A x, second pass, one block per row block R: wave w adds the slots of
+// the column blocks in its quarter [w q, (w + 1) q), eight loads in flight,
+// and the four quarter sums are added in order.
+__global__ __launch_bounds__(kBlock) void k_symv_sum(int n, int nt, const double* __restrict__ part,
+                                                     double* __restrict__ y) {
+  __shared__ double red[kBlock / 64][64];
+  const int R = blockIdx.x, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int q = (nt + 3) / 4, c0 = w * q, c1 = min(nt, c0 + q);
+  const double* p = part + (size_t)R * nt * 64 + lane;
+  double s = 0.0;
+  for (int c = c0; c < c1; c += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(size_t)min(c + u, c1 - 1) * 64];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (c + u < c1) s += v[u];
+  }
+  red[w][lane] = s;
+  __syncthreads();
+  const int i = R * 64 + lane;
+  if (w == 0 && i < n) y[i] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
 // ------------------------------------------------- values, casts, gradient
 
 // dst[e] = src_idx[e] >= 0 ? val[src_idx[e]] : 0 (layout fill from file-order values)

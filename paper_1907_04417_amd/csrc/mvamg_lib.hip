@@ -118,6 +118,13 @@ struct DevCoarse {
   double *r = nullptr, *z = nullptr;
   double *br = nullptr, *bz = nullptr;  // block vectors for the binary32 block cycle
   double* bsplit = nullptr;             // partial products of a split block product
+  // single problem: the inverse's lower-triangle 64 x 64 tiles for the
+  // symmetric product (half the bytes of Ainv), their (I, J), the slots of
+  // the first pass
+  int nt = 0, ntiles = 0;
+  double* tiles = nullptr;
+  int2* tij = nullptr;
+  double* spart = nullptr;
 };
 
 // per-system scalars and partials of the multi-system solves
@@ -461,10 +468,13 @@ template <>
 void coarse_solve<double>(mvamg_hier* h, const double* r, double* z, hipStream_t st) {
   // z = A_L^{-1} r with the inverse formed at upload from the Cholesky factor
   DevCoarse& C = h->co;
-  if (C.nb == 1)
-    klaunch(h, MVAMG_KC_COARSE, 8.0 * C.n * C.n + 16.0 * C.n, k_gemv, (C.n + 3) / 4, kBlock, st, C.n, C.np,
-            C.Ainv, r, z, 0);
-  else
+  if (C.nb == 1) {
+    // algorithmic bytes: the inverse's lower triangle and the two vectors,
+    // booked to the tile pass; the slot sums are overhead of the split
+    klaunch(h, MVAMG_KC_COARSE, 4.0 * C.n * (C.n + 1.0) + 16.0 * C.n, k_symv_tiles, C.ntiles, kBlock, st, C.n,
+            C.nt, (const int2*)C.tij, (const double*)C.tiles, r, C.spart);
+    klaunch(h, MVAMG_KC_COARSE, 0.0, k_symv_sum, C.nt, kBlock, st, C.n, C.nt, (const double*)C.spart, z);
+  } else
     klaunch(h, MVAMG_KC_COARSE, 8.0 * C.ainv_entries + 16.0 * C.n, k_gemv_batch, (C.n + 3) / 4, kBlock, st, C.n,
             C.cprob, C.coff, C.cnp, C.aoff, C.Ainv, r, z);
   LAUNCHCHECK("coarse_solve");
@@ -990,6 +1000,22 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
       h->dfree(M);
       h->dfree(Li);
       for (void* t : temps) h->dfree(t);
+      if (D.nb == 1) {
+        D.nt = D.np / 64;
+        D.ntiles = D.nt * (D.nt + 1) / 2;
+        std::vector<int> tij(2 * (size_t)D.ntiles);
+        int t = 0;
+        for (int I = 0; I < D.nt; ++I)
+          for (int J = 0; J <= I; ++J, ++t) {
+            tij[2 * t] = I;
+            tij[2 * t + 1] = J;
+          }
+        D.tij = reinterpret_cast<int2*>(h->upload_vec(tij, st));
+        D.tiles = h->dalloc<double>((size_t)D.ntiles * 4096);
+        D.spart = h->dalloc<double>((size_t)D.nt * D.nt * 64);
+        k_pack_tiles<<<D.ntiles, kBlock, 0, st>>>(D.n, D.np, D.tij, D.Ainv, D.tiles);
+        LAUNCHCHECK("pack_tiles");
+      }
       if (D.nb > 1) {
         std::vector<int> cprob(C.n);
         for (int bk = 0; bk < D.nb; ++bk)

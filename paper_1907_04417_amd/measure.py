@@ -25,7 +25,7 @@ COPY_BYTES = 256 << 20
 
 def kernel_class(name: str) -> str | None:
     """Kernel class (as in mvamg_kernel_stats) of a binary64 cycle kernel symbol."""
-    if "k_bgemm" in name or "k_bsum_splits" in name:
+    if "k_bgemm" in name or "k_bsum_splits" in name or "k_symv_" in name:
         return "coarse_solve"
     if "double" not in name and "k_gemv" not in name:
         return None
