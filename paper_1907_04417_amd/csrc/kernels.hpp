@@ -668,11 +668,11 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nagg, const int* __rest
   }
 }
 
-// x += P x_c in fine-row order (coalesced): thread per fine row i with
-// cinfo[i] = 8 * (first coarse row of its aggregate) + (k - 1) and the row's
-// k entries of U at Urow[q * n + i] (zero past k).
+// x += P x_c in fine-row order (coalesced) on the rows i < n: thread per
+// fine row i with cinfo[i] = 8 * (first coarse row of its aggregate) + (k - 1)
+// and the row's k entries of U at Urow[q * ld + i] (zero past k).
 template <typename T, int KMAX>
-__global__ __launch_bounds__(kBlock) void k_prolong_rows(int n, const int* __restrict__ cinfo,
+__global__ __launch_bounds__(kBlock) void k_prolong_rows(int n, int ld, const int* __restrict__ cinfo,
                                                          const T* __restrict__ Urow, const T* __restrict__ xc,
                                                          T* __restrict__ x, Skip sk) {
   for (int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
@@ -682,7 +682,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_rows(int n, const int* __res
     T t = T(0);
 #pragma unroll
     for (int q = 0; q < KMAX; ++q)
-      if (q < k) t += Urow[(size_t)q * n + i] * xc[c0 + q];
+      if (q < k) t += Urow[(size_t)q * ld + i] * xc[c0 + q];
     x[i] += t;
   }
 }

@@ -519,9 +519,10 @@ __global__ __launch_bounds__(kBlock) void k_brestrict(int nagg, const int* __res
   }
 }
 
-// x += P x_c for block vectors, in fine-row order (half wave per row)
+// x += P x_c for block vectors, in fine-row order (half wave per row), rows
+// i < n, U entries at Urow[q * ld + i]
 template <typename T, int KMAX>
-__global__ __launch_bounds__(kBlock) void k_bprolong_rows(int n, const int* __restrict__ cinfo,
+__global__ __launch_bounds__(kBlock) void k_bprolong_rows(int n, int ld, const int* __restrict__ cinfo,
                                                           const T* __restrict__ Urow, const T* __restrict__ xc,
                                                           T* __restrict__ x) {
   const int c = threadIdx.x & 31;
@@ -531,7 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_bprolong_rows(int n, const int* __re
     T t = T(0);
 #pragma unroll
     for (int q = 0; q < KMAX; ++q)
-      if (q < k) t += Urow[(size_t)q * n + i] * xc[(size_t)(c0 + q) * kNB + c];
+      if (q < k) t += Urow[(size_t)q * ld + i] * xc[(size_t)(c0 + q) * kNB + c];
     x[(size_t)i * kNB + c] += t;
   }
 }

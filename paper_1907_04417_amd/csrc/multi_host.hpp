@@ -254,14 +254,18 @@ void bvcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t s
   LAUNCHCHECK("brestrict");
   bvcycle<T>(h, l + 1, rc, xc, smoother, st, next_smoothed);
   {
-    const int pg = bgrid_elem(P.nf);
-    const double pby = (double)P.nu * sizeof(T) + (double)L.n * (4 + 2.0 * kNB * sizeof(T)) + (double)C.n * kNB * sizeof(T);
-    switch (P.kmax) {
-      case 1: klaunch(h, MVAMG_KC_PROLONG, pby, k_bprolong_rows<T, 1>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
-      case 2: klaunch(h, MVAMG_KC_PROLONG, pby, k_bprolong_rows<T, 2>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
+    // rows overwritten unread by the backward sweep's first stage are skipped
+    const bool gs = smoother == MVAMG_SMOOTH_GS;
+    const int nr = gs ? P.ncut : P.nf;
+    const double nu = gs ? (double)P.nu_cut : (double)P.nu;
+    const int pg = bgrid_elem(std::max(nr, 1));
+    const double pby = nu * sizeof(T) + (double)nr * (4 + 2.0 * kNB * sizeof(T)) + (double)C.n * kNB * sizeof(T);
+    if (nr > 0) switch (P.kmax) {
+      case 1: klaunch(h, MVAMG_KC_PROLONG, pby, k_bprolong_rows<T, 1>, pg, kBlock, st, nr, P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
+      case 2: klaunch(h, MVAMG_KC_PROLONG, pby, k_bprolong_rows<T, 2>, pg, kBlock, st, nr, P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
       case 3:
-      case 4: klaunch(h, MVAMG_KC_PROLONG, pby, k_bprolong_rows<T, 4>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
-      default: klaunch(h, MVAMG_KC_PROLONG, pby, k_bprolong_rows<T, 8>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
+      case 4: klaunch(h, MVAMG_KC_PROLONG, pby, k_bprolong_rows<T, 4>, pg, kBlock, st, nr, P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
+      default: klaunch(h, MVAMG_KC_PROLONG, pby, k_bprolong_rows<T, 8>, pg, kBlock, st, nr, P.nf, P.cinfo, tUrow<T>(P), xc, x); break;
     }
   }
   LAUNCHCHECK("bprolong");

@@ -100,6 +100,13 @@ struct DevTransfer {
   int* arec = nullptr;  // per-aggregate records (kARec ints each)
   int* aprob = nullptr; // batch, level 0: problem of every aggregate
   int nf = 0, kmax = 1;  // fine rows, widest block
+  // Point fine level: a Gauss-Seidel row update does not read the row's own
+  // value, so the rows [ncut, nf) of the last stage -- the first one the
+  // backward sweep after the prolongation relaxes -- are overwritten before
+  // anything reads them, and the prolongation stops at ncut (nu_cut U entries
+  // lie in the rows before it).  ncut = nf on levels with multi-row groups.
+  int ncut = 0;
+  int64_t nu_cut = 0;
   int64_t nu = 0;        // entries of the U blocks
   int* cinfo = nullptr;  // per fine row: 8 * first coarse row + (k - 1)
   double* Urow = nullptr;  // per fine row, column-major [q * nf + row]
@@ -541,15 +548,18 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   LAUNCHCHECK("restrict");
   vcycle<T>(h, l + 1, rc, xc, smoother, st, next_smoothed);
   {
-    const int pg = grid_elem(P.nf);
-    const double pby = skip_bytes(h, l, (double)P.nu * sizeof(T) + (double)L.n * (4 + 2 * sizeof(T)) + (double)C.n * sizeof(T));
+    const bool gs = smoother == MVAMG_SMOOTH_GS;
+    const int nr = gs ? P.ncut : P.nf;
+    const double nu = gs ? (double)P.nu_cut : (double)P.nu;
+    const int pg = grid_elem(std::max(nr, 1));
+    const double pby = skip_bytes(h, l, nu * sizeof(T) + (double)nr * (4 + 2 * sizeof(T)) + (double)C.n * sizeof(T));
     const Skip sk = lskip(h, l, SKIP_ROW);
-    switch (P.kmax) {
-      case 1: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 1>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x, sk); break;
-      case 2: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 2>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x, sk); break;
+    if (nr > 0) switch (P.kmax) {
+      case 1: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 1>, pg, kBlock, st, nr, P.nf, P.cinfo, tUrow<T>(P), xc, x, sk); break;
+      case 2: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 2>, pg, kBlock, st, nr, P.nf, P.cinfo, tUrow<T>(P), xc, x, sk); break;
       case 3:
-      case 4: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 4>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x, sk); break;
-      default: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 8>, pg, kBlock, st, P.nf, P.cinfo, tUrow<T>(P), xc, x, sk); break;
+      case 4: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 4>, pg, kBlock, st, nr, P.nf, P.cinfo, tUrow<T>(P), xc, x, sk); break;
+      default: klaunch(h, MVAMG_KC_PROLONG, pby, k_prolong_rows<T, 8>, pg, kBlock, st, nr, P.nf, P.cinfo, tUrow<T>(P), xc, x, sk); break;
     }
   }
   LAUNCHCHECK("prolong");
@@ -949,6 +959,12 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
         }
         P.nf = nf;
         P.kmax = kmax;
+        const LevelLayout& yf = Y[l];
+        const int nsf = (int)yf.sgrp.size() - 1;
+        const bool point = (int)yf.gstart.size() - 1 == nf;
+        P.ncut = point ? yf.gstart[yf.sgrp[nsf - 1]] : nf;
+        P.nu_cut = 0;
+        for (int p = 0; p < P.ncut; ++p) P.nu_cut += (cinfo[p] & 7) + 1;
         P.cinfo = h->upload_vec(cinfo, st);
         P.Urow = h->upload_vec(urow, st);
         P.Urow32 = h->dalloc<float>(urow.size());

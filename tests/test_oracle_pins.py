@@ -37,6 +37,31 @@ def test_gs_sweep_closed_form(fx, request):
         np.testing.assert_allclose(xb, x + np.linalg.solve(M.T, r - A @ x), rtol=1e-11, atol=1e-11)
 
 
+@pytest.mark.parametrize("fx", ["tiny_hier", "small3d_hier"])
+def test_backward_sweep_ignores_last_stage_start(fx, request):
+    """On a point level the backward sweep relaxes the last stage first, and a
+    row's update reads only its neighbours, never its own old value: the
+    sweep's result is bitwise independent of the last stage's starting values
+    (so the prolongation before it may leave those rows out), while any row
+    of an earlier stage does change it."""
+    P, path, _ = request.getfixturevalue(fx)
+    H = read_hierarchy(path)
+    L0 = H.levels[0]
+    assert len(L0.gptr) - 1 == L0.n  # point level
+    O = oracle.Oracle(path)
+    rng = np.random.default_rng(31)
+    r = rng.standard_normal(L0.n)
+    x1 = rng.standard_normal(L0.n)
+    last = L0.order[L0.gptr[L0.sptr[-2]]:]
+    x2 = x1.copy()
+    x2[last] = rng.standard_normal(len(last))
+    y1 = O.smooth(0, r, x1, forward=False)
+    assert np.array_equal(O.smooth(0, r, x2, forward=False), y1)
+    x3 = x1.copy()
+    x3[L0.order[0]] += 1.0
+    assert not np.array_equal(O.smooth(0, r, x3, forward=False), y1)
+
+
 def test_lexicographic_gs_closed_form(tiny_hier):
     """The paper's sequential GS (natural order) is the same closed form with O = 0..n-1."""
     _, path, _ = tiny_hier
