@@ -600,10 +600,11 @@ enum ARecField { AR_M0 = 0, AR_NA = 1, AR_K = 2, AR_UOFF = 3, AR_C0 = 4, AR_DB =
 // the others are zero -- the first Gauss-Seidel stage; INIT = 2: x_c = r_c / d_l1,
 // the first l1-Jacobi sweep).  The record, then U_a, the member rows and the
 // diagonal block's lower triangle are all requested before the gather of s.
+// Rows >= scut have s = 0 and are not read.
 template <typename T, int KMAX, int INIT>
 __global__ __launch_bounds__(kBlock) void k_restrict(int nagg, const int* __restrict__ arec,
                                                      const int* __restrict__ arows, const T* __restrict__ U,
-                                                     const T* __restrict__ s, T* __restrict__ rc,
+                                                     const T* __restrict__ s, int scut, T* __restrict__ rc,
                                                      const T* __restrict__ cdblk, const T* __restrict__ cdl1,
                                                      T* __restrict__ xc, Skip sk) {
   const int a = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) +
@@ -635,7 +636,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nagg, const int* __rest
     T u[KMAX];
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) u[q] = Ua[min(q, k - 1) * na + li];
-    const T sv = s[row];
+    const T sv = (row < scut) ? s[row] : T(0);
 #pragma unroll
     for (int q = 0; q < KMAX; ++q)
       if (q < k) acc[q] += u[q] * sv;

@@ -450,12 +450,12 @@ __global__ __launch_bounds__(kBlock) void k_bl1_update(int n, const T* __restric
 
 // r_c = P^T s for block vectors: wave per aggregate, half wave h takes members
 // h, h + 2, ... (four in flight), the halves are added with one exchange.
-// Aggregate records and INIT as in k_restrict (1: first Gauss-Seidel stage of
-// the next level from x_c = 0, 2: first l1-Jacobi step).
+// Aggregate records, scut and INIT as in k_restrict (1: first Gauss-Seidel
+// stage of the next level from x_c = 0, 2: first l1-Jacobi step).
 template <typename T, int INIT>
 __global__ __launch_bounds__(kBlock) void k_brestrict(int nagg, const int* __restrict__ arec,
                                                       const int* __restrict__ arows, const T* __restrict__ U,
-                                                      const T* __restrict__ s, T* __restrict__ rc,
+                                                      const T* __restrict__ s, int scut, T* __restrict__ rc,
                                                       const T* __restrict__ cdblk, const T* __restrict__ cdl1,
                                                       T* __restrict__ xc) {
   const int a = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) +
@@ -474,7 +474,10 @@ __global__ __launch_bounds__(kBlock) void k_brestrict(int nagg, const int* __res
 #pragma unroll
     for (int u = 0; u < 4; ++u) li[u] = min(l0 + 2 * u, na - 1);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) sv[u] = s[(size_t)arows[m0 + li[u]] * kNB + c];
+    for (int u = 0; u < 4; ++u) {
+      const int row = arows[m0 + li[u]];
+      sv[u] = (row < scut) ? s[(size_t)row * kNB + c] : T(0);
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (l0 + 2 * u < na) {

@@ -157,21 +157,29 @@ void bzero_stage0(mvamg_hier* h, int l, const DevLevel& L, const T* r, T* x, hip
 }
 
 // MODE 0: s = r - A x; MODE 1: s = A x and per-column x.s reduced by `mode`; MODE 2: s = A x
+// nst >= 0 (MODE 0): only the rows of stages [0, nst), as resid.
 template <typename T, int MODE>
-void bresid(mvamg_hier* h, const DevLevel& L, const T* r, const T* x, T* s, int mode, hipStream_t st) {
+void bresid(mvamg_hier* h, const DevLevel& L, const T* r, const T* x, T* s, int mode, hipStream_t st, int nst = -1) {
   const int kc = MODE != 0 ? MVAMG_KC_SPMV : MVAMG_KC_RESIDUAL;
-  const double by = (double)L.nnz * (sizeof(T) + 4) + 4.0 * (L.n + 1) +
-                    (double)L.n * kNB * sizeof(T) * (MODE != 0 ? 2 : 3);
-  const int grid = bresid_grid(L, MODE);
+  const bool part_rows = MODE == 0 && nst >= 0 && nst < L.ns;
+  const double by = part_rows ? resid_stage_bytes<T>(L, nst, 3.0 * kNB * sizeof(T))
+                              : (double)L.nnz * (sizeof(T) + 4) + 4.0 * (L.n + 1) +
+                                    (double)L.n * kNB * sizeof(T) * (MODE != 0 ? 2 : 3);
+  int grid = bresid_grid(L, MODE);
   double* part = h->mb.part;
   if (L.sell) {
-    klaunch(h, kc, by, k_bresid_sell<T, MODE>, grid, kBlock, st, L.slabs, L.nslabs, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part);
+    const int ns = part_rows ? L.h_sslab[nst] : L.nslabs;
+    if (part_rows) grid = std::max(1, std::min(grid, ns * (64 / kRowsPerBlock)));
+    if (ns > 0)
+      klaunch(h, kc, by, k_bresid_sell<T, MODE>, grid, kBlock, st, L.slabs, ns, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part);
   } else {
-    switch (L.G) {
-      case 1: klaunch(h, kc, by, k_bresid_grp<T, 1, MODE>, grid, kBlock, st, L.ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part); break;
-      case 2: klaunch(h, kc, by, k_bresid_grp<T, 2, MODE>, grid, kBlock, st, L.ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part); break;
-      case 4: klaunch(h, kc, by, k_bresid_grp<T, 4, MODE>, grid, kBlock, st, L.ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part); break;
-      default: klaunch(h, kc, by, k_bresid_grp<T, 8, MODE>, grid, kBlock, st, L.ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part); break;
+    const int ng = part_rows ? L.h_sgrp[nst] : L.ng;
+    if (part_rows) grid = std::max(1, std::min(grid, (ng + 3) / 4));
+    if (ng > 0) switch (L.G) {
+      case 1: klaunch(h, kc, by, k_bresid_grp<T, 1, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part); break;
+      case 2: klaunch(h, kc, by, k_bresid_grp<T, 2, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part); break;
+      case 4: klaunch(h, kc, by, k_bresid_grp<T, 4, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part); break;
+      default: klaunch(h, kc, by, k_bresid_grp<T, 8, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part); break;
     }
   }
   LAUNCHCHECK("bresid");
@@ -237,19 +245,22 @@ void bvcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t s
   } else if (!x_started) {
     k_bl1_init<T><<<bgrid_elem(L.n), kBlock, 0, st>>>(L.n, ldl1<T>(L), r, x);
   }
-  bresid<T, 0>(h, L, r, x, s, MM_STORE_R0, st);
+  // rows of a point level's last stage have zero residual after the sweep (as in vcycle)
+  const bool zero_last = smoother == MVAMG_SMOOTH_GS && L.ng == L.n;
+  bresid<T, 0>(h, L, r, x, s, MM_STORE_R0, st, zero_last ? L.ns - 1 : -1);
+  const int scut = zero_last ? L.h_srow[L.ns - 1] : L.n;
   const int tg = (P.nagg + 3) / 4;
-  const double tby = (double)P.nu * sizeof(T) + (double)L.n * (4 + kNB * sizeof(T)) + (double)C.n * kNB * sizeof(T);
+  const double tby = (double)P.nu * sizeof(T) + 4.0 * L.n + (double)scut * kNB * sizeof(T) + (double)C.n * kNB * sizeof(T);
   const bool next_smoothed = (l + 2 < h->nl);
   if (!next_smoothed) {
-    klaunch(h, MVAMG_KC_RESTRICT, tby, k_brestrict<T, 0>, tg, kBlock, st, P.nagg, P.arec, P.arows, tU<T>(P), s, rc,
+    klaunch(h, MVAMG_KC_RESTRICT, tby, k_brestrict<T, 0>, tg, kBlock, st, P.nagg, P.arec, P.arows, tU<T>(P), s, scut, rc,
             (const T*)nullptr, (const T*)nullptr, (T*)nullptr);
   } else if (smoother == MVAMG_SMOOTH_GS) {
     klaunch(h, MVAMG_KC_RESTRICT, tby + (double)C.n * kNB * sizeof(T), k_brestrict<T, 1>, tg, kBlock, st, P.nagg,
-            P.arec, P.arows, tU<T>(P), s, rc, ldblk<T>(C), (const T*)nullptr, xc);
+            P.arec, P.arows, tU<T>(P), s, scut, rc, ldblk<T>(C), (const T*)nullptr, xc);
   } else {
     klaunch(h, MVAMG_KC_RESTRICT, tby + (double)C.n * kNB * sizeof(T), k_brestrict<T, 2>, tg, kBlock, st, P.nagg,
-            P.arec, P.arows, tU<T>(P), s, rc, (const T*)nullptr, ldl1<T>(C), xc);
+            P.arec, P.arows, tU<T>(P), s, scut, rc, (const T*)nullptr, ldl1<T>(C), xc);
   }
   LAUNCHCHECK("brestrict");
   bvcycle<T>(h, l + 1, rc, xc, smoother, st, next_smoothed);

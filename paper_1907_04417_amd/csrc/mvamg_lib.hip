@@ -439,24 +439,39 @@ void zero_stage0(mvamg_hier* h, int l, const DevLevel& L, const T* r, T* x, hipS
 
 int resid_grid(const DevLevel& L);
 
-// MODE 0: s = r - A x;  MODE 1: s = A x and x.s reduced into scal by `mode`;  MODE 2: s = A x
+// Bytes of the residual over the rows of stages [0, nst).
+template <typename T>
+double resid_stage_bytes(const DevLevel& L, int nst, double vec_bytes) {
+  double b = 0.0;
+  for (int c = 0; c < nst; ++c) b += (double)L.stage_nnz[c] * (sizeof(T) + 4) + (double)L.stage_rows[c] * (4 + vec_bytes);
+  return b;
+}
+
+// MODE 0: s = r - A x;  MODE 1: s = A x and x.s reduced into scal by `mode`;  MODE 2: s = A x.
+// nst >= 0 (MODE 0): only the rows of stages [0, nst) (the rest of s is not
+// written).
 template <typename T, int MODE>
-void resid(mvamg_hier* h, int l, const DevLevel& L, const T* r, const T* x, T* s, int mode, hipStream_t st) {
+void resid(mvamg_hier* h, int l, const DevLevel& L, const T* r, const T* x, T* s, int mode, hipStream_t st,
+           int nst = -1) {
   const Red red = mkred(h);
   const int kc = MODE != 0 ? MVAMG_KC_SPMV : MVAMG_KC_RESIDUAL;
-  const double by = skip_bytes(h, l, (double)L.nnz * (sizeof(T) + 4) + 4.0 * (L.n + 1) +
-                                         (double)L.n * sizeof(T) * (MODE != 0 ? 2 : 3));
+  const bool part = MODE == 0 && nst >= 0 && nst < L.ns;
+  const double by = skip_bytes(h, l, part ? resid_stage_bytes<T>(L, nst, 3.0 * sizeof(T))
+                                          : (double)L.nnz * (sizeof(T) + 4) + 4.0 * (L.n + 1) +
+                                                (double)L.n * sizeof(T) * (MODE != 0 ? 2 : 3));
   if (L.sell) {
-    const int grid = (L.nslabs + 3) / 4;
-    klaunch(h, kc, by, k_resid_sell<T, MODE>, grid, kBlock, st, L.slabs, L.nslabs, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red,
-            lskip(h, l, SKIP_SLAB));
+    const int ns = part ? L.h_sslab[nst] : L.nslabs;
+    if (ns > 0)
+      klaunch(h, kc, by, k_resid_sell<T, MODE>, (ns + 3) / 4, kBlock, st, L.slabs, ns, L.col, lval<T>(L), ldblk<T>(L), r, x,
+              s, red, lskip(h, l, SKIP_SLAB));
   } else {
-    const int grid = (L.ng + 3) / 4;
-    switch (L.G) {
-      case 1: klaunch(h, kc, by, k_resid_grp<T, 1, MODE>, grid, kBlock, st, L.ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
-      case 2: klaunch(h, kc, by, k_resid_grp<T, 2, MODE>, grid, kBlock, st, L.ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
-      case 4: klaunch(h, kc, by, k_resid_grp<T, 4, MODE>, grid, kBlock, st, L.ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
-      default: klaunch(h, kc, by, k_resid_grp<T, 8, MODE>, grid, kBlock, st, L.ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
+    const int ng = part ? L.h_sgrp[nst] : L.ng;
+    const int grid = (ng + 3) / 4;
+    if (ng > 0) switch (L.G) {
+      case 1: klaunch(h, kc, by, k_resid_grp<T, 1, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
+      case 2: klaunch(h, kc, by, k_resid_grp<T, 2, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
+      case 4: klaunch(h, kc, by, k_resid_grp<T, 4, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
+      default: klaunch(h, kc, by, k_resid_grp<T, 8, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
     }
   }
   LAUNCHCHECK("resid");
@@ -517,10 +532,15 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   } else if (!x_started) {
     k_l1_init<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, ldl1<T>(L), r, x);
   }
-  // residual, restriction (fused with the first smoothing step of the next level)
-  resid<T, 0>(h, l, L, r, x, s, M_NONE, st);
+  // residual, restriction (fused with the first smoothing step of the next
+  // level).  After a Gauss-Seidel sweep, a row of a point level's last stage
+  // has zero residual: its neighbours all lie in earlier stages and have not
+  // changed since its update.  Those rows are neither computed nor restricted.
+  const bool zero_last = smoother == MVAMG_SMOOTH_GS && L.ng == L.n;
+  resid<T, 0>(h, l, L, r, x, s, M_NONE, st, zero_last ? L.ns - 1 : -1);
+  const int scut = zero_last ? L.h_srow[L.ns - 1] : L.n;
   const int tg = (P.nagg + 3) / 4;
-  const double tby = skip_bytes(h, l, (double)P.nu * sizeof(T) + (double)L.n * (4 + sizeof(T)) + (double)C.n * sizeof(T));
+  const double tby = skip_bytes(h, l, (double)P.nu * sizeof(T) + 4.0 * L.n + (double)scut * sizeof(T) + (double)C.n * sizeof(T));
   const bool next_smoothed = (l + 2 < h->nl);
   const int init = !next_smoothed ? 0 : (smoother == MVAMG_SMOOTH_GS ? 1 : 2);
   const double iby = next_smoothed ? skip_bytes(h, l, (double)C.n * sizeof(T)) : 0.0;
@@ -531,11 +551,11 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
 #define MVAMG_RESTRICT(KM)                                                                                        \
   switch (init) {                                                                                                 \
     case 0: klaunch(h, MVAMG_KC_RESTRICT, tby, k_restrict<T, KM, 0>, tg, kBlock, st, P.nagg, P.arec, P.arows,   \
-                    tU<T>(P), s, rc, cdblk, cdl1, xcs, ask); break;                                               \
+                    tU<T>(P), s, scut, rc, cdblk, cdl1, xcs, ask); break;                                               \
     case 1: klaunch(h, MVAMG_KC_RESTRICT, tby + iby, k_restrict<T, KM, 1>, tg, kBlock, st, P.nagg, P.arec,      \
-                    P.arows, tU<T>(P), s, rc, cdblk, cdl1, xcs, ask); break;                                      \
+                    P.arows, tU<T>(P), s, scut, rc, cdblk, cdl1, xcs, ask); break;                                      \
     default: klaunch(h, MVAMG_KC_RESTRICT, tby + iby, k_restrict<T, KM, 2>, tg, kBlock, st, P.nagg, P.arec,     \
-                     P.arows, tU<T>(P), s, rc, cdblk, cdl1, xcs, ask); break;                                     \
+                     P.arows, tU<T>(P), s, scut, rc, cdblk, cdl1, xcs, ask); break;                                     \
   }
   switch (P.kmax) {
     case 1: MVAMG_RESTRICT(1); break;
