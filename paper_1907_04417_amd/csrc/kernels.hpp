@@ -167,19 +167,46 @@ __device__ __forceinline__ void block_partials(double a0, double a1, double* par
   }
 }
 
+// The finisher: one block of kFinish threads; thread t adds the partials
+// t + kFinish u in u order, eight loads in flight, then the wave sums are
+// added in wave order.
+constexpr int kFinish = 1024;
 template <int NV>
-__global__ __launch_bounds__(kBlock) void k_finish(int nparts, const double* __restrict__ part, double* scal,
-                                                   int mode) {
-  __shared__ double lds[4];
+__global__ __launch_bounds__(kFinish) void k_finish(int nparts, const double* __restrict__ part, double* scal,
+                                                    int mode) {
+  __shared__ double lds[2][kFinish / 64];
   const double rho = scal[S_RHO], alpha = scal[S_ALPHA];
   double s0 = 0.0, s1 = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kBlock) {
-    s0 += part[i];
-    if (NV > 1) s1 += part[nparts + i];
+  for (int i0 = threadIdx.x; i0 < nparts; i0 += 8 * kFinish) {
+    double v0[8], v1[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * kFinish;
+      v0[u] = (i < nparts) ? part[i] : 0.0;
+      v1[u] = (NV > 1 && i < nparts) ? part[nparts + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      s0 += v0[u];
+      s1 += v1[u];
+    }
   }
-  s0 = block_sum(s0, lds);
-  if (NV > 1) s1 = block_sum(s1, lds);
-  if (threadIdx.x == 0) epilogue(mode, s0, s1, rho, alpha, scal);
+  s0 = wave_sum(s0);
+  if (NV > 1) s1 = wave_sum(s1);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    lds[0][w] = s0;
+    lds[1][w] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t0 = 0.0, t1 = 0.0;
+    for (int q = 0; q < kFinish / 64; ++q) {
+      t0 += lds[0][q];
+      t1 += lds[1][q];
+    }
+    epilogue(mode, t0, t1, rho, alpha, scal);
+  }
 }
 
 // ------------------------------------------------------- vector kernels
@@ -250,38 +277,47 @@ __global__ __launch_bounds__(kBlock) void k_xpay(int n, const double* __restrict
 // forward sweep from x = 0, lim is the stage's first row: entries of later
 // stages (column >= lim) multiply values that are still zero and are
 // skipped, so those rows need not be cleared beforehand; otherwise lim is
-// past every row.
-template <typename T>
+// past every row.  DOT = 1 (binary64, no batch skipping): the block also
+// writes the sum of x_p r_p over its new rows to part[blockIdx.x] (the last
+// sweep of a cycle then yields the partials of z.r).
+template <typename T, int DOT>
 __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ slabs, int s0, int s1,
                                                     const int* __restrict__ col, const T* __restrict__ val,
                                                     const T* __restrict__ diag, const T* __restrict__ r, T* x,
-                                                    Skip sk, int lim) {
+                                                    Skip sk, int lim, double* __restrict__ part) {
   const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
-  if (s >= s1 || skipped(sk, s)) return;
   const int lane = threadIdx.x & 63;
-  const Slab sl = slabs[s];
-  if (lane >= sl.nrows) return;
-  const int p = sl.row0 + lane;
-  const int* c = col + sl.off + lane;
-  const T* v = val + sl.off + lane;
-  T acc = r[p];
-  // entries in batches of 8: all index loads, then all gathers, then the sums
-  for (int j0 = 0; j0 < sl.width; j0 += 8) {
-    int cc[8];
-    T vv[8], xx[8];
+  double dsum = 0.0;
+  if (s < s1 && !skipped(sk, s)) {
+    const Slab sl = slabs[s];
+    if (lane < sl.nrows) {
+      const int p = sl.row0 + lane;
+      const int* c = col + sl.off + lane;
+      const T* v = val + sl.off + lane;
+      const T rp = r[p];
+      T acc = rp;
+      // entries in batches of 8: all index loads, then all gathers, then the sums
+      for (int j0 = 0; j0 < sl.width; j0 += 8) {
+        int cc[8];
+        T vv[8], xx[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int j = min(j0 + u, sl.width - 1);
-      cc[u] = c[64 * j];
-      vv[u] = v[64 * j];
+        for (int u = 0; u < 8; ++u) {
+          const int j = min(j0 + u, sl.width - 1);
+          cc[u] = c[64 * j];
+          vv[u] = v[64 * j];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xx[u] = x[min(cc[u], lim - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (j0 + u < sl.width && cc[u] < lim) acc -= vv[u] * xx[u];
+      }
+      const T xn = acc / diag[p];
+      x[p] = xn;
+      if (DOT) dsum = (double)xn * (double)rp;
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) xx[u] = x[min(cc[u], lim - 1)];
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (j0 + u < sl.width && cc[u] < lim) acc -= vv[u] * xx[u];
   }
-  x[p] = acc / diag[p];
+  if (DOT) block_partials<1>(dsum, 0.0, part);
 }
 
 // First stage of the forward sweep from x = 0 on a point level: x_p = r_p /

@@ -162,6 +162,7 @@ struct mvamg_hier {
   double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   double* scal = nullptr;
   double* part = nullptr;
+  int dot_nparts = 0;  // partials of z.r written by the last cycle's fine backward sweep
   double* pinned = nullptr;
   // batch of independent problems (nprob > 0): level-0 rows of problem p are
   // the file rows [poff[p], poff[p+1]); iperm0 maps a file row to smoother order
@@ -292,9 +293,9 @@ void harvest(mvamg_hier* h) {
 // Adds the block partials of the previous kernel (grid blocks) and applies `mode`.
 void finish(mvamg_hier* h, int nv, int grid, int mode, hipStream_t st) {
   if (nv == 1)
-    k_finish<1><<<1, kBlock, 0, st>>>(grid, h->part, h->scal, mode);
+    k_finish<1><<<1, kFinish, 0, st>>>(grid, h->part, h->scal, mode);
   else
-    k_finish<2><<<1, kBlock, 0, st>>>(grid, h->part, h->scal, mode);
+    k_finish<2><<<1, kFinish, 0, st>>>(grid, h->part, h->scal, mode);
   LAUNCHCHECK("finish");
 }
 
@@ -389,22 +390,32 @@ double stage_bytes(const DevLevel& L, int c) {
 }
 
 // first_sweep: forward sweep from x = 0 on a point level (entries of later
-// stages skipped; see k_gs_sell)
+// stages skipped; see k_gs_sell).  dot_part (binary64 sliced-ELL levels): the
+// stage also writes block partials of x.r for its rows there.  Returns the
+// number of partials written.
 template <typename T>
-void gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, int backward, hipStream_t st,
-              bool first_sweep = false) {
+int gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, int backward, hipStream_t st,
+             bool first_sweep = false, double* dot_part = nullptr) {
   const int kc = (l == 0) ? MVAMG_KC_SMOOTH_FINE : MVAMG_KC_SMOOTH_COARSE;
   const double by = skip_bytes(h, l, stage_bytes<T>(L, c));
   if (L.sell) {
     const int s0 = L.h_sslab[c], s1 = L.h_sslab[c + 1];
-    if (s1 <= s0) return;
+    if (s1 <= s0) return 0;
     const int grid = (s1 - s0 + 3) / 4;
     const int lim = first_sweep ? L.h_srow[c] : INT_MAX;
-    klaunch(h, kc, by, k_gs_sell<T>, grid, kBlock, st, L.slabs, s0, s1, L.col, lval<T>(L), ldblk<T>(L), r, x,
-            lskip(h, l, SKIP_SLAB), lim);
+    if constexpr (std::is_same<T, double>::value) {
+      if (dot_part) {
+        klaunch(h, kc, by, k_gs_sell<T, 1>, grid, kBlock, st, L.slabs, s0, s1, L.col, lval<T>(L), ldblk<T>(L), r, x,
+                lskip(h, l, SKIP_SLAB), lim, dot_part);
+        LAUNCHCHECK("gs_stage");
+        return grid;
+      }
+    }
+    klaunch(h, kc, by, k_gs_sell<T, 0>, grid, kBlock, st, L.slabs, s0, s1, L.col, lval<T>(L), ldblk<T>(L), r, x,
+            lskip(h, l, SKIP_SLAB), lim, (double*)nullptr);
   } else {
     const int g0 = L.h_sgrp[c], g1 = L.h_sgrp[c + 1];
-    if (g1 <= g0) return;
+    if (g1 <= g0) return 0;
     const int grid = (g1 - g0 + 3) / 4;
 #define MVAMG_GS_GRP(K)                                                                                             \
   (backward ? klaunch(h, kc, by, k_gs_grp<T, K, 1>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x) \
@@ -418,6 +429,7 @@ void gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, 
 #undef MVAMG_GS_GRP
   }
   LAUNCHCHECK("gs_stage");
+  return 0;
 }
 
 // First step of the forward sweep from x = 0.  Point levels: x = r / d on
@@ -513,8 +525,12 @@ void coarse_solve<float>(mvamg_hier* h, const float* r, float* z, hipStream_t st
 
 // x = B_l r (one V-cycle from a zero guess).  x_started: the restriction of
 // the finer level has already performed the first pre-smoothing step on x.
+// dot_part: the backward sweep of this level also writes the block partials
+// of x.r (binary64 sliced-ELL level, Gauss-Seidel); their count goes to
+// h->dot_nparts.
 template <typename T>
-void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st, bool x_started = false) {
+void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st, bool x_started = false,
+            double* dot_part = nullptr) {
   if (l == h->nl - 1) {
     coarse_solve<T>(h, r, x, st);
     return;
@@ -585,7 +601,9 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   LAUNCHCHECK("prolong");
   // post-smoothing: one backward sweep
   if (smoother == MVAMG_SMOOTH_GS) {
-    for (int c = L.ns - 1; c >= 0; --c) gs_stage<T>(h, l, L, c, r, x, 1, st);
+    int off = 0;
+    for (int c = L.ns - 1; c >= 0; --c) off += gs_stage<T>(h, l, L, c, r, x, 1, st, false, dot_part ? dot_part + off : nullptr);
+    if (dot_part) h->dot_nparts = off;
   } else {
     resid<T, 0>(h, l, L, r, x, s, M_NONE, st);
     k_l1_update<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, ldl1<T>(L), s, x);
@@ -665,14 +683,20 @@ void cg_step_a(mvamg_hier* h, hipStream_t st) {
   HIPCHECK(hipMemcpyAsync(h->pinned, h->scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, st));
 }
 
-// Half-step B: z = B r, beta (standard or flexible), p = z + beta p.
+// Half-step B: z = B r, beta (standard or flexible), p = z + beta p.  In
+// binary64 with Gauss-Seidel on a sliced-ELL fine level, the cycle's last
+// sweep writes the partials of z.r itself.
 void cg_step_b(mvamg_hier* h, int precision, int smoother, hipStream_t st) {
   const int n = h->n, eg = grid_for(n);
-  apply_B(h, h->r, h->z, precision, smoother, st);
-  if (precision == 32) {
+  if (precision == 64 && smoother == MVAMG_SMOOTH_GS && h->nl > 1 && h->lv[0].sell) {
+    vcycle<double>(h, 0, h->r, h->z, smoother, st, false, h->part);
+    finish(h, 1, h->dot_nparts, M_RZ, st);
+  } else if (precision == 32) {
+    apply_B(h, h->r, h->z, precision, smoother, st);
     k_dot<2><<<eg, kBlock, 0, st>>>(n, h->z, h->r, h->z, h->q, mkred(h));
     finish(h, 2, eg, M_RZ_FLEX, st);
   } else {
+    apply_B(h, h->r, h->z, precision, smoother, st);
     k_dot<1><<<eg, kBlock, 0, st>>>(n, h->z, h->r, nullptr, nullptr, mkred(h));
     finish(h, 1, eg, M_RZ, st);
   }
@@ -1095,7 +1119,18 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
       h->lv[0].r = h->r;
       h->lv[0].x = h->z;
       h->scal = h->dalloc<double>(S_NSCAL);
-      h->part = h->dalloc<double>(2 * (size_t)maxgrid);
+      {
+        // partials: two values per block of the widest reduction, or the
+        // per-stage blocks of the fine backward sweep, whichever is more
+        int64_t cap = 2 * (int64_t)maxgrid;
+        const DevLevel& F = h->lv[0];
+        if (F.sell && F.ns > 0) {
+          int64_t d = 0;
+          for (int c = 0; c < F.ns; ++c) d += (F.h_sslab[c + 1] - F.h_sslab[c] + 3) / 4;
+          cap = std::max(cap, d);
+        }
+        h->part = h->dalloc<double>((size_t)cap);
+      }
       HIPCHECK(hipMemsetAsync(h->scal, 0, S_NSCAL * sizeof(double), st));
       HIPCHECK(hipHostMalloc((void**)&h->pinned, S_NSCAL * sizeof(double), hipHostMallocDefault));
     }
