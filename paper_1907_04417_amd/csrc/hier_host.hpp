@@ -251,6 +251,13 @@ struct LevelLayout {
   std::vector<int> col;
   std::vector<double> val;
   std::vector<int> src;  // index of each entry in the file's CSR value array (-1: padding)
+  // sliced ELL with 16-bit columns: slab s whose j-th entries span at most
+  // 65535 columns stores them as col16[off + 64 j + i] = col - cbase[scb[s] + j]
+  // (cbase padded to a multiple of 8 per slab); scb[s] = -1 keeps col.
+  std::vector<uint16_t> col16;
+  std::vector<int> cbase, scb;
+  int64_t nnz16 = 0;                // stored entries (without padding) in 16-bit slabs
+  std::vector<int64_t> stage_nnz16;  // the same per stage
   // dense k x k diagonal blocks of the groups (row-major)
   std::vector<int> dboff;
   std::vector<double> dblk;
@@ -409,6 +416,48 @@ inline void build_level_layout(const HostLevel& L, LevelLayout& Y, const std::ve
         }
         for (; j < s.width; ++j) Y.col[(int64_t)s.off + (int64_t)j * 64 + lane] = p;  // zero padding
       }
+    // 16-bit column deltas per (slab, entry position) where they fit
+    Y.col16.assign(tot, 0);
+    Y.scb.assign(Y.slabs.size(), -1);
+    Y.cbase.clear();
+    Y.nnz16 = 0;
+    Y.stage_nnz16.assign(ns, 0);
+    std::vector<int> slab_stage(Y.slabs.size());
+    for (int c = 0; c < ns; ++c)
+      for (int q = Y.sslab[c]; q < Y.sslab[c + 1]; ++q) slab_stage[q] = c;
+    for (size_t q = 0; q < Y.slabs.size(); ++q) {
+      const Slab& s = Y.slabs[q];
+      std::vector<int> lo(s.width, INT32_MAX), hi(s.width, INT32_MIN);
+      int64_t real = 0;
+      for (int lane = 0; lane < s.nrows; ++lane) {
+        const int i = Y.perm[s.row0 + lane];
+        const int len = L.rp[i + 1] - L.rp[i] - 1;
+        real += len;
+        for (int j = 0; j < len; ++j) {
+          const int c = Y.col[(int64_t)s.off + (int64_t)j * 64 + lane];
+          lo[j] = std::min(lo[j], c);
+          hi[j] = std::max(hi[j], c);
+        }
+      }
+      bool fits = true;
+      for (int j = 0; j < s.width; ++j) {
+        if (lo[j] > hi[j]) lo[j] = hi[j] = s.row0;  // only padding in this position
+        fits = fits && (int64_t)hi[j] - lo[j] <= 65535;
+      }
+      if (!fits) continue;
+      Y.scb[q] = (int)Y.cbase.size();
+      const int wpad = (s.width + 7) / 8 * 8;
+      for (int j = 0; j < wpad; ++j) Y.cbase.push_back(lo[std::min(j, s.width - 1)]);
+      for (int lane = 0; lane < s.nrows; ++lane)
+        for (int j = 0; j < s.width; ++j) {
+          const int64_t at = (int64_t)s.off + (int64_t)j * 64 + lane;
+          const int64_t d = (int64_t)Y.col[at] - lo[j];
+          // padding (value 0) whose own row is out of range points at the base
+          Y.col16[at] = (uint16_t)((d >= 0 && d <= 65535) ? d : 0);
+        }
+      Y.nnz16 += real;
+      Y.stage_nnz16[slab_stage[q]] += real;
+    }
   } else {
     Y.rowptr.assign(n + 1, 0);
     Y.col.reserve(offcount);
@@ -437,15 +486,26 @@ inline void build_transfer_layout(const HostLevel& L, const LevelLayout& Yf, con
   T.aptr = L.aptr;
   T.uoff = L.uoff;
   // U_a stored column-major (k_a x n_a): column l of a block is one
-  // contiguous, coalesced run for the wave that handles the aggregate.
+  // contiguous, coalesced run for the wave that handles the aggregate.  The
+  // members of an aggregate are listed in increasing level order (the order
+  // of the file's members is immaterial to P), so the members of earlier
+  // smoother stages come first and the U entries of later stages' members
+  // share no cache line with them.
   T.U.resize(L.U.size());
-  for (int a = 0; a < na; ++a) {
-    const int m = L.aptr[a + 1] - L.aptr[a], k = L.coff[a + 1] - L.coff[a];
-    for (int li = 0; li < m; ++li)
-      for (int l = 0; l < k; ++l) T.U[(size_t)L.uoff[a] + (size_t)l * m + li] = L.U[(size_t)L.uoff[a] + (size_t)li * k + l];
-  }
   T.arows.resize(L.arows.size());
-  for (size_t q = 0; q < L.arows.size(); ++q) T.arows[q] = Yf.iperm[L.arows[q]];
+  std::vector<int> ord;
+  for (int a = 0; a < na; ++a) {
+    const int m = L.aptr[a + 1] - L.aptr[a], k = L.coff[a + 1] - L.coff[a], m0 = L.aptr[a];
+    ord.resize(m);
+    for (int li = 0; li < m; ++li) ord[li] = li;
+    std::sort(ord.begin(), ord.end(),
+              [&](int x, int y) { return Yf.iperm[L.arows[m0 + x]] < Yf.iperm[L.arows[m0 + y]]; });
+    for (int t = 0; t < m; ++t) {
+      const int li = ord[t];
+      T.arows[m0 + t] = Yf.iperm[L.arows[m0 + li]];
+      for (int l = 0; l < k; ++l) T.U[(size_t)L.uoff[a] + (size_t)l * m + t] = L.U[(size_t)L.uoff[a] + (size_t)li * k + l];
+    }
+  }
   T.cst.resize(na);
   T.kk.resize(na);
   T.max_na = 0;

@@ -14,6 +14,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "hier_host.hpp"
 
 namespace mvamg {
@@ -272,6 +274,32 @@ __global__ __launch_bounds__(kBlock) void k_xpay(int n, const double* __restrict
 
 // ------------------------------------------------- sliced-ELL (point) levels
 
+// Column indices of the slabs: 32-bit (col), or, where a slab's j-th entries
+// span at most 65535 columns, 16-bit deltas col16 from a per-(slab, entry
+// position) base cbase[scb[s] + j] (scb[s] = -1: 32-bit; the bases of a slab
+// are padded to a multiple of 8 with the last one).
+struct SellCols {
+  const int* __restrict__ col;
+  const uint16_t* __restrict__ col16;
+  const int* __restrict__ cbase;
+  const int* __restrict__ scb;
+};
+
+// Columns of the entries j0 .. j0 + 7 (clamped to the slab's width) of slab
+// row `lane`; cb = scb[slab] (wave-uniform).
+__device__ __forceinline__ void sell_cols8(const SellCols& C, const Slab& sl, int cb, int lane, int j0, int cc[8]) {
+  if (cb >= 0) {
+    const uint16_t* c16 = C.col16 + sl.off + lane;
+    const int* b = C.cbase + cb + j0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cc[u] = b[u] + (int)c16[64 * min(j0 + u, sl.width - 1)];
+  } else {
+    const int* c = C.col + sl.off + lane;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cc[u] = c[64 * min(j0 + u, sl.width - 1)];
+  }
+}
+
 // One Gauss-Seidel stage: x_p <- (r_p - sum_{j != p} a_pj x_j) / a_pp for the
 // rows of the slabs [s0, s1) (rows of one stage are not coupled).  In the
 // forward sweep from x = 0, lim is the stage's first row: entries of later
@@ -282,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_xpay(int n, const double* __restrict
 // sweep of a cycle then yields the partials of z.r).
 template <typename T, int DOT>
 __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ slabs, int s0, int s1,
-                                                    const int* __restrict__ col, const T* __restrict__ val,
+                                                    SellCols C, const T* __restrict__ val,
                                                     const T* __restrict__ diag, const T* __restrict__ r, T* x,
                                                     Skip sk, int lim, double* __restrict__ part) {
   const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
@@ -290,9 +318,9 @@ __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ sla
   double dsum = 0.0;
   if (s < s1 && !skipped(sk, s)) {
     const Slab sl = slabs[s];
+    const int cb = C.scb[s];
     if (lane < sl.nrows) {
       const int p = sl.row0 + lane;
-      const int* c = col + sl.off + lane;
       const T* v = val + sl.off + lane;
       const T rp = r[p];
       T acc = rp;
@@ -300,12 +328,9 @@ __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ sla
       for (int j0 = 0; j0 < sl.width; j0 += 8) {
         int cc[8];
         T vv[8], xx[8];
+        sell_cols8(C, sl, cb, lane, j0, cc);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int j = min(j0 + u, sl.width - 1);
-          cc[u] = c[64 * j];
-          vv[u] = v[64 * j];
-        }
+        for (int u = 0; u < 8; ++u) vv[u] = v[64 * min(j0 + u, sl.width - 1)];
 #pragma unroll
         for (int u = 0; u < 8; ++u) xx[u] = x[min(cc[u], lim - 1)];
 #pragma unroll
@@ -332,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_stage0_point(int rows0, const T* __r
 // s = r - A x (MODE 0), y = A x with sum x.y (MODE 1, binary64 only), or y = A x (MODE 2)
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ slabs, int nslabs,
-                                                       const int* __restrict__ col, const T* __restrict__ val,
+                                                       SellCols C, const T* __restrict__ val,
                                                        const T* __restrict__ diag, const T* __restrict__ r,
                                                        const T* __restrict__ x, T* __restrict__ s, Red red, Skip sk) {
   const int sidx = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
@@ -340,21 +365,18 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
   double dsum = 0.0;
   if (sidx < nslabs && !skipped(sk, sidx)) {
     const Slab sl = slabs[sidx];
+    const int cb = C.scb[sidx];
     if (lane < sl.nrows) {
       const int p = sl.row0 + lane;
-      const int* c = col + sl.off + lane;
       const T* v = val + sl.off + lane;
       const T xp = x[p];
       T acc = diag[p] * xp;
       for (int j0 = 0; j0 < sl.width; j0 += 8) {
         int cc[8];
         T vv[8], xx[8];
+        sell_cols8(C, sl, cb, lane, j0, cc);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int j = min(j0 + u, sl.width - 1);
-          cc[u] = c[64 * j];
-          vv[u] = v[64 * j];
-        }
+        for (int u = 0; u < 8; ++u) vv[u] = v[64 * min(j0 + u, sl.width - 1)];
 #pragma unroll
         for (int u = 0; u < 8; ++u) xx[u] = x[cc[u]];
 #pragma unroll
@@ -626,29 +648,30 @@ __global__ __launch_bounds__(kBlock) void k_l1norm_grp(int ng, const int* __rest
 constexpr int kARec = 8;
 enum ARecField { AR_M0 = 0, AR_NA = 1, AR_K = 2, AR_UOFF = 3, AR_C0 = 4, AR_DB = 5 };
 
-// r_c = P^T s with P = blockdiag(U_a): one wave per aggregate, lane li takes
-// member li; r_c[c0 + l] = sum_li U_a[li, l] s[member li].  U_a is stored
-// column-major (U[l * n_a + li]); KMAX bounds the block widths k.
+// r_c = P^T s with P = blockdiag(U_a): LPA lanes per aggregate (16: one DPP
+// row, four aggregates per wave; 64: one wave), lane g takes members g,
+// g + LPA, ... four at a time, all their loads in flight together;
+// r_c[c0 + l] = sum_li U_a[li, l] s[member li].  U_a is stored column-major
+// (U[l * n_a + li]), members in increasing row order; KMAX bounds the block
+// widths k.  Rows >= scut have s = 0: neither s nor U is read for them.
 //
 // The k coarse rows of an aggregate are one smoother group of the next level,
 // so the kernel can also start that level's pre-smoothing from x_c = 0
 // (INIT = 1: the groups of stage 0 solve their lower-triangular diagonal block,
 // the others are zero -- the first Gauss-Seidel stage; INIT = 2: x_c = r_c / d_l1,
 // the first l1-Jacobi sweep).  The record, then U_a, the member rows and the
-// diagonal block's lower triangle are all requested before the gather of s.
-// Rows >= scut have s = 0 and are not read.
-template <typename T, int KMAX, int INIT>
+// diagonal block's lower triangle are all requested before the gathers of s.
+template <typename T, int KMAX, int INIT, int LPA>
 __global__ __launch_bounds__(kBlock) void k_restrict(int nagg, const int* __restrict__ arec,
                                                      const int* __restrict__ arows, const T* __restrict__ U,
                                                      const T* __restrict__ s, int scut, T* __restrict__ rc,
                                                      const T* __restrict__ cdblk, const T* __restrict__ cdl1,
                                                      T* __restrict__ xc, Skip sk) {
-  const int a = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) +
-                                               (int)(threadIdx.x >> 6));
-  if (a >= nagg || skipped(sk, a)) return;
-  const int lane = threadIdx.x & 63;
-  const int* R = arec + (size_t)a * kARec;
-  const int m0 = R[AR_M0], na = R[AR_NA], k = R[AR_K], c0 = R[AR_C0];
+  const int g = threadIdx.x & (LPA - 1);
+  const int a = (xcd_block(blockIdx.x, gridDim.x) * kBlock + (int)threadIdx.x) / LPA;
+  const bool on = a < nagg && !skipped(sk, a);
+  const int* R = arec + (size_t)min(a, nagg - 1) * kARec;
+  const int m0 = R[AR_M0], na = on ? R[AR_NA] : 0, k = R[AR_K], c0 = R[AR_C0];
   const T* Ua = U + R[AR_UOFF];
   // lower triangle of the diagonal block (indices clamped into the k x k
   // block; a record without a block reads the level's first block, which is
@@ -667,41 +690,56 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nagg, const int* __rest
   T acc[KMAX];
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) acc[q] = T(0);
-  for (int li = lane; li < na; li += 64) {
-    const int row = arows[m0 + li];
-    T u[KMAX];
+  for (int b0 = 0; b0 < na; b0 += 4 * LPA) {
+    int row[4];
+    T u[4][KMAX], sv[4];
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q) u[q] = Ua[min(q, k - 1) * na + li];
-    const T sv = (row < scut) ? s[row] : T(0);
+    for (int v = 0; v < 4; ++v) {
+      const int li = b0 + g + v * LPA;
+      row[v] = (li < na) ? arows[m0 + li] : INT_MAX;
+    }
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q)
-      if (q < k) acc[q] += u[q] * sv;
+    for (int v = 0; v < 4; ++v) {
+      const int li = b0 + g + v * LPA;
+      const bool live = row[v] < scut;
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q) u[v][q] = live ? Ua[min(q, k - 1) * na + li] : T(0);
+      sv[v] = live ? s[row[v]] : T(0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q)
+        if (q < k) acc[q] += u[v][q] * sv[v];
   }
-  // wave sums (DPP inside each 16-lane row, then the four row sums in order)
+  // sums over the aggregate's lanes: DPP inside each 16-lane row, then (one
+  // aggregate per wave) the four row sums in order
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) {
-    if (q < k) {
-      const T v = lanes_sum<16>(acc[q]);
-      acc[q] = ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
-      if (lane == q) rc[c0 + q] = acc[q];
-    }
+    const T v = lanes_sum<16>(acc[q]);
+    acc[q] = (LPA == 16) ? v : ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
   }
+  T out = acc[0];
+#pragma unroll
+  for (int q = 1; q < KMAX; ++q)
+    if (g == q) out = acc[q];
+  if (on && g < k) rc[c0 + g] = out;
   if (INIT == 1) {
     T xv[KMAX];
 #pragma unroll
     for (int l = 0; l < KMAX; ++l) {
-      T t = acc[l];
+      T tt = acc[l];
 #pragma unroll
-      for (int q = 0; q < l; ++q) t -= bl[l * (l + 1) / 2 + q] * xv[q];
-      xv[l] = (db >= 0 && l < k) ? t / bl[l * (l + 1) / 2 + l] : T(0);
+      for (int q = 0; q < l; ++q) tt -= bl[l * (l + 1) / 2 + q] * xv[q];
+      xv[l] = (db >= 0 && l < k) ? tt / bl[l * (l + 1) / 2 + l] : T(0);
     }
+    T xo = xv[0];
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q)
-      if (q < k && lane == q) xc[c0 + q] = xv[q];
+    for (int q = 1; q < KMAX; ++q)
+      if (g == q) xo = xv[q];
+    if (on && g < k) xc[c0 + g] = xo;
   } else if (INIT == 2) {
-#pragma unroll
-    for (int q = 0; q < KMAX; ++q)
-      if (q < k && lane == q) xc[c0 + q] = acc[q] / cdl1[c0 + q];
+    if (on && g < k) xc[c0 + g] = out / cdl1[c0 + g];
   }
 }
 

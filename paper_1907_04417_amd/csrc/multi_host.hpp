@@ -162,7 +162,7 @@ template <typename T, int MODE>
 void bresid(mvamg_hier* h, const DevLevel& L, const T* r, const T* x, T* s, int mode, hipStream_t st, int nst = -1) {
   const int kc = MODE != 0 ? MVAMG_KC_SPMV : MVAMG_KC_RESIDUAL;
   const bool part_rows = MODE == 0 && nst >= 0 && nst < L.ns;
-  const double by = part_rows ? resid_stage_bytes<T>(L, nst, 3.0 * kNB * sizeof(T))
+  const double by = part_rows ? resid_stage_bytes<T>(L, nst, 3.0 * kNB * sizeof(T), false)
                               : (double)L.nnz * (sizeof(T) + 4) + 4.0 * (L.n + 1) +
                                     (double)L.n * kNB * sizeof(T) * (MODE != 0 ? 2 : 3);
   int grid = bresid_grid(L, MODE);

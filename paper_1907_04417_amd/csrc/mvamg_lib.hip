@@ -71,6 +71,11 @@ struct DevLevel {
   int* rowptr = nullptr;
   int* rec = nullptr;  // per group: 16-int record (first row, rows, block offset, row entry offsets)
   int* col = nullptr;
+  uint16_t* col16 = nullptr;  // sliced ELL: 16-bit column deltas (see SellCols)
+  int* cbase = nullptr;
+  int* scb = nullptr;
+  int64_t nnz16 = 0;                 // stored entries in 16-bit slabs
+  std::vector<int64_t> stage_nnz16;  // the same per stage
   double* val = nullptr;
   float* val32 = nullptr;
   int* src = nullptr;
@@ -107,6 +112,9 @@ struct DevTransfer {
   // lie in the rows before it).  ncut = nf on levels with multi-row groups.
   int ncut = 0;
   int64_t nu_cut = 0;
+  // U entries of the rows before the first row of the level's last stage
+  // (the rows a restriction after a Gauss-Seidel sweep reads on a point level)
+  int64_t nu_scut = 0;
   int64_t nu = 0;        // entries of the U blocks
   int* cinfo = nullptr;  // per fine row: 8 * first coarse row + (k - 1)
   double* Urow = nullptr;  // per fine row, column-major [q * nf + row]
@@ -383,11 +391,14 @@ float* ls<float>(DevLevel& L) {
 }
 
 // algorithmic bytes of one smoother stage: every stored entry of its rows
-// (value + 4-byte index), and per row an index, r, x written and x read
+// (value + 4-byte index, 2-byte in 16-bit slabs), and per row an index, r,
+// x written and x read
 template <typename T>
 double stage_bytes(const DevLevel& L, int c) {
-  return (double)L.stage_nnz[c] * (sizeof(T) + 4) + (double)L.stage_rows[c] * (4 + 3 * sizeof(T));
+  return (double)L.stage_nnz[c] * (sizeof(T) + 4) - 2.0 * L.stage_nnz16[c] + (double)L.stage_rows[c] * (4 + 3 * sizeof(T));
 }
+
+SellCols scols(const DevLevel& L) { return SellCols{L.col, L.col16, L.cbase, L.scb}; }
 
 // first_sweep: forward sweep from x = 0 on a point level (entries of later
 // stages skipped; see k_gs_sell).  dot_part (binary64 sliced-ELL levels): the
@@ -405,13 +416,13 @@ int gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, i
     const int lim = first_sweep ? L.h_srow[c] : INT_MAX;
     if constexpr (std::is_same<T, double>::value) {
       if (dot_part) {
-        klaunch(h, kc, by, k_gs_sell<T, 1>, grid, kBlock, st, L.slabs, s0, s1, L.col, lval<T>(L), ldblk<T>(L), r, x,
+        klaunch(h, kc, by, k_gs_sell<T, 1>, grid, kBlock, st, L.slabs, s0, s1, scols(L), lval<T>(L), ldblk<T>(L), r, x,
                 lskip(h, l, SKIP_SLAB), lim, dot_part);
         LAUNCHCHECK("gs_stage");
         return grid;
       }
     }
-    klaunch(h, kc, by, k_gs_sell<T, 0>, grid, kBlock, st, L.slabs, s0, s1, L.col, lval<T>(L), ldblk<T>(L), r, x,
+    klaunch(h, kc, by, k_gs_sell<T, 0>, grid, kBlock, st, L.slabs, s0, s1, scols(L), lval<T>(L), ldblk<T>(L), r, x,
             lskip(h, l, SKIP_SLAB), lim, (double*)nullptr);
   } else {
     const int g0 = L.h_sgrp[c], g1 = L.h_sgrp[c + 1];
@@ -451,11 +462,14 @@ void zero_stage0(mvamg_hier* h, int l, const DevLevel& L, const T* r, T* x, hipS
 
 int resid_grid(const DevLevel& L);
 
-// Bytes of the residual over the rows of stages [0, nst).
+// Bytes of the residual over the rows of stages [0, nst); idx16: the 16-bit
+// slabs' entries carry 2-byte indices.
 template <typename T>
-double resid_stage_bytes(const DevLevel& L, int nst, double vec_bytes) {
+double resid_stage_bytes(const DevLevel& L, int nst, double vec_bytes, bool idx16) {
   double b = 0.0;
-  for (int c = 0; c < nst; ++c) b += (double)L.stage_nnz[c] * (sizeof(T) + 4) + (double)L.stage_rows[c] * (4 + vec_bytes);
+  for (int c = 0; c < nst; ++c)
+    b += (double)L.stage_nnz[c] * (sizeof(T) + 4) - (idx16 ? 2.0 * L.stage_nnz16[c] : 0.0) +
+         (double)L.stage_rows[c] * (4 + vec_bytes);
   return b;
 }
 
@@ -468,13 +482,13 @@ void resid(mvamg_hier* h, int l, const DevLevel& L, const T* r, const T* x, T* s
   const Red red = mkred(h);
   const int kc = MODE != 0 ? MVAMG_KC_SPMV : MVAMG_KC_RESIDUAL;
   const bool part = MODE == 0 && nst >= 0 && nst < L.ns;
-  const double by = skip_bytes(h, l, part ? resid_stage_bytes<T>(L, nst, 3.0 * sizeof(T))
-                                          : (double)L.nnz * (sizeof(T) + 4) + 4.0 * (L.n + 1) +
+  const double by = skip_bytes(h, l, part ? resid_stage_bytes<T>(L, nst, 3.0 * sizeof(T), true)
+                                          : (double)L.nnz * (sizeof(T) + 4) - 2.0 * L.nnz16 + 4.0 * (L.n + 1) +
                                                 (double)L.n * sizeof(T) * (MODE != 0 ? 2 : 3));
   if (L.sell) {
     const int ns = part ? L.h_sslab[nst] : L.nslabs;
     if (ns > 0)
-      klaunch(h, kc, by, k_resid_sell<T, MODE>, (ns + 3) / 4, kBlock, st, L.slabs, ns, L.col, lval<T>(L), ldblk<T>(L), r, x,
+      klaunch(h, kc, by, k_resid_sell<T, MODE>, (ns + 3) / 4, kBlock, st, L.slabs, ns, scols(L), lval<T>(L), ldblk<T>(L), r, x,
               s, red, lskip(h, l, SKIP_SLAB));
   } else {
     const int ng = part ? L.h_sgrp[nst] : L.ng;
@@ -555,8 +569,12 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   const bool zero_last = smoother == MVAMG_SMOOTH_GS && L.ng == L.n;
   resid<T, 0>(h, l, L, r, x, s, M_NONE, st, zero_last ? L.ns - 1 : -1);
   const int scut = zero_last ? L.h_srow[L.ns - 1] : L.n;
-  const int tg = (P.nagg + 3) / 4;
-  const double tby = skip_bytes(h, l, (double)P.nu * sizeof(T) + 4.0 * L.n + (double)scut * sizeof(T) + (double)C.n * sizeof(T));
+  // 16 lanes per aggregate when there are enough aggregates to fill the GPU,
+  // else a wave each
+  const bool narrow = P.nagg >= 8192;
+  const int tg = narrow ? (P.nagg + 15) / 16 : (P.nagg + 3) / 4;
+  const double tby = skip_bytes(h, l, (double)(scut == L.n ? P.nu : P.nu_scut) * sizeof(T) + 4.0 * L.n +
+                                          (double)scut * sizeof(T) + (double)C.n * sizeof(T));
   const bool next_smoothed = (l + 2 < h->nl);
   const int init = !next_smoothed ? 0 : (smoother == MVAMG_SMOOTH_GS ? 1 : 2);
   const double iby = next_smoothed ? skip_bytes(h, l, (double)C.n * sizeof(T)) : 0.0;
@@ -564,14 +582,20 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   const T* cdl1 = init == 2 ? ldl1<T>(C) : nullptr;
   T* xcs = init != 0 ? xc : nullptr;
   const Skip ask = lskip(h, l, SKIP_AGG);
-#define MVAMG_RESTRICT(KM)                                                                                        \
+#define MVAMG_RESTRICT_L(KM, LPA)                                                                                 \
   switch (init) {                                                                                                 \
-    case 0: klaunch(h, MVAMG_KC_RESTRICT, tby, k_restrict<T, KM, 0>, tg, kBlock, st, P.nagg, P.arec, P.arows,   \
-                    tU<T>(P), s, scut, rc, cdblk, cdl1, xcs, ask); break;                                               \
-    case 1: klaunch(h, MVAMG_KC_RESTRICT, tby + iby, k_restrict<T, KM, 1>, tg, kBlock, st, P.nagg, P.arec,      \
-                    P.arows, tU<T>(P), s, scut, rc, cdblk, cdl1, xcs, ask); break;                                      \
-    default: klaunch(h, MVAMG_KC_RESTRICT, tby + iby, k_restrict<T, KM, 2>, tg, kBlock, st, P.nagg, P.arec,     \
-                     P.arows, tU<T>(P), s, scut, rc, cdblk, cdl1, xcs, ask); break;                                     \
+    case 0: klaunch(h, MVAMG_KC_RESTRICT, tby, k_restrict<T, KM, 0, LPA>, tg, kBlock, st, P.nagg, P.arec,       \
+                    P.arows, tU<T>(P), s, scut, rc, cdblk, cdl1, xcs, ask); break;                               \
+    case 1: klaunch(h, MVAMG_KC_RESTRICT, tby + iby, k_restrict<T, KM, 1, LPA>, tg, kBlock, st, P.nagg, P.arec, \
+                    P.arows, tU<T>(P), s, scut, rc, cdblk, cdl1, xcs, ask); break;                               \
+    default: klaunch(h, MVAMG_KC_RESTRICT, tby + iby, k_restrict<T, KM, 2, LPA>, tg, kBlock, st, P.nagg,        \
+                     P.arec, P.arows, tU<T>(P), s, scut, rc, cdblk, cdl1, xcs, ask); break;                      \
+  }
+#define MVAMG_RESTRICT(KM)          \
+  if (narrow) {                     \
+    MVAMG_RESTRICT_L(KM, 16)        \
+  } else {                          \
+    MVAMG_RESTRICT_L(KM, 64)        \
   }
   switch (P.kmax) {
     case 1: MVAMG_RESTRICT(1); break;
@@ -580,6 +604,7 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
     case 4: MVAMG_RESTRICT(4); break;
     default: MVAMG_RESTRICT(8); break;
   }
+#undef MVAMG_RESTRICT_L
 #undef MVAMG_RESTRICT
   LAUNCHCHECK("restrict");
   vcycle<T>(h, l + 1, rc, xc, smoother, st, next_smoothed);
@@ -910,7 +935,16 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
           L.stage_nnz[c] += H.lv[l].rp[i + 1] - H.lv[l].rp[i];
         }
       L.ndblk = (int64_t)y.dblk.size();
-      if (y.sell) L.slabs = h->upload_vec(y.slabs, st);
+      if (y.sell) {
+        L.slabs = h->upload_vec(y.slabs, st);
+        L.col16 = h->upload_vec(y.col16, st);
+        L.cbase = h->upload_vec(y.cbase.empty() ? std::vector<int>(8, 0) : y.cbase, st);
+        L.scb = h->upload_vec(y.scb, st);
+        L.nnz16 = y.nnz16;
+        L.stage_nnz16 = y.stage_nnz16;
+      } else {
+        L.stage_nnz16.assign(L.ns, 0);
+      }
       if (!y.sell) {
         L.rowptr = h->upload_vec(y.rowptr, st);
         std::vector<int> rec((size_t)L.ng * kRec, 0);
@@ -1009,6 +1043,7 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
         P.ncut = point ? yf.gstart[yf.sgrp[nsf - 1]] : nf;
         P.nu_cut = 0;
         for (int p = 0; p < P.ncut; ++p) P.nu_cut += (cinfo[p] & 7) + 1;
+        P.nu_scut = P.nu_cut;
         P.cinfo = h->upload_vec(cinfo, st);
         P.Urow = h->upload_vec(urow, st);
         P.Urow32 = h->dalloc<float>(urow.size());

@@ -70,6 +70,29 @@ static int check_level(const HostLevel& L, const LevelLayout& Y, const std::vect
       }
       CHECK(next == Y.gstart[Y.sgrp[c + 1]], "slabs end with the stage");
     }
+    // 16-bit column deltas reproduce every stored column; padding points at a row
+    CHECK(Y.scb.size() == Y.slabs.size() && Y.col16.size() == Y.col.size(), "16-bit column arrays");
+    int64_t real16 = 0;
+    for (size_t q = 0; q < Y.slabs.size(); ++q) {
+      if (Y.scb[q] < 0) continue;
+      const Slab& sl = Y.slabs[q];
+      const int cb = Y.scb[q];
+      CHECK(cb >= 0 && (size_t)cb + (size_t)((sl.width + 7) / 8 * 8) <= Y.cbase.size(), "bases padded to 8");
+      for (int i = 0; i < sl.nrows; ++i) {
+        const int r = Y.perm[sl.row0 + i], len = L.rp[r + 1] - L.rp[r] - 1;
+        for (int j = 0; j < sl.width; ++j) {
+          const int64_t at = (int64_t)sl.off + (int64_t)j * 64 + i;
+          const int64_t c16 = (int64_t)Y.cbase[cb + j] + Y.col16[at];
+          if (j < len) {
+            CHECK(c16 == Y.col[at], "16-bit column equals the stored column");
+            ++real16;
+          } else {
+            CHECK(c16 >= 0 && c16 < n && Y.val[at] == 0.0, "16-bit padding points at a row, value 0");
+          }
+        }
+      }
+    }
+    CHECK(real16 == Y.nnz16, "16-bit entry count");
   } else {
     CHECK((int)Y.rowptr.size() == n + 1 && Y.rowptr[n] == (int)Y.col.size(), "grouped CSR");
     for (int p = 0; p < n; ++p)
@@ -137,7 +160,8 @@ int main(int argc, char** argv) {
         }
         CHECK(cover == H.lv[l + 1].n, "aggregates cover the coarse level");
       }
-      std::printf("ok levels=%d n0=%d sell0=%d\n", H.nl, H.lv[0].n, H.nl > 1 ? (int)Y[0].sell : -1);
+      std::printf("ok levels=%d n0=%d sell0=%d nnz16_0=%lld nnz0=%lld\n", H.nl, H.lv[0].n, H.nl > 1 ? (int)Y[0].sell : -1,
+                  H.nl > 1 ? (long long)Y[0].nnz16 : 0LL, (long long)H.lv[0].rp[H.lv[0].n] - H.lv[0].n);
     }
   } catch (const std::exception& e) {
     std::fprintf(stderr, "error: %s\n", e.what());

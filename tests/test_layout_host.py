@@ -44,6 +44,10 @@ def test_layout_of_workloads(checker):
         out = _run(checker, path)
         if name == "elast12":
             assert "sell0=0" in out  # node-grouped fine level
+        else:
+            # every fine-level entry of a 7-point grid fits 16-bit column deltas
+            kv = dict(t.split("=") for t in out.split()[1:])
+            assert int(kv["nnz16_0"]) == int(kv["nnz0"]) > 0
 
 
 def test_layout_of_a_batch_union(checker):
