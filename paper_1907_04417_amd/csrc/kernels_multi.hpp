@@ -11,6 +11,8 @@
 // S_ACT stops its updates once its residual met the tolerance.
 #pragma once
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace mvamg {
@@ -184,6 +186,73 @@ __global__ __launch_bounds__(kBlock) void k_bxpay(int n, const double* __restric
   }
 }
 
+// Lane J of each 32-lane half wave, broadcast to the half wave (ds_swizzle
+// in bit mode: and-mask 0, or-mask J).
+template <int J>
+__device__ __forceinline__ int half_bcast(int v) {
+  return __builtin_amdgcn_ds_swizzle(v, J << 5);
+}
+template <int J>
+__device__ __forceinline__ double half_bcast(double v) {
+  return __hiloint2double(half_bcast<J>(__double2hiint(v)), half_bcast<J>(__double2loint(v)));
+}
+template <int J>
+__device__ __forceinline__ float half_bcast(float v) {
+  return __int_as_float(half_bcast<J>(__float_as_int(v)));
+}
+
+// Entries J0 .. J0 + 7 of a half wave's row, whose lane c holds entry c of
+// the current 32-entry chunk (mc, mv), broadcast to every lane.
+template <int J0, typename T>
+__device__ __forceinline__ void half_entries8(int mc, T mv, int (&cc)[8], T (&vv)[8]) {
+  cc[0] = half_bcast<J0 + 0>(mc); vv[0] = half_bcast<J0 + 0>(mv);
+  cc[1] = half_bcast<J0 + 1>(mc); vv[1] = half_bcast<J0 + 1>(mv);
+  cc[2] = half_bcast<J0 + 2>(mc); vv[2] = half_bcast<J0 + 2>(mv);
+  cc[3] = half_bcast<J0 + 3>(mc); vv[3] = half_bcast<J0 + 3>(mv);
+  cc[4] = half_bcast<J0 + 4>(mc); vv[4] = half_bcast<J0 + 4>(mv);
+  cc[5] = half_bcast<J0 + 5>(mc); vv[5] = half_bcast<J0 + 5>(mv);
+  cc[6] = half_bcast<J0 + 6>(mc); vv[6] = half_bcast<J0 + 6>(mv);
+  cc[7] = half_bcast<J0 + 7>(mc); vv[7] = half_bcast<J0 + 7>(mv);
+}
+
+// acc + SGN * (sum over the row's entries (col, val at cp[64 j], vp[64 j],
+// j < width) of val * x[col * kNB + c]), the terms added one after the other;
+// entries with col >= lim are skipped (forward sweep from zero).  Lane c loads
+// entry j0 + c of each 32-entry chunk once; the entries reach the other lanes
+// by swizzle.
+template <typename T, int SGN>
+__device__ __forceinline__ T half_row_sum(T acc, const int* __restrict__ cp, const T* __restrict__ vp, int width,
+                                          int c, const T* x, int lim) {
+  for (int j0 = 0; j0 < width; j0 += 32) {
+    const int jc = min(j0 + c, width - 1);
+    const int mc = cp[64 * jc];
+    const T mv = vp[64 * jc];
+    auto step = [&](auto J0c) {
+      constexpr int J0 = decltype(J0c)::value;
+      if (j0 + J0 < width) {
+        int cc[8];
+        T vv[8], xx[8];
+        half_entries8<J0>(mc, mv, cc, vv);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xx[u] = x[(size_t)min(cc[u], lim - 1) * kNB + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (j0 + J0 + u < width && cc[u] < lim) {
+            if (SGN > 0)
+              acc += vv[u] * xx[u];
+            else
+              acc -= vv[u] * xx[u];
+          }
+      }
+    };
+    step(std::integral_constant<int, 0>{});
+    step(std::integral_constant<int, 8>{});
+    step(std::integral_constant<int, 16>{});
+    step(std::integral_constant<int, 24>{});
+  }
+  return acc;
+}
+
 // Gauss-Seidel stage on the slabs [s0, s1) of a sliced-ELL level: half wave
 // per row, (blockIdx, threadIdx) -> row (s0 + hw / 64, hw % 64).  lim as in
 // k_gs_sell (forward sweep from zero: entries of later stages skipped).
@@ -199,24 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_bgs_sell(const Slab* __restrict__ sl
   if (i >= sl.nrows) return;
   const int c = threadIdx.x & 31;
   const int p = sl.row0 + i;
-  const int* cp = col + sl.off + i;
-  const T* vp = val + sl.off + i;
-  T acc = r[(size_t)p * kNB + c];
-  for (int j0 = 0; j0 < sl.width; j0 += 8) {
-    int cc[8];
-    T vv[8], xx[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int j = min(j0 + u, sl.width - 1);
-      cc[u] = cp[64 * j];
-      vv[u] = vp[64 * j];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) xx[u] = x[(size_t)min(cc[u], lim - 1) * kNB + c];
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (j0 + u < sl.width && cc[u] < lim) acc -= vv[u] * xx[u];
-  }
+  const T acc = half_row_sum<T, -1>(r[(size_t)p * kNB + c], col + sl.off + i, val + sl.off + i, sl.width, c, x, lim);
   x[(size_t)p * kNB + c] = acc / diag[p];
 }
 
@@ -246,25 +298,8 @@ __global__ __launch_bounds__(kBlock) void k_bresid_sell(const Slab* __restrict__
     const int i = hw & 63;
     if (i >= sl.nrows) continue;
     const int p = sl.row0 + i;
-    const int* cp = col + sl.off + i;
-    const T* vp = val + sl.off + i;
     const T xp = x[(size_t)p * kNB + c];
-    T acc = diag[p] * xp;
-    for (int j0 = 0; j0 < sl.width; j0 += 8) {
-      int cc[8];
-      T vv[8], xx[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int j = min(j0 + u, sl.width - 1);
-        cc[u] = cp[64 * j];
-        vv[u] = vp[64 * j];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) xx[u] = x[(size_t)cc[u] * kNB + c];
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (j0 + u < sl.width) acc += vv[u] * xx[u];
-    }
+    const T acc = half_row_sum<T, 1>(diag[p] * xp, col + sl.off + i, val + sl.off + i, sl.width, c, x, INT_MAX);
     if (MODE == 0) {
       s[(size_t)p * kNB + c] = r[(size_t)p * kNB + c] - acc;
     } else {
