@@ -20,8 +20,10 @@ residual per system:
   * multi_rhs: 32 right-hand sides B = A X* on the 1024^2 rotated anisotropic
     problem, one block solve against 32 single-system binary64 solves;
   * batch: 64 independent anisotropic problems (sides 32..512) in one batch
-    against 64 separate binary64 solves.
-Both with the binary64 and the binary32 cycle; kernel choices from the
+    against 64 separate binary64 solves;
+  * elasticity: the 48^3-node linear elasticity problem, binary64 solves and
+    binary32-cycle solves.
+All with the binary64 and the binary32 cycle; kernel choices from the
 project's autotuner.
 
 Prints one JSON line.
@@ -48,6 +50,9 @@ WORKLOAD_DESC = {
                "cubes (p=0.5), <=4 smooth vectors, rtol 1e-8",
     "aniso64": "aniso64: 2-D rotated anisotropic diffusion, 9-point FD, 64^2 interior nodes, eps=1e-2, "
                "theta=pi/4, <=3 smooth vectors, rtol 1e-8",
+    "elast48": "elast48: 3-D linear elasticity, trilinear hexahedra, 48^3 free nodes x 3 dofs (n = 331,776), E=1, "
+               "nu=0.3 with 10% nu=0.49 spherical inclusions, one face clamped; <=6 smooth vectors, node-grouped "
+               "fine smoother, rtol 1e-8",
 }
 
 
@@ -250,6 +255,50 @@ def bench_batch(args, torch, mvamg, workloads, tune_cache):
     }
 
 
+def bench_elasticity(args, torch, mvamg, workloads, tune_cache):
+    """3-D linear elasticity (48^3 nodes x 3 dofs, nearly incompressible
+    inclusions): binary64 solves and binary32-cycle solves with binary64 CG,
+    both to 1e-8."""
+    t0 = time.time()
+    P, path, st = workloads.load("elast48")
+    S = mvamg.Solver(path)
+    tune = mvamg.tuned(S.h, tune_cache)
+    log(f"[bench] elast48: levels={st['n']} setup+upload {time.time() - t0:.1f}s tuning {tune}")
+    b = torch.from_numpy(P.b).cuda()
+    x = torch.zeros_like(b)
+    steps = max(1, min(args.steps, 3))
+    res = {}
+    for prec in (64, 32):
+        def solve():
+            x.zero_()
+            return mvamg.pcg_solve(S.h, b, x, rtol=1e-8, maxit=1000, precision=prec)
+        ms, inf = _timed_ms(torch, solve, steps, 1)
+        res[prec] = dict(ms=ms, nit=inf.iterations, ok=bool(inf.converged) and inf.rel_res_true <= 1.01e-8,
+                         true=inf.rel_res_true, x=x.cpu().numpy())
+        log(f"[bench] elast48 precision {prec}: {ms:.2f} ms/solve, nit={inf.iterations}, "
+            f"true_res={inf.rel_res_true:.2e}")
+    mvamg.profile(S.h, True)
+    x.zero_()
+    mvamg.pcg_solve(S.h, b, x, rtol=1e-8, maxit=1000)
+    torch.cuda.synchronize()
+    kernels = _kernel_table(mvamg, S.h, 1)
+    mvamg.profile(S.h, False)
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_solve"])
+    S.close()
+    r64, r32 = res[64], res[32]
+    return {
+        "workload": WORKLOAD_DESC.get("elast48", "elast48"),
+        "value": 1e3 / r64["ms"], "unit": "solves/s", "ms_per_solve": r64["ms"], "nit": r64["nit"],
+        "levels": st["n"], "all_converged": r64["ok"] and r32["ok"],
+        "fp32_cycle": {"value": 1e3 / r32["ms"], "ms_per_solve": r32["ms"], "nit": r32["nit"],
+                       "rel_res_true": r32["true"], "speedup_vs_fp64": r64["ms"] / r32["ms"],
+                       "err_vs_fp64_solution": float(np.abs(r32["x"] - r64["x"]).max() / np.abs(r64["x"]).max())},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": kernels[dom]["gbs"] / HBM_PEAK_GBS, "traffic": recorded_traffic(dom, "elast48")},
+        "kernels": kernels,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -357,10 +406,11 @@ def main():
                           f"core; the oracle's own coarsest factorisation, {tf:.1f} s, is setup and not counted)")
         log(f"[bench] oracle: {tcpu:.1f} s/solve ({nit_c} iterations)")
 
-    multi = batch = None
+    multi = batch = elast = None
     if not args.no_multi:
         multi = bench_multi_rhs(args, torch, mvamg, workloads, tune_cache)
         batch = bench_batch(args, torch, mvamg, workloads, tune_cache)
+        elast = bench_elasticity(args, torch, mvamg, workloads, tune_cache)
 
     r32 = results[32]
     out = {
@@ -390,6 +440,7 @@ def main():
                   "err_vs_fp64_solution": float(np.abs(r32["x"] - r64["x"]).max() / np.abs(r64["x"]).max())},
         "multi_rhs": multi,
         "batch": batch,
+        "elasticity": elast,
     }
     print(json.dumps(out), flush=True)
 

@@ -594,6 +594,135 @@ __global__ __launch_bounds__(kBlock) void k_resid_grp(int ng, const int* __restr
   if (MODE == 1) block_partials<1>(dsum, 0.0, red.part);
 }
 
+// --------------------------------------------------- wide grouped kernels
+
+// Levels whose groups carry many entries (long rows, few groups per stage):
+// one block of NT threads per group (kWide for a smoother stage, which covers
+// few groups; kWideResid for a residual, which covers all of them).  Row l of
+// the group takes the NT / KMAX lanes l * NT / KMAX ..; every lane adds its
+// entries four at a time (their loads in flight together).  The lanes of a
+// row are summed in segments of up to 64 (DPP, then readlane), the segment
+// sums go to LDS and a row's segments are added in order.  The rest is as in
+// k_gs_grp and k_resid_grp.
+constexpr int kWide = 1024, kWideResid = 256;
+
+template <typename T, int KMAX, int NT>
+__device__ __forceinline__ void wide_rowsums(const GroupData<T, KMAX>& d, const int* __restrict__ col,
+                                             const T* __restrict__ val, const T* x, T (&a)[KMAX]) {
+  constexpr int LPR = NT / KMAX;                // lanes per row
+  constexpr int SEG = LPR < 64 ? LPR : 64;      // lanes per segment sum
+  constexpr int SPR = LPR / SEG;                // segments per row
+  static_assert(SEG >= 16, "at least 16 lanes per row");
+  __shared__ T red[NT / SEG];
+  const int l = (int)threadIdx.x / LPR, sub = (int)threadIdx.x % LPR;
+  T acc = T(0);
+  if (l < d.k) {
+    int e0 = d.gb[0], e1 = d.gb[1];
+#pragma unroll
+    for (int q = 1; q < KMAX; ++q)
+      if (q == l) {
+        e0 = d.gb[q];
+        e1 = d.gb[q + 1];
+      }
+    for (int e = e0 + sub; e < e1; e += 4 * LPR) {
+      int cc[4];
+      T vv[4], xx[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int ee = e + u * LPR;
+        const bool ok = ee < e1;
+        const int es = ok ? ee : e;
+        cc[u] = col[es];
+        vv[u] = ok ? val[es] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xx[u] = x[cc[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += vv[u] * xx[u];
+    }
+  }
+  acc = lanes_sum<16>(acc);
+  const int lane = threadIdx.x & 63;
+  if (SEG == 64) {
+    acc = ((lane_value(acc, 0) + lane_value(acc, 16)) + lane_value(acc, 32)) + lane_value(acc, 48);
+  } else if (SEG == 32) {
+    const T h0 = lane_value(acc, 0) + lane_value(acc, 16), h1 = lane_value(acc, 32) + lane_value(acc, 48);
+    acc = (lane < 32) ? h0 : h1;
+  }
+  if (((int)threadIdx.x % SEG) == 0) red[threadIdx.x / SEG] = acc;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    T t = red[q * SPR];
+#pragma unroll
+    for (int i = 1; i < SPR; ++i) t += red[q * SPR + i];
+    a[q] = t;
+  }
+}
+
+template <typename T, int KMAX, int BACK>
+__global__ __launch_bounds__(kWide) void k_gs_grp_wide(int g0, int g1, const int* __restrict__ rec,
+                                                       const int* __restrict__ col, const T* __restrict__ val,
+                                                       const T* __restrict__ dblk, const T* __restrict__ r, T* x) {
+  const int g = g0 + xcd_block(blockIdx.x, gridDim.x);
+  GroupData<T, KMAX> d;
+  load_group<T, KMAX, true>(g, rec, dblk, r, x, d);
+  T dinv[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) dinv[q] = T(1) / d.B[q][q];
+  T a[KMAX];
+  wide_rowsums<T, KMAX, kWide>(d, col, val, x, a);
+#pragma unroll
+  for (int t = 0; t < KMAX; ++t) {
+    const int ll = BACK ? KMAX - 1 - t : t;
+    if (ll < d.k) {
+      T s = d.rv[ll] - a[ll];
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q)
+        if (q < d.k && q != ll) s -= d.B[ll][q] * d.xv[q];
+      d.xv[ll] = s * dinv[ll];
+    }
+  }
+  const int l = threadIdx.x;
+  if (l < d.k) {
+    T v = d.xv[0];
+#pragma unroll
+    for (int q = 1; q < KMAX; ++q)
+      if (l == q) v = d.xv[q];
+    x[d.p0 + l] = v;
+  }
+}
+
+// s = r - A x on the groups [0, ng), one block per group.
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kWideResid) void k_resid_grp_wide(int ng, const int* __restrict__ rec,
+                                                          const int* __restrict__ col, const T* __restrict__ val,
+                                                          const T* __restrict__ dblk, const T* __restrict__ r,
+                                                          const T* __restrict__ x, T* __restrict__ s) {
+  const int g = xcd_block(blockIdx.x, gridDim.x);
+  GroupData<T, KMAX> d;
+  load_group<T, KMAX, false>(g, rec, dblk, r, x, d);
+  T a[KMAX];
+  wide_rowsums<T, KMAX, kWideResid>(d, col, val, x, a);
+  const int l = threadIdx.x;
+  if (l < d.k) {
+    T t = a[0];
+#pragma unroll
+    for (int q = 1; q < KMAX; ++q)
+      if (q == l) t = a[q];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+      T bq = d.B[0][q];
+#pragma unroll
+      for (int i = 1; i < KMAX; ++i)
+        if (i == l) bq = d.B[i][q];
+      if (q < d.k) t += bq * d.xv[q];
+    }
+    const int p = d.p0 + l;
+    s[p] = r[p] - t;
+  }
+}
+
 // ------------------------------------------------------------ l1-Jacobi
 
 template <typename T>

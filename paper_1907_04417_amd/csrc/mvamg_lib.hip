@@ -58,6 +58,7 @@ struct DevLevel {
   bool sell = false;
   int G = 8;   // kernel instantiation of a grouped level: 64 / G lanes per row (autotuned, >= G0)
   int G0 = 8;  // smallest admissible G: the level's largest group rounded up to a power of two
+  bool wide = false;  // grouped level: one block of kWide threads per group (autotuned)
   int ng = 0, ns = 0, nslabs = 0;
   int rows0 = 0;  // rows of stage 0 (point levels)
   std::vector<int> h_sgrp, h_sslab;
@@ -427,10 +428,14 @@ int gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, i
   } else {
     const int g0 = L.h_sgrp[c], g1 = L.h_sgrp[c + 1];
     if (g1 <= g0) return 0;
-    const int grid = (g1 - g0 + 3) / 4;
-#define MVAMG_GS_GRP(K)                                                                                             \
-  (backward ? klaunch(h, kc, by, k_gs_grp<T, K, 1>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x) \
-            : klaunch(h, kc, by, k_gs_grp<T, K, 0>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x))
+    const int grid = L.wide ? g1 - g0 : (g1 - g0 + 3) / 4;
+#define MVAMG_GS_GRP(K)                                                                                                 \
+  if (L.wide)                                                                                                           \
+    (backward ? klaunch(h, kc, by, k_gs_grp_wide<T, K, 1>, grid, kWide, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x) \
+              : klaunch(h, kc, by, k_gs_grp_wide<T, K, 0>, grid, kWide, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x)); \
+  else                                                                                                                  \
+    (backward ? klaunch(h, kc, by, k_gs_grp<T, K, 1>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x) \
+              : klaunch(h, kc, by, k_gs_grp<T, K, 0>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x))
     switch (L.G) {
       case 1: MVAMG_GS_GRP(1); break;
       case 2: MVAMG_GS_GRP(2); break;
@@ -493,7 +498,13 @@ void resid(mvamg_hier* h, int l, const DevLevel& L, const T* r, const T* x, T* s
   } else {
     const int ng = part ? L.h_sgrp[nst] : L.ng;
     const int grid = (ng + 3) / 4;
-    if (ng > 0) switch (L.G) {
+    if (MODE == 0 && L.wide && ng > 0) switch (L.G) {
+      case 1: klaunch(h, kc, by, k_resid_grp_wide<T, 1>, ng, kWideResid, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s); break;
+      case 2: klaunch(h, kc, by, k_resid_grp_wide<T, 2>, ng, kWideResid, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s); break;
+      case 4: klaunch(h, kc, by, k_resid_grp_wide<T, 4>, ng, kWideResid, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s); break;
+      default: klaunch(h, kc, by, k_resid_grp_wide<T, 8>, ng, kWideResid, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s); break;
+    }
+    else if (ng > 0) switch (L.G) {
       case 1: klaunch(h, kc, by, k_resid_grp<T, 1, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
       case 2: klaunch(h, kc, by, k_resid_grp<T, 2, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
       case 4: klaunch(h, kc, by, k_resid_grp<T, 4, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;

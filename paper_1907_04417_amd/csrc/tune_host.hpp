@@ -51,20 +51,30 @@ void tune_group_lanes(mvamg_hier* h, hipStream_t st, std::string& rep) {
     k_fill<double><<<grid_for(L.n), kBlock, 0, st>>>(L.n, 0.0, x);
     LAUNCHCHECK("tune fill");
     int best = L.G;
+    bool best_wide = false;
     double tbest = 1e30;
-    for (int G = L.G0; G <= kKmax; G *= 2) {
+    // wave-per-group kernels with 64 / G lanes per row, then the block-per-group kernels
+    std::vector<std::pair<int, bool>> cand;
+    for (int G = L.G0; G <= kKmax; G *= 2) cand.emplace_back(G, false);
+    cand.emplace_back(L.G0, true);
+    for (const auto& gw : cand) {
+      const int G = gw.first;
+      const bool wide = gw.second;
       L.G = G;
+      L.wide = wide;
       const double t = time_ms(st, 5, [&]() {
         for (int c = 1; c < L.ns; ++c) gs_stage<double>(h, l, L, c, r, x, 0, st);
         resid<double, 0>(h, l, L, r, x, L.s, M_NONE, st);
       });
-      rep += "level " + std::to_string(l) + " G=" + std::to_string(G) + ": " + fmt_us(t) + " us; ";
+      rep += "level " + std::to_string(l) + (wide ? " wide" : " G=" + std::to_string(G)) + ": " + fmt_us(t) + " us; ";
       if (t < tbest) {
         tbest = t;
         best = G;
+        best_wide = wide;
       }
     }
     L.G = best;
+    L.wide = best_wide;
   }
 }
 
@@ -113,13 +123,15 @@ void tune_batch_chunks(mvamg_hier* h, hipStream_t st, std::string& rep) {
 std::string tune_text(const mvamg_hier* h) {
   std::string s;
   for (int l = 0; l + 1 < h->nl; ++l)
-    if (!h->lv[l].sell) s += "G" + std::to_string(l) + "=" + std::to_string(h->lv[l].G) + ";";
+    if (!h->lv[l].sell)
+      s += "G" + std::to_string(l) + "=" + std::to_string(h->lv[l].G) + ";W" + std::to_string(l) + "=" +
+           std::to_string((int)h->lv[l].wide) + ";";
   s += "gemm=" + std::to_string(h->gemm_variant) + ";";
   if (h->nprob > 0) s += "chunks=" + std::to_string(h->pchunks) + ";";
   return s;
 }
 
-// Parses "key=value;..." (keys Gl, gemm, chunks) and applies it after
+// Parses "key=value;..." (keys Gl, Wl, gemm, chunks) and applies it after
 // checking every value; unknown keys are an error.
 void apply_tune_text(mvamg_hier* h, const std::string& text) {
   std::vector<std::pair<std::string, int>> kv;
@@ -145,12 +157,13 @@ void apply_tune_text(mvamg_hier* h, const std::string& text) {
       if (v < -1 || v >= kGemmVariantCount) throw Error(MVAMG_ERR_ARG, "tuning text: gemm variant out of range");
     } else if (k == "chunks") {
       if (h->nprob < 1 || v < 1 || v > 64) throw Error(MVAMG_ERR_ARG, "tuning text: chunks out of range");
-    } else if (k.size() > 1 && k[0] == 'G') {
+    } else if (k.size() > 1 && (k[0] == 'G' || k[0] == 'W')) {
       char* e = nullptr;
       const long l = std::strtol(k.c_str() + 1, &e, 10);
       if (*e || l < 0 || l + 1 >= h->nl || h->lv[l].sell) throw Error(MVAMG_ERR_ARG, "tuning text: no grouped level " + k);
       const int g0 = h->lv[l].G0;
-      if (v < g0 || v > kKmax || (v & (v - 1))) throw Error(MVAMG_ERR_ARG, "tuning text: bad G for " + k);
+      if (k[0] == 'G' && (v < g0 || v > kKmax || (v & (v - 1)))) throw Error(MVAMG_ERR_ARG, "tuning text: bad G for " + k);
+      if (k[0] == 'W' && v != 0 && v != 1) throw Error(MVAMG_ERR_ARG, "tuning text: W is 0 or 1 for " + k);
     } else {
       throw Error(MVAMG_ERR_ARG, "tuning text: unknown key " + k);
     }
@@ -160,6 +173,8 @@ void apply_tune_text(mvamg_hier* h, const std::string& text) {
       h->gemm_variant = p.second;
     else if (p.first == "chunks")
       h->pchunks = p.second;
+    else if (p.first[0] == 'W')
+      h->lv[std::strtol(p.first.c_str() + 1, nullptr, 10)].wide = p.second != 0;
     else
       h->lv[std::strtol(p.first.c_str() + 1, nullptr, 10)].G = p.second;
   }

@@ -253,6 +253,28 @@ int reduce_colours(const std::vector<int>& gp, const std::vector<int>& gi, std::
   return ncol;
 }
 
+// Size of a clique found greedily in the graph (gp, gi) (CSR, sorted
+// neighbour lists, no self loops): from every vertex, its neighbours are added
+// in order when adjacent to all vertices taken so far.  A lower bound on the
+// chromatic number: a colouring with that many colours cannot be improved.
+int greedy_clique(const std::vector<int>& gp, const std::vector<int>& gi) {
+  const int n = (int)gp.size() - 1;
+  auto adjacent = [&](int a, int b) { return std::binary_search(gi.begin() + gp[a], gi.begin() + gp[a + 1], b); };
+  int best = n > 0 ? 1 : 0;
+  std::vector<int> c;
+  for (int v = 0; v < n; ++v) {
+    c.assign(1, v);
+    for (int e = gp[v]; e < gp[v + 1]; ++e) {
+      const int u = gi[e];
+      bool all = true;
+      for (size_t i = 1; i < c.size() && all; ++i) all = adjacent(u, c[i]);
+      if (all) c.push_back(u);
+    }
+    best = std::max(best, (int)c.size());
+  }
+  return best;
+}
+
 // Smoother ordering of a multi-vector level.  Rows are split into groups of
 // consecutive indices (gstart); groups are coloured greedily (first fit, in
 // natural group order) on the graph in which two groups are adjacent when A
@@ -296,7 +318,9 @@ GsOrder group_order(const Csr& A, const std::vector<int>& gstart) {
         }
       gp[g + 1] = (int)gi.size();
     }
-    ncol = reduce_colours(gp, gi, gcol, ncol, 40 * (int64_t)gi.size() + 10000000);
+    for (int g = 0; g < G; ++g) std::sort(gi.begin() + gp[g], gi.begin() + gp[g + 1]);
+    if (greedy_clique(gp, gi) < ncol)
+      ncol = reduce_colours(gp, gi, gcol, ncol, std::min<int64_t>(100 * (int64_t)gi.size() + 10000000, 400000000));
   }
   GsOrder O;
   O.sptr.assign(ncol + 1, 0);

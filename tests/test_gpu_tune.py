@@ -45,6 +45,8 @@ def _grouped_levels(text):
 
 @pytest.mark.parametrize("name", ["jump16", "elast12"])
 def test_every_group_lane_variant_keeps_parity(name, torch_gpu):
+    """Every grouped-level kernel the tuner may choose (64 / G lanes per row,
+    or one block per group) keeps oracle parity."""
     P, path, st = workloads.load(name)
     S = mvamg.Solver(path)
     O = oracle.Oracle(path)
@@ -53,18 +55,20 @@ def test_every_group_lane_variant_keeps_parity(name, torch_gpu):
     assert levels
     r = np.random.default_rng(41).standard_normal(P.n)
     zo = O.vcycle(r)
+    text0 = mvamg.tune_get(S.h)
+    xo, ho, nito, _ = O.pcg(P.b, tol=1e-8)
     for l, g0 in levels.items():
-        g = g0
-        while g <= 8:
-            mvamg.tune_set(S.h, f"G{l}={g}")
+        # wave per group with 64 / g lanes per row, then one block per group
+        variants = [(g, 0) for g in (1, 2, 4, 8) if g >= g0] + [(g0, 1)]
+        for g, w in variants:
+            mvamg.tune_set(S.h, f"G{l}={g};W{l}={w}")
             z = S.cycle(_t(torch_gpu, r)).cpu().numpy()
-            assert _relinf(z, zo) <= 1e-11, (l, g)
+            assert _relinf(z, zo) <= 1e-11, (l, g, w)
             x, res = S.solve(_t(torch_gpu, P.b), rtol=1e-8)
-            xo, ho, nito, _ = O.pcg(P.b, tol=1e-8)
             _hist_parity(res.history, ho, 1e-8)
-            assert _relinf(x.cpu().numpy(), xo) <= 1e-9, (l, g)
-            g *= 2
-        mvamg.tune_set(S.h, f"G{l}={g0}")
+            assert _relinf(x.cpu().numpy(), xo) <= 1e-9, (l, g, w)
+        mvamg.tune_set(S.h, text0)
+    assert mvamg.tune_get(S.h) == text0
     S.close()
 
 
@@ -96,7 +100,7 @@ def test_autotune_report_roundtrip_and_rejects(torch_gpu, tmp_path):
     assert mvamg.tune_get(S.h) == text
     sig = mvamg.signature(S.h)
     assert sig.startswith("arch=") and f"n={P.n}," in sig
-    for bad in ["G0=8", "gemm=99", "foo=1", "G1=3", "G1=16", "chunks=4", "G1"]:
+    for bad in ["G0=8", "W0=1", "W1=2", "gemm=99", "foo=1", "G1=3", "G1=16", "chunks=4", "G1"]:
         with pytest.raises(mvamg.MvamgError) as e:
             mvamg.tune_set(S.h, bad)
         assert e.value.status == mvamg.ERR_ARG, bad
