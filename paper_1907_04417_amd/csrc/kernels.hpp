@@ -893,34 +893,6 @@ __global__ __launch_bounds__(kBlock) void k_prolong_rows(int n, int ld, const in
 
 // ------------------------------------------------------------- coarsest
 
-// y = A x (add = 0) or y += A x (add = 1), A dense row-major n x n with
-// leading dimension ld (a multiple of 2), one wave per row, 16-byte loads,
-// four loads in flight per lane.
-__global__ __launch_bounds__(kBlock) void k_gemv(int n, int ld, const double* __restrict__ A,
-                                                 const double* __restrict__ x, double* __restrict__ y, int add) {
-  const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  if (i >= n) return;
-  const int lane = threadIdx.x & 63;
-  const double2* Ai = reinterpret_cast<const double2*>(A + (size_t)i * ld);
-  const int n2 = n / 2;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int j = lane;
-  for (; j + 192 < n2; j += 256) {
-    const double2 v0 = Ai[j], v1 = Ai[j + 64], v2 = Ai[j + 128], v3 = Ai[j + 192];
-    a0 += v0.x * x[2 * j] + v0.y * x[2 * j + 1];
-    a1 += v1.x * x[2 * j + 128] + v1.y * x[2 * j + 129];
-    a2 += v2.x * x[2 * j + 256] + v2.y * x[2 * j + 257];
-    a3 += v3.x * x[2 * j + 384] + v3.y * x[2 * j + 385];
-  }
-  for (; j < n2; j += 64) {
-    const double2 v = Ai[j];
-    a0 += v.x * x[2 * j] + v.y * x[2 * j + 1];
-  }
-  if ((n & 1) && lane == 0) a1 += A[(size_t)i * ld + n - 1] * x[n - 1];
-  const double acc = wave_sum((a0 + a1) + (a2 + a3));
-  if (lane == 0) y[i] = add ? y[i] + acc : acc;
-}
-
 // Symmetric A (n x n) as its lower-triangle 64 x 64 tiles: tile t = (I, J),
 // J <= I, listed in tij, stored row-major at tiles + 4096 t with every entry
 // of a row or column >= n zero; diagonal tiles whole.  Built once from the
