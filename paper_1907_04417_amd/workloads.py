@@ -11,6 +11,9 @@ hierarchy file cached on disk (setup is the untimed input generator).
               exp(g), g a Gaussian random field (length 0.05, sigma 1), b = h^2 * 1
     aniso1024 the aniso64 operator on a 1024 x 1024 grid (32 right-hand sides
               B = A X* from block_rhs(seed 5) in the multi-RHS runs)
+    aniso520  the aniso64 operator on 520 x 520 (test size: its colour blocks
+              lie more than 65535 rows apart, so the fine level mixes 16-bit
+              and 32-bit column slabs)
     elast48   3-D linear elasticity, trilinear hexahedra, 48^3 free nodes x 3
               dofs (node-based), E = 1, nu = 0.3 with 10 % nu = 0.49 spherical
               inclusions, one face clamped and the opposite face pushed down;
@@ -43,6 +46,7 @@ CONFIGS = {
     "grf1024": dict(gen=lambda: problems.grf_fv5(1024, seed=0), nvec=3, setup={}),
     "grf32": dict(gen=lambda: problems.grf_fv5(32, seed=3), nvec=3, setup=dict(boot_coarse_min=8, coarse_cap=64)),
     "aniso1024": dict(gen=lambda: problems.aniso9(1024, 1e-2, math.pi / 4, seed=0), nvec=3, setup={}),
+    "aniso520": dict(gen=lambda: problems.aniso9(520, 1e-2, math.pi / 4, seed=0), nvec=3, setup={}),
     "elast48": dict(gen=lambda: problems.elast_q1(48, seed=0), nvec=6, setup=dict(fine_group=3)),
     "elast12": dict(gen=lambda: problems.elast_q1(12, seed=0), nvec=6,
                     setup=dict(fine_group=3, boot_coarse_min=8, coarse_cap=64)),

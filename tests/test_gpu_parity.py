@@ -15,7 +15,8 @@ from paper_1907_04417_amd import mvamg, workloads
 
 pytestmark = pytest.mark.gpu
 
-WORKLOADS = ["aniso64", "jump16", "jump32", "elast12"]
+# aniso520: fine-level slabs with 16-bit and with 32-bit columns
+WORKLOADS = ["aniso64", "jump16", "jump32", "elast12", "aniso520"]
 
 
 def _say(*a):

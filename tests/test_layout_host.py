@@ -39,15 +39,18 @@ def test_layout_of_single_hierarchies(checker, tiny_hier, small3d_hier):
 
 def test_layout_of_workloads(checker):
     from paper_1907_04417_amd import workloads
-    for name in ("jump16", "elast12"):
+    for name in ("jump16", "elast12", "aniso520"):
         _, path, _ = workloads.load(name)
         out = _run(checker, path)
+        kv = dict(t.split("=") for t in out.split()[1:])
         if name == "elast12":
             assert "sell0=0" in out  # node-grouped fine level
-        else:
+        elif name == "jump16":
             # every fine-level entry of a 7-point grid fits 16-bit column deltas
-            kv = dict(t.split("=") for t in out.split()[1:])
             assert int(kv["nnz16_0"]) == int(kv["nnz0"]) > 0
+        else:
+            # slabs that reach into two colour blocks keep 32-bit columns
+            assert 0 < int(kv["nnz16_0"]) < int(kv["nnz0"])
 
 
 def test_layout_of_a_batch_union(checker):
