@@ -643,7 +643,6 @@ __global__ __launch_bounds__(64 * W) void k_bgemm_mfma(int n, int ld, const doub
   const int s0 = ((ks * W + w) * nk) / (KS * W), s1 = ((ks * W + w + 1) * nk) / (KS * W);
   const double* Arow = A + (size_t)(r0 + li) * ld + 4 * lq;
   dbl4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
   for (int s = s0; s < s1; ++s) {
     const int kq = 16 * s + 4 * lq;
     const double2 a01 = *reinterpret_cast<const double2*>(Arow + 16 * s);
