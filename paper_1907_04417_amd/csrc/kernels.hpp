@@ -660,18 +660,64 @@ __device__ __forceinline__ void wide_rowsums(const GroupData<T, KMAX>& d, const 
   }
 }
 
+// Group data for a block-per-group kernel: the record with scalar loads, the
+// diagonal block, x and r of the group once per block into LDS (threads
+// t < KMAX * KMAX and t < KMAX); visible after the block's next barrier, and
+// read back by the first wave only, which finishes the group.
+template <typename T, int KMAX, bool WITH_R>
+struct WideStage {
+  T B[KMAX * KMAX], xv[KMAX], rv[KMAX];
+};
+
+template <typename T, int KMAX, bool WITH_R>
+__device__ __forceinline__ void wide_load_group(int g, const int* __restrict__ rec, const T* __restrict__ dblk,
+                                                const T* __restrict__ r, const T* x, GroupData<T, KMAX>& d,
+                                                WideStage<T, KMAX, WITH_R>& st) {
+  const int* R = rec + (size_t)g * kRec;
+  d.p0 = R[0];
+  d.k = R[1];
+  const int db = R[2];
+#pragma unroll
+  for (int q = 0; q <= kKmax; ++q) d.gb[q] = R[3 + q];
+  const int k = d.k, t = threadIdx.x;
+  if (t < KMAX * KMAX) st.B[t] = dblk[db + min(t / KMAX, k - 1) * k + min(t % KMAX, k - 1)];
+  if (t < KMAX) {
+    const T xi = x[d.p0 + min(t, k - 1)];
+    st.xv[t] = (t < k) ? xi : T(0);
+    if (WITH_R) {
+      const T ri = r[d.p0 + min(t, k - 1)];
+      st.rv[t] = (t < k) ? ri : T(0);
+    }
+  }
+}
+
+// Copies the staged block data into d (after the barrier).
+template <typename T, int KMAX, bool WITH_R>
+__device__ __forceinline__ void wide_take_group(const WideStage<T, KMAX, WITH_R>& st, GroupData<T, KMAX>& d) {
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) {
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) d.B[i][j] = st.B[i * KMAX + j];
+    d.xv[i] = st.xv[i];
+    if (WITH_R) d.rv[i] = st.rv[i];
+  }
+}
+
 template <typename T, int KMAX, int BACK>
 __global__ __launch_bounds__(kWide) void k_gs_grp_wide(int g0, int g1, const int* __restrict__ rec,
                                                        const int* __restrict__ col, const T* __restrict__ val,
                                                        const T* __restrict__ dblk, const T* __restrict__ r, T* x) {
   const int g = g0 + xcd_block(blockIdx.x, gridDim.x);
   GroupData<T, KMAX> d;
-  load_group<T, KMAX, true>(g, rec, dblk, r, x, d);
+  __shared__ WideStage<T, KMAX, true> st;
+  wide_load_group<T, KMAX, true>(g, rec, dblk, r, x, d, st);
+  T a[KMAX];
+  wide_rowsums<T, KMAX, kWide>(d, col, val, x, a);  // ends with a barrier
+  if (threadIdx.x >= 64) return;  // the first wave solves the group's rows
+  wide_take_group<T, KMAX, true>(st, d);
   T dinv[KMAX];
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) dinv[q] = T(1) / d.B[q][q];
-  T a[KMAX];
-  wide_rowsums<T, KMAX, kWide>(d, col, val, x, a);
 #pragma unroll
   for (int t = 0; t < KMAX; ++t) {
     const int ll = BACK ? KMAX - 1 - t : t;
@@ -701,9 +747,12 @@ __global__ __launch_bounds__(kWideResid) void k_resid_grp_wide(int ng, const int
                                                           const T* __restrict__ x, T* __restrict__ s) {
   const int g = xcd_block(blockIdx.x, gridDim.x);
   GroupData<T, KMAX> d;
-  load_group<T, KMAX, false>(g, rec, dblk, r, x, d);
+  __shared__ WideStage<T, KMAX, false> st;
+  wide_load_group<T, KMAX, false>(g, rec, dblk, r, x, d, st);
   T a[KMAX];
-  wide_rowsums<T, KMAX, kWideResid>(d, col, val, x, a);
+  wide_rowsums<T, KMAX, kWideResid>(d, col, val, x, a);  // ends with a barrier
+  if (threadIdx.x >= 64) return;  // the first wave finishes the group's rows
+  wide_take_group<T, KMAX, false>(st, d);
   const int l = threadIdx.x;
   if (l < d.k) {
     T t = a[0];
