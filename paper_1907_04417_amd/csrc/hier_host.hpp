@@ -248,6 +248,10 @@ struct LevelLayout {
   std::vector<Slab> slabs;
   std::vector<int> sslab;  // nstages + 1 slab ranges of the stages
   std::vector<int> rowptr;
+  // grouped CSR: a row's entries in increasing column order; rsplit[p] is its
+  // first entry in a later smoother stage (the forward sweep from x = 0 reads
+  // only the entries before it)
+  std::vector<int> rsplit;
   std::vector<int> col;
   std::vector<double> val;
   std::vector<int> src;  // index of each entry in the file's CSR value array (-1: padding)
@@ -460,17 +464,27 @@ inline void build_level_layout(const HostLevel& L, LevelLayout& Y, const std::ve
     }
   } else {
     Y.rowptr.assign(n + 1, 0);
+    Y.rsplit.assign(n, 0);
     Y.col.reserve(offcount);
     Y.val.reserve(offcount);
     Y.src.reserve(offcount);
+    std::vector<int> ents;
     for (int p = 0; p < n; ++p) {
       const int i = Y.perm[p], g = grp[p], g0 = Y.gstart[g], k = Y.gstart[g + 1] - g0;
+      ents.clear();
       for (int e = L.rp[i]; e < L.rp[i + 1]; ++e) {
         const int q = Y.iperm[L.ci[e]];
-        if (q >= g0 && q < g0 + k) continue;
+        if (q < g0 || q >= g0 + k) ents.push_back(e);
+      }
+      std::sort(ents.begin(), ents.end(), [&](int a, int b) { return Y.iperm[L.ci[a]] < Y.iperm[L.ci[b]]; });
+      const int later = Y.gstart[Y.sgrp[stage[g] + 1]];  // first row of the next stage
+      Y.rsplit[p] = (int)Y.col.size();
+      for (int e : ents) {
+        const int q = Y.iperm[L.ci[e]];
         Y.col.push_back(q);
         Y.val.push_back(L.v[e]);
         Y.src.push_back(e);
+        if (q < later) Y.rsplit[p] = (int)Y.col.size();
       }
       Y.rowptr[p + 1] = (int)Y.col.size();
     }

@@ -398,22 +398,28 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
 
 // Grouped levels: one wavefront per group, LPR = 64 / KMAX lanes per row
 // (KMAX a power of two, at least the level's largest group).  Every group has
-// a 64-byte record, read with scalar loads while the rest of the group's data
+// a 96-byte record, read with scalar loads while the rest of the group's data
 // is requested:
 //   rec[0] first row p0, rec[1] rows k, rec[2] offset of its k x k diagonal
 //   block (dense row-major), rec[3 + q] entry offset of row q (q = 0..8,
-//   repeated past row k), rec[12..15] unused.
+//   repeated past row k), rec[12 + q] (q < 8) the end of row q's entries in
+//   earlier smoother stages (a row's entries are in increasing column order),
+//   rec[20..23] unused.
+// In the forward sweep from x = 0 (first = 1) the rows are summed only up to
+// that end: the entries of later stages multiply values that are still zero.
 // Lane sub of row l strides over row l's off-group entries (batches of 4:
 // index loads, gathers, sums); the row is summed inside its aligned group of
 // lanes with DPP moves and each row sum is read into a scalar with readlane.
-constexpr int kRec = 16;
+constexpr int kRec = 24;
 
 // Row sums a[q] (q < KMAX; zero past row k) of the off-group entries of group
 // g times x.  Uniform across the wave.
+// split (forward sweep from zero): the group's record + 12, whose entry l
+// ends row l's sum; nullptr: whole rows.
 template <typename T, int KMAX>
 __device__ __forceinline__ void group_rowsums(const int (&gb)[kKmax + 1], int l, int sub,
                                               const int* __restrict__ col, const T* __restrict__ val, const T* x,
-                                              T (&a)[KMAX]) {
+                                              T (&a)[KMAX], const int* __restrict__ split = nullptr) {
   constexpr int LPR = 64 / KMAX;
   int e0 = gb[0], e1 = gb[1];
 #pragma unroll
@@ -422,6 +428,7 @@ __device__ __forceinline__ void group_rowsums(const int (&gb)[kKmax + 1], int l,
       e0 = gb[q];
       e1 = gb[q + 1];
     }
+  if (split) e1 = split[min(l, kKmax - 1)];
   T acc = T(0);
   for (int e = e0 + sub; e < e1; e += 4 * LPR) {
     int cc[4];
@@ -486,7 +493,8 @@ __device__ __forceinline__ void load_group(int g, const int* __restrict__ rec, c
 template <typename T, int KMAX, int BACK>
 __global__ __launch_bounds__(kBlock) void k_gs_grp(int g0, int g1, const int* __restrict__ rec,
                                                    const int* __restrict__ col, const T* __restrict__ val,
-                                                   const T* __restrict__ dblk, const T* __restrict__ r, T* x) {
+                                                   const T* __restrict__ dblk, const T* __restrict__ r, T* x,
+                                                   int first) {
   const int graw = g0 + xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (int)(threadIdx.x >> 6);
   const int g = __builtin_amdgcn_readfirstlane(min(graw, g1 - 1));
   const int lane = threadIdx.x & 63;
@@ -498,7 +506,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_grp(int g0, int g1, const int* __
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) dinv[q] = T(1) / d.B[q][q];
   T a[KMAX];
-  group_rowsums<T, KMAX>(d.gb, l, sub, col, val, x, a);
+  group_rowsums<T, KMAX>(d.gb, l, sub, col, val, x, a, first ? rec + (size_t)g * kRec + 12 : nullptr);
 #pragma unroll
   for (int t = 0; t < KMAX; ++t) {
     const int ll = BACK ? KMAX - 1 - t : t;
@@ -608,7 +616,8 @@ constexpr int kWide = 1024, kWideResid = 256;
 
 template <typename T, int KMAX, int NT>
 __device__ __forceinline__ void wide_rowsums(const GroupData<T, KMAX>& d, const int* __restrict__ col,
-                                             const T* __restrict__ val, const T* x, T (&a)[KMAX]) {
+                                             const T* __restrict__ val, const T* x, T (&a)[KMAX],
+                                             const int* __restrict__ split = nullptr) {
   constexpr int LPR = NT / KMAX;                // lanes per row
   constexpr int SEG = LPR < 64 ? LPR : 64;      // lanes per segment sum
   constexpr int SPR = LPR / SEG;                // segments per row
@@ -624,6 +633,7 @@ __device__ __forceinline__ void wide_rowsums(const GroupData<T, KMAX>& d, const 
         e0 = d.gb[q];
         e1 = d.gb[q + 1];
       }
+    if (split) e1 = split[min(l, kKmax - 1)];
     for (int e = e0 + sub; e < e1; e += 4 * LPR) {
       int cc[4];
       T vv[4], xx[4];
@@ -691,50 +701,43 @@ __device__ __forceinline__ void wide_load_group(int g, const int* __restrict__ r
   }
 }
 
-// Copies the staged block data into d (after the barrier).
-template <typename T, int KMAX, bool WITH_R>
-__device__ __forceinline__ void wide_take_group(const WideStage<T, KMAX, WITH_R>& st, GroupData<T, KMAX>& d) {
-#pragma unroll
-  for (int i = 0; i < KMAX; ++i) {
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j) d.B[i][j] = st.B[i * KMAX + j];
-    d.xv[i] = st.xv[i];
-    if (WITH_R) d.rv[i] = st.rv[i];
-  }
-}
-
 template <typename T, int KMAX, int BACK>
 __global__ __launch_bounds__(kWide) void k_gs_grp_wide(int g0, int g1, const int* __restrict__ rec,
                                                        const int* __restrict__ col, const T* __restrict__ val,
-                                                       const T* __restrict__ dblk, const T* __restrict__ r, T* x) {
+                                                       const T* __restrict__ dblk, const T* __restrict__ r, T* x,
+                                                       int first) {
   const int g = g0 + xcd_block(blockIdx.x, gridDim.x);
   GroupData<T, KMAX> d;
   __shared__ WideStage<T, KMAX, true> st;
   wide_load_group<T, KMAX, true>(g, rec, dblk, r, x, d, st);
   T a[KMAX];
-  wide_rowsums<T, KMAX, kWide>(d, col, val, x, a);  // ends with a barrier
+  wide_rowsums<T, KMAX, kWide>(d, col, val, x, a, first ? rec + (size_t)g * kRec + 12 : nullptr);  // ends with a barrier
   if (threadIdx.x >= 64) return;  // the first wave solves the group's rows
-  wide_take_group<T, KMAX, true>(st, d);
-  T dinv[KMAX];
+  // the block stays in LDS; x and r of the group in registers
+  T xv[KMAX], rv[KMAX], dinv[KMAX];
 #pragma unroll
-  for (int q = 0; q < KMAX; ++q) dinv[q] = T(1) / d.B[q][q];
+  for (int q = 0; q < KMAX; ++q) {
+    xv[q] = st.xv[q];
+    rv[q] = st.rv[q];
+    dinv[q] = T(1) / st.B[q * KMAX + q];
+  }
 #pragma unroll
   for (int t = 0; t < KMAX; ++t) {
     const int ll = BACK ? KMAX - 1 - t : t;
     if (ll < d.k) {
-      T s = d.rv[ll] - a[ll];
+      T s = rv[ll] - a[ll];
 #pragma unroll
       for (int q = 0; q < KMAX; ++q)
-        if (q < d.k && q != ll) s -= d.B[ll][q] * d.xv[q];
-      d.xv[ll] = s * dinv[ll];
+        if (q < d.k && q != ll) s -= st.B[ll * KMAX + q] * xv[q];
+      xv[ll] = s * dinv[ll];
     }
   }
   const int l = threadIdx.x;
   if (l < d.k) {
-    T v = d.xv[0];
+    T v = xv[0];
 #pragma unroll
     for (int q = 1; q < KMAX; ++q)
-      if (l == q) v = d.xv[q];
+      if (l == q) v = xv[q];
     x[d.p0 + l] = v;
   }
 }
@@ -752,21 +755,16 @@ __global__ __launch_bounds__(kWideResid) void k_resid_grp_wide(int ng, const int
   T a[KMAX];
   wide_rowsums<T, KMAX, kWideResid>(d, col, val, x, a);  // ends with a barrier
   if (threadIdx.x >= 64) return;  // the first wave finishes the group's rows
-  wide_take_group<T, KMAX, false>(st, d);
   const int l = threadIdx.x;
   if (l < d.k) {
     T t = a[0];
 #pragma unroll
     for (int q = 1; q < KMAX; ++q)
       if (q == l) t = a[q];
+    // row l of the block from LDS, x of the group in order
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q) {
-      T bq = d.B[0][q];
-#pragma unroll
-      for (int i = 1; i < KMAX; ++i)
-        if (i == l) bq = d.B[i][q];
-      if (q < d.k) t += bq * d.xv[q];
-    }
+    for (int q = 0; q < KMAX; ++q)
+      if (q < d.k) t += st.B[l * KMAX + q] * st.xv[q];
     const int p = d.p0 + l;
     s[p] = r[p] - t;
   }

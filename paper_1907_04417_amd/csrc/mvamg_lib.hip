@@ -77,6 +77,7 @@ struct DevLevel {
   int* scb = nullptr;
   int64_t nnz16 = 0;                 // stored entries in 16-bit slabs
   std::vector<int64_t> stage_nnz16;  // the same per stage
+  std::vector<int64_t> stage_later;  // grouped levels: entries of a stage's rows in later stages
   double* val = nullptr;
   float* val32 = nullptr;
   int* src = nullptr;
@@ -401,15 +402,16 @@ double stage_bytes(const DevLevel& L, int c) {
 
 SellCols scols(const DevLevel& L) { return SellCols{L.col, L.col16, L.cbase, L.scb}; }
 
-// first_sweep: forward sweep from x = 0 on a point level (entries of later
-// stages skipped; see k_gs_sell).  dot_part (binary64 sliced-ELL levels): the
+// first_sweep: forward sweep from x = 0 (entries of later stages skipped;
+// see k_gs_sell and k_gs_grp).  dot_part (binary64 sliced-ELL levels): the
 // stage also writes block partials of x.r for its rows there.  Returns the
 // number of partials written.
 template <typename T>
 int gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, int backward, hipStream_t st,
              bool first_sweep = false, double* dot_part = nullptr) {
   const int kc = (l == 0) ? MVAMG_KC_SMOOTH_FINE : MVAMG_KC_SMOOTH_COARSE;
-  const double by = skip_bytes(h, l, stage_bytes<T>(L, c));
+  const bool gfirst = first_sweep && !L.sell && !backward;
+  const double by = skip_bytes(h, l, stage_bytes<T>(L, c) - (gfirst ? (double)L.stage_later[c] * (sizeof(T) + 4) : 0.0));
   if (L.sell) {
     const int s0 = L.h_sslab[c], s1 = L.h_sslab[c + 1];
     if (s1 <= s0) return 0;
@@ -431,11 +433,11 @@ int gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, i
     const int grid = L.wide ? g1 - g0 : (g1 - g0 + 3) / 4;
 #define MVAMG_GS_GRP(K)                                                                                                 \
   if (L.wide)                                                                                                           \
-    (backward ? klaunch(h, kc, by, k_gs_grp_wide<T, K, 1>, grid, kWide, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x) \
-              : klaunch(h, kc, by, k_gs_grp_wide<T, K, 0>, grid, kWide, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x)); \
+    (backward ? klaunch(h, kc, by, k_gs_grp_wide<T, K, 1>, grid, kWide, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, 0) \
+              : klaunch(h, kc, by, k_gs_grp_wide<T, K, 0>, grid, kWide, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, (int)gfirst)); \
   else                                                                                                                  \
-    (backward ? klaunch(h, kc, by, k_gs_grp<T, K, 1>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x) \
-              : klaunch(h, kc, by, k_gs_grp<T, K, 0>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x))
+    (backward ? klaunch(h, kc, by, k_gs_grp<T, K, 1>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, 0) \
+              : klaunch(h, kc, by, k_gs_grp<T, K, 0>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, (int)gfirst))
     switch (L.G) {
       case 1: MVAMG_GS_GRP(1); break;
       case 2: MVAMG_GS_GRP(2); break;
@@ -569,7 +571,10 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   // pre-smoothing: one forward sweep from x = 0
   if (smoother == MVAMG_SMOOTH_GS) {
     if (!x_started) zero_stage0<T>(h, l, L, r, x, st);
-    for (int c = 1; c < L.ns; ++c) gs_stage<T>(h, l, L, c, r, x, 0, st, !x_started && L.sell);
+    // from zero: a point level's forward stages skip later-stage columns when
+    // its stage 0 was just written by zero_stage0, a grouped level's always
+    // (its other groups are zero either way)
+    for (int c = 1; c < L.ns; ++c) gs_stage<T>(h, l, L, c, r, x, 0, st, L.sell ? !x_started : true);
   } else if (!x_started) {
     k_l1_init<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, ldl1<T>(L), r, x);
   }
@@ -966,7 +971,12 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
           R[1] = k;
           R[2] = y.dboff[g];
           for (int q = 0; q <= kKmax; ++q) R[3 + q] = y.rowptr[p0 + std::min(q, k)];
+          for (int q = 0; q < kKmax; ++q) R[12 + q] = q < k ? y.rsplit[p0 + q] : y.rowptr[p0 + k];
         }
+        // entries of later stages, per stage (not read by the forward sweep from zero)
+        L.stage_later.assign(L.ns, 0);
+        for (int c = 0; c < L.ns; ++c)
+          for (int p = y.gstart[y.sgrp[c]]; p < y.gstart[y.sgrp[c + 1]]; ++p) L.stage_later[c] += y.rowptr[p + 1] - y.rsplit[p];
         L.rec = h->upload_vec(rec, st);
       }
       L.col = h->upload_vec(y.col, st);

@@ -95,6 +95,20 @@ static int check_level(const HostLevel& L, const LevelLayout& Y, const std::vect
     CHECK(real16 == Y.nnz16, "16-bit entry count");
   } else {
     CHECK((int)Y.rowptr.size() == n + 1 && Y.rowptr[n] == (int)Y.col.size(), "grouped CSR");
+    // a row's entries in increasing column order; rsplit separates the entries
+    // of earlier stages from those of later stages
+    CHECK((int)Y.rsplit.size() == n, "row splits");
+    std::vector<int> stage_of(n, 0);
+    for (int c = 0; c < ns; ++c)
+      for (int p = Y.gstart[Y.sgrp[c]]; p < Y.gstart[Y.sgrp[c + 1]]; ++p) stage_of[p] = c;
+    for (int p = 0; p < n; ++p) {
+      const int later = Y.gstart[Y.sgrp[stage_of[p] + 1]];
+      CHECK(Y.rsplit[p] >= Y.rowptr[p] && Y.rsplit[p] <= Y.rowptr[p + 1], "split inside the row");
+      for (int e = Y.rowptr[p]; e < Y.rowptr[p + 1]; ++e) {
+        if (e > Y.rowptr[p]) CHECK(Y.col[e - 1] < Y.col[e], "row entries in increasing column order");
+        CHECK((e < Y.rsplit[p]) == (Y.col[e] < later), "split separates earlier and later stages");
+      }
+    }
     for (int p = 0; p < n; ++p)
       for (int e = Y.rowptr[p]; e < Y.rowptr[p + 1]; ++e) {
         const int q = Y.col[e];
