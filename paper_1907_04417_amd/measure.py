@@ -15,6 +15,7 @@
 from __future__ import annotations
 
 import csv
+import tempfile
 import os
 import re
 import sys
@@ -67,10 +68,13 @@ def run(workload: str = "jump128", steps: int = 3) -> None:
     c.copy_(a)  # the calibration copy: reads and writes COPY_BYTES
     torch.cuda.synchronize()
     del a, c
+    # kernel choices as bench.py makes them (same tuning cache)
+    cache = os.environ.get("MVAMG_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "mvamg_tune.json"))
     if workload == "aniso1024x32":
         from . import problems
         P, path, st = workloads.load("aniso1024")
         S = mvamg.Solver(path)
+        mvamg.tuned(S.h, cache)
         B, _ = problems.block_rhs(P, 32, seed=workloads.BLOCK_RHS_SEED)
         Bd = torch.from_numpy(B).cuda()
         for _ in range(steps):
@@ -79,6 +83,7 @@ def run(workload: str = "jump128", steps: int = 3) -> None:
     else:
         P, path, st = workloads.load(workload)
         S = mvamg.Solver(path)
+        mvamg.tuned(S.h, cache)
         b = torch.from_numpy(P.b).cuda()
         for _ in range(steps):
             x = torch.zeros_like(b)
