@@ -41,6 +41,8 @@ def kernel_class(name: str) -> str | None:
         return "restrict"
     if "k_bprolong_rows" in name:
         return "prolong"
+    if "k_resid_grp_wide" in name:
+        return "residual"
     if "k_gs_sell" in name or "k_stage0_point" in name:
         return "smooth_fine"
     if "k_gs_grp" in name or "k_zero_stage0_grp" in name:
@@ -55,6 +57,30 @@ def kernel_class(name: str) -> str | None:
     if "k_gemv" in name:
         return "coarse_solve"
     return None
+
+
+def classify_dispatches(names: dict) -> dict:
+    """Kernel class of every cycle dispatch (dispatch id -> class).  A grouped
+    smoother kernel can run on the fine level or on a coarse one, so the level
+    is followed through the dispatch order: a restriction moves one level down,
+    a prolongation one level up, and the CG product (which only the fine level
+    has) marks the fine level again."""
+    out = {}
+    level = 0
+    for d in sorted(names):
+        k = kernel_class(names[d])
+        if k is None:
+            continue
+        if k in ("smooth_fine", "smooth_coarse"):
+            k = "smooth_fine" if level == 0 else "smooth_coarse"
+        elif k == "spmv":
+            level = 0
+        elif k == "restrict":
+            level += 1
+        elif k == "prolong":
+            level = max(level - 1, 0)
+        out[d] = k
+    return out
 
 
 def run(workload: str = "jump128", steps: int = 3) -> None:
@@ -115,11 +141,9 @@ def traffic(fetch_csv: str, write_csv: str, workload: str) -> None:
         copy_kib = max((per[d] for d in copy), default=0.0)
         scale = (COPY_BYTES / 1024.0) / copy_kib if copy_kib > 0 else 1.0
         acc = defaultdict(lambda: [0, 0.0])
-        for d, n in names.items():
-            k = kernel_class(n)
-            if k:
-                acc[k][0] += 1
-                acc[k][1] += per[d] * 1024.0 * scale
+        for d, k in classify_dispatches(names).items():
+            acc[k][0] += 1
+            acc[k][1] += per[d] * 1024.0 * scale
         out[counter] = (scale, acc)
     src = kernel_source_hash()
     fs, fa = out["FETCH_SIZE"]
