@@ -1,0 +1,46 @@
+"""Host logic of the profile tooling: kernel classes of rocprofv3 dispatches."""
+from paper_1907_04417_amd.measure import classify_dispatches, kernel_class
+
+
+def _cycle(fine_stage, coarse_stage, coarse_resid):
+    """Kernel names of one PCG iteration on a three-level hierarchy with a
+    grouped fine level, in launch order."""
+    seq = ["void mvamg::k_zero_stage0_grp<double>(int)"] + [fine_stage.format(0)] * 3
+    seq += ["void mvamg::k_resid_grp<double, 4, 0>(int)", "void mvamg::k_restrict<double, 8, 1, 64>(int)"]
+    seq += ["void mvamg::k_zero_stage0_grp<double>(int)"] + [coarse_stage.format(0)] * 4
+    seq += [coarse_resid, "void mvamg::k_restrict<double, 8, 0, 64>(int)", "void mvamg::k_symv_tiles(int)",
+            "void mvamg::k_symv_sum(int)", "void mvamg::k_prolong_rows<double, 8>(int)"]
+    seq += [coarse_stage.format(1)] * 5 + ["void mvamg::k_prolong_rows<double, 8>(int)"]
+    seq += [fine_stage.format(1)] * 4 + ["void mvamg::k_resid_grp<double, 4, 1>(int)", "void mvamg::k_finish<1>(int)"]
+    return seq
+
+
+def test_grouped_smoothers_take_the_level_of_the_dispatch_order():
+    # the same kernel name runs on the fine and on the coarse level
+    names = _cycle("void mvamg::k_gs_grp<double, 4, {}>(int)", "void mvamg::k_gs_grp<double, 4, {}>(int)",
+                   "void mvamg::k_resid_grp<double, 4, 0>(int)") * 2
+    cls = classify_dispatches(dict(enumerate(names)))
+    count = {}
+    for k in cls.values():
+        count[k] = count.get(k, 0) + 1
+    assert count["smooth_fine"] == 2 * (1 + 3 + 4)
+    assert count["smooth_coarse"] == 2 * (1 + 4 + 5)
+    assert count["residual"] == 2 * 2 and count["spmv"] == 2
+    assert count["restrict"] == 4 and count["prolong"] == 4 and count["coarse_solve"] == 4
+    assert "k_finish" not in str(count)  # not a cycle kernel
+
+
+def test_wide_kernels_are_classed():
+    assert kernel_class("void mvamg::k_resid_grp_wide<double, 8>(int)") == "residual"
+    assert kernel_class("void mvamg::k_gs_grp_wide<double, 8, 1>(int)") in ("smooth_fine", "smooth_coarse")
+    names = _cycle("void mvamg::k_gs_grp<double, 4, {}>(int)", "void mvamg::k_gs_grp_wide<double, 8, {}>(int)",
+                   "void mvamg::k_resid_grp_wide<double, 8>(int)")
+    cls = classify_dispatches(dict(enumerate(names)))
+    wide = [cls[d] for d, n in enumerate(names) if "k_gs_grp_wide" in n]
+    assert wide and set(wide) == {"smooth_coarse"}
+    assert [cls[d] for d, n in enumerate(names) if "k_gs_grp<" in n] == ["smooth_fine"] * 7
+
+
+def test_binary32_kernels_are_not_classed():
+    assert kernel_class("void mvamg::k_gs_grp<float, 4, 1>(int)") is None
+    assert kernel_class("void mvamg::k_gs_sell<double, false>(int)") == "smooth_fine"
