@@ -252,6 +252,14 @@ struct LevelLayout {
   // first entry in a later smoother stage (the forward sweep from x = 0 reads
   // only the entries before it)
   std::vector<int> rsplit;
+  // grouped CSR, the index lists the kernels read: the rows of a group
+  // usually share one column list (the Galerkin product couples whole
+  // aggregates), stored once; otherwise the group's rows' lists follow each
+  // other.  Entry e of row l (0-based in the group) of group g has its column
+  // at gcol[e + gcsh[g] - l * gcm[g]] (gcm = the shared row length, or 0).
+  std::vector<int> gcol, gcsh, gcm;
+  std::vector<int64_t> stage_gidx;       // per stage: stored column indices
+  std::vector<int64_t> stage_later_idx;  // per stage: stored indices of later-stage columns
   std::vector<int> col;
   std::vector<double> val;
   std::vector<int> src;  // index of each entry in the file's CSR value array (-1: padding)
@@ -468,26 +476,83 @@ inline void build_level_layout(const HostLevel& L, LevelLayout& Y, const std::ve
     Y.col.reserve(offcount);
     Y.val.reserve(offcount);
     Y.src.reserve(offcount);
-    std::vector<int> ents;
-    for (int p = 0; p < n; ++p) {
-      const int i = Y.perm[p], g = grp[p], g0 = Y.gstart[g], k = Y.gstart[g + 1] - g0;
-      ents.clear();
-      for (int e = L.rp[i]; e < L.rp[i + 1]; ++e) {
-        const int q = Y.iperm[L.ci[e]];
-        if (q < g0 || q >= g0 + k) ents.push_back(e);
-      }
-      std::sort(ents.begin(), ents.end(), [&](int a, int b) { return Y.iperm[L.ci[a]] < Y.iperm[L.ci[b]]; });
+    // The rows of a group whose column lists differ only a little (a few
+    // structurally zero couplings) are padded with explicit zeros (src -1) to
+    // the union of their lists, so that they share one list: at most a
+    // quarter more stored values.
+    std::vector<std::vector<int>> ents(kKmax);
+    std::vector<int> uni;
+    const int ngr = (int)Y.gstart.size() - 1;
+    for (int g = 0; g < ngr; ++g) {
+      const int g0 = Y.gstart[g], k = Y.gstart[g + 1] - g0;
       const int later = Y.gstart[Y.sgrp[stage[g] + 1]];  // first row of the next stage
-      Y.rsplit[p] = (int)Y.col.size();
-      for (int e : ents) {
-        const int q = Y.iperm[L.ci[e]];
-        Y.col.push_back(q);
-        Y.val.push_back(L.v[e]);
-        Y.src.push_back(e);
-        if (q < later) Y.rsplit[p] = (int)Y.col.size();
+      int64_t own = 0;
+      uni.clear();
+      for (int l = 0; l < k; ++l) {
+        const int i = Y.perm[g0 + l];
+        std::vector<int>& el = ents[l];
+        el.clear();
+        for (int e = L.rp[i]; e < L.rp[i + 1]; ++e) {
+          const int q = Y.iperm[L.ci[e]];
+          if (q < g0 || q >= g0 + k) el.push_back(e);
+        }
+        std::sort(el.begin(), el.end(), [&](int a, int b) { return Y.iperm[L.ci[a]] < Y.iperm[L.ci[b]]; });
+        own += (int64_t)el.size();
+        for (int e : el) uni.push_back(Y.iperm[L.ci[e]]);
       }
-      Y.rowptr[p + 1] = (int)Y.col.size();
+      std::sort(uni.begin(), uni.end());
+      uni.erase(std::unique(uni.begin(), uni.end()), uni.end());
+      const bool pad = k > 1 && 4 * (int64_t)k * (int64_t)uni.size() <= 5 * own;
+      for (int l = 0; l < k; ++l) {
+        const int p = g0 + l;
+        Y.rsplit[p] = (int)Y.col.size();
+        size_t t = 0;
+        const std::vector<int>& el = ents[l];
+        const size_t len = pad ? uni.size() : el.size();
+        for (size_t u = 0; u < len; ++u) {
+          int q, e = -1;
+          if (pad) {
+            q = uni[u];
+            if (t < el.size() && Y.iperm[L.ci[el[t]]] == q) e = el[t++];
+          } else {
+            e = el[u];
+            q = Y.iperm[L.ci[e]];
+          }
+          Y.col.push_back(q);
+          Y.val.push_back(e >= 0 ? L.v[e] : 0.0);
+          Y.src.push_back(e);
+          if (q < later) Y.rsplit[p] = (int)Y.col.size();
+        }
+        Y.rowptr[p + 1] = (int)Y.col.size();
+      }
     }
+    // shared column lists
+    const int ng = (int)Y.gstart.size() - 1, ns = (int)Y.sgrp.size() - 1;
+    Y.gcsh.assign(ng, 0);
+    Y.gcm.assign(ng, 0);
+    Y.gcol.clear();
+    Y.stage_gidx.assign(ns, 0);
+    Y.stage_later_idx.assign(ns, 0);
+    for (int c = 0; c < ns; ++c)
+      for (int g = Y.sgrp[c]; g < Y.sgrp[c + 1]; ++g) {
+        const int p0 = Y.gstart[g], k = Y.gstart[g + 1] - p0, e0 = Y.rowptr[p0], m = Y.rowptr[p0 + 1] - e0;
+        bool shared = true;
+        for (int l = 1; l < k && shared; ++l) {
+          const int el = Y.rowptr[p0 + l];
+          shared = Y.rowptr[p0 + l + 1] - el == m && Y.rsplit[p0 + l] - el == Y.rsplit[p0] - e0 &&
+                   std::equal(Y.col.begin() + el, Y.col.begin() + el + m, Y.col.begin() + e0);
+        }
+        const int at = (int)Y.gcol.size();
+        const int e1 = shared ? e0 + m : Y.rowptr[p0 + k];
+        Y.gcol.insert(Y.gcol.end(), Y.col.begin() + e0, Y.col.begin() + e1);
+        Y.gcsh[g] = at - e0;
+        Y.gcm[g] = shared ? m : 0;
+        Y.stage_gidx[c] += e1 - e0;
+        if (shared)
+          Y.stage_later_idx[c] += Y.rowptr[p0 + 1] - Y.rsplit[p0];
+        else
+          for (int l = 0; l < k; ++l) Y.stage_later_idx[c] += Y.rowptr[p0 + l + 1] - Y.rsplit[p0 + l];
+      }
     // kernels are instantiated for groups of up to 1, 2, 4 or 8 rows
     Y.G = Y.kmax <= 1 ? 1 : Y.kmax <= 2 ? 2 : Y.kmax <= 4 ? 4 : 8;
   }

@@ -404,7 +404,9 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
 //   block (dense row-major), rec[3 + q] entry offset of row q (q = 0..8,
 //   repeated past row k), rec[12 + q] (q < 8) the end of row q's entries in
 //   earlier smoother stages (a row's entries are in increasing column order),
-//   rec[20..23] unused.
+//   rec[20] and rec[21]: entry e of row q has its column index at
+//   col[e + rec[20] - q rec[21]] (rec[21] is the row length when the rows
+//   share one stored column list, else 0), rec[22..23] unused.
 // In the forward sweep from x = 0 (first = 1) the rows are summed only up to
 // that end: the entries of later stages multiply values that are still zero.
 // Lane sub of row l strides over row l's off-group entries (batches of 4:
@@ -413,11 +415,12 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
 constexpr int kRec = 24;
 
 // Row sums a[q] (q < KMAX; zero past row k) of the off-group entries of group
-// g times x.  Uniform across the wave.
+// g times x.  Uniform across the wave.  csh: the lane's row's column shift
+// (rec[20] - l rec[21]).
 // split (forward sweep from zero): the group's record + 12, whose entry l
 // ends row l's sum; nullptr: whole rows.
 template <typename T, int KMAX>
-__device__ __forceinline__ void group_rowsums(const int (&gb)[kKmax + 1], int l, int sub,
+__device__ __forceinline__ void group_rowsums(const int (&gb)[kKmax + 1], int l, int sub, int csh,
                                               const int* __restrict__ col, const T* __restrict__ val, const T* x,
                                               T (&a)[KMAX], const int* __restrict__ split = nullptr) {
   constexpr int LPR = 64 / KMAX;
@@ -436,7 +439,7 @@ __device__ __forceinline__ void group_rowsums(const int (&gb)[kKmax + 1], int l,
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int ee = min(e + u * LPR, e1 - 1);
-      cc[u] = col[ee];
+      cc[u] = col[ee + csh];
       vv[u] = val[ee];
     }
 #pragma unroll
@@ -459,7 +462,7 @@ __device__ __forceinline__ void group_rowsums(const int (&gb)[kKmax + 1], int l,
 // requested before any is used; indices clamped into the group).
 template <typename T, int KMAX>
 struct GroupData {
-  int p0, k;
+  int p0, k, cs, cm;  // cs, cm: rec[20], rec[21]
   int gb[kKmax + 1];
   T B[KMAX][KMAX], xv[KMAX], rv[KMAX];
 };
@@ -471,6 +474,8 @@ __device__ __forceinline__ void load_group(int g, const int* __restrict__ rec, c
   d.p0 = R[0];
   d.k = R[1];
   const T* B = dblk + R[2];
+  d.cs = R[20];
+  d.cm = R[21];
 #pragma unroll
   for (int q = 0; q <= kKmax; ++q) d.gb[q] = R[3 + q];
   const int k = d.k;
@@ -506,7 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_grp(int g0, int g1, const int* __
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) dinv[q] = T(1) / d.B[q][q];
   T a[KMAX];
-  group_rowsums<T, KMAX>(d.gb, l, sub, col, val, x, a, first ? rec + (size_t)g * kRec + 12 : nullptr);
+  group_rowsums<T, KMAX>(d.gb, l, sub, d.cs - l * d.cm, col, val, x, a, first ? rec + (size_t)g * kRec + 12 : nullptr);
 #pragma unroll
   for (int t = 0; t < KMAX; ++t) {
     const int ll = BACK ? KMAX - 1 - t : t;
@@ -573,7 +578,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_grp(int ng, const int* __restr
   GroupData<T, KMAX> d;
   load_group<T, KMAX, false>(g, rec, dblk, r, x, d);
   T a[KMAX];
-  group_rowsums<T, KMAX>(d.gb, l, sub, col, val, x, a);
+  group_rowsums<T, KMAX>(d.gb, l, sub, d.cs - l * d.cm, col, val, x, a);
   double dsum = 0.0;
   if (graw < ng && sub == 0 && l < d.k) {
     T t = T(0), xl = T(0);
@@ -634,6 +639,7 @@ __device__ __forceinline__ void wide_rowsums(const GroupData<T, KMAX>& d, const 
         e1 = d.gb[q + 1];
       }
     if (split) e1 = split[min(l, kKmax - 1)];
+    const int csh = d.cs - l * d.cm;
     for (int e = e0 + sub; e < e1; e += 4 * LPR) {
       int cc[4];
       T vv[4], xx[4];
@@ -642,7 +648,7 @@ __device__ __forceinline__ void wide_rowsums(const GroupData<T, KMAX>& d, const 
         const int ee = e + u * LPR;
         const bool ok = ee < e1;
         const int es = ok ? ee : e;
-        cc[u] = col[es];
+        cc[u] = col[es + csh];
         vv[u] = ok ? val[es] : T(0);
       }
 #pragma unroll
@@ -686,6 +692,8 @@ __device__ __forceinline__ void wide_load_group(int g, const int* __restrict__ r
   const int* R = rec + (size_t)g * kRec;
   d.p0 = R[0];
   d.k = R[1];
+  d.cs = R[20];
+  d.cm = R[21];
   const int db = R[2];
 #pragma unroll
   for (int q = 0; q <= kKmax; ++q) d.gb[q] = R[3 + q];

@@ -78,6 +78,11 @@ struct DevLevel {
   int64_t nnz16 = 0;                 // stored entries in 16-bit slabs
   std::vector<int64_t> stage_nnz16;  // the same per stage
   std::vector<int64_t> stage_later;  // grouped levels: entries of a stage's rows in later stages
+  // grouped levels: per stage, the stored column indices (shared group
+  // lists) and those of later-stage columns
+  std::vector<int64_t> stage_gidx, stage_later_idx;
+  int64_t gidx = 0;
+  int* gcol = nullptr;  // grouped levels: the column index lists the single-vector kernels read
   double* val = nullptr;
   float* val32 = nullptr;
   int* src = nullptr;
@@ -395,9 +400,16 @@ float* ls<float>(DevLevel& L) {
 // algorithmic bytes of one smoother stage: every stored entry of its rows
 // (value + 4-byte index, 2-byte in 16-bit slabs), and per row an index, r,
 // x written and x read
+// Column index bytes the single-vector kernels read for stage c: 4 or 2
+// (16-bit slabs) per entry on point levels, 4 per stored list entry on
+// grouped levels.
+double stage_idx_bytes(const DevLevel& L, int c) {
+  return L.sell ? 4.0 * L.stage_nnz[c] - 2.0 * L.stage_nnz16[c] : 4.0 * L.stage_gidx[c];
+}
+
 template <typename T>
 double stage_bytes(const DevLevel& L, int c) {
-  return (double)L.stage_nnz[c] * (sizeof(T) + 4) - 2.0 * L.stage_nnz16[c] + (double)L.stage_rows[c] * (4 + 3 * sizeof(T));
+  return (double)L.stage_nnz[c] * sizeof(T) + stage_idx_bytes(L, c) + (double)L.stage_rows[c] * (4 + 3 * sizeof(T));
 }
 
 SellCols scols(const DevLevel& L) { return SellCols{L.col, L.col16, L.cbase, L.scb}; }
@@ -411,7 +423,9 @@ int gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, i
              bool first_sweep = false, double* dot_part = nullptr) {
   const int kc = (l == 0) ? MVAMG_KC_SMOOTH_FINE : MVAMG_KC_SMOOTH_COARSE;
   const bool gfirst = first_sweep && !L.sell && !backward;
-  const double by = skip_bytes(h, l, stage_bytes<T>(L, c) - (gfirst ? (double)L.stage_later[c] * (sizeof(T) + 4) : 0.0));
+  const double by = skip_bytes(h, l, stage_bytes<T>(L, c) - (gfirst ? (double)L.stage_later[c] * sizeof(T) +
+                                                                           4.0 * L.stage_later_idx[c]
+                                                                     : 0.0));
   if (L.sell) {
     const int s0 = L.h_sslab[c], s1 = L.h_sslab[c + 1];
     if (s1 <= s0) return 0;
@@ -433,11 +447,11 @@ int gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, i
     const int grid = L.wide ? g1 - g0 : (g1 - g0 + 3) / 4;
 #define MVAMG_GS_GRP(K)                                                                                                 \
   if (L.wide)                                                                                                           \
-    (backward ? klaunch(h, kc, by, k_gs_grp_wide<T, K, 1>, grid, kWide, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, 0) \
-              : klaunch(h, kc, by, k_gs_grp_wide<T, K, 0>, grid, kWide, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, (int)gfirst)); \
+    (backward ? klaunch(h, kc, by, k_gs_grp_wide<T, K, 1>, grid, kWide, st, g0, g1, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, 0) \
+              : klaunch(h, kc, by, k_gs_grp_wide<T, K, 0>, grid, kWide, st, g0, g1, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, (int)gfirst)); \
   else                                                                                                                  \
-    (backward ? klaunch(h, kc, by, k_gs_grp<T, K, 1>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, 0) \
-              : klaunch(h, kc, by, k_gs_grp<T, K, 0>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, (int)gfirst))
+    (backward ? klaunch(h, kc, by, k_gs_grp<T, K, 1>, grid, kBlock, st, g0, g1, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, 0) \
+              : klaunch(h, kc, by, k_gs_grp<T, K, 0>, grid, kBlock, st, g0, g1, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, (int)gfirst))
     switch (L.G) {
       case 1: MVAMG_GS_GRP(1); break;
       case 2: MVAMG_GS_GRP(2); break;
@@ -469,13 +483,14 @@ void zero_stage0(mvamg_hier* h, int l, const DevLevel& L, const T* r, T* x, hipS
 
 int resid_grid(const DevLevel& L);
 
-// Bytes of the residual over the rows of stages [0, nst); idx16: the 16-bit
-// slabs' entries carry 2-byte indices.
+// Bytes of the residual over the rows of stages [0, nst); compact: the
+// kernels read the compact index forms (16-bit slab entries, shared group
+// lists), not 4 bytes per entry.
 template <typename T>
-double resid_stage_bytes(const DevLevel& L, int nst, double vec_bytes, bool idx16) {
+double resid_stage_bytes(const DevLevel& L, int nst, double vec_bytes, bool compact) {
   double b = 0.0;
   for (int c = 0; c < nst; ++c)
-    b += (double)L.stage_nnz[c] * (sizeof(T) + 4) - (idx16 ? 2.0 * L.stage_nnz16[c] : 0.0) +
+    b += (double)L.stage_nnz[c] * sizeof(T) + (compact ? stage_idx_bytes(L, c) : 4.0 * L.stage_nnz[c]) +
          (double)L.stage_rows[c] * (4 + vec_bytes);
   return b;
 }
@@ -490,7 +505,9 @@ void resid(mvamg_hier* h, int l, const DevLevel& L, const T* r, const T* x, T* s
   const int kc = MODE != 0 ? MVAMG_KC_SPMV : MVAMG_KC_RESIDUAL;
   const bool part = MODE == 0 && nst >= 0 && nst < L.ns;
   const double by = skip_bytes(h, l, part ? resid_stage_bytes<T>(L, nst, 3.0 * sizeof(T), true)
-                                          : (double)L.nnz * (sizeof(T) + 4) - 2.0 * L.nnz16 + 4.0 * (L.n + 1) +
+                                          : (double)L.nnz * sizeof(T) +
+                                                (L.sell ? 4.0 * L.nnz - 2.0 * L.nnz16 : 4.0 * L.gidx) +
+                                                4.0 * (L.n + 1) +
                                                 (double)L.n * sizeof(T) * (MODE != 0 ? 2 : 3));
   if (L.sell) {
     const int ns = part ? L.h_sslab[nst] : L.nslabs;
@@ -501,16 +518,16 @@ void resid(mvamg_hier* h, int l, const DevLevel& L, const T* r, const T* x, T* s
     const int ng = part ? L.h_sgrp[nst] : L.ng;
     const int grid = (ng + 3) / 4;
     if (MODE == 0 && L.wide && ng > 0) switch (L.G) {
-      case 1: klaunch(h, kc, by, k_resid_grp_wide<T, 1>, ng, kWideResid, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s); break;
-      case 2: klaunch(h, kc, by, k_resid_grp_wide<T, 2>, ng, kWideResid, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s); break;
-      case 4: klaunch(h, kc, by, k_resid_grp_wide<T, 4>, ng, kWideResid, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s); break;
-      default: klaunch(h, kc, by, k_resid_grp_wide<T, 8>, ng, kWideResid, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s); break;
+      case 1: klaunch(h, kc, by, k_resid_grp_wide<T, 1>, ng, kWideResid, st, ng, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, s); break;
+      case 2: klaunch(h, kc, by, k_resid_grp_wide<T, 2>, ng, kWideResid, st, ng, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, s); break;
+      case 4: klaunch(h, kc, by, k_resid_grp_wide<T, 4>, ng, kWideResid, st, ng, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, s); break;
+      default: klaunch(h, kc, by, k_resid_grp_wide<T, 8>, ng, kWideResid, st, ng, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, s); break;
     }
     else if (ng > 0) switch (L.G) {
-      case 1: klaunch(h, kc, by, k_resid_grp<T, 1, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
-      case 2: klaunch(h, kc, by, k_resid_grp<T, 2, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
-      case 4: klaunch(h, kc, by, k_resid_grp<T, 4, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
-      default: klaunch(h, kc, by, k_resid_grp<T, 8, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
+      case 1: klaunch(h, kc, by, k_resid_grp<T, 1, MODE>, grid, kBlock, st, ng, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
+      case 2: klaunch(h, kc, by, k_resid_grp<T, 2, MODE>, grid, kBlock, st, ng, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
+      case 4: klaunch(h, kc, by, k_resid_grp<T, 4, MODE>, grid, kBlock, st, ng, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
+      default: klaunch(h, kc, by, k_resid_grp<T, 8, MODE>, grid, kBlock, st, ng, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, s, red); break;
     }
   }
   LAUNCHCHECK("resid");
@@ -958,8 +975,13 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
         L.scb = h->upload_vec(y.scb, st);
         L.nnz16 = y.nnz16;
         L.stage_nnz16 = y.stage_nnz16;
+        L.stage_gidx.assign(L.ns, 0);
+        L.stage_later_idx.assign(L.ns, 0);
       } else {
         L.stage_nnz16.assign(L.ns, 0);
+        L.stage_gidx = y.stage_gidx;
+        L.stage_later_idx = y.stage_later_idx;
+        for (int64_t v : y.stage_gidx) L.gidx += v;
       }
       if (!y.sell) {
         L.rowptr = h->upload_vec(y.rowptr, st);
@@ -972,7 +994,10 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
           R[2] = y.dboff[g];
           for (int q = 0; q <= kKmax; ++q) R[3 + q] = y.rowptr[p0 + std::min(q, k)];
           for (int q = 0; q < kKmax; ++q) R[12 + q] = q < k ? y.rsplit[p0 + q] : y.rowptr[p0 + k];
+          R[20] = y.gcsh[g];
+          R[21] = y.gcm[g];
         }
+        L.gcol = h->upload_vec(y.gcol.empty() ? std::vector<int>(1, 0) : y.gcol, st);
         // entries of later stages, per stage (not read by the forward sweep from zero)
         L.stage_later.assign(L.ns, 0);
         for (int c = 0; c < L.ns; ++c)

@@ -109,6 +109,26 @@ static int check_level(const HostLevel& L, const LevelLayout& Y, const std::vect
         CHECK((e < Y.rsplit[p]) == (Y.col[e] < later), "split separates earlier and later stages");
       }
     }
+    // the kernels' index lists: entry e of row l of group g at gcol[e + gcsh[g] - l gcm[g]]
+    const int ngr = (int)Y.gstart.size() - 1;
+    CHECK((int)Y.gcsh.size() == ngr && (int)Y.gcm.size() == ngr, "group index records");
+    int64_t saved = 0, stored = 0;
+    for (int g = 0; g < ngr; ++g) {
+      const int p0 = Y.gstart[g], k = Y.gstart[g + 1] - p0;
+      for (int l = 0; l < k; ++l) {
+        if (Y.gcm[g] > 0) CHECK(Y.rowptr[p0 + l + 1] - Y.rowptr[p0 + l] == Y.gcm[g], "shared row length");
+        for (int e = Y.rowptr[p0 + l]; e < Y.rowptr[p0 + l + 1]; ++e) {
+          const int64_t at = (int64_t)e + Y.gcsh[g] - (int64_t)l * Y.gcm[g];
+          CHECK(at >= 0 && at < (int64_t)Y.gcol.size() && Y.gcol[at] == Y.col[e], "group index list");
+        }
+      }
+      stored += Y.gcm[g] > 0 ? Y.gcm[g] : Y.rowptr[p0 + k] - Y.rowptr[p0];
+      saved += Y.gcm[g] > 0 ? (int64_t)(k - 1) * Y.gcm[g] : 0;
+    }
+    int64_t sstored = 0;
+    for (int c = 0; c < ns; ++c) sstored += Y.stage_gidx[c];
+    CHECK(stored == (int64_t)Y.gcol.size() && sstored == stored && saved + stored == (int64_t)Y.col.size(),
+          "group index list sizes");
     for (int p = 0; p < n; ++p)
       for (int e = Y.rowptr[p]; e < Y.rowptr[p + 1]; ++e) {
         const int q = Y.col[e];
@@ -174,8 +194,16 @@ int main(int argc, char** argv) {
         }
         CHECK(cover == H.lv[l + 1].n, "aggregates cover the coarse level");
       }
-      std::printf("ok levels=%d n0=%d sell0=%d nnz16_0=%lld nnz0=%lld\n", H.nl, H.lv[0].n, H.nl > 1 ? (int)Y[0].sell : -1,
-                  H.nl > 1 ? (long long)Y[0].nnz16 : 0LL, (long long)H.lv[0].rp[H.lv[0].n] - H.lv[0].n);
+      long long gsh = 0, gall = 0;  // groups of grouped levels, and those with a shared column list
+      for (int l = 0; l + 1 < H.nl; ++l)
+        if (!Y[l].sell)
+          for (int m : Y[l].gcm) {
+            gall += 1;
+            gsh += m > 0;
+          }
+      std::printf("ok levels=%d n0=%d sell0=%d nnz16_0=%lld nnz0=%lld gshared=%lld/%lld\n", H.nl, H.lv[0].n,
+                  H.nl > 1 ? (int)Y[0].sell : -1, H.nl > 1 ? (long long)Y[0].nnz16 : 0LL,
+                  (long long)H.lv[0].rp[H.lv[0].n] - H.lv[0].n, gsh, gall);
     }
   } catch (const std::exception& e) {
     std::fprintf(stderr, "error: %s\n", e.what());

@@ -51,6 +51,10 @@ def test_layout_of_workloads(checker):
         else:
             # slabs that reach into two colour blocks keep 32-bit columns
             assert 0 < int(kv["nnz16_0"]) < int(kv["nnz0"])
+        # Galerkin coarse blocks couple whole aggregates, so the rows of a
+        # coarse group (and of an elasticity node) share one column list
+        sh, alln = map(int, kv["gshared"].split("/"))
+        assert alln > 0 and sh == alln, (name, kv["gshared"])
 
 
 def test_layout_of_a_batch_union(checker):
