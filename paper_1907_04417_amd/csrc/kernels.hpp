@@ -171,11 +171,12 @@ __device__ __forceinline__ void block_partials(double a0, double a1, double* par
 
 // The finisher: one block of kFinish threads; thread t adds the partials
 // t + kFinish u in u order, eight loads in flight, then the wave sums are
-// added in wave order.
+// added in wave order.  host (optional): mapped host memory that also gets
+// the scalars (system-scope stores; the host reads them after the stream).
 constexpr int kFinish = 1024;
 template <int NV>
 __global__ __launch_bounds__(kFinish) void k_finish(int nparts, const double* __restrict__ part, double* scal,
-                                                    int mode) {
+                                                    int mode, double* host) {
   __shared__ double lds[2][kFinish / 64];
   const double rho = scal[S_RHO], alpha = scal[S_ALPHA];
   double s0 = 0.0, s1 = 0.0;
@@ -208,6 +209,13 @@ __global__ __launch_bounds__(kFinish) void k_finish(int nparts, const double* __
       t1 += lds[1][q];
     }
     epilogue(mode, t0, t1, rho, alpha, scal);
+    if (host != nullptr) {
+      double v[S_NSCAL];
+#pragma unroll
+      for (int i = 0; i < S_NSCAL; ++i) v[i] = scal[i];
+#pragma unroll
+      for (int i = 0; i < S_NSCAL; ++i) __hip_atomic_store(host + i, v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 

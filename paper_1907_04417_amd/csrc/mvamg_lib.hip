@@ -178,7 +178,8 @@ struct mvamg_hier {
   double* scal = nullptr;
   double* part = nullptr;
   int dot_nparts = 0;  // partials of z.r written by the last cycle's fine backward sweep
-  double* pinned = nullptr;
+  double* pinned = nullptr;  // host copy of scal (mapped; see cg_step_a)
+  double* pinned_dev = nullptr;
   // batch of independent problems (nprob > 0): level-0 rows of problem p are
   // the file rows [poff[p], poff[p+1]); iperm0 maps a file row to smoother order
   int nprob = 0;
@@ -305,12 +306,13 @@ void harvest(mvamg_hier* h) {
   h->pending.clear();
 }
 
-// Adds the block partials of the previous kernel (grid blocks) and applies `mode`.
-void finish(mvamg_hier* h, int nv, int grid, int mode, hipStream_t st) {
+// Adds the block partials of the previous kernel (grid blocks) and applies
+// `mode`; host: also copies the scalars there (mapped host memory).
+void finish(mvamg_hier* h, int nv, int grid, int mode, hipStream_t st, double* host = nullptr) {
   if (nv == 1)
-    k_finish<1><<<1, kFinish, 0, st>>>(grid, h->part, h->scal, mode);
+    k_finish<1><<<1, kFinish, 0, st>>>(grid, h->part, h->scal, mode, host);
   else
-    k_finish<2><<<1, kFinish, 0, st>>>(grid, h->part, h->scal, mode);
+    k_finish<2><<<1, kFinish, 0, st>>>(grid, h->part, h->scal, mode, host);
   LAUNCHCHECK("finish");
 }
 
@@ -731,14 +733,14 @@ void check_device(const mvamg_hier* h) {
 }
 
 // One CG half-step A: q = A p, alpha = rho / p.q, x += alpha p, r -= alpha q,
-// r.r -- then the scalars are copied to pinned host memory.
+// r.r -- whose finisher also writes the scalars to the mapped host buffer
+// (no copy node).
 void cg_step_a(mvamg_hier* h, hipStream_t st) {
   const int n = h->n, eg = grid_for(n);
   spmv0_dot(h, h->p, h->q, M_PQ, st);
   k_axpy2_dot<<<eg, kBlock, 0, st>>>(n, h->scal, h->p, h->q, h->x, h->r, mkred(h));
   LAUNCHCHECK("axpy2");
-  finish(h, 1, eg, M_STORE_RR, st);
-  HIPCHECK(hipMemcpyAsync(h->pinned, h->scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, st));
+  finish(h, 1, eg, M_STORE_RR, st, h->pinned_dev);
 }
 
 // Half-step B: z = B r, beta (standard or flexible), p = z + beta p.  In
@@ -1213,7 +1215,9 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
         h->part = h->dalloc<double>((size_t)cap);
       }
       HIPCHECK(hipMemsetAsync(h->scal, 0, S_NSCAL * sizeof(double), st));
-      HIPCHECK(hipHostMalloc((void**)&h->pinned, S_NSCAL * sizeof(double), hipHostMallocDefault));
+      // mapped and coherent: a finisher kernel writes it, the host reads it after the stream
+      HIPCHECK(hipHostMalloc((void**)&h->pinned, S_NSCAL * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+      HIPCHECK(hipHostGetDevicePointer((void**)&h->pinned_dev, h->pinned, 0));
     }
     for (int l = 0; l + 1 < H.nl; ++l) derive_level(h.get(), l, st);
     HIPCHECK(hipStreamSynchronize(st));
