@@ -269,6 +269,12 @@ struct LevelLayout {
   std::vector<uint16_t> col16;
   std::vector<int> cbase, scb;
   int64_t nnz16 = 0;                // stored entries (without padding) in 16-bit slabs
+  // sliced ELL with few distinct values: 1-byte codes into a table of at most
+  // 256 values, for the entries (vcode, same positions as val) and for the
+  // diagonal (dcode, one per row)
+  bool vcoded = false, dcoded = false;
+  std::vector<uint8_t> vcode, dcode;
+  std::vector<double> vtab, dtab;
   std::vector<int64_t> stage_nnz16;  // the same per stage
   // dense k x k diagonal blocks of the groups (row-major)
   std::vector<int> dboff;
@@ -285,6 +291,25 @@ struct TransferLayout {
 
 // rowprob (optional, file-row order): the problem of every row when the
 // level belongs to a batch; sliced-ELL slabs are then cut where it changes.
+// 1-byte codes of v into a table of its distinct values (compared bit for
+// bit), if there are at most 256 of them; false (code and tab cleared) if not.
+inline bool encode_values(const std::vector<double>& v, std::vector<uint8_t>& code, std::vector<double>& tab) {
+  code.clear();
+  tab.clear();
+  std::vector<uint64_t> bits(v.size());
+  std::memcpy(bits.data(), v.data(), v.size() * sizeof(double));
+  std::vector<uint64_t> u(bits);
+  std::sort(u.begin(), u.end());
+  u.erase(std::unique(u.begin(), u.end()), u.end());
+  if (u.empty() || u.size() > 256) return false;
+  tab.resize(u.size());
+  std::memcpy(tab.data(), u.data(), u.size() * sizeof(double));
+  code.resize(v.size());
+  for (size_t i = 0; i < v.size(); ++i)
+    code[i] = (uint8_t)(std::lower_bound(u.begin(), u.end(), bits[i]) - u.begin());
+  return true;
+}
+
 inline void build_level_layout(const HostLevel& L, LevelLayout& Y, const std::vector<int>* rowprob = nullptr) {
   const int n = L.n;
   Y.n = n;
@@ -470,6 +495,11 @@ inline void build_level_layout(const HostLevel& L, LevelLayout& Y, const std::ve
       Y.nnz16 += real;
       Y.stage_nnz16[slab_stage[q]] += real;
     }
+    // value dictionaries: where a sliced-ELL level's entries (or its
+    // diagonal) take at most 256 distinct values, the kernels read 1-byte
+    // codes and look the values up (exact: the same binary64 values)
+    Y.vcoded = encode_values(Y.val, Y.vcode, Y.vtab);
+    Y.dcoded = encode_values(Y.dblk, Y.dcode, Y.dtab);
   } else {
     Y.rowptr.assign(n + 1, 0);
     Y.rsplit.assign(n, 0);

@@ -308,6 +308,56 @@ __device__ __forceinline__ void sell_cols8(const SellCols& C, const Slab& sl, in
   }
 }
 
+// Values of a sliced-ELL level: the entries (slab layout, as the columns)
+// and the diagonal, each either stored or as 1-byte codes into a table of at
+// most 256 values (the same binary64 values, or their binary32 roundings).
+// A kernel stages the tables in LDS (stage_tables) and looks codes up there.
+template <typename T>
+struct SellVals {
+  const T* __restrict__ val;
+  const T* __restrict__ diag;
+  const uint8_t* __restrict__ vcode;  // nullptr: read val
+  const uint8_t* __restrict__ dcode;  // nullptr: read diag
+  const T* __restrict__ vtab;
+  const T* __restrict__ dtab;
+  int nvtab, ndtab;
+};
+
+constexpr int kTab = 256;
+
+// All threads of the block; ends with a barrier.
+template <typename T>
+__device__ __forceinline__ void stage_tables(const SellVals<T>& V, T* vt, T* dt) {
+  if (V.vcode)
+    for (int i = threadIdx.x; i < V.nvtab; i += blockDim.x) vt[i] = V.vtab[i];
+  if (V.dcode)
+    for (int i = threadIdx.x; i < V.ndtab; i += blockDim.x) dt[i] = V.dtab[i];
+  __syncthreads();
+}
+
+// Values of the entries j0 .. j0 + 7 (clamped to the slab's width) of slab row `lane`.
+template <typename T>
+__device__ __forceinline__ void sell_vals8(const SellVals<T>& V, const T* vt, const Slab& sl, int lane, int j0,
+                                           T vv[8]) {
+  if (V.vcode) {
+    const uint8_t* c = V.vcode + sl.off + lane;
+    int cc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cc[u] = c[64 * min(j0 + u, sl.width - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) vv[u] = vt[cc[u]];
+  } else {
+    const T* v = V.val + sl.off + lane;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) vv[u] = v[64 * min(j0 + u, sl.width - 1)];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T sell_diag(const SellVals<T>& V, const T* dt, int p) {
+  return V.dcode ? dt[V.dcode[p]] : V.diag[p];
+}
+
 // One Gauss-Seidel stage: x_p <- (r_p - sum_{j != p} a_pj x_j) / a_pp for the
 // rows of the slabs [s0, s1) (rows of one stage are not coupled).  In the
 // forward sweep from x = 0, lim is the stage's first row: entries of later
@@ -318,9 +368,10 @@ __device__ __forceinline__ void sell_cols8(const SellCols& C, const Slab& sl, in
 // sweep of a cycle then yields the partials of z.r).
 template <typename T, int DOT>
 __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ slabs, int s0, int s1,
-                                                    SellCols C, const T* __restrict__ val,
-                                                    const T* __restrict__ diag, const T* __restrict__ r, T* x,
+                                                    SellCols C, SellVals<T> V, const T* __restrict__ r, T* x,
                                                     Skip sk, int lim, double* __restrict__ part) {
+  __shared__ T vt[kTab], dt[kTab];
+  stage_tables(V, vt, dt);
   const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   double dsum = 0.0;
@@ -329,23 +380,21 @@ __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ sla
     const int cb = C.scb[s];
     if (lane < sl.nrows) {
       const int p = sl.row0 + lane;
-      const T* v = val + sl.off + lane;
       const T rp = r[p];
       T acc = rp;
-      // entries in batches of 8: all index loads, then all gathers, then the sums
+      // entries in batches of 8: all index and value loads, then all gathers, then the sums
       for (int j0 = 0; j0 < sl.width; j0 += 8) {
         int cc[8];
         T vv[8], xx[8];
         sell_cols8(C, sl, cb, lane, j0, cc);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) vv[u] = v[64 * min(j0 + u, sl.width - 1)];
+        sell_vals8(V, vt, sl, lane, j0, vv);
 #pragma unroll
         for (int u = 0; u < 8; ++u) xx[u] = x[min(cc[u], lim - 1)];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
           if (j0 + u < sl.width && cc[u] < lim) acc -= vv[u] * xx[u];
       }
-      const T xn = acc / diag[p];
+      const T xn = acc / sell_diag(V, dt, p);
       x[p] = xn;
       if (DOT) dsum = (double)xn * (double)rp;
     }
@@ -356,18 +405,22 @@ __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ sla
 // First stage of the forward sweep from x = 0 on a point level: x_p = r_p /
 // a_pp for the rows p < rows0 (the other rows are written by their stages).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_stage0_point(int rows0, const T* __restrict__ diag,
-                                                         const T* __restrict__ r, T* __restrict__ x, Skip sk) {
+__global__ __launch_bounds__(kBlock) void k_stage0_point(int rows0, SellVals<T> V, const T* __restrict__ r,
+                                                         T* __restrict__ x, Skip sk) {
+  __shared__ T vt[1], dt[kTab];
+  V.vcode = nullptr;  // entries are not read
+  stage_tables(V, vt, dt);
   for (int p = blockIdx.x * kBlock + threadIdx.x; p < rows0; p += gridDim.x * kBlock)
-    if (!skipped(sk, p)) x[p] = r[p] / diag[p];
+    if (!skipped(sk, p)) x[p] = r[p] / sell_diag(V, dt, p);
 }
 
 // s = r - A x (MODE 0), y = A x with sum x.y (MODE 1, binary64 only), or y = A x (MODE 2)
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ slabs, int nslabs,
-                                                       SellCols C, const T* __restrict__ val,
-                                                       const T* __restrict__ diag, const T* __restrict__ r,
+                                                       SellCols C, SellVals<T> V, const T* __restrict__ r,
                                                        const T* __restrict__ x, T* __restrict__ s, Red red, Skip sk) {
+  __shared__ T vt[kTab], dt[kTab];
+  stage_tables(V, vt, dt);
   const int sidx = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   double dsum = 0.0;
@@ -376,15 +429,13 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
     const int cb = C.scb[sidx];
     if (lane < sl.nrows) {
       const int p = sl.row0 + lane;
-      const T* v = val + sl.off + lane;
       const T xp = x[p];
-      T acc = diag[p] * xp;
+      T acc = sell_diag(V, dt, p) * xp;
       for (int j0 = 0; j0 < sl.width; j0 += 8) {
         int cc[8];
         T vv[8], xx[8];
         sell_cols8(C, sl, cb, lane, j0, cc);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) vv[u] = v[64 * min(j0 + u, sl.width - 1)];
+        sell_vals8(V, vt, sl, lane, j0, vv);
 #pragma unroll
         for (int u = 0; u < 8; ++u) xx[u] = x[cc[u]];
 #pragma unroll

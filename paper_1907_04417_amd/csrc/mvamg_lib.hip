@@ -83,6 +83,14 @@ struct DevLevel {
   std::vector<int64_t> stage_gidx, stage_later_idx;
   int64_t gidx = 0;
   int* gcol = nullptr;  // grouped levels: the column index lists the single-vector kernels read
+  // sliced-ELL levels with few distinct values: 1-byte codes of the entries
+  // and of the diagonal, and their tables (binary64 and binary32); valid
+  // for the values uploaded with the layout, cleared by a value refill
+  uint8_t *vcode = nullptr, *dcode = nullptr;
+  double *vtab = nullptr, *dtab = nullptr;
+  float *vtab32 = nullptr, *dtab32 = nullptr;
+  int nvtab = 0, ndtab = 0;
+  bool vcoded = false, dcoded = false;
   double* val = nullptr;
   float* val32 = nullptr;
   int* src = nullptr;
@@ -339,6 +347,29 @@ const float* ldblk<float>(const DevLevel& L) {
   return L.dblk32;
 }
 template <typename T>
+SellVals<T> svals(const DevLevel& L) {
+  SellVals<T> V{lval<T>(L), ldblk<T>(L), L.vcoded ? L.vcode : nullptr, L.dcoded ? L.dcode : nullptr, nullptr, nullptr,
+                L.nvtab, L.ndtab};
+  if constexpr (std::is_same<T, double>::value) {
+    V.vtab = L.vtab;
+    V.dtab = L.dtab;
+  } else {
+    V.vtab = L.vtab32;
+    V.dtab = L.dtab32;
+  }
+  return V;
+}
+
+// Bytes of the matrix data the single-vector kernels read for rows rows with
+// nnz entries (nnz16 of them off-diagonal with 2-byte indices) of a
+// sliced-ELL level: values or codes, indices, diagonal.
+template <typename T>
+double sell_mat_bytes(const DevLevel& L, double nnz, double rows, double nnz16) {
+  const double vb = L.vcoded ? 1.0 : sizeof(T), db = L.dcoded ? 1.0 : sizeof(T);
+  return (nnz - rows) * (vb + 4.0) - 2.0 * nnz16 + rows * db;
+}
+
+template <typename T>
 const T* ldl1(const DevLevel& L);
 template <>
 const double* ldl1<double>(const DevLevel& L) {
@@ -411,6 +442,9 @@ double stage_idx_bytes(const DevLevel& L, int c) {
 
 template <typename T>
 double stage_bytes(const DevLevel& L, int c) {
+  if (L.sell)
+    return sell_mat_bytes<T>(L, L.stage_nnz[c], L.stage_rows[c], L.stage_nnz16[c]) +
+           (double)L.stage_rows[c] * (4 + 2 * sizeof(T));
   return (double)L.stage_nnz[c] * sizeof(T) + stage_idx_bytes(L, c) + (double)L.stage_rows[c] * (4 + 3 * sizeof(T));
 }
 
@@ -435,13 +469,13 @@ int gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, i
     const int lim = first_sweep ? L.h_srow[c] : INT_MAX;
     if constexpr (std::is_same<T, double>::value) {
       if (dot_part) {
-        klaunch(h, kc, by, k_gs_sell<T, 1>, grid, kBlock, st, L.slabs, s0, s1, scols(L), lval<T>(L), ldblk<T>(L), r, x,
+        klaunch(h, kc, by, k_gs_sell<T, 1>, grid, kBlock, st, L.slabs, s0, s1, scols(L), svals<T>(L), r, x,
                 lskip(h, l, SKIP_SLAB), lim, dot_part);
         LAUNCHCHECK("gs_stage");
         return grid;
       }
     }
-    klaunch(h, kc, by, k_gs_sell<T, 0>, grid, kBlock, st, L.slabs, s0, s1, scols(L), lval<T>(L), ldblk<T>(L), r, x,
+    klaunch(h, kc, by, k_gs_sell<T, 0>, grid, kBlock, st, L.slabs, s0, s1, scols(L), svals<T>(L), r, x,
             lskip(h, l, SKIP_SLAB), lim, (double*)nullptr);
   } else {
     const int g0 = L.h_sgrp[c], g1 = L.h_sgrp[c + 1];
@@ -473,8 +507,8 @@ template <typename T>
 void zero_stage0(mvamg_hier* h, int l, const DevLevel& L, const T* r, T* x, hipStream_t st) {
   const int kc = (l == 0) ? MVAMG_KC_SMOOTH_FINE : MVAMG_KC_SMOOTH_COARSE;
   if (L.sell) {
-    const double by = skip_bytes(h, l, (double)L.rows0 * (3 * sizeof(T)));
-    klaunch(h, kc, by, k_stage0_point<T>, grid_elem(L.rows0), kBlock, st, L.rows0, ldblk<T>(L), r, x,
+    const double by = skip_bytes(h, l, (double)L.rows0 * (2 * sizeof(T) + (L.dcoded ? 1 : sizeof(T))));
+    klaunch(h, kc, by, k_stage0_point<T>, grid_elem(L.rows0), kBlock, st, L.rows0, svals<T>(L), r, x,
             lskip(h, l, SKIP_ROW));
   } else {
     const double by = skip_bytes(h, l, (double)L.n * sizeof(T) + (double)L.stage_rows[0] * (2 * sizeof(T)));
@@ -492,8 +526,11 @@ template <typename T>
 double resid_stage_bytes(const DevLevel& L, int nst, double vec_bytes, bool compact) {
   double b = 0.0;
   for (int c = 0; c < nst; ++c)
-    b += (double)L.stage_nnz[c] * sizeof(T) + (compact ? stage_idx_bytes(L, c) : 4.0 * L.stage_nnz[c]) +
-         (double)L.stage_rows[c] * (4 + vec_bytes);
+    b += (compact && L.sell)
+             ? sell_mat_bytes<T>(L, L.stage_nnz[c], L.stage_rows[c], L.stage_nnz16[c]) +
+                   (double)L.stage_rows[c] * (4 + vec_bytes)
+             : (double)L.stage_nnz[c] * sizeof(T) + (compact ? stage_idx_bytes(L, c) : 4.0 * L.stage_nnz[c]) +
+                   (double)L.stage_rows[c] * (4 + vec_bytes);
   return b;
 }
 
@@ -507,14 +544,14 @@ void resid(mvamg_hier* h, int l, const DevLevel& L, const T* r, const T* x, T* s
   const int kc = MODE != 0 ? MVAMG_KC_SPMV : MVAMG_KC_RESIDUAL;
   const bool part = MODE == 0 && nst >= 0 && nst < L.ns;
   const double by = skip_bytes(h, l, part ? resid_stage_bytes<T>(L, nst, 3.0 * sizeof(T), true)
-                                          : (double)L.nnz * sizeof(T) +
-                                                (L.sell ? 4.0 * L.nnz - 2.0 * L.nnz16 : 4.0 * L.gidx) +
+                                          : (L.sell ? sell_mat_bytes<T>(L, L.nnz, L.n, L.nnz16)
+                                                    : (double)L.nnz * sizeof(T) + 4.0 * L.gidx) +
                                                 4.0 * (L.n + 1) +
                                                 (double)L.n * sizeof(T) * (MODE != 0 ? 2 : 3));
   if (L.sell) {
     const int ns = part ? L.h_sslab[nst] : L.nslabs;
     if (ns > 0)
-      klaunch(h, kc, by, k_resid_sell<T, MODE>, (ns + 3) / 4, kBlock, st, L.slabs, ns, scols(L), lval<T>(L), ldblk<T>(L), r, x,
+      klaunch(h, kc, by, k_resid_sell<T, MODE>, (ns + 3) / 4, kBlock, st, L.slabs, ns, scols(L), svals<T>(L), r, x,
               s, red, lskip(h, l, SKIP_SLAB));
   } else {
     const int ng = part ? L.h_sgrp[nst] : L.ng;
@@ -703,6 +740,7 @@ void read_scalars(mvamg_hier* h, hipStream_t st) {
 
 void fill_level_values(mvamg_hier* h, int l, const double* val_file, hipStream_t st) {
   DevLevel& L = h->lv[l];
+  L.vcoded = L.dcoded = false;  // the codes describe the values uploaded with the layout
   k_fill_values<<<grid_for(L.nent), kBlock, 0, st>>>(L.nent, L.src, val_file, L.val);
   k_fill_values<<<grid_for(L.ndblk), kBlock, 0, st>>>(L.ndblk, L.dsrc, val_file, L.dblk);
   LAUNCHCHECK("fill_values");
@@ -712,6 +750,8 @@ void derive_level(mvamg_hier* h, int l, hipStream_t st) {
   DevLevel& L = h->lv[l];
   k_to_f32<<<grid_for(L.nent), kBlock, 0, st>>>(L.nent, L.val, L.val32);
   k_to_f32<<<grid_for(L.ndblk), kBlock, 0, st>>>(L.ndblk, L.dblk, L.dblk32);
+  if (L.vcoded) k_to_f32<<<1, kBlock, 0, st>>>(L.nvtab, L.vtab, L.vtab32);
+  if (L.dcoded) k_to_f32<<<1, kBlock, 0, st>>>(L.ndtab, L.dtab, L.dtab32);
   if (L.sell) {
     k_l1norm_sell<<<(L.nslabs + 3) / 4, kBlock, 0, st>>>(L.slabs, L.nslabs, L.val, L.dblk, L.dl1);
   } else {
@@ -976,6 +1016,20 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
         L.cbase = h->upload_vec(y.cbase.empty() ? std::vector<int>(8, 0) : y.cbase, st);
         L.scb = h->upload_vec(y.scb, st);
         L.nnz16 = y.nnz16;
+        if (y.vcoded) {
+          L.vcode = h->upload_vec(y.vcode, st);
+          L.vtab = h->upload_vec(y.vtab, st);
+          L.vtab32 = h->dalloc<float>(y.vtab.size());
+          L.nvtab = (int)y.vtab.size();
+          L.vcoded = true;
+        }
+        if (y.dcoded) {
+          L.dcode = h->upload_vec(y.dcode, st);
+          L.dtab = h->upload_vec(y.dtab, st);
+          L.dtab32 = h->dalloc<float>(y.dtab.size());
+          L.ndtab = (int)y.dtab.size();
+          L.dcoded = true;
+        }
         L.stage_nnz16 = y.stage_nnz16;
         L.stage_gidx.assign(L.ns, 0);
         L.stage_later_idx.assign(L.ns, 0);
@@ -1393,8 +1447,10 @@ mvamg_status mvamg_set_fine_values(mvamg_hier* h, const double* val, void* strea
     if (!h || !val) throw Error(MVAMG_ERR_ARG, "null argument");
     check_device(h);
     hipStream_t st = (hipStream_t)stream;
-    fill_level_values(h, 0, val, st);
+    const bool coded = h->lv[0].vcoded || h->lv[0].dcoded;
+    fill_level_values(h, 0, val, st);  // drops the value codes: kernels read the values from now on
     derive_level(h, 0, st);
+    if (coded) drop_graphs(h);  // captured iterations hold the codes
     return MVAMG_OK;
   } catch (const Error& e) {
     return fail_status(e);

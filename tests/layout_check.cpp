@@ -93,6 +93,19 @@ static int check_level(const HostLevel& L, const LevelLayout& Y, const std::vect
       }
     }
     CHECK(real16 == Y.nnz16, "16-bit entry count");
+    // value dictionaries decode to the stored values bit for bit
+    if (Y.vcoded) {
+      CHECK(Y.vcode.size() == Y.val.size() && !Y.vtab.empty() && Y.vtab.size() <= 256, "entry codes");
+      for (size_t i = 0; i < Y.val.size(); ++i)
+        CHECK(Y.vcode[i] < Y.vtab.size() && std::memcmp(&Y.vtab[Y.vcode[i]], &Y.val[i], sizeof(double)) == 0,
+              "entry code decodes to the value");
+    }
+    if (Y.dcoded) {
+      CHECK(Y.dcode.size() == Y.dblk.size() && (int)Y.dblk.size() == n && Y.dtab.size() <= 256, "diagonal codes");
+      for (size_t i = 0; i < Y.dblk.size(); ++i)
+        CHECK(Y.dcode[i] < Y.dtab.size() && std::memcmp(&Y.dtab[Y.dcode[i]], &Y.dblk[i], sizeof(double)) == 0,
+              "diagonal code decodes to the value");
+    }
   } else {
     CHECK((int)Y.rowptr.size() == n + 1 && Y.rowptr[n] == (int)Y.col.size(), "grouped CSR");
     // a row's entries in increasing column order; rsplit separates the entries
@@ -201,9 +214,10 @@ int main(int argc, char** argv) {
             gall += 1;
             gsh += m > 0;
           }
-      std::printf("ok levels=%d n0=%d sell0=%d nnz16_0=%lld nnz0=%lld gshared=%lld/%lld\n", H.nl, H.lv[0].n,
-                  H.nl > 1 ? (int)Y[0].sell : -1, H.nl > 1 ? (long long)Y[0].nnz16 : 0LL,
-                  (long long)H.lv[0].rp[H.lv[0].n] - H.lv[0].n, gsh, gall);
+      std::printf("ok levels=%d n0=%d sell0=%d nnz16_0=%lld nnz0=%lld gshared=%lld/%lld coded0=%d%d\n", H.nl,
+                  H.lv[0].n, H.nl > 1 ? (int)Y[0].sell : -1, H.nl > 1 ? (long long)Y[0].nnz16 : 0LL,
+                  (long long)H.lv[0].rp[H.lv[0].n] - H.lv[0].n, gsh, gall, H.nl > 1 ? (int)Y[0].vcoded : 0,
+                  H.nl > 1 ? (int)Y[0].dcoded : 0);
     }
   } catch (const std::exception& e) {
     std::fprintf(stderr, "error: %s\n", e.what());

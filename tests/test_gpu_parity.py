@@ -133,6 +133,10 @@ def test_nearby_matrix_values(cases, torch_gpu):
     P, path, st, S0, O = cases["jump16"]
     _say("[nearby] jump16")
     S = mvamg.Solver(path)
+    # a solve with the uploaded values first: its captured iteration reads the
+    # fine level's value codes, which the refill below must retire
+    _, r0 = S.solve(_t(torch_gpu, P.b), rtol=1e-9)
+    assert r0.converged
     rng = np.random.default_rng(5)
     # a near-by s.p.d. matrix with the same pattern: D A D, D = exp(0.05 N(0, 1))
     d = np.exp(0.05 * rng.standard_normal(P.n))
@@ -152,6 +156,28 @@ def test_nearby_matrix_values(cases, torch_gpu):
     true_rel = np.linalg.norm(b - oracle.spmv(P.rowptr, P.col, v2, xg)) / np.linalg.norm(b)
     assert res.converged and true_rel <= 1.01e-9
     assert abs(res.iterations - nito) <= max(3, nito // 5)
+    S.close()
+
+
+def test_value_codes_are_exact(cases, torch_gpu):
+    """The fine level of jump16 has few distinct values, so its kernels read
+    1-byte codes into a value table.  Refilling the same values switches them
+    to the stored values: A x, one cycle and a solve must not change by a bit."""
+    P, path, st, S0, O = cases["jump16"]
+    _say("[codes] jump16")
+    S = mvamg.Solver(path)
+    b = _t(torch_gpu, np.random.default_rng(9).standard_normal(P.n))
+    outs = []
+    for refill in (False, True):
+        if refill:
+            mvamg.set_fine_values(S.h, _t(torch_gpu, P.val))
+        y = S.spmv(b).cpu().numpy()
+        z = S.cycle(b).cpu().numpy()
+        z32 = S.cycle(b, precision=32).cpu().numpy()
+        x, res = S.solve(b, rtol=1e-9)
+        outs.append((y, z, z32, x.cpu().numpy(), res.iterations))
+    for a, c in zip(outs[0], outs[1]):
+        assert np.array_equal(a, c)
     S.close()
 
 

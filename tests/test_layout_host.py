@@ -55,6 +55,9 @@ def test_layout_of_workloads(checker):
         # coarse group (and of an elasticity node) share one column list
         sh, alln = map(int, kv["gshared"].split("/"))
         assert alln > 0 and sh == alln, (name, kv["gshared"])
+        # piecewise-constant coefficients on a grid: few distinct entries,
+        # coded on the sliced-ELL fine level (a grouped fine level is not)
+        assert kv["coded0"] == ("00" if name == "elast12" else "11"), (name, kv["coded0"])
 
 
 def test_layout_of_a_batch_union(checker):
