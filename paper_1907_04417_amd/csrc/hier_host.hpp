@@ -268,6 +268,11 @@ struct LevelLayout {
   // (cbase padded to a multiple of 8 per slab); scb[s] = -1 keeps col.
   std::vector<uint16_t> col16;
   std::vector<int> cbase, scb;
+  // col16 and vcode are stored lane-packed: the slots of entries j .. j + 7
+  // (j a multiple of 8) of a slab's lane are adjacent, at pk_index(s, j, lane)
+  // (one 16-byte / 8-byte load per lane for eight entries; positions past
+  // the width up to a multiple of 8 hold delta 0 and code 0)
+  std::vector<int> pk;
   int64_t nnz16 = 0;                // stored entries (without padding) in 16-bit slabs
   // sliced ELL with few distinct values: 1-byte codes into a table of at most
   // 256 values, for the entries (vcode, same positions as val) and for the
@@ -281,6 +286,10 @@ struct LevelLayout {
   std::vector<double> dblk;
   std::vector<int> dsrc;
 };
+
+inline int64_t pk_index(const LevelLayout& Y, int s, int j, int lane) {
+  return (int64_t)Y.pk[s] + (int64_t)(j / 8) * 512 + lane * 8 + (j % 8);
+}
 
 struct TransferLayout {
   int nagg = 0, max_na = 0;
@@ -500,6 +509,27 @@ inline void build_level_layout(const HostLevel& L, LevelLayout& Y, const std::ve
     // codes and look the values up (exact: the same binary64 values)
     Y.vcoded = encode_values(Y.val, Y.vcode, Y.vtab);
     Y.dcoded = encode_values(Y.dblk, Y.dcode, Y.dtab);
+    // lane-packed copies of the 16-bit deltas and the codes
+    Y.pk.assign(Y.slabs.size(), 0);
+    int64_t tp = 0;
+    for (size_t q = 0; q < Y.slabs.size(); ++q) {
+      Y.pk[q] = (int)tp;
+      tp += (int64_t)(Y.slabs[q].width + 7) / 8 * 512;
+      if (tp > ((int64_t)1 << 31) - 1) throw Error(-1, "level too large for 32-bit packed offsets");
+    }
+    std::vector<uint16_t> c16p(tp, 0);
+    std::vector<uint8_t> vcp(Y.vcoded ? tp : 0, 0);
+    for (size_t q = 0; q < Y.slabs.size(); ++q) {
+      const Slab& sl = Y.slabs[q];
+      for (int j = 0; j < sl.width; ++j)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int64_t at = (int64_t)sl.off + (int64_t)j * 64 + lane, to = pk_index(Y, (int)q, j, lane);
+          c16p[to] = Y.col16[at];
+          if (Y.vcoded) vcp[to] = Y.vcode[at];
+        }
+    }
+    Y.col16.swap(c16p);
+    if (Y.vcoded) Y.vcode.swap(vcp);
   } else {
     Y.rowptr.assign(n + 1, 0);
     Y.rsplit.assign(n, 0);

@@ -285,22 +285,29 @@ __global__ __launch_bounds__(kBlock) void k_xpay(int n, const double* __restrict
 // Column indices of the slabs: 32-bit (col), or, where a slab's j-th entries
 // span at most 65535 columns, 16-bit deltas col16 from a per-(slab, entry
 // position) base cbase[scb[s] + j] (scb[s] = -1: 32-bit; the bases of a slab
-// are padded to a multiple of 8 with the last one).
+// are padded to a multiple of 8 with the last one).  col16 (and the value
+// codes) are lane-packed: the eight slots j0 .. j0 + 7 of a lane are adjacent
+// at pk[s] + 64 j0 + 8 lane, one 16-byte load; slots past the width point at
+// a row and their products are dropped.
 struct SellCols {
   const int* __restrict__ col;
   const uint16_t* __restrict__ col16;
   const int* __restrict__ cbase;
   const int* __restrict__ scb;
+  const int* __restrict__ pk;
 };
 
-// Columns of the entries j0 .. j0 + 7 (clamped to the slab's width) of slab
-// row `lane`; cb = scb[slab] (wave-uniform).
-__device__ __forceinline__ void sell_cols8(const SellCols& C, const Slab& sl, int cb, int lane, int j0, int cc[8]) {
+// Columns of the entries j0 .. j0 + 7 (clamped to the slab's width, or
+// packed slots past it) of slab row `lane`; cb = scb[slab], po = pk[slab]
+// (wave-uniform).
+__device__ __forceinline__ void sell_cols8(const SellCols& C, const Slab& sl, int cb, int po, int lane, int j0,
+                                           int cc[8]) {
   if (cb >= 0) {
-    const uint16_t* c16 = C.col16 + sl.off + lane;
+    const uint4 w = *reinterpret_cast<const uint4*>(C.col16 + po + 64 * j0 + 8 * lane);
     const int* b = C.cbase + cb + j0;
+    const unsigned d[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-    for (int u = 0; u < 8; ++u) cc[u] = b[u] + (int)c16[64 * min(j0 + u, sl.width - 1)];
+    for (int u = 0; u < 8; ++u) cc[u] = b[u] + (int)((d[u >> 1] >> (16 * (u & 1))) & 0xffffu);
   } else {
     const int* c = C.col + sl.off + lane;
 #pragma unroll
@@ -335,17 +342,15 @@ __device__ __forceinline__ void stage_tables(const SellVals<T>& V, T* vt, T* dt)
   __syncthreads();
 }
 
-// Values of the entries j0 .. j0 + 7 (clamped to the slab's width) of slab row `lane`.
+// Values of the entries j0 .. j0 + 7 (clamped to the slab's width, or
+// packed slots past it) of slab row `lane`; po = pk[slab].
 template <typename T>
-__device__ __forceinline__ void sell_vals8(const SellVals<T>& V, const T* vt, const Slab& sl, int lane, int j0,
-                                           T vv[8]) {
+__device__ __forceinline__ void sell_vals8(const SellVals<T>& V, const T* vt, const Slab& sl, int po, int lane,
+                                           int j0, T vv[8]) {
   if (V.vcode) {
-    const uint8_t* c = V.vcode + sl.off + lane;
-    int cc[8];
+    const uint2 w = *reinterpret_cast<const uint2*>(V.vcode + po + 64 * j0 + 8 * lane);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) cc[u] = c[64 * min(j0 + u, sl.width - 1)];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) vv[u] = vt[cc[u]];
+    for (int u = 0; u < 8; ++u) vv[u] = vt[((u < 4 ? w.x : w.y) >> (8 * (u & 3))) & 0xffu];
   } else {
     const T* v = V.val + sl.off + lane;
 #pragma unroll
@@ -371,13 +376,21 @@ __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ sla
                                                     SellCols C, SellVals<T> V, const T* __restrict__ r, T* x,
                                                     Skip sk, int lim, double* __restrict__ part) {
   __shared__ T vt[kTab], dt[kTab];
-  stage_tables(V, vt, dt);
   const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
+  // the slab's descriptors are requested before the tables' barrier, so the
+  // two round trips overlap
+  const bool act = s < s1 && !skipped(sk, s);
+  Slab sl{0, 0, 0, 0};
+  int cb = -1, po = 0;
+  if (act) {
+    sl = slabs[s];
+    cb = C.scb[s];
+    po = C.pk[s];
+  }
+  stage_tables(V, vt, dt);
   double dsum = 0.0;
-  if (s < s1 && !skipped(sk, s)) {
-    const Slab sl = slabs[s];
-    const int cb = C.scb[s];
+  if (act) {
     if (lane < sl.nrows) {
       const int p = sl.row0 + lane;
       const T rp = r[p];
@@ -386,8 +399,8 @@ __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ sla
       for (int j0 = 0; j0 < sl.width; j0 += 8) {
         int cc[8];
         T vv[8], xx[8];
-        sell_cols8(C, sl, cb, lane, j0, cc);
-        sell_vals8(V, vt, sl, lane, j0, vv);
+        sell_cols8(C, sl, cb, po, lane, j0, cc);
+        sell_vals8(V, vt, sl, po, lane, j0, vv);
 #pragma unroll
         for (int u = 0; u < 8; ++u) xx[u] = x[min(cc[u], lim - 1)];
 #pragma unroll
@@ -420,13 +433,20 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
                                                        SellCols C, SellVals<T> V, const T* __restrict__ r,
                                                        const T* __restrict__ x, T* __restrict__ s, Red red, Skip sk) {
   __shared__ T vt[kTab], dt[kTab];
-  stage_tables(V, vt, dt);
   const int sidx = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
+  // descriptors requested before the tables' barrier (see k_gs_sell)
+  const bool act = sidx < nslabs && !skipped(sk, sidx);
+  Slab sl{0, 0, 0, 0};
+  int cb = -1, po = 0;
+  if (act) {
+    sl = slabs[sidx];
+    cb = C.scb[sidx];
+    po = C.pk[sidx];
+  }
+  stage_tables(V, vt, dt);
   double dsum = 0.0;
-  if (sidx < nslabs && !skipped(sk, sidx)) {
-    const Slab sl = slabs[sidx];
-    const int cb = C.scb[sidx];
+  if (act) {
     if (lane < sl.nrows) {
       const int p = sl.row0 + lane;
       const T xp = x[p];
@@ -434,8 +454,8 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
       for (int j0 = 0; j0 < sl.width; j0 += 8) {
         int cc[8];
         T vv[8], xx[8];
-        sell_cols8(C, sl, cb, lane, j0, cc);
-        sell_vals8(V, vt, sl, lane, j0, vv);
+        sell_cols8(C, sl, cb, po, lane, j0, cc);
+        sell_vals8(V, vt, sl, po, lane, j0, vv);
 #pragma unroll
         for (int u = 0; u < 8; ++u) xx[u] = x[cc[u]];
 #pragma unroll

@@ -72,7 +72,8 @@ struct DevLevel {
   int* rowptr = nullptr;
   int* rec = nullptr;  // per group: 16-int record (first row, rows, block offset, row entry offsets)
   int* col = nullptr;
-  uint16_t* col16 = nullptr;  // sliced ELL: 16-bit column deltas (see SellCols)
+  uint16_t* col16 = nullptr;  // sliced ELL: 16-bit column deltas, lane-packed (see SellCols)
+  int* pk = nullptr;          // sliced ELL: per slab, offset of its lane-packed deltas and codes
   int* cbase = nullptr;
   int* scb = nullptr;
   int64_t nnz16 = 0;                 // stored entries in 16-bit slabs
@@ -448,7 +449,7 @@ double stage_bytes(const DevLevel& L, int c) {
   return (double)L.stage_nnz[c] * sizeof(T) + stage_idx_bytes(L, c) + (double)L.stage_rows[c] * (4 + 3 * sizeof(T));
 }
 
-SellCols scols(const DevLevel& L) { return SellCols{L.col, L.col16, L.cbase, L.scb}; }
+SellCols scols(const DevLevel& L) { return SellCols{L.col, L.col16, L.cbase, L.scb, L.pk}; }
 
 // first_sweep: forward sweep from x = 0 (entries of later stages skipped;
 // see k_gs_sell and k_gs_grp).  dot_part (binary64 sliced-ELL levels): the
@@ -1013,6 +1014,7 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
       if (y.sell) {
         L.slabs = h->upload_vec(y.slabs, st);
         L.col16 = h->upload_vec(y.col16, st);
+        L.pk = h->upload_vec(y.pk, st);
         L.cbase = h->upload_vec(y.cbase.empty() ? std::vector<int>(8, 0) : y.cbase, st);
         L.scb = h->upload_vec(y.scb, st);
         L.nnz16 = y.nnz16;

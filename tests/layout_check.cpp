@@ -71,7 +71,13 @@ static int check_level(const HostLevel& L, const LevelLayout& Y, const std::vect
       CHECK(next == Y.gstart[Y.sgrp[c + 1]], "slabs end with the stage");
     }
     // 16-bit column deltas reproduce every stored column; padding points at a row
-    CHECK(Y.scb.size() == Y.slabs.size() && Y.col16.size() == Y.col.size(), "16-bit column arrays");
+    CHECK(Y.scb.size() == Y.slabs.size() && Y.pk.size() == Y.slabs.size(), "16-bit column arrays");
+    int64_t packed = 0;
+    for (size_t q = 0; q < Y.slabs.size(); ++q) {
+      CHECK(Y.pk[q] == packed && Y.pk[q] % 512 == 0, "packed slab offsets");
+      packed += (int64_t)(Y.slabs[q].width + 7) / 8 * 512;
+    }
+    CHECK((int64_t)Y.col16.size() == packed && (!Y.vcoded || (int64_t)Y.vcode.size() == packed), "packed sizes");
     int64_t real16 = 0;
     for (size_t q = 0; q < Y.slabs.size(); ++q) {
       if (Y.scb[q] < 0) continue;
@@ -82,7 +88,7 @@ static int check_level(const HostLevel& L, const LevelLayout& Y, const std::vect
         const int r = Y.perm[sl.row0 + i], len = L.rp[r + 1] - L.rp[r] - 1;
         for (int j = 0; j < sl.width; ++j) {
           const int64_t at = (int64_t)sl.off + (int64_t)j * 64 + i;
-          const int64_t c16 = (int64_t)Y.cbase[cb + j] + Y.col16[at];
+          const int64_t c16 = (int64_t)Y.cbase[cb + j] + Y.col16[pk_index(Y, (int)q, j, i)];
           if (j < len) {
             CHECK(c16 == Y.col[at], "16-bit column equals the stored column");
             ++real16;
@@ -90,15 +96,28 @@ static int check_level(const HostLevel& L, const LevelLayout& Y, const std::vect
             CHECK(c16 >= 0 && c16 < n && Y.val[at] == 0.0, "16-bit padding points at a row, value 0");
           }
         }
+        // packed slots past the width (read by the eight-slot loads, products dropped) point at a row
+        for (int j = sl.width; j < (sl.width + 7) / 8 * 8; ++j) {
+          const int64_t c16 = (int64_t)Y.cbase[cb + j] + Y.col16[pk_index(Y, (int)q, j, i)];
+          CHECK(c16 >= 0 && c16 < n, "packed padding slot points at a row");
+        }
       }
     }
     CHECK(real16 == Y.nnz16, "16-bit entry count");
     // value dictionaries decode to the stored values bit for bit
     if (Y.vcoded) {
-      CHECK(Y.vcode.size() == Y.val.size() && !Y.vtab.empty() && Y.vtab.size() <= 256, "entry codes");
-      for (size_t i = 0; i < Y.val.size(); ++i)
-        CHECK(Y.vcode[i] < Y.vtab.size() && std::memcmp(&Y.vtab[Y.vcode[i]], &Y.val[i], sizeof(double)) == 0,
-              "entry code decodes to the value");
+      CHECK(!Y.vtab.empty() && Y.vtab.size() <= 256, "entry codes");
+      for (size_t q = 0; q < Y.slabs.size(); ++q) {
+        const Slab& sl = Y.slabs[q];
+        for (int j = 0; j < (sl.width + 7) / 8 * 8; ++j)
+          for (int i = 0; i < 64; ++i) {
+            const uint8_t c = Y.vcode[pk_index(Y, (int)q, j, i)];
+            CHECK(c < Y.vtab.size(), "code inside the table");
+            if (j < sl.width)
+              CHECK(std::memcmp(&Y.vtab[c], &Y.val[(int64_t)sl.off + (int64_t)j * 64 + i], sizeof(double)) == 0,
+                    "entry code decodes to the value");
+          }
+      }
     }
     if (Y.dcoded) {
       CHECK(Y.dcode.size() == Y.dblk.size() && (int)Y.dblk.size() == n && Y.dtab.size() <= 256, "diagonal codes");
