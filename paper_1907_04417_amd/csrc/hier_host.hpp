@@ -305,12 +305,13 @@ struct TransferLayout {
 inline bool encode_values(const std::vector<double>& v, std::vector<uint8_t>& code, std::vector<double>& tab) {
   code.clear();
   tab.clear();
+  if (v.empty()) return false;
   std::vector<uint64_t> bits(v.size());
   std::memcpy(bits.data(), v.data(), v.size() * sizeof(double));
   std::vector<uint64_t> u(bits);
   std::sort(u.begin(), u.end());
   u.erase(std::unique(u.begin(), u.end()), u.end());
-  if (u.empty() || u.size() > 256) return false;
+  if (u.size() > 256) return false;
   tab.resize(u.size());
   std::memcpy(tab.data(), u.data(), u.size() * sizeof(double));
   code.resize(v.size());

@@ -80,3 +80,15 @@ def test_invalid_colouring_is_rejected(checker, tmp_path):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
     r = subprocess.run([checker, bad], capture_output=True, text=True, env=env, timeout=300)
     assert r.returncode == 3 and "couples two of its groups" in r.stderr, r.stderr
+
+
+def test_value_dictionary(tmp_path):
+    """encode_values (value codes of sliced-ELL levels): exact decoding, the
+    256-value limit, bitwise-distinct values kept apart, empty input
+    (tests/encode_check.cpp under AddressSanitizer and UBSan)."""
+    exe = str(tmp_path / "encode_check")
+    inc = os.path.join(ROOT, "paper_1907_04417_amd", "csrc")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                    "-I", inc, os.path.join(ROOT, "tests", "encode_check.cpp"), "-o", exe], check=True)
+    out = _run(exe)
+    assert out.strip() == "ok"
