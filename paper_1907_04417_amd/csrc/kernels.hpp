@@ -258,20 +258,6 @@ __global__ __launch_bounds__(kBlock) void k_dot(int n, const double* __restrict_
   block_partials<NV>(s0, s1, red.part);
 }
 
-// x += alpha p; r -= alpha q; sum r.r
-__global__ __launch_bounds__(kBlock) void k_axpy2_dot(int n, const double* __restrict__ scal,
-                                                      const double* __restrict__ p, const double* __restrict__ q,
-                                                      double* __restrict__ x, double* __restrict__ r, Red red) {
-  const double alpha = scal[S_ALPHA];
-  double s = 0.0;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    s += ri * ri;
-  }
-  block_partials<1>(s, 0.0, red.part);
-}
 
 // p = z + beta p
 __global__ __launch_bounds__(kBlock) void k_xpay(int n, const double* __restrict__ scal, const double* __restrict__ z,
@@ -413,6 +399,28 @@ __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ sla
     }
   }
   if (DOT) block_partials<1>(dsum, 0.0, part);
+}
+
+// x += alpha p; r -= alpha q; sum r.r.  rows0 > 0: also the first stage of
+// the next cycle's forward sweep from zero on a point fine level,
+// z_p = r_p / a_pp for p < rows0 (as k_stage0_point, from the new r).
+__global__ __launch_bounds__(kBlock) void k_axpy2_dot(int n, const double* __restrict__ scal,
+                                                      const double* __restrict__ p, const double* __restrict__ q,
+                                                      double* __restrict__ x, double* __restrict__ r, Red red,
+                                                      int rows0, SellVals<double> V, double* __restrict__ z) {
+  __shared__ double vt[1], dt[kTab];
+  V.vcode = nullptr;  // entries are not read
+  if (rows0 > 0) stage_tables(V, vt, dt);
+  const double alpha = scal[S_ALPHA];
+  double s = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    s += ri * ri;
+    if (i < rows0) z[i] = ri / sell_diag(V, dt, i);
+  }
+  block_partials<1>(s, 0.0, red.part);
 }
 
 // First stage of the forward sweep from x = 0 on a point level: x_p = r_p /

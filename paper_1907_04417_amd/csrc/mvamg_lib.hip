@@ -609,12 +609,14 @@ void coarse_solve<float>(mvamg_hier* h, const float* r, float* z, hipStream_t st
 
 // x = B_l r (one V-cycle from a zero guess).  x_started: the restriction of
 // the finer level has already performed the first pre-smoothing step on x.
+// stage0_written (point level): the first stage of the sweep from zero is
+// already in x (written with r by the CG update), the other rows are not set.
 // dot_part: the backward sweep of this level also writes the block partials
 // of x.r (binary64 sliced-ELL level, Gauss-Seidel); their count goes to
 // h->dot_nparts.
 template <typename T>
 void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st, bool x_started = false,
-            double* dot_part = nullptr) {
+            double* dot_part = nullptr, bool stage0_written = false) {
   if (l == h->nl - 1) {
     coarse_solve<T>(h, r, x, st);
     return;
@@ -627,7 +629,7 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   T* xc = lx<T>(C);
   // pre-smoothing: one forward sweep from x = 0
   if (smoother == MVAMG_SMOOTH_GS) {
-    if (!x_started) zero_stage0<T>(h, l, L, r, x, st);
+    if (!x_started && !stage0_written) zero_stage0<T>(h, l, L, r, x, st);
     // from zero: a point level's forward stages skip later-stage columns when
     // its stage 0 was just written by zero_stage0, a grouped level's always
     // (its other groups are zero either way)
@@ -776,10 +778,13 @@ void check_device(const mvamg_hier* h) {
 // One CG half-step A: q = A p, alpha = rho / p.q, x += alpha p, r -= alpha q,
 // r.r -- whose finisher also writes the scalars to the mapped host buffer
 // (no copy node).
-void cg_step_a(mvamg_hier* h, hipStream_t st) {
+// stage0: the update also writes the next cycle's first sweep stage into z
+// (see cg_step_b).
+void cg_step_a(mvamg_hier* h, hipStream_t st, bool stage0) {
   const int n = h->n, eg = grid_for(n);
   spmv0_dot(h, h->p, h->q, M_PQ, st);
-  k_axpy2_dot<<<eg, kBlock, 0, st>>>(n, h->scal, h->p, h->q, h->x, h->r, mkred(h));
+  k_axpy2_dot<<<eg, kBlock, 0, st>>>(n, h->scal, h->p, h->q, h->x, h->r, mkred(h), stage0 ? h->lv[0].rows0 : 0,
+                                      svals<double>(h->lv[0]), h->z);
   LAUNCHCHECK("axpy2");
   finish(h, 1, eg, M_STORE_RR, st, h->pinned_dev);
 }
@@ -787,10 +792,16 @@ void cg_step_a(mvamg_hier* h, hipStream_t st) {
 // Half-step B: z = B r, beta (standard or flexible), p = z + beta p.  In
 // binary64 with Gauss-Seidel on a sliced-ELL fine level, the cycle's last
 // sweep writes the partials of z.r itself.
+// The binary64 Gauss-Seidel cycle on a sliced-ELL fine level: its first
+// sweep stage comes with the preceding CG update (cg_step_a).
+bool fused_cycle(const mvamg_hier* h, int precision, int smoother) {
+  return precision == 64 && smoother == MVAMG_SMOOTH_GS && h->nl > 1 && h->lv[0].sell;
+}
+
 void cg_step_b(mvamg_hier* h, int precision, int smoother, hipStream_t st) {
   const int n = h->n, eg = grid_for(n);
-  if (precision == 64 && smoother == MVAMG_SMOOTH_GS && h->nl > 1 && h->lv[0].sell) {
-    vcycle<double>(h, 0, h->r, h->z, smoother, st, false, h->part);
+  if (fused_cycle(h, precision, smoother)) {
+    vcycle<double>(h, 0, h->r, h->z, smoother, st, false, h->part, true);
     finish(h, 1, h->dot_nparts, M_RZ, st);
   } else if (precision == 32) {
     apply_B(h, h->r, h->z, precision, smoother, st);
@@ -816,7 +827,7 @@ hipGraphExec_t iteration_graph(mvamg_hier* h, int precision, int smoother) {
   HIPCHECK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
   try {
     cg_step_b(h, precision, smoother, h->cap);
-    cg_step_a(h, h->cap);
+    cg_step_a(h, h->cap, fused_cycle(h, precision, smoother));
   } catch (...) {
     (void)hipStreamEndCapture(h->cap, &g);
     if (g) (void)hipGraphDestroy(g);
@@ -879,13 +890,13 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
       bool first = true;
       while (it < prm->maxit) {
         if (first) {
-          cg_step_a(h, st);
+          cg_step_a(h, st, fused_cycle(h, prm->precision, prm->smoother));
           first = false;
         } else if (ge) {
           HIPCHECK(hipGraphLaunch(ge, st));
         } else {
           cg_step_b(h, prm->precision, prm->smoother, st);
-          cg_step_a(h, st);
+          cg_step_a(h, st, fused_cycle(h, prm->precision, prm->smoother));
         }
         HIPCHECK(hipStreamSynchronize(st));
         ++it;
