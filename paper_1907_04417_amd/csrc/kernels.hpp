@@ -259,11 +259,23 @@ __global__ __launch_bounds__(kBlock) void k_dot(int n, const double* __restrict_
 }
 
 
-// p = z + beta p
+// x += alpha p (the previous step's, deferred to here: p is read anyway),
+// then p = z + beta p
 __global__ __launch_bounds__(kBlock) void k_xpay(int n, const double* __restrict__ scal, const double* __restrict__ z,
-                                                 double* __restrict__ p) {
-  const double beta = scal[S_BETA];
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = z[i] + beta * p[i];
+                                                 double* __restrict__ p, double* __restrict__ x) {
+  const double beta = scal[S_BETA], alpha = scal[S_ALPHA];
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const double pi = p[i];
+    x[i] += alpha * pi;
+    p[i] = z[i] + beta * pi;
+  }
+}
+
+// x += alpha p: the deferred update of the last CG step
+__global__ __launch_bounds__(kBlock) void k_x_update(int n, const double* __restrict__ scal,
+                                                     const double* __restrict__ p, double* __restrict__ x) {
+  const double alpha = scal[S_ALPHA];
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) x[i] += alpha * p[i];
 }
 
 // ------------------------------------------------- sliced-ELL (point) levels
@@ -401,20 +413,19 @@ __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ sla
   if (DOT) block_partials<1>(dsum, 0.0, part);
 }
 
-// x += alpha p; r -= alpha q; sum r.r.  rows0 > 0: also the first stage of
-// the next cycle's forward sweep from zero on a point fine level,
-// z_p = r_p / a_pp for p < rows0 (as k_stage0_point, from the new r).
-__global__ __launch_bounds__(kBlock) void k_axpy2_dot(int n, const double* __restrict__ scal,
-                                                      const double* __restrict__ p, const double* __restrict__ q,
-                                                      double* __restrict__ x, double* __restrict__ r, Red red,
-                                                      int rows0, SellVals<double> V, double* __restrict__ z) {
+// r -= alpha q; sum r.r (x += alpha p follows in k_xpay or k_x_update).
+// rows0 > 0: also the first stage of the next cycle's forward sweep from
+// zero on a point fine level, z_p = r_p / a_pp for p < rows0 (as
+// k_stage0_point, from the new r).
+__global__ __launch_bounds__(kBlock) void k_axpy_dot(int n, const double* __restrict__ scal,
+                                                     const double* __restrict__ q, double* __restrict__ r, Red red,
+                                                     int rows0, SellVals<double> V, double* __restrict__ z) {
   __shared__ double vt[1], dt[kTab];
   V.vcode = nullptr;  // entries are not read
   if (rows0 > 0) stage_tables(V, vt, dt);
   const double alpha = scal[S_ALPHA];
   double s = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    x[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
     s += ri * ri;

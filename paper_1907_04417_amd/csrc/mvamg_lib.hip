@@ -775,21 +775,23 @@ void check_device(const mvamg_hier* h) {
   if (dev != h->device) throw Error(MVAMG_ERR_ARG, "handle used with a different current device");
 }
 
-// One CG half-step A: q = A p, alpha = rho / p.q, x += alpha p, r -= alpha q,
-// r.r -- whose finisher also writes the scalars to the mapped host buffer
-// (no copy node).
+// One CG half-step A: q = A p, alpha = rho / p.q, r -= alpha q, r.r --
+// whose finisher also writes the scalars to the mapped host buffer (no copy
+// node).  x += alpha p is left pending: the next half-step B applies it
+// where it reads p anyway, or pcg after its last step (k_x_update).
 // stage0: the update also writes the next cycle's first sweep stage into z
 // (see cg_step_b).
 void cg_step_a(mvamg_hier* h, hipStream_t st, bool stage0) {
   const int n = h->n, eg = grid_for(n);
   spmv0_dot(h, h->p, h->q, M_PQ, st);
-  k_axpy2_dot<<<eg, kBlock, 0, st>>>(n, h->scal, h->p, h->q, h->x, h->r, mkred(h), stage0 ? h->lv[0].rows0 : 0,
-                                      svals<double>(h->lv[0]), h->z);
-  LAUNCHCHECK("axpy2");
+  k_axpy_dot<<<eg, kBlock, 0, st>>>(n, h->scal, h->q, h->r, mkred(h), stage0 ? h->lv[0].rows0 : 0,
+                                     svals<double>(h->lv[0]), h->z);
+  LAUNCHCHECK("axpy");
   finish(h, 1, eg, M_STORE_RR, st, h->pinned_dev);
 }
 
-// Half-step B: z = B r, beta (standard or flexible), p = z + beta p.  In
+// Half-step B: z = B r, beta (standard or flexible), the pending x += alpha p,
+// p = z + beta p.  In
 // binary64 with Gauss-Seidel on a sliced-ELL fine level, the cycle's last
 // sweep writes the partials of z.r itself.
 // The binary64 Gauss-Seidel cycle on a sliced-ELL fine level: its first
@@ -812,7 +814,7 @@ void cg_step_b(mvamg_hier* h, int precision, int smoother, hipStream_t st) {
     k_dot<1><<<eg, kBlock, 0, st>>>(n, h->z, h->r, nullptr, nullptr, mkred(h));
     finish(h, 1, eg, M_RZ, st);
   }
-  k_xpay<<<grid_elem(n), kBlock, 0, st>>>(n, h->scal, h->z, h->p);
+  k_xpay<<<grid_elem(n), kBlock, 0, st>>>(n, h->scal, h->z, h->p, h->x);
   LAUNCHCHECK("xpay");
 }
 
@@ -911,6 +913,11 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
           met = true;
           break;
         }
+      }
+      // the last step's pending x += alpha p (see cg_step_a)
+      if (!first) {
+        k_x_update<<<grid_elem(n), kBlock, 0, st>>>(n, h->scal, h->p, h->x);
+        LAUNCHCHECK("x_update");
       }
       if (!flex) {
         if (met) status = MVAMG_OK;
