@@ -106,7 +106,11 @@ mvamg_status mvamg_levels(const mvamg_hier* h, int* nlevels, int* n, int64_t* nn
 /* Replaces the values of the finest matrix by val_dev (device, float64,
    nnz entries in the CSR order of the file's level 0): a near-by matrix with
    the same pattern (Section 1).  The fine-level products and smoothing use
-   the new values, coarser levels keep the stored Galerkin matrices. */
+   the new values, coarser levels keep the stored Galerkin matrices.  The
+   1-byte value codes a sliced-ELL fine level may use describe the uploaded
+   values only: from this call on the kernels read the stored values, and the
+   captured iteration graphs are rebuilt on the next solve.  Ordered on
+   `stream` like the solves; errors: MVAMG_ERR_ARG, MVAMG_ERR_HIP. */
 mvamg_status mvamg_set_fine_values(mvamg_hier* h, const double* val_dev, void* stream);
 
 /* ---------------------------------------------------------------- solve */
