@@ -44,3 +44,36 @@ def test_wide_kernels_are_classed():
 def test_binary32_kernels_are_not_classed():
     assert kernel_class("void mvamg::k_gs_grp<float, 4, 1>(int)") is None
     assert kernel_class("void mvamg::k_gs_sell<double, false>(int)") == "smooth_fine"
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: --gpus above 1 exits with a message before
+    any GPU work."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode == 2 and "one GPU only" in r.stderr
+    assert r.stdout == ""
+
+
+def test_recorded_traffic_matches_source_and_workload(tmp_path, monkeypatch):
+    """bench.py takes a traffic line only for its kernel class, its workload and
+    the current kernel-source hash (lines of other sources are stale)."""
+    import bench
+    src = bench.kernel_source_hash()
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic.md").write_text(
+        "```\n"
+        f"traffic: smooth_coarse jump128 bytes_per_launch=1.5e+07 source={src}  (fetch ...)\n"
+        "traffic: smooth_coarse jump128 bytes_per_launch=9.9e+07 source=000000000000  (older source)\n"
+        f"traffic: spmv elast48 bytes_per_launch=3.0e+08 source={src}\n"
+        "```\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: src)
+    assert bench.recorded_traffic("smooth_coarse", "jump128") == 1.5e7
+    assert bench.recorded_traffic("spmv", "elast48") == 3.0e8
+    assert bench.recorded_traffic("spmv", "jump128") is None
+    assert bench.recorded_traffic("residual", "elast48") is None
