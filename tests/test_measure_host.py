@@ -77,3 +77,19 @@ def test_recorded_traffic_matches_source_and_workload(tmp_path, monkeypatch):
     assert bench.recorded_traffic("spmv", "elast48") == 3.0e8
     assert bench.recorded_traffic("spmv", "jump128") is None
     assert bench.recorded_traffic("residual", "elast48") is None
+
+
+def test_block_path_dispatch_classes():
+    """The block (several right-hand sides) kernels: a point fine level's
+    stages are fine smoothing, the grouped coarse stages coarse smoothing, the
+    block SpMV resets to the fine level."""
+    seq = ["void mvamg::k_bstage0_point<double>(int)", "void mvamg::k_bgs_sell<double>(int)",
+           "void mvamg::k_bresid_sell<double, 0>(int)", "void mvamg::k_brestrict<double, 4>(int)",
+           "void mvamg::k_bgs_grp<double, 4>(int)", "void mvamg::k_bresid_grp<double, 4, 0>(int)",
+           "void mvamg::k_brestrict<double, 4>(int)", "void mvamg::k_bgemm_mfma<0>(int)",
+           "void mvamg::k_bprolong_rows<double, 4>(int)", "void mvamg::k_bgs_grp<double, 4>(int)",
+           "void mvamg::k_bprolong_rows<double, 4>(int)", "void mvamg::k_bgs_sell<double>(int)",
+           "void mvamg::k_bresid_sell<double, 1>(int)"]
+    cls = [classify_dispatches(dict(enumerate(seq)))[d] for d in range(len(seq))]
+    assert cls == ["smooth_fine", "smooth_fine", "residual", "restrict", "smooth_coarse", "residual", "restrict",
+                   "coarse_solve", "prolong", "smooth_coarse", "prolong", "smooth_fine", "spmv"]
