@@ -66,12 +66,13 @@ def _load():
         L.orc_vcycle32.argtypes = [ctypes.c_void_p, _F, _F, _F]
         L.orc_coarse_solve.argtypes = [ctypes.c_void_p, _D, _D]
         L.orc_smooth.argtypes = [ctypes.c_void_p, ctypes.c_int, _D, _D, ctypes.c_int]
+        L.orc_smooth32.argtypes = [ctypes.c_void_p, ctypes.c_int, _F, _F, ctypes.c_int]
         L.orc_spmv.argtypes = [ctypes.c_int, _I, _I, _D, _D, _D]
         L.orc_pcg.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _I, _I, _D, _D, _D,
                               ctypes.c_double, ctypes.c_int, _D, _I]
         L.orc_pcg.restype = ctypes.c_int
         L.orc_pcg_mixed.argtypes = [ctypes.c_void_p, ctypes.c_int, _I, _I, _D, _D, _D, ctypes.c_double,
-                                    ctypes.c_int, ctypes.c_int, _D, _I, _D]
+                                    ctypes.c_int, ctypes.c_int, _D, _I, _D, _I]
         L.orc_pcg_mixed.restype = ctypes.c_int
         L.orc_grad_coeffs.argtypes = [ctypes.c_int, _I, _I, _D, _D, _D]
         _lib = L
@@ -154,6 +155,13 @@ class Oracle:
         _load().orc_smooth(self._h, level, _p(r, _D), _p(x, _D), 1 if forward else 0)
         return x
 
+    def smooth32(self, level: int, r, x, forward: bool = True) -> np.ndarray:
+        """One sweep in binary32 on the level's binary32 values."""
+        r = np.ascontiguousarray(r, dtype=np.float32)
+        x = np.ascontiguousarray(x, dtype=np.float32).copy()
+        _load().orc_smooth32(self._h, level, _p(r, _F), _p(x, _F), 1 if forward else 0)
+        return x
+
     def matrix_dense(self, level: int = 0) -> np.ndarray:
         L = self.h.levels[level]
         M = np.zeros((L.n, L.n))
@@ -172,17 +180,20 @@ class Oracle:
                              _p(v, _D), _p(b, _D), _p(x, _D), tol, maxit, _p(hist, _D), ctypes.byref(nit))
         return x, hist[:nit.value + 1].copy(), nit.value, st
 
-    def pcg_mixed(self, b, x0=None, tol=1e-8, maxit=1000, max_restarts=3):
-        """Returns (x, hist, nit, status, true_rel)."""
+    def pcg_mixed(self, b, x0=None, tol=1e-8, maxit=1000, max_restarts=3, with_restarts=False):
+        """Returns (x, hist, nit, status, true_rel), and the restart count as a
+        sixth value when with_restarts is set."""
         b = _f64(b)
         x = np.zeros(self.n) if x0 is None else _f64(x0).copy()
         hist = np.zeros(maxit + 1)
         nit = ctypes.c_int(0)
         tr = ctypes.c_double(0.0)
+        rs = ctypes.c_int(0)
         st = _load().orc_pcg_mixed(self._h, self.n, _p(self.rowptr, _I), _p(self.col, _I), _p(self.val, _D),
                                    _p(b, _D), _p(x, _D), tol, maxit, max_restarts, _p(hist, _D),
-                                   ctypes.byref(nit), ctypes.byref(tr))
-        return x, hist[:nit.value + 1].copy(), nit.value, st, tr.value
+                                   ctypes.byref(nit), ctypes.byref(tr), ctypes.byref(rs))
+        out = (x, hist[:nit.value + 1].copy(), nit.value, st, tr.value)
+        return out + (rs.value,) if with_restarts else out
 
 
 def spmv(rowptr, col, val, x) -> np.ndarray:

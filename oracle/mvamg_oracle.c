@@ -384,6 +384,14 @@ void orc_smooth(const orc_hier* H, int l, const double* r, double* x, int forwar
     gs_sweep(H, l, H->lv[l].val, r, x, forward);
 }
 
+/* The same sweep in binary32 on the level's binary32 values, for tests. */
+void orc_smooth32(const orc_hier* H, int l, const float* r, float* x, int forward) {
+  if (H->smoother == ORC_L1_JACOBI)
+    l1_jacobi32(&H->lv[l], H->val32[l], r, x);
+  else
+    gs_sweep32(H, l, H->val32[l], r, x, forward);
+}
+
 void orc_spmv(int n, const int* rp, const int* ci, const double* v, const double* x, double* y) {
   csr_mv(n, rp, ci, v, x, y);
 }
@@ -461,11 +469,12 @@ done:
  * meets tol, the true residual b - A x is recomputed in binary64; if it does
  * not meet tol the iteration restarts from x (at most max_restarts times).
  * hist receives the recursive residual history (restarts continue it);
- * *nit counts all iterations.  tol is relative to the initial ||b - A x0||.
+ * *nit counts all iterations, *restarts the restarts taken.  tol is relative
+ * to the initial ||b - A x0||.
  */
 int orc_pcg_mixed(const orc_hier* H, int n, const int* rp, const int* ci, const double* v,
                   const double* b, double* x, double tol, int maxit, int max_restarts, double* hist,
-                  int* nit, double* true_rel) {
+                  int* nit, double* true_rel, int* restarts) {
   double* r = (double*)malloc(sizeof(double) * (size_t)n);
   double* z = (double*)malloc(sizeof(double) * (size_t)n);
   double* p = (double*)malloc(sizeof(double) * (size_t)n);
@@ -475,6 +484,7 @@ int orc_pcg_mixed(const orc_hier* H, int n, const int* rp, const int* ci, const 
   float* v32 = (float*)malloc(sizeof(float) * (size_t)(rp[n] > 0 ? rp[n] : 1));
   for (int k = 0; k < rp[n]; ++k) v32[k] = (float)v[k];
   int status = 1, it = 0;
+  *restarts = 0;
   csr_mv(n, rp, ci, v, x, q);
   for (int i = 0; i < n; ++i) r[i] = b[i] - q[i];
   const double r0 = sqrt(dotp(r, r, n));
@@ -486,6 +496,7 @@ int orc_pcg_mixed(const orc_hier* H, int n, const int* rp, const int* ci, const 
   }
   for (int restart = 0; restart <= max_restarts && it < maxit; ++restart) {
     if (restart > 0) {
+      *restarts = restart;
       csr_mv(n, rp, ci, v, x, q);
       for (int i = 0; i < n; ++i) r[i] = b[i] - q[i];
     }

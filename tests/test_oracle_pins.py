@@ -282,3 +282,122 @@ def test_hierarchy_file_rejects_corruption(tiny_hier, tmp_path):
     bad.write_bytes(buf[: len(buf) // 2])
     with pytest.raises(ValueError):
         read_hierarchy(str(bad))
+
+
+# ------------------------------------------------------------ l1-Jacobi
+
+@pytest.mark.parametrize("fx", ["tiny_hier", "small3d_hier"])
+def test_l1_sweep_closed_form(fx, request):
+    """One l1-Jacobi sweep equals x + D_l1^{-1}(r - A x) with
+    D_l1 = diag(sum_j |a_ij|), the full l1 row norm, built densely; in
+    binary64, and in binary32 to the binary32 rounding of the same map."""
+    P, path, _ = request.getfixturevalue(fx)
+    O = oracle.Oracle(path, smoother=oracle.L1_JACOBI)
+    H = O.h
+    for l in range(H.nlevels - 1):
+        L = H.levels[l]
+        A = dr.dense(L.rowptr, L.col, L.val)
+        M = dr.l1_splitting(A)
+        rng = np.random.default_rng(40 + l)
+        r, x = rng.standard_normal(L.n), rng.standard_normal(L.n)
+        want = x + np.linalg.solve(M, r - A @ x)
+        for fwd in (True, False):  # l1-Jacobi has no direction
+            np.testing.assert_allclose(O.smooth(l, r, x, forward=fwd), want, rtol=1e-12, atol=1e-12)
+        r32, x32 = r.astype(np.float32), x.astype(np.float32)
+        A32 = dr.dense(L.rowptr, L.col, L.val.astype(np.float32).astype(np.float64))
+        want32 = x32 + np.linalg.solve(dr.l1_splitting(A32), r32 - A32 @ x32)
+        got32 = O.smooth32(l, r32, x32).astype(np.float64)
+        assert np.abs(got32 - want32).max() <= 1e-5 * np.abs(want32).max()
+
+
+@pytest.mark.parametrize("fx", ["tiny_hier", "small3d_hier"])
+def test_l1_vcycle_equals_closed_form(fx, request):
+    """The l1-Jacobi V-cycle equals the recursive error-propagator form with
+    M_l = D_l1 on every level (pre and post alike, so B is symmetric); it is
+    s.p.d. with the spectrum of E = I - BA in [0, 1), and the binary32 cycle
+    stays within binary32 rounding of it."""
+    P, path, _ = request.getfixturevalue(fx)
+    O = oracle.Oracle(path, smoother=oracle.L1_JACOBI)
+    B = _oracle_B(O)
+    Bc = dr.vcycle_matrix(O.h, smoother="l1")
+    assert np.abs(B - Bc).max() <= 1e-10 * np.abs(Bc).max()
+    assert np.abs(B - B.T).max() <= 1e-12 * np.abs(B).max()
+    A = O.matrix_dense(0)
+    Lc = np.linalg.cholesky(A)
+    S = np.eye(O.n) - Lc.T @ B @ Lc
+    ev = np.linalg.eigvalsh(0.5 * (S + S.T))
+    assert ev.min() >= -1e-10 and ev.max() < 1.0
+    r = np.random.default_rng(41).standard_normal(O.n)
+    z32 = O.vcycle32(r.astype(np.float32)).astype(np.float64)
+    zc = Bc @ r.astype(np.float32).astype(np.float64)
+    assert np.abs(z32 - zc).max() <= 1e-5 * np.abs(zc).max()
+
+
+# --------------------------------------------- binary32 cycle under CG
+
+def _directions_conjugacy(A, xs):
+    """|d_{k+1}^T A d_k| / (||d_{k+1}||_A ||d_k||_A) for d_k = x_{k+1} - x_k."""
+    d = [xs[k + 1] - xs[k] for k in range(len(xs) - 1)]
+    an = lambda v: np.sqrt(v @ A @ v)
+    return np.array([abs(d[k + 1] @ A @ d[k]) / (an(d[k + 1]) * an(d[k])) for k in range(len(d) - 1)])
+
+
+def test_mixed_pcg_is_flexible_cg(small3d_hier):
+    """The binary64 CG around the binary32 cycle is flexible CG (Notay 2000).
+
+    1. Step by step against a NumPy flexible CG written from Notay's
+       definition, beta = z_{k+1}^T (r_{k+1} - r_k) / rho_k, calling the same
+       binary32 cycle: the first four residuals agree to 1e-12.  (After that a
+       one-unit difference in r flips the binary32 rounding of some entries at
+       the cycle's entry and the two runs separate by ~10x per iteration; the
+       Fletcher-Reeves rule already differs by ~1e-9 at the second step.)
+    2. A property that holds for the flexible rule only: consecutive search
+       directions, recovered from the iterates as x_{k+1} - x_k, are
+       A-conjugate (Notay's beta makes p_{k+1}^T A p_k = 0 whatever the cycle
+       returns); with the standard rule the binary32 cycle's asymmetry leaves
+       ~1e-8.  Checked on the first pairs, before the differences of iterates
+       lose digits to cancellation."""
+    P, path, _ = small3d_hier
+    O = oracle.Oracle(path)
+    A = O.matrix_dense(0)
+    mv = lambda x: dr.seq_csr_mv(O.rowptr, O.col, O.val, x)
+    prec = lambda r: O.vcycle32(r.astype(np.float32)).astype(np.float64)
+    xo, ho, nito, sto, tro = O.pcg_mixed(P.b, tol=1e-10, maxit=100)
+    xn, hn, nitn, stn, trn, rsn, _ = dr.flexible_pcg(mv, prec, P.b, 1e-10, 100, 3)
+    assert sto == stn == 0 and abs(nito - nitn) <= 1
+    np.testing.assert_allclose(ho[:5], hn[:5], rtol=1e-12)
+    _, hf, *_ = dr.flexible_pcg(mv, prec, P.b, 1e-10, 4, 0, beta_rule="fletcher_reeves")
+    assert (np.abs(hf[:5] - hn[:5]) / hn[:5]).max() > 1e-9  # the pin tells the rules apart
+    xs = [np.zeros(O.n)] + [O.pcg_mixed(P.b, tol=0.0, maxit=k, max_restarts=0)[0] for k in range(1, 6)]
+    assert _directions_conjugacy(A, xs)[:3].max() <= 1e-12
+    xf = [np.zeros(O.n)] + [dr.flexible_pcg(mv, prec, P.b, 0.0, k, 0, "fletcher_reeves")[0] for k in range(1, 6)]
+    assert _directions_conjugacy(A, xf)[:3].max() > 1e-10
+    np.testing.assert_allclose(xo, np.linalg.solve(A, P.b), rtol=1e-8, atol=1e-9)
+
+
+def test_mixed_pcg_restarts(small3d_hier):
+    """True-residual restarts.  With tol = 1e-17, below what binary64 can
+    reach on the true residual (~1e-16 here), the recursive residual still
+    meets tol; the recomputed b - A x then misses it, so every allowed restart
+    is taken and the call ends not converged, with x at the binary64 floor.
+    The restart count, the status and the history before the first restart
+    match the NumPy flexible CG; max_restarts bounds the
+    count.  (Where a segment ends is decided by residuals within rounding of
+    tol, so the restart points themselves may differ by an iteration.)"""
+    P, path, _ = small3d_hier
+    O = oracle.Oracle(path)
+    A = O.matrix_dense(0)
+    mv = lambda x: dr.seq_csr_mv(O.rowptr, O.col, O.val, x)
+    prec = lambda r: O.vcycle32(r.astype(np.float32)).astype(np.float64)
+    xs = np.linalg.solve(A, P.b)
+    for mr in (3, 1):
+        xo, ho, nito, sto, tro, rso = O.pcg_mixed(P.b, tol=1e-17, maxit=200, max_restarts=mr, with_restarts=True)
+        xn, hn, nitn, stn, trn, rsn, rits = dr.flexible_pcg(mv, prec, P.b, 1e-17, 200, mr)
+        assert rso == rsn == mr and sto == stn == 1
+        assert abs(nito - nitn) <= 1 + mr
+        # a segment stops at the first recursive residual that meets tol, so
+        # the history holds exactly one such value per segment, the last last
+        assert np.sum(ho <= 1e-17) == mr + 1 and ho[-1] <= 1e-17 and len(rits) == mr
+        np.testing.assert_allclose(ho[:5], hn[:5], rtol=1e-12)
+        assert 0.0 < tro <= 1e-14
+        np.testing.assert_allclose(xo, xs, rtol=0, atol=1e-12 * np.abs(xs).max())
