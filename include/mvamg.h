@@ -126,8 +126,10 @@ mvamg_status mvamg_cycle_apply(mvamg_hier* h, const double* r_dev, double* z_dev
 
 /* Preconditioned CG (Section 5) on A x = b with B = one V-cycle.  x_dev holds
    x_0 on entry (zero for the paper's setting) and the solution on exit.
-   Returns MVAMG_OK, MVAMG_NOT_CONVERGED, or an error.  One 8-byte
-   device-to-host copy per iteration carries ||r_k|| for the stopping test. */
+   Returns MVAMG_OK, MVAMG_NOT_CONVERGED, or an error.  Each iteration's
+   scalars (||r_k||^2 for the stopping test, the breakdown flag) are written
+   by the last kernel of the iteration straight into mapped host memory that
+   the handle owns; the host reads them after synchronising the stream. */
 mvamg_status mvamg_pcg_solve(mvamg_hier* h, const double* b_dev, double* x_dev,
                              const mvamg_solve_params* prm, mvamg_info* info, void* stream);
 

@@ -4,8 +4,10 @@ is no CPU fallback: if the library is missing or no GPU is present, the calls
 raise.
 
 Function names mirror the C entry points (``mvamg_`` prefix dropped).  Device
-vectors are passed as torch CUDA tensors (float64, contiguous) or raw device
-addresses; streams default to torch's current stream.
+vectors are passed as torch CUDA tensors (float64, contiguous, on the handle's
+device); their type, length and device are checked here before any call,
+since the C ABI receives bare pointers.  Streams default to torch's current
+stream.
 """
 from __future__ import annotations
 
@@ -109,13 +111,56 @@ def _check(st, allow=(OK,)):
     return st
 
 
-def _dev(t) -> int:
-    """Device address of a torch CUDA tensor (float64/int, contiguous) or an int."""
-    if isinstance(t, int):
-        return t
+# Handles uploaded through this module: level-0 rows (all problems of a
+# batch), stored level-0 entries, problem count and the device they live on.
+# The C side cannot see the length or type of what a pointer points to, so
+# every device vector is checked here against these before any call.
+_HANDLES: dict = {}
+
+
+def _register(h: int) -> None:
+    import torch
+    lv = levels(h)
+    k, _ = batch_problems(h)
+    _HANDLES[h] = dict(n=lv["n"][0], nnz=lv["nnz"][0], nprob=k, device=torch.cuda.current_device())
+
+
+def _hinfo(h: int) -> dict:
+    try:
+        return _HANDLES[h]
+    except KeyError:
+        raise ValueError("unknown or freed handle (upload it through this module)") from None
+
+
+def _vec(h: int, t, numel: int, what: str, dtype: str = "float64") -> int:
+    """Device address of t after checking that it is a contiguous torch tensor
+    of `dtype` with `numel` elements on the handle's device."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch device tensor, got {type(t).__name__}")
     if not t.is_cuda or not t.is_contiguous():
-        raise ValueError("expected a contiguous device tensor")
+        raise ValueError(f"{what}: expected a contiguous device tensor")
+    if t.dtype != getattr(torch, dtype):
+        raise ValueError(f"{what}: expected {dtype}, got {t.dtype}")
+    if t.numel() != numel:
+        raise ValueError(f"{what}: expected {numel} elements, got {t.numel()}")
+    dev = _hinfo(h)["device"]
+    if t.device.index != dev:
+        raise ValueError(f"{what}: tensor on cuda:{t.device.index}, handle on cuda:{dev}")
     return t.data_ptr()
+
+
+def _history(history, rows: int, maxit: int):
+    """Host history buffer: float64, C-contiguous, at least rows x (maxit + 1)."""
+    if history is None:
+        return None
+    if not isinstance(history, np.ndarray) or history.dtype != np.float64 or not history.flags.c_contiguous:
+        raise ValueError("history: expected a C-contiguous float64 numpy array")
+    if history.size < rows * (maxit + 1):
+        raise ValueError(f"history: needs {rows * (maxit + 1)} values, has {history.size}")
+    if rows > 1 and (history.ndim != 2 or history.shape[1] != maxit + 1):
+        raise ValueError(f"history: expected shape ({rows}, {maxit + 1})")
+    return history.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
 def _stream(stream) -> int | None:
@@ -146,10 +191,12 @@ def hier_host_info(hh: int):
 def upload(hh: int, stream=None) -> int:
     h = ctypes.c_void_p()
     _check(load().mvamg_upload(hh, _stream(stream), ctypes.byref(h)))
+    _register(h.value)
     return h.value
 
 
 def free(h: int) -> None:
+    _HANDLES.pop(h, None)
     load().mvamg_free(h)
 
 
@@ -164,42 +211,50 @@ def levels(h: int):
 
 
 def set_fine_values(h: int, val, stream=None) -> None:
-    _check(load().mvamg_set_fine_values(h, _dev(val), _stream(stream)))
+    _check(load().mvamg_set_fine_values(h, _vec(h, val, _hinfo(h)["nnz"], "val"), _stream(stream)))
 
 
 def spmv(h: int, x, y, stream=None) -> None:
-    _check(load().mvamg_spmv(h, _dev(x), _dev(y), _stream(stream)))
+    n = _hinfo(h)["n"]
+    _check(load().mvamg_spmv(h, _vec(h, x, n, "x"), _vec(h, y, n, "y"), _stream(stream)))
 
 
 def cycle_apply(h: int, r, z, precision: int = 64, smoother: int = SMOOTH_GS, stream=None) -> None:
-    _check(load().mvamg_cycle_apply(h, _dev(r), _dev(z), precision, smoother, _stream(stream)))
+    n = _hinfo(h)["n"]
+    _check(load().mvamg_cycle_apply(h, _vec(h, r, n, "r"), _vec(h, z, n, "z"), precision, smoother,
+                                    _stream(stream)))
 
 
-def _params(rtol, maxit, precision, smoother, max_restarts, history):
-    hp = history.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if history is not None else None
-    return SolveParams(precision, smoother, rtol, maxit, max_restarts, hp)
+def _params(rtol, maxit, precision, smoother, max_restarts, history, rows=1):
+    if not isinstance(maxit, int) or maxit < 0:
+        raise ValueError("maxit must be a non-negative int")
+    return SolveParams(precision, smoother, rtol, maxit, max_restarts, _history(history, rows, maxit))
 
 
 def pcg_solve(h: int, b, x, rtol=1e-8, maxit=1000, precision=64, smoother=SMOOTH_GS, max_restarts=3,
               history: np.ndarray | None = None, stream=None) -> Info:
     info = Info()
+    n = _hinfo(h)["n"]
     prm = _params(rtol, maxit, precision, smoother, max_restarts, history)
-    _check(load().mvamg_pcg_solve(h, _dev(b), _dev(x), ctypes.byref(prm), ctypes.byref(info), _stream(stream)),
-           allow=(OK, NOT_CONVERGED))
+    _check(load().mvamg_pcg_solve(h, _vec(h, b, n, "b"), _vec(h, x, n, "x"), ctypes.byref(prm), ctypes.byref(info),
+                                  _stream(stream)), allow=(OK, NOT_CONVERGED))
     return info
 
 
 def adjoint_solve(h: int, dLdx, lam, rtol=1e-8, maxit=1000, precision=64, smoother=SMOOTH_GS, max_restarts=3,
                   history: np.ndarray | None = None, stream=None) -> Info:
     info = Info()
+    n = _hinfo(h)["n"]
     prm = _params(rtol, maxit, precision, smoother, max_restarts, history)
-    _check(load().mvamg_adjoint_solve(h, _dev(dLdx), _dev(lam), ctypes.byref(prm), ctypes.byref(info),
-                                      _stream(stream)), allow=(OK, NOT_CONVERGED))
+    _check(load().mvamg_adjoint_solve(h, _vec(h, dLdx, n, "dLdx"), _vec(h, lam, n, "lambda"), ctypes.byref(prm),
+                                      ctypes.byref(info), _stream(stream)), allow=(OK, NOT_CONVERGED))
     return info
 
 
 def grad_coeffs(h: int, lam, x, dval, stream=None) -> None:
-    _check(load().mvamg_grad_coeffs(h, _dev(lam), _dev(x), _dev(dval), _stream(stream)))
+    hi = _hinfo(h)
+    _check(load().mvamg_grad_coeffs(h, _vec(h, lam, hi["n"], "lambda"), _vec(h, x, hi["n"], "x"),
+                                    _vec(h, dval, hi["nnz"], "dval"), _stream(stream)))
 
 
 def _block_width(X) -> int:
@@ -209,13 +264,22 @@ def _block_width(X) -> int:
     return m
 
 
+def _block(h: int, X, m: int, what: str) -> int:
+    """An n x m row-major block (n x 1 may be a vector)."""
+    if X.dim() not in (1, 2) or (X.dim() == 2 and X.shape[1] != m) or (X.dim() == 1 and m != 1):
+        raise ValueError(f"{what}: expected shape (n, {m})")
+    return _vec(h, X, _hinfo(h)["n"] * m, what)
+
+
 def spmv_block(h: int, X, Y, stream=None) -> None:
     """Y = A X for an n x m row-major block (m <= 32)."""
-    _check(load().mvamg_spmv_block(h, _dev(X), _dev(Y), _block_width(X), _stream(stream)))
+    m = _block_width(X)
+    _check(load().mvamg_spmv_block(h, _block(h, X, m, "X"), _block(h, Y, m, "Y"), m, _stream(stream)))
 
 
 def cycle_apply_block(h: int, R, Z, precision: int = 64, smoother: int = SMOOTH_GS, stream=None) -> None:
-    _check(load().mvamg_cycle_apply_block(h, _dev(R), _dev(Z), _block_width(R), precision, smoother,
+    m = _block_width(R)
+    _check(load().mvamg_cycle_apply_block(h, _block(h, R, m, "R"), _block(h, Z, m, "Z"), m, precision, smoother,
                                           _stream(stream)))
 
 
@@ -225,9 +289,9 @@ def pcg_solve_block(h: int, B, X, rtol=1e-8, maxit=1000, precision=64, smoother=
     history: m x (maxit + 1) array or None.  Returns one Info per column."""
     m = _block_width(B)
     infos = (Info * m)()
-    prm = _params(rtol, maxit, precision, smoother, max_restarts, history)
-    _check(load().mvamg_pcg_solve_block(h, _dev(B), _dev(X), m, ctypes.byref(prm), infos, _stream(stream)),
-           allow=(OK, NOT_CONVERGED))
+    prm = _params(rtol, maxit, precision, smoother, max_restarts, history, rows=m)
+    _check(load().mvamg_pcg_solve_block(h, _block(h, B, m, "B"), _block(h, X, m, "X"), m, ctypes.byref(prm), infos,
+                                        _stream(stream)), allow=(OK, NOT_CONVERGED))
     return list(infos)
 
 
@@ -236,6 +300,7 @@ def batch_upload(hhs, stream=None) -> int:
     arr = (ctypes.c_void_p * len(hhs))(*hhs)
     h = ctypes.c_void_p()
     _check(load().mvamg_batch_upload(arr, len(hhs), _stream(stream), ctypes.byref(h)))
+    _register(h.value)
     return h.value
 
 
@@ -253,10 +318,11 @@ def batch_pcg_solve(h: int, b, x, rtol=1e-8, maxit=1000, precision=64, smoother=
     """CG on every problem of a batch (b, x: the problems' vectors one after
     another).  history: nprob x (maxit + 1) array or None.  One Info per problem."""
     k, _ = batch_problems(h)
+    n = _hinfo(h)["n"]
     infos = (Info * k)()
-    prm = _params(rtol, maxit, precision, smoother, max_restarts, history)
-    _check(load().mvamg_batch_pcg_solve(h, _dev(b), _dev(x), ctypes.byref(prm), infos, _stream(stream)),
-           allow=(OK, NOT_CONVERGED))
+    prm = _params(rtol, maxit, precision, smoother, max_restarts, history, rows=max(k, 1))
+    _check(load().mvamg_batch_pcg_solve(h, _vec(h, b, n, "b"), _vec(h, x, n, "x"), ctypes.byref(prm), infos,
+                                        _stream(stream)), allow=(OK, NOT_CONVERGED))
     return list(infos)
 
 

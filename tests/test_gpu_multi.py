@@ -4,7 +4,8 @@ Block right-hand sides: the method applied to each column is the
 single-system method, so column c of every block result is compared with the
 oracle's single-system result for that column (same tolerances as the
 single-system parity tests: products 1e-13, binary64 cycle 1e-11, CG history
-1e-10, solution 1e-9 relative; binary32 cycle 1e-4 relative).
+1e-10, solution 1e-9 relative; binary32 cycle element by element within
+8 x the oracle's own binary32-versus-binary64 distance).
 
 Batch of problems: the block-diagonal hierarchy's cycle is each problem's own
 cycle, and every problem runs its own CG, so problem p is compared with the
@@ -17,6 +18,7 @@ import pytest
 
 import oracle
 from paper_1907_04417_amd import mvamg, problems, workloads
+from tests.parity_util import fp32_cycle_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -100,8 +102,8 @@ def test_cycle_block_fp32(name, blk, torch_gpu):
     mvamg.cycle_apply_block(S.h, _t(torch_gpu, R), Z, precision=32)
     Z = Z.cpu().numpy()
     for c in range(0, 32, 3):
-        z32 = O.vcycle32(R[:, c].astype(np.float32)).astype(np.float64)
-        assert np.linalg.norm(Z[:, c] - z32) <= 1e-4 * np.linalg.norm(z32), c
+        z32, z64, bound = fp32_cycle_bound(O, R[:, c])
+        assert _relinf(Z[:, c], z32) <= bound and _relinf(Z[:, c], z64) <= bound, c
 
 
 @pytest.mark.parametrize("m", [32, 5])

@@ -3,7 +3,11 @@ same hierarchy file and the same seeded inputs.
 
 Tolerances: binary64 cycle and CG history 1e-10 relative, solution 1e-9
 relative (rounding-order differences only: parallel reductions, FMA
-contraction); binary32 cycle 1e-4 relative to the oracle's binary32 cycle.
+contraction).  Binary32 cycle, element by element: within 8 delta of the
+oracle's binary32 cycle and of its binary64 cycle (relative to the largest
+entry), where delta is the oracle's own binary32-versus-binary64 distance on
+the same input.  The GPU and the oracle round the same binary32 operations in
+different orders, so each is about delta away from the binary64 result.
 """
 import sys
 
@@ -12,6 +16,7 @@ import pytest
 
 import oracle
 from paper_1907_04417_amd import mvamg, workloads
+from tests.parity_util import fp32_cycle_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -70,16 +75,17 @@ def test_cycle_parity(name, smoother, cases, torch_gpu):
     assert _relinf(z, Oc.vcycle(r)) <= 1e-11
 
 
+@pytest.mark.parametrize("smoother", [mvamg.SMOOTH_GS, mvamg.SMOOTH_L1JACOBI])
 @pytest.mark.parametrize("name", WORKLOADS)
-def test_cycle_fp32_parity(name, cases, torch_gpu):
+def test_cycle_fp32_parity(name, smoother, cases, torch_gpu):
     P, path, st, S, O = cases[name]
-    _say(f"[cycle32] {name}")
+    Oc = O if smoother == mvamg.SMOOTH_GS else oracle.Oracle(path, smoother=oracle.L1_JACOBI)
     r = np.random.default_rng(3).standard_normal(P.n)
-    z = S.cycle(_t(torch_gpu, r), precision=32).cpu().numpy()
-    z32 = O.vcycle32(r.astype(np.float32)).astype(np.float64)
-    z64 = O.vcycle(r)
-    assert np.linalg.norm(z - z32) <= 1e-4 * np.linalg.norm(z32)
-    assert np.linalg.norm(z - z64) <= 1e-4 * np.linalg.norm(z64)
+    z = S.cycle(_t(torch_gpu, r), precision=32, smoother=smoother).cpu().numpy()
+    z32, z64, bound = fp32_cycle_bound(Oc, r)
+    e32, e64 = _relinf(z, z32), _relinf(z, z64)
+    _say(f"[cycle32] {name} smoother={smoother}: vs oracle32 {e32:.2e}, vs oracle64 {e64:.2e}, bound {bound:.2e}")
+    assert e32 <= bound and e64 <= bound
 
 
 def _hist_parity(hg, ho, tol):
@@ -115,10 +121,37 @@ def test_pcg_mixed_precision(name, cases, torch_gpu):
     xo, ho, nito, sto, tro = O.pcg_mixed(P.b, tol=1e-8)
     x64, _, nit64, _ = O.pcg(P.b, tol=1e-8)
     assert res.converged and res.rel_res_true <= 1e-8
-    assert abs(res.iterations - nito) <= max(3, nito // 10)
     err = _relinf(x.cpu().numpy(), x64)
     _say(f"  mixed: it={res.iterations} (oracle mixed {nito}, fp64 {nit64}) err_vs_fp64={err:.2e}")
+    assert abs(res.iterations - nito) <= max(3, nito // 10)
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["jump16", "aniso64"])
+def test_pcg_mixed_restarts(name, cases, torch_gpu):
+    """The binary32 cycle's true-residual restarts.  rtol = 1e-17 lies below
+    what binary64 reaches on the true residual (~1e-16), while the recursive
+    residual still meets it: every allowed restart is taken, on the GPU and in
+    the oracle alike, and the call ends not converged with x at the binary64
+    floor.  Where a restart segment ends is decided by residuals within
+    rounding of rtol, so each segment may end one iteration apart: the
+    iteration counts agree to 1 + restarts.  Both solutions sit at the binary64
+    floor: true residual ~2e-16 relative, condition numbers up to 4e6 (jump16),
+    so they agree with each other and with a binary64 solve to 1e-9 (measured
+    on the oracle: 1e-12)."""
+    P, path, st, S, O = cases[name]
+    xs, *_ = O.pcg(P.b, tol=1e-14)
+    for mr in (3, 1):
+        _say(f"[pcg32 restarts] {name} max_restarts={mr}")
+        x, res = S.solve(_t(torch_gpu, P.b), rtol=1e-17, precision=32, max_restarts=mr, maxit=400)
+        xo, ho, nito, sto, tro, rso = O.pcg_mixed(P.b, tol=1e-17, maxit=400, max_restarts=mr, with_restarts=True)
+        _say(f"  gpu it={res.iterations} restarts={res.restarts} true {res.rel_res_true:.1e}; "
+             f"oracle it={nito} restarts={rso} true {tro:.1e}")
+        assert res.restarts == rso == mr
+        assert not res.converged and sto == 1
+        assert abs(res.iterations - nito) <= 1 + mr
+        assert res.rel_res_true <= 1e-14
+        assert _relinf(x.cpu().numpy(), xo) <= 1e-9 and _relinf(x.cpu().numpy(), xs) <= 1e-9
 
 
 def test_nearby_matrix_values(cases, torch_gpu):

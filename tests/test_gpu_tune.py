@@ -113,20 +113,25 @@ def test_autotune_report_roundtrip_and_rejects(torch_gpu, tmp_path):
 
 
 def test_batch_chunk_variants_keep_parity(torch_gpu):
+    """Every reduction chunking the tuner may choose for a batch keeps every
+    problem's CG history and solution at oracle parity."""
     Ps, paths, stats = workloads.load_batch("batch6")
     BS = mvamg.BatchSolver(paths)
     rep = mvamg.autotune(BS.h, mvamg.TUNE_BATCH_CHUNKS | mvamg.TUNE_GROUP_LANES)
     _say(f"[tune batch] {rep}")
     assert "chunks" in rep
     b = np.concatenate([P.b for P in Ps])
-    ref = None
+    ref = [oracle.Oracle(p).pcg(P.b, tol=1e-8) for p, P in zip(paths, Ps)]
     for c in (4, 16, 64):
+        _say(f"[tune batch] chunks={c}")
         mvamg.tune_set(BS.h, f"chunks={c}")
         x = torch_gpu.zeros(BS.offsets[-1], dtype=torch_gpu.float64, device="cuda")
-        infos = mvamg.batch_pcg_solve(BS.h, _t(torch_gpu, b), x, rtol=1e-8)
+        H = np.zeros((BS.nprob, 1001))
+        infos = mvamg.batch_pcg_solve(BS.h, _t(torch_gpu, b), x, rtol=1e-8, history=H)
         xs = x.cpu().numpy()
-        assert all(i.converged for i in infos)
-        if ref is None:
-            ref = xs
-        assert _relinf(xs, ref) <= 1e-9
+        for p in range(BS.nprob):
+            xo, ho, nito, sto = ref[p]
+            assert infos[p].converged and sto == 0, (c, p)
+            _hist_parity(H[p, :infos[p].iterations + 1], ho, 1e-8)
+            assert _relinf(xs[BS.offsets[p]:BS.offsets[p + 1]], xo) <= 1e-9, (c, p)
     BS.close()
