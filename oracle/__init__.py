@@ -75,6 +75,10 @@ def _load():
                                     ctypes.c_int, ctypes.c_int, _D, _I, _D, _I]
         L.orc_pcg_mixed.restype = ctypes.c_int
         L.orc_grad_coeffs.argtypes = [ctypes.c_int, _I, _I, _D, _D, _D]
+        L.orc_kcycle.argtypes = [ctypes.c_void_p, _D, _D, _D]
+        L.orc_pcg_kcycle.argtypes = [ctypes.c_void_p, ctypes.c_int, _I, _I, _D, _D, _D, ctypes.c_double,
+                                     ctypes.c_int, _D, _I]
+        L.orc_pcg_kcycle.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -136,6 +140,26 @@ class Oracle:
         v0 = None if val0 is None else _p(_f64(val0), _D)
         _load().orc_vcycle(self._h, v0, _p(r, _D), _p(z, _D))
         return z
+
+    def kcycle(self, r, val0=None) -> np.ndarray:
+        """z = K r: the K-cycle (two inner flexible-CG iterations on every
+        level but the finest and the coarsest)."""
+        r = _f64(r)
+        z = np.zeros(self.n)
+        v0 = None if val0 is None else _p(_f64(val0), _D)
+        _load().orc_kcycle(self._h, v0, _p(r, _D), _p(z, _D))
+        return z
+
+    def pcg_kcycle(self, b, x0=None, tol=1e-8, maxit=1000, val=None):
+        """Flexible CG preconditioned by the K-cycle: (x, hist, nit, status)."""
+        b = _f64(b)
+        x = np.zeros(self.n) if x0 is None else _f64(x0).copy()
+        v = self.val if val is None else _f64(val)
+        hist = np.zeros(maxit + 1)
+        nit = ctypes.c_int(0)
+        st = _load().orc_pcg_kcycle(self._h, self.n, _p(self.rowptr, _I), _p(self.col, _I), _p(v, _D), _p(b, _D),
+                                    _p(x, _D), tol, maxit, _p(hist, _D), ctypes.byref(nit))
+        return x, hist[:nit.value + 1].copy(), nit.value, st
 
     def vcycle32(self, r) -> np.ndarray:
         r = np.ascontiguousarray(r, dtype=np.float32)

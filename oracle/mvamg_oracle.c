@@ -19,6 +19,10 @@
  *                binary64 flexible PCG outside it (extension beyond the paper).
  *   orc_grad_coeffs  dL/da_ij = -lambda_i x_j on the sparsity pattern
  *                (adjoint of A x = b for symmetric A; extension).
+ *   orc_kcycle / orc_pcg_kcycle  the K-cycle (nonlinear AMLI cycle) over the
+ *                same hierarchy, and CG with it as preconditioner (Section 5:
+ *                the bootstrap applies its AMG components as K-cycles with
+ *                two inner flexible-CG iterations per level but the coarsest).
  */
 #include <math.h>
 #include <stdint.h>
@@ -211,6 +215,81 @@ static void vcycle(const orc_hier* H, int l, const double* val0, const double* r
   vcycle(H, l + 1, val0, rc, xc);
   prolong_add(L, xc, x);
   /* post-smoothing: one backward sweep */
+  if (H->smoother == ORC_L1_JACOBI)
+    l1_jacobi(L, val, r, x);
+  else
+    gs_sweep(H, l, val, r, x, 0);
+  free(s);
+  free(rc);
+  free(xc);
+}
+
+/* ------------------------------------------------------------ K-cycle */
+
+static void kcycle(const orc_hier* H, int l, const double* val0, const double* r, double* x);
+
+/* y ~ A_m^{-1} g by two iterations of flexible CG from y = 0, both
+   preconditioned by the K-cycle of level m (Notay & Vassilevski 2008;
+   Section 5 takes two inner iterations).  The first direction is c1 = K g;
+   the second, c2 = K r2 with r2 = g - alpha1 A c1, is made A-orthogonal to
+   c1, so y is the A-orthogonal projection of A_m^{-1} g on span{c1, c2}. */
+static void kc_fcg2(const orc_hier* H, int m, const double* g, double* y) {
+  const orc_level* L = &H->lv[m];
+  const int n = L->n;
+  double* c1 = (double*)calloc((size_t)n, sizeof(double));
+  double* v1 = (double*)calloc((size_t)n, sizeof(double));
+  double* r2 = (double*)calloc((size_t)n, sizeof(double));
+  double* c2 = (double*)calloc((size_t)n, sizeof(double));
+  double* v2 = (double*)calloc((size_t)n, sizeof(double));
+  /* first iteration: y1 = alpha1 c1 */
+  kcycle(H, m, NULL, g, c1);
+  csr_mv(n, L->rowptr, L->col, L->val, c1, v1);
+  const double rho1 = dotp(c1, v1, n);
+  const double alpha1 = dotp(c1, g, n) / rho1;
+  for (int i = 0; i < n; ++i) r2[i] = g[i] - alpha1 * v1[i];
+  /* second iteration: direction p2 = c2 - (gamma / rho1) c1 */
+  kcycle(H, m, NULL, r2, c2);
+  csr_mv(n, L->rowptr, L->col, L->val, c2, v2);
+  const double gamma = dotp(c2, v1, n);
+  const double beta = dotp(c2, v2, n) - gamma * gamma / rho1; /* p2^T A p2 */
+  const double alpha2 = dotp(c2, r2, n) / beta;
+  /* y = alpha1 c1 + alpha2 p2 */
+  const double t1 = alpha1 - alpha2 * gamma / rho1;
+  for (int i = 0; i < n; ++i) y[i] = t1 * c1[i] + alpha2 * c2[i];
+  free(c1);
+  free(v1);
+  free(r2);
+  free(c2);
+  free(v2);
+}
+
+/* x = K_l r: the V-cycle's smoothing and transfers, with the coarse
+   correction on a level that is not the coarsest taken from kc_fcg2. */
+static void kcycle(const orc_hier* H, int l, const double* val0, const double* r, double* x) {
+  const orc_level* L = &H->lv[l];
+  const int n = L->n;
+  if (l == H->nl - 1) {
+    chol_solve(H->Lc, n, r, x);
+    return;
+  }
+  const double* val = (l == 0 && val0) ? val0 : L->val;
+  const int nc = H->lv[l + 1].n;
+  double* s = (double*)malloc(sizeof(double) * (size_t)n);
+  double* rc = (double*)malloc(sizeof(double) * (size_t)nc);
+  double* xc = (double*)malloc(sizeof(double) * (size_t)nc);
+  for (int i = 0; i < n; ++i) x[i] = 0.0;
+  if (H->smoother == ORC_L1_JACOBI)
+    l1_jacobi(L, val, r, x);
+  else
+    gs_sweep(H, l, val, r, x, 1);
+  csr_mv(n, L->rowptr, L->col, val, x, s);
+  for (int i = 0; i < n; ++i) s[i] = r[i] - s[i];
+  restrict_p(L, s, rc);
+  if (l + 1 == H->nl - 1)
+    chol_solve(H->Lc, nc, rc, xc);
+  else
+    kc_fcg2(H, l + 1, rc, xc);
+  prolong_add(L, xc, x);
   if (H->smoother == ORC_L1_JACOBI)
     l1_jacobi(L, val, r, x);
   else
@@ -548,6 +627,65 @@ done:
   free(r32);
   free(z32);
   free(v32);
+  return status;
+}
+
+void orc_kcycle(const orc_hier* H, const double* val0, const double* r, double* z) {
+  kcycle(H, 0, val0, r, z);
+}
+
+/*
+ * CG preconditioned by the K-cycle.  The K-cycle is not a linear operator
+ * (its inner coefficients depend on the residual), so CG takes the flexible
+ * beta = -alpha_k z_{k+1}.q_k / rho_k (Notay 2000), as orc_pcg_mixed does.
+ * Everything in binary64; stopping rule and history as orc_pcg.
+ */
+int orc_pcg_kcycle(const orc_hier* H, int n, const int* rp, const int* ci, const double* v, const double* b,
+                   double* x, double tol, int maxit, double* hist, int* nit) {
+  double* r = (double*)malloc(sizeof(double) * (size_t)n);
+  double* z = (double*)malloc(sizeof(double) * (size_t)n);
+  double* p = (double*)malloc(sizeof(double) * (size_t)n);
+  double* q = (double*)malloc(sizeof(double) * (size_t)n);
+  int status = 1;
+  *nit = 0;
+  csr_mv(n, rp, ci, v, x, q);
+  for (int i = 0; i < n; ++i) r[i] = b[i] - q[i];
+  const double r0 = sqrt(dotp(r, r, n));
+  if (hist) hist[0] = 1.0;
+  if (r0 == 0.0) {
+    status = 0;
+    goto done;
+  }
+  kcycle(H, 0, v, r, z);
+  memcpy(p, z, sizeof(double) * (size_t)n);
+  double rho = dotp(r, z, n);
+  for (int k = 0; k < maxit; ++k) {
+    csr_mv(n, rp, ci, v, p, q);
+    const double pq = dotp(p, q, n);
+    if (!(pq > 0.0)) {
+      status = -5;
+      break;
+    }
+    const double alpha = rho / pq;
+    for (int i = 0; i < n; ++i) x[i] += alpha * p[i];
+    for (int i = 0; i < n; ++i) r[i] -= alpha * q[i];
+    *nit = k + 1;
+    const double h = sqrt(dotp(r, r, n)) / r0;
+    if (hist) hist[k + 1] = h;
+    if (h <= tol) {
+      status = 0;
+      break;
+    }
+    kcycle(H, 0, v, r, z);
+    const double beta = -alpha * dotp(z, q, n) / rho;
+    rho = dotp(r, z, n);
+    for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+  }
+done:
+  free(r);
+  free(z);
+  free(p);
+  free(q);
   return status;
 }
 

@@ -163,3 +163,36 @@ def flexible_pcg(mv, prec, b, tol, maxit, max_restarts, beta_rule="notay"):
             status = 0
             break
     return x, np.array(hist), it, status, true_rel, restarts, restart_its
+
+
+def kcycle_dense(H, r, smoother="gs", level=0):
+    """K-cycle of the hierarchy H applied to r, from its definition with dense
+    matrices: the V-cycle's smoothing and transfers, and on a coarse level that
+    is not the coarsest, the A-orthogonal projection of A_c^{-1} r_c on the
+    span of c1 = K r_c and c2 = K (r_c - alpha1 A_c c1), alpha1 = c1^T r_c /
+    c1^T A_c c1 (what two steps of flexible CG produce: Notay and
+    Vassilevski, "Recursive Krylov-based multigrid cycles", 2008).  The
+    projection is taken by solving the 2 x 2 Galerkin system, not by the CG
+    recurrences."""
+    L = H.nlevels - 1
+    lv = H.levels[level]
+    A = dense(lv.rowptr, lv.col, lv.val)
+    if level == L:
+        return np.linalg.solve(A, r)
+    M = gs_splitting(A, lv.order) if smoother == "gs" else l1_splitting(A)
+    nc = H.levels[level + 1].n
+    P = prolongator(H.transfers[level], A.shape[0], nc)
+    x = np.linalg.solve(M, r)
+    rc = P.T @ (r - A @ x)
+    if level + 1 == L:
+        xc = np.linalg.solve(dense(H.levels[L].rowptr, H.levels[L].col, H.levels[L].val), rc)
+    else:
+        Ac = dense(H.levels[level + 1].rowptr, H.levels[level + 1].col, H.levels[level + 1].val)
+        c1 = kcycle_dense(H, rc, smoother, level + 1)
+        alpha1 = (c1 @ rc) / (c1 @ Ac @ c1)
+        c2 = kcycle_dense(H, rc - alpha1 * (Ac @ c1), smoother, level + 1)
+        V = np.stack([c1, c2], axis=1)
+        xc = V @ np.linalg.solve(V.T @ Ac @ V, V.T @ rc)
+    x = x + P @ xc
+    x = x + np.linalg.solve(M.T, r - A @ x)
+    return x
