@@ -79,6 +79,13 @@ def _load():
         L.orc_pcg_kcycle.argtypes = [ctypes.c_void_p, ctypes.c_int, _I, _I, _D, _D, _D, ctypes.c_double,
                                      ctypes.c_int, _D, _I]
         L.orc_pcg_kcycle.restype = ctypes.c_int
+        VP = ctypes.POINTER(ctypes.c_void_p)
+        L.orc_composite_apply.argtypes = [VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I, _I, _D, _D, _D]
+        L.orc_composite_test.argtypes = [VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I, _I, _D,
+                                         _D, _D]
+        L.orc_pcg_composite.argtypes = [VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I, _I, _D, _D, _D,
+                                        ctypes.c_double, ctypes.c_int, _D, _I]
+        L.orc_pcg_composite.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -220,6 +227,50 @@ class Oracle:
         return out + (rs.value,) if with_restarts else out
 
 
+class Composite:
+    """The composite AMG over bootstrap hierarchies B_1..B_r (Oracle objects
+    of the same fine matrix): the symmetrized multiplicative product of
+    Section 5 item (i), its testing phase and CG preconditioned by it.
+    kcycle selects K-cycle components instead of V-cycles."""
+
+    def __init__(self, oracles, kcycle: bool = False):
+        self.os = list(oracles)
+        self.r = len(self.os)
+        self.k = 1 if kcycle else 0
+        O0 = self.os[0]
+        for O in self.os[1:]:
+            if O.n != O0.n or not np.array_equal(O.val, O0.val) or not np.array_equal(O.col, O0.col):
+                raise ValueError("the hierarchies are not built on the same fine matrix")
+        self.n, self.rowptr, self.col, self.val = O0.n, O0.rowptr, O0.col, O0.val
+        self._hs = (ctypes.c_void_p * self.r)(*[O._h for O in self.os])
+
+    def apply(self, res) -> np.ndarray:
+        res = _f64(res)
+        z = np.zeros(self.n)
+        _load().orc_composite_apply(self._hs, self.r, self.k, self.n, _p(self.rowptr, _I), _p(self.col, _I),
+                                    _p(self.val, _D), _p(res, _D), _p(z, _D))
+        return z
+
+    def test(self, x0, nu: int = 15):
+        """(x^nu / ||x^nu||_A, rho estimate) of the testing phase from x0."""
+        x = _f64(x0).copy()
+        rho = ctypes.c_double(0.0)
+        _load().orc_composite_test(self._hs, self.r, self.k, nu, self.n, _p(self.rowptr, _I), _p(self.col, _I),
+                                   _p(self.val, _D), _p(x, _D), ctypes.byref(rho))
+        return x, rho.value
+
+    def pcg(self, b, tol=1e-8, maxit=1000):
+        """(x, hist, nit, status) of CG preconditioned by the composite."""
+        b = _f64(b)
+        x = np.zeros(self.n)
+        hist = np.zeros(maxit + 1)
+        nit = ctypes.c_int(0)
+        st = _load().orc_pcg_composite(self._hs, self.r, self.k, self.n, _p(self.rowptr, _I), _p(self.col, _I),
+                                       _p(self.val, _D), _p(b, _D), _p(x, _D), tol, maxit, _p(hist, _D),
+                                       ctypes.byref(nit))
+        return x, hist[:nit.value + 1].copy(), nit.value, st
+
+
 def spmv(rowptr, col, val, x) -> np.ndarray:
     rp, ci, v, x = _i32(rowptr), _i32(col), _f64(val), _f64(x)
     y = np.zeros(rp.shape[0] - 1)
@@ -234,4 +285,4 @@ def grad_coeffs(rowptr, col, lam, x) -> np.ndarray:
     return d
 
 
-__all__ = ["Oracle", "read_hierarchy", "spmv", "grad_coeffs", "build", "GS_COLOUR", "GS_LEX", "L1_JACOBI"]
+__all__ = ["Oracle", "Composite", "read_hierarchy", "spmv", "grad_coeffs", "build", "GS_COLOUR", "GS_LEX", "L1_JACOBI"]

@@ -23,6 +23,11 @@
  *                same hierarchy, and CG with it as preconditioner (Section 5:
  *                the bootstrap applies its AMG components as K-cycles with
  *                two inner flexible-CG iterations per level but the coarsest).
+ *   orc_composite_apply / orc_composite_test / orc_pcg_composite  the
+ *                bootstrap's composite AMG over several hierarchies B_1..B_r
+ *                (eq. 1.1, Algorithm 1, Section 5 item (i): the symmetrized
+ *                multiplicative product (I - B_1 A)..(I - B_r A)(I - B_r A)..
+ *                (I - B_1 A)), its testing phase, and CG preconditioned by it.
  */
 #include <math.h>
 #include <stdint.h>
@@ -683,6 +688,132 @@ int orc_pcg_kcycle(const orc_hier* H, int n, const int* rp, const int* ci, const
   }
 done:
   free(r);
+  free(z);
+  free(p);
+  free(q);
+  return status;
+}
+
+/* ------------------------------------------------------ composite AMG */
+
+/* z = B_k r with the V-cycle (kcyc == 0) or the K-cycle of hierarchy H; the
+   level-0 values are v (every bootstrap hierarchy is built on the same A). */
+static void component(const orc_hier* H, int kcyc, const double* v, const double* r, double* z) {
+  if (kcyc)
+    kcycle(H, 0, v, r, z);
+  else
+    vcycle(H, 0, v, r, z);
+}
+
+/* Index of the j-th factor of the symmetrized product, j = 0 .. 2r-1: the
+   order 1, 2, .., r, r, .., 2, 1 (0-based). */
+static int sym_index(int r, int j) { return j < r ? j : 2 * r - 1 - j; }
+
+/*
+ * z = B res for the symmetrized multiplicative composite of the r
+ * hierarchies Hs (eq. 1.1 and Section 5 item (i)): its error propagator is
+ * I - B A = (I - B_1 A)..(I - B_r A)(I - B_r A)..(I - B_1 A).  Starting from
+ * z = 0, every factor k in the order 1, .., r, r, .., 1 takes
+ * z <- z + B_k (res - A z), which multiplies the error A^{-1} res - z by
+ * (I - B_k A); the factor applied first is the rightmost one.
+ */
+void orc_composite_apply(const orc_hier* const* Hs, int r, int kcyc, int n, const int* rp, const int* ci,
+                         const double* v, const double* res, double* z) {
+  double* t = (double*)malloc(sizeof(double) * (size_t)n);
+  double* u = (double*)malloc(sizeof(double) * (size_t)n);
+  for (int i = 0; i < n; ++i) z[i] = 0.0;
+  for (int j = 0; j < 2 * r; ++j) {
+    csr_mv(n, rp, ci, v, z, t);
+    for (int i = 0; i < n; ++i) t[i] = res[i] - t[i];
+    component(Hs[sym_index(r, j)], kcyc, v, t, u);
+    for (int i = 0; i < n; ++i) z[i] += u[i];
+  }
+  free(t);
+  free(u);
+}
+
+/*
+ * The testing phase of Algorithm 1 with the symmetrized product: x <- E x,
+ * E = (I - B_1 A)..(I - B_r A)(I - B_r A)..(I - B_1 A), nu times, from the
+ * given x (every factor x <- x - B_k A x, rightmost first).  *rho receives
+ * the convergence estimate ||x^nu||_A / ||x^{nu-1}||_A and x the new smooth
+ * vector x^nu / ||x^nu||_A (left as x^nu when its A-norm is zero).
+ */
+void orc_composite_test(const orc_hier* const* Hs, int r, int kcyc, int nu, int n, const int* rp,
+                        const int* ci, const double* v, double* x, double* rho) {
+  double* t = (double*)malloc(sizeof(double) * (size_t)n);
+  double* u = (double*)malloc(sizeof(double) * (size_t)n);
+  double* prev = (double*)malloc(sizeof(double) * (size_t)n);
+  for (int it = 0; it < nu; ++it) {
+    memcpy(prev, x, sizeof(double) * (size_t)n);
+    for (int j = 0; j < 2 * r; ++j) {
+      csr_mv(n, rp, ci, v, x, t);
+      component(Hs[sym_index(r, j)], kcyc, v, t, u);
+      for (int i = 0; i < n; ++i) x[i] -= u[i];
+    }
+  }
+  csr_mv(n, rp, ci, v, x, t);
+  const double an = sqrt(fmax(0.0, dotp(x, t, n)));
+  csr_mv(n, rp, ci, v, prev, t);
+  const double ap = sqrt(fmax(0.0, dotp(prev, t, n)));
+  *rho = (ap > 0.0) ? an / ap : 0.0;
+  if (an > 0.0)
+    for (int i = 0; i < n; ++i) x[i] /= an;
+  free(t);
+  free(u);
+  free(prev);
+}
+
+/*
+ * CG preconditioned by the composite AMG (the paper's original bootstrap
+ * AMG, the b-it / b-ts comparison of Section 5).  With K-cycle components the
+ * preconditioner is not linear, so CG takes the flexible beta
+ * -alpha_k z_{k+1}.q_k / rho_k (Notay 2000) in both cases.  Stopping rule and
+ * history as orc_pcg.
+ */
+int orc_pcg_composite(const orc_hier* const* Hs, int r, int kcyc, int n, const int* rp, const int* ci,
+                      const double* v, const double* b, double* x, double tol, int maxit, double* hist, int* nit) {
+  double* rr = (double*)malloc(sizeof(double) * (size_t)n);
+  double* z = (double*)malloc(sizeof(double) * (size_t)n);
+  double* p = (double*)malloc(sizeof(double) * (size_t)n);
+  double* q = (double*)malloc(sizeof(double) * (size_t)n);
+  int status = 1;
+  *nit = 0;
+  csr_mv(n, rp, ci, v, x, q);
+  for (int i = 0; i < n; ++i) rr[i] = b[i] - q[i];
+  const double r0 = sqrt(dotp(rr, rr, n));
+  if (hist) hist[0] = 1.0;
+  if (r0 == 0.0) {
+    status = 0;
+    goto done;
+  }
+  orc_composite_apply(Hs, r, kcyc, n, rp, ci, v, rr, z);
+  memcpy(p, z, sizeof(double) * (size_t)n);
+  double rho = dotp(rr, z, n);
+  for (int k = 0; k < maxit; ++k) {
+    csr_mv(n, rp, ci, v, p, q);
+    const double pq = dotp(p, q, n);
+    if (!(pq > 0.0)) {
+      status = -5;
+      break;
+    }
+    const double alpha = rho / pq;
+    for (int i = 0; i < n; ++i) x[i] += alpha * p[i];
+    for (int i = 0; i < n; ++i) rr[i] -= alpha * q[i];
+    *nit = k + 1;
+    const double h = sqrt(dotp(rr, rr, n)) / r0;
+    if (hist) hist[k + 1] = h;
+    if (h <= tol) {
+      status = 0;
+      break;
+    }
+    orc_composite_apply(Hs, r, kcyc, n, rp, ci, v, rr, z);
+    const double beta = -alpha * dotp(z, q, n) / rho;
+    rho = dotp(rr, z, n);
+    for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+  }
+done:
+  free(rr);
   free(z);
   free(p);
   free(q);

@@ -63,6 +63,10 @@ def _load():
         lib.mvsetup_build.argtypes = [ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_double),
                                       P(ctypes.c_double), P(_Params), ctypes.c_char_p, P(ctypes.c_double)]
         lib.mvsetup_build.restype = ctypes.c_int
+        lib.mvsetup_build_boot.argtypes = [ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_double),
+                                           P(ctypes.c_double), P(_Params), ctypes.c_char_p, P(ctypes.c_double),
+                                           ctypes.c_char_p]
+        lib.mvsetup_build_boot.restype = ctypes.c_int
         lib.mvsetup_last_error.restype = ctypes.c_char_p
         lib.mvsetup_pairwise.argtypes = [ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_double),
                                          P(ctypes.c_double), P(ctypes.c_int), P(ctypes.c_double)]
@@ -86,11 +90,14 @@ def _csr(rowptr, col, val):
             np.ascontiguousarray(val, dtype=np.float64))
 
 
-def build_hierarchy(rowptr, col, val, path: str, x0: np.ndarray, params: SetupParams | None = None) -> dict:
+def build_hierarchy(rowptr, col, val, path: str, x0: np.ndarray, params: SetupParams | None = None,
+                    boot_prefix: str | None = None) -> dict:
     """Run the setup on A (CSR) and write the hierarchy to ``path``.
 
     ``x0`` is a (nvec_max - 1, n) array of random initial iterates for the
-    bootstrap testing phase.  Returns the setup statistics."""
+    bootstrap testing phase.  With ``boot_prefix``, the hierarchy of every
+    bootstrap stage r is also written, to ``<boot_prefix>_b<r>.bin``.
+    Returns the setup statistics."""
     lib = _load()
     p = params or SetupParams()
     rp, ci, v = _csr(rowptr, col, val)
@@ -102,9 +109,9 @@ def build_hierarchy(rowptr, col, val, path: str, x0: np.ndarray, params: SetupPa
     cp = _Params(p.nvec_max, p.nu, p.rho_des, p.maxstage, p.tol_svd, p.compose, p.coarse_cap,
                  p.boot_coarse_min, p.hier_stage, p.store_w, p.max_levels, p.nthreads, p.fine_group)
     stats = np.zeros(64)
-    rc = lib.mvsetup_build(n, _ptr(rp, ctypes.c_int), _ptr(ci, ctypes.c_int), _ptr(v, ctypes.c_double),
-                           _ptr(x0, ctypes.c_double), ctypes.byref(cp), path.encode(),
-                           _ptr(stats, ctypes.c_double))
+    rc = lib.mvsetup_build_boot(n, _ptr(rp, ctypes.c_int), _ptr(ci, ctypes.c_int), _ptr(v, ctypes.c_double),
+                                _ptr(x0, ctypes.c_double), ctypes.byref(cp), path.encode(),
+                                _ptr(stats, ctypes.c_double), boot_prefix.encode() if boot_prefix else None)
     if rc != 0:
         raise RuntimeError("setup failed: " + lib.mvsetup_last_error().decode())
     nl = int(stats[0])

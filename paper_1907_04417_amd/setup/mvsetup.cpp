@@ -896,6 +896,77 @@ void write_file(const char* path, const std::vector<Chunk>& chunks) {
   if (!ok) fail(std::string("write error on ") + path);
 }
 
+// Writes the bootstrap operator B_r (one hierarchy of Algorithm 1) in the
+// same file format as the multiple-vector hierarchy: per level the matrix,
+// its Gauss-Seidel order (the greedy colouring: every row its own group, the
+// colours as stages, which is the order gs_sweep relaxes in), and the
+// transfer as aggregates with one column each -- the composite pairwise
+// prolongator's values on the aggregate's members, of unit norm per
+// aggregate.  The meta record marks the file as stage `stage` of a bootstrap.
+void write_boot_hierarchy(const BHier& H, const char* path, int stage) {
+  const int L = (int)H.lv.size() - 1;
+  std::vector<Chunk> ch;
+  std::vector<int64_t> meta = {1, L + 1, 1, H.lv[0].A.n, (int64_t)H.lv[0].A.nnz(), 0, (int64_t)stage};
+  std::vector<double> prmv = {0.0, 0.0, 0.0, 1.0, 0.0, 0.0};
+  std::vector<double> st = {0.0, 0.0};
+  std::vector<double> none;
+  ch.push_back({"meta", 3, meta.data(), meta.size()});
+  ch.push_back({"params", 2, prmv.data(), prmv.size()});
+  ch.push_back({"stats", 2, st.data(), st.size()});
+  ch.push_back({"rho", 2, none.data(), 0});
+  struct Tr {
+    std::vector<int> gptr, aptr, arows, coff, uoff;
+    std::vector<double> U, drop2;
+  };
+  std::vector<Tr> tr(L);
+  auto nm = [&](const char* f, int l) {
+    char b[64];
+    std::snprintf(b, sizeof b, f, l);
+    return std::string(b);
+  };
+  for (int l = 0; l < L; ++l) {
+    const BLevel& B = H.lv[l];
+    Tr& T = tr[l];
+    const int n = B.A.n, nc = B.P.nc;
+    T.gptr.resize(n + 1);
+    for (int i = 0; i <= n; ++i) T.gptr[i] = i;
+    T.aptr.assign(nc + 1, 0);
+    for (int i = 0; i < n; ++i) T.aptr[B.P.agg[i] + 1]++;
+    for (int a = 0; a < nc; ++a) T.aptr[a + 1] += T.aptr[a];
+    T.arows.resize(n);
+    T.U.resize(n);
+    std::vector<int> pos(T.aptr.begin(), T.aptr.end() - 1);
+    for (int i = 0; i < n; ++i) {
+      const int q = pos[B.P.agg[i]]++;
+      T.arows[q] = i;
+      T.U[q] = B.P.p[i];
+    }
+    T.coff.resize(nc + 1);
+    for (int a = 0; a <= nc; ++a) T.coff[a] = a;
+    T.uoff = T.aptr;
+    T.drop2.assign(nc, 0.0);
+  }
+  for (int l = 0; l <= L; ++l) {
+    const Csr& A = H.lv[l].A;
+    ch.push_back({nm("A%d.rowptr", l), 1, A.rp.data(), A.rp.size()});
+    ch.push_back({nm("A%d.col", l), 1, A.ci.data(), A.ci.size()});
+    ch.push_back({nm("A%d.val", l), 2, A.v.data(), A.v.size()});
+    if (l == L) break;
+    const Colouring& C = H.lv[l].C;
+    const Tr& T = tr[l];
+    ch.push_back({nm("A%d.order", l), 1, C.crows.data(), C.crows.size()});
+    ch.push_back({nm("A%d.gptr", l), 1, T.gptr.data(), T.gptr.size()});
+    ch.push_back({nm("A%d.sptr", l), 1, C.cptr.data(), C.cptr.size()});
+    ch.push_back({nm("P%d.aptr", l), 1, T.aptr.data(), T.aptr.size()});
+    ch.push_back({nm("P%d.arows", l), 1, T.arows.data(), T.arows.size()});
+    ch.push_back({nm("P%d.coff", l), 1, T.coff.data(), T.coff.size()});
+    ch.push_back({nm("P%d.uoff", l), 1, T.uoff.data(), T.uoff.size()});
+    ch.push_back({nm("P%d.U", l), 2, T.U.data(), T.U.size()});
+    ch.push_back({nm("P%d.drop2", l), 2, T.drop2.data(), T.drop2.size()});
+  }
+  write_file(path, ch);
+}
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -918,9 +989,21 @@ const char* mvsetup_last_error(void) { return g_err.c_str(); }
 // phase: (nvec_max - 1) vectors of length n, one after the other.  `stats`
 // receives up to 64 doubles: [0] nlevels, [1] nvec, [2] opc, [3] cr,
 // [4] nstages, [5..] per-stage rho, [24..] per-level n, [44..] per-level nnz.
+int mvsetup_build_boot(int n, const int* rowptr, const int* col, const double* val, const double* x0,
+                       const mvsetup_params* prm_in, const char* path, double* stats, const char* boot_prefix);
+
 int mvsetup_build(int n, const int* rowptr, const int* col, const double* val,
                   const double* x0, const mvsetup_params* prm_in, const char* path,
                   double* stats) {
+  return mvsetup_build_boot(n, rowptr, col, val, x0, prm_in, path, stats, nullptr);
+}
+
+// As mvsetup_build; when boot_prefix is not null, also writes the hierarchy
+// of every bootstrap stage r = 1, 2, ... (the operators B_r whose symmetrized
+// multiplicative composite the testing phase applies) to
+// "<boot_prefix>_b<r>.bin".
+int mvsetup_build_boot(int n, const int* rowptr, const int* col, const double* val, const double* x0,
+                       const mvsetup_params* prm_in, const char* path, double* stats, const char* boot_prefix) {
   try {
     if (!prm_in || n <= 0 || !rowptr || !col || !val || !path) fail("invalid argument");
     Params prm{prm_in->nvec_max, prm_in->nu,         prm_in->rho_des,
@@ -983,6 +1066,10 @@ int mvsetup_build(int n, const int* rowptr, const int* col, const double* val,
       }
     }
     const int nvec = (int)W.size();
+    if (boot_prefix)
+      for (size_t r = 0; r < hs.size(); ++r)
+        write_boot_hierarchy(hs[r], (std::string(boot_prefix) + "_b" + std::to_string(r + 1) + ".bin").c_str(),
+                             (int)r + 1);
     const int hsel = (prm.hier_stage < 0) ? (int)hs.size() - 1 : std::min(prm.hier_stage, (int)hs.size() - 1);
     BHier& H = hs[hsel];
     const int D = (int)H.lv.size() - 1;  // index of the bootstrap coarsest level
