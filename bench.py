@@ -103,6 +103,16 @@ def counted_bytes_per_iteration(lv, nu):
     return b
 
 
+def host_cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def measured_copy_gbs(torch, mib=1024, reps=10):
     """Stream-copy bandwidth of this GPU: bytes read + written per second by a
     plain device-to-device copy of `mib` MiB."""
@@ -143,13 +153,88 @@ def _kernel_table(mvamg, h, nsolves):
     return kernels
 
 
+def bench_latency(args, torch, mvamg, workloads, tune_cache):
+    """The small 2-D case (64^2 rotated anisotropic): a solve is a chain of
+    short launches, so this measures latency, not bandwidth."""
+    P, path, st = workloads.load("aniso64")
+    S = mvamg.Solver(path)
+    tune = mvamg.tuned(S.h, tune_cache)
+    b = torch.from_numpy(P.b).cuda()
+    x = torch.zeros_like(b)
+    res = {}
+    for prec in (64, 32):
+        def solve():
+            x.zero_()
+            return mvamg.pcg_solve(S.h, b, x, rtol=1e-8, maxit=1000, precision=prec)
+        ms, inf = _timed_ms(torch, solve, max(3, args.steps), 2)
+        res[prec] = dict(ms=ms, nit=inf.iterations, ok=bool(inf.converged) and inf.rel_res_true <= 1.01e-8)
+        log(f"[bench] aniso64 precision {prec}: {ms:.3f} ms/solve, nit={inf.iterations}")
+    S.close()
+    r64, r32 = res[64], res[32]
+    return {
+        "workload": WORKLOAD_DESC["aniso64"], "value": 1e3 / r64["ms"], "unit": "solves/s",
+        "ms_per_solve": r64["ms"], "us_per_iteration": 1e3 * r64["ms"] / r64["nit"], "nit": r64["nit"],
+        "levels": st["n"], "all_converged": r64["ok"] and r32["ok"], "tuning": tune,
+        "fp32_cycle": {"value": 1e3 / r32["ms"], "ms_per_solve": r32["ms"], "nit": r32["nit"]},
+    }
+
+
+def bench_adjoint(args, torch, mvamg, workloads, tune_cache):
+    """The differentiable solve on 1024^2 cells (kappa = exp(g), g a Gaussian
+    random field): one step is the forward solve, the adjoint solve for
+    L = ||x - x_obs||^2 and the coefficient gradient -lambda_i x_j, all to
+    1e-8 with the binary64 cycle."""
+    P, path, st = workloads.load("grf1024")
+    S = mvamg.Solver(path)
+    tune = mvamg.tuned(S.h, tune_cache)
+    b = torch.from_numpy(P.b).cuda()
+    val = torch.from_numpy(P.val).cuda()
+    A = (None, None, val)
+    x = torch.zeros_like(b)
+    lam = torch.zeros_like(b)
+    dval = torch.empty_like(val)
+    mvamg.pcg_solve(S.h, b, x, rtol=1e-12, maxit=2000, A=A)
+    rng = np.random.default_rng(1)
+    rms = float(torch.sqrt((x * x).mean()))
+    x_obs = x + torch.from_numpy(rng.normal(0.0, 0.01 * rms, P.n)).cuda()
+    out = {}
+
+    def step():
+        x.zero_()
+        fi = mvamg.pcg_solve(S.h, b, x, rtol=1e-8, maxit=1000, A=A)
+        gx = 2.0 * (x - x_obs)
+        ai = mvamg.adjoint_solve(S.h, gx, lam, rtol=1e-8, maxit=1000, A=A)
+        mvamg.grad_coeffs(S.h, lam, x, dval)
+        out["f"], out["a"] = fi, ai
+        return fi, ai
+    ms, _ = _timed_ms(torch, step, max(1, min(args.steps, 5)), 1)
+
+    def fwd():
+        x.zero_()
+        return mvamg.pcg_solve(S.h, b, x, rtol=1e-8, maxit=1000, A=A)
+    ms_f, _ = _timed_ms(torch, fwd, max(1, min(args.steps, 5)), 1)
+    fi, ai = out["f"], out["a"]
+    ok = bool(fi.converged and ai.converged) and fi.rel_res_true <= 1.01e-8 and ai.rel_res_true <= 1.01e-8
+    log(f"[bench] grf1024 forward + adjoint + gradient: {ms:.2f} ms (forward alone {ms_f:.2f} ms), "
+        f"nit {fi.iterations} + {ai.iterations}")
+    S.close()
+    return {
+        "workload": "grf1024: cell-centred 5-point finite volumes on 1024^2 cells, kappa = exp(g), g Gaussian random "
+                    "field (squared-exponential covariance, length 0.05), b = h^2; L = ||x - x_obs||^2; forward and "
+                    "adjoint solves to rtol 1e-8 (binary64 cycle) and the coefficient gradient",
+        "value": 1e3 / ms, "unit": "gradients/s", "ms_per_gradient": ms, "ms_forward": ms_f,
+        "nit_forward": fi.iterations, "nit_adjoint": ai.iterations, "levels": st["n"], "all_converged": ok,
+        "tuning": tune,
+    }
+
+
 def bench_multi_rhs(args, torch, mvamg, workloads, tune_cache):
     """32 right-hand sides through one hierarchy (block solve) against 32
     single-system solves of the same columns."""
     from paper_1907_04417_amd import problems
     t0 = time.time()
     P, path, st = workloads.load("aniso1024")
-    S = mvamg.Solver(path)
+    S = mvamg.Solver(path, nrhs=32)
     tune = mvamg.tuned(S.h, tune_cache)
     log(f"[bench] multi-rhs aniso1024: levels={st['n']} setup+upload {time.time() - t0:.1f}s tuning {tune}")
     B, _ = problems.block_rhs(P, 32, seed=workloads.BLOCK_RHS_SEED)
@@ -250,7 +335,7 @@ def bench_batch(args, torch, mvamg, workloads, tune_cache):
         "fp32_cycle": {"value": 64e3 / r32["ms"], "ms_per_batch": r32["ms"], "nit": r32["its"],
                        "speedup_vs_separate_fp64": r64["ms_seq"] / r32["ms"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": kernels[dom]["gbs"] / HBM_PEAK_GBS, "traffic": None},
+                     "frac": kernels[dom]["gbs"] / HBM_PEAK_GBS, "traffic": recorded_traffic(dom, "batch64")},
         "kernels": kernels,
     }
 
@@ -316,7 +401,6 @@ def main():
 
     import torch
     from paper_1907_04417_amd import mvamg, workloads
-    from oracle.hierfile import read_hierarchy
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     copy_gbs = measured_copy_gbs(torch)
@@ -332,11 +416,18 @@ def main():
     b = torch.from_numpy(P.b).cuda()
     x = torch.zeros_like(b)
     hist = np.zeros(1001)
+    # the matrix is passed to every solve (its pattern and values are checked
+    # against the hierarchy's inside the timed call)
+    A = (torch.from_numpy(P.rowptr.astype(np.int32)).cuda(), torch.from_numpy(P.col.astype(np.int32)).cuda(),
+         torch.from_numpy(P.val).cuda())
+    # at most 256 distinct off-diagonal values: the fine kernels read 1-byte codes
+    offdiag = P.val[P.col != np.repeat(np.arange(P.n), np.diff(P.rowptr))]
+    value_codes = bool(np.unique(offdiag).size <= 256)
 
     def solve(precision):
         x.zero_()
         return mvamg.pcg_solve(S.h, b, x, rtol=1e-8, maxit=1000, precision=precision, history=hist,
-                               stream=stream)
+                               stream=stream, A=A)
 
     def timed(precision):
         for _ in range(args.warmup):
@@ -358,59 +449,98 @@ def main():
                              rel_res_true=inf.rel_res_true, x=xs)
         log(f"[bench] precision {prec}: {ms:.3f} ms/solve, nit={inf.iterations}, true_res={inf.rel_res_true:.2e}")
 
-    H = read_hierarchy(path)
+    for prec, r in results.items():
+        if not (r["converged"] and r["rel_res_true"] <= 1.01e-8):
+            log(f"[bench] FAILED: precision {prec} did not reach 1e-8 (converged={r['converged']}, "
+                f"true residual {r['rel_res_true']:.2e})")
+            sys.exit(3)
     lv = mvamg.levels(S.h)
-    nu = [int(T.U.shape[0]) for T in H.transfers]
-    bpi = counted_bytes_per_iteration(lv, nu)
+    bpi = counted_bytes_per_iteration(lv, mvamg.transfers(S.h)["nu"])
     r64 = results[64]
 
     roofline = None
     kernels = {}
     if not args.no_profile_pass:
-        mvamg.profile(S.h, True)
-        t_prof = time.perf_counter()
-        for _ in range(args.steps):
-            solve(64)
-        torch.cuda.synchronize()
-        t_prof = (time.perf_counter() - t_prof) * 1e3 / args.steps
-        for kc, name in enumerate(mvamg.KC_NAMES):
-            nl, ms, by = mvamg.kernel_stats(S.h, kc)
-            if nl:
-                kernels[name] = dict(launches=nl // args.steps, ms_per_step=ms / args.steps,
-                                     us_per_launch=1e3 * ms / nl, gbs=by / (ms * 1e-3) / 1e9 if ms > 0 else None)
-        mvamg.profile(S.h, False)
+        # two passes with per-launch events: bytes in the plain model (12 B per
+        # stored binary64 entry, the figure `frac` uses) and in the compact forms
+        # the kernels actually read
+        booked = {}
+        for booking in (mvamg.BOOK_PLAIN, mvamg.BOOK_COMPACT):
+            mvamg.profile(S.h, True, booking)
+            t_prof = time.perf_counter()
+            for _ in range(args.steps):
+                solve(64)
+            torch.cuda.synchronize()
+            t_prof = (time.perf_counter() - t_prof) * 1e3 / args.steps
+            tab = {}
+            for kc, name in enumerate(mvamg.KC_NAMES):
+                nl, ms, by = mvamg.kernel_stats(S.h, kc)
+                if nl:
+                    tab[name] = dict(launches=nl // args.steps, ms_per_step=ms / args.steps,
+                                     us_per_launch=1e3 * ms / nl, gbs=by / (ms * 1e-3) / 1e9 if ms > 0 else None,
+                                     bytes_per_launch=by / nl)
+            mvamg.profile(S.h, False)
+            booked[booking] = (tab, t_prof)
+        kernels, t_prof = booked[mvamg.BOOK_PLAIN]
+        compact = booked[mvamg.BOOK_COMPACT][0]
+        for name, k in kernels.items():
+            k["gbs_compact"] = compact[name]["gbs"]
+            k["bytes_per_launch_compact"] = compact[name]["bytes_per_launch"]
         dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-        kc = mvamg.KC_NAMES.index(dom)
         dl = kernels[dom]
         achieved = dl["gbs"]
         traffic = recorded_traffic(dom, args.workload)
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
+                    "bytes_model": "plain: 12 B per stored binary64 entry + 4 B per row + 8 B per vector element "
+                                   "touched (frac); compact: the forms the kernels read (frac_compact)",
+                    "bytes_per_launch": dl["bytes_per_launch"],
+                    "achieved_compact": dl["gbs_compact"], "frac_compact": dl["gbs_compact"] / HBM_PEAK_GBS,
+                    "bytes_per_launch_compact": dl["bytes_per_launch_compact"],
+                    "fine_value_codes": value_codes,
                     "measured_copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                     "launches_per_step": dl["launches"], "us_per_launch": dl["us_per_launch"],
                     "profiled_ms_per_step": t_prof}
         log(f"[bench] dominant kernel class {dom}: {dl['ms_per_step']:.2f} ms/step over {dl['launches']} launches, "
-            f"{achieved:.0f} GB/s")
+            f"{achieved:.0f} GB/s plain, {dl['gbs_compact']:.0f} GB/s compact")
+
+    # the same solves reading the stored values (no 1-byte value codes): a
+    # refill with the same values retires the codes
+    codes_off = None
+    if value_codes:
+        mvamg.set_fine_values(S.h, A[2])
+        ms_off, inf_off = timed(64)
+        codes_off = {"value": 1e3 / ms_off, "unit": "solves/s", "ms_per_step": ms_off, "nit": inf_off.iterations,
+                     "rel_res_true": inf_off.rel_res_true}
+        log(f"[bench] without value codes: {ms_off:.3f} ms/solve")
 
     cpu = None
+    x_oracle = None
     if not args.no_cpu_baseline:
         import oracle
         tc = time.perf_counter()
-        O = oracle.Oracle(H)
+        O = oracle.Oracle(path)
         tf = time.perf_counter() - tc
         tc = time.perf_counter()
-        _, ho, nit_c, _ = O.pcg(P.b, tol=1e-8)
+        x_oracle, ho, nit_c, _ = O.pcg(P.b, tol=1e-8)
         tcpu = time.perf_counter() - tc
         cpu = dict(value=1.0 / tcpu, unit="solves/s", cores=1, kind="oracle",
+                   host_cpu=host_cpu_model(), host_threads=os.cpu_count(),
                    sample=f"one complete solve of the same system ({nit_c} CG iterations, {tcpu:.1f} s on one host "
                           f"core; the oracle's own coarsest factorisation, {tf:.1f} s, is setup and not counted)")
         log(f"[bench] oracle: {tcpu:.1f} s/solve ({nit_c} iterations)")
 
-    multi = batch = elast = None
+    S.close()
+    multi = batch = elast = latency = adjoint = None
     if not args.no_multi:
+        latency = bench_latency(args, torch, mvamg, workloads, tune_cache)
         multi = bench_multi_rhs(args, torch, mvamg, workloads, tune_cache)
         batch = bench_batch(args, torch, mvamg, workloads, tune_cache)
         elast = bench_elasticity(args, torch, mvamg, workloads, tune_cache)
+        adjoint = bench_adjoint(args, torch, mvamg, workloads, tune_cache)
+
+    def err_vs(xa, xb):
+        return None if xb is None else float(np.abs(xa - xb).max() / np.abs(xb).max())
 
     r32 = results[32]
     out = {
@@ -434,10 +564,16 @@ def main():
         "hbm_gbs_counted_whole_solve": bpi * r64["nit"] / (r64["ms"] * 1e-3) / 1e9,
         "bytes_per_iteration": bpi,
         "kernels": kernels,
+        "rel_res_true": r64["rel_res_true"],
+        "err_vs_oracle": err_vs(r64["x"], x_oracle),
+        "value_codes_off": codes_off,
         "mixed": {"value": 1e3 / r32["ms"], "unit": "solves/s", "dtype": "f32 cycle, f64 CG",
                   "ms_per_step": r32["ms"], "nit": r32["nit"], "speedup_vs_fp64": r64["ms"] / r32["ms"],
                   "rel_res_true": r32["rel_res_true"],
-                  "err_vs_fp64_solution": float(np.abs(r32["x"] - r64["x"]).max() / np.abs(r64["x"]).max())},
+                  "err_vs_oracle": err_vs(r32["x"], x_oracle),
+                  "err_vs_fp64_solution": err_vs(r32["x"], r64["x"])},
+        "latency": latency,
+        "adjoint": adjoint,
         "multi_rhs": multi,
         "batch": batch,
         "elasticity": elast,

@@ -55,6 +55,14 @@ typedef struct mvamg_hier_host mvamg_hier_host;
 typedef struct mvamg_hier mvamg_hier;
 
 enum { MVAMG_SMOOTH_GS = 0, MVAMG_SMOOTH_L1JACOBI = 1 };
+/* The preconditioner CG applies: one V-cycle, or one K-cycle -- the V-cycle's
+   smoothing and transfers, with the coarse correction on every level that is
+   neither the finest nor the coarsest taken as two flexible-CG iterations on
+   that level, each preconditioned by the K-cycle of that level (Section 5:
+   the bootstrap applies its AMG components as K-cycles, nonlinear AMLI
+   cycles, with two inner flexible-CG iterations per level but the
+   coarsest). */
+enum { MVAMG_CYCLE_V = 0, MVAMG_CYCLE_K = 1 };
 
 typedef struct {
   int precision;     /* 64: whole cycle in binary64; 32: cycle (smoother, level
@@ -68,6 +76,9 @@ typedef struct {
                         residual misses rtol (iterative refinement); ignored for 64 */
   double* history;   /* host, optional (NULL): receives ||r_k|| / ||r_0|| for
                         k = 0..iterations; capacity maxit + 1 */
+  int cycle;         /* MVAMG_CYCLE_V, or MVAMG_CYCLE_K (precision 64 only; the
+                        K-cycle is not a linear operator, so CG then takes the
+                        flexible beta); block and batch solves take V only */
 } mvamg_solve_params;
 
 typedef struct {
@@ -89,19 +100,46 @@ void mvamg_hier_host_free(mvamg_hier_host* h);
 /* Level count, fine size n and fine nonzeros of a parsed file. */
 mvamg_status mvamg_hier_host_info(const mvamg_hier_host* h, int* nlevels, int* n, int64_t* nnz);
 
-/* Copies the hierarchy to the current device in the library's layout
-   (rows permuted into smoother order, off-group entries in sliced-ELL or
-   grouped CSR, per-aggregate U blocks), keeps binary32 copies for the mixed
-   cycle, and factors the coarsest matrix with a dense Cholesky on the device
-   (Section 5 uses a direct coarsest solve).  The host object may be freed
-   afterwards.  Errors: MVAMG_ERR_ARG, MVAMG_ERR_NOT_SPD, MVAMG_ERR_HIP. */
-mvamg_status mvamg_upload(const mvamg_hier_host* h, void* stream, mvamg_hier** out);
+/* Device memory of a handle.  The caller owns all of it: one arena (a
+   device buffer, 256-byte aligned, e.g. a torch uint8 tensor) per handle,
+   passed to mvamg_upload and borrowed by the handle until mvamg_free; it
+   must not be freed or reused before.  The library keeps only host
+   structures (the parsed layout, mapped host memory for the per-iteration
+   scalars, captured graphs).
+
+   *bytes receives the arena size mvamg_upload needs for h: the level
+   layouts in binary64 and binary32, the transfers, the coarsest inverse, the
+   CG and cycle work vectors, and the temporaries of the coarsest
+   factorisation (released inside the arena and reused).  nrhs > 1 (at most
+   MVAMG_BLOCK_MAX) adds the work space of the block calls for several
+   right-hand sides.  Host only, nothing touches the device.
+   Errors: MVAMG_ERR_ARG. */
+mvamg_status mvamg_arena_bytes(const mvamg_hier_host* h, int nrhs, size_t* bytes);
+
+/* Copies the hierarchy into the caller's arena (arena_bytes bytes at
+   arena_dev) in the library's layout (rows permuted into smoother order,
+   off-group entries in sliced-ELL or grouped CSR, per-aggregate U blocks),
+   keeps binary32 copies for the mixed cycle, and factors the coarsest matrix
+   with a dense Cholesky on the device (Section 5 uses a direct coarsest
+   solve).  Allocates no device memory.  The host object may be freed
+   afterwards.  Errors: MVAMG_ERR_ARG (null or unaligned arena, an arena
+   smaller than mvamg_arena_bytes reports -- also raised by the first block
+   call when the arena was sized with nrhs = 1), MVAMG_ERR_NOT_SPD,
+   MVAMG_ERR_HIP. */
+mvamg_status mvamg_upload(const mvamg_hier_host* h, void* arena_dev, size_t arena_bytes, void* stream,
+                          mvamg_hier** out);
+/* Releases the handle's host structures; the arena goes back to the caller. */
 void mvamg_free(mvamg_hier* h);
 
 /* Level count and sizes of an uploaded hierarchy: n[l], nnz[l] for
    l < nlevels (arrays of capacity 32, may be NULL), stages[l] = number of
    smoother stages (0 on the coarsest). */
 mvamg_status mvamg_levels(const mvamg_hier* h, int* nlevels, int* n, int64_t* nnz, int* stages);
+
+/* Sizes of the transfers P^l of an uploaded hierarchy, l < nlevels - 1:
+   nagg[l] aggregates and nu[l] = sum over aggregates of n_a k_a stored
+   entries of the blocks U_a (arrays of capacity 32, may be NULL). */
+mvamg_status mvamg_transfers(const mvamg_hier* h, int* nagg, int64_t* nu);
 
 /* Replaces the values of the finest matrix by val_dev (device, float64,
    nnz entries in the CSR order of the file's level 0): a near-by matrix with
@@ -124,21 +162,41 @@ mvamg_status mvamg_spmv(mvamg_hier* h, const double* x_dev, double* y_dev, void*
 mvamg_status mvamg_cycle_apply(mvamg_hier* h, const double* r_dev, double* z_dev, int precision,
                                int smoother, void* stream);
 
-/* Preconditioned CG (Section 5) on A x = b with B = one V-cycle.  x_dev holds
+/* z = K r: one K-cycle (MVAMG_CYCLE_K) from a zero initial guess, binary64,
+   smoother as in mvamg_solve_params.  On a two-level hierarchy it equals
+   mvamg_cycle_apply.  r_dev and z_dev must not alias. */
+mvamg_status mvamg_kcycle_apply(mvamg_hier* h, const double* r_dev, double* z_dev, int smoother, void* stream);
+
+/* Preconditioned CG (Section 5) on A x = b with B = one V-cycle.  A is the
+   finest-level matrix in the file's CSR form (device arrays: rowptr int32
+   [n+1], col int32 [nnz], val float64 [nnz]).  It must have the hierarchy's
+   pattern; its values may differ from the hierarchy's A_0 (a near-by matrix,
+   Section 1): the fine-level products and smoothing then use them, coarser
+   levels keep the stored Galerkin matrices.  rowptr and col are compared
+   with the stored pattern (MVAMG_ERR_ARG if they differ); both may be NULL to
+   skip that check.  val is compared with the values in use and, if any
+   entry differs, replaces them as mvamg_set_fine_values does; NULL keeps
+   the values in use.  x_dev holds
    x_0 on entry (zero for the paper's setting) and the solution on exit.
    Returns MVAMG_OK, MVAMG_NOT_CONVERGED, or an error.  Each iteration's
    scalars (||r_k||^2 for the stopping test, the breakdown flag) are written
    by the last kernel of the iteration straight into mapped host memory that
-   the handle owns; the host reads them after synchronising the stream. */
-mvamg_status mvamg_pcg_solve(mvamg_hier* h, const double* b_dev, double* x_dev,
-                             const mvamg_solve_params* prm, mvamg_info* info, void* stream);
+   the handle owns; the host reads them after synchronising the stream.  The
+   first solve of each precision and smoother captures one iteration as a
+   HIP graph and replays it; the runtime's executable graph holds about 2 MiB
+   of device memory of its own until mvamg_free (the environment variable
+   MVAMG_NO_GRAPH=1, read at upload, runs plain launches instead). */
+mvamg_status mvamg_pcg_solve(mvamg_hier* h, const int* rowptr_dev, const int* col_dev, const double* val_dev,
+                             const double* b_dev, double* x_dev, const mvamg_solve_params* prm, mvamg_info* info,
+                             void* stream);
 
 /* Adjoint solve for a loss L(x): A^T lambda = dL/dx.  A is symmetric, so
    this is the same preconditioned CG with right-hand side dLdx_dev (the
-   hierarchy is reused as is).  lambda_dev receives the solution (initial
-   guess zero). */
-mvamg_status mvamg_adjoint_solve(mvamg_hier* h, const double* dLdx_dev, double* lambda_dev,
-                                 const mvamg_solve_params* prm, mvamg_info* info, void* stream);
+   hierarchy is reused as is).  rowptr_dev, col_dev, val_dev: A, as for
+   mvamg_pcg_solve.  lambda_dev receives the solution (initial guess zero). */
+mvamg_status mvamg_adjoint_solve(mvamg_hier* h, const int* rowptr_dev, const int* col_dev, const double* val_dev,
+                                 const double* dLdx_dev, double* lambda_dev, const mvamg_solve_params* prm,
+                                 mvamg_info* info, void* stream);
 
 /* Gradient of L with respect to the stored finest-matrix values:
    dval[k] = -lambda_i x_j for the k-th stored entry (i, j) of the file's
@@ -154,9 +212,10 @@ mvamg_status mvamg_grad_coeffs(mvamg_hier* h, const double* lambda_dev, const do
    of n x m binary64 values, row-major (row i holds the m values of row i of
    every column, file order of the rows).  The library stages them in n x 32
    blocks so that one load of a matrix entry serves every column; columns
-   m..31 are carried as zero.  The first block call on a handle allocates
-   about (7 x 8 + 3 x 4) x 32 bytes per fine row of work space, kept until
-   mvamg_free.  Not available on batch handles. */
+   m..31 are carried as zero.  The first block call on a handle takes
+   about (7 x 8 + 3 x 4) x 32 bytes per fine row of work space from the
+   arena, kept until mvamg_free: size the arena with nrhs > 1
+   (mvamg_arena_bytes).  Not available on batch handles. */
 #define MVAMG_BLOCK_MAX 32
 
 /* Y = A X for m columns (1 <= m <= 32). */
@@ -186,9 +245,14 @@ mvamg_status mvamg_pcg_solve_block(mvamg_hier* h, const double* B_dev, double* X
    batch are the problems' vectors one after another (problem p at rows
    offsets[p] .. offsets[p+1]-1 of mvamg_batch_problems).  The handle is
    released with mvamg_free; mvamg_spmv, mvamg_cycle_apply (block diagonal)
-   and mvamg_set_fine_values accept it, mvamg_pcg_solve does not.
-   Errors: MVAMG_ERR_ARG (level counts differ, too large), as mvamg_upload. */
-mvamg_status mvamg_batch_upload(const mvamg_hier_host* const* hs, int nprob, void* stream, mvamg_hier** out);
+   and mvamg_set_fine_values accept it, mvamg_pcg_solve does not.  The
+   caller owns the device memory, as for mvamg_upload: *bytes of
+   mvamg_batch_arena_bytes (host only) is the arena mvamg_batch_upload needs.
+   Errors: MVAMG_ERR_ARG (level counts differ, too large, arena too small),
+   as mvamg_upload. */
+mvamg_status mvamg_batch_arena_bytes(const mvamg_hier_host* const* hs, int nprob, size_t* bytes);
+mvamg_status mvamg_batch_upload(const mvamg_hier_host* const* hs, int nprob, void* arena_dev, size_t arena_bytes,
+                                void* stream, mvamg_hier** out);
 
 /* Problem count (0 for a single-problem handle) and row offsets
    (nprob + 1 entries, may be NULL). */
@@ -246,11 +310,18 @@ enum {
   MVAMG_KC_COUNT = 7
 };
 
-/* Measurement switch (not needed for solving).  enable != 0: every later
+/* Measurement switch (not needed for solving).  enable 1 or 2: every later
    launch of the classes above carries start/stop HIP events on its stream
-   (graph replay is off meanwhile) and its algorithmic HBM bytes (each stored
-   matrix entry = value + 4-byte index, each vector element touched once) are
-   booked to its class.  Calling it resets the totals. */
+   (graph replay is off meanwhile) and its algorithmic HBM bytes are booked
+   to its class, each vector element touched once and each row's pointer 4
+   bytes, with the matrix data counted as
+     2: the plain model -- every stored entry a value (8 bytes, 4 in the
+        binary32 cycle) and a 4-byte index, the coarsest inverse whole;
+     1: the compact forms the kernels read -- 1-byte value codes and 2-byte
+        column deltas on sliced-ELL levels, one index per shared column-list
+        entry on grouped levels, the lower triangle of the coarsest inverse.
+   enable 0 turns measurement off.  Calling it resets the totals.
+   Errors: MVAMG_ERR_ARG for another enable. */
 mvamg_status mvamg_profile(mvamg_hier* h, int enable);
 
 /* Launch count, summed kernel time (ms) and summed algorithmic bytes of one

@@ -1,8 +1,9 @@
 """Differentiable AMG-PCG solve: x = A(vals)^{-1} b as a torch.autograd.Function.
 
-Forward: the finest-matrix values are loaded into the uploaded hierarchy
-(a near-by matrix with the hierarchy's pattern, whose coarse levels stay as
-built) and A x = b is solved with the preconditioned CG.  Backward: the adjoint
+Forward: A x = b is solved with the preconditioned CG, passing the finest
+matrix's values to the solve (a near-by matrix with the hierarchy's pattern,
+whose coarse levels stay as built; the library takes them where they differ
+from the values in use).  Backward: the adjoint
 system A^T lambda = dL/dx is solved with the same hierarchy (A is symmetric),
 dL/db = lambda and dL/dvals[k] = -lambda_i x_j for the stored entry (i, j).
 All of it runs in the HIP library.
@@ -18,9 +19,8 @@ class AMGSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, vals, b, solver, rtol=1e-10, maxit=1000):
         vals = vals.detach().contiguous()
-        mvamg.set_fine_values(solver.h, vals)
         x = torch.zeros_like(b)
-        info = mvamg.pcg_solve(solver.h, b.detach().contiguous(), x, rtol=rtol, maxit=maxit)
+        info = mvamg.pcg_solve(solver.h, b.detach().contiguous(), x, rtol=rtol, maxit=maxit, A=(None, None, vals))
         if not info.converged:
             raise RuntimeError(f"AMG-PCG did not converge ({info.iterations} iterations, rel. res. {info.rel_res:.2e})")
         ctx.solver, ctx.rtol, ctx.maxit = solver, rtol, maxit
@@ -31,9 +31,9 @@ class AMGSolve(torch.autograd.Function):
     def backward(ctx, gx):
         vals, x = ctx.saved_tensors
         solver = ctx.solver
-        mvamg.set_fine_values(solver.h, vals)
         lam = torch.zeros_like(x)
-        info = mvamg.adjoint_solve(solver.h, gx.contiguous(), lam, rtol=ctx.rtol, maxit=ctx.maxit)
+        info = mvamg.adjoint_solve(solver.h, gx.contiguous(), lam, rtol=ctx.rtol, maxit=ctx.maxit,
+                                   A=(None, None, vals))
         if not info.converged:
             raise RuntimeError("adjoint AMG-PCG did not converge")
         dvals = torch.empty_like(vals)

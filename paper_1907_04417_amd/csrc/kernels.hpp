@@ -219,6 +219,64 @@ __global__ __launch_bounds__(kFinish) void k_finish(int nparts, const double* __
   }
 }
 
+// ------------------------------------------- K-cycle inner iterations
+//
+// Two flexible-CG iterations on a coarse level (the K-cycle's coarse
+// correction): NV inner products as block partials, one block adding them in
+// block order, and the two vector updates that read the results.  Scalars of
+// level m live at ks[0..4]: c1.v1, c1.g, then c2.v1, c2.v2, c2.r2.
+
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_kdots(int n, const double* __restrict__ a0, const double* __restrict__ b0,
+                                                  const double* __restrict__ a1, const double* __restrict__ b1,
+                                                  const double* __restrict__ a2, const double* __restrict__ b2,
+                                                  double* __restrict__ part) {
+  __shared__ double lds[4];
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) {
+    s[0] += a0[p] * b0[p];
+    if (NV > 1) s[1] += a1[p] * b1[p];
+    if (NV > 2) s[2] += a2[p] * b2[p];
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double t = block_sum(s[k], lds);
+    if (threadIdx.x == 0) part[k * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// out[k] = sum of the nparts partials of value k, added in block order.
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_kfinish(int nparts, const double* __restrict__ part,
+                                                    double* __restrict__ out) {
+  __shared__ double lds[4];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += kBlock) s += part[k * nparts + i];
+    const double t = block_sum(s, lds);
+    if (threadIdx.x == 0) out[k] = t;
+  }
+}
+
+// r2 = g - alpha1 v1, alpha1 = (c1.g) / (c1.v1)
+__global__ __launch_bounds__(kBlock) void k_kresid(int n, const double* __restrict__ ks, const double* __restrict__ g,
+                                                   const double* __restrict__ v1, double* __restrict__ r2) {
+  const double alpha1 = ks[1] / ks[0];
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) r2[p] = g[p] - alpha1 * v1[p];
+}
+
+// y = alpha1 c1 + alpha2 (c2 - (gamma / rho1) c1): the second direction made
+// A-orthogonal to the first; beta = p2^T A p2 = c2.v2 - gamma^2 / rho1,
+// alpha2 = (c2.r2) / beta.  y may alias c1.
+__global__ __launch_bounds__(kBlock) void k_kcombine(int n, const double* __restrict__ ks, const double* c1,
+                                                     const double* __restrict__ c2, double* y) {
+  const double rho1 = ks[0], alpha1 = ks[1] / rho1, gamma = ks[2];
+  const double beta = ks[3] - gamma * gamma / rho1, alpha2 = ks[4] / beta;
+  const double t1 = alpha1 - alpha2 * gamma / rho1;
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) y[p] = t1 * c1[p] + alpha2 * c2[p];
+}
+
 // ------------------------------------------------------- vector kernels
 
 __global__ __launch_bounds__(kBlock) void k_gather(int n, const int* __restrict__ perm,
@@ -1140,6 +1198,17 @@ __global__ __launch_bounds__(kBlock) void k_symv_sum(int n, int nt, const double
 }
 
 // ------------------------------------------------- values, casts, gradient
+
+// flag[0] = 1 if a and b differ in any of their n entries (several threads
+// may store the same 1).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_differs(int64_t n, const T* __restrict__ a, const T* __restrict__ b,
+                                                    int* __restrict__ flag) {
+  bool d = false;
+  for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock)
+    d |= (a[e] != b[e]);
+  if (d) flag[0] = 1;
+}
 
 // dst[e] = src_idx[e] >= 0 ? val[src_idx[e]] : 0 (layout fill from file-order values)
 __global__ __launch_bounds__(kBlock) void k_fill_values(int64_t m, const int* __restrict__ src,

@@ -26,6 +26,8 @@ constexpr GemmVariant kGemmVariants[] = {{0, 0, 1}, {1, 16, 1}, {1, 4, 2}, {1, 4
 constexpr int kGemmVariantCount = sizeof(kGemmVariants) / sizeof(kGemmVariants[0]);
 constexpr int kGemmDefault = 4;
 constexpr int kGemmMaxSplit = 8;
+// most partial-sum chunks per problem of the batch reductions (autotuned)
+constexpr int kMaxChunks = 64;
 
 // ----------------------------------------------------- work arrays
 
@@ -43,6 +45,7 @@ void ensure_multi(mvamg_hier* h, int nsys, int nparts) {
   M.scal = h->dalloc<double>((size_t)M.nsys * S_NSCAL);
   M.part = h->dalloc<double>(2 * (size_t)M.nsys * M.nparts);
   M.act = h->dalloc<double>(M.nsys);
+  if (h->sizing()) return;
   HIPCHECK(hipHostMalloc((void**)&M.pinned, (size_t)M.nsys * S_NSCAL * sizeof(double), hipHostMallocDefault));
   HIPCHECK(hipHostMalloc((void**)&M.pact, (size_t)M.nsys * sizeof(double), hipHostMallocDefault));
   // graphs captured earlier hold the old addresses
@@ -80,11 +83,41 @@ int bresid_grid(const DevLevel& L, int mode) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, mode == 1 ? kMaxBlockParts : (int64_t)1 << 24));
 }
 
+int block_nparts(const mvamg_hier* h) {
+  int nparts = 2048;
+  for (int l = 0; l + 1 < h->nl; ++l) nparts = std::max(nparts, bresid_grid(h->lv[l], 1));
+  return nparts;
+}
+
+// Bytes of every array ensure_block takes, in the order it takes them.
+std::vector<size_t> block_request(const mvamg_hier* h) {
+  std::vector<size_t> b;
+  for (int l = 0; l < h->nl; ++l) {
+    const size_t m = (size_t)h->lv[l].n * kNB;
+    b.insert(b.end(), {8 * m, 8 * m, 4 * m, 4 * m});
+    if (l + 1 < h->nl) b.insert(b.end(), {8 * m, 4 * m});
+  }
+  const size_t m0 = (size_t)h->n * kNB;
+  b.insert(b.end(), {8 * m0, 8 * m0, 8 * m0, 8 * m0});
+  b.insert(b.end(), {8 * (size_t)h->co.n * kNB, 8 * (size_t)h->co.n * kNB, 8 * (size_t)kGemmMaxSplit * h->co.n * kNB});
+  const MultiBufs& M = h->mb;
+  if (M.nsys < kNB || M.nparts < block_nparts(h)) {
+    const size_t nsys = std::max(M.nsys, kNB), np = std::max(M.nparts, block_nparts(h));
+    b.insert(b.end(), {8 * nsys * S_NSCAL, 16 * nsys * np, 8 * nsys});
+  }
+  return b;
+}
+
+// Whether the arena still has room for the block work space.
+bool block_fits(const mvamg_hier* h) { return h->blk_ready || h->fits(block_request(h)); }
+
 void ensure_block(mvamg_hier* h) {
   if (h->blk_ready) return;
   if (h->nprob > 0) throw Error(MVAMG_ERR_ARG, "block right-hand sides are not supported on a batch of problems");
   for (int l = 0; l < h->nl; ++l)
     if ((int64_t)h->lev_n[l] * kNB >= ((int64_t)1 << 31)) throw Error(MVAMG_ERR_ARG, "level too large for 32-column blocks");
+  if (!block_fits(h))
+    throw Error(MVAMG_ERR_ARG, "the arena has no room for the block work space (size it with nrhs > 1)");
   for (int l = 0; l < h->nl; ++l) {
     DevLevel& L = h->lv[l];
     const size_t m = (size_t)L.n * kNB;
@@ -105,9 +138,7 @@ void ensure_block(mvamg_hier* h) {
   h->co.br = h->dalloc<double>((size_t)h->co.n * kNB);
   h->co.bz = h->dalloc<double>((size_t)h->co.n * kNB);
   h->co.bsplit = h->dalloc<double>((size_t)kGemmMaxSplit * h->co.n * kNB);
-  int nparts = 2048;
-  for (int l = 0; l + 1 < h->nl; ++l) nparts = std::max(nparts, bresid_grid(h->lv[l], 1));
-  ensure_multi(h, kNB, nparts);
+  ensure_multi(h, kNB, block_nparts(h));
   h->blk_ready = true;
 }
 
@@ -162,7 +193,7 @@ template <typename T, int MODE>
 void bresid(mvamg_hier* h, const DevLevel& L, const T* r, const T* x, T* s, int mode, hipStream_t st, int nst = -1) {
   const int kc = MODE != 0 ? MVAMG_KC_SPMV : MVAMG_KC_RESIDUAL;
   const bool part_rows = MODE == 0 && nst >= 0 && nst < L.ns;
-  const double by = part_rows ? resid_stage_bytes<T>(L, nst, 3.0 * kNB * sizeof(T), false)
+  const double by = part_rows ? resid_stage_bytes<T>(h, L, nst, 3.0 * kNB * sizeof(T), false)
                               : (double)L.nnz * (sizeof(T) + 4) + 4.0 * (L.n + 1) +
                                     (double)L.n * kNB * sizeof(T) * (MODE != 0 ? 2 : 3);
   int grid = bresid_grid(L, MODE);

@@ -110,6 +110,10 @@ struct DevLevel {
   // batch, level 0: problem of every slab and of every row (smoother order)
   int* slabprob = nullptr;
   int* rowprob = nullptr;
+  // K-cycle, levels 1 .. nl - 2 (binary64): the inner iterations' vectors
+  // (A c1, the second residual, the second direction c2 and A c2; c1 is x)
+  // and their five scalars
+  double *kv1 = nullptr, *kr2 = nullptr, *kc2 = nullptr, *kv2 = nullptr, *ks = nullptr;
   // block work vectors (n x 32, allocated on the first block call)
   double *br = nullptr, *bx = nullptr, *bs = nullptr;
   float *br32 = nullptr, *bx32 = nullptr, *bs32 = nullptr;
@@ -182,6 +186,8 @@ struct mvamg_hier {
   int* perm0 = nullptr;  // level-0 new -> file index
   int* frp = nullptr;    // file CSR pattern of level 0
   int* fci = nullptr;
+  double* fval = nullptr;  // the level-0 values in use, file CSR order
+  int* cmpflag = nullptr;  // two flags of the matrix check (pattern, values)
   // CG vectors (binary64, level-0 smoother order)
   double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   double* scal = nullptr;
@@ -210,6 +216,11 @@ struct mvamg_hier {
   bool use_graphs = true;
   // measurement: per-launch HIP events for every instrumented kernel
   bool prof = false;
+  // byte booking while measuring: false, the compact forms the kernels read
+  // (value codes, 2-byte column deltas, shared group lists); true, the plain
+  // model (every stored entry a value and a 4-byte index, the coarsest
+  // inverse whole)
+  bool book_plain = false;
   std::vector<hipEvent_t> ev_pool;
   struct Pending {
     int kc;
@@ -219,28 +230,54 @@ struct mvamg_hier {
   std::vector<Pending> pending;
   int64_t kc_launches[MVAMG_KC_COUNT] = {};
   double kc_ms[MVAMG_KC_COUNT] = {}, kc_bytes[MVAMG_KC_COUNT] = {};
-  std::vector<void*> allocs;
+  // Device memory: every array lives in the caller's arena (mvamg_upload).
+  // Allocation bumps an offset; a release of the newest live arrays gives
+  // their space back (the coarsest factorisation's temporaries).  With no
+  // arena base the handle only sizes: nothing touches the device, and
+  // arena_peak ends as the bytes an arena needs.
+  unsigned char* arena = nullptr;
+  size_t arena_cap = 0, arena_top = 0, arena_peak = 0;
+  struct Live {
+    size_t off, end;
+    bool freed;
+  };
+  std::vector<Live> live;
+  bool sizing() const { return arena == nullptr; }
+  // while sizing, addresses start at a non-null value that nothing dereferences
+  uintptr_t arena_base() const { return sizing() ? (uintptr_t)4096 : reinterpret_cast<uintptr_t>(arena); }
 
   template <typename T>
   T* dalloc(size_t count) {
-    void* ptr = nullptr;
     if (count == 0) count = 1;
-    HIPCHECK(hipMalloc(&ptr, count * sizeof(T)));
-    allocs.push_back(ptr);
-    return (T*)ptr;
+    const size_t off = (arena_top + 255) / 256 * 256, end = off + count * sizeof(T);
+    if (!sizing() && end > arena_cap)
+      throw Error(MVAMG_ERR_ARG, "device arena of " + std::to_string(arena_cap) +
+                                     " bytes is too small for this handle (size it with mvamg_arena_bytes)");
+    arena_top = end;
+    arena_peak = std::max(arena_peak, end);
+    live.push_back({off, end, false});
+    // while sizing, a distinct non-null address that nothing dereferences
+    return reinterpret_cast<T*>(arena_base() + off);
   }
   void dfree(void* ptr) {
-    for (auto it = allocs.begin(); it != allocs.end(); ++it)
-      if (*it == ptr) {
-        (void)hipFree(ptr);
-        allocs.erase(it);
-        return;
-      }
+    const size_t off = (size_t)(reinterpret_cast<uintptr_t>(ptr) - arena_base());
+    for (auto& a : live)
+      if (a.off == off && !a.freed) a.freed = true;
+    while (!live.empty() && live.back().freed) live.pop_back();
+    arena_top = live.empty() ? 0 : live.back().end;
+  }
+  // whether arrays of these byte counts, taken in order, fit the arena
+  bool fits(const std::vector<size_t>& bytes) const {
+    if (sizing()) return true;
+    size_t top = arena_top;
+    for (size_t b : bytes) top = (top + 255) / 256 * 256 + std::max<size_t>(b, 1);
+    return top <= arena_cap;
   }
   template <typename T>
   T* upload_vec(const std::vector<T>& v, hipStream_t st) {
     T* d = dalloc<T>(v.size());
-    if (!v.empty()) HIPCHECK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    if (!v.empty() && !sizing())
+      HIPCHECK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
     return d;
   }
   ~mvamg_hier() {
@@ -251,7 +288,6 @@ struct mvamg_hier {
     }
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
     if (cap) (void)hipStreamDestroy(cap);
-    for (void* p : allocs) (void)hipFree(p);
     if (pinned) (void)hipHostFree(pinned);
     if (mb.pinned) (void)hipHostFree(mb.pinned);
     if (mb.pact) (void)hipHostFree(mb.pact);
@@ -365,7 +401,8 @@ SellVals<T> svals(const DevLevel& L) {
 // nnz entries (nnz16 of them off-diagonal with 2-byte indices) of a
 // sliced-ELL level: values or codes, indices, diagonal.
 template <typename T>
-double sell_mat_bytes(const DevLevel& L, double nnz, double rows, double nnz16) {
+double sell_mat_bytes(const mvamg_hier* h, const DevLevel& L, double nnz, double rows, double nnz16) {
+  if (h->book_plain) return nnz * (sizeof(T) + 4.0);
   const double vb = L.vcoded ? 1.0 : sizeof(T), db = L.dcoded ? 1.0 : sizeof(T);
   return (nnz - rows) * (vb + 4.0) - 2.0 * nnz16 + rows * db;
 }
@@ -437,16 +474,17 @@ float* ls<float>(DevLevel& L) {
 // Column index bytes the single-vector kernels read for stage c: 4 or 2
 // (16-bit slabs) per entry on point levels, 4 per stored list entry on
 // grouped levels.
-double stage_idx_bytes(const DevLevel& L, int c) {
+double stage_idx_bytes(const mvamg_hier* h, const DevLevel& L, int c) {
+  if (h->book_plain) return 4.0 * L.stage_nnz[c];
   return L.sell ? 4.0 * L.stage_nnz[c] - 2.0 * L.stage_nnz16[c] : 4.0 * L.stage_gidx[c];
 }
 
 template <typename T>
-double stage_bytes(const DevLevel& L, int c) {
+double stage_bytes(const mvamg_hier* h, const DevLevel& L, int c) {
   if (L.sell)
-    return sell_mat_bytes<T>(L, L.stage_nnz[c], L.stage_rows[c], L.stage_nnz16[c]) +
+    return sell_mat_bytes<T>(h, L, L.stage_nnz[c], L.stage_rows[c], L.stage_nnz16[c]) +
            (double)L.stage_rows[c] * (4 + 2 * sizeof(T));
-  return (double)L.stage_nnz[c] * sizeof(T) + stage_idx_bytes(L, c) + (double)L.stage_rows[c] * (4 + 3 * sizeof(T));
+  return (double)L.stage_nnz[c] * sizeof(T) + stage_idx_bytes(h, L, c) + (double)L.stage_rows[c] * (4 + 3 * sizeof(T));
 }
 
 SellCols scols(const DevLevel& L) { return SellCols{L.col, L.col16, L.cbase, L.scb, L.pk}; }
@@ -460,9 +498,12 @@ int gs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x, i
              bool first_sweep = false, double* dot_part = nullptr) {
   const int kc = (l == 0) ? MVAMG_KC_SMOOTH_FINE : MVAMG_KC_SMOOTH_COARSE;
   const bool gfirst = first_sweep && !L.sell && !backward;
-  const double by = skip_bytes(h, l, stage_bytes<T>(L, c) - (gfirst ? (double)L.stage_later[c] * sizeof(T) +
-                                                                           4.0 * L.stage_later_idx[c]
-                                                                     : 0.0));
+  // entries of later stages, not read by a grouped level's forward sweep from
+  // zero (stage_later and stage_later_idx exist on grouped levels only)
+  const double later = gfirst ? (double)L.stage_later[c] * sizeof(T) +
+                                    4.0 * (h->book_plain ? (double)L.stage_later[c] : (double)L.stage_later_idx[c])
+                              : 0.0;
+  const double by = skip_bytes(h, l, stage_bytes<T>(h, L, c) - later);
   if (L.sell) {
     const int s0 = L.h_sslab[c], s1 = L.h_sslab[c + 1];
     if (s1 <= s0) return 0;
@@ -508,7 +549,7 @@ template <typename T>
 void zero_stage0(mvamg_hier* h, int l, const DevLevel& L, const T* r, T* x, hipStream_t st) {
   const int kc = (l == 0) ? MVAMG_KC_SMOOTH_FINE : MVAMG_KC_SMOOTH_COARSE;
   if (L.sell) {
-    const double by = skip_bytes(h, l, (double)L.rows0 * (2 * sizeof(T) + (L.dcoded ? 1 : sizeof(T))));
+    const double by = skip_bytes(h, l, (double)L.rows0 * (2 * sizeof(T) + (L.dcoded && !h->book_plain ? 1 : sizeof(T))));
     klaunch(h, kc, by, k_stage0_point<T>, grid_elem(L.rows0), kBlock, st, L.rows0, svals<T>(L), r, x,
             lskip(h, l, SKIP_ROW));
   } else {
@@ -524,13 +565,14 @@ int resid_grid(const DevLevel& L);
 // kernels read the compact index forms (16-bit slab entries, shared group
 // lists), not 4 bytes per entry.
 template <typename T>
-double resid_stage_bytes(const DevLevel& L, int nst, double vec_bytes, bool compact) {
+double resid_stage_bytes(const mvamg_hier* h, const DevLevel& L, int nst, double vec_bytes, bool compact) {
+  compact = compact && !h->book_plain;
   double b = 0.0;
   for (int c = 0; c < nst; ++c)
     b += (compact && L.sell)
-             ? sell_mat_bytes<T>(L, L.stage_nnz[c], L.stage_rows[c], L.stage_nnz16[c]) +
+             ? sell_mat_bytes<T>(h, L, L.stage_nnz[c], L.stage_rows[c], L.stage_nnz16[c]) +
                    (double)L.stage_rows[c] * (4 + vec_bytes)
-             : (double)L.stage_nnz[c] * sizeof(T) + (compact ? stage_idx_bytes(L, c) : 4.0 * L.stage_nnz[c]) +
+             : (double)L.stage_nnz[c] * sizeof(T) + (compact ? stage_idx_bytes(h, L, c) : 4.0 * L.stage_nnz[c]) +
                    (double)L.stage_rows[c] * (4 + vec_bytes);
   return b;
 }
@@ -542,11 +584,13 @@ template <typename T, int MODE>
 void resid(mvamg_hier* h, int l, const DevLevel& L, const T* r, const T* x, T* s, int mode, hipStream_t st,
            int nst = -1) {
   const Red red = mkred(h);
-  const int kc = MODE != 0 ? MVAMG_KC_SPMV : MVAMG_KC_RESIDUAL;
+  // the CG product is the finest level's; products inside a cycle are residual work
+  const int kc = (MODE != 0 && l == 0) ? MVAMG_KC_SPMV : MVAMG_KC_RESIDUAL;
   const bool part = MODE == 0 && nst >= 0 && nst < L.ns;
-  const double by = skip_bytes(h, l, part ? resid_stage_bytes<T>(L, nst, 3.0 * sizeof(T), true)
-                                          : (L.sell ? sell_mat_bytes<T>(L, L.nnz, L.n, L.nnz16)
-                                                    : (double)L.nnz * sizeof(T) + 4.0 * L.gidx) +
+  const double by = skip_bytes(h, l, part ? resid_stage_bytes<T>(h, L, nst, 3.0 * sizeof(T), true)
+                                          : (L.sell ? sell_mat_bytes<T>(h, L, L.nnz, L.n, L.nnz16)
+                                                    : (double)L.nnz * sizeof(T) +
+                                                          4.0 * (h->book_plain ? (double)L.nnz : (double)L.gidx)) +
                                                 4.0 * (L.n + 1) +
                                                 (double)L.n * sizeof(T) * (MODE != 0 ? 2 : 3));
   if (L.sell) {
@@ -589,7 +633,8 @@ void coarse_solve<double>(mvamg_hier* h, const double* r, double* z, hipStream_t
   if (C.nb == 1) {
     // algorithmic bytes: the inverse's lower triangle and the two vectors,
     // booked to the tile pass; the slot sums are overhead of the split
-    klaunch(h, MVAMG_KC_COARSE, 4.0 * C.n * (C.n + 1.0) + 16.0 * C.n, k_symv_tiles, C.ntiles, kBlock, st, C.n,
+    klaunch(h, MVAMG_KC_COARSE, (h->book_plain ? 8.0 * C.n * (double)C.n : 4.0 * C.n * (C.n + 1.0)) + 16.0 * C.n,
+            k_symv_tiles, C.ntiles, kBlock, st, C.n,
             C.nt, (const int2*)C.tij, (const double*)C.tiles, r, C.spart);
     klaunch(h, MVAMG_KC_COARSE, 0.0, k_symv_sum, C.nt, kBlock, st, C.n, C.nt, (const double*)C.spart, z);
   } else
@@ -615,8 +660,14 @@ void coarse_solve<float>(mvamg_hier* h, const float* r, float* z, hipStream_t st
 // of x.r (binary64 sliced-ELL level, Gauss-Seidel); their count goes to
 // h->dot_nparts.
 template <typename T>
+void kc_fcg2(mvamg_hier* h, int m, const T* g, T* y, int smoother, hipStream_t st, bool y_started);
+
+// kcyc: the K-cycle -- the coarse correction on a level that is not the
+// coarsest is two flexible-CG iterations preconditioned by the K-cycle of
+// that level (kc_fcg2), not one recursive cycle.
+template <typename T>
 void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st, bool x_started = false,
-            double* dot_part = nullptr, bool stage0_written = false) {
+            double* dot_part = nullptr, bool stage0_written = false, bool kcyc = false) {
   if (l == h->nl - 1) {
     coarse_solve<T>(h, r, x, st);
     return;
@@ -682,7 +733,10 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
 #undef MVAMG_RESTRICT_L
 #undef MVAMG_RESTRICT
   LAUNCHCHECK("restrict");
-  vcycle<T>(h, l + 1, rc, xc, smoother, st, next_smoothed);
+  if (kcyc && next_smoothed)
+    kc_fcg2<T>(h, l + 1, rc, xc, smoother, st, true);
+  else
+    vcycle<T>(h, l + 1, rc, xc, smoother, st, next_smoothed, nullptr, false, kcyc);
   {
     const bool gs = smoother == MVAMG_SMOOTH_GS;
     const int nr = gs ? P.ncut : P.nf;
@@ -711,9 +765,42 @@ void vcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st
   LAUNCHCHECK("vcycle");
 }
 
-// z = B r for level-0 binary64 vectors in smoother order
-void apply_B(mvamg_hier* h, const double* r, double* z, int precision, int smoother, hipStream_t st) {
-  if (precision == 64) {
+// y ~ A_m^{-1} g: two flexible-CG iterations from y = 0 on level m (not the
+// finest, not the coarsest), each preconditioned by the K-cycle of level m.
+// y is the level's x vector (c1 is built there); y_started: the restriction
+// that produced g has already taken the first smoothing step of c1.
+template <>
+void kc_fcg2<double>(mvamg_hier* h, int m, const double* g, double* y, int smoother, hipStream_t st, bool y_started) {
+  DevLevel& L = h->lv[m];
+  const int n = L.n, grid = std::min(grid_for(n), 512);
+  // c1 = K g, v1 = A c1, (c1.v1, c1.g), r2 = g - alpha1 v1
+  vcycle<double>(h, m, g, y, smoother, st, y_started, nullptr, false, true);
+  resid<double, 2>(h, m, L, nullptr, y, L.kv1, M_NONE, st);
+  k_kdots<2><<<grid, kBlock, 0, st>>>(n, y, L.kv1, y, g, nullptr, nullptr, h->part);
+  k_kfinish<2><<<1, kBlock, 0, st>>>(grid, h->part, L.ks);
+  k_kresid<<<grid_elem(n), kBlock, 0, st>>>(n, L.ks, g, L.kv1, L.kr2);
+  // c2 = K r2, v2 = A c2, (c2.v1, c2.v2, c2.r2), y = combination of c1, c2
+  vcycle<double>(h, m, L.kr2, L.kc2, smoother, st, false, nullptr, false, true);
+  resid<double, 2>(h, m, L, nullptr, L.kc2, L.kv2, M_NONE, st);
+  k_kdots<3><<<grid, kBlock, 0, st>>>(n, L.kc2, L.kv1, L.kc2, L.kv2, L.kc2, L.kr2, h->part);
+  k_kfinish<3><<<1, kBlock, 0, st>>>(grid, h->part, L.ks + 2);
+  k_kcombine<<<grid_elem(n), kBlock, 0, st>>>(n, L.ks, y, L.kc2, y);
+  LAUNCHCHECK("kc_fcg2");
+}
+
+template <>
+void kc_fcg2<float>(mvamg_hier*, int, const float*, float*, int, hipStream_t, bool) {
+  throw Error(MVAMG_ERR_ARG, "the K-cycle runs in binary64 only");
+}
+
+// z = B r for level-0 binary64 vectors in smoother order (the K-cycle when
+// cycle is MVAMG_CYCLE_K)
+void apply_B(mvamg_hier* h, const double* r, double* z, int precision, int smoother, hipStream_t st,
+             int cycle = MVAMG_CYCLE_V) {
+  if (cycle == MVAMG_CYCLE_K) {
+    if (precision != 64) throw Error(MVAMG_ERR_ARG, "the K-cycle runs in binary64 only");
+    vcycle<double>(h, 0, r, z, smoother, st, false, nullptr, false, true);
+  } else if (precision == 64) {
     vcycle<double>(h, 0, r, z, smoother, st);
   } else {
     DevLevel& L = h->lv[0];
@@ -796,17 +883,18 @@ void cg_step_a(mvamg_hier* h, hipStream_t st, bool stage0) {
 // sweep writes the partials of z.r itself.
 // The binary64 Gauss-Seidel cycle on a sliced-ELL fine level: its first
 // sweep stage comes with the preceding CG update (cg_step_a).
-bool fused_cycle(const mvamg_hier* h, int precision, int smoother) {
-  return precision == 64 && smoother == MVAMG_SMOOTH_GS && h->nl > 1 && h->lv[0].sell;
+bool fused_cycle(const mvamg_hier* h, int precision, int smoother, int cycle) {
+  return precision == 64 && smoother == MVAMG_SMOOTH_GS && cycle == MVAMG_CYCLE_V && h->nl > 1 && h->lv[0].sell;
 }
 
-void cg_step_b(mvamg_hier* h, int precision, int smoother, hipStream_t st) {
+void cg_step_b(mvamg_hier* h, int precision, int smoother, int cycle, hipStream_t st) {
   const int n = h->n, eg = grid_for(n);
-  if (fused_cycle(h, precision, smoother)) {
+  if (fused_cycle(h, precision, smoother, cycle)) {
     vcycle<double>(h, 0, h->r, h->z, smoother, st, false, h->part, true);
     finish(h, 1, h->dot_nparts, M_RZ, st);
-  } else if (precision == 32) {
-    apply_B(h, h->r, h->z, precision, smoother, st);
+  } else if (precision == 32 || cycle == MVAMG_CYCLE_K) {
+    // a preconditioner that is not a fixed symmetric operator: flexible beta
+    apply_B(h, h->r, h->z, precision, smoother, st, cycle);
     k_dot<2><<<eg, kBlock, 0, st>>>(n, h->z, h->r, h->z, h->q, mkred(h));
     finish(h, 2, eg, M_RZ_FLEX, st);
   } else {
@@ -820,16 +908,16 @@ void cg_step_b(mvamg_hier* h, int precision, int smoother, hipStream_t st) {
 
 // One full iteration (B then A) captured once as a HIP graph and replayed:
 // about 60 kernels and one copy per launch instead of as many host launches.
-hipGraphExec_t iteration_graph(mvamg_hier* h, int precision, int smoother) {
-  const int key = precision * 4 + smoother;
+hipGraphExec_t iteration_graph(mvamg_hier* h, int precision, int smoother, int cycle) {
+  const int key = (precision * 4 + smoother) * 2 + cycle;
   auto it = h->graphs.find(key);
   if (it != h->graphs.end()) return it->second;
   if (!h->cap) HIPCHECK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
   hipGraph_t g = nullptr;
   HIPCHECK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
   try {
-    cg_step_b(h, precision, smoother, h->cap);
-    cg_step_a(h, h->cap, fused_cycle(h, precision, smoother));
+    cg_step_b(h, precision, smoother, cycle, h->cap);
+    cg_step_a(h, h->cap, fused_cycle(h, precision, smoother, cycle));
   } catch (...) {
     (void)hipStreamEndCapture(h->cap, &g);
     if (g) (void)hipGraphDestroy(g);
@@ -844,6 +932,44 @@ hipGraphExec_t iteration_graph(mvamg_hier* h, int precision, int smoother) {
   return ge;
 }
 
+// Captured iteration graphs are rebuilt on the next solve.
+void drop_graphs(mvamg_hier* h) {
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.second);
+  h->graphs.clear();
+}
+
+// Level-0 values replaced by val (file CSR order, nnz entries): a near-by
+// matrix with the hierarchy's pattern.  Drops the value codes (the kernels
+// read the values from now on) and the captured iterations that hold them.
+void refill_fine(mvamg_hier* h, const double* val, hipStream_t st) {
+  const bool coded = h->lv[0].vcoded || h->lv[0].dcoded;
+  fill_level_values(h, 0, val, st);
+  derive_level(h, 0, st);
+  k_copy<double><<<grid_for(h->nnz), kBlock, 0, st>>>((int)h->nnz, val, h->fval);
+  LAUNCHCHECK("refill_fine");
+  if (coded) drop_graphs(h);
+}
+
+// The matrix a solve is asked for.  rowptr/col (both or neither): checked
+// against the hierarchy's level-0 pattern; val: compared with the values in
+// use and, where any differs, taken as the new level-0 values.
+void use_matrix(mvamg_hier* h, const int* rowptr, const int* col, const double* val, hipStream_t st) {
+  if ((rowptr == nullptr) != (col == nullptr)) throw Error(MVAMG_ERR_ARG, "rowptr and col are passed together");
+  if (!rowptr && !val) return;
+  k_fill<int><<<1, kBlock, 0, st>>>(2, 0, h->cmpflag);
+  if (rowptr) {
+    k_differs<int><<<grid_for(h->n + 1), kBlock, 0, st>>>(h->n + 1, rowptr, h->frp, h->cmpflag);
+    k_differs<int><<<grid_for(h->nnz), kBlock, 0, st>>>(h->nnz, col, h->fci, h->cmpflag);
+  }
+  if (val) k_differs<double><<<grid_for(h->nnz), kBlock, 0, st>>>(h->nnz, val, h->fval, h->cmpflag + 1);
+  LAUNCHCHECK("use_matrix");
+  int flags[2] = {0, 0};
+  HIPCHECK(hipMemcpyAsync(flags, h->cmpflag, sizeof(flags), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  if (flags[0]) throw Error(MVAMG_ERR_ARG, "matrix pattern differs from the hierarchy's finest level");
+  if (flags[1]) refill_fine(h, val, st);
+}
+
 // Core CG loop shared by solve and adjoint solve.
 mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvamg_solve_params* prm,
                  mvamg_info* info, hipStream_t st) {
@@ -851,6 +977,9 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
   if (prm->precision != 64 && prm->precision != 32) throw Error(MVAMG_ERR_ARG, "precision must be 64 or 32");
   if (prm->smoother != MVAMG_SMOOTH_GS && prm->smoother != MVAMG_SMOOTH_L1JACOBI)
     throw Error(MVAMG_ERR_ARG, "unknown smoother");
+  if (prm->cycle != MVAMG_CYCLE_V && prm->cycle != MVAMG_CYCLE_K) throw Error(MVAMG_ERR_ARG, "unknown cycle");
+  if (prm->cycle == MVAMG_CYCLE_K && prm->precision != 64)
+    throw Error(MVAMG_ERR_ARG, "the K-cycle runs in binary64 only");
   if (prm->maxit < 0 || !(prm->rtol >= 0.0)) throw Error(MVAMG_ERR_ARG, "invalid maxit or rtol");
   if (h->nprob > 0) throw Error(MVAMG_ERR_ARG, "a batch handle is solved with mvamg_batch_pcg_solve");
   check_device(h);
@@ -884,21 +1013,22 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
         resid<double, 0>(h, 0, L0, h->b, h->x, h->r, M_NONE, st);
         inf.restarts = restart;
       }
-      apply_B(h, h->r, h->z, prm->precision, prm->smoother, st);
+      apply_B(h, h->r, h->z, prm->precision, prm->smoother, st, prm->cycle);
       dot(h, h->r, h->z, M_RHO0, st);
       k_copy<double><<<eg, kBlock, 0, st>>>(n, h->z, h->p);
       bool met = false;
-      hipGraphExec_t ge = (h->use_graphs && !h->prof) ? iteration_graph(h, prm->precision, prm->smoother) : nullptr;
+      hipGraphExec_t ge =
+          (h->use_graphs && !h->prof) ? iteration_graph(h, prm->precision, prm->smoother, prm->cycle) : nullptr;
       bool first = true;
       while (it < prm->maxit) {
         if (first) {
-          cg_step_a(h, st, fused_cycle(h, prm->precision, prm->smoother));
+          cg_step_a(h, st, fused_cycle(h, prm->precision, prm->smoother, prm->cycle));
           first = false;
         } else if (ge) {
           HIPCHECK(hipGraphLaunch(ge, st));
         } else {
-          cg_step_b(h, prm->precision, prm->smoother, st);
-          cg_step_a(h, st, fused_cycle(h, prm->precision, prm->smoother));
+          cg_step_b(h, prm->precision, prm->smoother, prm->cycle, st);
+          cg_step_a(h, st, fused_cycle(h, prm->precision, prm->smoother, prm->cycle));
         }
         HIPCHECK(hipStreamSynchronize(st));
         ++it;
@@ -979,13 +1109,20 @@ void factor_block(mvamg_hier* h, const HostLevel& C, int np, double* M, double* 
 
 // Device copy of a hierarchy; cblk lists the diagonal blocks of its
 // coarsest level (one for a single problem, one per problem of a batch).
+// arena: the caller's device buffer of arena_cap bytes, or null to size
+// only (no device work; h->arena_peak is then the bytes an arena needs).
 std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<const HostLevel*>& cblk, hipStream_t st,
-                                        const std::vector<int>* rowprob0 = nullptr) {
+                                        const std::vector<int>* rowprob0, void* arena, size_t arena_cap) {
   std::unique_ptr<mvamg_hier> h;
   try {
     if (H.nl < 2) throw Error(MVAMG_ERR_ARG, "hierarchy needs at least two levels");
+    if (arena && reinterpret_cast<uintptr_t>(arena) % 256 != 0)
+      throw Error(MVAMG_ERR_ARG, "device arena must be 256-byte aligned");
     h.reset(new mvamg_hier);
-    HIPCHECK(hipGetDevice(&h->device));
+    h->arena = (unsigned char*)arena;
+    h->arena_cap = arena_cap;
+    const bool dev = !h->sizing();
+    if (dev) HIPCHECK(hipGetDevice(&h->device));
     {
       const char* ev = std::getenv("MVAMG_NO_GRAPH");
       h->use_graphs = !(ev && ev[0] && ev[0] != '0');
@@ -1100,6 +1237,11 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
       if (l > 0) {
         L.r = h->dalloc<double>(y.n);
         L.x = h->dalloc<double>(y.n);
+        L.kv1 = h->dalloc<double>(y.n);
+        L.kr2 = h->dalloc<double>(y.n);
+        L.kc2 = h->dalloc<double>(y.n);
+        L.kv2 = h->dalloc<double>(y.n);
+        L.ks = h->dalloc<double>(8);
       }
       maxgrid = std::max(maxgrid, resid_grid(L));
     }
@@ -1139,8 +1281,10 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
       }
       P.U = h->upload_vec(T.U, st);
       P.U32 = h->dalloc<float>(T.U.size());
-      k_to_f32<<<grid_for((int64_t)T.U.size()), kBlock, 0, st>>>((int64_t)T.U.size(), P.U, P.U32);
-      LAUNCHCHECK("U32");
+      if (dev) {
+        k_to_f32<<<grid_for((int64_t)T.U.size()), kBlock, 0, st>>>((int64_t)T.U.size(), P.U, P.U32);
+        LAUNCHCHECK("U32");
+      }
       {
         // row-order copy of P for the prolongation
         const int nf = H.lv[l].n;
@@ -1169,8 +1313,10 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
         P.cinfo = h->upload_vec(cinfo, st);
         P.Urow = h->upload_vec(urow, st);
         P.Urow32 = h->dalloc<float>(urow.size());
-        k_to_f32<<<grid_for((int64_t)urow.size()), kBlock, 0, st>>>((int64_t)urow.size(), P.Urow, P.Urow32);
-        LAUNCHCHECK("Urow32");
+        if (dev) {
+          k_to_f32<<<grid_for((int64_t)urow.size()), kBlock, 0, st>>>((int64_t)urow.size(), P.Urow, P.Urow32);
+          LAUNCHCHECK("Urow32");
+        }
       }
     }
     // ---- coarsest level: blocked dense Cholesky and inverse of every diagonal block
@@ -1206,17 +1352,29 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
       double* M = h->dalloc<double>((size_t)npmax * npmax);
       double* Li = h->dalloc<double>((size_t)npmax * npmax);
       int* flag = h->dalloc<int>(1);
-      HIPCHECK(hipMemsetAsync(flag, 0, sizeof(int), st));
       std::vector<void*> temps;
-      for (int bk = 0; bk < D.nb; ++bk) factor_block(h.get(), *cblk[bk], cnp[bk], M, Li, D.Ainv + aoff[bk], flag, temps, st);
-      LAUNCHCHECK("coarsest factorisation");
-      int hflag = 0;
-      HIPCHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-      HIPCHECK(hipStreamSynchronize(st));
-      if (hflag) throw Error(MVAMG_ERR_NOT_SPD, "coarsest matrix is not positive definite (Cholesky pivot <= 0)");
-      h->dfree(M);
+      if (dev) {
+        k_fill<int><<<1, kBlock, 0, st>>>(1, 0, flag);
+        for (int bk = 0; bk < D.nb; ++bk)
+          factor_block(h.get(), *cblk[bk], cnp[bk], M, Li, D.Ainv + aoff[bk], flag, temps, st);
+        LAUNCHCHECK("coarsest factorisation");
+        int hflag = 0;
+        HIPCHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        if (hflag) throw Error(MVAMG_ERR_NOT_SPD, "coarsest matrix is not positive definite (Cholesky pivot <= 0)");
+      } else {
+        // the temporaries factor_block takes: the block's CSR arrays
+        for (int bk = 0; bk < D.nb; ++bk) {
+          temps.push_back(h->dalloc<int>(cblk[bk]->rp.size()));
+          temps.push_back(h->dalloc<int>(cblk[bk]->ci.size()));
+          temps.push_back(h->dalloc<double>(cblk[bk]->v.size()));
+        }
+      }
+      // released newest first, so their space is reused by what follows
+      for (auto it = temps.rbegin(); it != temps.rend(); ++it) h->dfree(*it);
+      h->dfree(flag);
       h->dfree(Li);
-      for (void* t : temps) h->dfree(t);
+      h->dfree(M);
       if (D.nb == 1) {
         D.nt = D.np / 64;
         D.ntiles = D.nt * (D.nt + 1) / 2;
@@ -1230,8 +1388,10 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
         D.tij = reinterpret_cast<int2*>(h->upload_vec(tij, st));
         D.tiles = h->dalloc<double>((size_t)D.ntiles * 4096);
         D.spart = h->dalloc<double>((size_t)D.nt * D.nt * 64);
-        k_pack_tiles<<<D.ntiles, kBlock, 0, st>>>(D.n, D.np, D.tij, D.Ainv, D.tiles);
-        LAUNCHCHECK("pack_tiles");
+        if (dev) {
+          k_pack_tiles<<<D.ntiles, kBlock, 0, st>>>(D.n, D.np, D.tij, D.Ainv, D.tiles);
+          LAUNCHCHECK("pack_tiles");
+        }
       }
       if (D.nb > 1) {
         std::vector<int> cprob(C.n);
@@ -1267,6 +1427,8 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
       h->iperm0 = h->upload_vec(Y[0].iperm, st);
       h->frp = h->upload_vec(H.lv[0].rp, st);
       h->fci = h->upload_vec(H.lv[0].ci, st);
+      h->fval = h->upload_vec(H.lv[0].v, st);
+      h->cmpflag = h->dalloc<int>(2);
       h->b = h->dalloc<double>(n);
       h->x = h->dalloc<double>(n);
       h->r = h->dalloc<double>(n);
@@ -1288,13 +1450,17 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
         }
         h->part = h->dalloc<double>((size_t)cap);
       }
-      HIPCHECK(hipMemsetAsync(h->scal, 0, S_NSCAL * sizeof(double), st));
-      // mapped and coherent: a finisher kernel writes it, the host reads it after the stream
-      HIPCHECK(hipHostMalloc((void**)&h->pinned, S_NSCAL * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
-      HIPCHECK(hipHostGetDevicePointer((void**)&h->pinned_dev, h->pinned, 0));
+      if (dev) {
+        HIPCHECK(hipMemsetAsync(h->scal, 0, S_NSCAL * sizeof(double), st));
+        // mapped and coherent: a finisher kernel writes it, the host reads it after the stream
+        HIPCHECK(hipHostMalloc((void**)&h->pinned, S_NSCAL * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+        HIPCHECK(hipHostGetDevicePointer((void**)&h->pinned_dev, h->pinned, 0));
+      }
     }
-    for (int l = 0; l + 1 < H.nl; ++l) derive_level(h.get(), l, st);
-    HIPCHECK(hipStreamSynchronize(st));
+    if (dev) {
+      for (int l = 0; l + 1 < H.nl; ++l) derive_level(h.get(), l, st);
+      HIPCHECK(hipStreamSynchronize(st));
+    }
   } catch (...) {
     (void)hipStreamSynchronize(st);  // queued work may still use h's memory
     throw;
@@ -1308,6 +1474,42 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
 
 }  // namespace
 
+
+namespace {
+
+// Uploads (or, with a null arena, sizes) a batch as one block-diagonal hierarchy.
+std::unique_ptr<mvamg_hier> upload_batch(const mvamg_hier_host* const* hs, int nprob, hipStream_t st, void* arena,
+                                         size_t arena_bytes) {
+  if (!hs || nprob < 1) throw Error(MVAMG_ERR_ARG, "null argument or empty batch");
+  std::vector<const HostHier*> Hs;
+  for (int p = 0; p < nprob; ++p) {
+    if (!hs[p]) throw Error(MVAMG_ERR_ARG, "null hierarchy in batch");
+    Hs.push_back(&hs[p]->h);
+  }
+  const HostHier U = union_hierarchy(Hs);
+  if (U.nl < 2) throw Error(MVAMG_ERR_ARG, "hierarchy needs at least two levels");
+  std::vector<const HostLevel*> cb;
+  for (const HostHier* H : Hs) cb.push_back(&H->lv[H->nl - 1]);
+  std::vector<int> rowprob0;
+  for (int p = 0; p < nprob; ++p) rowprob0.insert(rowprob0.end(), Hs[p]->lv[0].n, p);
+  std::unique_ptr<mvamg_hier> h = upload_hier(U, cb, st, &rowprob0, arena, arena_bytes);
+  h->nprob = nprob;
+  h->h_poff.assign(nprob + 1, 0);
+  int maxn = 1;
+  for (int p = 0; p < nprob; ++p) {
+    h->h_poff[p + 1] = h->h_poff[p] + Hs[p]->lv[0].n;
+    maxn = std::max(maxn, Hs[p]->lv[0].n);
+  }
+  h->poff = h->upload_vec(h->h_poff, st);
+  h->pchunks = std::min(kMaxChunks, std::max(1, (maxn + 2047) / 2048));
+  // room for every chunk count the autotuner may choose, so nothing grows later
+  ensure_multi(h.get(), nprob, kMaxChunks);
+  if (!h->sizing()) HIPCHECK(hipStreamSynchronize(st));
+  return h;
+}
+
+}  // namespace
+
 // ====================================================================== ABI
 
 extern "C" {
@@ -1318,8 +1520,10 @@ mvamg_status mvamg_profile(mvamg_hier* h, int enable) {
   try {
     if (!h) throw Error(MVAMG_ERR_ARG, "null handle");
     HIPCHECK(hipDeviceSynchronize());
+    if (enable < 0 || enable > 2) throw Error(MVAMG_ERR_ARG, "enable must be 0, 1 or 2");
     harvest(h);
     h->prof = enable != 0;
+    h->book_plain = enable == 2;
     for (int k = 0; k < MVAMG_KC_COUNT; ++k) {
       h->kc_launches[k] = 0;
       h->kc_ms[k] = 0.0;
@@ -1374,15 +1578,16 @@ mvamg_status mvamg_hier_host_info(const mvamg_hier_host* h, int* nlevels, int* n
   return MVAMG_OK;
 }
 
-mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** out) {
-  hipStream_t st = (hipStream_t)stream;
+mvamg_status mvamg_arena_bytes(const mvamg_hier_host* hh, int nrhs, size_t* bytes) {
   try {
-    if (!hh || !out) throw Error(MVAMG_ERR_ARG, "null argument");
-    *out = nullptr;
+    if (!hh || !bytes) throw Error(MVAMG_ERR_ARG, "null argument");
+    if (nrhs < 1 || nrhs > MVAMG_BLOCK_MAX) throw Error(MVAMG_ERR_ARG, "nrhs must be in 1..32");
     const HostHier& H = hh->h;
     if (H.nl < 2) throw Error(MVAMG_ERR_ARG, "hierarchy needs at least two levels");
     const std::vector<const HostLevel*> cb{&H.lv[H.nl - 1]};
-    *out = upload_hier(H, cb, st).release();
+    std::unique_ptr<mvamg_hier> h = upload_hier(H, cb, nullptr, nullptr, nullptr, 0);
+    if (nrhs > 1) ensure_block(h.get());
+    *bytes = h->arena_peak;
     return MVAMG_OK;
   } catch (const Error& e) {
     return fail_status(e);
@@ -1392,35 +1597,44 @@ mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* stream, mvamg_hier** 
   }
 }
 
-mvamg_status mvamg_batch_upload(const mvamg_hier_host* const* hs, int nprob, void* stream, mvamg_hier** out) {
+mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* arena, size_t arena_bytes, void* stream, mvamg_hier** out) {
   hipStream_t st = (hipStream_t)stream;
   try {
-    if (!hs || !out || nprob < 1) throw Error(MVAMG_ERR_ARG, "null argument or empty batch");
+    if (!hh || !out || !arena) throw Error(MVAMG_ERR_ARG, "null argument");
     *out = nullptr;
-    std::vector<const HostHier*> Hs;
-    for (int p = 0; p < nprob; ++p) {
-      if (!hs[p]) throw Error(MVAMG_ERR_ARG, "null hierarchy in batch");
-      Hs.push_back(&hs[p]->h);
-    }
-    const HostHier U = union_hierarchy(Hs);
-    if (U.nl < 2) throw Error(MVAMG_ERR_ARG, "hierarchy needs at least two levels");
-    std::vector<const HostLevel*> cb;
-    for (const HostHier* H : Hs) cb.push_back(&H->lv[H->nl - 1]);
-    std::vector<int> rowprob0;
-    for (int p = 0; p < nprob; ++p) rowprob0.insert(rowprob0.end(), Hs[p]->lv[0].n, p);
-    std::unique_ptr<mvamg_hier> h = upload_hier(U, cb, st, &rowprob0);
-    h->nprob = nprob;
-    h->h_poff.assign(nprob + 1, 0);
-    int maxn = 1;
-    for (int p = 0; p < nprob; ++p) {
-      h->h_poff[p + 1] = h->h_poff[p] + Hs[p]->lv[0].n;
-      maxn = std::max(maxn, Hs[p]->lv[0].n);
-    }
-    h->poff = h->upload_vec(h->h_poff, st);
-    h->pchunks = std::min(64, std::max(1, (maxn + 2047) / 2048));
-    ensure_multi(h.get(), nprob, h->pchunks);
-    HIPCHECK(hipStreamSynchronize(st));
-    *out = h.release();
+    const HostHier& H = hh->h;
+    if (H.nl < 2) throw Error(MVAMG_ERR_ARG, "hierarchy needs at least two levels");
+    const std::vector<const HostLevel*> cb{&H.lv[H.nl - 1]};
+    *out = upload_hier(H, cb, st, nullptr, arena, arena_bytes).release();
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return MVAMG_ERR_HIP;
+  }
+}
+
+mvamg_status mvamg_batch_arena_bytes(const mvamg_hier_host* const* hs, int nprob, size_t* bytes) {
+  try {
+    if (!bytes) throw Error(MVAMG_ERR_ARG, "null argument");
+    *bytes = upload_batch(hs, nprob, nullptr, nullptr, 0)->arena_peak;
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return MVAMG_ERR_HIP;
+  }
+}
+
+mvamg_status mvamg_batch_upload(const mvamg_hier_host* const* hs, int nprob, void* arena, size_t arena_bytes,
+                                void* stream, mvamg_hier** out) {
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    if (!out || !arena) throw Error(MVAMG_ERR_ARG, "null argument");
+    *out = nullptr;
+    *out = upload_batch(hs, nprob, st, arena, arena_bytes).release();
     return MVAMG_OK;
   } catch (const Error& e) {
     if (st) (void)hipStreamSynchronize(st);
@@ -1462,15 +1676,24 @@ mvamg_status mvamg_levels(const mvamg_hier* h, int* nlevels, int* n, int64_t* nn
   return MVAMG_OK;
 }
 
+mvamg_status mvamg_transfers(const mvamg_hier* h, int* nagg, int64_t* nu) {
+  if (!h) {
+    g_err = "null handle";
+    return MVAMG_ERR_ARG;
+  }
+  for (int l = 0; l + 1 < h->nl && l < 32; ++l) {
+    if (nagg) nagg[l] = h->tr[l].nagg;
+    if (nu) nu[l] = h->tr[l].nu;
+  }
+  return MVAMG_OK;
+}
+
 mvamg_status mvamg_set_fine_values(mvamg_hier* h, const double* val, void* stream) {
   try {
     if (!h || !val) throw Error(MVAMG_ERR_ARG, "null argument");
     check_device(h);
     hipStream_t st = (hipStream_t)stream;
-    const bool coded = h->lv[0].vcoded || h->lv[0].dcoded;
-    fill_level_values(h, 0, val, st);  // drops the value codes: kernels read the values from now on
-    derive_level(h, 0, st);
-    if (coded) drop_graphs(h);  // captured iterations hold the codes
+    refill_fine(h, val, st);
     return MVAMG_OK;
   } catch (const Error& e) {
     return fail_status(e);
@@ -1513,22 +1736,47 @@ mvamg_status mvamg_cycle_apply(mvamg_hier* h, const double* r, double* z, int pr
   }
 }
 
-mvamg_status mvamg_pcg_solve(mvamg_hier* h, const double* b, double* x, const mvamg_solve_params* prm,
-                             mvamg_info* info, void* stream) {
+mvamg_status mvamg_kcycle_apply(mvamg_hier* h, const double* r, double* z, int smoother, void* stream) {
+  try {
+    if (!h || !r || !z) throw Error(MVAMG_ERR_ARG, "null argument");
+    if (r == z) throw Error(MVAMG_ERR_ARG, "r and z must not alias");
+    if (smoother != MVAMG_SMOOTH_GS && smoother != MVAMG_SMOOTH_L1JACOBI) throw Error(MVAMG_ERR_ARG, "unknown smoother");
+    check_device(h);
+    hipStream_t st = (hipStream_t)stream;
+    const int eg = grid_for(h->n);
+    k_gather<<<eg, kBlock, 0, st>>>(h->n, h->perm0, r, h->r);
+    apply_B(h, h->r, h->z, 64, smoother, st, MVAMG_CYCLE_K);
+    k_scatter<<<eg, kBlock, 0, st>>>(h->n, h->perm0, h->z, z);
+    LAUNCHCHECK("kcycle_apply");
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_pcg_solve(mvamg_hier* h, const int* rowptr, const int* col, const double* val, const double* b,
+                             double* x, const mvamg_solve_params* prm, mvamg_info* info, void* stream) {
   try {
     if (!h) throw Error(MVAMG_ERR_ARG, "null handle");
+    if (!prm || !b || !x) throw Error(MVAMG_ERR_ARG, "null argument");
+    if (h->nprob > 0) throw Error(MVAMG_ERR_ARG, "a batch handle is solved with mvamg_batch_pcg_solve");
+    check_device(h);
+    use_matrix(h, rowptr, col, val, (hipStream_t)stream);
     return pcg(h, b, x, prm, info, (hipStream_t)stream);
   } catch (const Error& e) {
     return fail_status(e);
   }
 }
 
-mvamg_status mvamg_adjoint_solve(mvamg_hier* h, const double* dLdx, double* lambda, const mvamg_solve_params* prm,
-                                 mvamg_info* info, void* stream) {
+mvamg_status mvamg_adjoint_solve(mvamg_hier* h, const int* rowptr, const int* col, const double* val,
+                                 const double* dLdx, double* lambda, const mvamg_solve_params* prm, mvamg_info* info,
+                                 void* stream) {
   try {
-    if (!h || !lambda) throw Error(MVAMG_ERR_ARG, "null argument");
+    if (!h || !lambda || !prm || !dLdx) throw Error(MVAMG_ERR_ARG, "null argument");
+    if (h->nprob > 0) throw Error(MVAMG_ERR_ARG, "a batch handle is solved with mvamg_batch_pcg_solve");
     check_device(h);
     hipStream_t st = (hipStream_t)stream;
+    use_matrix(h, rowptr, col, val, st);
     HIPCHECK(hipMemsetAsync(lambda, 0, sizeof(double) * (size_t)h->n, st));
     return pcg(h, dLdx, lambda, prm, info, st);
   } catch (const Error& e) {
@@ -1593,6 +1841,7 @@ mvamg_status mvamg_pcg_solve_block(mvamg_hier* h, const double* B, double* X, in
   try {
     if (!h) throw Error(MVAMG_ERR_ARG, "null handle");
     if (m < 1 || m > MVAMG_BLOCK_MAX) throw Error(MVAMG_ERR_ARG, "block width must be 1..32");
+    if (prm && prm->cycle != MVAMG_CYCLE_V) throw Error(MVAMG_ERR_ARG, "block solves run the V-cycle only");
     check_device(h);
     ensure_block(h);
     BlockOps O(h, m);
@@ -1607,6 +1856,7 @@ mvamg_status mvamg_batch_pcg_solve(mvamg_hier* h, const double* b, double* x, co
   try {
     if (!h) throw Error(MVAMG_ERR_ARG, "null handle");
     if (h->nprob < 1) throw Error(MVAMG_ERR_ARG, "not a batch handle (use mvamg_pcg_solve)");
+    if (prm && prm->cycle != MVAMG_CYCLE_V) throw Error(MVAMG_ERR_ARG, "batch solves run the V-cycle only");
     check_device(h);
     BatchOps O(h);
     return multi_pcg(O, b, x, prm, info, (hipStream_t)stream);
@@ -1626,7 +1876,12 @@ mvamg_status mvamg_autotune(mvamg_hier* h, int what, char* report, size_t cap, v
     std::string rep;
     try {
       if (what & MVAMG_TUNE_GROUP_LANES) tune_group_lanes(h, st, rep);
-      if ((what & MVAMG_TUNE_BLOCK_COARSE) && h->nprob == 0) tune_block_coarse(h, st, rep);
+      if ((what & MVAMG_TUNE_BLOCK_COARSE) && h->nprob == 0) {
+        if (block_fits(h))
+          tune_block_coarse(h, st, rep);
+        else
+          rep += "gemm: skipped (the arena has no block work space); ";
+      }
       if (what & MVAMG_TUNE_BATCH_CHUNKS) tune_batch_chunks(h, st, rep);
     } catch (...) {
       h->prof = prof;

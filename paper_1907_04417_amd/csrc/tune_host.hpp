@@ -30,11 +30,6 @@ double time_ms(hipStream_t st, int reps, F fn) {
   return ms / reps;
 }
 
-void drop_graphs(mvamg_hier* h) {
-  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.second);
-  h->graphs.clear();
-}
-
 std::string fmt_us(double ms) {
   char b[32];
   std::snprintf(b, sizeof b, "%.2f", 1e3 * ms);
@@ -100,7 +95,7 @@ constexpr int kChunkCandidates[] = {4, 8, 16, 32, 64};
 
 void tune_batch_chunks(mvamg_hier* h, hipStream_t st, std::string& rep) {
   if (h->nprob < 1) return;
-  ensure_multi(h, h->nprob, 64);
+  ensure_multi(h, h->nprob, kMaxChunks);
   k_fill<double><<<grid_for(h->n), kBlock, 0, st>>>(h->n, 1.0, h->r);
   LAUNCHCHECK("tune fill");
   int best = h->pchunks;

@@ -3,7 +3,8 @@
     python -m paper_1907_04417_amd.measure run [workload] [steps]
         a plain 256 MiB device copy (counter calibration) followed by `steps`
         binary64 solves; meant to run under rocprofv3.  Workload
-        aniso1024x32: the 32-column block solve on aniso1024.
+        aniso1024x32: the 32-column block solve on aniso1024; batch64: one
+        batch solve of the 64 anisotropic problems.
     python -m paper_1907_04417_amd.measure traffic <fetch.csv> <write.csv> <workload>
         per-launch HBM traffic of every kernel class from two rocprofv3 --pmc
         runs (FETCH_SIZE, WRITE_SIZE), each scaled by the ratio of the copy's
@@ -99,13 +100,21 @@ def run(workload: str = "jump128", steps: int = 3) -> None:
     if workload == "aniso1024x32":
         from . import problems
         P, path, st = workloads.load("aniso1024")
-        S = mvamg.Solver(path)
+        S = mvamg.Solver(path, nrhs=32)
         mvamg.tuned(S.h, cache)
         B, _ = problems.block_rhs(P, 32, seed=workloads.BLOCK_RHS_SEED)
         Bd = torch.from_numpy(B).cuda()
         for _ in range(steps):
             X = torch.zeros_like(Bd)
             mvamg.pcg_solve_block(S.h, Bd, X, rtol=1e-8)
+    elif workload == "batch64":
+        Ps, paths, stats = workloads.load_batch("batch64")
+        S = mvamg.BatchSolver(paths)
+        mvamg.tuned(S.h, cache)
+        b = torch.from_numpy(np.concatenate([P.b for P in Ps])).cuda()
+        for _ in range(steps):
+            x = torch.zeros_like(b)
+            mvamg.batch_pcg_solve(S.h, b, x, rtol=1e-8)
     else:
         P, path, st = workloads.load(workload)
         S = mvamg.Solver(path)

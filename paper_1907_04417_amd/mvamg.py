@@ -23,13 +23,16 @@ LIB_PATH = os.path.join(_HERE, "libmvamg.so")
 OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_FILE, ERR_NOT_SPD, ERR_NONFINITE, ERR_BREAKDOWN, ERR_HIP = -1, -2, -3, -4, -5, -6
 SMOOTH_GS, SMOOTH_L1JACOBI = 0, 1
+CYCLE_V, CYCLE_K = 0, 1
 
-EXPORTED = ["mvamg_hier_read", "mvamg_hier_host_free", "mvamg_hier_host_info", "mvamg_upload", "mvamg_free",
+EXPORTED = ["mvamg_hier_read", "mvamg_hier_host_free", "mvamg_hier_host_info", "mvamg_arena_bytes",
+            "mvamg_upload", "mvamg_free", "mvamg_batch_arena_bytes",
             "mvamg_levels", "mvamg_set_fine_values", "mvamg_spmv", "mvamg_cycle_apply", "mvamg_pcg_solve",
             "mvamg_adjoint_solve", "mvamg_grad_coeffs", "mvamg_profile", "mvamg_kernel_stats",
             "mvamg_last_error", "mvamg_spmv_block", "mvamg_cycle_apply_block", "mvamg_pcg_solve_block",
             "mvamg_batch_upload", "mvamg_batch_problems", "mvamg_batch_pcg_solve", "mvamg_autotune",
-            "mvamg_tune_get", "mvamg_tune_set", "mvamg_signature"]
+            "mvamg_tune_get", "mvamg_tune_set", "mvamg_signature",
+            "mvamg_transfers", "mvamg_kcycle_apply"]
 BLOCK_MAX = 32
 TUNE_GROUP_LANES, TUNE_BLOCK_COARSE, TUNE_BATCH_CHUNKS, TUNE_ALL = 1, 2, 4, 7
 
@@ -47,7 +50,7 @@ class MvamgError(RuntimeError):
 class SolveParams(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("smoother", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("max_restarts", ctypes.c_int),
-                ("history", ctypes.POINTER(ctypes.c_double))]
+                ("history", ctypes.POINTER(ctypes.c_double)), ("cycle", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -70,15 +73,19 @@ def load(path: str = LIB_PATH):
         L.mvamg_hier_host_free.argtypes = [vp]
         L.mvamg_hier_host_free.restype = None
         L.mvamg_hier_host_info.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int64)]
-        L.mvamg_upload.argtypes = [vp, vp, P(vp)]
+        L.mvamg_arena_bytes.argtypes = [vp, ctypes.c_int, P(ctypes.c_size_t)]
+        L.mvamg_upload.argtypes = [vp, vp, ctypes.c_size_t, vp, P(vp)]
+        L.mvamg_batch_arena_bytes.argtypes = [P(vp), ctypes.c_int, P(ctypes.c_size_t)]
         L.mvamg_free.argtypes = [vp]
         L.mvamg_free.restype = None
         L.mvamg_levels.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int64), P(ctypes.c_int)]
         L.mvamg_set_fine_values.argtypes = [vp, vp, vp]
+        L.mvamg_transfers.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int64)]
         L.mvamg_spmv.argtypes = [vp, vp, vp, vp]
         L.mvamg_cycle_apply.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
-        L.mvamg_pcg_solve.argtypes = [vp, vp, vp, P(SolveParams), P(Info), vp]
-        L.mvamg_adjoint_solve.argtypes = [vp, vp, vp, P(SolveParams), P(Info), vp]
+        L.mvamg_kcycle_apply.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+        L.mvamg_pcg_solve.argtypes = [vp, vp, vp, vp, vp, vp, P(SolveParams), P(Info), vp]
+        L.mvamg_adjoint_solve.argtypes = [vp, vp, vp, vp, vp, vp, P(SolveParams), P(Info), vp]
         L.mvamg_grad_coeffs.argtypes = [vp, vp, vp, vp, vp]
         L.mvamg_profile.argtypes = [vp, ctypes.c_int]
         L.mvamg_kernel_stats.argtypes = [vp, ctypes.c_int, P(ctypes.c_int64), P(ctypes.c_double),
@@ -87,7 +94,7 @@ def load(path: str = LIB_PATH):
         L.mvamg_spmv_block.argtypes = [vp, vp, vp, ctypes.c_int, vp]
         L.mvamg_cycle_apply_block.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
         L.mvamg_pcg_solve_block.argtypes = [vp, vp, vp, ctypes.c_int, P(SolveParams), P(Info), vp]
-        L.mvamg_batch_upload.argtypes = [P(vp), ctypes.c_int, vp, P(vp)]
+        L.mvamg_batch_upload.argtypes = [P(vp), ctypes.c_int, vp, ctypes.c_size_t, vp, P(vp)]
         L.mvamg_batch_problems.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int)]
         L.mvamg_batch_pcg_solve.argtypes = [vp, vp, vp, P(SolveParams), P(Info), vp]
         L.mvamg_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t, vp]
@@ -118,11 +125,13 @@ def _check(st, allow=(OK,)):
 _HANDLES: dict = {}
 
 
-def _register(h: int) -> None:
+def _register(h: int, arena, nrhs: int = 1) -> None:
     import torch
     lv = levels(h)
     k, _ = batch_problems(h)
-    _HANDLES[h] = dict(n=lv["n"][0], nnz=lv["nnz"][0], nprob=k, device=torch.cuda.current_device())
+    # the handle borrows the arena: the tensor is kept here until free(h)
+    _HANDLES[h] = dict(n=lv["n"][0], nnz=lv["nnz"][0], nprob=k, device=torch.cuda.current_device(), arena=arena,
+                      nrhs=nrhs)
 
 
 def _hinfo(h: int) -> dict:
@@ -188,16 +197,31 @@ def hier_host_info(hh: int):
     return nl.value, n.value, nnz.value
 
 
-def upload(hh: int, stream=None) -> int:
+def arena_bytes(hh: int, nrhs: int = 1) -> int:
+    """Device bytes mvamg_upload needs for a parsed hierarchy (nrhs > 1: with
+    the work space of the block calls)."""
+    b = ctypes.c_size_t()
+    _check(load().mvamg_arena_bytes(hh, nrhs, ctypes.byref(b)))
+    return b.value
+
+
+def _arena(nbytes: int):
+    import torch
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
+
+
+def upload(hh: int, stream=None, nrhs: int = 1) -> int:
+    """Uploads into a torch-owned arena sized by arena_bytes(hh, nrhs)."""
+    arena = _arena(arena_bytes(hh, nrhs))
     h = ctypes.c_void_p()
-    _check(load().mvamg_upload(hh, _stream(stream), ctypes.byref(h)))
-    _register(h.value)
+    _check(load().mvamg_upload(hh, arena.data_ptr(), arena.numel(), _stream(stream), ctypes.byref(h)))
+    _register(h.value, arena, nrhs)
     return h.value
 
 
 def free(h: int) -> None:
+    load().mvamg_free(h)  # waits for the device; the arena is then released with the entry
     _HANDLES.pop(h, None)
-    load().mvamg_free(h)
 
 
 def levels(h: int):
@@ -208,6 +232,15 @@ def levels(h: int):
     _check(load().mvamg_levels(h, ctypes.byref(nl), n, nnz, stg))
     k = nl.value
     return dict(nlevels=k, n=list(n[:k]), nnz=list(nnz[:k]), stages=list(stg[:k]))
+
+
+def transfers(h: int):
+    """Aggregate counts and sum(n_a k_a) of the transfers P^l, l < nlevels - 1."""
+    k = levels(h)["nlevels"] - 1
+    na = (ctypes.c_int * 32)()
+    nu = (ctypes.c_int64 * 32)()
+    _check(load().mvamg_transfers(h, na, nu))
+    return dict(nagg=list(na[:k]), nu=list(nu[:k]))
 
 
 def set_fine_values(h: int, val, stream=None) -> None:
@@ -225,29 +258,56 @@ def cycle_apply(h: int, r, z, precision: int = 64, smoother: int = SMOOTH_GS, st
                                     _stream(stream)))
 
 
-def _params(rtol, maxit, precision, smoother, max_restarts, history, rows=1):
+def kcycle_apply(h: int, r, z, smoother: int = SMOOTH_GS, stream=None) -> None:
+    """z = K r, one K-cycle (binary64)."""
+    n = _hinfo(h)["n"]
+    _check(load().mvamg_kcycle_apply(h, _vec(h, r, n, "r"), _vec(h, z, n, "z"), smoother, _stream(stream)))
+
+
+def _params(rtol, maxit, precision, smoother, max_restarts, history, rows=1, cycle=CYCLE_V):
     if not isinstance(maxit, int) or maxit < 0:
         raise ValueError("maxit must be a non-negative int")
-    return SolveParams(precision, smoother, rtol, maxit, max_restarts, _history(history, rows, maxit))
+    return SolveParams(precision, smoother, rtol, maxit, max_restarts, _history(history, rows, maxit), cycle)
+
+
+def _matrix(h: int, A):
+    """Device addresses of A = (rowptr, col, val) in the file's level-0 CSR
+    form; any of them may be None (see mvamg_pcg_solve)."""
+    if A is None:
+        return None, None, None
+    rowptr, col, val = A
+    if (rowptr is None) != (col is None):
+        raise ValueError("A: rowptr and col are passed together")
+    hi = _hinfo(h)
+    rp = None if rowptr is None else _vec(h, rowptr, hi["n"] + 1, "A.rowptr", "int32")
+    ci = None if col is None else _vec(h, col, hi["nnz"], "A.col", "int32")
+    v = None if val is None else _vec(h, val, hi["nnz"], "A.val")
+    return rp, ci, v
 
 
 def pcg_solve(h: int, b, x, rtol=1e-8, maxit=1000, precision=64, smoother=SMOOTH_GS, max_restarts=3,
-              history: np.ndarray | None = None, stream=None) -> Info:
+              history: np.ndarray | None = None, stream=None, A=None, cycle=CYCLE_V) -> Info:
+    """CG on A x = b.  A: (rowptr, col, val) device tensors of the finest
+    matrix (same pattern as the hierarchy's, values may differ) or None for
+    the values in use.  cycle: CYCLE_V or CYCLE_K (the preconditioner)."""
     info = Info()
     n = _hinfo(h)["n"]
-    prm = _params(rtol, maxit, precision, smoother, max_restarts, history)
-    _check(load().mvamg_pcg_solve(h, _vec(h, b, n, "b"), _vec(h, x, n, "x"), ctypes.byref(prm), ctypes.byref(info),
-                                  _stream(stream)), allow=(OK, NOT_CONVERGED))
+    prm = _params(rtol, maxit, precision, smoother, max_restarts, history, cycle=cycle)
+    rp, ci, v = _matrix(h, A)
+    _check(load().mvamg_pcg_solve(h, rp, ci, v, _vec(h, b, n, "b"), _vec(h, x, n, "x"), ctypes.byref(prm),
+                                  ctypes.byref(info), _stream(stream)), allow=(OK, NOT_CONVERGED))
     return info
 
 
 def adjoint_solve(h: int, dLdx, lam, rtol=1e-8, maxit=1000, precision=64, smoother=SMOOTH_GS, max_restarts=3,
-                  history: np.ndarray | None = None, stream=None) -> Info:
+                  history: np.ndarray | None = None, stream=None, A=None, cycle=CYCLE_V) -> Info:
     info = Info()
     n = _hinfo(h)["n"]
-    prm = _params(rtol, maxit, precision, smoother, max_restarts, history)
-    _check(load().mvamg_adjoint_solve(h, _vec(h, dLdx, n, "dLdx"), _vec(h, lam, n, "lambda"), ctypes.byref(prm),
-                                      ctypes.byref(info), _stream(stream)), allow=(OK, NOT_CONVERGED))
+    prm = _params(rtol, maxit, precision, smoother, max_restarts, history, cycle=cycle)
+    rp, ci, v = _matrix(h, A)
+    _check(load().mvamg_adjoint_solve(h, rp, ci, v, _vec(h, dLdx, n, "dLdx"), _vec(h, lam, n, "lambda"),
+                                      ctypes.byref(prm), ctypes.byref(info), _stream(stream)),
+           allow=(OK, NOT_CONVERGED))
     return info
 
 
@@ -296,11 +356,16 @@ def pcg_solve_block(h: int, B, X, rtol=1e-8, maxit=1000, precision=64, smoother=
 
 
 def batch_upload(hhs, stream=None) -> int:
-    """Upload parsed hierarchies (mvamg_hier_read handles) as one batch."""
+    """Upload parsed hierarchies (mvamg_hier_read handles) as one batch, into
+    a torch-owned arena."""
     arr = (ctypes.c_void_p * len(hhs))(*hhs)
+    nb = ctypes.c_size_t()
+    _check(load().mvamg_batch_arena_bytes(arr, len(hhs), ctypes.byref(nb)))
+    arena = _arena(nb.value)
     h = ctypes.c_void_p()
-    _check(load().mvamg_batch_upload(arr, len(hhs), _stream(stream), ctypes.byref(h)))
-    _register(h.value)
+    _check(load().mvamg_batch_upload(arr, len(hhs), arena.data_ptr(), arena.numel(), _stream(stream),
+                                     ctypes.byref(h)))
+    _register(h.value, arena)
     return h.value
 
 
@@ -356,7 +421,8 @@ def tuned(h: int, cache_path: str | None = None, what: int = TUNE_ALL, stream=No
     import json
     path = cache_path or os.environ.get("MVAMG_TUNE_CACHE",
                                         os.path.join(os.path.expanduser("~"), ".cache", "mvamg_tune.json"))
-    key = f"{signature(h)}|what={what}"
+    # a handle without block work space skips the block-product choice
+    key = f"{signature(h)}|what={what}" + ("|block" if _hinfo(h)["nrhs"] > 1 else "")
     cache = {}
     if os.path.exists(path):
         with open(path) as f:
@@ -375,9 +441,14 @@ def tuned(h: int, cache_path: str | None = None, what: int = TUNE_ALL, stream=No
     return text
 
 
-def profile(h: int, enable: bool) -> None:
-    """Turn per-launch kernel timing on or off (resets the totals)."""
-    _check(load().mvamg_profile(h, 1 if enable else 0))
+BOOK_COMPACT, BOOK_PLAIN = 1, 2
+
+
+def profile(h: int, enable, booking: int = BOOK_COMPACT) -> None:
+    """Turn per-launch kernel timing on or off (resets the totals).  booking:
+    BOOK_COMPACT books the compact forms the kernels read, BOOK_PLAIN the
+    plain model (12 bytes per stored binary64 entry)."""
+    _check(load().mvamg_profile(h, booking if enable else 0))
 
 
 def kernel_stats(h: int, kclass: int):
@@ -402,14 +473,15 @@ class SolveResult:
 class Solver:
     """A hierarchy file uploaded to the current GPU."""
 
-    def __init__(self, path: str, stream=None):
+    def __init__(self, path: str, stream=None, nrhs: int = 1):
+        """nrhs > 1: the arena also holds the work space of block calls."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("mvamg needs a GPU (HIP device)")
         hh = hier_read(path)
         try:
             self.nlevels, self.n, self.nnz = hier_host_info(hh)
-            self.h = upload(hh, stream)
+            self.h = upload(hh, stream, nrhs)
         finally:
             hier_host_free(hh)
         self.info = levels(self.h)
@@ -426,12 +498,12 @@ class Solver:
             pass
 
     def solve(self, b, x=None, rtol=1e-8, maxit=1000, precision=64, smoother=SMOOTH_GS, max_restarts=3,
-              stream=None):
+              stream=None, A=None, cycle=CYCLE_V):
         import torch
         if x is None:
             x = torch.zeros_like(b)
         hist = np.zeros(maxit + 1)
-        inf = pcg_solve(self.h, b, x, rtol, maxit, precision, smoother, max_restarts, hist, stream)
+        inf = pcg_solve(self.h, b, x, rtol, maxit, precision, smoother, max_restarts, hist, stream, A, cycle)
         return x, SolveResult(inf.iterations, bool(inf.converged), inf.rel_res, inf.rel_res_true, inf.restarts,
                               hist[:inf.iterations + 1].copy())
 

@@ -116,6 +116,58 @@ def aniso9(m: int = 64, eps: float = 1e-2, theta: float = math.pi / 4, seed: int
                    dict(m=m, eps=eps, theta=theta, seed=seed))
 
 
+def ani_p1_matrix(m: int, eps: float, theta: float):
+    """Linear finite elements for -div(K grad u) (K of Section 5.1) on the unit
+    square with homogeneous Dirichlet boundary: a structured triangulation of
+    (m + 1)^2 squares, each cut by its south-west to north-east diagonal, and
+    the m^2 interior nodes as unknowns (numbered x-fastest).  The element
+    matrix of a triangle T is |T| G^T K G, G the gradients of its barycentric
+    functions; the sum over elements is exact (no quadrature error)."""
+    a = eps + math.cos(theta) ** 2
+    b = eps + math.sin(theta) ** 2
+    c = math.cos(theta) * math.sin(theta)
+    K = np.array([[a, c], [c, b]])
+    N = m + 2  # grid points per side, boundary included
+    h = 1.0 / (m + 1)
+    gy, gx = np.meshgrid(np.arange(N - 1), np.arange(N - 1), indexing="ij")
+    gx, gy = gx.ravel(), gy.ravel()
+    node = lambda x, y: y * N + x  # noqa: E731
+    # the two triangles of every square, vertices counter-clockwise
+    tris = np.concatenate([
+        np.stack([node(gx, gy), node(gx + 1, gy), node(gx + 1, gy + 1)], axis=1),
+        np.stack([node(gx, gy), node(gx + 1, gy + 1), node(gx, gy + 1)], axis=1)])
+    xy = np.stack([(np.arange(N * N) % N) * h, (np.arange(N * N) // N) * h], axis=1)
+    p = xy[tris]                      # (ntri, 3, 2)
+    e1, e2 = p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]
+    det = e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0]
+    area = 0.5 * det
+    # gradients of the barycentric functions: rows of inv([e1 e2])^T, lambda_0 = 1 - l1 - l2
+    g1 = np.stack([e2[:, 1], -e2[:, 0]], axis=1) / det[:, None]
+    g2 = np.stack([-e1[:, 1], e1[:, 0]], axis=1) / det[:, None]
+    G = np.stack([-(g1 + g2), g1, g2], axis=1)  # (ntri, 3, 2)
+    Ke = area[:, None, None] * np.einsum("tik,kl,tjl->tij", G, K, G)
+    rows = np.repeat(tris, 3, axis=1).ravel()
+    cols = np.tile(tris, (1, 3)).ravel()
+    Aall = sp.coo_matrix((Ke.ravel(), (rows, cols)), shape=(N * N, N * N)).tocsr()
+    inner = ((xy[:, 0] > 0.5 * h) & (xy[:, 0] < 1 - 0.5 * h) & (xy[:, 1] > 0.5 * h) & (xy[:, 1] < 1 - 0.5 * h))
+    idx = np.flatnonzero(inner)
+    A = Aall[idx][:, idx].tocsr()
+    A.eliminate_zeros()
+    A.sort_indices()
+    rp, ci, v = A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64)
+    return _symmetrize_exact(rp, ci, v)
+
+
+def ani_p1(m: int, eps: float = 1e-3, theta: float = 0.0) -> Problem:
+    """The paper's ANI test problems (Section 5.1: eps = 1e-3, theta = 0 for
+    ANI1, pi/8 for ANI2) with linear elements on a structured triangulation of
+    m^2 interior nodes, and the unit vector as right-hand side, as in the
+    paper's runs (no random draw)."""
+    rp, ci, v = ani_p1_matrix(m, eps, theta)
+    n = m * m
+    return Problem(f"ani_p1_m{m}", rp, ci, v, np.ones(n), None, dict(m=m, eps=eps, theta=theta))
+
+
 def block_rhs(P: Problem, k: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
     """k right-hand sides B = A X* for one matrix, X* ~ U[-1, 1] drawn as one
     (n, k) array (row-major: row i holds the k values of unknown i).

@@ -19,6 +19,12 @@ hierarchy file cached on disk (setup is the untimed input generator).
               inclusions, one face clamped and the opposite face pushed down;
               at most 6 smooth vectors, smoother groups of the 3 dofs of a node
     elast12   the same family on 12^3 nodes (test size)
+    ani1_410  the paper's ANI1 (Section 5.1: eps = 1e-3, theta = 0) with linear
+              elements on a structured triangulation, 410^2 interior nodes
+              (n = 168,100), unit right-hand side, 5 smooth vectors (the
+              paper's best solve time at its n = 168,577)
+    ani1_160 / ani2_160  ANI1 and ANI2 (theta = pi/8) on 160^2 nodes with 4
+              and 5 smooth vectors (test size)
 
 Batches (load_batch): independent problems, each with its own hierarchy, all
 set up with three levels (bootstrap depth at most 6, three bootstrap levels
@@ -47,6 +53,9 @@ CONFIGS = {
     "grf32": dict(gen=lambda: problems.grf_fv5(32, seed=3), nvec=3, setup=dict(boot_coarse_min=8, coarse_cap=64)),
     "aniso1024": dict(gen=lambda: problems.aniso9(1024, 1e-2, math.pi / 4, seed=0), nvec=3, setup={}),
     "aniso520": dict(gen=lambda: problems.aniso9(520, 1e-2, math.pi / 4, seed=0), nvec=3, setup={}),
+    "ani1_410": dict(gen=lambda: problems.ani_p1(410, 1e-3, 0.0), nvec=5, setup={}),
+    "ani1_160": dict(gen=lambda: problems.ani_p1(160, 1e-3, 0.0), nvec=4, setup={}),
+    "ani2_160": dict(gen=lambda: problems.ani_p1(160, 1e-3, math.pi / 8), nvec=5, setup={}),
     "elast48": dict(gen=lambda: problems.elast_q1(48, seed=0), nvec=6, setup=dict(fine_group=3)),
     "elast12": dict(gen=lambda: problems.elast_q1(12, seed=0), nvec=6,
                     setup=dict(fine_group=3, boot_coarse_min=8, coarse_cap=64)),
@@ -83,7 +92,8 @@ def load(name: str, **setup_overrides):
     P = cfg["gen"]()
     sp = dict(cfg["setup"])
     sp.update(setup_overrides)
-    params = SetupParams(nvec_max=cfg["nvec"], **sp)
+    sp.setdefault("nvec_max", cfg["nvec"])
+    params = SetupParams(**sp)
     key = hashlib.sha1(json.dumps([name, sorted(params.__dict__.items()), _setup_source_tag()],
                                   default=str).encode()).hexdigest()[:12]
     path = os.path.join(cache_dir(), f"{name}_{key}.bin")
@@ -91,7 +101,7 @@ def load(name: str, **setup_overrides):
     if os.path.exists(path) and os.path.exists(meta):
         with open(meta) as f:
             return P, path, json.load(f)
-    x0 = problems.random_vectors(P.n, max(cfg["nvec"] - 1, 1), BOOTSTRAP_SEED)
+    x0 = problems.random_vectors(P.n, max(params.nvec_max - 1, 1), BOOTSTRAP_SEED)
     st = build_hierarchy(P.rowptr, P.col, P.val, path + ".tmp", x0, params)
     os.replace(path + ".tmp", path)
     with open(meta, "w") as f:

@@ -78,13 +78,42 @@ def test_batch_upload_validates_on_the_host(lib, tiny_hier, tmp_path):
     hs = [mvamg.hier_read(path3), mvamg.hier_read(path2)]
     try:
         out = ctypes.c_void_p()
+        nb = ctypes.c_size_t()
         arr = (ctypes.c_void_p * 2)(*hs)
-        assert lib.mvamg_batch_upload(arr, 2, None, ctypes.byref(out)) == mvamg.ERR_ARG
+        assert lib.mvamg_batch_arena_bytes(arr, 2, ctypes.byref(nb)) == mvamg.ERR_ARG
         assert "same number of levels" in mvamg.last_error()
-        assert lib.mvamg_batch_upload(arr, 0, None, ctypes.byref(out)) == mvamg.ERR_ARG
+        assert lib.mvamg_batch_arena_bytes(arr, 0, ctypes.byref(nb)) == mvamg.ERR_ARG
         nul = (ctypes.c_void_p * 2)(hs[0], None)
-        assert lib.mvamg_batch_upload(nul, 2, None, ctypes.byref(out)) == mvamg.ERR_ARG
+        assert lib.mvamg_batch_arena_bytes(nul, 2, ctypes.byref(nb)) == mvamg.ERR_ARG
+        # no arena: rejected before any device work
+        same = (ctypes.c_void_p * 2)(hs[0], hs[0])
+        assert lib.mvamg_batch_arena_bytes(same, 2, ctypes.byref(nb)) == mvamg.OK and nb.value > 0
+        assert lib.mvamg_batch_upload(same, 2, None, nb.value, None, ctypes.byref(out)) == mvamg.ERR_ARG
         assert out.value is None
     finally:
         for hh in hs:
             mvamg.hier_host_free(hh)
+
+
+def test_arena_bytes_on_the_host(lib, tiny_hier):
+    """The arena size is computed on the host (no device work): it covers at
+    least the stored matrices, grows with the block work space, and the
+    upload rejects a missing or unaligned arena before touching the device."""
+    P, path, st = tiny_hier
+    hh = mvamg.hier_read(path)
+    try:
+        b1, b32 = mvamg.arena_bytes(hh, 1), mvamg.arena_bytes(hh, 32)
+        # every level's values in binary64 and binary32 and its column indices
+        assert b1 >= sum(12 * z + 4 * z for z in st["nnz"][:-1])
+        # block work space: at least r, x in both precisions per row and level, 32 columns
+        assert b32 - b1 >= sum(24 * 32 * n for n in st["n"])
+        assert mvamg.arena_bytes(hh, 1) == b1  # deterministic
+        nb = ctypes.c_size_t()
+        for bad in (0, 33):
+            assert lib.mvamg_arena_bytes(hh, bad, ctypes.byref(nb)) == mvamg.ERR_ARG
+        out = ctypes.c_void_p()
+        assert lib.mvamg_upload(hh, None, b1, None, ctypes.byref(out)) == mvamg.ERR_ARG
+        assert lib.mvamg_upload(hh, ctypes.c_void_p(0x10000 + 8), b1, None, ctypes.byref(out)) == mvamg.ERR_ARG
+        assert "aligned" in mvamg.last_error() and out.value is None
+    finally:
+        mvamg.hier_host_free(hh)

@@ -35,7 +35,7 @@ def _fake(n, dtype=torch.float64, dev=0):
 @pytest.fixture
 def handle():
     h = 0x7fff0000
-    mvamg._HANDLES[h] = dict(n=10, nnz=34, nprob=0, device=0)
+    mvamg._HANDLES[h] = dict(n=10, nnz=34, nprob=0, device=0, arena=None, nrhs=1)
     yield h
     mvamg._HANDLES.pop(h, None)
 
@@ -97,3 +97,21 @@ def test_history_buffers(handle):
 def test_unknown_handle():
     with pytest.raises(ValueError, match="unknown or freed handle"):
         mvamg.spmv(0x1234, _fake(10), _fake(10))
+
+
+def test_matrix_arrays_are_checked(handle):
+    """A passed to a solve: rowptr int32 n+1, col int32 nnz, val float64 nnz,
+    rowptr and col together."""
+    ok = (_fake(11, torch.int32), _fake(34, torch.int32), _fake(34))
+    cases = [
+        ((_fake(10, torch.int32), ok[1], ok[2]), "expected 11 elements"),
+        ((_fake(11, torch.int64), ok[1], ok[2]), "expected int32"),
+        ((ok[0], _fake(33, torch.int32), ok[2]), "expected 34 elements"),
+        ((ok[0], ok[1], _fake(34, torch.float32)), "expected float64"),
+        ((ok[0], None, ok[2]), "passed together"),
+    ]
+    for A, msg in cases:
+        with pytest.raises(ValueError, match=msg):
+            mvamg.pcg_solve(handle, _fake(10), _fake(10), A=A)
+        with pytest.raises(ValueError, match=msg):
+            mvamg.adjoint_solve(handle, _fake(10), _fake(10), A=A)

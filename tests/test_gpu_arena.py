@@ -1,0 +1,172 @@
+"""Caller-owned device memory and the matrix passed to a solve, through the
+C ABI.
+
+* The handle lives in the caller's arena: an arena one byte short of what
+  mvamg_arena_bytes reports is rejected, and neither the upload nor the
+  solves change the device's free memory (the library allocates nothing);
+  only the HIP runtime's captured iteration graphs take memory, once.
+* A block call on a handle whose arena was sized for one right-hand side is
+  rejected; the autotuner skips the block-product choice there.
+* mvamg_pcg_solve with A: the hierarchy's own A gives the same iterates bit
+  for bit as no A; a near-by A (same pattern, Section 1) gives what
+  mvamg_set_fine_values followed by a solve gives, and matches the oracle's
+  operator with those values; a different pattern is rejected.
+"""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1907_04417_amd import mvamg, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _t(torch, a, dtype=None):
+    return torch.from_numpy(np.ascontiguousarray(a if dtype is None else a.astype(dtype))).cuda()
+
+
+def _upload_into(torch, hh, nbytes):
+    lib = mvamg.load()
+    arena = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    out = ctypes.c_void_p()
+    rc = lib.mvamg_upload(hh, arena.data_ptr(), arena.numel(), torch.cuda.current_stream().cuda_stream,
+                          ctypes.byref(out))
+    return rc, out.value, arena
+
+
+def _free_mem(torch):
+    torch.cuda.synchronize()
+    return torch.cuda.mem_get_info()[0]
+
+
+def test_upload_needs_the_reported_arena(torch_gpu, monkeypatch):
+    """An arena one byte short is rejected.  With the reported size, neither
+    the upload nor any solve moves the device's free memory when the
+    iterations run as plain launches; with captured iteration graphs, the HIP
+    runtime's graph objects take their memory once, on the first solve of
+    each kind, and later solves move nothing."""
+    torch = torch_gpu
+    P, path, st = workloads.load("jump16")
+    hh = mvamg.hier_read(path)
+    try:
+        need = mvamg.arena_bytes(hh, 1)
+        _say(f"[arena] jump16 needs {need} bytes")
+        rc, h, small = _upload_into(torch, hh, need - 1)
+        assert rc == mvamg.ERR_ARG and "too small" in mvamg.last_error() and h is None
+        del small
+        b = _t(torch, P.b)
+        x = torch.zeros_like(b)
+        for graphs in (False, True):
+            if graphs:
+                monkeypatch.delenv("MVAMG_NO_GRAPH", raising=False)
+            else:
+                monkeypatch.setenv("MVAMG_NO_GRAPH", "1")  # read at upload
+            arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+            free0 = _free_mem(torch)
+            out = ctypes.c_void_p()
+            assert mvamg.load().mvamg_upload(hh, arena.data_ptr(), arena.numel(),
+                                             torch.cuda.current_stream().cuda_stream, ctypes.byref(out)) == mvamg.OK
+            h = out.value
+            mvamg._register(h, arena)
+            try:
+                free1 = _free_mem(torch)
+                for prec in (64, 32):
+                    x.zero_()
+                    assert mvamg.pcg_solve(h, b, x, rtol=1e-8, precision=prec).converged
+                free2 = _free_mem(torch)
+                for prec in (64, 32):
+                    x.zero_()
+                    assert mvamg.pcg_solve(h, b, x, rtol=1e-8, precision=prec).converged
+                free3 = _free_mem(torch)
+                _say(f"[arena] graphs={graphs}: free memory before upload {free0}, after {free1}, "
+                     f"after the first solves {free2}, after more solves {free3}")
+                assert free1 == free0 and free3 == free2
+                if not graphs:
+                    assert free2 == free0
+            finally:
+                mvamg.free(h)
+    finally:
+        mvamg.hier_host_free(hh)
+
+
+def test_block_calls_need_block_space(torch_gpu):
+    torch = torch_gpu
+    P, path, st = workloads.load("jump16")
+    S = mvamg.Solver(path)  # arena for one right-hand side
+    try:
+        R = torch.zeros((P.n, 4), dtype=torch.float64, device="cuda")
+        with pytest.raises(mvamg.MvamgError) as ei:
+            mvamg.cycle_apply_block(S.h, R, torch.empty_like(R))
+        assert ei.value.status == mvamg.ERR_ARG and "block work space" in str(ei.value)
+        rep = mvamg.autotune(S.h)
+        _say(f"[arena] autotune without block space: {rep}")
+        assert "gemm: skipped" in rep
+        # the handle still solves
+        b = _t(torch, P.b)
+        x, res = S.solve(b)
+        assert res.converged
+    finally:
+        S.close()
+
+
+def test_solve_with_the_matrix(torch_gpu):
+    torch = torch_gpu
+    P, path, st = workloads.load("jump16")
+    O = oracle.Oracle(path)
+    rp, ci = _t(torch, P.rowptr, np.int32), _t(torch, P.col, np.int32)
+    S = mvamg.Solver(path)
+    S2 = mvamg.Solver(path)
+    try:
+        b = _t(torch, P.b)
+        _say("[matrix] jump16: the hierarchy's own A")
+        x0, r0 = S.solve(b)
+        x1, r1 = S.solve(b, A=(rp, ci, _t(torch, P.val)))
+        assert r1.iterations == r0.iterations and np.array_equal(r1.history, r0.history)
+        assert torch.equal(x0, x1)
+        # a near-by s.p.d. matrix with the same pattern: D A D
+        rng = np.random.default_rng(8)
+        d = np.exp(0.05 * rng.standard_normal(P.n))
+        rows = np.repeat(np.arange(P.n), np.diff(P.rowptr))
+        v2 = P.val * d[rows] * d[P.col]
+        _say("[matrix] jump16: a near-by A passed to the solve")
+        x2, r2 = S.solve(b, A=(rp, ci, _t(torch, v2)), rtol=1e-9)
+        mvamg.set_fine_values(S2.h, _t(torch, v2))
+        x3, r3 = S2.solve(b, rtol=1e-9)
+        assert r2.iterations == r3.iterations and np.array_equal(r2.history, r3.history)
+        assert torch.equal(x2, x3)
+        # the solve used v2: the operator against the oracle with those values
+        y = S.spmv(b).cpu().numpy()
+        assert np.abs(y - oracle.spmv(P.rowptr, P.col, v2, P.b)).max() <= 1e-13 * np.abs(y).max()
+        z = S.cycle(b).cpu().numpy()
+        zo = O.vcycle(P.b, val0=v2)
+        assert np.abs(z - zo).max() <= 1e-11 * np.abs(zo).max()
+        true_rel = np.linalg.norm(P.b - oracle.spmv(P.rowptr, P.col, v2, x2.cpu().numpy())) / np.linalg.norm(P.b)
+        assert r2.converged and true_rel <= 1.01e-9
+        # the values again: same as a fresh pass with them, no refill needed
+        x4, r4 = S.solve(b, A=(None, None, _t(torch, v2)), rtol=1e-9)
+        assert np.array_equal(r4.history, r2.history)
+        # a different pattern is rejected before the solve
+        ci_bad = ci.clone()
+        ci_bad[5] = (int(ci_bad[5]) + 1) % P.n
+        with pytest.raises(mvamg.MvamgError) as ei:
+            S.solve(b, A=(rp, ci_bad, _t(torch, v2)))
+        assert ei.value.status == mvamg.ERR_ARG and "pattern" in str(ei.value)
+    finally:
+        S.close()
+        S2.close()

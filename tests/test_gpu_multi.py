@@ -60,7 +60,7 @@ def blk(torch_gpu):
     for name in BLOCK_CASES:
         P, path, st = workloads.load(name)
         _say(f"[block case] {name}: n={P.n} levels={st['n']}")
-        out[name] = (P, path, mvamg.Solver(path), oracle.Oracle(path))
+        out[name] = (P, path, mvamg.Solver(path, nrhs=32), oracle.Oracle(path))
     return out
 
 
@@ -186,7 +186,7 @@ def test_block_full_size_aniso1024(torch_gpu):
     torch = torch_gpu
     P, path, st = workloads.load("aniso1024")
     _say(f"[block full] aniso1024 levels={st['n']}")
-    S = mvamg.Solver(path)
+    S = mvamg.Solver(path, nrhs=32)
     B, _ = problems.block_rhs(P, 32, seed=workloads.BLOCK_RHS_SEED)
     X = torch.zeros((P.n, 32), dtype=torch.float64, device="cuda")
     H = np.zeros((32, 1001))

@@ -74,7 +74,7 @@ def test_every_group_lane_variant_keeps_parity(name, torch_gpu):
 
 def test_every_block_coarse_variant_keeps_parity(torch_gpu):
     P, path, st = workloads.load("jump16")
-    S = mvamg.Solver(path)
+    S = mvamg.Solver(path, nrhs=32)
     O = oracle.Oracle(path)
     R = np.random.default_rng(42).standard_normal((P.n, 32))
     zo = [O.vcycle(R[:, c]) for c in range(0, 32, 5)]
@@ -91,7 +91,7 @@ def test_every_block_coarse_variant_keeps_parity(torch_gpu):
 
 def test_autotune_report_roundtrip_and_rejects(torch_gpu, tmp_path):
     P, path, st = workloads.load("jump16")
-    S = mvamg.Solver(path)
+    S = mvamg.Solver(path, nrhs=32)
     rep = mvamg.autotune(S.h)
     _say(f"[tune] {rep}")
     assert "chosen:" in rep and "gemm" in rep

@@ -1,6 +1,11 @@
 """Input generators (no GPU): the finite-volume map g -> A(g) used by the
-differentiable solve, and the Gaussian random field."""
+differentiable solve, the Gaussian random field, and the linear-element
+anisotropic problems of the paper's Section 5.1."""
+import math
+
 import numpy as np
+import pytest
+import scipy.sparse as sp
 import torch
 
 from paper_1907_04417_amd import problems
@@ -114,3 +119,37 @@ def test_block_rhs_and_batch_draws():
     assert all(10 <= s <= 20 for s in sides)
     assert all(1e-4 <= p.meta["eps"] <= 1.0 and 0.0 <= p.meta["theta"] < np.pi for p in Ps)
     assert [p.meta["seed"] for p in Ps] == [3001 + p for p in range(5)]
+
+
+def test_ani_p1_reduces_to_five_point_at_theta_zero():
+    """Linear elements on right triangles couple no nodes across the
+    diagonals when K is diagonal: at theta = 0 the matrix is the 5-point
+    difference stencil (times h^2)."""
+    rp, ci, v = problems.ani_p1_matrix(9, 1e-3, 0.0)
+    r2, c2, v2 = problems.aniso9_matrix(9, 1e-3, 0.0)
+    A = sp.csr_matrix((v, ci, rp), shape=(81, 81)).toarray()
+    B = sp.csr_matrix((v2, c2, r2), shape=(81, 81)).toarray()
+    assert np.abs(A - B).max() <= 1e-14
+
+
+@pytest.mark.parametrize("theta", [0.0, math.pi / 8, 1.0])
+def test_ani_p1_consistent_on_quadratics(theta):
+    """At nodes whose neighbours are all interior, the element stencil applied
+    to u = x^2, x y, y^2 gives h^2 (-div K grad u) = -2 h^2 a, -2 h^2 c,
+    -2 h^2 b exactly (up to rounding); the matrix is symmetric and s.p.d."""
+    m, eps = 12, 1e-3
+    h = 1.0 / (m + 1)
+    a = eps + math.cos(theta) ** 2
+    b = eps + math.sin(theta) ** 2
+    c = math.cos(theta) * math.sin(theta)
+    P = problems.ani_p1(m, eps, theta)
+    A = P.scipy()
+    assert abs(A - A.T).max() == 0.0
+    assert np.linalg.eigvalsh(A.toarray()).min() > 0
+    ix, iy = np.arange(m * m) % m, np.arange(m * m) // m
+    x, y = (ix + 1) * h, (iy + 1) * h
+    inner = (ix > 0) & (ix < m - 1) & (iy > 0) & (iy < m - 1)
+    for u, want in ((x * x, -2 * a), (x * y, -2 * c), (y * y, -2 * b)):
+        got = (A @ u)[inner] / h ** 2
+        assert np.abs(got - want).max() <= 1e-9
+    assert np.array_equal(P.b, np.ones(m * m))
