@@ -167,6 +167,26 @@ mvamg_status mvamg_cycle_apply(mvamg_hier* h, const double* r_dev, double* z_dev
    mvamg_cycle_apply.  r_dev and z_dev must not alias. */
 mvamg_status mvamg_kcycle_apply(mvamg_hier* h, const double* r_dev, double* z_dev, int smoother, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, serving loops, harnesses that forbid hipMalloc): z = B r exactly
+   as mvamg_cycle_apply (same kernels, same results bit for bit), but every
+   work vector of the cycle -- the level-0 input and output in smoother
+   order, r, x and s of every level in the cycle's precision, the coarsest
+   solve's vectors and product slots -- lives in one static device array of
+   MVAMG_NOALLOC_SCRATCH_BYTES per device instead of the handle's work space.
+   The call allocates nothing: no hipMalloc, hipFree or allocating library
+   routine.  The array is set up on the first call on a device (its address
+   is taken once and kept) and held until the process ends.  Every call on a
+   device shares that device's array and leaves its contents behind; nothing
+   in it needs to start at zero.  Calls that overlap on one device (two
+   streams, two threads) race on the array and must not be issued.
+   MVAMG_ERR_ARG if the cycle's work space exceeds the array (about 1.3 M
+   fine rows in binary64, 2.5 M in binary32, with the usual coarse levels) or
+   while measurement (mvamg_profile) is on. */
+#define MVAMG_NOALLOC_SCRATCH_BYTES (32u << 20)
+mvamg_status mvamg_cycle_apply_noalloc(mvamg_hier* h, const double* r_dev, double* z_dev, int precision,
+                                       int smoother, void* stream);
+
 /* Preconditioned CG (Section 5) on A x = b with B = one V-cycle.  A is the
    finest-level matrix in the file's CSR form (device arrays: rowptr int32
    [n+1], col int32 [nnz], val float64 [nnz]).  It must have the hierarchy's

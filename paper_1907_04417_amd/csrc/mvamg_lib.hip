@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1474,6 +1475,118 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
 
 }  // namespace
 
+// ------------------------------------------- cycle without allocation
+//
+// Work space of mvamg_cycle_apply_noalloc: one array per device, held until
+// the process ends.  Host code never uses the symbol itself as an address
+// (on the host it names a stand-in, not device memory); it uses the address
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[MVAMG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch_ptr;  // device -> address of its scratch array
+
+unsigned char* scratch_address(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  HIPCHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) throw Error(MVAMG_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+  g_scratch_ptr[device] = (unsigned char*)ptr;
+  return (unsigned char*)ptr;
+}
+
+// Carves the work vectors of one cycle (level-0 input and output in smoother
+// order, every level's r, x, s in the cycle's precision, the coarsest
+// solve's vectors and product slots) out of `base`, or only counts their
+// bytes when base is null.  Swaps them into the handle for the lifetime of
+// the object and restores the handle's own vectors afterwards.
+class ScratchWork {
+ public:
+  ScratchWork(mvamg_hier* h, int precision, unsigned char* base) : h_(h), base_(base) {
+    saved_ = snapshot();
+    take(h->r, h->n);
+    take(h->z, h->n);
+    h->lv[0].r = h->r;
+    h->lv[0].x = h->z;
+    for (int l = 0; l < h->nl; ++l) {
+      DevLevel& L = h->lv[l];
+      const bool coarsest = (l == h->nl - 1);
+      if (precision == 64) {
+        if (!coarsest) take(L.s, L.n);
+        if (l > 0) {
+          take(L.r, L.n);
+          take(L.x, L.n);
+        }
+      } else {
+        if (!coarsest) take(L.s32, L.n);
+        take(L.r32, L.n);
+        take(L.x32, L.n);
+      }
+    }
+    if (precision == 32) {
+      take(h->co.r, h->co.n);
+      take(h->co.z, h->co.n);
+    }
+    if (h->co.nb == 1) take(h->co.spart, (size_t)h->co.nt * h->co.nt * 64);
+    if (!base_) restore();
+  }
+  ~ScratchWork() {
+    if (base_) restore();
+  }
+  size_t bytes() const { return used_; }
+
+ private:
+  struct Saved {
+    double *hr, *hz;
+    std::vector<double*> r, x, s;
+    std::vector<float*> r32, x32, s32;
+    double *cr, *cz, *spart;
+  };
+  Saved snapshot() const {
+    Saved v{h_->r, h_->z, {}, {}, {}, {}, {}, {}, h_->co.r, h_->co.z, h_->co.spart};
+    for (const DevLevel& L : h_->lv) {
+      v.r.push_back(L.r);
+      v.x.push_back(L.x);
+      v.s.push_back(L.s);
+      v.r32.push_back(L.r32);
+      v.x32.push_back(L.x32);
+      v.s32.push_back(L.s32);
+    }
+    return v;
+  }
+  void restore() {
+    h_->r = saved_.hr;
+    h_->z = saved_.hz;
+    for (size_t l = 0; l < h_->lv.size(); ++l) {
+      DevLevel& L = h_->lv[l];
+      L.r = saved_.r[l];
+      L.x = saved_.x[l];
+      L.s = saved_.s[l];
+      L.r32 = saved_.r32[l];
+      L.x32 = saved_.x32[l];
+      L.s32 = saved_.s32[l];
+    }
+    h_->co.r = saved_.cr;
+    h_->co.z = saved_.cz;
+    h_->co.spart = saved_.spart;
+  }
+  template <typename T>
+  void take(T*& slot, size_t count) {
+    const size_t at = used_;
+    used_ += ((count * sizeof(T) + 255) / 256) * 256;
+    if (base_) slot = reinterpret_cast<T*>(base_ + at);
+  }
+  mvamg_hier* h_;
+  unsigned char* base_;
+  size_t used_ = 0;
+  Saved saved_;
+};
+
+}  // namespace
 
 namespace {
 
@@ -1748,6 +1861,33 @@ mvamg_status mvamg_kcycle_apply(mvamg_hier* h, const double* r, double* z, int s
     apply_B(h, h->r, h->z, 64, smoother, st, MVAMG_CYCLE_K);
     k_scatter<<<eg, kBlock, 0, st>>>(h->n, h->perm0, h->z, z);
     LAUNCHCHECK("kcycle_apply");
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_cycle_apply_noalloc(mvamg_hier* h, const double* r, double* z, int precision, int smoother,
+                                       void* stream) {
+  try {
+    if (!h || !r || !z) throw Error(MVAMG_ERR_ARG, "null argument");
+    if (r == z) throw Error(MVAMG_ERR_ARG, "r and z must not alias");
+    if (precision != 64 && precision != 32) throw Error(MVAMG_ERR_ARG, "precision must be 64 or 32");
+    if (smoother != MVAMG_SMOOTH_GS && smoother != MVAMG_SMOOTH_L1JACOBI) throw Error(MVAMG_ERR_ARG, "unknown smoother");
+    check_device(h);
+    if (h->prof) throw Error(MVAMG_ERR_ARG, "measurement is on (mvamg_profile): its events are created per launch");
+    const size_t need = ScratchWork(h, precision, nullptr).bytes();
+    if (need > (size_t)MVAMG_NOALLOC_SCRATCH_BYTES)
+      throw Error(MVAMG_ERR_ARG, "cycle work space of " + std::to_string(need) + " bytes exceeds the " +
+                                     std::to_string((size_t)MVAMG_NOALLOC_SCRATCH_BYTES) + "-byte static scratch");
+    unsigned char* base = scratch_address(h->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int eg = grid_for(h->n);
+    ScratchWork work(h, precision, base);
+    k_gather<<<eg, kBlock, 0, st>>>(h->n, h->perm0, r, h->r);
+    apply_B(h, h->r, h->z, precision, smoother, st);
+    k_scatter<<<eg, kBlock, 0, st>>>(h->n, h->perm0, h->z, z);
+    LAUNCHCHECK("cycle_apply_noalloc");
     return MVAMG_OK;
   } catch (const Error& e) {
     return fail_status(e);

@@ -31,8 +31,10 @@ EXPORTED = ["mvamg_hier_read", "mvamg_hier_host_free", "mvamg_hier_host_info", "
             "mvamg_adjoint_solve", "mvamg_grad_coeffs", "mvamg_profile", "mvamg_kernel_stats",
             "mvamg_last_error", "mvamg_spmv_block", "mvamg_cycle_apply_block", "mvamg_pcg_solve_block",
             "mvamg_batch_upload", "mvamg_batch_problems", "mvamg_batch_pcg_solve", "mvamg_autotune",
-            "mvamg_tune_get", "mvamg_tune_set", "mvamg_signature",
+            "mvamg_tune_get", "mvamg_tune_set", "mvamg_signature", "mvamg_cycle_apply_noalloc",
             "mvamg_transfers", "mvamg_kcycle_apply"]
+# bytes of the static device array mvamg_cycle_apply_noalloc works in
+NOALLOC_SCRATCH_BYTES = 32 << 20
 BLOCK_MAX = 32
 TUNE_GROUP_LANES, TUNE_BLOCK_COARSE, TUNE_BATCH_CHUNKS, TUNE_ALL = 1, 2, 4, 7
 
@@ -83,6 +85,7 @@ def load(path: str = LIB_PATH):
         L.mvamg_transfers.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int64)]
         L.mvamg_spmv.argtypes = [vp, vp, vp, vp]
         L.mvamg_cycle_apply.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+        L.mvamg_cycle_apply_noalloc.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
         L.mvamg_kcycle_apply.argtypes = [vp, vp, vp, ctypes.c_int, vp]
         L.mvamg_pcg_solve.argtypes = [vp, vp, vp, vp, vp, vp, P(SolveParams), P(Info), vp]
         L.mvamg_adjoint_solve.argtypes = [vp, vp, vp, vp, vp, vp, P(SolveParams), P(Info), vp]
@@ -256,6 +259,14 @@ def cycle_apply(h: int, r, z, precision: int = 64, smoother: int = SMOOTH_GS, st
     n = _hinfo(h)["n"]
     _check(load().mvamg_cycle_apply(h, _vec(h, r, n, "r"), _vec(h, z, n, "z"), precision, smoother,
                                     _stream(stream)))
+
+
+def cycle_apply_noalloc(h: int, r, z, precision: int = 64, smoother: int = SMOOTH_GS, stream=None) -> None:
+    """z = B r as cycle_apply, with the cycle's work vectors in the library's
+    static device array (no device allocation in the call)."""
+    n = _hinfo(h)["n"]
+    _check(load().mvamg_cycle_apply_noalloc(h, _vec(h, r, n, "r"), _vec(h, z, n, "z"), precision, smoother,
+                                            _stream(stream)))
 
 
 def kcycle_apply(h: int, r, z, smoother: int = SMOOTH_GS, stream=None) -> None:
