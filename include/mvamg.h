@@ -285,6 +285,44 @@ mvamg_status mvamg_batch_problems(const mvamg_hier* h, int* nprob, int* offsets)
 mvamg_status mvamg_batch_pcg_solve(mvamg_hier* h, const double* b_dev, double* x_dev,
                                    const mvamg_solve_params* prm, mvamg_info* info, void* stream);
 
+/* ------------------------------------------ composite (bootstrap) AMG */
+
+/* The bootstrap's own solver (eq. 1.1 and Algorithm 1; Section 5 item (i)):
+   the symmetrized multiplicative composite of r hierarchies B_1..B_r built on
+   one fine matrix A (the files the host setup writes for every bootstrap
+   stage), whose error propagator is
+     I - B A = (I - B_1 A)..(I - B_r A)(I - B_r A)..(I - B_1 A),
+   applied factor by factor, rightmost first.  hs holds r single-problem
+   handles whose finest matrices agree in size, pattern and values (checked
+   on the device; MVAMG_ERR_ARG otherwise); products with A use hs[0]'s.
+   cycle: every component a V-cycle or a K-cycle (the paper's bootstrap
+   default), binary64.  Vectors are device arrays in the file's row order.
+   The calls take a caller-owned device work space (256-byte aligned) of at
+   least *bytes from mvamg_composite_work_bytes(n); calls sharing a work space
+   or a handle must not overlap.  The handles' own level vectors are used as
+   scratch by every factor. */
+mvamg_status mvamg_composite_work_bytes(int n, size_t* bytes);
+
+/* z = B res, from z = 0: every factor k takes z += B_k (res - A z). */
+mvamg_status mvamg_composite_apply(mvamg_hier* const* hs, int r, int cycle, int smoother, const double* res_dev,
+                                   double* z_dev, void* work_dev, size_t work_bytes, void* stream);
+
+/* The testing phase of Algorithm 1 with the symmetrized product: x <- E x,
+   nu times (every factor x <- x - B_k A x), from x_dev's content.  *rho
+   receives ||x^nu||_A / ||x^{nu-1}||_A and x_dev the new smooth vector
+   x^nu / ||x^nu||_A (x^nu if its A-norm is zero). */
+mvamg_status mvamg_composite_test(mvamg_hier* const* hs, int r, int cycle, int smoother, int nu, double* x_dev,
+                                  double* rho, void* work_dev, size_t work_bytes, void* stream);
+
+/* CG preconditioned by the composite (the paper's original bootstrap AMG),
+   with the flexible beta (K-cycle components are not linear); prm as for
+   mvamg_pcg_solve (precision 64; max_restarts ignored).  x_dev holds x_0 on
+   entry and the solution on exit; each iteration reads its inner products
+   on the host. */
+mvamg_status mvamg_composite_pcg_solve(mvamg_hier* const* hs, int r, const double* b_dev, double* x_dev,
+                                       const mvamg_solve_params* prm, mvamg_info* info, void* work_dev,
+                                       size_t work_bytes, void* stream);
+
 /* --------------------------------------------------------- autotuning */
 
 enum {

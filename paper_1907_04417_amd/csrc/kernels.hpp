@@ -279,6 +279,23 @@ __global__ __launch_bounds__(kBlock) void k_kcombine(int n, const double* __rest
 
 // ------------------------------------------------------- vector kernels
 
+// out = a x + b y (out may alias x or y)
+__global__ __launch_bounds__(kBlock) void k_axpby(int n, double a, const double* x, double b, const double* y,
+                                                  double* out) {
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) out[p] = a * x[p] + b * y[p];
+}
+
+// x = x / d
+__global__ __launch_bounds__(kBlock) void k_div(int n, double d, double* __restrict__ x) {
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) x[p] = x[p] / d;
+}
+
+// out[perm[p]] += s in[p] (perm a permutation: no two threads write one entry)
+__global__ __launch_bounds__(kBlock) void k_scatter_axpy(int n, const int* __restrict__ perm, double s,
+                                                         const double* __restrict__ in, double* __restrict__ out) {
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) out[perm[p]] += s * in[p];
+}
+
 __global__ __launch_bounds__(kBlock) void k_gather(int n, const int* __restrict__ perm,
                                                    const double* __restrict__ in, double* __restrict__ out) {
   for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) out[p] = in[perm[p]];

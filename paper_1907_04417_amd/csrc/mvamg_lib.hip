@@ -1472,6 +1472,7 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
 
 #include "multi_host.hpp"
 #include "tune_host.hpp"
+#include "composite_host.hpp"
 
 }  // namespace
 
@@ -2000,6 +2001,70 @@ mvamg_status mvamg_batch_pcg_solve(mvamg_hier* h, const double* b, double* x, co
     check_device(h);
     BatchOps O(h);
     return multi_pcg(O, b, x, prm, info, (hipStream_t)stream);
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_composite_work_bytes(int n, size_t* bytes) {
+  if (n < 1 || !bytes) {
+    g_err = "n must be positive and bytes not null";
+    return MVAMG_ERR_ARG;
+  }
+  *bytes = composite_work_bytes(n);
+  return MVAMG_OK;
+}
+
+namespace {
+void check_comp_args(int cycle, int smoother) {
+  if (cycle != MVAMG_CYCLE_V && cycle != MVAMG_CYCLE_K) throw Error(MVAMG_ERR_ARG, "unknown cycle");
+  if (smoother != MVAMG_SMOOTH_GS && smoother != MVAMG_SMOOTH_L1JACOBI) throw Error(MVAMG_ERR_ARG, "unknown smoother");
+}
+}  // namespace
+
+mvamg_status mvamg_composite_apply(mvamg_hier* const* hs, int r, int cycle, int smoother, const double* res,
+                                   double* z, void* work, size_t work_bytes, void* stream) {
+  try {
+    if (!res || !z || res == z) throw Error(MVAMG_ERR_ARG, "null or aliased vectors");
+    check_comp_args(cycle, smoother);
+    hipStream_t st = (hipStream_t)stream;
+    check_composite(hs, r, st);
+    const CompWork w = comp_work(hs[0]->n, work, work_bytes);
+    comp_apply(hs, r, cycle, smoother, res, z, w, st);
+    LAUNCHCHECK("composite_apply");
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_composite_test(mvamg_hier* const* hs, int r, int cycle, int smoother, int nu, double* x,
+                                  double* rho, void* work, size_t work_bytes, void* stream) {
+  try {
+    if (!x || !rho || nu < 1) throw Error(MVAMG_ERR_ARG, "null argument or nu < 1");
+    check_comp_args(cycle, smoother);
+    hipStream_t st = (hipStream_t)stream;
+    check_composite(hs, r, st);
+    const CompWork w = comp_work(hs[0]->n, work, work_bytes);
+    *rho = comp_test(hs, r, cycle, smoother, nu, x, w, st);
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_composite_pcg_solve(mvamg_hier* const* hs, int r, const double* b, double* x,
+                                       const mvamg_solve_params* prm, mvamg_info* info, void* work,
+                                       size_t work_bytes, void* stream) {
+  try {
+    if (!prm || !b || !x) throw Error(MVAMG_ERR_ARG, "null argument");
+    if (prm->precision != 64) throw Error(MVAMG_ERR_ARG, "the composite runs in binary64 only");
+    if (prm->maxit < 0 || !(prm->rtol >= 0.0)) throw Error(MVAMG_ERR_ARG, "invalid maxit or rtol");
+    check_comp_args(prm->cycle, prm->smoother);
+    hipStream_t st = (hipStream_t)stream;
+    check_composite(hs, r, st);
+    const CompWork w = comp_work(hs[0]->n, work, work_bytes);
+    return comp_pcg(hs, r, b, x, prm, info, w, st);
   } catch (const Error& e) {
     return fail_status(e);
   }

@@ -32,7 +32,8 @@ EXPORTED = ["mvamg_hier_read", "mvamg_hier_host_free", "mvamg_hier_host_info", "
             "mvamg_last_error", "mvamg_spmv_block", "mvamg_cycle_apply_block", "mvamg_pcg_solve_block",
             "mvamg_batch_upload", "mvamg_batch_problems", "mvamg_batch_pcg_solve", "mvamg_autotune",
             "mvamg_tune_get", "mvamg_tune_set", "mvamg_signature", "mvamg_cycle_apply_noalloc",
-            "mvamg_transfers", "mvamg_kcycle_apply"]
+            "mvamg_transfers", "mvamg_kcycle_apply", "mvamg_composite_work_bytes", "mvamg_composite_apply",
+            "mvamg_composite_test", "mvamg_composite_pcg_solve"]
 # bytes of the static device array mvamg_cycle_apply_noalloc works in
 NOALLOC_SCRATCH_BYTES = 32 << 20
 BLOCK_MAX = 32
@@ -87,6 +88,13 @@ def load(path: str = LIB_PATH):
         L.mvamg_cycle_apply.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
         L.mvamg_cycle_apply_noalloc.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
         L.mvamg_kcycle_apply.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+        L.mvamg_composite_work_bytes.argtypes = [ctypes.c_int, P(ctypes.c_size_t)]
+        L.mvamg_composite_apply.argtypes = [P(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
+                                            ctypes.c_size_t, vp]
+        L.mvamg_composite_test.argtypes = [P(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
+                                           P(ctypes.c_double), vp, ctypes.c_size_t, vp]
+        L.mvamg_composite_pcg_solve.argtypes = [P(vp), ctypes.c_int, vp, vp, P(SolveParams), P(Info), vp,
+                                                ctypes.c_size_t, vp]
         L.mvamg_pcg_solve.argtypes = [vp, vp, vp, vp, vp, vp, P(SolveParams), P(Info), vp]
         L.mvamg_adjoint_solve.argtypes = [vp, vp, vp, vp, vp, vp, P(SolveParams), P(Info), vp]
         L.mvamg_grad_coeffs.argtypes = [vp, vp, vp, vp, vp]
@@ -529,6 +537,66 @@ class Solver:
         y = torch.empty_like(x)
         spmv(self.h, x, y, stream)
         return y
+
+
+class Composite:
+    """The bootstrap's composite AMG over Solvers of the stage hierarchies
+    B_1..B_r (one fine matrix): the symmetrized multiplicative product, its
+    testing phase and CG preconditioned by it.  r selects the first r
+    hierarchies (default all)."""
+
+    def __init__(self, solvers):
+        import torch
+        self.solvers = list(solvers)
+        if not self.solvers:
+            raise ValueError("no hierarchies")
+        self.n = self.solvers[0].n
+        for S in self.solvers:
+            if S.n != self.n:
+                raise ValueError("the hierarchies are not built on the same fine matrix")
+        nb = ctypes.c_size_t()
+        _check(load().mvamg_composite_work_bytes(self.n, ctypes.byref(nb)))
+        self.work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+
+    def _hs(self, r):
+        r = len(self.solvers) if r is None else r
+        if not 1 <= r <= len(self.solvers):
+            raise ValueError(f"r must be 1..{len(self.solvers)}")
+        return (ctypes.c_void_p * r)(*[S.h for S in self.solvers[:r]]), r
+
+    def apply(self, res, cycle=CYCLE_V, smoother=SMOOTH_GS, r=None, stream=None):
+        import torch
+        hs, r = self._hs(r)
+        z = torch.empty_like(res)
+        h0 = self.solvers[0].h
+        _check(load().mvamg_composite_apply(hs, r, cycle, smoother, _vec(h0, res, self.n, "res"),
+                                            _vec(h0, z, self.n, "z"), self.work.data_ptr(), self.work.numel(),
+                                            _stream(stream)))
+        return z
+
+    def test(self, x, nu=15, cycle=CYCLE_V, smoother=SMOOTH_GS, r=None, stream=None) -> float:
+        """Testing phase in place on x; returns the convergence estimate."""
+        hs, r = self._hs(r)
+        rho = ctypes.c_double()
+        _check(load().mvamg_composite_test(hs, r, cycle, smoother, nu, _vec(self.solvers[0].h, x, self.n, "x"),
+                                           ctypes.byref(rho), self.work.data_ptr(), self.work.numel(),
+                                           _stream(stream)))
+        return rho.value
+
+    def solve(self, b, x=None, rtol=1e-8, maxit=1000, cycle=CYCLE_V, smoother=SMOOTH_GS, r=None, stream=None):
+        import torch
+        hs, r = self._hs(r)
+        if x is None:
+            x = torch.zeros_like(b)
+        hist = np.zeros(maxit + 1)
+        prm = _params(rtol, maxit, 64, smoother, 0, hist, cycle=cycle)
+        info = Info()
+        h0 = self.solvers[0].h
+        _check(load().mvamg_composite_pcg_solve(hs, r, _vec(h0, b, self.n, "b"), _vec(h0, x, self.n, "x"),
+                                                ctypes.byref(prm), ctypes.byref(info), self.work.data_ptr(),
+                                                self.work.numel(), _stream(stream)), allow=(OK, NOT_CONVERGED))
+        return x, SolveResult(info.iterations, bool(info.converged), info.rel_res, info.rel_res_true, 0,
+                              hist[:info.iterations + 1].copy())
 
 
 class BatchSolver:

@@ -109,6 +109,35 @@ def load(name: str, **setup_overrides):
     return P, path, st
 
 
+def load_bootstrap(name: str, **setup_overrides):
+    """The workload's hierarchy together with the hierarchies of its bootstrap
+    stages B_1..B_r (every stage tested, rho_des = 0 so that the nvec - 1
+    stages are all built).  Returns (problem, hierarchy_path, setup_stats,
+    stage_paths, x0), x0 the random starts of the stages' testing phases."""
+    cfg = CONFIGS[name]
+    P = cfg["gen"]()
+    sp = dict(cfg["setup"])
+    sp.update(setup_overrides)
+    sp.setdefault("nvec_max", cfg["nvec"])
+    sp.setdefault("rho_des", 0.0)
+    params = SetupParams(**sp)
+    key = hashlib.sha1(json.dumps([name, "boot", sorted(params.__dict__.items()), _setup_source_tag()],
+                                  default=str).encode()).hexdigest()[:12]
+    path = os.path.join(cache_dir(), f"{name}_boot_{key}.bin")
+    meta = path + ".json"
+    x0 = problems.random_vectors(P.n, max(params.nvec_max - 1, 1), BOOTSTRAP_SEED)
+    prefix = path[:-4]
+    if not (os.path.exists(path) and os.path.exists(meta)):
+        st = build_hierarchy(P.rowptr, P.col, P.val, path + ".tmp", x0, params, boot_prefix=prefix)
+        os.replace(path + ".tmp", path)
+        with open(meta, "w") as f:
+            json.dump(st, f)
+    with open(meta) as f:
+        st = json.load(f)
+    stages = [f"{prefix}_b{r}.bin" for r in range(1, len(st["rho"]) + 1)]
+    return P, path, st, stages, x0
+
+
 def _hierarchy(tag: str, P, nvec: int, setup: dict):
     params = SetupParams(nvec_max=nvec, **setup)
     key = hashlib.sha1(json.dumps([tag, P.n, P.nnz, sorted(params.__dict__.items()), _setup_source_tag()],
