@@ -324,6 +324,21 @@ def bench_batch(args, torch, mvamg, workloads, tune_cache):
     for S1 in Ss:
         S1.close()
     BS.close()
+    # the one-launch small-problem path for the problems up to a size threshold
+    # (every problem at the largest), the rest lockstep; binary64
+    small = {}
+    for thr in (16384, 65536, 1 << 30):
+        BSm = mvamg.BatchSolver(paths, mini_rows=thr)
+        nsmall = sum(mvamg.batch_small_path(BSm.h))
+
+        def batm():
+            x.zero_()
+            return mvamg.batch_pcg_solve(BSm.h, b, x, rtol=1e-8)
+        msm, infos = _timed_ms(torch, batm, steps, 1)
+        ok = all(i.converged and i.rel_res_true <= 1.01e-8 for i in infos)
+        small[str(thr)] = dict(problems_on_small_path=nsmall, ms_per_batch=msm, all_converged=ok)
+        log(f"[bench] batch with problems up to {thr} rows on the small path ({nsmall} of 64): {msm:.1f} ms")
+        BSm.close()
     r64, r32 = res[64], res[32]
     return {
         "workload": "batch64: 64 independent 2-D rotated anisotropic 9-point problems, sides U{32..512}, eps "
@@ -334,6 +349,7 @@ def bench_batch(args, torch, mvamg, workloads, tune_cache):
         "separate_fp64_ms_for_64": r64["ms_seq"], "speedup_vs_separate_fp64": r64["ms_seq"] / r64["ms"],
         "fp32_cycle": {"value": 64e3 / r32["ms"], "ms_per_batch": r32["ms"], "nit": r32["its"],
                        "speedup_vs_separate_fp64": r64["ms_seq"] / r32["ms"]},
+        "small_path_fp64": small,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": kernels[dom]["gbs"] / HBM_PEAK_GBS, "traffic": recorded_traffic(dom, "batch64")},
         "kernels": kernels,

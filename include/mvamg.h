@@ -257,22 +257,33 @@ mvamg_status mvamg_pcg_solve_block(mvamg_hier* h, const double* B_dev, double* X
 
 /* ------------------------------------------------ batch of problems */
 
-/* Uploads nprob independent hierarchies (each parsed by mvamg_hier_read, all
-   with the same number of levels) as one block-diagonal hierarchy: level l
-   holds level l of every problem, smoother stage c holds stage c of every
-   problem, and every problem keeps its own coarsest inverse.  Each launch of
-   a level kernel then covers the same step of all problems.  Vectors of a
-   batch are the problems' vectors one after another (problem p at rows
-   offsets[p] .. offsets[p+1]-1 of mvamg_batch_problems).  The handle is
-   released with mvamg_free; mvamg_spmv, mvamg_cycle_apply (block diagonal)
-   and mvamg_set_fine_values accept it, mvamg_pcg_solve does not.  The
+/* Uploads nprob independent hierarchies (each parsed by mvamg_hier_read) as
+   one batch.  Vectors of a batch are the problems' vectors one after another
+   (problem p at rows offsets[p] .. offsets[p+1]-1 of mvamg_batch_problems).
+   The problems are split between two paths:
+   - the small-problem path: every problem with at most mini_rows rows, and
+     every problem whose level count differs from the most common one among
+     the others, is solved by one persistent launch in which one workgroup
+     runs the whole CG and V-cycle of a problem over its own hierarchy (any
+     depth from 2 to 16 levels, coarsest at most 2048 rows), using only
+     workgroup barriers; the workgroups stride over the problems;
+   - the lockstep path: the other problems form one block-diagonal hierarchy
+     (level l holds level l of every such problem, smoother stage c holds
+     stage c of every problem, every problem keeps its own coarsest inverse),
+     and each launch of a level kernel covers the same step of all of them.
+   mini_rows = 0 puts everything on the lockstep path unless the level counts
+   differ.  The handle is released with mvamg_free; mvamg_spmv,
+   mvamg_cycle_apply (block diagonal) and mvamg_set_fine_values accept it
+   when no problem is on the small path; mvamg_pcg_solve does not.  The
    caller owns the device memory, as for mvamg_upload: *bytes of
    mvamg_batch_arena_bytes (host only) is the arena mvamg_batch_upload needs.
-   Errors: MVAMG_ERR_ARG (level counts differ, too large, arena too small),
-   as mvamg_upload. */
-mvamg_status mvamg_batch_arena_bytes(const mvamg_hier_host* const* hs, int nprob, size_t* bytes);
-mvamg_status mvamg_batch_upload(const mvamg_hier_host* const* hs, int nprob, void* arena_dev, size_t arena_bytes,
-                                void* stream, mvamg_hier** out);
+   Errors: MVAMG_ERR_ARG (too large, arena too small), as mvamg_upload. */
+mvamg_status mvamg_batch_arena_bytes(const mvamg_hier_host* const* hs, int nprob, int mini_rows, size_t* bytes);
+mvamg_status mvamg_batch_upload(const mvamg_hier_host* const* hs, int nprob, int mini_rows, void* arena_dev,
+                                size_t arena_bytes, void* stream, mvamg_hier** out);
+
+/* flags[p] (nprob entries) = 1 if problem p is on the small-problem path. */
+mvamg_status mvamg_batch_small_path(const mvamg_hier* h, int* flags);
 
 /* Problem count (0 for a single-problem handle) and row offsets
    (nprob + 1 entries, may be NULL). */
@@ -281,7 +292,10 @@ mvamg_status mvamg_batch_problems(const mvamg_hier* h, int* nprob, int* offsets)
 /* Preconditioned CG on every problem of a batch, each with its own
    recurrence, stopping test and restarts (as mvamg_pcg_solve_block with
    problems in place of columns; info and history have nprob entries /
-   rows). */
+   rows).  With problems on the small-problem path: precision 64 only and
+   maxit at most 1000; that path's launch runs on a second stream of the
+   handle while the lockstep path runs on `stream`, and the call returns when
+   both are done. */
 mvamg_status mvamg_batch_pcg_solve(mvamg_hier* h, const double* b_dev, double* x_dev,
                                    const mvamg_solve_params* prm, mvamg_info* info, void* stream);
 
@@ -322,6 +336,59 @@ mvamg_status mvamg_composite_test(mvamg_hier* const* hs, int r, int cycle, int s
 mvamg_status mvamg_composite_pcg_solve(mvamg_hier* const* hs, int r, const double* b_dev, double* x_dev,
                                        const mvamg_solve_params* prm, mvamg_info* info, void* work_dev,
                                        size_t work_bytes, void* stream);
+
+/* ------------------------------------------ numeric setup of a level */
+
+/* One multiple-vector level's numeric setup on the device (Section 4):
+   the local bases (eq. 4.3), the Galerkin coarse matrix A_c = P^T A P with
+   P = blockdiag(U_a), and the smooth vectors on the coarse level (Section
+   4.1).  The aggregates come from the host setup (matching and composition,
+   Sections 3 and 4).  Arrays are device arrays unless stated; the caller
+   owns all of them.  Aggregate a has the members arows[aptr[a] ..
+   aptr[a+1]) (rows of the level, 0-based).
+
+   Bases: W (n_level x m, row-major, 1 <= m <= 16) holds the smooth vectors on
+   the level.  For every aggregate, the singular value decomposition of its
+   n_a x m block (one-sided Jacobi) gives the left singular vectors whose
+   singular values exceed TOL_a = tol * n_a / n_level, at least one and at
+   most min(n_a, m) (Section 5: TOL = 0.1), each with its entry of largest
+   magnitude (lowest row on ties) positive.  Outputs: k[a] (nagg) the number
+   kept; U (n_level x m, row-major, laid out like the members: row
+   aptr[a] + i holds member i's entries of u_0 .. u_{k_a - 1}, then zeros);
+   dropped[a] the sum of the squared singular values not kept; flag: one int
+   of scratch.  max_na bounds every n_a (max_na * m <= 8192).
+   MVAMG_ERR_ARG for sizes out of range or an aggregate whose smooth vectors
+   are all zero. */
+mvamg_status mvamg_setup_bases(int n_level, int m, int nagg, int max_na, const int* aptr_dev,
+                               const int* arows_dev, const double* W_dev, double tol, int* k_dev, double* U_dev,
+                               double* dropped_dev, int* flag_dev, void* stream);
+
+/* Coarse pattern of P^T A P, on the host (host arrays): A's pattern (rowptr,
+   col), the aggregates and the widths k.  Fills agg (n: aggregate of each
+   row), loc (n: the row's place among its aggregate's members), coff
+   (nagg + 1: first coarse dof of each aggregate), cagg (nc = coff[nagg]:
+   aggregate of each coarse dof), and *nnz (coarse nonzeros); when crp and
+   ccol are not NULL, also crp (nc + 1) and ccol (*nnz, sorted rows).  The
+   rows of aggregate a couple to every dof of every aggregate that A couples
+   a's rows to.  MVAMG_ERR_ARG if the aggregates do not partition the rows. */
+mvamg_status mvamg_setup_pattern(int n, const int* rowptr, const int* col, int nagg, const int* aptr,
+                                 const int* arows, const int* k, int* agg, int* loc, int* coff, int* cagg,
+                                 int* crp, int* ccol, int64_t* nnz);
+
+/* Values of A_c = P^T A P on the pattern of mvamg_setup_pattern (all arrays
+   on the device, as that call and mvamg_setup_bases produced them): each
+   entry sums U_a[i][l] a_ij U_b[j][mm] over the fine entries between the two
+   aggregates in a fixed order, and (A_c + A_c^T) / 2 is stored, so cval is
+   exactly symmetric.  work: nnz doubles of scratch; flag: one int. */
+mvamg_status mvamg_setup_galerkin(int m, int nagg, int nc, const int* aptr_dev, const int* arows_dev,
+                                  const int* coff_dev, const int* agg_dev, const int* loc_dev, const int* cagg_dev,
+                                  const int* rowptr_dev, const int* col_dev, const double* val_dev,
+                                  const double* U_dev, const int* crp_dev, const int* ccol_dev, double* cval_dev,
+                                  double* work_dev, int* flag_dev, void* stream);
+
+/* The smooth vectors on the coarse level: Wc = P^T W (nc x m, row-major). */
+mvamg_status mvamg_setup_restrict(int m, int nagg, const int* aptr_dev, const int* arows_dev, const int* coff_dev,
+                                  const double* U_dev, const double* W_dev, double* Wc_dev, void* stream);
 
 /* --------------------------------------------------------- autotuning */
 

@@ -290,6 +290,17 @@ __global__ __launch_bounds__(kBlock) void k_div(int n, double d, double* __restr
   for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) x[p] = x[p] / d;
 }
 
+// out[p] = in[map[perm[p]]] and its inverse: a batch's part in its own
+// numbering, read from and written to the caller's rows
+__global__ __launch_bounds__(kBlock) void k_gather2(int n, const int* __restrict__ perm, const int* __restrict__ map,
+                                                    const double* __restrict__ in, double* __restrict__ out) {
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) out[p] = in[map[perm[p]]];
+}
+__global__ __launch_bounds__(kBlock) void k_scatter2(int n, const int* __restrict__ perm, const int* __restrict__ map,
+                                                     const double* __restrict__ in, double* __restrict__ out) {
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) out[map[perm[p]]] = in[p];
+}
+
 // out[perm[p]] += s in[p] (perm a permutation: no two threads write one entry)
 __global__ __launch_bounds__(kBlock) void k_scatter_axpy(int n, const int* __restrict__ perm, double s,
                                                          const double* __restrict__ in, double* __restrict__ out) {

@@ -113,7 +113,8 @@ bool block_fits(const mvamg_hier* h) { return h->blk_ready || h->fits(block_requ
 
 void ensure_block(mvamg_hier* h) {
   if (h->blk_ready) return;
-  if (h->nprob > 0) throw Error(MVAMG_ERR_ARG, "block right-hand sides are not supported on a batch of problems");
+  if (h->nprob > 0 || h->nall > 0)
+    throw Error(MVAMG_ERR_ARG, "block right-hand sides are not supported on a batch of problems");
   for (int l = 0; l < h->nl; ++l)
     if ((int64_t)h->lev_n[l] * kNB >= ((int64_t)1 << 31)) throw Error(MVAMG_ERR_ARG, "level too large for 32-column blocks");
   if (!block_fits(h))
@@ -647,13 +648,23 @@ struct BatchOps : MultiOps {
   };
   const double* act() const { return h->mb.scal + S_ACT; }
   dim3 pgrid() const { return dim3(h->pchunks, h->nprob); }
+  // with problems on the small-problem path, the caller's vectors hold every
+  // problem: umap takes a row of this part to the caller's row
   void load(const double* b, const double* x, hipStream_t st) override {
-    k_gather<<<grid_for(h->n), kBlock, 0, st>>>(h->n, h->perm0, b, h->b);
-    k_gather<<<grid_for(h->n), kBlock, 0, st>>>(h->n, h->perm0, x, h->x);
+    if (h->umap) {
+      k_gather2<<<grid_for(h->n), kBlock, 0, st>>>(h->n, h->perm0, h->umap, b, h->b);
+      k_gather2<<<grid_for(h->n), kBlock, 0, st>>>(h->n, h->perm0, h->umap, x, h->x);
+    } else {
+      k_gather<<<grid_for(h->n), kBlock, 0, st>>>(h->n, h->perm0, b, h->b);
+      k_gather<<<grid_for(h->n), kBlock, 0, st>>>(h->n, h->perm0, x, h->x);
+    }
     LAUNCHCHECK("gather");
   }
   void store(double* x, hipStream_t st) override {
-    k_scatter<<<grid_for(h->n), kBlock, 0, st>>>(h->n, h->perm0, h->x, x);
+    if (h->umap)
+      k_scatter2<<<grid_for(h->n), kBlock, 0, st>>>(h->n, h->perm0, h->umap, h->x, x);
+    else
+      k_scatter<<<grid_for(h->n), kBlock, 0, st>>>(h->n, h->perm0, h->x, x);
     LAUNCHCHECK("scatter");
   }
   void resid(hipStream_t st) override { ::resid<double, 0>(h, 0, h->lv[0], h->b, h->x, r, M_NONE, st); }

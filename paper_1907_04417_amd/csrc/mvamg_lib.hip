@@ -19,6 +19,8 @@
 #include "dense.hpp"
 #include "kernels.hpp"
 #include "kernels_multi.hpp"
+#include "setup_kernels.hpp"
+#include "mini_kernels.hpp"
 #include "mvamg.h"
 
 using namespace mvamg;
@@ -201,6 +203,20 @@ struct mvamg_hier {
   int nprob = 0;
   int pchunks = 1;
   std::vector<int> h_poff;
+  // batch with problems on the one-launch small-problem path: the caller's
+  // view (all problems, their row offsets), which of them form the lockstep
+  // part above (uid) and which the small path (mid), and the small path's data
+  int nall = 0;
+  std::vector<int> h_aoff, uid, mid;
+  int* umap = nullptr;  // lockstep part's row -> caller's row
+  int nmini = 0, mini_maxit = 0;
+  MiniProb* mprobs = nullptr;
+  MiniLevel* mlevs = nullptr;
+  int* mints = nullptr;
+  double *mdbls = nullptr, *mwork = nullptr, *mhist = nullptr;
+  MiniInfo* minfo = nullptr;
+  hipStream_t mstream = nullptr;
+  hipEvent_t mev[2] = {nullptr, nullptr};
   int* poff = nullptr;
   int* iperm0 = nullptr;
   // while set (batch CG iterations), level-0 kernels skip the work units of
@@ -289,6 +305,9 @@ struct mvamg_hier {
     }
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
     if (cap) (void)hipStreamDestroy(cap);
+    if (mstream) (void)hipStreamDestroy(mstream);
+    for (hipEvent_t e : mev)
+      if (e) (void)hipEventDestroy(e);
     if (pinned) (void)hipHostFree(pinned);
     if (mb.pinned) (void)hipHostFree(mb.pinned);
     if (mb.pact) (void)hipHostFree(mb.pact);
@@ -857,6 +876,12 @@ mvamg_status fail_status(const Error& e) {
   return (mvamg_status)e.status;
 }
 
+// Calls that need the whole batch in one hierarchy
+void no_small_path(const mvamg_hier* h) {
+  if (h->nmini > 0 || h->nl == 0)
+    throw Error(MVAMG_ERR_ARG, "not available on a batch with problems on the small-problem path");
+}
+
 void check_device(const mvamg_hier* h) {
   int dev = -1;
   HIPCHECK(hipGetDevice(&dev));
@@ -982,7 +1007,7 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
   if (prm->cycle == MVAMG_CYCLE_K && prm->precision != 64)
     throw Error(MVAMG_ERR_ARG, "the K-cycle runs in binary64 only");
   if (prm->maxit < 0 || !(prm->rtol >= 0.0)) throw Error(MVAMG_ERR_ARG, "invalid maxit or rtol");
-  if (h->nprob > 0) throw Error(MVAMG_ERR_ARG, "a batch handle is solved with mvamg_batch_pcg_solve");
+  if (h->nprob > 0 || h->nall > 0) throw Error(MVAMG_ERR_ARG, "a batch handle is solved with mvamg_batch_pcg_solve");
   check_device(h);
   const int n = h->n;
   const int eg = grid_for(n);
@@ -1473,6 +1498,8 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
 #include "multi_host.hpp"
 #include "tune_host.hpp"
 #include "composite_host.hpp"
+#include "setup_host.hpp"
+#include "mini_host.hpp"
 
 }  // namespace
 
@@ -1591,35 +1618,147 @@ class ScratchWork {
 
 namespace {
 
-// Uploads (or, with a null arena, sizes) a batch as one block-diagonal hierarchy.
-std::unique_ptr<mvamg_hier> upload_batch(const mvamg_hier_host* const* hs, int nprob, hipStream_t st, void* arena,
-                                         size_t arena_bytes) {
+// Uploads (or, with a null arena, sizes) a batch.  Problems with at most
+// mini_rows rows, and problems whose level count differs from that of the
+// most common one among the others, take the one-launch small-problem path
+// (mini_kernels.hpp); the rest form one block-diagonal hierarchy solved by
+// lockstep launches.
+std::unique_ptr<mvamg_hier> upload_batch(const mvamg_hier_host* const* hs, int nprob, int mini_rows, hipStream_t st,
+                                         void* arena, size_t arena_bytes) {
   if (!hs || nprob < 1) throw Error(MVAMG_ERR_ARG, "null argument or empty batch");
-  std::vector<const HostHier*> Hs;
+  if (mini_rows < 0) throw Error(MVAMG_ERR_ARG, "negative small-problem threshold");
+  std::vector<const HostHier*> all;
   for (int p = 0; p < nprob; ++p) {
     if (!hs[p]) throw Error(MVAMG_ERR_ARG, "null hierarchy in batch");
-    Hs.push_back(&hs[p]->h);
+    all.push_back(&hs[p]->h);
   }
-  const HostHier U = union_hierarchy(Hs);
-  if (U.nl < 2) throw Error(MVAMG_ERR_ARG, "hierarchy needs at least two levels");
-  std::vector<const HostLevel*> cb;
-  for (const HostHier* H : Hs) cb.push_back(&H->lv[H->nl - 1]);
-  std::vector<int> rowprob0;
-  for (int p = 0; p < nprob; ++p) rowprob0.insert(rowprob0.end(), Hs[p]->lv[0].n, p);
-  std::unique_ptr<mvamg_hier> h = upload_hier(U, cb, st, &rowprob0, arena, arena_bytes);
-  h->nprob = nprob;
-  h->h_poff.assign(nprob + 1, 0);
-  int maxn = 1;
-  for (int p = 0; p < nprob; ++p) {
-    h->h_poff[p + 1] = h->h_poff[p] + Hs[p]->lv[0].n;
-    maxn = std::max(maxn, Hs[p]->lv[0].n);
+  // the lockstep part: the problems above the threshold with the most common depth
+  std::map<int, int> depth;
+  for (const HostHier* H : all)
+    if (H->lv[0].n > mini_rows) depth[H->nl]++;
+  int dstar = -1, best = 0;
+  for (auto& d : depth)
+    if (d.second > best) {
+      best = d.second;
+      dstar = d.first;
+    }
+  std::vector<int> uid, mid;
+  for (int p = 0; p < nprob; ++p) (all[p]->lv[0].n > mini_rows && all[p]->nl == dstar ? uid : mid).push_back(p);
+  std::vector<int> aoff(nprob + 1, 0);
+  for (int p = 0; p < nprob; ++p) aoff[p + 1] = aoff[p] + all[p]->lv[0].n;
+  std::unique_ptr<mvamg_hier> h;
+  if (!uid.empty()) {
+    std::vector<const HostHier*> Hs;
+    for (int p : uid) Hs.push_back(all[p]);
+    const HostHier U = union_hierarchy(Hs);
+    if (U.nl < 2) throw Error(MVAMG_ERR_ARG, "hierarchy needs at least two levels");
+    std::vector<const HostLevel*> cb;
+    for (const HostHier* H : Hs) cb.push_back(&H->lv[H->nl - 1]);
+    std::vector<int> rowprob0;
+    for (size_t q = 0; q < Hs.size(); ++q) rowprob0.insert(rowprob0.end(), Hs[q]->lv[0].n, (int)q);
+    h = upload_hier(U, cb, st, &rowprob0, arena, arena_bytes);
+    const int nu = (int)uid.size();
+    h->nprob = nu;
+    h->h_poff.assign(nu + 1, 0);
+    int maxn = 1;
+    for (int q = 0; q < nu; ++q) {
+      h->h_poff[q + 1] = h->h_poff[q] + Hs[q]->lv[0].n;
+      maxn = std::max(maxn, Hs[q]->lv[0].n);
+    }
+    h->poff = h->upload_vec(h->h_poff, st);
+    h->pchunks = std::min(kMaxChunks, std::max(1, (maxn + 2047) / 2048));
+    // room for every chunk count the autotuner may choose, so nothing grows later
+    ensure_multi(h.get(), nu, kMaxChunks);
+    if (!mid.empty()) {
+      std::vector<int> umap(h->n);
+      for (int q = 0; q < nu; ++q)
+        for (int i = h->h_poff[q]; i < h->h_poff[q + 1]; ++i) umap[i] = aoff[uid[q]] + (i - h->h_poff[q]);
+      h->umap = h->upload_vec(umap, st);
+    }
+  } else {
+    // every problem on the small path: a handle without levels
+    h.reset(new mvamg_hier);
+    h->arena = (unsigned char*)arena;
+    h->arena_cap = arena_bytes;
+    if (arena && reinterpret_cast<uintptr_t>(arena) % 256 != 0)
+      throw Error(MVAMG_ERR_ARG, "device arena must be 256-byte aligned");
+    if (!h->sizing()) HIPCHECK(hipGetDevice(&h->device));
   }
-  h->poff = h->upload_vec(h->h_poff, st);
-  h->pchunks = std::min(kMaxChunks, std::max(1, (maxn + 2047) / 2048));
-  // room for every chunk count the autotuner may choose, so nothing grows later
-  ensure_multi(h.get(), nprob, kMaxChunks);
+  h->nall = nprob;
+  h->h_aoff = aoff;
+  h->uid = uid;
+  h->mid = mid;
+  if (!mid.empty()) {
+    MiniBuild B;
+    for (int p : mid) mini_add(B, *all[p], aoff[p]);
+    h->nmini = (int)mid.size();
+    h->mini_maxit = kMiniMaxIt;
+    std::vector<int> pb(B.probs.size() * sizeof(MiniProb) / sizeof(int) + 1);
+    std::memcpy(pb.data(), B.probs.data(), B.probs.size() * sizeof(MiniProb));
+    std::vector<int> lb(B.levs.size() * sizeof(MiniLevel) / sizeof(int) + 1);
+    std::memcpy(lb.data(), B.levs.data(), B.levs.size() * sizeof(MiniLevel));
+    h->mprobs = reinterpret_cast<MiniProb*>(h->upload_vec(pb, st));
+    h->mlevs = reinterpret_cast<MiniLevel*>(h->upload_vec(lb, st));
+    h->mints = h->upload_vec(B.ints, st);
+    h->mdbls = h->upload_vec(B.dbls, st);
+    h->mwork = h->dalloc<double>((size_t)B.work);
+    h->mhist = h->dalloc<double>((size_t)h->nmini * (kMiniMaxIt + 1));
+    h->minfo = reinterpret_cast<MiniInfo*>(h->dalloc<double>((size_t)h->nmini * (sizeof(MiniInfo) / sizeof(double) + 1)));
+    if (!h->sizing()) {
+      HIPCHECK(hipStreamCreateWithFlags(&h->mstream, hipStreamNonBlocking));
+      HIPCHECK(hipEventCreateWithFlags(&h->mev[0], hipEventDisableTiming));
+      HIPCHECK(hipEventCreateWithFlags(&h->mev[1], hipEventDisableTiming));
+    }
+  }
   if (!h->sizing()) HIPCHECK(hipStreamSynchronize(st));
   return h;
+}
+
+// The small-problem path's solve (prm->precision 64): one launch on the
+// handle's second stream, ordered after the work queued on st so far; returns
+// after queuing.  mini_collect waits for it and writes the results.
+void mini_launch(mvamg_hier* h, const double* b, double* x, const mvamg_solve_params* prm, hipStream_t st) {
+  if (prm->maxit > h->mini_maxit) throw Error(MVAMG_ERR_ARG, "small-problem path: maxit above 1000");
+  HIPCHECK(hipEventRecord(h->mev[0], st));
+  HIPCHECK(hipStreamWaitEvent(h->mstream, h->mev[0], 0));
+  const int grid = std::min(h->nmini, 1024);
+  k_mini_pcg<<<grid, kMiniBlock, 0, h->mstream>>>(h->nmini, h->mprobs, h->mlevs, h->mints, h->mdbls, h->mwork, b,
+                                                    x, prm->rtol, prm->maxit, prm->smoother, h->mhist, h->minfo);
+  LAUNCHCHECK("mini_pcg");
+  HIPCHECK(hipEventRecord(h->mev[1], h->mstream));
+}
+
+// Waits for the small path and writes its problems' info and history (the
+// caller's order: problem mid[q]); returns whether all converged.
+bool mini_collect(mvamg_hier* h, const mvamg_solve_params* prm, mvamg_info* info, hipStream_t st) {
+  HIPCHECK(hipStreamWaitEvent(st, h->mev[1], 0));
+  std::vector<MiniInfo> mi(h->nmini);
+  HIPCHECK(hipMemcpyAsync(mi.data(), h->minfo, sizeof(MiniInfo) * h->nmini, hipMemcpyDeviceToHost, st));
+  std::vector<double> hist;
+  if (prm->history) {
+    hist.resize((size_t)h->nmini * (h->mini_maxit + 1));
+    HIPCHECK(hipMemcpyAsync(hist.data(), h->mhist, sizeof(double) * hist.size(), hipMemcpyDeviceToHost, st));
+  }
+  HIPCHECK(hipStreamSynchronize(st));
+  bool all = true;
+  for (int q = 0; q < h->nmini; ++q) {
+    const MiniInfo& m = mi[q];
+    if (m.status == -5) throw Error(MVAMG_ERR_BREAKDOWN, "CG breakdown: p^T A p <= 0 (matrix not s.p.d.)");
+    if (m.status == -4) throw Error(MVAMG_ERR_NONFINITE, "non-finite residual during CG");
+    const int p = h->mid[q];
+    if (info) {
+      info[p].iterations = m.iterations;
+      info[p].converged = m.converged;
+      info[p].restarts = 0;
+      info[p].rel_res = m.rel_res;
+      info[p].rel_res_true = m.rel_res_true;
+    }
+    if (prm->history)
+      for (int k = 0; k <= m.iterations; ++k)
+        prm->history[(size_t)p * (prm->maxit + 1) + k] = hist[(size_t)q * (h->mini_maxit + 1) + k];
+    all = all && m.converged;
+  }
+  return all;
 }
 
 }  // namespace
@@ -1729,10 +1868,10 @@ mvamg_status mvamg_upload(const mvamg_hier_host* hh, void* arena, size_t arena_b
   }
 }
 
-mvamg_status mvamg_batch_arena_bytes(const mvamg_hier_host* const* hs, int nprob, size_t* bytes) {
+mvamg_status mvamg_batch_arena_bytes(const mvamg_hier_host* const* hs, int nprob, int mini_rows, size_t* bytes) {
   try {
     if (!bytes) throw Error(MVAMG_ERR_ARG, "null argument");
-    *bytes = upload_batch(hs, nprob, nullptr, nullptr, 0)->arena_peak;
+    *bytes = upload_batch(hs, nprob, mini_rows, nullptr, nullptr, 0)->arena_peak;
     return MVAMG_OK;
   } catch (const Error& e) {
     return fail_status(e);
@@ -1742,13 +1881,13 @@ mvamg_status mvamg_batch_arena_bytes(const mvamg_hier_host* const* hs, int nprob
   }
 }
 
-mvamg_status mvamg_batch_upload(const mvamg_hier_host* const* hs, int nprob, void* arena, size_t arena_bytes,
-                                void* stream, mvamg_hier** out) {
+mvamg_status mvamg_batch_upload(const mvamg_hier_host* const* hs, int nprob, int mini_rows, void* arena,
+                                size_t arena_bytes, void* stream, mvamg_hier** out) {
   hipStream_t st = (hipStream_t)stream;
   try {
     if (!out || !arena) throw Error(MVAMG_ERR_ARG, "null argument");
     *out = nullptr;
-    *out = upload_batch(hs, nprob, st, arena, arena_bytes).release();
+    *out = upload_batch(hs, nprob, mini_rows, st, arena, arena_bytes).release();
     return MVAMG_OK;
   } catch (const Error& e) {
     if (st) (void)hipStreamSynchronize(st);
@@ -1764,9 +1903,23 @@ mvamg_status mvamg_batch_problems(const mvamg_hier* h, int* nprob, int* offsets)
     g_err = "null handle";
     return MVAMG_ERR_ARG;
   }
-  if (nprob) *nprob = h->nprob;
+  // the caller's view: every problem of the batch, on either path
+  const int np = h->nall > 0 ? h->nall : h->nprob;
+  const std::vector<int>& off = h->nall > 0 ? h->h_aoff : h->h_poff;
+  if (nprob) *nprob = np;
   if (offsets)
-    for (int p = 0; p <= h->nprob && h->nprob > 0; ++p) offsets[p] = h->h_poff[p];
+    for (int p = 0; p <= np && np > 0; ++p) offsets[p] = off[p];
+  return MVAMG_OK;
+}
+
+mvamg_status mvamg_batch_small_path(const mvamg_hier* h, int* flags) {
+  if (!h || !flags) {
+    g_err = "null argument";
+    return MVAMG_ERR_ARG;
+  }
+  const int np = h->nall > 0 ? h->nall : h->nprob;
+  for (int p = 0; p < np; ++p) flags[p] = 0;
+  for (int p : h->mid) flags[p] = 1;
   return MVAMG_OK;
 }
 
@@ -1805,6 +1958,7 @@ mvamg_status mvamg_transfers(const mvamg_hier* h, int* nagg, int64_t* nu) {
 mvamg_status mvamg_set_fine_values(mvamg_hier* h, const double* val, void* stream) {
   try {
     if (!h || !val) throw Error(MVAMG_ERR_ARG, "null argument");
+    no_small_path(h);
     check_device(h);
     hipStream_t st = (hipStream_t)stream;
     refill_fine(h, val, st);
@@ -1817,6 +1971,7 @@ mvamg_status mvamg_set_fine_values(mvamg_hier* h, const double* val, void* strea
 mvamg_status mvamg_spmv(mvamg_hier* h, const double* x, double* y, void* stream) {
   try {
     if (!h || !x || !y) throw Error(MVAMG_ERR_ARG, "null argument");
+    no_small_path(h);
     check_device(h);
     hipStream_t st = (hipStream_t)stream;
     const int eg = grid_for(h->n);
@@ -1838,6 +1993,7 @@ mvamg_status mvamg_cycle_apply(mvamg_hier* h, const double* r, double* z, int pr
     if (precision != 64 && precision != 32) throw Error(MVAMG_ERR_ARG, "precision must be 64 or 32");
     if (smoother != MVAMG_SMOOTH_GS && smoother != MVAMG_SMOOTH_L1JACOBI) throw Error(MVAMG_ERR_ARG, "unknown smoother");
     check_device(h);
+    no_small_path(h);
     hipStream_t st = (hipStream_t)stream;
     const int eg = grid_for(h->n);
     k_gather<<<eg, kBlock, 0, st>>>(h->n, h->perm0, r, h->r);
@@ -1856,6 +2012,7 @@ mvamg_status mvamg_kcycle_apply(mvamg_hier* h, const double* r, double* z, int s
     if (r == z) throw Error(MVAMG_ERR_ARG, "r and z must not alias");
     if (smoother != MVAMG_SMOOTH_GS && smoother != MVAMG_SMOOTH_L1JACOBI) throw Error(MVAMG_ERR_ARG, "unknown smoother");
     check_device(h);
+    no_small_path(h);
     hipStream_t st = (hipStream_t)stream;
     const int eg = grid_for(h->n);
     k_gather<<<eg, kBlock, 0, st>>>(h->n, h->perm0, r, h->r);
@@ -1876,6 +2033,7 @@ mvamg_status mvamg_cycle_apply_noalloc(mvamg_hier* h, const double* r, double* z
     if (precision != 64 && precision != 32) throw Error(MVAMG_ERR_ARG, "precision must be 64 or 32");
     if (smoother != MVAMG_SMOOTH_GS && smoother != MVAMG_SMOOTH_L1JACOBI) throw Error(MVAMG_ERR_ARG, "unknown smoother");
     check_device(h);
+    no_small_path(h);
     if (h->prof) throw Error(MVAMG_ERR_ARG, "measurement is on (mvamg_profile): its events are created per launch");
     const size_t need = ScratchWork(h, precision, nullptr).bytes();
     if (need > (size_t)MVAMG_NOALLOC_SCRATCH_BYTES)
@@ -1900,7 +2058,7 @@ mvamg_status mvamg_pcg_solve(mvamg_hier* h, const int* rowptr, const int* col, c
   try {
     if (!h) throw Error(MVAMG_ERR_ARG, "null handle");
     if (!prm || !b || !x) throw Error(MVAMG_ERR_ARG, "null argument");
-    if (h->nprob > 0) throw Error(MVAMG_ERR_ARG, "a batch handle is solved with mvamg_batch_pcg_solve");
+    if (h->nprob > 0 || h->nall > 0) throw Error(MVAMG_ERR_ARG, "a batch handle is solved with mvamg_batch_pcg_solve");
     check_device(h);
     use_matrix(h, rowptr, col, val, (hipStream_t)stream);
     return pcg(h, b, x, prm, info, (hipStream_t)stream);
@@ -1914,7 +2072,7 @@ mvamg_status mvamg_adjoint_solve(mvamg_hier* h, const int* rowptr, const int* co
                                  void* stream) {
   try {
     if (!h || !lambda || !prm || !dLdx) throw Error(MVAMG_ERR_ARG, "null argument");
-    if (h->nprob > 0) throw Error(MVAMG_ERR_ARG, "a batch handle is solved with mvamg_batch_pcg_solve");
+    if (h->nprob > 0 || h->nall > 0) throw Error(MVAMG_ERR_ARG, "a batch handle is solved with mvamg_batch_pcg_solve");
     check_device(h);
     hipStream_t st = (hipStream_t)stream;
     use_matrix(h, rowptr, col, val, st);
@@ -1929,6 +2087,7 @@ mvamg_status mvamg_grad_coeffs(mvamg_hier* h, const double* lambda, const double
   try {
     if (!h || !lambda || !x || !dval) throw Error(MVAMG_ERR_ARG, "null argument");
     check_device(h);
+    no_small_path(h);
     hipStream_t st = (hipStream_t)stream;
     k_grad_coeffs<<<grid_for(h->n), kBlock, 0, st>>>(h->n, h->frp, h->fci, lambda, x, dval);
     LAUNCHCHECK("grad_coeffs");
@@ -1996,11 +2155,113 @@ mvamg_status mvamg_batch_pcg_solve(mvamg_hier* h, const double* b, double* x, co
                                    mvamg_info* info, void* stream) {
   try {
     if (!h) throw Error(MVAMG_ERR_ARG, "null handle");
-    if (h->nprob < 1) throw Error(MVAMG_ERR_ARG, "not a batch handle (use mvamg_pcg_solve)");
+    if (h->nprob < 1 && h->nall < 1) throw Error(MVAMG_ERR_ARG, "not a batch handle (use mvamg_pcg_solve)");
     if (prm && prm->cycle != MVAMG_CYCLE_V) throw Error(MVAMG_ERR_ARG, "batch solves run the V-cycle only");
     check_device(h);
-    BatchOps O(h);
-    return multi_pcg(O, b, x, prm, info, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    if (h->nmini == 0) {
+      BatchOps O(h);
+      return multi_pcg(O, b, x, prm, info, st);
+    }
+    // problems on the small path: one launch on the second stream, the
+    // lockstep part meanwhile on st; results in the caller's problem order
+    if (!prm || !b || !x) throw Error(MVAMG_ERR_ARG, "null argument");
+    if (prm->precision != 64) throw Error(MVAMG_ERR_ARG, "the small-problem path runs the binary64 cycle only");
+    if (prm->smoother != MVAMG_SMOOTH_GS && prm->smoother != MVAMG_SMOOTH_L1JACOBI)
+      throw Error(MVAMG_ERR_ARG, "unknown smoother");
+    if (prm->maxit < 0 || !(prm->rtol >= 0.0)) throw Error(MVAMG_ERR_ARG, "invalid maxit or rtol");
+    mini_launch(h, b, x, prm, st);
+    mvamg_status su = MVAMG_OK;
+    try {
+      if (h->nprob > 0) {
+        const int nu = h->nprob;
+        std::vector<mvamg_info> ui(nu);
+        std::vector<double> uh;
+        mvamg_solve_params up = *prm;
+        if (prm->history) {
+          uh.assign((size_t)nu * (prm->maxit + 1), 0.0);
+          up.history = uh.data();
+        }
+        BatchOps O(h);
+        su = multi_pcg(O, b, x, &up, ui.data(), st);
+        for (int q = 0; q < nu; ++q) {
+          const int p = h->uid[q];
+          if (info) info[p] = ui[q];
+          if (prm->history)
+            std::memcpy(prm->history + (size_t)p * (prm->maxit + 1), uh.data() + (size_t)q * (prm->maxit + 1),
+                        sizeof(double) * (prm->maxit + 1));
+        }
+      }
+    } catch (...) {
+      (void)hipStreamSynchronize(h->mstream);
+      throw;
+    }
+    const bool mall = mini_collect(h, prm, info, st);
+    return (su == MVAMG_OK && mall) ? MVAMG_OK : MVAMG_NOT_CONVERGED;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_setup_bases(int n_level, int m, int nagg, int max_na, const int* aptr, const int* arows,
+                               const double* W, double tol, int* k, double* U, double* dropped, int* flag,
+                               void* stream) {
+  try {
+    if (!aptr || !arows || !W || !k || !U || !dropped || !flag) throw Error(MVAMG_ERR_ARG, "null argument");
+    setup_bases(m, nagg, max_na, aptr, arows, W, tol, n_level, k, U, dropped, flag, (hipStream_t)stream);
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_setup_pattern(int n, const int* rowptr, const int* col, int nagg, const int* aptr,
+                                 const int* arows, const int* k, int* agg, int* loc, int* coff, int* cagg,
+                                 int* crp, int* ccol, int64_t* nnz) {
+  try {
+    if (!rowptr || !col || !aptr || !arows || !k || !agg || !loc || !coff || !cagg || !nnz)
+      throw Error(MVAMG_ERR_ARG, "null argument");
+    if ((crp == nullptr) != (ccol == nullptr)) throw Error(MVAMG_ERR_ARG, "crp and ccol are passed together");
+    *nnz = galerkin_pattern(n, rowptr, col, nagg, aptr, arows, k, agg, loc, coff, cagg, crp, ccol);
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_setup_galerkin(int m, int nagg, int nc, const int* aptr, const int* arows, const int* coff,
+                                  const int* agg, const int* loc, const int* cagg, const int* rowptr, const int* col,
+                                  const double* val, const double* U, const int* crp, const int* ccol,
+                                  double* cval, double* work, int* flag, void* stream) {
+  try {
+    if (!aptr || !arows || !coff || !agg || !loc || !cagg || !rowptr || !col || !val || !U || !crp || !ccol ||
+        !cval || !work || !flag)
+      throw Error(MVAMG_ERR_ARG, "null argument");
+    if (m < 1 || m > kSvdMaxM || nagg < 1 || nc < 1) throw Error(MVAMG_ERR_ARG, "sizes out of range");
+    hipStream_t st = (hipStream_t)stream;
+    k_fill<int><<<1, kBlock, 0, st>>>(1, 0, flag);
+    k_setup_galerkin<<<nagg, 64, 0, st>>>(m, nagg, aptr, arows, coff, agg, loc, cagg, rowptr, col, val, U, crp,
+                                          ccol, work);
+    k_symmetrize<<<grid_for(nc), kBlock, 0, st>>>(nc, crp, ccol, work, cval, flag);
+    LAUNCHCHECK("setup_galerkin");
+    int hflag = 0;
+    HIPCHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    if (hflag) throw Error(MVAMG_ERR_ARG, "coarse pattern is not symmetric (A's pattern must be)");
+    return MVAMG_OK;
+  } catch (const Error& e) {
+    return fail_status(e);
+  }
+}
+
+mvamg_status mvamg_setup_restrict(int m, int nagg, const int* aptr, const int* arows, const int* coff,
+                                  const double* U, const double* W, double* Wc, void* stream) {
+  try {
+    if (!aptr || !arows || !coff || !U || !W || !Wc) throw Error(MVAMG_ERR_ARG, "null argument");
+    if (m < 1 || m > kSvdMaxM || nagg < 1) throw Error(MVAMG_ERR_ARG, "sizes out of range");
+    k_setup_restrict<<<nagg, 64, 0, (hipStream_t)stream>>>(m, nagg, aptr, arows, coff, U, W, Wc);
+    LAUNCHCHECK("setup_restrict");
+    return MVAMG_OK;
   } catch (const Error& e) {
     return fail_status(e);
   }
@@ -2081,7 +2342,7 @@ mvamg_status mvamg_autotune(mvamg_hier* h, int what, char* report, size_t cap, v
     std::string rep;
     try {
       if (what & MVAMG_TUNE_GROUP_LANES) tune_group_lanes(h, st, rep);
-      if ((what & MVAMG_TUNE_BLOCK_COARSE) && h->nprob == 0) {
+      if ((what & MVAMG_TUNE_BLOCK_COARSE) && h->nprob == 0 && h->nall == 0) {
         if (block_fits(h))
           tune_block_coarse(h, st, rep);
         else

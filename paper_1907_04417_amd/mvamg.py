@@ -33,7 +33,8 @@ EXPORTED = ["mvamg_hier_read", "mvamg_hier_host_free", "mvamg_hier_host_info", "
             "mvamg_batch_upload", "mvamg_batch_problems", "mvamg_batch_pcg_solve", "mvamg_autotune",
             "mvamg_tune_get", "mvamg_tune_set", "mvamg_signature", "mvamg_cycle_apply_noalloc",
             "mvamg_transfers", "mvamg_kcycle_apply", "mvamg_composite_work_bytes", "mvamg_composite_apply",
-            "mvamg_composite_test", "mvamg_composite_pcg_solve"]
+            "mvamg_composite_test", "mvamg_composite_pcg_solve", "mvamg_setup_bases", "mvamg_setup_pattern",
+            "mvamg_setup_galerkin", "mvamg_setup_restrict", "mvamg_batch_small_path"]
 # bytes of the static device array mvamg_cycle_apply_noalloc works in
 NOALLOC_SCRATCH_BYTES = 32 << 20
 BLOCK_MAX = 32
@@ -78,7 +79,7 @@ def load(path: str = LIB_PATH):
         L.mvamg_hier_host_info.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int64)]
         L.mvamg_arena_bytes.argtypes = [vp, ctypes.c_int, P(ctypes.c_size_t)]
         L.mvamg_upload.argtypes = [vp, vp, ctypes.c_size_t, vp, P(vp)]
-        L.mvamg_batch_arena_bytes.argtypes = [P(vp), ctypes.c_int, P(ctypes.c_size_t)]
+        L.mvamg_batch_arena_bytes.argtypes = [P(vp), ctypes.c_int, ctypes.c_int, P(ctypes.c_size_t)]
         L.mvamg_free.argtypes = [vp]
         L.mvamg_free.restype = None
         L.mvamg_levels.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int64), P(ctypes.c_int)]
@@ -89,6 +90,12 @@ def load(path: str = LIB_PATH):
         L.mvamg_cycle_apply_noalloc.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
         L.mvamg_kcycle_apply.argtypes = [vp, vp, vp, ctypes.c_int, vp]
         L.mvamg_composite_work_bytes.argtypes = [ctypes.c_int, P(ctypes.c_size_t)]
+        ci = ctypes.c_int
+        L.mvamg_setup_bases.argtypes = [ci, ci, ci, ci, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp]
+        IP = P(ctypes.c_int)
+        L.mvamg_setup_pattern.argtypes = [ci, IP, IP, ci, IP, IP, IP, IP, IP, IP, IP, IP, IP, P(ctypes.c_int64)]
+        L.mvamg_setup_galerkin.argtypes = [ci, ci, ci] + [vp] * 15 + [vp]
+        L.mvamg_setup_restrict.argtypes = [ci, ci, vp, vp, vp, vp, vp, vp, vp]
         L.mvamg_composite_apply.argtypes = [P(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
                                             ctypes.c_size_t, vp]
         L.mvamg_composite_test.argtypes = [P(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
@@ -105,7 +112,8 @@ def load(path: str = LIB_PATH):
         L.mvamg_spmv_block.argtypes = [vp, vp, vp, ctypes.c_int, vp]
         L.mvamg_cycle_apply_block.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
         L.mvamg_pcg_solve_block.argtypes = [vp, vp, vp, ctypes.c_int, P(SolveParams), P(Info), vp]
-        L.mvamg_batch_upload.argtypes = [P(vp), ctypes.c_int, vp, ctypes.c_size_t, vp, P(vp)]
+        L.mvamg_batch_upload.argtypes = [P(vp), ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp, P(vp)]
+        L.mvamg_batch_small_path.argtypes = [vp, P(ctypes.c_int)]
         L.mvamg_batch_problems.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int)]
         L.mvamg_batch_pcg_solve.argtypes = [vp, vp, vp, P(SolveParams), P(Info), vp]
         L.mvamg_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t, vp]
@@ -139,7 +147,9 @@ _HANDLES: dict = {}
 def _register(h: int, arena, nrhs: int = 1) -> None:
     import torch
     lv = levels(h)
-    k, _ = batch_problems(h)
+    k, off = batch_problems(h)
+    if k > 0:  # a batch: the caller's vectors hold every problem, on either path
+        lv = dict(n=[off[-1]] + lv["n"][1:], nnz=(lv["nnz"] or [0]))
     # the handle borrows the arena: the tensor is kept here until free(h)
     _HANDLES[h] = dict(n=lv["n"][0], nnz=lv["nnz"][0], nprob=k, device=torch.cuda.current_device(), arena=arena,
                       nrhs=nrhs)
@@ -374,18 +384,27 @@ def pcg_solve_block(h: int, B, X, rtol=1e-8, maxit=1000, precision=64, smoother=
     return list(infos)
 
 
-def batch_upload(hhs, stream=None) -> int:
+def batch_upload(hhs, stream=None, mini_rows: int = 0) -> int:
     """Upload parsed hierarchies (mvamg_hier_read handles) as one batch, into
-    a torch-owned arena."""
+    a torch-owned arena; problems of at most mini_rows rows (and problems of
+    an odd level count) take the one-launch small-problem path."""
     arr = (ctypes.c_void_p * len(hhs))(*hhs)
     nb = ctypes.c_size_t()
-    _check(load().mvamg_batch_arena_bytes(arr, len(hhs), ctypes.byref(nb)))
+    _check(load().mvamg_batch_arena_bytes(arr, len(hhs), mini_rows, ctypes.byref(nb)))
     arena = _arena(nb.value)
     h = ctypes.c_void_p()
-    _check(load().mvamg_batch_upload(arr, len(hhs), arena.data_ptr(), arena.numel(), _stream(stream),
+    _check(load().mvamg_batch_upload(arr, len(hhs), mini_rows, arena.data_ptr(), arena.numel(), _stream(stream),
                                      ctypes.byref(h)))
     _register(h.value, arena)
     return h.value
+
+
+def batch_small_path(h: int) -> list:
+    """Per problem: True if it is solved on the small-problem path."""
+    k, _ = batch_problems(h)
+    f = (ctypes.c_int * max(k, 1))()
+    _check(load().mvamg_batch_small_path(h, f))
+    return [bool(v) for v in f[:k]]
 
 
 def batch_problems(h: int):
@@ -600,9 +619,10 @@ class Composite:
 
 
 class BatchSolver:
-    """Several hierarchy files (same number of levels) uploaded as one batch."""
+    """Several hierarchy files uploaded as one batch (mini_rows: the size up to
+    which problems take the one-launch small-problem path)."""
 
-    def __init__(self, paths, stream=None):
+    def __init__(self, paths, stream=None, mini_rows: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("mvamg needs a GPU (HIP device)")
@@ -610,7 +630,7 @@ class BatchSolver:
         try:
             for p in paths:
                 hhs.append(hier_read(p))
-            self.h = batch_upload(hhs, stream)
+            self.h = batch_upload(hhs, stream, mini_rows)
         finally:
             for hh in hhs:
                 hier_host_free(hh)

@@ -65,8 +65,9 @@ def test_null_handle_is_an_argument_error(lib):
 
 
 def test_batch_upload_validates_on_the_host(lib, tiny_hier, tmp_path):
-    """A batch needs at least one problem, no null entries and the same number
-    of levels in every hierarchy; these are rejected before any device work."""
+    """A batch needs at least one problem and no null entries; hierarchies of
+    different depth are accepted (the odd ones take the small-problem path).
+    Checked before any device work."""
     from paper_1907_04417_amd import problems
     from paper_1907_04417_amd.setup import SetupParams, build_hierarchy
     _, path3, st3 = tiny_hier
@@ -80,15 +81,15 @@ def test_batch_upload_validates_on_the_host(lib, tiny_hier, tmp_path):
         out = ctypes.c_void_p()
         nb = ctypes.c_size_t()
         arr = (ctypes.c_void_p * 2)(*hs)
-        assert lib.mvamg_batch_arena_bytes(arr, 2, ctypes.byref(nb)) == mvamg.ERR_ARG
-        assert "same number of levels" in mvamg.last_error()
-        assert lib.mvamg_batch_arena_bytes(arr, 0, ctypes.byref(nb)) == mvamg.ERR_ARG
+        assert lib.mvamg_batch_arena_bytes(arr, 2, 0, ctypes.byref(nb)) == mvamg.OK and nb.value > 0
+        assert lib.mvamg_batch_arena_bytes(arr, 0, 0, ctypes.byref(nb)) == mvamg.ERR_ARG
+        assert lib.mvamg_batch_arena_bytes(arr, 2, -1, ctypes.byref(nb)) == mvamg.ERR_ARG
         nul = (ctypes.c_void_p * 2)(hs[0], None)
-        assert lib.mvamg_batch_arena_bytes(nul, 2, ctypes.byref(nb)) == mvamg.ERR_ARG
+        assert lib.mvamg_batch_arena_bytes(nul, 2, 0, ctypes.byref(nb)) == mvamg.ERR_ARG
+        # every problem on the small path, and a mixed split: both sized on the host
+        assert lib.mvamg_batch_arena_bytes(arr, 2, 1 << 30, ctypes.byref(nb)) == mvamg.OK and nb.value > 0
         # no arena: rejected before any device work
-        same = (ctypes.c_void_p * 2)(hs[0], hs[0])
-        assert lib.mvamg_batch_arena_bytes(same, 2, ctypes.byref(nb)) == mvamg.OK and nb.value > 0
-        assert lib.mvamg_batch_upload(same, 2, None, nb.value, None, ctypes.byref(out)) == mvamg.ERR_ARG
+        assert lib.mvamg_batch_upload(arr, 2, 0, None, nb.value, None, ctypes.byref(out)) == mvamg.ERR_ARG
         assert out.value is None
     finally:
         for hh in hs:
