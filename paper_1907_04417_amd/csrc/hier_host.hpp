@@ -258,6 +258,7 @@ struct LevelLayout {
   // other.  Entry e of row l (0-based in the group) of group g has its column
   // at gcol[e + gcsh[g] - l * gcm[g]] (gcm = the shared row length, or 0).
   std::vector<int> gcol, gcsh, gcm;
+  bool all_shared = false;  // every group's rows share one list
   std::vector<int64_t> stage_gidx;       // per stage: stored column indices
   std::vector<int64_t> stage_later_idx;  // per stage: stored indices of later-stage columns
   std::vector<int> col;
@@ -591,6 +592,7 @@ inline void build_level_layout(const HostLevel& L, LevelLayout& Y, const std::ve
     const int ng = (int)Y.gstart.size() - 1, ns = (int)Y.sgrp.size() - 1;
     Y.gcsh.assign(ng, 0);
     Y.gcm.assign(ng, 0);
+    Y.all_shared = true;
     Y.gcol.clear();
     Y.stage_gidx.assign(ns, 0);
     Y.stage_later_idx.assign(ns, 0);
@@ -608,6 +610,7 @@ inline void build_level_layout(const HostLevel& L, LevelLayout& Y, const std::ve
         Y.gcol.insert(Y.gcol.end(), Y.col.begin() + e0, Y.col.begin() + e1);
         Y.gcsh[g] = at - e0;
         Y.gcm[g] = shared ? m : 0;
+        Y.all_shared = Y.all_shared && shared;
         Y.stage_gidx[c] += e1 - e0;
         if (shared)
           Y.stage_later_idx[c] += Y.rowptr[p0 + 1] - Y.rsplit[p0];

@@ -416,14 +416,24 @@ struct SellVals {
 
 constexpr int kTab = 256;
 
-// All threads of the block; ends with a barrier.
+// All threads of the block; ends with a barrier.  Thread t requests entry t
+// of both tables before writing either (one round trip).
 template <typename T>
 __device__ __forceinline__ void stage_tables(const SellVals<T>& V, T* vt, T* dt) {
-  if (V.vcode)
-    for (int i = threadIdx.x; i < V.nvtab; i += blockDim.x) vt[i] = V.vtab[i];
-  if (V.dcode)
-    for (int i = threadIdx.x; i < V.ndtab; i += blockDim.x) dt[i] = V.dtab[i];
+  static_assert(kBlock >= kTab, "one table entry per thread");
+  const int t = threadIdx.x;
+  T a = T(0), b = T(0);
+  if (V.vcode) a = V.vtab[min(t, V.nvtab - 1)];
+  if (V.dcode) b = V.dtab[min(t, V.ndtab - 1)];
+  if (V.vcode && t < V.nvtab) vt[t] = a;
+  if (V.dcode && t < V.ndtab) dt[t] = b;
   __syncthreads();
+}
+
+// A slab descriptor in one 16-byte load.
+__device__ __forceinline__ Slab load_slab(const Slab* __restrict__ slabs, int s) {
+  const int4 v = *reinterpret_cast<const int4*>(slabs + s);
+  return Slab{v.x, v.y, v.z, v.w};
 }
 
 // Values of the entries j0 .. j0 + 7 (clamped to the slab's width, or
@@ -455,6 +465,12 @@ __device__ __forceinline__ T sell_diag(const SellVals<T>& V, const T* dt, int p)
 // past every row.  DOT = 1 (binary64, no batch skipping): the block also
 // writes the sum of x_p r_p over its new rows to part[blockIdx.x] (the last
 // sweep of a cycle then yields the partials of z.r).
+//
+// Load order: the slab's descriptors with the value tables, then (after the
+// tables' barrier) r, the diagonal and the entries together, then the
+// neighbour values.  A lane past its slab's rows works on the slab's last
+// row and stores nothing, and a skipped entry is a zero weight, so no branch
+// puts a wait between these requests.
 template <typename T, int DOT>
 __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ slabs, int s0, int s1,
                                                     SellCols C, SellVals<T> V, const T* __restrict__ r, T* x,
@@ -462,36 +478,36 @@ __global__ __launch_bounds__(kBlock) void k_gs_sell(const Slab* __restrict__ sla
   __shared__ T vt[kTab], dt[kTab];
   const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  // the slab's descriptors are requested before the tables' barrier, so the
-  // two round trips overlap
-  const bool act = s < s1 && !skipped(sk, s);
-  Slab sl{0, 0, 0, 0};
-  int cb = -1, po = 0;
-  if (act) {
-    sl = slabs[s];
-    cb = C.scb[s];
-    po = C.pk[s];
-  }
+  const int sc = min(s, s1 - 1);
+  const Slab sl = load_slab(slabs, sc);
+  const int cb = C.scb[sc], po = C.pk[sc];
+  // (wave-uniform; a batch's stopped problems skip all further loads)
+  const bool act = s < s1 && !skipped(sk, sc);
   stage_tables(V, vt, dt);
   double dsum = 0.0;
   if (act) {
-    if (lane < sl.nrows) {
-      const int p = sl.row0 + lane;
-      const T rp = r[p];
-      T acc = rp;
-      // entries in batches of 8: all index and value loads, then all gathers, then the sums
-      for (int j0 = 0; j0 < sl.width; j0 += 8) {
-        int cc[8];
-        T vv[8], xx[8];
-        sell_cols8(C, sl, cb, po, lane, j0, cc);
-        sell_vals8(V, vt, sl, po, lane, j0, vv);
+    const int li = min(lane, sl.nrows - 1);
+    const int p = sl.row0 + li;
+    const T rp = r[p];
+    const int dcode = V.dcode ? (int)V.dcode[p] : 0;
+    const T dval = V.dcode ? T(0) : V.diag[p];
+    T acc = rp;
+    // entries in batches of 8: all index and value loads, then all gathers, then the sums
+    for (int j0 = 0; j0 < sl.width; j0 += 8) {
+      int cc[8];
+      T vv[8], xx[8];
+      sell_cols8(C, sl, cb, po, li, j0, cc);
+      sell_vals8(V, vt, sl, po, li, j0, vv);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) xx[u] = x[min(cc[u], lim - 1)];
+      for (int u = 0; u < 8; ++u) xx[u] = x[min(cc[u], lim - 1)];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (j0 + u < sl.width && cc[u] < lim) acc -= vv[u] * xx[u];
+      for (int u = 0; u < 8; ++u) {
+        const T w = (j0 + u < sl.width && cc[u] < lim) ? vv[u] : T(0);
+        acc -= w * xx[u];
       }
-      const T xn = acc / sell_diag(V, dt, p);
+    }
+    const T xn = acc / (V.dcode ? dt[dcode] : dval);
+    if (lane < sl.nrows) {
       x[p] = xn;
       if (DOT) dsum = (double)xn * (double)rp;
     }
@@ -532,7 +548,9 @@ __global__ __launch_bounds__(kBlock) void k_stage0_point(int rows0, SellVals<T> 
     if (!skipped(sk, p)) x[p] = r[p] / sell_diag(V, dt, p);
 }
 
-// s = r - A x (MODE 0), y = A x with sum x.y (MODE 1, binary64 only), or y = A x (MODE 2)
+// s = r - A x (MODE 0), y = A x with sum x.y (MODE 1, binary64 only), or y = A x
+// (MODE 2).  Load order and clamping as in k_gs_sell; the diagonal term is
+// added after the off-diagonal sum.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ slabs, int nslabs,
                                                        SellCols C, SellVals<T> V, const T* __restrict__ r,
@@ -540,35 +558,38 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
   __shared__ T vt[kTab], dt[kTab];
   const int sidx = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  // descriptors requested before the tables' barrier (see k_gs_sell)
-  const bool act = sidx < nslabs && !skipped(sk, sidx);
-  Slab sl{0, 0, 0, 0};
-  int cb = -1, po = 0;
-  if (act) {
-    sl = slabs[sidx];
-    cb = C.scb[sidx];
-    po = C.pk[sidx];
-  }
+  const int sc = min(sidx, nslabs - 1);
+  const Slab sl = load_slab(slabs, sc);
+  const int cb = C.scb[sc], po = C.pk[sc];
+  // (wave-uniform; a batch's stopped problems skip all further loads)
+  const bool act = sidx < nslabs && !skipped(sk, sc);
   stage_tables(V, vt, dt);
   double dsum = 0.0;
   if (act) {
-    if (lane < sl.nrows) {
-      const int p = sl.row0 + lane;
-      const T xp = x[p];
-      T acc = sell_diag(V, dt, p) * xp;
-      for (int j0 = 0; j0 < sl.width; j0 += 8) {
-        int cc[8];
-        T vv[8], xx[8];
-        sell_cols8(C, sl, cb, po, lane, j0, cc);
-        sell_vals8(V, vt, sl, po, lane, j0, vv);
+    const int li = min(lane, sl.nrows - 1);
+    const int p = sl.row0 + li;
+    const T xp = x[p];
+    const T rp = MODE == 0 ? r[p] : T(0);
+    const int dcode = V.dcode ? (int)V.dcode[p] : 0;
+    const T dval = V.dcode ? T(0) : V.diag[p];
+    T acc = T(0);
+    for (int j0 = 0; j0 < sl.width; j0 += 8) {
+      int cc[8];
+      T vv[8], xx[8];
+      sell_cols8(C, sl, cb, po, li, j0, cc);
+      sell_vals8(V, vt, sl, po, li, j0, vv);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) xx[u] = x[cc[u]];
+      for (int u = 0; u < 8; ++u) xx[u] = x[cc[u]];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (j0 + u < sl.width) acc += vv[u] * xx[u];
+      for (int u = 0; u < 8; ++u) {
+        const T w = (j0 + u < sl.width) ? vv[u] : T(0);
+        acc += w * xx[u];
       }
+    }
+    acc += (V.dcode ? dt[dcode] : dval) * xp;
+    if (lane < sl.nrows) {
       if (MODE == 0) {
-        s[p] = r[p] - acc;
+        s[p] = rp - acc;
       } else {
         s[p] = acc;
         if (MODE == 1) dsum = (double)xp * (double)acc;
@@ -582,8 +603,8 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
 
 // Grouped levels: one wavefront per group, LPR = 64 / KMAX lanes per row
 // (KMAX a power of two, at least the level's largest group).  Every group has
-// a 96-byte record, read with scalar loads while the rest of the group's data
-// is requested:
+// a 96-byte record (read by the lanes, word t in lane t, and taken apart with
+// readlane):
 //   rec[0] first row p0, rec[1] rows k, rec[2] offset of its k x k diagonal
 //   block (dense row-major), rec[3 + q] entry offset of row q (q = 0..8,
 //   repeated past row k), rec[12 + q] (q < 8) the end of row q's entries in
@@ -598,24 +619,53 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(const Slab* __restrict__ 
 // lanes with DPP moves and each row sum is read into a scalar with readlane.
 constexpr int kRec = 24;
 
-// Row sums a[q] (q < KMAX; zero past row k) of the off-group entries of group
-// g times x.  Uniform across the wave.  csh: the lane's row's column shift
-// (rec[20] - l rec[21]).
-// split (forward sweep from zero): the group's record + 12, whose entry l
-// ends row l's sum; nullptr: whole rows.
+// The group's record, diagonal block, and current x and r of its rows, as
+// the block-per-group kernels hold them (indices clamped into the group).
 template <typename T, int KMAX>
-__device__ __forceinline__ void group_rowsums(const int (&gb)[kKmax + 1], int l, int sub, int csh,
-                                              const int* __restrict__ col, const T* __restrict__ val, const T* x,
-                                              T (&a)[KMAX], const int* __restrict__ split = nullptr) {
+struct GroupData {
+  int p0, k, cs, cm;  // cs, cm: rec[20], rec[21]
+  int gb[kKmax + 1];
+  T B[KMAX][KMAX], xv[KMAX], rv[KMAX];
+};
+
+// One Gauss-Seidel stage on the groups [g0, g1): every group relaxes its rows
+// one after the other (forward: l = 0..k-1, backward: l = k-1..0) with the
+// latest values of the other rows.  The record is read by the lanes (lane t
+// holds word t) and its uniform fields taken with readlane: one vector load
+// and one wait, after which the diagonal block, x and r of the rows and the
+// row entries are all requested together; they reach every lane by readlane
+// once the row sums are done.  The dependent chain is record -> entries and
+// group data -> neighbour values -> store.
+template <typename T, int KMAX, int BACK>
+__global__ __launch_bounds__(kBlock) void k_gs_grp(int g0, int g1, const int* __restrict__ rec,
+                                                   const int* __restrict__ col, const T* __restrict__ val,
+                                                   const T* __restrict__ dblk, const T* __restrict__ r, T* x,
+                                                   int first) {
   constexpr int LPR = 64 / KMAX;
-  int e0 = gb[0], e1 = gb[1];
+  const int graw = g0 + xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (int)(threadIdx.x >> 6);
+  const int g = __builtin_amdgcn_readfirstlane(min(graw, g1 - 1));
+  const int lane = threadIdx.x & 63;
+  const int l = lane / LPR, sub = lane % LPR;
+  const int rw = rec[(size_t)g * kRec + min(lane, kRec - 1)];
+  const int p0 = __builtin_amdgcn_readlane(rw, 0), k = __builtin_amdgcn_readlane(rw, 1);
+  const int boff = __builtin_amdgcn_readlane(rw, 2);
+  const int csh = __builtin_amdgcn_readlane(rw, 20) - l * __builtin_amdgcn_readlane(rw, 21);
+  int e0 = __builtin_amdgcn_readlane(rw, 3), e1 = __builtin_amdgcn_readlane(rw, 4);
+  int sp = __builtin_amdgcn_readlane(rw, 12);
 #pragma unroll
   for (int q = 1; q < KMAX; ++q)
     if (l == q) {
-      e0 = gb[q];
-      e1 = gb[q + 1];
+      e0 = __builtin_amdgcn_readlane(rw, 3 + q);
+      e1 = __builtin_amdgcn_readlane(rw, 4 + q);
+      sp = __builtin_amdgcn_readlane(rw, 12 + q);
     }
-  if (split) e1 = split[min(l, kKmax - 1)];
+  if (first) e1 = sp;  // forward sweep from zero: entries of earlier stages only
+  // group data: lane t < KMAX^2 the block entry (t / KMAX, t % KMAX), lane t
+  // < KMAX row t's x and r (indices clamped into the group)
+  const int tb = min(lane, KMAX * KMAX - 1);
+  const T bq = dblk[boff + min(tb / KMAX, k - 1) * k + min(tb % KMAX, k - 1)];
+  const T xo = x[p0 + min(lane, k - 1)];
+  const T ro = r[p0 + min(lane, k - 1)];
   T acc = T(0);
   for (int e = e0 + sub; e < e1; e += 4 * LPR) {
     int cc[4];
@@ -633,86 +683,36 @@ __device__ __forceinline__ void group_rowsums(const int (&gb)[kKmax + 1], int l,
       if (e + u * LPR < e1) acc += vv[u] * xx[u];
   }
   acc = lanes_sum<LPR>(acc);
+  T a[KMAX], B[KMAX][KMAX], xv[KMAX], dinv[KMAX];
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) {
     T t = lane_value(acc, q * LPR);
 #pragma unroll
     for (int j = 1; j < LPR / 16; ++j) t += lane_value(acc, q * LPR + 16 * j);
     a[q] = t;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) B[q][j] = lane_value(bq, q * KMAX + j);
+    xv[q] = (q < k) ? lane_value(xo, q) : T(0);
+    a[q] = (q < k) ? lane_value(ro, q) - a[q] : T(0);  // r minus the off-group sum
+    dinv[q] = T(1) / B[q][q];
   }
-}
-
-// The group's record, diagonal block, and current x and r of its rows (all
-// requested before any is used; indices clamped into the group).
-template <typename T, int KMAX>
-struct GroupData {
-  int p0, k, cs, cm;  // cs, cm: rec[20], rec[21]
-  int gb[kKmax + 1];
-  T B[KMAX][KMAX], xv[KMAX], rv[KMAX];
-};
-
-template <typename T, int KMAX, bool WITH_R>
-__device__ __forceinline__ void load_group(int g, const int* __restrict__ rec, const T* __restrict__ dblk,
-                                           const T* __restrict__ r, const T* x, GroupData<T, KMAX>& d) {
-  const int* R = rec + (size_t)g * kRec;
-  d.p0 = R[0];
-  d.k = R[1];
-  const T* B = dblk + R[2];
-  d.cs = R[20];
-  d.cm = R[21];
-#pragma unroll
-  for (int q = 0; q <= kKmax; ++q) d.gb[q] = R[3 + q];
-  const int k = d.k;
-#pragma unroll
-  for (int i = 0; i < KMAX; ++i) {
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j) d.B[i][j] = B[min(i, k - 1) * k + min(j, k - 1)];
-    const T xi = x[d.p0 + min(i, k - 1)];
-    d.xv[i] = (i < k) ? xi : T(0);
-    if (WITH_R) {
-      const T ri = r[d.p0 + min(i, k - 1)];
-      d.rv[i] = (i < k) ? ri : T(0);
-    }
-  }
-}
-
-// One Gauss-Seidel stage on the groups [g0, g1): every group relaxes its rows
-// one after the other (forward: l = 0..k-1, backward: l = k-1..0) with the
-// latest values of the other rows.
-template <typename T, int KMAX, int BACK>
-__global__ __launch_bounds__(kBlock) void k_gs_grp(int g0, int g1, const int* __restrict__ rec,
-                                                   const int* __restrict__ col, const T* __restrict__ val,
-                                                   const T* __restrict__ dblk, const T* __restrict__ r, T* x,
-                                                   int first) {
-  const int graw = g0 + xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (int)(threadIdx.x >> 6);
-  const int g = __builtin_amdgcn_readfirstlane(min(graw, g1 - 1));
-  const int lane = threadIdx.x & 63;
-  const int l = lane / (64 / KMAX), sub = lane % (64 / KMAX);
-  GroupData<T, KMAX> d;
-  load_group<T, KMAX, true>(g, rec, dblk, r, x, d);
-  // reciprocals of the diagonal, computed while the entry gathers are in flight
-  T dinv[KMAX];
-#pragma unroll
-  for (int q = 0; q < KMAX; ++q) dinv[q] = T(1) / d.B[q][q];
-  T a[KMAX];
-  group_rowsums<T, KMAX>(d.gb, l, sub, d.cs - l * d.cm, col, val, x, a, first ? rec + (size_t)g * kRec + 12 : nullptr);
 #pragma unroll
   for (int t = 0; t < KMAX; ++t) {
     const int ll = BACK ? KMAX - 1 - t : t;
-    if (ll < d.k) {
-      T s = d.rv[ll] - a[ll];
+    if (ll < k) {
+      T s = a[ll];
 #pragma unroll
       for (int q = 0; q < KMAX; ++q)
-        if (q < d.k && q != ll) s -= d.B[ll][q] * d.xv[q];
-      d.xv[ll] = s * dinv[ll];
+        if (q < k && q != ll) s -= B[ll][q] * xv[q];
+      xv[ll] = s * dinv[ll];
     }
   }
-  if (graw < g1 && sub == 0 && l < d.k) {
-    T v = d.xv[0];
+  if (graw < g1 && sub == 0 && l < k) {
+    T v = xv[0];
 #pragma unroll
     for (int q = 1; q < KMAX; ++q)
-      if (l == q) v = d.xv[q];
-    x[d.p0 + l] = v;
+      if (l == q) v = xv[q];
+    x[p0 + l] = v;
   }
 }
 
@@ -749,40 +749,78 @@ __global__ __launch_bounds__(kBlock) void k_zero_stage0_grp(int ng, int ng0, con
 }
 
 // s = r - A x (MODE 0), y = A x with sum x.y (MODE 1, binary64) or y = A x
-// (MODE 2) on all groups; wave per group.
+// (MODE 2) on all groups; wave per group.  Loads as in k_gs_grp: the record
+// by the lanes, then the block, x of the rows, r of the lane's row and the
+// entries together, then the neighbour values.
 template <typename T, int KMAX, int MODE>
 __global__ __launch_bounds__(kBlock) void k_resid_grp(int ng, const int* __restrict__ rec,
                                                       const int* __restrict__ col, const T* __restrict__ val,
                                                       const T* __restrict__ dblk, const T* __restrict__ r,
                                                       const T* __restrict__ x, T* __restrict__ s, Red red) {
+  constexpr int LPR = 64 / KMAX;
   const int graw = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (int)(threadIdx.x >> 6);
   const int g = __builtin_amdgcn_readfirstlane(min(graw, ng - 1));
   const int lane = threadIdx.x & 63;
-  const int l = lane / (64 / KMAX), sub = lane % (64 / KMAX);
-  GroupData<T, KMAX> d;
-  load_group<T, KMAX, false>(g, rec, dblk, r, x, d);
-  T a[KMAX];
-  group_rowsums<T, KMAX>(d.gb, l, sub, d.cs - l * d.cm, col, val, x, a);
-  double dsum = 0.0;
-  if (graw < ng && sub == 0 && l < d.k) {
-    T t = T(0), xl = T(0);
+  const int l = lane / LPR, sub = lane % LPR;
+  const int rw = rec[(size_t)g * kRec + min(lane, kRec - 1)];
+  const int p0 = __builtin_amdgcn_readlane(rw, 0), k = __builtin_amdgcn_readlane(rw, 1);
+  const int boff = __builtin_amdgcn_readlane(rw, 2);
+  const int csh = __builtin_amdgcn_readlane(rw, 20) - l * __builtin_amdgcn_readlane(rw, 21);
+  int e0 = __builtin_amdgcn_readlane(rw, 3), e1 = __builtin_amdgcn_readlane(rw, 4);
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q)
-      if (q == l) {
-        t = a[q];
-        xl = d.xv[q];
-      }
-#pragma unroll
-    for (int q = 0; q < KMAX; ++q) {
-      T bq = d.B[0][q];
-#pragma unroll
-      for (int i = 1; i < KMAX; ++i)
-        if (i == l) bq = d.B[i][q];
-      if (q < d.k) t += bq * d.xv[q];
+  for (int q = 1; q < KMAX; ++q)
+    if (l == q) {
+      e0 = __builtin_amdgcn_readlane(rw, 3 + q);
+      e1 = __builtin_amdgcn_readlane(rw, 4 + q);
     }
-    const int p = d.p0 + l;
+  const int tb = min(lane, KMAX * KMAX - 1);
+  const T bq = dblk[boff + min(tb / KMAX, k - 1) * k + min(tb % KMAX, k - 1)];
+  const T xo = x[p0 + min(lane, k - 1)];
+  const int pl = p0 + min(l, k - 1);
+  const T rl = MODE == 0 ? r[pl] : T(0);
+  T acc = T(0);
+  for (int e = e0 + sub; e < e1; e += 4 * LPR) {
+    int cc[4];
+    T vv[4], xx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int ee = min(e + u * LPR, e1 - 1);
+      cc[u] = col[ee + csh];
+      vv[u] = val[ee];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xx[u] = x[cc[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (e + u * LPR < e1) acc += vv[u] * xx[u];
+  }
+  acc = lanes_sum<LPR>(acc);
+  // this lane's row l: its off-group sum, then the diagonal block's terms
+  T t = T(0), xl = T(0);
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    T aq = lane_value(acc, q * LPR);
+#pragma unroll
+    for (int j = 1; j < LPR / 16; ++j) aq += lane_value(acc, q * LPR + 16 * j);
+    const T xq = lane_value(xo, q);
+    if (q == l) {
+      t = aq;
+      xl = xq;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    T bl = lane_value(bq, q);  // row 0
+#pragma unroll
+    for (int i = 1; i < KMAX; ++i)
+      if (i == l) bl = lane_value(bq, i * KMAX + q);
+    if (q < k) t += bl * lane_value(xo, q);
+  }
+  double dsum = 0.0;
+  if (graw < ng && sub == 0 && l < k) {
+    const int p = p0 + l;
     if (MODE == 0) {
-      s[p] = r[p] - t;
+      s[p] = rl - t;
     } else {
       s[p] = t;
       if (MODE == 1) dsum = (double)xl * (double)t;
@@ -1120,13 +1158,22 @@ __global__ __launch_bounds__(kBlock) void k_prolong_rows(int n, int ld, const in
                                                          T* __restrict__ x, Skip sk) {
   for (int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     if (skipped(sk, i)) continue;
+    // x, the record and all KMAX entries of U (zero past k) are requested
+    // together; the coarse values past k are read at a clamped index and
+    // weighted by those zeros
+    const T xi = x[i];
     const int ci = cinfo[i];
+    T u[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) u[q] = Urow[(size_t)q * ld + i];
     const int c0 = ci >> 3, k = (ci & 7) + 1;
     T t = T(0);
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q)
-      if (q < k) t += Urow[(size_t)q * ld + i] * xc[c0 + q];
-    x[i] += t;
+    for (int q = 0; q < KMAX; ++q) {
+      const T v = xc[c0 + min(q, k - 1)];
+      t += (q < k ? u[q] : T(0)) * v;
+    }
+    x[i] = xi + t;
   }
 }
 

@@ -219,7 +219,9 @@ __device__ __forceinline__ void half_entries8(int mc, T mv, int (&cc)[8], T (&vv
 // j < width) of val * x[col * kNB + c]), the terms added one after the other;
 // entries with col >= lim are skipped (forward sweep from zero).  Lane c loads
 // entry j0 + c of each 32-entry chunk once; the entries reach the other lanes
-// by swizzle.
+// by swizzle.  The eight neighbour rows of a step are requested together with
+// in-range indices, and a skipped term is a zero weight (a select, not a
+// branch), so no wait sits between the requests.
 template <typename T, int SGN>
 __device__ __forceinline__ T half_row_sum(T acc, const int* __restrict__ cp, const T* __restrict__ vp, int width,
                                           int c, const T* x, int lim) {
@@ -236,13 +238,15 @@ __device__ __forceinline__ T half_row_sum(T acc, const int* __restrict__ cp, con
 #pragma unroll
         for (int u = 0; u < 8; ++u) xx[u] = x[(size_t)min(cc[u], lim - 1) * kNB + c];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (j0 + J0 + u < width && cc[u] < lim) {
-            if (SGN > 0)
-              acc += vv[u] * xx[u];
-            else
-              acc -= vv[u] * xx[u];
-          }
+        for (int u = 0; u < 8; ++u) {
+          // a skipped term adds a zero product (xx is a finite value of a
+          // row that is set: the index was clamped into range)
+          const T w = ((j0 + J0 + u < width) & (cc[u] < lim)) ? vv[u] : T(0);
+          if (SGN > 0)
+            acc += w * xx[u];
+          else
+            acc -= w * xx[u];
+        }
       }
     };
     step(std::integral_constant<int, 0>{});
@@ -255,7 +259,8 @@ __device__ __forceinline__ T half_row_sum(T acc, const int* __restrict__ cp, con
 
 // Gauss-Seidel stage on the slabs [s0, s1) of a sliced-ELL level: half wave
 // per row, (blockIdx, threadIdx) -> row (s0 + hw / 64, hw % 64).  lim as in
-// k_gs_sell (forward sweep from zero: entries of later stages skipped).
+// k_gs_sell (forward sweep from zero: entries of later stages skipped).  The
+// row's r and diagonal are requested with its entries.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bgs_sell(const Slab* __restrict__ slabs, int s0, int s1,
                                                      const int* __restrict__ col, const T* __restrict__ val,
@@ -264,12 +269,18 @@ __global__ __launch_bounds__(kBlock) void k_bgs_sell(const Slab* __restrict__ sl
   const int hw = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) >> 5;
   const int s = s0 + (hw >> 6), i = hw & 63;
   if (s >= s1) return;
-  const Slab sl = slabs[s];
-  if (i >= sl.nrows) return;
+  // a lane past the slab's rows works on its last row and stores nothing
+  // (no branch between the descriptor and the loads that need it)
+  const Slab sl = load_slab(slabs, s);
+  const int ii = min(i, sl.nrows - 1);
   const int c = threadIdx.x & 31;
-  const int p = sl.row0 + i;
-  const T acc = half_row_sum<T, -1>(r[(size_t)p * kNB + c], col + sl.off + i, val + sl.off + i, sl.width, c, x, lim);
-  x[(size_t)p * kNB + c] = acc / diag[p];
+  const int p = sl.row0 + ii;
+  const T rp = r[(size_t)p * kNB + c];
+  const T dp = diag[p];
+  // the off-diagonal sum first, r added at the end, so that no wait for r
+  // precedes the entry requests
+  const T acc = half_row_sum<T, -1>(T(0), col + sl.off + ii, val + sl.off + ii, sl.width, c, x, lim);
+  if (i < sl.nrows) x[(size_t)p * kNB + c] = (rp + acc) / dp;
 }
 
 // x = r / d on the rows p < rows0 (first stage of the forward sweep from zero)
@@ -282,7 +293,9 @@ __global__ __launch_bounds__(kBlock) void k_bstage0_point(int rows0, const T* __
 }
 
 // MODE 0: s = r - A x;  MODE 1: s = A x with per-column x.s partials;
-// MODE 2: s = A x.  Grid-stride over the rows of all slabs.
+// MODE 2: s = A x.  Every block takes one contiguous run of the slabs' rows
+// (kRowsPerBlock at a time), and the runs of an XCD's blocks are adjacent, so
+// the rows an XCD handles at one time, and their neighbours, stay together.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_bresid_sell(const Slab* __restrict__ slabs, int nslabs,
                                                         const int* __restrict__ col, const T* __restrict__ val,
@@ -292,19 +305,26 @@ __global__ __launch_bounds__(kBlock) void k_bresid_sell(const Slab* __restrict__
   const int c = threadIdx.x & 31;
   double dsum = 0.0;
   const int nhw = nslabs * 64;
-  for (int hw = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) >> 5; hw < nhw;
-       hw += gridDim.x * kRowsPerBlock) {
-    const Slab sl = slabs[hw >> 6];
+  const int per = ((nhw + (int)gridDim.x - 1) / (int)gridDim.x + kRowsPerBlock - 1) / kRowsPerBlock * kRowsPerBlock;
+  const int hw0 = xcd_block(blockIdx.x, gridDim.x) * per, hw1 = min(nhw, hw0 + per);
+  for (int hw = hw0 + (int)(threadIdx.x >> 5); hw < hw1; hw += kRowsPerBlock) {
+    const Slab sl = load_slab(slabs, hw >> 6);
     const int i = hw & 63;
-    if (i >= sl.nrows) continue;
-    const int p = sl.row0 + i;
+    // past the slab's rows: its last row again, nothing stored
+    const int ii = min(i, sl.nrows - 1);
+    const int p = sl.row0 + ii;
+    // the row's own values are requested with its entries
     const T xp = x[(size_t)p * kNB + c];
-    const T acc = half_row_sum<T, 1>(diag[p] * xp, col + sl.off + i, val + sl.off + i, sl.width, c, x, INT_MAX);
-    if (MODE == 0) {
-      s[(size_t)p * kNB + c] = r[(size_t)p * kNB + c] - acc;
-    } else {
-      s[(size_t)p * kNB + c] = acc;
-      if (MODE == 1) dsum += (double)xp * (double)acc;
+    const T dp = diag[p];
+    const T rp = MODE == 0 ? r[(size_t)p * kNB + c] : T(0);
+    const T acc = dp * xp + half_row_sum<T, 1>(T(0), col + sl.off + ii, val + sl.off + ii, sl.width, c, x, INT_MAX);
+    if (i < sl.nrows) {
+      if (MODE == 0) {
+        s[(size_t)p * kNB + c] = rp - acc;
+      } else {
+        s[(size_t)p * kNB + c] = acc;
+        if (MODE == 1) dsum += (double)xp * (double)acc;
+      }
     }
   }
   if (MODE == 1) bcol_partials(dsum, 0, part);
@@ -389,6 +409,175 @@ __global__ __launch_bounds__(kBlock) void k_bgs_grp(int g0, int g1, const int* _
 #pragma unroll
   for (int q = 0; q < KMAX; ++q)
     if (q < k && (q & 1) == h) x[(size_t)(p0 + q) * kNB + c] = xv[q];
+}
+
+// ---- block per group, shared column lists
+//
+// On levels where every group's rows share one column list (rec[21] the row
+// length, rec[20] the shift into gcol), one 256-thread block takes a group:
+// its 8 half waves split the group's columns (half wave w: columns w, w + 8,
+// ...), each column's block-vector row of x is gathered once and used for
+// all k rows, and NU columns per half wave are in flight at a time.  The
+// partial row sums go to LDS and the first wave adds them in half-wave order
+// and finishes the group.  The record is read by the lanes (readlane for its
+// fields); the first wave requests the group's own x, r and diagonal block
+// before the column loop.
+template <int KMAX>
+constexpr int shared_nu() { return KMAX <= 2 ? 8 : KMAX == 4 ? 4 : 2; }
+
+template <typename T, int KMAX>
+struct SharedGroup {
+  int p0, k, len, boff, cs, gb[KMAX];
+};
+
+template <typename T, int KMAX>
+__device__ __forceinline__ SharedGroup<T, KMAX> shared_group(const int* __restrict__ rec, int g, int lane) {
+  const int rw = rec[(size_t)g * kRec + min(lane, kRec - 1)];
+  SharedGroup<T, KMAX> d;
+  d.p0 = __builtin_amdgcn_readlane(rw, 0);
+  d.k = __builtin_amdgcn_readlane(rw, 1);
+  d.boff = __builtin_amdgcn_readlane(rw, 2);
+  d.cs = __builtin_amdgcn_readlane(rw, 20);
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) d.gb[q] = __builtin_amdgcn_readlane(rw, 3 + q);
+  d.len = __builtin_amdgcn_readlane(rw, 4) - d.gb[0];
+  return d;
+}
+
+// This half wave's partial sums over its columns: acc[q] = sum of
+// a_(row q, column j) x[column j] (column c of the block vector).
+template <typename T, int KMAX>
+__device__ __forceinline__ void shared_partial(const SharedGroup<T, KMAX>& d, int hw, int c,
+                                               const int* __restrict__ gcol, const T* __restrict__ val, const T* x,
+                                               T (&acc)[KMAX]) {
+  constexpr int NU = shared_nu<KMAX>();
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) acc[q] = T(0);
+  // rows past k read row 0's values (their sums are not used)
+  int gq[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) gq[q] = (q < d.k) ? d.gb[q] : d.gb[0];
+  for (int j0 = hw; j0 < d.len; j0 += 8 * NU) {
+    int jj[NU], cc[NU];
+    T vv[NU][KMAX], xx[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      jj[u] = min(j0 + 8 * u, d.len - 1);
+      cc[u] = gcol[d.gb[0] + jj[u] + d.cs];
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q) vv[u][q] = val[gq[q] + jj[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) xx[u] = x[(size_t)cc[u] * kNB + c];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const bool on = j0 + 8 * u < d.len;
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q) acc[q] += (on ? vv[u][q] : T(0)) * xx[u];
+    }
+  }
+}
+
+// The first wave's group data: x and r of the rows for column c, and the
+// diagonal block with lane t holding entry (t / KMAX, t % KMAX) (indices
+// clamped into the group), for the block's LDS copy Bs.
+template <typename T, int KMAX, bool WITH_R>
+__device__ __forceinline__ void shared_own(const SharedGroup<T, KMAX>& d, int lane, int c,
+                                           const T* __restrict__ dblk, const T* __restrict__ r, const T* x,
+                                           T (&xv)[KMAX], T (&rv)[KMAX], T& bq) {
+  const int tb = min(lane, KMAX * KMAX - 1);
+  bq = dblk[d.boff + min(tb / KMAX, d.k - 1) * d.k + min(tb % KMAX, d.k - 1)];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    const size_t i = (size_t)(d.p0 + min(q, d.k - 1)) * kNB + c;
+    xv[q] = x[i];
+    rv[q] = WITH_R ? r[i] : T(0);
+  }
+}
+
+// Gauss-Seidel stage on the groups [g0, g1), block per group (see above).
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kBlock) void k_bgs_grps(int g0, int g1, const int* __restrict__ rec,
+                                                     const int* __restrict__ gcol, const T* __restrict__ val,
+                                                     const T* __restrict__ dblk, const T* __restrict__ r, T* x,
+                                                     int backward) {
+  __shared__ T part[8][KMAX][kNB];
+  __shared__ T Bs[KMAX * KMAX];
+  const int g = g0 + xcd_block(blockIdx.x, gridDim.x);
+  if (g >= g1) return;
+  const int lane = threadIdx.x & 63, hw = threadIdx.x >> 5, c = threadIdx.x & 31;
+  const SharedGroup<T, KMAX> d = shared_group<T, KMAX>(rec, g, lane);
+  T xv[KMAX], rv[KMAX], bq = T(0);
+  if (threadIdx.x < 64) shared_own<T, KMAX, true>(d, lane, c, dblk, r, x, xv, rv, bq);
+  T acc[KMAX];
+  shared_partial<T, KMAX>(d, hw, c, gcol, val, x, acc);
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) part[hw][q][c] = acc[q];
+  if (threadIdx.x < KMAX * KMAX) Bs[threadIdx.x] = bq;
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
+  const T(*B)[KMAX] = reinterpret_cast<const T(*)[KMAX]>(Bs);
+  T a[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    T t = part[0][q][c];
+#pragma unroll
+    for (int w = 1; w < 8; ++w) t += part[w][q][c];
+    a[q] = t;
+    xv[q] = (q < d.k) ? xv[q] : T(0);
+  }
+#pragma unroll
+  for (int t = 0; t < KMAX; ++t) {
+    const int ll = backward ? KMAX - 1 - t : t;
+    if (ll < d.k) {
+      T s = rv[ll] - a[ll];
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q)
+        if (q < d.k && q != ll) s -= B[ll][q] * xv[q];
+      xv[ll] = s / B[ll][ll];
+    }
+  }
+  if (lane < 32) {
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q)
+      if (q < d.k) x[(size_t)(d.p0 + q) * kNB + c] = xv[q];
+  }
+}
+
+// s = r - A x on the groups [0, ng), block per group (see above).
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kBlock) void k_bresid_grps(int ng, const int* __restrict__ rec,
+                                                        const int* __restrict__ gcol, const T* __restrict__ val,
+                                                        const T* __restrict__ dblk, const T* __restrict__ r,
+                                                        const T* __restrict__ x, T* __restrict__ s) {
+  __shared__ T part[8][KMAX][kNB];
+  __shared__ T Bs[KMAX * KMAX];
+  const int g = xcd_block(blockIdx.x, gridDim.x);
+  if (g >= ng) return;
+  const int lane = threadIdx.x & 63, hw = threadIdx.x >> 5, c = threadIdx.x & 31;
+  const SharedGroup<T, KMAX> d = shared_group<T, KMAX>(rec, g, lane);
+  T xv[KMAX], rv[KMAX], bq = T(0);
+  if (threadIdx.x < 64) shared_own<T, KMAX, true>(d, lane, c, dblk, r, x, xv, rv, bq);
+  T acc[KMAX];
+  shared_partial<T, KMAX>(d, hw, c, gcol, val, x, acc);
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) part[hw][q][c] = acc[q];
+  if (threadIdx.x < KMAX * KMAX) Bs[threadIdx.x] = bq;
+  __syncthreads();
+  if (threadIdx.x >= 32) return;
+  const T(*B)[KMAX] = reinterpret_cast<const T(*)[KMAX]>(Bs);
+#pragma unroll
+  for (int l = 0; l < KMAX; ++l) {
+    if (l < d.k) {
+      T t = part[0][l][c];
+#pragma unroll
+      for (int w = 1; w < 8; ++w) t += part[w][l][c];
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q)
+        if (q < d.k) t += B[l][q] * xv[q];
+      s[(size_t)(d.p0 + l) * kNB + c] = rv[l] - t;
+    }
+  }
 }
 
 // forward sweep from x = 0 on a grouped level (thread per group and column)
@@ -486,8 +675,13 @@ __global__ __launch_bounds__(kBlock) void k_bl1_update(int n, const T* __restric
 // r_c = P^T s for block vectors: wave per aggregate, half wave h takes members
 // h, h + 2, ... (four in flight), the halves are added with one exchange.
 // Aggregate records, scut and INIT as in k_restrict (1: first Gauss-Seidel
-// stage of the next level from x_c = 0, 2: first l1-Jacobi step).
-template <typename T, int INIT>
+// stage of the next level from x_c = 0, 2: first l1-Jacobi step); KMAX
+// bounds the block widths k.  The record is read by the lanes and its fields
+// taken with readlane; the diagonal block (INIT = 1), the member indices and
+// their U entries are requested right after it, and the members' rows of s
+// after the indices with no other wait: a member at or past scut (where
+// s = 0) reads row scut - 1 instead and is weighted by zero.
+template <typename T, int KMAX, int INIT>
 __global__ __launch_bounds__(kBlock) void k_brestrict(int nagg, const int* __restrict__ arec,
                                                       const int* __restrict__ arows, const T* __restrict__ U,
                                                       const T* __restrict__ s, int scut, T* __restrict__ rc,
@@ -497,62 +691,68 @@ __global__ __launch_bounds__(kBlock) void k_brestrict(int nagg, const int* __res
                                                (int)(threadIdx.x >> 6));
   if (a >= nagg) return;
   const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
-  const int* R = arec + (size_t)a * kARec;
-  const int m0 = R[AR_M0], na = R[AR_NA], k = R[AR_K];
-  const T* Ua = U + R[AR_UOFF];
-  T acc[kKmax];
+  const int rw = arec[(size_t)a * kARec + min(lane, kARec - 1)];
+  const int m0 = __builtin_amdgcn_readlane(rw, AR_M0), na = __builtin_amdgcn_readlane(rw, AR_NA);
+  const int k = __builtin_amdgcn_readlane(rw, AR_K), c0 = __builtin_amdgcn_readlane(rw, AR_C0);
+  const T* Ua = U + __builtin_amdgcn_readlane(rw, AR_UOFF);
+  // lower triangle of the next level's diagonal block (INIT = 1; indices
+  // clamped into the k x k block; without a block the level's first block,
+  // at least k x k, is read and discarded)
+  constexpr int NB = (INIT == 1) ? KMAX * (KMAX + 1) / 2 : 1;
+  T bl[NB];
+  int db = -1;
+  if (INIT == 1) {
+    db = __builtin_amdgcn_readlane(rw, AR_DB);
+    const T* B = cdblk + max(db, 0);
 #pragma unroll
-  for (int q = 0; q < kKmax; ++q) acc[q] = T(0);
+    for (int l = 0; l < KMAX; ++l)
+#pragma unroll
+      for (int q = 0; q <= l; ++q) bl[l * (l + 1) / 2 + q] = B[min(l, k - 1) * k + min(q, k - 1)];
+  }
+  const int slast = max(scut - 1, 0);
+  T acc[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) acc[q] = T(0);
   for (int l0 = h; l0 < na; l0 += 8) {
-    T sv[4];
-    int li[4];
+    int li[4], row[4];
+    T sv[4], u[4][KMAX];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) li[u] = min(l0 + 2 * u, na - 1);
+    for (int v = 0; v < 4; ++v) {
+      li[v] = min(l0 + 2 * v, na - 1);
+      row[v] = arows[m0 + li[v]];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int row = arows[m0 + li[u]];
-      sv[u] = (row < scut) ? s[(size_t)row * kNB + c] : T(0);
+      for (int q = 0; q < KMAX; ++q) u[v][q] = Ua[min(q, k - 1) * na + li[v]];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (l0 + 2 * u < na) {
+    for (int v = 0; v < 4; ++v) sv[v] = s[(size_t)min(row[v], slast) * kNB + c];
 #pragma unroll
-        for (int q = 0; q < kKmax; ++q)
-          if (q < k) acc[q] += Ua[q * na + li[u]] * sv[u];
-      }
+    for (int v = 0; v < 4; ++v) {
+      const T w = (l0 + 2 * v < na && row[v] < scut) ? sv[v] : T(0);
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q)
+        if (q < k) acc[q] += u[v][q] * w;
+    }
   }
 #pragma unroll
-  for (int q = 0; q < kKmax; ++q) acc[q] += __shfl_xor(acc[q], 32, 64);
-  const int c0 = R[AR_C0];
+  for (int q = 0; q < KMAX; ++q) acc[q] += __shfl_xor(acc[q], 32, 64);
 #pragma unroll
-  for (int q = 0; q < kKmax; ++q)
+  for (int q = 0; q < KMAX; ++q)
     if (q < k && (q & 1) == h) rc[(size_t)(c0 + q) * kNB + c] = acc[q];
   if (INIT == 1) {
-    const int db = R[AR_DB];
-    T xv[kKmax];
-    if (db >= 0) {
-      const T* B = cdblk + db;
+    T xv[KMAX];
 #pragma unroll
-      for (int l = 0; l < kKmax; ++l) {
-        xv[l] = T(0);
-        if (l < k) {
-          T t = acc[l];
+    for (int l = 0; l < KMAX; ++l) {
+      T t = acc[l];
 #pragma unroll
-          for (int q = 0; q < kKmax; ++q)
-            if (q < l) t -= B[l * k + q] * xv[q];
-          xv[l] = t / B[l * k + l];
-        }
-      }
-    } else {
-#pragma unroll
-      for (int l = 0; l < kKmax; ++l) xv[l] = T(0);
+      for (int q = 0; q < l; ++q) t -= bl[l * (l + 1) / 2 + q] * xv[q];
+      xv[l] = (db >= 0 && l < k) ? t / bl[l * (l + 1) / 2 + l] : T(0);
     }
 #pragma unroll
-    for (int q = 0; q < kKmax; ++q)
+    for (int q = 0; q < KMAX; ++q)
       if (q < k && (q & 1) == h) xc[(size_t)(c0 + q) * kNB + c] = xv[q];
   } else if (INIT == 2) {
 #pragma unroll
-    for (int q = 0; q < kKmax; ++q)
+    for (int q = 0; q < KMAX; ++q)
       if (q < k && (q & 1) == h) xc[(size_t)(c0 + q) * kNB + c] = acc[q] / cdl1[c0 + q];
   }
 }
@@ -565,13 +765,20 @@ __global__ __launch_bounds__(kBlock) void k_bprolong_rows(int n, int ld, const i
                                                           T* __restrict__ x) {
   const int c = threadIdx.x & 31;
   for (int i = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) >> 5; i < n; i += gridDim.x * kRowsPerBlock) {
+    // as k_prolong_rows: every load requested together, entries past k zero
+    const T xi = x[(size_t)i * kNB + c];
     const int ci = cinfo[i];
+    T u[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) u[q] = Urow[(size_t)q * ld + i];
     const int c0 = ci >> 3, k = (ci & 7) + 1;
     T t = T(0);
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q)
-      if (q < k) t += Urow[(size_t)q * ld + i] * xc[(size_t)(c0 + q) * kNB + c];
-    x[(size_t)i * kNB + c] += t;
+    for (int q = 0; q < KMAX; ++q) {
+      const T v = xc[(size_t)(c0 + min(q, k - 1)) * kNB + c];
+      t += (q < k ? u[q] : T(0)) * v;
+    }
+    x[(size_t)i * kNB + c] = xi + t;
   }
 }
 

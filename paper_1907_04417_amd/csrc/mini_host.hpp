@@ -33,7 +33,8 @@ std::vector<double> dense_spd_inverse(const HostLevel& C) {
       for (int k = i + 1; k < n; ++k) s -= M[(size_t)k * n + i] * y[k];
       y[i] = s / M[(size_t)i * n + i];
     }
-    for (int i = 0; i < n; ++i) inv[(size_t)i * n + j] = y[i];
+    // column j of the inverse, stored contiguously: inv[j n + i] = (A^-1)_ij
+    for (int i = 0; i < n; ++i) inv[(size_t)j * n + i] = y[i];
   }
   return inv;
 }

@@ -12,7 +12,7 @@
 
 namespace mvamg {
 
-constexpr int kMiniBlock = 256;
+constexpr int kMiniBlock = 1024;
 constexpr int kMiniMaxLevels = 16;
 constexpr int kMiniMaxIt = 1000;  // history slots per problem
 
@@ -31,7 +31,7 @@ struct MiniLevel {
 struct MiniProb {
   int nl, lev0, n;    // levels, first MiniLevel, fine rows
   int64_t perm0;      // ints: smoother order -> the problem's rows
-  int64_t ainv;       // reals: coarsest inverse (n_L x n_L, row-major)
+  int64_t ainv;       // reals: coarsest inverse (n_L x n_L, entry (i, j) at j n_L + i)
   int64_t row0;       // first row of the problem in the batch vectors
   int64_t cr, cz, cp, cq, cx;  // work: the CG vectors (n)
 };
@@ -150,9 +150,11 @@ __device__ void mini_vcycle(const MiniProb& P, const MiniLevel* lev, const int* 
     const double* rc = W + C.r;
     double* xc = W + C.x;
     const double* Ai = D + P.ainv;
+    // the inverse is stored column by column (entry (i, j) at j n + i), so
+    // the threads' reads of one j are adjacent
     for (int i = threadIdx.x; i < C.n; i += kMiniBlock) {
       double acc = 0.0;
-      for (int j = 0; j < C.n; ++j) acc += Ai[(int64_t)i * C.n + j] * rc[j];
+      for (int j = 0; j < C.n; ++j) acc += Ai[(int64_t)j * C.n + i] * rc[j];
       xc[i] = acc;
     }
     __syncthreads();

@@ -164,6 +164,16 @@ void bgs_stage(mvamg_hier* h, int l, const DevLevel& L, int c, const T* r, T* x,
   } else {
     const int g0 = L.h_sgrp[c], g1 = L.h_sgrp[c + 1];
     if (g1 <= g0) return;
+    if (L.gshared) {  // block per group over the shared column lists
+      switch (L.G0) {
+        case 1: klaunch(h, kc, by, k_bgs_grps<T, 1>, g1 - g0, kBlock, st, g0, g1, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, backward); break;
+        case 2: klaunch(h, kc, by, k_bgs_grps<T, 2>, g1 - g0, kBlock, st, g0, g1, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, backward); break;
+        case 4: klaunch(h, kc, by, k_bgs_grps<T, 4>, g1 - g0, kBlock, st, g0, g1, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, backward); break;
+        default: klaunch(h, kc, by, k_bgs_grps<T, 8>, g1 - g0, kBlock, st, g0, g1, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, backward); break;
+      }
+      LAUNCHCHECK("bgs_stage");
+      return;
+    }
     const int grid = (g1 - g0 + 3) / 4;
     switch (L.G) {
       case 1: klaunch(h, kc, by, k_bgs_grp<T, 1>, grid, kBlock, st, g0, g1, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, backward); break;
@@ -202,12 +212,22 @@ void bresid(mvamg_hier* h, const DevLevel& L, const T* r, const T* x, T* s, int 
   if (L.sell) {
     const int ns = part_rows ? L.h_sslab[nst] : L.nslabs;
     if (part_rows) grid = std::max(1, std::min(grid, ns * (64 / kRowsPerBlock)));
+    // slabs in spatial order where the rows span several stages (their
+    // neighbours' rows are then read by one XCD, close in time)
+    const Slab* sl = !part_rows ? L.bslab_full : (nst == L.ns - 1 ? L.bslab_part : L.slabs);
     if (ns > 0)
-      klaunch(h, kc, by, k_bresid_sell<T, MODE>, grid, kBlock, st, L.slabs, ns, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part);
+      klaunch(h, kc, by, k_bresid_sell<T, MODE>, grid, kBlock, st, sl, ns, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part);
   } else {
     const int ng = part_rows ? L.h_sgrp[nst] : L.ng;
     if (part_rows) grid = std::max(1, std::min(grid, (ng + 3) / 4));
-    if (ng > 0) switch (L.G) {
+    if (MODE == 0 && L.gshared && ng > 0) {  // block per group over the shared column lists
+      switch (L.G0) {
+        case 1: klaunch(h, kc, by, k_bresid_grps<T, 1>, ng, kBlock, st, ng, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, s); break;
+        case 2: klaunch(h, kc, by, k_bresid_grps<T, 2>, ng, kBlock, st, ng, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, s); break;
+        case 4: klaunch(h, kc, by, k_bresid_grps<T, 4>, ng, kBlock, st, ng, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, s); break;
+        default: klaunch(h, kc, by, k_bresid_grps<T, 8>, ng, kBlock, st, ng, L.rec, L.gcol, lval<T>(L), ldblk<T>(L), r, x, s); break;
+      }
+    } else if (ng > 0) switch (L.G) {
       case 1: klaunch(h, kc, by, k_bresid_grp<T, 1, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part); break;
       case 2: klaunch(h, kc, by, k_bresid_grp<T, 2, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part); break;
       case 4: klaunch(h, kc, by, k_bresid_grp<T, 4, MODE>, grid, kBlock, st, ng, L.rec, L.col, lval<T>(L), ldblk<T>(L), r, x, s, part); break;
@@ -284,15 +304,28 @@ void bvcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t s
   const int tg = (P.nagg + 3) / 4;
   const double tby = (double)P.nu * sizeof(T) + 4.0 * L.n + (double)scut * kNB * sizeof(T) + (double)C.n * kNB * sizeof(T);
   const bool next_smoothed = (l + 2 < h->nl);
-  if (!next_smoothed) {
-    klaunch(h, MVAMG_KC_RESTRICT, tby, k_brestrict<T, 0>, tg, kBlock, st, P.nagg, P.arec, P.arows, tU<T>(P), s, scut, rc,
-            (const T*)nullptr, (const T*)nullptr, (T*)nullptr);
-  } else if (smoother == MVAMG_SMOOTH_GS) {
-    klaunch(h, MVAMG_KC_RESTRICT, tby + (double)C.n * kNB * sizeof(T), k_brestrict<T, 1>, tg, kBlock, st, P.nagg,
-            P.arec, P.arows, tU<T>(P), s, scut, rc, ldblk<T>(C), (const T*)nullptr, xc);
-  } else {
-    klaunch(h, MVAMG_KC_RESTRICT, tby + (double)C.n * kNB * sizeof(T), k_brestrict<T, 2>, tg, kBlock, st, P.nagg,
-            P.arec, P.arows, tU<T>(P), s, scut, rc, (const T*)nullptr, ldl1<T>(C), xc);
+  // KMAX: the transfer's widest aggregate basis rounded up to 1, 2, 4 or 8
+  auto launch = [&](auto km, auto init) {
+    constexpr int KM = decltype(km)::value, IN = decltype(init)::value;
+    const double by = tby + (IN == 0 ? 0.0 : (double)C.n * kNB * sizeof(T));
+    klaunch(h, MVAMG_KC_RESTRICT, by, k_brestrict<T, KM, IN>, tg, kBlock, st, P.nagg, P.arec, P.arows, tU<T>(P), s,
+            scut, rc, IN == 1 ? ldblk<T>(C) : (const T*)nullptr, IN == 2 ? ldl1<T>(C) : (const T*)nullptr,
+            IN == 0 ? (T*)nullptr : xc);
+  };
+  auto by_init = [&](auto km) {
+    if (!next_smoothed)
+      launch(km, std::integral_constant<int, 0>{});
+    else if (smoother == MVAMG_SMOOTH_GS)
+      launch(km, std::integral_constant<int, 1>{});
+    else
+      launch(km, std::integral_constant<int, 2>{});
+  };
+  switch (P.kmax) {
+    case 1: by_init(std::integral_constant<int, 1>{}); break;
+    case 2: by_init(std::integral_constant<int, 2>{}); break;
+    case 3:
+    case 4: by_init(std::integral_constant<int, 4>{}); break;
+    default: by_init(std::integral_constant<int, 8>{}); break;
   }
   LAUNCHCHECK("brestrict");
   bvcycle<T>(h, l + 1, rc, xc, smoother, st, next_smoothed);

@@ -62,6 +62,7 @@ struct DevLevel {
   int G = 8;   // kernel instantiation of a grouped level: 64 / G lanes per row (autotuned, >= G0)
   int G0 = 8;  // smallest admissible G: the level's largest group rounded up to a power of two
   bool wide = false;  // grouped level: one block of kWide threads per group (autotuned)
+  bool gshared = false;  // grouped level whose groups all share one column list per group
   int ng = 0, ns = 0, nslabs = 0;
   int rows0 = 0;  // rows of stage 0 (point levels)
   std::vector<int> h_sgrp, h_sslab;
@@ -72,6 +73,13 @@ struct DevLevel {
   int64_t ndblk = 0;
   // device arrays
   Slab* slabs = nullptr;
+  // sliced ELL: the slabs again, in the order of the file index of their
+  // first row (for a grid numbering, spatial order), for the block kernels
+  // that sweep many stages at once: all stages (bslab_full) or all but the
+  // last (bslab_part, nslab_part of them).  Neighbouring rows of different
+  // colours are then handled close in time, by the same XCD.
+  Slab *bslab_full = nullptr, *bslab_part = nullptr;
+  int nslab_part = 0;
   int* rowptr = nullptr;
   int* rec = nullptr;  // per group: 16-int record (first row, rows, block offset, row entry offsets)
   int* col = nullptr;
@@ -1173,6 +1181,7 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
       L.sell = y.sell;
       L.G = y.G;
       L.G0 = y.G;
+      L.gshared = !y.sell && y.all_shared;
       L.ng = (int)y.gstart.size() - 1;
       L.ns = (int)y.sgrp.size() - 1;
       L.h_sgrp = y.sgrp;
@@ -1194,6 +1203,20 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
       L.ndblk = (int64_t)y.dblk.size();
       if (y.sell) {
         L.slabs = h->upload_vec(y.slabs, st);
+        {
+          auto spatial = [&](int q1) {
+            std::vector<int> o(q1);
+            for (int q = 0; q < q1; ++q) o[q] = q;
+            std::stable_sort(o.begin(), o.end(),
+                             [&](int a, int b) { return y.perm[y.slabs[a].row0] < y.perm[y.slabs[b].row0]; });
+            std::vector<Slab> v(q1);
+            for (int q = 0; q < q1; ++q) v[q] = y.slabs[o[q]];
+            return v;
+          };
+          L.nslab_part = y.sslab[L.ns - 1];
+          L.bslab_full = h->upload_vec(spatial(L.nslabs), st);
+          L.bslab_part = L.nslab_part > 0 ? h->upload_vec(spatial(L.nslab_part), st) : nullptr;
+        }
         L.col16 = h->upload_vec(y.col16, st);
         L.pk = h->upload_vec(y.pk, st);
         L.cbase = h->upload_vec(y.cbase.empty() ? std::vector<int>(8, 0) : y.cbase, st);
@@ -1316,8 +1339,12 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
         const int nf = H.lv[l].n;
         int kmax = 1;
         for (int a = 0; a < T.nagg; ++a) kmax = std::max(kmax, T.kk[a]);
+        if (kmax > kKmax) throw Error(MVAMG_ERR_ARG, "aggregate basis wider than 8 columns is not supported");
+        // the prolongation kernels read all planes of their instantiation
+        // (kmax rounded up to 1, 2, 4 or 8); planes past an aggregate's k are zero
+        const int kpad = kmax <= 1 ? 1 : kmax <= 2 ? 2 : kmax <= 4 ? 4 : 8;
         std::vector<int> cinfo(nf);
-        std::vector<double> urow((size_t)kmax * nf, 0.0);
+        std::vector<double> urow((size_t)kpad * nf, 0.0);
         for (int a = 0; a < T.nagg; ++a) {
           const int m = T.aptr[a + 1] - T.aptr[a], k = T.kk[a];
           if ((int64_t)T.cst[a] * 8 >= ((int64_t)1 << 31)) throw Error(MVAMG_ERR_ARG, "coarse level too large");
