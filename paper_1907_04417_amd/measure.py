@@ -35,6 +35,8 @@ def kernel_class(name: str) -> str | None:
         return "smooth_fine"
     if "k_bgs_grp" in name or "k_bzero_stage0_grp" in name:
         return "smooth_coarse"
+    if "k_bresid_grps" in name:  # block per group: residual only
+        return "residual"
     m = re.search(r"k_bresid_(sell|grp)<double,(?:\d,)?(\d)>", name.replace(" ", ""))
     if m:
         return "spmv" if m.group(2) == "1" else "residual"

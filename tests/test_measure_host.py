@@ -32,6 +32,8 @@ def test_grouped_smoothers_take_the_level_of_the_dispatch_order():
 
 def test_wide_kernels_are_classed():
     assert kernel_class("void mvamg::k_resid_grp_wide<double, 8>(int)") == "residual"
+    assert kernel_class("void mvamg::k_bresid_grps<double, 4>(int)") == "residual"
+    assert kernel_class("void mvamg::k_bgs_grps<double, 4>(int)") in ("smooth_fine", "smooth_coarse")
     assert kernel_class("void mvamg::k_gs_grp_wide<double, 8, 1>(int)") in ("smooth_fine", "smooth_coarse")
     names = _cycle("void mvamg::k_gs_grp<double, 4, {}>(int)", "void mvamg::k_gs_grp_wide<double, 8, {}>(int)",
                    "void mvamg::k_resid_grp_wide<double, 8>(int)")
