@@ -153,11 +153,18 @@ __global__ __launch_bounds__(kBlock) void k_bdot(int n, const double* __restrict
   if (NV > 1) bcol_partials(s1, 1, part);
 }
 
-// columns still running: x += alpha_c p, r -= alpha_c q; per-column r.r
-__global__ __launch_bounds__(kBlock) void k_baxpy2_dot(int n, const double* __restrict__ scal,
-                                                       const double* __restrict__ p, const double* __restrict__ q,
-                                                       double* __restrict__ x, double* __restrict__ r,
-                                                       double* __restrict__ part) {
+// columns still running: r -= alpha_c q; per-column r.r.  The matching
+// x += alpha_c p is deferred to the next p update (k_bxpay), which reads p
+// anyway, or to k_bx_update after the last step: alpha stays in the column's
+// scalars until the next p.A p replaces it (with zero once the column has
+// stopped), so no update is lost or applied twice.
+// rows0 > 0: also the first stage of the next cycle's forward sweep from
+// zero on a point fine level, z = r / d on the rows below rows0 (as
+// k_bstage0_point, from the new r).
+__global__ __launch_bounds__(kBlock) void k_br_update_dot(int n, const double* __restrict__ scal,
+                                                          const double* __restrict__ q, double* __restrict__ r,
+                                                          double* __restrict__ part, int rows0,
+                                                          const double* __restrict__ diag, double* __restrict__ z) {
   const int c = threadIdx.x & 31;
   const double alpha = scal[c * S_NSCAL + S_ALPHA];
   const bool act = scal[c * S_NSCAL + S_ACT] != 0.0;
@@ -166,23 +173,37 @@ __global__ __launch_bounds__(kBlock) void k_baxpy2_dot(int n, const double* __re
     const size_t i = (size_t)row * kNB + c;
     double ri = r[i];
     if (act) {
-      x[i] += alpha * p[i];
       ri -= alpha * q[i];
       r[i] = ri;
     }
     s += ri * ri;
+    if (row < rows0) z[i] = ri / diag[row];
   }
   bcol_partials(s, 0, part);
 }
 
-// p = z + beta_c p
+// x += alpha_c p (the previous step's, deferred), then p = z + beta_c p
 __global__ __launch_bounds__(kBlock) void k_bxpay(int n, const double* __restrict__ scal,
-                                                  const double* __restrict__ z, double* __restrict__ p) {
+                                                  const double* __restrict__ z, double* __restrict__ p,
+                                                  double* __restrict__ x) {
   const int c = threadIdx.x & 31;
-  const double beta = scal[c * S_NSCAL + S_BETA];
+  const double beta = scal[c * S_NSCAL + S_BETA], alpha = scal[c * S_NSCAL + S_ALPHA];
   for (int row = (blockIdx.x * kBlock + threadIdx.x) >> 5; row < n; row += gridDim.x * kRowsPerBlock) {
     const size_t i = (size_t)row * kNB + c;
-    p[i] = z[i] + beta * p[i];
+    const double pi = p[i];
+    x[i] += alpha * pi;
+    p[i] = z[i] + beta * pi;
+  }
+}
+
+// x += alpha_c p: the deferred update of the last step
+__global__ __launch_bounds__(kBlock) void k_bx_update(int n, const double* __restrict__ scal,
+                                                      const double* __restrict__ p, double* __restrict__ x) {
+  const int c = threadIdx.x & 31;
+  const double alpha = scal[c * S_NSCAL + S_ALPHA];
+  for (int row = (blockIdx.x * kBlock + threadIdx.x) >> 5; row < n; row += gridDim.x * kRowsPerBlock) {
+    const size_t i = (size_t)row * kNB + c;
+    x[i] += alpha * p[i];
   }
 }
 

@@ -280,7 +280,8 @@ void bcoarse_solve(mvamg_hier* h, const T* r, T* z, hipStream_t st) {
 
 // X = B_l R for block vectors (one V-cycle from a zero guess per column)
 template <typename T>
-void bvcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st, bool x_started = false) {
+void bvcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t st, bool x_started = false,
+             bool stage0_written = false) {
   if (l == h->nl - 1) {
     bcoarse_solve<T>(h, r, x, st);
     return;
@@ -292,7 +293,9 @@ void bvcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t s
   T* rc = pick<T>(C.br, C.br32);
   T* xc = pick<T>(C.bx, C.bx32);
   if (smoother == MVAMG_SMOOTH_GS) {
-    if (!x_started) bzero_stage0<T>(h, l, L, r, x, st);
+    // stage0_written: a point level's stage 0 of the sweep from zero is
+    // already in x (written with r by the CG update); the other rows are not set
+    if (!x_started && !stage0_written) bzero_stage0<T>(h, l, L, r, x, st);
     for (int c = 1; c < L.ns; ++c) bgs_stage<T>(h, l, L, c, r, x, 0, st, !x_started && L.sell);
   } else if (!x_started) {
     k_bl1_init<T><<<bgrid_elem(L.n), kBlock, 0, st>>>(L.n, ldl1<T>(L), r, x);
@@ -355,9 +358,10 @@ void bvcycle(mvamg_hier* h, int l, const T* r, T* x, int smoother, hipStream_t s
 }
 
 // Z = B R for level-0 binary64 block vectors in smoother order
-void bapply_B(mvamg_hier* h, const double* r, double* z, int precision, int smoother, hipStream_t st) {
+void bapply_B(mvamg_hier* h, const double* r, double* z, int precision, int smoother, hipStream_t st,
+              bool stage0_written = false) {
   if (precision == 64) {
-    bvcycle<double>(h, 0, r, z, smoother, st);
+    bvcycle<double>(h, 0, r, z, smoother, st, false, stage0_written);
   } else {
     DevLevel& L = h->lv[0];
     const int64_t m = (int64_t)L.n * kNB;
@@ -389,11 +393,16 @@ struct MultiOps {
                         hipStream_t st) {
     dot(a, b, c, d, nv, mode, st);
   }
-  virtual void cycle(int precision, int smoother, hipStream_t st) = 0;  // z = B r
+  // z = B r; after_update: r comes from this solve's last axpy2, which may
+  // have written the first sweep stage of z already (see BlockOps)
+  virtual void cycle(int precision, int smoother, hipStream_t st, bool after_update) = 0;
+  int precision = 64, smoother = MVAMG_SMOOTH_GS;  // of the solve in progress
   virtual void copy_zp(hipStream_t st) = 0;
   virtual void spmv_pq(hipStream_t st) = 0;    // q = A p, per-system p.q (MM_PQ)
   virtual void axpy2(hipStream_t st) = 0;      // x += alpha p, r -= alpha q, per-system r.r (MM_STORE_RR)
   virtual void xpay(hipStream_t st) = 0;       // p = z + beta p
+  // an x update that axpy2 defers to the next xpay, applied after the last step
+  virtual void flush(hipStream_t) {}
 };
 
 void multi_step_a(MultiOps& O, hipStream_t st) {
@@ -405,7 +414,7 @@ void multi_step_a(MultiOps& O, hipStream_t st) {
 }
 
 void multi_step_b(MultiOps& O, int precision, int smoother, hipStream_t st) {
-  O.cycle(precision, smoother, st);
+  O.cycle(precision, smoother, st, true);
   if (precision == 32)
     O.dot_iter(O.z, O.r, O.z, O.q, 2, MM_RZ_FLEX, st);
   else
@@ -471,6 +480,8 @@ mvamg_status multi_pcg(MultiOps& O, const double* b, double* x, const mvamg_solv
   const bool flex = (prm->precision == 32);
   const int max_restarts = flex ? std::max(0, prm->max_restarts) : 0;
   const size_t hstride = (size_t)prm->maxit + 1;
+  O.precision = prm->precision;
+  O.smoother = prm->smoother;
   O.load(b, x, st);
   k_minit<<<1, kBlock, 0, st>>>(ns, M.scal, prm->rtol);
   LAUNCHCHECK("minit");
@@ -505,7 +516,7 @@ mvamg_status multi_pcg(MultiOps& O, const double* b, double* x, const mvamg_solv
     for (int s = 0; s < ns; ++s)
       if (run[s]) met[s] = 0;
     upload_active(h, ns, act, st);
-    O.cycle(prm->precision, prm->smoother, st);
+    O.cycle(prm->precision, prm->smoother, st, false);
     O.dot(O.r, O.z, nullptr, nullptr, 1, MM_RHO0, st);
     O.copy_zp(st);
     hipGraphExec_t ge = (h->use_graphs && !h->prof) ? multi_graph(O, prm->precision, prm->smoother) : nullptr;
@@ -544,6 +555,7 @@ mvamg_status multi_pcg(MultiOps& O, const double* b, double* x, const mvamg_solv
       }
       if (changed && any(act)) upload_active(h, ns, act, st);
     }
+    O.flush(st);
     if (!flex) {
       for (int s = 0; s < ns; ++s)
         if (run[s]) {
@@ -630,22 +642,36 @@ struct BlockOps : MultiOps {
     }
     LAUNCHCHECK("bdot");
   }
-  void cycle(int precision, int smoother, hipStream_t st) override { bapply_B(h, r, z, precision, smoother, st); }
+  // The binary64 Gauss-Seidel cycle on a point fine level starts with z = r / d
+  // on stage 0; the residual update writes those rows with the new r.
+  bool fuse_stage0() const {
+    return precision == 64 && smoother == MVAMG_SMOOTH_GS && h->lv[0].sell && h->nl > 1;
+  }
+  void cycle(int prec, int sm, hipStream_t st, bool after_update) override {
+    bapply_B(h, r, z, prec, sm, st, after_update && fuse_stage0());
+  }
   void copy_zp(hipStream_t st) override {
     const int64_t e = (int64_t)n() * kNB;
     k_copy<double><<<grid_elem(e), kBlock, 0, st>>>((int)e, z, p);
     LAUNCHCHECK("bcopy");
   }
   void spmv_pq(hipStream_t st) override { bresid<double, 1>(h, h->lv[0], nullptr, p, q, MM_PQ, st); }
+  // r -= alpha q now; x += alpha p with the next p update (or flush)
   void axpy2(hipStream_t st) override {
     const int grid = bgrid_for(n());
-    k_baxpy2_dot<<<grid, kBlock, 0, st>>>(n(), h->mb.scal, p, q, h->bxv, r, h->mb.part);
+    const DevLevel& L = h->lv[0];
+    k_br_update_dot<<<grid, kBlock, 0, st>>>(n(), h->mb.scal, q, r, h->mb.part, fuse_stage0() ? L.rows0 : 0,
+                                             ldblk<double>(L), z);
     k_mfinish<1><<<kNB, kBlock, 0, st>>>(kNB, grid, h->mb.part, h->mb.scal, MM_STORE_RR);
-    LAUNCHCHECK("baxpy2");
+    LAUNCHCHECK("br_update");
   }
   void xpay(hipStream_t st) override {
-    k_bxpay<<<bgrid_elem(n()), kBlock, 0, st>>>(n(), h->mb.scal, z, p);
+    k_bxpay<<<bgrid_elem(n()), kBlock, 0, st>>>(n(), h->mb.scal, z, p, h->bxv);
     LAUNCHCHECK("bxpay");
+  }
+  void flush(hipStream_t st) override {
+    k_bx_update<<<bgrid_elem(n()), kBlock, 0, st>>>(n(), h->mb.scal, p, h->bxv);
+    LAUNCHCHECK("bx_update");
   }
 };
 
@@ -724,9 +750,9 @@ struct BatchOps : MultiOps {
                 hipStream_t st) override {
     pdot(a, b, c, d, nv, mode, act(), st);
   }
-  void cycle(int precision, int smoother, hipStream_t st) override {
+  void cycle(int prec, int sm, hipStream_t st, bool) override {
     SkipScope sk(h, host_act);
-    apply_B(h, r, z, precision, smoother, st);
+    apply_B(h, r, z, prec, sm, st);
   }
   void copy_zp(hipStream_t st) override {
     k_copy<double><<<grid_elem(h->n), kBlock, 0, st>>>(h->n, z, p);
