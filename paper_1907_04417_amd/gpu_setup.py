@@ -26,9 +26,6 @@ def _iptr(a):
 
 
 def setup_level(rowptr, col, val, W, aptr, arows, tol: float = 0.1, stream=None):
-    import torch
-    L = mvamg.load()
-    st = mvamg._stream(stream)
     rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
     col = np.ascontiguousarray(col, dtype=np.int32)
     aptr = np.ascontiguousarray(aptr, dtype=np.int32)
@@ -36,10 +33,22 @@ def setup_level(rowptr, col, val, W, aptr, arows, tol: float = 0.1, stream=None)
     W = np.ascontiguousarray(W, dtype=np.float64)
     n, m = W.shape
     nagg = aptr.shape[0] - 1
-    if rowptr.shape[0] != n + 1 or col.shape[0] != rowptr[-1] or np.asarray(val).shape[0] != rowptr[-1]:
+    # the kernels index with these arrays' contents, so they are checked here,
+    # on the host, before anything reaches the device
+    if rowptr.shape[0] != n + 1 or rowptr[0] != 0 or np.any(np.diff(rowptr) < 0):
+        raise ValueError("rowptr must start at 0 and not decrease, with n + 1 entries")
+    if col.shape[0] != rowptr[-1] or np.asarray(val).shape[0] != rowptr[-1]:
         raise ValueError("A's arrays do not match the level size")
-    if arows.shape[0] != n or aptr[-1] != n:
+    if col.size and (col.min() < 0 or col.max() >= n):
+        raise ValueError("column index out of range")
+    if aptr.shape[0] < 2 or aptr[0] != 0 or aptr[-1] != n or np.any(np.diff(aptr) < 1):
+        raise ValueError("aggregates must be non-empty ranges that cover every row")
+    if arows.shape[0] != n or (n and (arows.min() < 0 or arows.max() >= n)) or \
+            np.any(np.bincount(arows, minlength=n) != 1):
         raise ValueError("aggregates must list every row once")
+    import torch
+    L = mvamg.load()
+    st = mvamg._stream(stream)
     d_aptr, d_arows = _dev(torch, aptr, np.int32), _dev(torch, arows, np.int32)
     d_W = _dev(torch, W, np.float64)
     d_k = torch.zeros(nagg, dtype=torch.int32, device="cuda")

@@ -115,3 +115,57 @@ def test_matrix_arrays_are_checked(handle):
             mvamg.pcg_solve(handle, _fake(10), _fake(10), A=A)
         with pytest.raises(ValueError, match=msg):
             mvamg.adjoint_solve(handle, _fake(10), _fake(10), A=A)
+
+
+def _level_args(n=6):
+    """A valid 1-D Laplacian level of n rows with aggregates of two rows."""
+    rowptr, col, val = [0], [], []
+    for i in range(n):
+        for j in (i - 1, i, i + 1):
+            if 0 <= j < n:
+                col.append(j)
+                val.append(2.0 if i == j else -1.0)
+        rowptr.append(len(col))
+    W = np.ones((n, 1))
+    aptr = np.arange(0, n + 1, 2)
+    arows = np.arange(n)
+    return [np.array(rowptr), np.array(col), np.array(val), W, aptr, arows]
+
+
+@pytest.mark.parametrize("case", [
+    "rowptr_len", "rowptr_start", "rowptr_decreasing", "col_len", "val_len",
+    "col_negative", "col_high", "aptr_short", "aptr_empty_agg", "aptr_end",
+    "arows_len", "arows_dup", "arows_high"])
+def test_setup_level_rejects_bad_level(case):
+    """Level set-up checks A and the aggregates before any device use."""
+    from paper_1907_04417_amd import gpu_setup
+    a = _level_args()
+    rowptr, col, val, W, aptr, arows = a
+    if case == "rowptr_len":
+        a[0] = rowptr[:-1]
+    elif case == "rowptr_start":
+        a[0] = rowptr + 1
+    elif case == "rowptr_decreasing":
+        r = rowptr.copy(); r[2], r[3] = r[3], r[2]; a[0] = r
+    elif case == "col_len":
+        a[1] = col[:-1]
+    elif case == "val_len":
+        a[2] = val[:-1]
+    elif case == "col_negative":
+        c = col.copy(); c[0] = -1; a[1] = c
+    elif case == "col_high":
+        c = col.copy(); c[-1] = 6; a[1] = c
+    elif case == "aptr_short":
+        a[4] = np.array([0])
+    elif case == "aptr_empty_agg":
+        a[4] = np.array([0, 2, 2, 6])
+    elif case == "aptr_end":
+        a[4] = np.array([0, 2, 4, 5])
+    elif case == "arows_len":
+        a[5] = arows[:-1]
+    elif case == "arows_dup":
+        r = arows.copy(); r[1] = 0; a[5] = r
+    elif case == "arows_high":
+        r = arows.copy(); r[5] = 6; a[5] = r
+    with pytest.raises(ValueError):
+        gpu_setup.setup_level(*a, tol=0.1)
