@@ -23,7 +23,8 @@ class _Params(ctypes.Structure):
                 ("compose", ctypes.c_int), ("coarse_cap", ctypes.c_int),
                 ("boot_coarse_min", ctypes.c_int), ("hier_stage", ctypes.c_int),
                 ("store_w", ctypes.c_int), ("max_levels", ctypes.c_int),
-                ("nthreads", ctypes.c_int), ("fine_group", ctypes.c_int)]
+                ("nthreads", ctypes.c_int), ("fine_group", ctypes.c_int),
+                ("boot_dense_max", ctypes.c_int), ("coarsest_max", ctypes.c_int)]
 
 
 @dataclass
@@ -48,6 +49,14 @@ class SetupParams:
     max_levels: int = 40
     nthreads: int = 0
     fine_group: int = 1
+    # a bootstrap hierarchy's coarsest level is factored densely up to this
+    # many rows and by a sparse Cholesky above (only a coarsening that stalls
+    # stops above it)
+    boot_dense_max: int = 4096
+    # the coarsest multiple-vector level may have at most this many rows; when
+    # the last bootstrap stage's levels cannot get there, those of the latest
+    # earlier stage that can are composed
+    coarsest_max: int = 8192
 
 
 _lib = None
@@ -77,6 +86,9 @@ def _load():
         lib.mvsetup_aggregate_basis.argtypes = [P(ctypes.c_double), ctypes.c_int, ctypes.c_int,
                                                 ctypes.c_double, P(ctypes.c_double), P(ctypes.c_double)]
         lib.mvsetup_aggregate_basis.restype = ctypes.c_int
+        lib.mvsetup_sparse_solve.argtypes = [ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_double),
+                                             P(ctypes.c_double), P(ctypes.c_double)]
+        lib.mvsetup_sparse_solve.restype = ctypes.c_int64
         _lib = lib
     return _lib
 
@@ -107,7 +119,8 @@ def build_hierarchy(rowptr, col, val, path: str, x0: np.ndarray, params: SetupPa
     if x0.size < k * n:
         raise ValueError(f"x0 must hold {k} vectors of length {n}")
     cp = _Params(p.nvec_max, p.nu, p.rho_des, p.maxstage, p.tol_svd, p.compose, p.coarse_cap,
-                 p.boot_coarse_min, p.hier_stage, p.store_w, p.max_levels, p.nthreads, p.fine_group)
+                 p.boot_coarse_min, p.hier_stage, p.store_w, p.max_levels, p.nthreads, p.fine_group,
+                 p.boot_dense_max, p.coarsest_max)
     stats = np.zeros(64)
     rc = lib.mvsetup_build_boot(n, _ptr(rp, ctypes.c_int), _ptr(ci, ctypes.c_int), _ptr(v, ctypes.c_double),
                                 _ptr(x0, ctypes.c_double), ctypes.byref(cp), path.encode(),
@@ -117,7 +130,7 @@ def build_hierarchy(rowptr, col, val, path: str, x0: np.ndarray, params: SetupPa
     nl = int(stats[0])
     ns = int(stats[4])
     return dict(nlevels=nl, nvec=int(stats[1]), opc=float(stats[2]), cr=float(stats[3]),
-                rho=[float(r) for r in stats[5:5 + ns]],
+                rho=[float(r) for r in stats[5:5 + min(ns, 18)]], composed_stage=int(stats[23]),
                 n=[int(x) for x in stats[24:24 + nl]], nnz=[int(x) for x in stats[44:44 + nl]])
 
 
@@ -161,3 +174,19 @@ def aggregate_basis(Pa: np.ndarray, tol_a: float):
     if k < 0:
         raise RuntimeError(lib.mvsetup_last_error().decode())
     return U[:na * k].reshape(na, k), d2.value
+
+
+def sparse_solve(rowptr, col, val, b):
+    """Solve A x = b with the sparse Cholesky factor the setup uses for a
+    bootstrap coarsest level above the dense limit.  Returns (x, fill), fill
+    the number of off-diagonal entries of L."""
+    lib = _load()
+    rp, ci, v = _csr(rowptr, col, val)
+    n = rp.shape[0] - 1
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(n)
+    nl = lib.mvsetup_sparse_solve(n, _ptr(rp, ctypes.c_int), _ptr(ci, ctypes.c_int), _ptr(v, ctypes.c_double),
+                                  _ptr(b, ctypes.c_double), _ptr(x, ctypes.c_double))
+    if nl < 0:
+        raise RuntimeError("sparse solve failed: " + lib.mvsetup_last_error().decode())
+    return x, int(nl)

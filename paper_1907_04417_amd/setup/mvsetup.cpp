@@ -21,6 +21,9 @@
 //     restricted smooth vectors (eq. 4.3) truncated at
 //     TOL * size(a)/size(A) (Section 5), block-diagonal orthonormal P and
 //     Galerkin coarse matrices, smooth vectors projected level by level;
+//   * a direct solve on the coarsest level of every bootstrap hierarchy: a
+//     dense Cholesky factor, or a sparse one (minimum-degree order) where a
+//     stalled coarsening left that level large;
 //   * the Gauss-Seidel order of every non-coarsest level: a greedy first-fit
 //     colouring of groups of rows (single rows on the finest level, the k_a
 //     coarse dofs of one aggregate on coarser levels), groups listed colour by
@@ -34,6 +37,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <string>
@@ -586,6 +590,129 @@ void dense_cholesky_solve(const std::vector<double>& L, int n, const double* b, 
   }
 }
 
+// Sparse Cholesky L L^T = A(perm, perm) of a coarsest level too large for the
+// dense factor (a bootstrap hierarchy whose coarsening stalled).  The pivot
+// order is minimum degree on the elimination graph (ties to the lower index):
+// eliminating a vertex joins its remaining neighbours into a clique, and that
+// neighbour set is the pattern of its column of L.  The graphs a stall leaves
+// are star-like (many degree-1 vertices around a few hubs), which this order
+// eliminates leaf first, with little fill.
+struct SparseChol {
+  int n = 0;
+  std::vector<int> perm;       // perm[k]: row of A eliminated k-th
+  std::vector<int64_t> lp;     // column k of L below the diagonal: li/lx[lp[k] .. lp[k + 1])
+  std::vector<int> li;         // pivot positions, increasing within a column
+  std::vector<double> lx, ld;  // off-diagonal values, diagonal of L
+};
+
+SparseChol sparse_cholesky(const Csr& A) {
+  const int n = A.n;
+  SparseChol F;
+  F.n = n;
+  std::vector<std::vector<int>> adj(n);  // uneliminated neighbours, sorted
+  for (int i = 0; i < n; ++i)
+    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
+      if (A.ci[k] != i) adj[i].push_back(A.ci[k]);
+  std::vector<char> gone(n, 0);
+  std::vector<std::pair<int, int>> heap;  // (degree, vertex), lazily updated
+  auto cmp = [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a > b; };
+  for (int i = 0; i < n; ++i) heap.push_back({(int)adj[i].size(), i});
+  std::make_heap(heap.begin(), heap.end(), cmp);
+  std::vector<std::vector<int>> pat(n);  // column patterns as vertices
+  std::vector<int> merged;
+  F.perm.reserve(n);
+  while (!heap.empty()) {
+    std::pop_heap(heap.begin(), heap.end(), cmp);
+    const auto [deg, v] = heap.back();
+    heap.pop_back();
+    if (gone[v] || deg != (int)adj[v].size()) continue;  // stale entry
+    gone[v] = 1;
+    F.perm.push_back(v);
+    const std::vector<int>& nb = adj[v];
+    for (int u : nb) {
+      merged.clear();
+      std::set_union(adj[u].begin(), adj[u].end(), nb.begin(), nb.end(), std::back_inserter(merged));
+      merged.erase(std::remove_if(merged.begin(), merged.end(), [&](int x) { return x == u || x == v; }),
+                   merged.end());
+      const bool changed = merged.size() != adj[u].size();
+      adj[u].swap(merged);
+      if (changed) {  // the entry with the old degree goes stale
+        heap.push_back({(int)adj[u].size(), u});
+        std::push_heap(heap.begin(), heap.end(), cmp);
+      }
+    }
+    pat[v] = std::move(adj[v]);
+    adj[v].clear();
+  }
+  if ((int)F.perm.size() != n) fail("sparse coarsest factor: ordering incomplete");
+  std::vector<int> pos(n);
+  for (int k = 0; k < n; ++k) pos[F.perm[k]] = k;
+  F.lp.assign(n + 1, 0);
+  for (int k = 0; k < n; ++k) F.lp[k + 1] = F.lp[k] + (int64_t)pat[F.perm[k]].size();
+  F.li.resize(F.lp[n]);
+  F.lx.assign(F.lp[n], 0.0);
+  F.ld.assign(n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    int* c = F.li.data() + F.lp[k];
+    int t = 0;
+    for (int u : pat[F.perm[k]]) c[t++] = pos[u];
+    std::sort(c, c + t);
+  }
+  pat.clear();
+  // rows of L: for pivot j, the columns k < j with L(j, k) != 0 and where j sits in them
+  std::vector<int64_t> rp(n + 1, 0);
+  for (int64_t q = 0; q < F.lp[n]; ++q) rp[F.li[q] + 1]++;
+  for (int j = 0; j < n; ++j) rp[j + 1] += rp[j];
+  std::vector<int64_t> rq(F.lp[n]), fill(rp.begin(), rp.end() - 1);
+  std::vector<int> rk(F.lp[n]);
+  for (int k = 0; k < n; ++k)
+    for (int64_t q = F.lp[k]; q < F.lp[k + 1]; ++q) {
+      rk[fill[F.li[q]]] = k;
+      rq[fill[F.li[q]]++] = q;
+    }
+  // left-looking numeric factorization with a dense work column
+  std::vector<double> w(n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    const int r = F.perm[j];
+    for (int k = A.rp[r]; k < A.rp[r + 1]; ++k) {
+      const int pj = pos[A.ci[k]];
+      if (pj >= j) w[pj] += A.v[k];
+    }
+    for (int64_t t = rp[j]; t < rp[j + 1]; ++t) {
+      const int64_t q = rq[t];  // L(j, k) at position q of column k
+      const int k = rk[t];
+      const double ljk = F.lx[q];
+      for (int64_t e = q; e < F.lp[k + 1]; ++e) w[F.li[e]] -= F.lx[e] * ljk;
+    }
+    const double d = w[j];
+    if (!(d > 0.0)) fail("coarsest matrix is not positive definite");
+    const double ljj = std::sqrt(d);
+    F.ld[j] = ljj;
+    w[j] = 0.0;
+    for (int64_t e = F.lp[j]; e < F.lp[j + 1]; ++e) {
+      F.lx[e] = w[F.li[e]] / ljj;
+      w[F.li[e]] = 0.0;
+    }
+  }
+  return F;
+}
+
+void sparse_cholesky_solve(const SparseChol& F, const double* b, double* x) {
+  const int n = F.n;
+  std::vector<double> y(n);
+  for (int k = 0; k < n; ++k) y[k] = b[F.perm[k]];
+  for (int j = 0; j < n; ++j) {
+    y[j] /= F.ld[j];
+    for (int64_t e = F.lp[j]; e < F.lp[j + 1]; ++e) y[F.li[e]] -= F.lx[e] * y[j];
+  }
+  for (int j = n - 1; j >= 0; --j) {
+    double s = y[j];
+    for (int64_t e = F.lp[j]; e < F.lp[j + 1]; ++e) s -= F.lx[e] * y[F.li[e]];
+    y[j] = s / F.ld[j];
+  }
+  for (int k = 0; k < n; ++k) x[F.perm[k]] = y[k];
+}
+
 std::vector<double> densify(const Csr& A) {
   std::vector<double> M((size_t)A.n * A.n, 0.0);
   for (int i = 0; i < A.n; ++i)
@@ -606,6 +733,9 @@ struct BLevel {
 struct BHier {
   std::vector<BLevel> lv;
   std::vector<double> Lc;  // dense Cholesky factor of the coarsest matrix
+  SparseChol Fc;           // sparse factor instead, above the dense limit
+  bool sparse = false;
+  bool stalled = false;    // coarsening stopped above the dense limit
   int ncoarse = 0;
 };
 
@@ -622,6 +752,8 @@ struct Params {
   int store_w;          // store projected smooth vectors in the file
   int max_levels;       // cap on bootstrap hierarchy depth
   int fine_group;       // rows per smoother group on the finest level (1: point)
+  int boot_dense_max;   // largest bootstrap coarsest level factored densely
+  int coarsest_max;     // largest coarsest multiple-vector level
 };
 
 // Builds B_r's hierarchy from the fine matrix and smooth vector w
@@ -655,12 +787,26 @@ BHier build_bootstrap_hierarchy(const Csr& A0, const std::vector<double>& w0, co
         comp.agg[i] = P2.agg[P1.agg[i]];
         comp.p[i] = P1.p[i] * P2.p[P1.agg[i]];
       }
-      if ((double)comp.nc > 0.95 * (double)n) coarsest = n <= 4096;
+      // A stalled coarsening (a step that keeps more than 95% of the rows)
+      // ends the hierarchy.  Matching-based pairwise steps stall where the
+      // graph has turned star-like: a vertex whose only neighbour is matched
+      // elsewhere stays a singleton and stays a leaf of that neighbour's
+      // aggregate, so each further step can match only around the hubs.
+      if ((double)comp.nc > 0.95 * (double)n) {
+        coarsest = true;
+        H.stalled = n > prm.boot_dense_max;
+      }
     }
     if (coarsest) {
-      if (n > 4096) fail("bootstrap hierarchy cannot coarsen below 4096 rows");
-      H.Lc = densify(L.A);
-      dense_cholesky(H.Lc, n);
+      // a direct solve on the coarsest level (Section 5); dense up to
+      // boot_dense_max rows, sparse above
+      if (n <= prm.boot_dense_max) {
+        H.Lc = densify(L.A);
+        dense_cholesky(H.Lc, n);
+      } else {
+        H.Fc = sparse_cholesky(L.A);
+        H.sparse = true;
+      }
       H.ncoarse = n;
       L.r.assign(n, 0.0);
       L.x.assign(n, 0.0);
@@ -685,7 +831,10 @@ void bh_vcycle(BHier& H, int l, const double* r, double* x) {
   BLevel& L = H.lv[l];
   const int n = L.A.n;
   if (l + 1 == (int)H.lv.size()) {
-    dense_cholesky_solve(H.Lc, n, r, x);
+    if (H.sparse)
+      sparse_cholesky_solve(H.Fc, r, x);
+    else
+      dense_cholesky_solve(H.Lc, n, r, x);
     return;
   }
   std::fill(x, x + n, 0.0);
@@ -980,6 +1129,8 @@ struct mvsetup_params {
   double tol_svd;
   int compose, coarse_cap, boot_coarse_min, hier_stage, store_w, max_levels, nthreads;
   int fine_group;
+  int boot_dense_max;  // 0: 4096
+  int coarsest_max;    // 0: 8192
 };
 
 const char* mvsetup_last_error(void) { return g_err.c_str(); }
@@ -988,7 +1139,8 @@ const char* mvsetup_last_error(void) { return g_err.c_str(); }
 // to `path`.  `x0` holds the random initial iterates of the bootstrap testing
 // phase: (nvec_max - 1) vectors of length n, one after the other.  `stats`
 // receives up to 64 doubles: [0] nlevels, [1] nvec, [2] opc, [3] cr,
-// [4] nstages, [5..] per-stage rho, [24..] per-level n, [44..] per-level nnz.
+// [4] nstages, [5..22] per-stage rho, [23] the stage whose hierarchy was
+// composed (0 = first), [24..] per-level n, [44..] per-level nnz.
 int mvsetup_build_boot(int n, const int* rowptr, const int* col, const double* val, const double* x0,
                        const mvsetup_params* prm_in, const char* path, double* stats, const char* boot_prefix);
 
@@ -1009,7 +1161,9 @@ int mvsetup_build_boot(int n, const int* rowptr, const int* col, const double* v
     Params prm{prm_in->nvec_max, prm_in->nu,         prm_in->rho_des,
                prm_in->maxstage, prm_in->tol_svd,    prm_in->compose,
                prm_in->coarse_cap, prm_in->boot_coarse_min, prm_in->hier_stage,
-               prm_in->store_w,  prm_in->max_levels, prm_in->fine_group};
+               prm_in->store_w,  prm_in->max_levels, prm_in->fine_group,
+               prm_in->boot_dense_max > 0 ? prm_in->boot_dense_max : 4096,
+               prm_in->coarsest_max > 0 ? prm_in->coarsest_max : 8192};
     if (prm.nvec_max < 1 || prm.nu < 1 || prm.compose < 1 || prm.max_levels < 2 ||
         prm.fine_group < 1 || n % prm.fine_group != 0)
       fail("invalid setup parameters");
@@ -1029,6 +1183,8 @@ int mvsetup_build_boot(int n, const int* rowptr, const int* col, const double* v
         if (!std::isfinite(A.v[k])) fail("non-finite matrix value");
       }
     const std::vector<double> d0 = diag_of(A);
+    // one line per bootstrap stage on stderr when MVSETUP_PROGRESS is set
+    const bool progress = std::getenv("MVSETUP_PROGRESS") != nullptr;
 
     // ---- bootstrap (Algorithm 1)
     std::vector<std::vector<double>> W;
@@ -1057,6 +1213,9 @@ int mvsetup_build_boot(int n, const int* rowptr, const int* col, const double* v
       const double ap = std::sqrt(std::max(0.0, dot(xprev.data(), Ax.data(), n)));
       const double rho = (ap > 0.0) ? an / ap : 0.0;
       rhos.push_back(rho);
+      if (progress)
+        std::fprintf(stderr, "mvsetup: stage %d: %d bootstrap levels (coarsest %d rows%s), rho %.3f\n", r,
+                     (int)hs.back().lv.size(), hs.back().ncoarse, hs.back().stalled ? ", stalled" : "", rho);
       if (!(an > 0.0)) break;  // the composite solver is exact: nothing left to learn
       for (int i = 0; i < n; ++i) x[i] /= an;
       W.push_back(std::move(x));
@@ -1070,17 +1229,15 @@ int mvsetup_build_boot(int n, const int* rowptr, const int* col, const double* v
       for (size_t r = 0; r < hs.size(); ++r)
         write_boot_hierarchy(hs[r], (std::string(boot_prefix) + "_b" + std::to_string(r + 1) + ".bin").c_str(),
                              (int)r + 1);
-    const int hsel = (prm.hier_stage < 0) ? (int)hs.size() - 1 : std::min(prm.hier_stage, (int)hs.size() - 1);
-    BHier& H = hs[hsel];
+    // ---- multiple-vector hierarchy (Section 4), from the levels of one
+    // bootstrap hierarchy H
+    auto compose_levels = [&](const BHier& H) {
     const int D = (int)H.lv.size() - 1;  // index of the bootstrap coarsest level
-
-    // ---- multiple-vector hierarchy (Section 4)
     std::vector<MvLevel> mv(1);
-    mv[0].A = std::move(A);
+    mv[0].A = A;
     mv[0].W.assign((size_t)n * nvec, 0.0);
     for (int i = 0; i < n; ++i)
       for (int r = 0; r < nvec; ++r) mv[0].W[(size_t)i * nvec + r] = W[r][i];
-    W.clear();
     std::vector<int> bnode(n);
     for (int i = 0; i < n; ++i) bnode[i] = i;
     int t = 0;
@@ -1174,8 +1331,25 @@ int mvsetup_build_boot(int n, const int* rowptr, const int* col, const double* v
       t = tn;
       mv.push_back(std::move(next));
     }
+    return mv;
+    };
+    // The paper composes the first hierarchy; by default the last one is
+    // composed, and if its levels cannot get down to a coarsest level of at
+    // most coarsest_max rows (its own coarsening stalled above that), the
+    // latest earlier one whose levels can.
+    int hsel = (prm.hier_stage < 0) ? (int)hs.size() - 1 : std::min(prm.hier_stage, (int)hs.size() - 1);
+    std::vector<MvLevel> mv;
+    for (;; --hsel) {
+      if (progress) std::fprintf(stderr, "mvsetup: composing the levels of stage %d\n", hsel + 1);
+      mv = compose_levels(hs[hsel]);
+      if (mv.back().A.n <= prm.coarsest_max || prm.hier_stage >= 0 || hsel == 0) break;
+    }
+    W.clear();
+    A = Csr();
     const int L = (int)mv.size() - 1;
-    if (mv[L].A.n > 8192) fail("coarsest level larger than 8192 rows; raise compose or lower coarse_cap");
+    if (mv[L].A.n > prm.coarsest_max)
+      fail("coarsest level larger than " + std::to_string(prm.coarsest_max) +
+           " rows; raise compose or lower coarse_cap");
 
     // ---- statistics
     double nnz_tot = 0, cr = 0;
@@ -1188,7 +1362,8 @@ int mvsetup_build_boot(int n, const int* rowptr, const int* col, const double* v
       stats[2] = nnz_tot / (double)mv[0].A.nnz();
       stats[3] = (L > 0) ? cr / L : 0.0;
       stats[4] = (double)rhos.size();
-      for (size_t s = 0; s < rhos.size() && s < 19; ++s) stats[5 + s] = rhos[s];
+      for (size_t s = 0; s < rhos.size() && s < 18; ++s) stats[5 + s] = rhos[s];
+      stats[23] = hsel;
       for (int l = 0; l <= L && l < 20; ++l) {
         stats[24 + l] = mv[l].A.n;
         stats[44 + l] = (double)mv[l].A.nnz();
@@ -1257,6 +1432,28 @@ int mvsetup_pairwise(int n, const int* rowptr, const int* col, const double* val
     std::copy(P.agg.begin(), P.agg.end(), agg);
     std::copy(P.p.begin(), P.p.end(), p);
     return P.nc;
+  } catch (const Fail& f) {
+    g_err = f.msg;
+    return -1;
+  }
+}
+
+// Solves A x = b with the sparse Cholesky factor of a stalled coarsest level
+// (A symmetric positive definite, CSR with sorted columns).  Returns the
+// number of off-diagonal entries of L, or -1 (error text in
+// mvsetup_last_error).
+int64_t mvsetup_sparse_solve(int n, const int* rowptr, const int* col, const double* val, const double* b,
+                             double* x) {
+  try {
+    if (n <= 0 || !rowptr || !col || !val || !b || !x) fail("invalid argument");
+    Csr A;
+    A.n = n;
+    A.rp.assign(rowptr, rowptr + n + 1);
+    A.ci.assign(col, col + A.rp[n]);
+    A.v.assign(val, val + A.rp[n]);
+    const SparseChol F = sparse_cholesky(A);
+    sparse_cholesky_solve(F, b, x);
+    return F.lp[n];
   } catch (const Fail& f) {
     g_err = f.msg;
     return -1;

@@ -95,10 +95,11 @@ def run(cases, sizes, nsvs, steps: int = 3, out=sys.stdout):
                 cr = float(np.mean([n[k - 1] / n[k] for k in range(1, len(n))]))
                 row = dict(case=case, m=m, n=P.n, nsv=nsv, nl=st["nlevels"], opc=st["opc"], rho=st["rho"][-1],
                            cr=cr, tb=tb, nit=inf.iterations, converged=bool(inf.converged), ts_ms=1e3 * ts,
-                           levels=n)
+                           levels=n, composed=st["composed_stage"] + 1)
                 rows.append(row)
                 print(f"{case} n={P.n} nsv={nsv}: nl={row['nl']} opc={row['opc']:.2f} rho={row['rho']:.2f} "
-                      f"cr={cr:.2f} tb={tb:.1f}s nit={row['nit']} ts={row['ts_ms']:.2f}ms", file=out, flush=True)
+                      f"cr={cr:.2f} tb={tb:.1f}s nit={row['nit']} ts={row['ts_ms']:.2f}ms "
+                      f"(levels of stage {row['composed']} of {len(st['rho'])})", file=out, flush=True)
     return rows
 
 

@@ -221,3 +221,75 @@ def test_colour_search_lowers_the_stage_count(setup_lib):
     stages = len(L.sptr) - 1
     assert stages < greedy, (stages, greedy)
     assert stages == 5 and greedy == 8
+
+
+def _spd(kind, rng):
+    import scipy.sparse as sp
+    if kind == "star":  # one hub joined to every other vertex: what a stalled coarsening leaves
+        n = 300
+        S = sp.lil_matrix((n, n))
+        for i in range(1, n):
+            S[0, i] = S[i, 0] = -rng.uniform(0.5, 1.5)
+        S = S.tocsr()
+    elif kind == "grid":
+        T = sp.diags([-1.0, 2.0, -1.0], [-1, 0, 1], shape=(17, 17))
+        return sp.csr_matrix(sp.kronsum(T, T))
+    elif kind == "random":
+        S = sp.random(300, 300, density=0.02, random_state=int(rng.integers(1 << 30)))
+        S = S + S.T
+    else:
+        return sp.csr_matrix(sp.diags(rng.uniform(1.0, 2.0, 40)))
+    return sp.csr_matrix(S + sp.diags(np.abs(S).sum(1).A1 + 0.1))
+
+
+@pytest.mark.parametrize("kind", ["star", "grid", "random", "diagonal"])
+def test_sparse_coarsest_solve(setup_lib, kind):
+    """The sparse Cholesky factor that a bootstrap coarsest level above the
+    dense limit gets solves A x = b to rounding (against a dense solve), and
+    the minimum-degree order factors a star with no fill: L keeps exactly the
+    off-diagonal entries of one triangle of A."""
+    rng = np.random.default_rng(7)
+    A = _spd(kind, rng)
+    A.sort_indices()
+    b = rng.standard_normal(A.shape[0])
+    x, nl = mvs.sparse_solve(A.indptr, A.indices, A.data, b)
+    xd = np.linalg.solve(A.toarray(), b)
+    assert np.abs(x - xd).max() <= 1e-12 * np.abs(xd).max()
+    if kind in ("star", "diagonal"):
+        assert nl == (A.nnz - A.shape[0]) // 2
+
+
+def test_sparse_coarsest_rejects_indefinite(setup_lib):
+    rp, ci = np.array([0, 2, 4]), np.array([0, 1, 0, 1])
+    with pytest.raises(RuntimeError, match="positive definite"):
+        mvs.sparse_solve(rp, ci, np.array([1.0, 2.0, 2.0, 1.0]), np.ones(2))
+
+
+def test_stalled_bootstrap_coarsening(setup_lib, tmp_path):
+    """ANI2 (theta = pi/8) on 410^2 nodes, three smooth vectors: the second
+    stage's pairwise coarsening stalls at 914 rows (the next double step keeps
+    871 of them), so that level is the second stage's coarsest.  With the
+    dense limit at 512 rows it gets the sparse factor instead of the dense
+    one, and the whole hierarchy agrees to rounding.  With the coarsest
+    multiple-vector level capped below what the second stage's levels reach
+    (1631 rows), the levels are composed from the first stage's hierarchy."""
+    import math
+    P = problems.ani_p1(410, 1e-3, math.pi / 8)
+    x0 = problems.random_vectors(P.n, 2, 1000)
+    H, st = {}, {}
+    for tag, kw in (("dense", {}), ("sparse", dict(boot_dense_max=512)), ("cap", dict(coarsest_max=1500))):
+        path = str(tmp_path / f"h_{tag}.bin")
+        st[tag] = mvs.build_hierarchy(P.rowptr, P.col, P.val, path, x0, mvs.SetupParams(nvec_max=3, **kw))
+        H[tag] = read_hierarchy(path)
+    assert st["dense"]["composed_stage"] == 1 and int(H["dense"].meta[6]) == 1
+    assert st["dense"]["n"] == [168100, 13043, 1631]
+    # sparse coarsest factor: same hierarchy up to rounding
+    assert st["sparse"]["composed_stage"] == 1 and st["sparse"]["n"] == st["dense"]["n"]
+    np.testing.assert_allclose(st["sparse"]["rho"], st["dense"]["rho"], rtol=1e-10)
+    for Ls, Ld in zip(H["sparse"].levels, H["dense"].levels):
+        np.testing.assert_array_equal(Ls.col, Ld.col)
+        np.testing.assert_allclose(Ls.W, Ld.W, rtol=0, atol=1e-10)
+    # the cap: the first stage's levels, whose coarsest fits
+    assert st["cap"]["composed_stage"] == 0 and int(H["cap"].meta[6]) == 0
+    assert st["cap"]["n"][-1] <= 1500
+    np.testing.assert_allclose(st["cap"]["rho"], st["dense"]["rho"], rtol=0, atol=0)
