@@ -118,3 +118,23 @@ def test_arena_bytes_on_the_host(lib, tiny_hier):
         assert "aligned" in mvamg.last_error() and out.value is None
     finally:
         mvamg.hier_host_free(hh)
+
+
+def test_single_level_hierarchy_is_rejected_on_the_host(lib, setup_lib, tmp_path):
+    """A problem no larger than the bootstrap's coarsest size gives a one-level
+    hierarchy (the whole solve would be the coarsest level's direct solve).
+    The library needs a level to smooth and says so before any device work."""
+    from paper_1907_04417_amd import problems
+    from paper_1907_04417_amd import setup as mvs
+    P = problems.aniso9(6, 1e-2, 0.5)
+    path = str(tmp_path / "one.bin")
+    st = mvs.build_hierarchy(P.rowptr, P.col, P.val, path, problems.random_vectors(P.n, 2, 1),
+                             mvs.SetupParams(nvec_max=3))
+    assert st["nlevels"] == 1
+    hh = mvamg.hier_read(path)
+    try:
+        nb = ctypes.c_size_t()
+        assert lib.mvamg_arena_bytes(hh, 1, ctypes.byref(nb)) == mvamg.ERR_ARG
+        assert "two levels" in mvamg.last_error()
+    finally:
+        mvamg.hier_host_free(hh)
