@@ -201,11 +201,15 @@ mvamg_status mvamg_cycle_apply_noalloc(mvamg_hier* h, const double* r_dev, doubl
    Returns MVAMG_OK, MVAMG_NOT_CONVERGED, or an error.  Each iteration's
    scalars (||r_k||^2 for the stopping test, the breakdown flag) are written
    by the last kernel of the iteration straight into mapped host memory that
-   the handle owns; the host reads them after synchronising the stream.  The
-   first solve of each precision and smoother captures one iteration as a
-   HIP graph and replays it; the runtime's executable graph holds about 2 MiB
-   of device memory of its own until mvamg_free (the environment variable
-   MVAMG_NO_GRAPH=1, read at upload, runs plain launches instead). */
+   the handle owns (two slots, alternating); the host reads them once the
+   iteration has ended.  The first solve of each precision and smoother
+   captures one iteration as a HIP graph and replays it, with the next
+   iteration queued before the host reads the current one's scalars; an
+   iteration queued past the stopping one only applies the last step's
+   pending x update.  The runtime's executable graph holds about 2 MiB of
+   device memory of its own until mvamg_free (the environment variable
+   MVAMG_NO_GRAPH=1, read at upload, runs plain launches, one iteration at a
+   time, instead). */
 mvamg_status mvamg_pcg_solve(mvamg_hier* h, const int* rowptr_dev, const int* col_dev, const double* val_dev,
                              const double* b_dev, double* x_dev, const mvamg_solve_params* prm, mvamg_info* info,
                              void* stream);

@@ -44,6 +44,7 @@ enum Scalar {
   S_FLAG = 5,  // breakdown flag (p.Ap <= 0)
   S_R0 = 6,    // ||r_0||^2
   S_ZQ = 7,    // z.q (flexible beta)
+  S_STEPS = 15,  // CG steps finished in this solve (their scalars alternate between two host slots)
   S_NSCAL = 16
 };
 
@@ -210,11 +211,15 @@ __global__ __launch_bounds__(kFinish) void k_finish(int nparts, const double* __
     }
     epilogue(mode, t0, t1, rho, alpha, scal);
     if (host != nullptr) {
+      // step g of the solve (g = scal[S_STEPS]) writes host slot g mod 2, so
+      // the host can still read step g while step g + 1 runs
       double v[S_NSCAL];
 #pragma unroll
       for (int i = 0; i < S_NSCAL; ++i) v[i] = scal[i];
+      double* slot = host + ((int)v[S_STEPS] & 1) * S_NSCAL;
+      scal[S_STEPS] = v[S_STEPS] + 1.0;
 #pragma unroll
-      for (int i = 0; i < S_NSCAL; ++i) __hip_atomic_store(host + i, v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      for (int i = 0; i < S_NSCAL; ++i) __hip_atomic_store(slot + i, v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
 }

@@ -204,7 +204,7 @@ struct mvamg_hier {
   double* scal = nullptr;
   double* part = nullptr;
   int dot_nparts = 0;  // partials of z.r written by the last cycle's fine backward sweep
-  double* pinned = nullptr;  // host copy of scal (mapped; see cg_step_a)
+  double* pinned = nullptr;  // host copies of scal, two slots (mapped; see cg_step_a)
   double* pinned_dev = nullptr;
   // batch of independent problems (nprob > 0): level-0 rows of problem p are
   // the file rows [poff[p], poff[p+1]); iperm0 maps a file row to smoother order
@@ -239,6 +239,7 @@ struct mvamg_hier {
   hipStream_t cap = nullptr;              // stream used only to capture graphs
   std::map<int, hipGraphExec_t> graphs;   // one CG iteration per (precision, smoother)
   bool use_graphs = true;
+  hipEvent_t itev[2] = {nullptr, nullptr};  // ends of the CG steps in flight (one ahead of the host)
   // measurement: per-launch HIP events for every instrumented kernel
   bool prof = false;
   // byte booking while measuring: false, the compact forms the kernels read
@@ -315,6 +316,8 @@ struct mvamg_hier {
     if (cap) (void)hipStreamDestroy(cap);
     if (mstream) (void)hipStreamDestroy(mstream);
     for (hipEvent_t e : mev)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : itev)
       if (e) (void)hipEventDestroy(e);
     if (pinned) (void)hipHostFree(pinned);
     if (mb.pinned) (void)hipHostFree(mb.pinned);
@@ -1035,6 +1038,7 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
   if (prm->history) prm->history[0] = 1.0;
   mvamg_status status = MVAMG_NOT_CONVERGED;
   double h_last = 1.0;
+  int64_t steps = 0;  // CG steps queued in this solve (the device counts them in scal[S_STEPS])
   if (r0 == 0.0) {
     status = MVAMG_OK;
     inf.converged = 1;
@@ -1053,8 +1057,18 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
       bool met = false;
       hipGraphExec_t ge =
           (h->use_graphs && !h->prof) ? iteration_graph(h, prm->precision, prm->smoother, prm->cycle) : nullptr;
+      // With the iteration graph the device runs one iteration ahead of the
+      // host: iteration j + 1 is queued before j's scalars are read (they sit
+      // in host slot j mod 2, see k_finish), so the device never waits for
+      // the host between iterations.  An iteration queued past the one that
+      // stops the loop is discarded; its only lasting effect is the pending
+      // x += alpha p of the stopping step, applied by its p update with the
+      // same arithmetic as k_x_update.
+      if (ge && !h->itev[0])
+        for (hipEvent_t& e : h->itev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       bool first = true;
-      while (it < prm->maxit) {
+      int queued = it;  // iterations queued; it: iterations whose scalars were read
+      auto queue_next = [&]() {
         if (first) {
           cg_step_a(h, st, fused_cycle(h, prm->precision, prm->smoother, prm->cycle));
           first = false;
@@ -1064,22 +1078,39 @@ mvamg_status pcg(mvamg_hier* h, const double* b_file, double* x_file, const mvam
           cg_step_b(h, prm->precision, prm->smoother, prm->cycle, st);
           cg_step_a(h, st, fused_cycle(h, prm->precision, prm->smoother, prm->cycle));
         }
-        HIPCHECK(hipStreamSynchronize(st));
+        if (ge) HIPCHECK(hipEventRecord(h->itev[steps & 1], st));
+        ++steps;
+        ++queued;
+      };
+      while (it < prm->maxit) {
+        if (queued == it) queue_next();
+        const int64_t rd = steps - (queued - it);  // step index of iteration it + 1
+        if (ge && queued < prm->maxit) queue_next();
+        if (ge)
+          HIPCHECK(hipEventSynchronize(h->itev[rd & 1]));
+        else
+          HIPCHECK(hipStreamSynchronize(st));
         ++it;
-        if (h->pinned[S_FLAG] != 0.0) {
+        const double* sc = h->pinned + (rd & 1) * S_NSCAL;
+        if (sc[S_FLAG] != 0.0) {
           inf.iterations = it;
+          (void)hipStreamSynchronize(st);
           throw Error(MVAMG_ERR_BREAKDOWN, "CG breakdown: p^T A p <= 0 (matrix not s.p.d.)");
         }
-        h_last = std::sqrt(h->pinned[S_RR]) / r0;
+        h_last = std::sqrt(sc[S_RR]) / r0;
         if (prm->history) prm->history[it] = h_last;
-        if (!std::isfinite(h_last)) throw Error(MVAMG_ERR_NONFINITE, "non-finite residual during CG");
+        if (!std::isfinite(h_last)) {
+          (void)hipStreamSynchronize(st);
+          throw Error(MVAMG_ERR_NONFINITE, "non-finite residual during CG");
+        }
         if (h_last <= prm->rtol) {
           met = true;
           break;
         }
       }
-      // the last step's pending x += alpha p (see cg_step_a)
-      if (!first) {
+      // the last step's pending x += alpha p (see cg_step_a), unless a
+      // discarded iteration has applied it
+      if (!first && queued == it) {
         k_x_update<<<grid_elem(n), kBlock, 0, st>>>(n, h->scal, h->p, h->x);
         LAUNCHCHECK("x_update");
       }
@@ -1506,7 +1537,8 @@ std::unique_ptr<mvamg_hier> upload_hier(const HostHier& H, const std::vector<con
       if (dev) {
         HIPCHECK(hipMemsetAsync(h->scal, 0, S_NSCAL * sizeof(double), st));
         // mapped and coherent: a finisher kernel writes it, the host reads it after the stream
-        HIPCHECK(hipHostMalloc((void**)&h->pinned, S_NSCAL * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+        HIPCHECK(hipHostMalloc((void**)&h->pinned, 2 * S_NSCAL * sizeof(double),
+                               hipHostMallocMapped | hipHostMallocCoherent));
         HIPCHECK(hipHostGetDevicePointer((void**)&h->pinned_dev, h->pinned, 0));
       }
     }
