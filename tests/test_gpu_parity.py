@@ -277,7 +277,10 @@ def test_solves_are_bitwise_repeatable(cases, torch_gpu):
 def test_graph_replay_matches_eager(cases, torch_gpu):
     """A CG iteration replayed from a captured HIP graph gives bitwise the same
     iterates as the same kernels launched one by one; checked on several
-    replays with other eager work in between."""
+    replays with other eager work in between.  The graph path queues each
+    iteration before the previous one's scalars are read and discards the one
+    queued past the stop; a run stopped by maxit (nothing discarded) and one
+    stopped by the tolerance (one discarded) both match."""
     import os
     torch = torch_gpu
     P, path, st, Sg, O = cases["jump32"]
@@ -292,6 +295,12 @@ def test_graph_replay_matches_eager(cases, torch_gpu):
         xg, rg = Sg.solve(b, precision=prec)
         _ = Se.spmv(b)  # unrelated eager work between replays
         xe, re_ = Se.solve(b, precision=prec)
+        assert np.array_equal(xg.cpu().numpy(), xe.cpu().numpy())
+        assert np.array_equal(rg.history, re_.history)
+    for maxit in (1, 2, 5):
+        xg, rg = Sg.solve(b, maxit=maxit)
+        xe, re_ = Se.solve(b, maxit=maxit)
+        assert rg.iterations == re_.iterations == maxit and not rg.converged
         assert np.array_equal(xg.cpu().numpy(), xe.cpu().numpy())
         assert np.array_equal(rg.history, re_.history)
     Se.close()
