@@ -411,7 +411,7 @@ def main():
     ap.add_argument("--no-multi", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path; "
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library has no multi-GPU path; "
               f"run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
