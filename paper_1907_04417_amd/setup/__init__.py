@@ -24,7 +24,8 @@ class _Params(ctypes.Structure):
                 ("boot_coarse_min", ctypes.c_int), ("hier_stage", ctypes.c_int),
                 ("store_w", ctypes.c_int), ("max_levels", ctypes.c_int),
                 ("nthreads", ctypes.c_int), ("fine_group", ctypes.c_int),
-                ("boot_dense_max", ctypes.c_int), ("coarsest_max", ctypes.c_int)]
+                ("boot_dense_max", ctypes.c_int), ("coarsest_max", ctypes.c_int),
+                ("boot_kcycle", ctypes.c_int)]
 
 
 @dataclass
@@ -57,6 +58,9 @@ class SetupParams:
     # the last bootstrap stage's levels cannot get there, those of the latest
     # earlier stage that can are composed
     coarsest_max: int = 8192
+    # 1: the bootstrap's testing phase applies the stage operators as K-cycles
+    # (two inner flexible-CG iterations per level), 0: as V-cycles
+    boot_kcycle: int = 0
 
 
 _lib = None
@@ -120,7 +124,7 @@ def build_hierarchy(rowptr, col, val, path: str, x0: np.ndarray, params: SetupPa
         raise ValueError(f"x0 must hold {k} vectors of length {n}")
     cp = _Params(p.nvec_max, p.nu, p.rho_des, p.maxstage, p.tol_svd, p.compose, p.coarse_cap,
                  p.boot_coarse_min, p.hier_stage, p.store_w, p.max_levels, p.nthreads, p.fine_group,
-                 p.boot_dense_max, p.coarsest_max)
+                 p.boot_dense_max, p.coarsest_max, p.boot_kcycle)
     stats = np.zeros(64)
     rc = lib.mvsetup_build_boot(n, _ptr(rp, ctypes.c_int), _ptr(ci, ctypes.c_int), _ptr(v, ctypes.c_double),
                                 _ptr(x0, ctypes.c_double), ctypes.byref(cp), path.encode(),

@@ -728,6 +728,7 @@ struct BLevel {
   Colouring C;
   PcMap P;  // to the next level (empty on the coarsest)
   std::vector<double> r, x, s;  // work vectors
+  std::vector<double> c1, c2, v1, v2, rt;  // K-cycle: the inner iterations on this level
 };
 
 struct BHier {
@@ -754,6 +755,7 @@ struct Params {
   int fine_group;       // rows per smoother group on the finest level (1: point)
   int boot_dense_max;   // largest bootstrap coarsest level factored densely
   int coarsest_max;     // largest coarsest multiple-vector level
+  int boot_kcycle;      // the testing phase applies B_r as K-cycles (else V-cycles)
 };
 
 // Builds B_r's hierarchy from the fine matrix and smooth vector w
@@ -817,6 +819,8 @@ BHier build_bootstrap_hierarchy(const Csr& A0, const std::vector<double>& w0, co
     L.r.assign(n, 0.0);
     L.x.assign(n, 0.0);
     L.s.assign(n, 0.0);
+    if (l > 0 && prm.boot_kcycle)
+      for (auto* v : {&L.c1, &L.c2, &L.v1, &L.v2, &L.rt}) v->assign(n, 0.0);
     BLevel next;
     next.A = std::move(A2);
     H.lv.push_back(std::move(next));
@@ -846,6 +850,61 @@ void bh_vcycle(BHier& H, int l, const double* r, double* x) {
   std::fill(C.r.begin(), C.r.end(), 0.0);
   for (int i = 0; i < n; ++i) C.r[L.P.agg[i]] += L.P.p[i] * L.s[i];
   bh_vcycle(H, l + 1, C.r.data(), C.x.data());
+#pragma omp parallel for schedule(static, 4096)
+  for (int i = 0; i < n; ++i) x[i] += L.P.p[i] * C.x[L.P.agg[i]];
+  gs_sweep(L.A, L.d, L.C, r, x, false);
+}
+
+// x = B r with the K-cycle (nonlinear AMLI): as the V-cycle, except that the
+// coarse correction of a level whose next level is not the coarsest is two
+// flexible-CG iterations on A_c e = r_c, each preconditioned by the K-cycle
+// of the next level (Section 5; Notay and Vassilevski's K-cycle).  With
+// c1 = B_c r_c, c2 = B_c (r_c - (c1' r_c / c1' A_c c1) A_c c1), the result is
+// the A_c-orthogonal projection of the error onto span{c1, c2}.
+void bh_kcycle(BHier& H, int l, const double* r, double* x) {
+  BLevel& L = H.lv[l];
+  const int n = L.A.n;
+  if (l + 1 == (int)H.lv.size()) {
+    if (H.sparse)
+      sparse_cholesky_solve(H.Fc, r, x);
+    else
+      dense_cholesky_solve(H.Lc, n, r, x);
+    return;
+  }
+  std::fill(x, x + n, 0.0);
+  gs_sweep(L.A, L.d, L.C, r, x, true);
+  spmv(L.A, x, L.s.data());
+#pragma omp parallel for schedule(static, 4096)
+  for (int i = 0; i < n; ++i) L.s[i] = r[i] - L.s[i];
+  BLevel& C = H.lv[l + 1];
+  const int nc = C.A.n;
+  std::fill(C.r.begin(), C.r.end(), 0.0);
+  for (int i = 0; i < n; ++i) C.r[L.P.agg[i]] += L.P.p[i] * L.s[i];
+  if (l + 2 == (int)H.lv.size()) {
+    bh_kcycle(H, l + 1, C.r.data(), C.x.data());  // exact on the coarsest
+  } else {
+    bh_kcycle(H, l + 1, C.r.data(), C.c1.data());
+    spmv(C.A, C.c1.data(), C.v1.data());
+    const double rho1 = dot(C.c1.data(), C.v1.data(), nc);
+    const double a1 = dot(C.c1.data(), C.r.data(), nc);
+    if (!(rho1 > 0.0)) fail("K-cycle: c1' A_c c1 <= 0");
+#pragma omp parallel for schedule(static, 4096)
+    for (int i = 0; i < nc; ++i) C.rt[i] = C.r[i] - (a1 / rho1) * C.v1[i];
+    bh_kcycle(H, l + 1, C.rt.data(), C.c2.data());
+    spmv(C.A, C.c2.data(), C.v2.data());
+    const double gam = dot(C.c2.data(), C.v1.data(), nc);
+    const double bet = dot(C.c2.data(), C.v2.data(), nc);
+    const double a2 = dot(C.c2.data(), C.rt.data(), nc);
+    const double rho2 = bet - gam * gam / rho1;
+    if (rho2 > 0.0) {
+      const double f1 = a1 / rho1 - gam * a2 / (rho1 * rho2), f2 = a2 / rho2;
+#pragma omp parallel for schedule(static, 4096)
+      for (int i = 0; i < nc; ++i) C.x[i] = f1 * C.c1[i] + f2 * C.c2[i];
+    } else {  // c2 adds nothing A_c-independent of c1: one iteration
+#pragma omp parallel for schedule(static, 4096)
+      for (int i = 0; i < nc; ++i) C.x[i] = (a1 / rho1) * C.c1[i];
+    }
+  }
 #pragma omp parallel for schedule(static, 4096)
   for (int i = 0; i < n; ++i) x[i] += L.P.p[i] * C.x[L.P.agg[i]];
   gs_sweep(L.A, L.d, L.C, r, x, false);
@@ -1131,6 +1190,7 @@ struct mvsetup_params {
   int fine_group;
   int boot_dense_max;  // 0: 4096
   int coarsest_max;    // 0: 8192
+  int boot_kcycle;     // 1: K-cycles in the bootstrap's testing phase
 };
 
 const char* mvsetup_last_error(void) { return g_err.c_str(); }
@@ -1163,7 +1223,8 @@ int mvsetup_build_boot(int n, const int* rowptr, const int* col, const double* v
                prm_in->coarse_cap, prm_in->boot_coarse_min, prm_in->hier_stage,
                prm_in->store_w,  prm_in->max_levels, prm_in->fine_group,
                prm_in->boot_dense_max > 0 ? prm_in->boot_dense_max : 4096,
-               prm_in->coarsest_max > 0 ? prm_in->coarsest_max : 8192};
+               prm_in->coarsest_max > 0 ? prm_in->coarsest_max : 8192,
+               prm_in->boot_kcycle != 0};
     if (prm.nvec_max < 1 || prm.nu < 1 || prm.compose < 1 || prm.max_levels < 2 ||
         prm.fine_group < 1 || n % prm.fine_group != 0)
       fail("invalid setup parameters");
@@ -1198,7 +1259,10 @@ int mvsetup_build_boot(int n, const int* rowptr, const int* col, const double* v
       std::vector<double> x(x0 + (size_t)(r - 1) * n, x0 + (size_t)r * n), xprev(n);
       auto apply_factor = [&](BHier& H) {  // x <- (I - B A) x
         spmv(A, x.data(), Ax.data());
-        bh_vcycle(H, 0, Ax.data(), Bz.data());
+        if (prm.boot_kcycle)
+          bh_kcycle(H, 0, Ax.data(), Bz.data());
+        else
+          bh_vcycle(H, 0, Ax.data(), Bz.data());
 #pragma omp parallel for schedule(static, 4096)
         for (int i = 0; i < n; ++i) x[i] -= Bz[i];
       };

@@ -132,3 +132,29 @@ def test_composite_pcg_is_flexible_cg(boot, kcyc):
     assert status == 0 and std == 0 and nit == nitd
     assert np.all(np.abs(hist - hd) <= 1e-8 * hd)
     assert np.abs(x - np.linalg.solve(A, P.b)).max() <= 1e-8 * np.abs(x).max()
+
+
+def test_testing_phase_with_kcycles_reproduces_the_setup(setup_lib, tmp_path):
+    """With boot_kcycle the setup tests its composite with K-cycle components
+    (two inner flexible-CG iterations per level, as Section 5 describes for the
+    original bootstrap); the oracle's composite of the same stage files with
+    K-cycle components, from the same random starts, gets the setup's
+    estimates and smooth vectors.  The 24 x 24 problem gives stage
+    hierarchies of four levels, so the inner iterations run on two levels."""
+    P = problems.aniso9(24, 1e-2, np.pi / 4, seed=6)
+    x0 = problems.random_vectors(P.n, NVEC - 1, 1000)
+    st = build_hierarchy(P.rowptr, P.col, P.val, str(tmp_path / "main.bin"), x0,
+                         SetupParams(nvec_max=NVEC, boot_coarse_min=6, rho_des=0.0, boot_kcycle=1),
+                         boot_prefix=str(tmp_path / "boot"))
+    paths = [str(tmp_path / f"boot_b{r}.bin") for r in range(1, len(st["rho"]) + 1)]
+    assert len(paths) == NVEC - 1
+    assert min(len(read_hierarchy(p).levels) for p in paths) >= 4
+    W0 = read_hierarchy(str(tmp_path / "main.bin")).levels[0].W
+    for r in range(1, len(paths) + 1):
+        C = oracle.Composite([oracle.Oracle(p) for p in paths[:r]], kcycle=True)
+        w, rho = C.test(x0[r - 1], nu=15)
+        assert abs(rho - st["rho"][r - 1]) <= 1e-9 * rho, (r, rho, st["rho"][r - 1])
+        assert np.abs(w - W0[:, r]).max() <= 1e-8 * np.abs(W0[:, r]).max(), r
+    # and the V-cycle testing phase gives other estimates on the same problem
+    C = oracle.Composite([oracle.Oracle(paths[0])], kcycle=False)
+    assert abs(C.test(x0[0], nu=15)[1] - st["rho"][0]) > 1e-6 * st["rho"][0]
