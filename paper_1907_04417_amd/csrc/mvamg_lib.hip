@@ -944,7 +944,7 @@ void cg_step_b(mvamg_hier* h, int precision, int smoother, int cycle, hipStream_
 }
 
 // One full iteration (B then A) captured once as a HIP graph and replayed:
-// about 60 kernels and one copy per launch instead of as many host launches.
+// about 60 kernels per launch instead of as many host launches.
 hipGraphExec_t iteration_graph(mvamg_hier* h, int precision, int smoother, int cycle) {
   const int key = (precision * 4 + smoother) * 2 + cycle;
   auto it = h->graphs.find(key);
