@@ -2299,8 +2299,14 @@ mvamg_status mvamg_setup_galerkin(int m, int nagg, int nc, const int* aptr, cons
     if (m < 1 || m > kSvdMaxM || nagg < 1 || nc < 1) throw Error(MVAMG_ERR_ARG, "sizes out of range");
     hipStream_t st = (hipStream_t)stream;
     k_fill<int><<<1, kBlock, 0, st>>>(1, 0, flag);
-    k_setup_galerkin<<<nagg, 64, 0, st>>>(m, nagg, aptr, arows, coff, agg, loc, cagg, rowptr, col, val, U, crp,
-                                          ccol, work);
+    // few aggregates (a coarse level): several waves per aggregate, or the
+    // device would hold a handful of long waves
+    if (nagg < kGalSplitBelow)
+      k_setup_galerkin_split<<<nagg, 64 * kGalWaves, 0, st>>>(m, nagg, aptr, arows, coff, agg, loc, cagg, rowptr,
+                                                              col, val, U, crp, ccol, work);
+    else
+      k_setup_galerkin<<<nagg, 64, 0, st>>>(m, nagg, aptr, arows, coff, agg, loc, cagg, rowptr, col, val, U, crp,
+                                            ccol, work);
     k_symmetrize<<<grid_for(nc), kBlock, 0, st>>>(nc, crp, ccol, work, cval, flag);
     LAUNCHCHECK("setup_galerkin");
     int hflag = 0;

@@ -174,6 +174,64 @@ __global__ __launch_bounds__(64) void k_setup_galerkin(
   }
 }
 
+// The same values for levels with few, large aggregates: one block of
+// kGalWaves waves per aggregate.  Wave w takes the w-th of kGalWaves
+// contiguous runs of a's member rows and sums over them as above; the runs'
+// sums go to LDS and are added in run order.  (Each value is then a sum of
+// kGalWaves ordered partial sums instead of one running sum: the same terms,
+// rounded in another grouping.)
+constexpr int kGalWaves = 4;
+constexpr int kGalSplitBelow = 8192;  // aggregates
+
+__global__ __launch_bounds__(64 * kGalWaves) void k_setup_galerkin_split(
+    int m, int nagg, const int* __restrict__ aptr, const int* __restrict__ arows, const int* __restrict__ coff,
+    const int* __restrict__ agg, const int* __restrict__ loc, const int* __restrict__ cagg,
+    const int* __restrict__ rowptr, const int* __restrict__ col, const double* __restrict__ val,
+    const double* __restrict__ U, const int* __restrict__ crp, const int* __restrict__ ccol,
+    double* __restrict__ cval) {
+  __shared__ double part[kGalWaves][kSvdMaxM][64];
+  const int a = blockIdx.x;
+  if (a >= nagg) return;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r0 = aptr[a], na = aptr[a + 1] - r0, ka = coff[a + 1] - coff[a];
+  const int I0 = coff[a], c0 = crp[I0], len = crp[I0 + 1] - c0;
+  const int li0 = (int)((int64_t)na * w / kGalWaves), li1 = (int)((int64_t)na * (w + 1) / kGalWaves);
+  for (int t0 = 0; t0 < len; t0 += 64) {
+    const int t = t0 + lane;
+    double acc[kSvdMaxM];
+#pragma unroll
+    for (int l = 0; l < kSvdMaxM; ++l) acc[l] = 0.0;
+    if (t < len) {
+      const int C = ccol[c0 + t];
+      const int b = cagg[C], mm = C - coff[b];
+      for (int li = li0; li < li1; ++li) {
+        const int i = arows[r0 + li];
+        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+          const int j = col[e];
+          if (agg[j] != b) continue;
+          const double wv = val[e] * U[(size_t)(aptr[b] + loc[j]) * m + mm];
+#pragma unroll
+          for (int l = 0; l < kSvdMaxM; ++l)
+            if (l < ka) acc[l] += U[(size_t)(r0 + li) * m + l] * wv;
+        }
+      }
+    }
+#pragma unroll
+    for (int l = 0; l < kSvdMaxM; ++l) part[w][l][lane] = acc[l];
+    __syncthreads();
+    if (w == 0 && t < len)
+#pragma unroll
+      for (int l = 0; l < kSvdMaxM; ++l)
+        if (l < ka) {
+          double v = part[0][l][lane];
+#pragma unroll
+          for (int q = 1; q < kGalWaves; ++q) v += part[q][l][lane];
+          cval[crp[I0 + l] + t] = v;
+        }
+    __syncthreads();
+  }
+}
+
 // out_IJ = (in_IJ + in_JI) / 2 over a structurally symmetric CSR with sorted
 // rows (the entry J I found by binary search): exactly symmetric.
 __global__ __launch_bounds__(kBlock) void k_symmetrize(int n, const int* __restrict__ rp, const int* __restrict__ ci,
